@@ -1,0 +1,255 @@
+"""FP64 CPU oracle for Pinv-Recon's Cholesky route.  TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the package's smoke check and the benchmark's CPU-baseline leg
+may import this module.  The device library never calls it and shares no code
+with it.  It is slow on purpose: every step is the plain definition, in
+complex128, so it can be checked against the paper by eye.
+
+What it computes (paper Sec. 2.2, Eq. 6 and Eq. 8):
+
+    G   = E^H E                      (Gram matrix, Hermitian PSD)
+    G_l = G + lam * I                (Tikhonov shift; `lam` is the paper's lambda^2)
+    G_l = L L^H                      (Cholesky, L lower triangular)
+    x   = L^-H L^-1 E^H d            (regularised least-squares image)
+    R   = L^-H L^-1 E^H              (the reconstruction matrix, formed for small N)
+
+The encoding element (paper Eq. 2 and the generalised product form of Sec. 3.3,
+with the sign convention exp(-i 2 pi ...) used throughout this project):
+
+    E[(c,i),(s,v)] = C_c(v) * exp(-i 2 pi (k_i . r_v + (f_s + B0(v)) t_i))
+
+Rows m = c*K + i (coil-major), columns n = s*V + v with v = iy*nx + ix.
+Voxel centres r_v = ((ix - nx/2)/nx, (iy - ny/2)/ny) in FOV units, k in
+cycles/FOV, frequencies in Hz, times in seconds.
+
+Each function names the passage it follows.  Pins for every step live in
+tests/test_oracle_pins.py (Cartesian inverse DFT, DFT special cases for the
+species and off-resonance factors, SVD filter factors, Moore-Penrose
+conditions, conjugate-phase limit, closed-form diagonal, coil-sum identity,
+normal-equation residual, push-through identity, eigen route, SRF identity).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+ROW_BLOCK = 4096
+
+
+class NotPositiveDefinite(ArithmeticError):
+    """Raised by `cholesky` when a pivot is not > 0; `.column` names it."""
+
+    def __init__(self, column: int, pivot: float):
+        super().__init__(f"matrix is not positive definite: pivot {pivot!r} at column {column}")
+        self.column = column
+        self.pivot = pivot
+
+
+# ----------------------------------------------------------------------------
+# the encoding matrix  (Eq. 1, Eq. 2; generalised product encoding, Sec. 3.3)
+# ----------------------------------------------------------------------------
+
+def _dims(enc):
+    V = enc.nx * enc.ny
+    S = 1 if enc.species_hz is None else len(enc.species_hz)
+    K = enc.k.shape[0]
+    C = 1 if enc.coil is None else enc.coil.shape[0]
+    return V, S, K, C
+
+
+def voxel_positions(nx: int, ny: int):
+    x = (np.arange(nx, dtype=np.float64) - nx / 2.0) / nx
+    y = (np.arange(ny, dtype=np.float64) - ny / 2.0) / ny
+    X, Y = np.meshgrid(x, y)
+    return X.ravel(), Y.ravel()
+
+
+def encoding_rows(enc, m0: int, m1: int) -> np.ndarray:
+    """Rows m0..m1-1 of E, explicitly, [m1-m0, N] complex128.
+
+    Phase in turns = k.r + (f_s + B0) t, reduced to (-1/2, 1/2] before the
+    trigonometric functions so the FP64 angle keeps full relative accuracy.
+    """
+    V, S, K, C = _dims(enc)
+    X, Y = voxel_positions(enc.nx, enc.ny)
+    m = np.arange(m0, m1)
+    c = m // K
+    i = m % K
+    kx = enc.k[i, 0][:, None]
+    ky = enc.k[i, 1][:, None]
+    spatial = kx * X[None, :] + ky * Y[None, :]                    # [rows, V]
+    species = np.zeros(S) if enc.species_hz is None else np.asarray(enc.species_hz, float)
+    b0 = np.zeros(V) if enc.b0_hz is None else np.asarray(enc.b0_hz, float)
+    t = np.zeros(K) if enc.t is None else np.asarray(enc.t, float)
+    blocks = []
+    for s in range(S):
+        turns = spatial + (species[s] + b0[None, :]) * t[i][:, None]
+        frac = turns - np.round(turns)
+        phase = np.cos(2.0 * math.pi * frac) - 1j * np.sin(2.0 * math.pi * frac)
+        if enc.coil is not None:
+            phase = phase * enc.coil[c, :]
+        blocks.append(phase)
+    return np.concatenate(blocks, axis=1)
+
+
+def encoding_matrix(enc) -> np.ndarray:
+    """The whole E, [M, N] (small cases only)."""
+    V, S, K, C = _dims(enc)
+    return encoding_rows(enc, 0, C * K)
+
+
+def _row_blocks(enc):
+    """Row ranges coil by coil (Eq. 11), each split into <= ROW_BLOCK rows."""
+    V, S, K, C = _dims(enc)
+    for c in range(C):
+        for i0 in range(0, K, ROW_BLOCK):
+            yield c * K + i0, c * K + min(K, i0 + ROW_BLOCK)
+
+
+# ----------------------------------------------------------------------------
+# Gram matrix and regularisation  (Sec. 2.2; Eq. 6; Eq. 11)
+# ----------------------------------------------------------------------------
+
+def gram(enc) -> np.ndarray:
+    """G = E^H E accumulated as the sum of per-coil products E_c^H E_c (Eq. 11)."""
+    V, S, K, C = _dims(enc)
+    N = S * V
+    G = np.zeros((N, N), dtype=np.complex128)
+    for m0, m1 in _row_blocks(enc):
+        Eb = encoding_rows(enc, m0, m1)
+        G += Eb.conj().T @ Eb
+    return G
+
+
+def adjoint(enc, d: np.ndarray) -> np.ndarray:
+    """E^H d for frames d [F, M] -> [F, N], summed coil by coil (Eq. 11 remark)."""
+    d = np.atleast_2d(d)
+    V, S, K, C = _dims(enc)
+    out = np.zeros((d.shape[0], S * V), dtype=np.complex128)
+    for m0, m1 in _row_blocks(enc):
+        Eb = encoding_rows(enc, m0, m1)
+        out += d[:, m0:m1] @ Eb.conj()
+    return out
+
+
+def forward(enc, x: np.ndarray) -> np.ndarray:
+    """data = E x (Eq. 1) for images x [F, N] -> [F, M]."""
+    x = np.atleast_2d(x)
+    V, S, K, C = _dims(enc)
+    out = np.empty((x.shape[0], C * K), dtype=np.complex128)
+    for m0, m1 in _row_blocks(enc):
+        Eb = encoding_rows(enc, m0, m1)
+        out[:, m0:m1] = x @ Eb.T
+    return out
+
+
+def lambda_abs(G: np.ndarray, rel: float) -> float:
+    """Diagonal shift rel * trace(E^H E) / N (= rel * mean diagonal)."""
+    return float(rel * np.trace(G).real / G.shape[0])
+
+
+# ----------------------------------------------------------------------------
+# Cholesky and triangular solves  (Eq. 8)
+# ----------------------------------------------------------------------------
+
+def cholesky(A: np.ndarray) -> np.ndarray:
+    """Lower L with A = L L^H, column by column (Cholesky-Crout), no pivoting.
+
+    L[j,j] = sqrt(A[j,j] - sum_k |L[j,k]|^2)
+    L[i,j] = (A[i,j] - sum_k L[i,k] conj(L[j,k])) / L[j,j],  i > j
+    Raises NotPositiveDefinite if a pivot is not > 0 (or is NaN).
+    """
+    N = A.shape[0]
+    L = np.zeros_like(A, dtype=np.complex128)
+    for j in range(N):
+        lj = L[j, :j]
+        piv = A[j, j].real - float(np.vdot(lj, lj).real)
+        if not piv > 0.0:
+            raise NotPositiveDefinite(j, piv)
+        ljj = math.sqrt(piv)
+        L[j, j] = ljj
+        if j + 1 < N:
+            L[j + 1:, j] = (A[j + 1:, j] - L[j + 1:, :j] @ lj.conj()) / ljj
+    return L
+
+
+def forward_substitution(L: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """Solve L Y = B (B is [N, ncols]) row by row."""
+    N = L.shape[0]
+    Y = np.zeros_like(B, dtype=np.complex128)
+    for i in range(N):
+        Y[i] = (B[i] - L[i, :i] @ Y[:i]) / L[i, i]
+    return Y
+
+
+def back_substitution_h(L: np.ndarray, Y: np.ndarray) -> np.ndarray:
+    """Solve L^H X = Y (L lower, so L^H upper) from the last row up."""
+    N = L.shape[0]
+    X = np.zeros_like(Y, dtype=np.complex128)
+    for i in range(N - 1, -1, -1):
+        # (L^H)[i, j] = conj(L[j, i]) for j > i
+        X[i] = (Y[i] - L[i + 1:, i].conj() @ X[i + 1:]) / np.conj(L[i, i])
+    return X
+
+
+def solve_normal(L: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """X = (L L^H)^-1 B = L^-H L^-1 B."""
+    return back_substitution_h(L, forward_substitution(L, B))
+
+
+# ----------------------------------------------------------------------------
+# the method end to end  (Eq. 3, Eq. 6, Eq. 8)
+# ----------------------------------------------------------------------------
+
+class Build:
+    """The data-independent part: Gram, shift and factor (computed once, reused
+    for every frame of every acquisition with the same encoding)."""
+
+    def __init__(self, enc, rel: float = None, lam: float = None, G: np.ndarray = None):
+        self.enc = enc
+        self.G = gram(enc) if G is None else G
+        if (rel is None) == (lam is None):
+            raise ValueError("give exactly one of rel or lam")
+        self.lam = lambda_abs(self.G, rel) if lam is None else float(lam)
+        N = self.G.shape[0]
+        self.L = cholesky(self.G + self.lam * np.eye(N))
+
+    def reconstruct(self, d: np.ndarray) -> np.ndarray:
+        """Images x = (E^H E + lam I)^-1 E^H d for frames d [F, M] -> [F, N]."""
+        b = adjoint(self.enc, d)                 # [F, N]
+        return solve_normal(self.L, b.T).T
+
+    def recon_matrix(self) -> np.ndarray:
+        """R = L^-H L^-1 E^H, [N, M] (small N only)."""
+        Eh = encoding_matrix(self.enc).conj().T
+        return solve_normal(self.L, Eh)
+
+    def normal_residual(self, d: np.ndarray, x: np.ndarray) -> np.ndarray:
+        """E^H (d - E x) - lam x, per frame [F, N] (zero at the exact solution)."""
+        return adjoint(self.enc, np.atleast_2d(d) - forward(self.enc, x)) - self.lam * np.atleast_2d(x)
+
+
+def reconstruct(enc, d: np.ndarray, rel: float = None, lam: float = None) -> np.ndarray:
+    return Build(enc, rel=rel, lam=lam).reconstruct(d)
+
+
+# ----------------------------------------------------------------------------
+# image metrics from R  (Eq. 9, Eq. 10)
+# ----------------------------------------------------------------------------
+
+def srf_matrix(R: np.ndarray, E: np.ndarray) -> np.ndarray:
+    """SRF = R E (Eq. 9); its diagonal reshaped to the grid is the SRF map."""
+    return R @ E
+
+
+def noise_matrix(R: np.ndarray, psi: np.ndarray) -> np.ndarray:
+    """X = R Psi R^H for a data-noise covariance Psi [M, M] (Eq. 10)."""
+    return R @ psi @ R.conj().T
+
+
+def relative_error(x: np.ndarray, ref: np.ndarray) -> np.ndarray:
+    """Per-frame ||x - ref|| / ||ref|| for [F, N] arrays."""
+    x = np.atleast_2d(x)
+    ref = np.atleast_2d(ref)
+    return np.linalg.norm(x - ref, axis=1) / np.linalg.norm(ref, axis=1)

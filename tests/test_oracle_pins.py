@@ -1,0 +1,328 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+Each test names the passage it rests on.  None of them retypes the oracle's
+formulas: the expected values come from numpy's FFT, SVD, eigh and dense solve,
+from closed forms, or from identities between separate oracle calls.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2410_06129_amd import synth
+
+
+def cartesian_enc(n):
+    return synth.Encoding(n, n, synth.cartesian_full(n, n))
+
+
+def tiny_enc(seed=0, nx=6, ny=5, C=2, K=40, species=None, b0=False):
+    rng = np.random.default_rng(seed)
+    k = rng.uniform(-max(nx, ny) / 2, max(nx, ny) / 2, size=(K, 2))
+    coil = synth.coil_maps(nx, ny, C, rng) if C > 1 else None
+    need_t = b0 or (species is not None and len(species) > 1)
+    t = synth.sample_times(K, 50e-6) if need_t else None
+    b0m = synth.b0_map(nx, ny, rng) if b0 else None
+    sp = None if species is None else np.asarray(species, float)
+    return synth.Encoding(nx, ny, k, t=t, coil=coil, b0_hz=b0m, species_hz=sp)
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+# --- P1: fully sampled Cartesian reduces to the DFT (Sec. 4.2: pinv along a
+#         uniformly sampled axis without regularisation equals the 1-D FFT) ---
+
+@pytest.mark.parametrize("n", [4, 8, 10])
+def test_p1_cartesian_gram_is_scaled_identity(n):
+    enc = cartesian_enc(n)
+    G = oracle.gram(enc)
+    N = n * n
+    assert np.max(np.abs(G - N * np.eye(N))) <= 1e-12 * N
+
+
+@pytest.mark.parametrize("n", [4, 8])
+def test_p1_cartesian_lambda0_is_inverse_dft(n):
+    enc = cartesian_enc(n)
+    rng = np.random.default_rng(7)
+    d = synth.unit_complex_noise((3, n * n), rng)
+    x = oracle.reconstruct(enc, d, lam=0.0)
+    for f in range(3):
+        D = d[f].reshape(n, n)                   # [ky, kx], k = index - n/2
+        ref = np.fft.fftshift(np.fft.ifft2(np.fft.ifftshift(D)))   # [iy, ix]
+        assert rel(x[f], ref.ravel()) < 1e-13
+
+
+def test_p1_cartesian_R_is_scaled_adjoint():
+    n, lam = 6, 3.5
+    enc = cartesian_enc(n)
+    b = oracle.Build(enc, lam=lam)
+    R = b.recon_matrix()
+    # unitary-up-to-scale E: R = E^H/(N+lam); E^H from numpy's inverse DFT matrix
+    N = n * n
+    eye = np.eye(N)
+    # column j of E^H d for d = e_j is the inverse DFT (times N) of a unit impulse
+    cols = []
+    for j in range(N):
+        D = eye[j].reshape(n, n)
+        cols.append(N * np.fft.fftshift(np.fft.ifft2(np.fft.ifftshift(D))).ravel())
+    EH = np.stack(cols, axis=1)
+    assert rel(R, EH / (N + lam)) < 1e-13
+
+
+# --- species and off-resonance factors reduce to a DFT too (Sec. 3.3) ---------
+
+def test_species_factor_is_a_dft_over_time():
+    S, dt = 8, 1e-3
+    # one voxel, k = 0, species at f_s = s/(S dt), t_i = i dt:  E[i,s] = exp(-i2pi s i/S)
+    enc = synth.Encoding(1, 1, np.zeros((S, 2)), t=np.arange(S) * dt,
+                         species_hz=np.arange(S) / (S * dt))
+    d = synth.unit_complex_noise((2, S), np.random.default_rng(3))
+    x = oracle.reconstruct(enc, d, lam=0.0)
+    assert rel(x, np.fft.ifft(d, axis=1)) < 1e-13
+
+
+def test_b0_factor_is_a_dft_over_time():
+    V, dt = 8, 1e-3
+    enc = synth.Encoding(V, 1, np.zeros((V, 2)), t=np.arange(V) * dt,
+                         b0_hz=np.arange(V) / (V * dt))
+    d = synth.unit_complex_noise((2, V), np.random.default_rng(4))
+    x = oracle.reconstruct(enc, d, lam=0.0)
+    assert rel(x, np.fft.ifft(d, axis=1)) < 1e-13
+
+
+def test_uniform_b0_equals_species_shift():
+    """A constant off-resonance b behaves as a single species at b Hz: the two
+    factors enter the exponent with the same sign and time axis."""
+    base = tiny_enc(seed=5, C=1)
+    t = synth.sample_times(base.K, 100e-6)
+    e1 = synth.Encoding(base.nx, base.ny, base.k, t=t, b0_hz=np.full(base.V, 37.0))
+    e2 = synth.Encoding(base.nx, base.ny, base.k, t=t, species_hz=np.array([37.0]))
+    assert np.max(np.abs(oracle.encoding_matrix(e1) - oracle.encoding_matrix(e2))) < 1e-13
+
+
+def test_cartesian_sign_matches_numpy_forward_fft():
+    """data = E x with exp(-i2pi k.r) is numpy's forward FFT up to index shifts."""
+    n = 8
+    enc = cartesian_enc(n)
+    x = synth.unit_complex_noise((1, n * n), np.random.default_rng(8))
+    d = oracle.forward(enc, x)[0].reshape(n, n)
+    ref = np.fft.fftshift(np.fft.fft2(np.fft.ifftshift(x[0].reshape(n, n))))
+    assert rel(d, ref) < 1e-13
+
+
+# --- P2: SVD with Tikhonov filter factors (Eq. 4; Sec. 2.2 eigenvalues = s^2) --
+
+@pytest.mark.parametrize("seed,lam", [(0, 0.3), (1, 5.0), (2, 1e-2)])
+def test_p2_matches_svd_filter_factors(seed, lam):
+    enc = tiny_enc(seed=seed)
+    E = oracle.encoding_matrix(enc)
+    U, s, Vh = np.linalg.svd(E, full_matrices=False)
+    R_svd = (Vh.conj().T * (s / (s * s + lam))) @ U.conj().T
+    R = oracle.Build(enc, lam=lam).recon_matrix()
+    kappa = (s[0] ** 2 + lam) / (s[-1] ** 2 + lam)
+    assert rel(R, R_svd) < 1e-13 * kappa
+
+
+# --- P3: Moore-Penrose conditions at lam = 0 (Sec. 2; left pseudoinverse) -----
+
+def test_p3_moore_penrose_conditions():
+    enc = tiny_enc(seed=11, K=60)
+    E = oracle.encoding_matrix(enc)
+    R = oracle.Build(enc, lam=0.0).recon_matrix()
+    s = np.linalg.svd(E, compute_uv=False)
+    tol = 1e-12 * (s[0] / s[-1]) ** 2
+    N = E.shape[1]
+    assert rel(E @ R @ E, E) < tol
+    assert rel(R @ E @ R, R) < tol
+    ER, RE = E @ R, R @ E
+    assert np.linalg.norm(ER - ER.conj().T) / np.linalg.norm(ER) < tol
+    assert np.linalg.norm(RE - RE.conj().T) / np.linalg.norm(RE) < tol
+    assert np.linalg.norm(RE - np.eye(N)) / math.sqrt(N) < tol
+
+
+# --- P4: large lambda tends to conjugate phase (Sec. 2.2) ---------------------
+
+def test_p4_large_lambda_conjugate_phase():
+    enc = tiny_enc(seed=12)
+    E = oracle.encoding_matrix(enc)
+    gnorm = np.linalg.norm(E, 2) ** 2
+    prev = None
+    for f in (1e3, 1e5, 1e7):
+        lam = f * gnorm
+        R = oracle.Build(enc, lam=lam).recon_matrix()
+        err = np.linalg.norm(lam * R - E.conj().T) / np.linalg.norm(E.conj().T)
+        assert err <= 1.01 * gnorm / lam
+        if prev is not None:
+            assert err < prev
+        prev = err
+
+
+# --- P5: closed-form diagonal and trace; Hermitian PSD Gram (Sec. 2.2) ---------
+
+@pytest.mark.parametrize("kw", [dict(C=1), dict(C=3), dict(C=2, species=[0.0, 150.0], b0=True)])
+def test_p5_closed_form_diagonal(kw):
+    enc = tiny_enc(seed=13, **kw)
+    G = oracle.gram(enc)
+    coilpow = np.ones(enc.V) if enc.coil is None else np.sum(np.abs(enc.coil) ** 2, axis=0)
+    want = enc.K * np.tile(coilpow, enc.S)
+    assert np.max(np.abs(G.diagonal() - want)) < 1e-12 * np.max(want)
+    assert abs(np.trace(G).real - enc.K * enc.S * coilpow.sum()) < 1e-11 * enc.K * enc.S * coilpow.sum()
+    assert np.max(np.abs(G - G.conj().T)) < 1e-12 * np.max(want)
+    assert np.linalg.eigvalsh(G).min() > -1e-10 * np.max(want)
+
+
+# --- P6: coil-sum identity (Eq. 11) --------------------------------------------
+
+def test_p6_coil_sum_identity():
+    enc = tiny_enc(seed=14, C=3)
+    G = oracle.gram(enc)
+    d = synth.unit_complex_noise((2, enc.M), np.random.default_rng(1))
+    b = oracle.adjoint(enc, d)
+    Gs = np.zeros_like(G)
+    bs = np.zeros_like(b)
+    for c in range(enc.C):
+        ec = synth.Encoding(enc.nx, enc.ny, enc.k, coil=enc.coil[c:c + 1])
+        Gs += oracle.gram(ec)
+        bs += oracle.adjoint(ec, d[:, c * enc.K:(c + 1) * enc.K])
+    assert rel(Gs, G) < 1e-14
+    assert rel(bs, b) < 1e-14
+
+
+def test_forward_is_adjoint_of_adjoint():
+    enc = tiny_enc(seed=15, C=2, species=[0.0, 80.0, 200.0], b0=True)
+    rng = np.random.default_rng(2)
+    x = synth.unit_complex_noise((1, enc.N), rng)
+    d = synth.unit_complex_noise((1, enc.M), rng)
+    lhs = np.vdot(d, oracle.forward(enc, x))
+    rhs = np.vdot(oracle.adjoint(enc, d), x)
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+# --- P7: normal-equation residual (Eq. 6) --------------------------------------
+
+@pytest.mark.parametrize("kw", [dict(C=1), dict(C=3), dict(C=2, species=[0.0, 150.0], b0=True)])
+def test_p7_normal_equation_residual(kw):
+    enc = tiny_enc(seed=16, K=70, **kw)
+    b = oracle.Build(enc, rel=1e-3)
+    d = synth.unit_complex_noise((3, enc.M), np.random.default_rng(5))
+    x = b.reconstruct(d)
+    r = b.normal_residual(d, x)
+    ehd = oracle.adjoint(enc, d)
+    assert np.max(np.linalg.norm(r, axis=1) / np.linalg.norm(ehd, axis=1)) < 1e-12
+
+
+# --- P8: push-through identity between over- and underdetermined forms ---------
+
+def test_p8_push_through():
+    enc = tiny_enc(seed=17)
+    E = oracle.encoding_matrix(enc)
+    lam = 0.7
+    R = oracle.Build(enc, lam=lam).recon_matrix()
+    M = E.shape[0]
+    R2 = E.conj().T @ np.linalg.solve(E @ E.conj().T + lam * np.eye(M), np.eye(M))
+    assert rel(R, R2) < 1e-12
+
+
+# --- P9: decomposition independence: eigen route (Eq. 7) -----------------------
+
+def test_p9_eigen_route():
+    enc = tiny_enc(seed=18, C=3)
+    E = oracle.encoding_matrix(enc)
+    lam = 0.05 * np.trace(E.conj().T @ E).real / E.shape[1]
+    G = E.conj().T @ E + lam * np.eye(E.shape[1])
+    w, P = np.linalg.eigh(G)
+    R_eig = (P / w) @ P.conj().T @ E.conj().T
+    R = oracle.Build(enc, lam=lam).recon_matrix()
+    assert rel(R, R_eig) < 1e-12
+
+
+# --- P10: SRF identity (Eq. 9) -------------------------------------------------
+
+def test_p10_srf():
+    enc = tiny_enc(seed=19, C=2)
+    lam = 0.4
+    b = oracle.Build(enc, lam=lam)
+    E = oracle.encoding_matrix(enc)
+    srf = oracle.srf_matrix(b.recon_matrix(), E)
+    Gl = E.conj().T @ E + lam * np.eye(E.shape[1])
+    want = np.eye(E.shape[1]) - lam * np.linalg.inv(Gl)
+    assert rel(srf, want) < 1e-12
+    dg = srf.diagonal()
+    assert np.all(dg.real > 0) and np.all(dg.real <= 1 + 1e-12) and np.max(np.abs(dg.imag)) < 1e-12
+    n = 4
+    cb = oracle.Build(cartesian_enc(n), lam=lam)
+    srf_c = oracle.srf_matrix(cb.recon_matrix(), oracle.encoding_matrix(cartesian_enc(n)))
+    N = n * n
+    assert np.max(np.abs(srf_c - N / (N + lam) * np.eye(N))) < 1e-13
+
+
+def test_noise_matrix_white_noise():
+    """With Psi = I the noise matrix equals G_l^-1 - lam G_l^-2 (Eq. 10)."""
+    enc = tiny_enc(seed=20)
+    lam = 0.3
+    E = oracle.encoding_matrix(enc)
+    R = oracle.Build(enc, lam=lam).recon_matrix()
+    X = oracle.noise_matrix(R, np.eye(E.shape[0]))
+    Gi = np.linalg.inv(E.conj().T @ E + lam * np.eye(E.shape[1]))
+    assert rel(X, Gi - lam * Gi @ Gi) < 1e-11
+
+
+# --- Cholesky failure and determinism ------------------------------------------
+
+def test_not_pd_without_regularisation_when_underdetermined():
+    enc = tiny_enc(seed=21, C=1, K=12)     # M=12 < N=30 -> rank deficient Gram
+    with pytest.raises(oracle.NotPositiveDefinite) as ei:
+        oracle.Build(enc, lam=0.0)
+    assert 12 <= ei.value.column < 30
+
+
+def test_cholesky_matches_numpy():
+    rng = np.random.default_rng(22)
+    A = rng.standard_normal((40, 40)) + 1j * rng.standard_normal((40, 40))
+    H = A @ A.conj().T + 40 * np.eye(40)
+    L = oracle.cholesky(H)
+    assert rel(L, np.linalg.cholesky(H)) < 1e-14
+
+
+def test_thread_count_independence():
+    threadpoolctl = pytest.importorskip("threadpoolctl")
+    enc = tiny_enc(seed=23, nx=12, ny=10, C=3, K=300)
+    d = synth.unit_complex_noise((2, enc.M), np.random.default_rng(6))
+    with threadpoolctl.threadpool_limits(1):
+        x1 = oracle.reconstruct(enc, d, rel=1e-3)
+    with threadpoolctl.threadpool_limits(4):
+        x4 = oracle.reconstruct(enc, d, rel=1e-3)
+    assert rel(x1, x4) < 1e-13
+
+
+# --- planted mistakes are caught (the mistake is planted in a copy of the oracle
+#     on the CPU; the pins above must reject it) ---------------------------------
+
+def test_planted_sign_error_is_caught(monkeypatch):
+    import oracle.pinv_oracle as po
+    orig = po.encoding_rows
+
+    def flipped(enc, m0, m1):
+        return orig(enc, m0, m1).conj()     # exp(+i...) instead of exp(-i...) (coil-free case)
+    monkeypatch.setattr(po, "encoding_rows", flipped)
+    n = 8
+    enc = cartesian_enc(n)
+    x = synth.unit_complex_noise((1, n * n), np.random.default_rng(8))
+    d = po.forward(enc, x)[0].reshape(n, n)
+    ref = np.fft.fftshift(np.fft.fft2(np.fft.ifftshift(x[0].reshape(n, n))))
+    assert rel(d, ref) > 0.5
+
+
+def test_planted_transpose_in_cholesky_is_caught(monkeypatch):
+    import oracle.pinv_oracle as po
+    orig = po.cholesky
+    monkeypatch.setattr(po, "cholesky", lambda A: orig(A).conj())
+    enc = tiny_enc(seed=0)
+    E = po.encoding_matrix(enc)
+    U, s, Vh = np.linalg.svd(E, full_matrices=False)
+    R_svd = (Vh.conj().T * (s / (s * s + 0.3))) @ U.conj().T
+    R = po.Build(enc, lam=0.3).recon_matrix()
+    assert rel(R, R_svd) > 1e-6
