@@ -1,0 +1,195 @@
+/*
+ * pinv.h -- C-ABI of libpinv, the Pinv-Recon hot path on AMD MI355X (gfx950).
+ *
+ * The library computes the regularised pseudoinverse of an MRI encoding matrix
+ * E by the Cholesky route and applies it to k-space frames:
+ *
+ *     data  = E x                                      (paper Eq. 1)
+ *     R     = (E^H E + lambda I)^-1 E^H                (Eq. 6, normal equations)
+ *     E^H E + lambda I = L L^H,  R = L^-H L^-1 E^H     (Eq. 8, Cholesky route)
+ *     image = R data                                   (Eq. 3)
+ *
+ * `lambda` here is the diagonal shift itself (the paper writes it lambda^2).
+ * R depends on the encoding only, so it is built once and applied to any
+ * number of frames and acquisitions (Sec. 4.5; Sec. 5).
+ *
+ * The encoding element (Eq. 2 with the coil, chemical-shift and off-resonance
+ * factors of Sec. 3.3 multiplied in; sign convention exp(-i 2 pi ...)):
+ *
+ *     E[m, n] = C_c(v) exp(-i 2 pi (k_i . r_v + (f_s + B0(v)) t_i))
+ *     m = c*nk + i          (coil-major rows, i = sample within a coil)
+ *     n = s*V + v,  v = iy*nx + ix,  V = nx*ny   (species-major columns)
+ *     r_v = ((ix - nx/2)/nx, (iy - ny/2)/ny)     (field-of-view units)
+ *     k in cycles per field of view, f_s and B0 in Hz, t in seconds.
+ *
+ * Conventions for every entry point:
+ *   - Status codes only: no exceptions or aborts cross this ABI.  The detail
+ *     of the last failure on the calling thread is in pinv_last_error().
+ *   - "host" pointers are read during the call and may be freed on return.
+ *   - "device" pointers are HIP device memory owned by the caller; they must
+ *     stay valid until the work enqueued on `hip_stream` has completed.
+ *   - `hip_stream` is a hipStream_t (NULL = the default stream).  Work is
+ *     enqueued asynchronously; nothing blocks unless stated.
+ *   - Complex arrays are interleaved (re, im) pairs, row-major:
+ *     complex64 (float2) for FP32 and BF16X3 plans, complex128 (double2)
+ *     for FP64 plans.
+ */
+#ifndef PINV_H
+#define PINV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PINV_OK = 0,
+  PINV_ERR_INVALID = 1,     /* bad argument or encoding */
+  PINV_ERR_NOMEM = 2,       /* device memory or the context budget exhausted */
+  PINV_ERR_NOT_PD = 3,      /* a Cholesky pivot was <= 0 or NaN (message names the column) */
+  PINV_ERR_DEVICE = 4,      /* a HIP runtime error */
+  PINV_ERR_BUSY = 5,        /* the plan is still building (non-blocking query) */
+  PINV_ERR_UNSUPPORTED = 6  /* a valid request this build does not implement */
+} pinv_status;
+
+typedef enum {
+  PINV_FP64 = 0,    /* everything in FP64 (complex128 data and images) */
+  PINV_FP32 = 1,    /* Gram, R and apply on FP32 MFMA; factorisation in FP64 */
+  PINV_BF16X3 = 2   /* as FP32 but products as three BF16 MFMAs (hi*hi + hi*lo + lo*hi) */
+} pinv_precision;
+
+typedef enum {
+  PINV_LAMBDA_ABS = 0,           /* lambda is the absolute diagonal shift */
+  PINV_LAMBDA_REL_MEAN_DIAG = 1  /* shift = lambda * trace(E^H E) / N (= lambda * mean diagonal) */
+} pinv_lambda_mode;
+
+/* Encoding description (all host pointers, FP64; copied during pinv_build).
+ * Defines E as above (Eq. 2; Sec. 3.3 generalised encoding; Eq. 11 coil rows). */
+typedef struct {
+  int32_t nx, ny;             /* image grid, nx, ny >= 1 */
+  int64_t nk;                 /* samples per coil, >= 1 */
+  const double *k;            /* [nk][2] (kx, ky) in cycles/FOV; required */
+  const double *t;            /* [nk] sample times in s; required if nspecies > 1,
+                                 species_hz != NULL or b0_hz != NULL */
+  int32_t ncoil;              /* C >= 1 */
+  const double *coil;         /* [C][V][2] complex sensitivities; NULL => C == 1, all ones */
+  const double *b0_hz;        /* [V] off-resonance in Hz, or NULL */
+  int32_t nspecies;           /* S >= 1 */
+  const double *species_hz;   /* [S] species frequencies in Hz, or NULL (=> S == 1 at 0 Hz) */
+} pinv_encoding;
+
+#define PINV_FLAG_KEEP_GRAM 1   /* keep a copy of E^H E (lower, FP64) for inspection */
+#define PINV_FLAG_UNCACHED 2    /* build a fresh plan outside the cache (freed on its last release) */
+
+typedef struct {
+  double lambda;              /* >= 0; meaning set by lambda_mode */
+  int32_t lambda_mode;        /* pinv_lambda_mode */
+  int32_t prec;               /* pinv_precision */
+  int32_t flags;              /* PINV_FLAG_* */
+  int32_t reserved;           /* must be 0 */
+} pinv_build_opts;
+
+typedef struct {
+  int64_t N, M;               /* unknowns S*V and rows C*nk */
+  double lambda_abs;          /* the diagonal shift actually used */
+  int32_t prec;               /* pinv_precision */
+  int32_t ready;              /* 1 once pinv_plan_wait has returned PINV_OK */
+  uint64_t key;               /* cache key (hash of encoding, shift and precision) */
+  size_t device_bytes;        /* device memory the plan holds */
+  float stage_ms[4];          /* Gram, Cholesky+inverse, W = L^-1 E^H, R = L^-H W
+                                 (HIP event times on the build stream; valid when ready) */
+} pinv_plan_info;
+
+typedef struct {
+  const void *plan;           /* const pinv_plan* */
+  const void *data;           /* device [F][M] */
+  void *image;                /* device [F][N] */
+  int64_t F;                  /* frames >= 0 */
+} pinv_apply_item;
+
+typedef struct pinv_context pinv_context;
+typedef struct pinv_plan pinv_plan;
+
+/* Create a context on HIP device `device`.  It owns the plan cache and an HBM
+ * budget: `hbm_budget_bytes` (0 = 90% of the device memory free at creation).
+ * Errors: INVALID (bad device), DEVICE. */
+pinv_status pinv_context_create(int device, size_t hbm_budget_bytes, pinv_context **out);
+
+/* Destroy a context: synchronises the device and frees every cached plan.
+ * Plans the caller still holds become invalid. */
+pinv_status pinv_context_destroy(pinv_context *ctx);
+
+/* Build (or fetch from the cache) R for encoding `e` (Eq. 6, Eq. 8).
+ * Enqueues on `hip_stream` and returns at once with a new reference to the
+ * plan in *out (release it with pinv_plan_release).  A plan with the same key
+ * already in the cache is returned without new work.  Admission: if the plan's
+ * footprint exceeds the free budget, least-recently-used cached plans that no
+ * caller holds are evicted; if that is not enough, NOMEM.
+ * Errors: INVALID (bad encoding, lambda < 0, lambda == 0 with M < N),
+ * NOMEM, DEVICE.  A non-positive-definite shifted Gram is reported by
+ * pinv_plan_wait as NOT_PD. */
+pinv_status pinv_build(pinv_context *ctx, const pinv_encoding *e, const pinv_build_opts *o,
+                       void *hip_stream, pinv_plan **out);
+
+/* Block until the plan's build has finished; returns its outcome
+ * (OK, NOT_PD with the failing column in pinv_last_error, DEVICE). */
+pinv_status pinv_plan_wait(pinv_plan *p);
+
+/* image[f] = R data[f] for F frames (Eq. 3), enqueued on `hip_stream` behind
+ * the plan's build.  data: device [F][M], image: device [F][N], dtype of the
+ * plan (see conventions).  refine_steps (0..4) adds iterative refinement on
+ * the normal equations (Eq. 6): r = E^H (d - E x) - lambda x in FP64 with E
+ * regenerated in FP64, then x += L^-H L^-1 r.  The result for a frame does not
+ * depend on F or on the other frames.  Errors: INVALID, NOMEM (scratch), DEVICE. */
+pinv_status pinv_apply(pinv_context *ctx, const pinv_plan *p, const void *data, int64_t F,
+                       void *image, int32_t refine_steps, void *hip_stream);
+
+/* Several applies (possibly of different plans and sizes) in grouped launches:
+ * one MFMA launch per run of up to 32 items of the same precision.  Each
+ * item's result equals what pinv_apply gives for it alone.  Errors as
+ * pinv_apply. */
+pinv_status pinv_apply_grouped(pinv_context *ctx, int32_t n, const pinv_apply_item *items,
+                               int32_t refine_steps, void *hip_stream);
+
+/* Forward model data[f] = E image[f] (Eq. 1) in the plan's precision, with E
+ * generated on the fly.  image: device [F][N], data: device [F][M]. */
+pinv_status pinv_forward(pinv_context *ctx, const pinv_plan *p, const void *image, int64_t F,
+                         void *data, void *hip_stream);
+
+/* Plan metadata; stage_ms are filled once the plan is ready. */
+pinv_status pinv_plan_info_get(const pinv_plan *p, pinv_plan_info *out);
+
+/* Device pointers held by a ready plan (any may be NULL on output):
+ *   R     [N][M] complex, the reconstruction matrix
+ *   Linv  [N][N] complex, L^-1 (lower; FP32 plans hold it as complex64)
+ *   gram  [N][N] complex128, E^H E (lower part valid; only with PINV_FLAG_KEEP_GRAM)
+ * The memory stays owned by the plan. */
+pinv_status pinv_plan_buffers(const pinv_plan *p, void **R, void **Linv, void **gram);
+
+/* Copy one of the plan's buffers (0 = R, 1 = L^-1, 2 = Gram) into caller
+ * device memory `dst` of `bytes` bytes (must equal the buffer's size:
+ * N*M or N*N complex of the plan's type; the Gram is complex128), enqueued on
+ * `hip_stream` behind the build.  Errors: INVALID (size or missing buffer). */
+pinv_status pinv_plan_copy_buffer(const pinv_plan *p, int32_t which, void *dst, size_t bytes,
+                                  void *hip_stream);
+
+/* Drop one reference.  The last reference held by neither a caller nor the
+ * cache frees the plan once its enqueued work has completed. */
+pinv_status pinv_plan_release(pinv_plan *p);
+
+/* Evict every cached plan no caller holds; returns the bytes freed in *freed. */
+pinv_status pinv_cache_trim(pinv_context *ctx, size_t *freed);
+
+/* Budget accounting: bytes in use by plans and the budget. */
+pinv_status pinv_context_usage(const pinv_context *ctx, size_t *used, size_t *budget,
+                               int32_t *cached_plans);
+
+const char *pinv_status_string(pinv_status s);
+const char *pinv_last_error(void);   /* thread-local detail of the last failure */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PINV_H */

@@ -1,0 +1,733 @@
+// C-ABI of libpinv: contexts, plan cache with HBM admission, encoding tables,
+// and the build / apply / forward pipelines.  Every arithmetic step of the
+// path runs in the kernels of pinv_kernels.hip.
+#include <math.h>
+#include <string.h>
+
+#include <atomic>
+#include <cstdio>
+#include <list>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/pinv.h"
+#include "pinv_internal.h"
+
+using namespace pinv;
+
+static thread_local std::string g_last_error;
+
+static pinv_status fail(pinv_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+#define HIPCHK(expr)                                                                 \
+  do {                                                                               \
+    hipError_t _e = (expr);                                                          \
+    if (_e != hipSuccess)                                                            \
+      return fail(_e == hipErrorOutOfMemory ? PINV_ERR_NOMEM : PINV_ERR_DEVICE,      \
+                  std::string(#expr) + ": " + hipGetErrorString(_e));                \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// objects
+// ---------------------------------------------------------------------------
+struct pinv_plan {
+  pinv_context* ctx = nullptr;
+  std::atomic<int> refs{0};
+  bool cached = false;
+  uint64_t key = 0;
+  int prec = PINV_FP32;
+  int N = 0, M = 0, K = 0, C = 0, S = 0, V = 0, nx = 0, ny = 0;
+  double lam = 0.0;
+  // device memory held for the plan's lifetime
+  void* tab32 = nullptr;
+  void* tab64 = nullptr;
+  EncDev<float> e32{};
+  EncDev<double> e64{};
+  void* R = nullptr;
+  void* Linv = nullptr;      // complex64 for FP32/BF16X3 plans, complex128 for FP64
+  void* gram = nullptr;      // only with PINV_FLAG_KEEP_GRAM
+  int* info = nullptr;
+  std::vector<void*> host_stage;   // pinned staging of the tables, freed once the build is done
+  size_t bytes = 0;
+  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  bool waited = false;
+  pinv_status status = PINV_OK;
+  int info_host = 0;
+  float stage_ms[4] = {0, 0, 0, 0};
+  std::list<pinv_plan*>::iterator lru_it;
+};
+
+struct pinv_context {
+  int device = 0;
+  size_t budget = 0;
+  size_t used = 0;
+  std::mutex mu;
+  std::unordered_map<uint64_t, pinv_plan*> cache;
+  std::list<pinv_plan*> lru;   // front = most recently used
+};
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+namespace {
+
+// FNV-1a 64-bit hash (Fowler, Noll, Vo) over raw bytes.
+struct Fnv {
+  uint64_t h = 1469598103934665603ull;
+  void add(const void* p, size_t n) {
+    const unsigned char* b = (const unsigned char*)p;
+    for (size_t i = 0; i < n; ++i) {
+      h ^= b[i];
+      h *= 1099511628211ull;
+    }
+  }
+  template <typename X> void add(const X& x) { add(&x, sizeof(X)); }
+};
+
+size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
+struct Dims {
+  int nx, ny, V, S, C, K, N, M;
+  bool has_q, has_coil, has_b0;
+};
+
+pinv_status validate(const pinv_encoding* e, Dims* d) {
+  if (!e) return fail(PINV_ERR_INVALID, "encoding is NULL");
+  if (e->nx < 1 || e->ny < 1) return fail(PINV_ERR_INVALID, "nx and ny must be >= 1");
+  if (e->nk < 1) return fail(PINV_ERR_INVALID, "nk must be >= 1");
+  if (!e->k) return fail(PINV_ERR_INVALID, "k is NULL");
+  if (e->ncoil < 1) return fail(PINV_ERR_INVALID, "ncoil must be >= 1");
+  if (e->nspecies < 1) return fail(PINV_ERR_INVALID, "nspecies must be >= 1");
+  if (e->ncoil > 1 && !e->coil) return fail(PINV_ERR_INVALID, "ncoil > 1 needs coil maps");
+  if (e->nspecies > 1 && !e->species_hz)
+    return fail(PINV_ERR_INVALID, "nspecies > 1 needs species_hz");
+  const bool need_t = e->nspecies > 1 || e->species_hz != nullptr || e->b0_hz != nullptr;
+  if (need_t && !e->t) return fail(PINV_ERR_INVALID, "sample times t are required with species or B0");
+  const long long V = (long long)e->nx * e->ny;
+  const long long N = V * e->nspecies;
+  const long long M = (long long)e->ncoil * e->nk;
+  if (N > 65536) return fail(PINV_ERR_UNSUPPORTED, "N = S*nx*ny above 65536");
+  if (M > (1LL << 30)) return fail(PINV_ERR_UNSUPPORTED, "M = C*nk above 2^30");
+  d->nx = e->nx;
+  d->ny = e->ny;
+  d->V = (int)V;
+  d->S = e->nspecies;
+  d->C = e->ncoil;
+  d->K = (int)e->nk;
+  d->N = (int)N;
+  d->M = (int)M;
+  bool q = false;
+  if (e->species_hz)
+    for (int s = 0; s < e->nspecies; ++s) q = q || e->species_hz[s] != 0.0;
+  d->has_q = q || e->nspecies > 1;
+  d->has_coil = e->coil != nullptr;
+  d->has_b0 = e->b0_hz != nullptr;
+  for (long long i = 0; i < 2 * (long long)e->nk; ++i)
+    if (!isfinite(e->k[i])) return fail(PINV_ERR_INVALID, "non-finite k");
+  return PINV_OK;
+}
+
+uint64_t plan_key(const pinv_encoding* e, const Dims& d, double lam, int prec) {
+  Fnv f;
+  f.add(d.nx);
+  f.add(d.ny);
+  f.add(d.K);
+  f.add(d.C);
+  f.add(d.S);
+  f.add(e->k, sizeof(double) * 2 * d.K);
+  f.add(uint8_t(e->t != nullptr));
+  if (e->t) f.add(e->t, sizeof(double) * d.K);
+  f.add(uint8_t(e->coil != nullptr));
+  if (e->coil) f.add(e->coil, sizeof(double) * 2 * (size_t)d.C * d.V);
+  f.add(uint8_t(e->b0_hz != nullptr));
+  if (e->b0_hz) f.add(e->b0_hz, sizeof(double) * d.V);
+  f.add(uint8_t(e->species_hz != nullptr));
+  if (e->species_hz) f.add(e->species_hz, sizeof(double) * d.S);
+  f.add(lam);
+  f.add(prec);
+  return f.h;
+}
+
+// exp(-i 2 pi turns) with the turn count reduced to (-1/2, 1/2] first.
+inline void phasor(double turns, double* re, double* im) {
+  const double f = turns - nearbyint(turns);
+  *re = cos(2.0 * M_PI * f);
+  *im = -sin(2.0 * M_PI * f);
+}
+
+// Host FP64 tables (Px, Py, Q, coil, b0, t), laid out contiguously.
+struct HostTables {
+  std::vector<double> px, py, q, coil, b0, t;
+};
+
+void build_tables(const pinv_encoding* e, const Dims& d, HostTables* h) {
+  h->px.resize(2 * (size_t)d.K * d.nx);
+  h->py.resize(2 * (size_t)d.K * d.ny);
+  for (int i = 0; i < d.K; ++i) {
+    const double kx = e->k[2 * i], ky = e->k[2 * i + 1];
+    for (int ix = 0; ix < d.nx; ++ix) {
+      const double x = (ix - d.nx / 2.0) / d.nx;
+      phasor(kx * x, &h->px[2 * ((size_t)i * d.nx + ix)], &h->px[2 * ((size_t)i * d.nx + ix) + 1]);
+    }
+    for (int iy = 0; iy < d.ny; ++iy) {
+      const double y = (iy - d.ny / 2.0) / d.ny;
+      phasor(ky * y, &h->py[2 * ((size_t)i * d.ny + iy)], &h->py[2 * ((size_t)i * d.ny + iy) + 1]);
+    }
+  }
+  if (d.has_q) {
+    h->q.resize(2 * (size_t)d.K * d.S);
+    for (int i = 0; i < d.K; ++i)
+      for (int s = 0; s < d.S; ++s) {
+        const double f = e->species_hz ? e->species_hz[s] : 0.0;
+        phasor(f * e->t[i], &h->q[2 * ((size_t)i * d.S + s)], &h->q[2 * ((size_t)i * d.S + s) + 1]);
+      }
+  }
+  if (d.has_coil) h->coil.assign(e->coil, e->coil + 2 * (size_t)d.C * d.V);
+  if (d.has_b0) {
+    h->b0.assign(e->b0_hz, e->b0_hz + d.V);
+    h->t.assign(e->t, e->t + d.K);
+  }
+}
+
+// Upload tables as type T into one device allocation; fill the EncDev view.
+template <typename T>
+pinv_status upload_tables(const HostTables& h, const Dims& d, hipStream_t s, void** dev,
+                          EncDev<T>* ev, std::vector<void*>* host_keep) {
+  const size_t n_px = h.px.size(), n_py = h.py.size(), n_q = h.q.size(), n_c = h.coil.size(),
+               n_b = h.b0.size(), n_t = h.t.size();
+  size_t off[6], tot = 0;
+  const size_t ns[6] = {n_px, n_py, n_q, n_c, n_b, n_t};
+  for (int i = 0; i < 6; ++i) {
+    off[i] = tot;
+    tot += align256(ns[i] * sizeof(T));
+  }
+  void* host = nullptr;
+  HIPCHK(hipHostMalloc(&host, tot, hipHostMallocDefault));
+  host_keep->push_back(host);
+  const std::vector<double>* src[6] = {&h.px, &h.py, &h.q, &h.coil, &h.b0, &h.t};
+  for (int i = 0; i < 6; ++i) {
+    T* dst = (T*)((char*)host + off[i]);
+    for (size_t j = 0; j < ns[i]; ++j) dst[j] = (T)(*src[i])[j];
+  }
+  HIPCHK(hipMalloc(dev, tot));
+  HIPCHK(hipMemcpyAsync(*dev, host, tot, hipMemcpyHostToDevice, s));
+  char* b = (char*)*dev;
+  ev->px = (const T*)(b + off[0]);
+  ev->py = (const T*)(b + off[1]);
+  ev->q = n_q ? (const T*)(b + off[2]) : nullptr;
+  ev->coil = n_c ? (const T*)(b + off[3]) : nullptr;
+  ev->b0 = n_b ? (const T*)(b + off[4]) : nullptr;
+  ev->t = n_t ? (const T*)(b + off[5]) : nullptr;
+  ev->nx = d.nx;
+  ev->ny = d.ny;
+  ev->S = d.S;
+  ev->C = d.C;
+  ev->K = d.K;
+  ev->V = d.V;
+  ev->M = d.M;
+  ev->N = d.N;
+  return PINV_OK;
+}
+
+void free_host_stage(pinv_plan* p) {
+  for (void* h : p->host_stage) (void)hipHostFree(h);
+  p->host_stage.clear();
+}
+
+void free_plan_memory(pinv_plan* p) {
+  if (p->ev[4]) (void)hipEventSynchronize(p->ev[4]);
+  free_host_stage(p);
+  for (void* q : {p->tab32, p->tab64, p->R, p->Linv, p->gram, (void*)p->info})
+    if (q) (void)hipFree(q);
+  for (auto& e : p->ev)
+    if (e) (void)hipEventDestroy(e);
+}
+
+size_t plan_footprint(const Dims& d, int prec, bool keep_gram) {
+  const size_t N = d.N, M = d.M;
+  const size_t cs = prec == PINV_FP64 ? 16 : 8;
+  size_t b = 0;
+  b += 16 * N * N;              // Gram / factor workspace (FP64)
+  b += 16 * N * N;              // L^-1 in FP64 during the factorisation
+  b += cs * N * N;              // L^-1 kept
+  b += cs * N * M;              // W
+  b += cs * N * M;              // R
+  if (keep_gram) b += 16 * N * N;
+  b += 64ull << 20;             // tables and slack
+  return b;
+}
+
+size_t plan_resident(const Dims& d, int prec, bool keep_gram) {
+  const size_t N = d.N, M = d.M;
+  const size_t cs = prec == PINV_FP64 ? 16 : 8;
+  return cs * N * M + cs * N * N + (keep_gram ? 16 * N * N : 0) + (16ull << 20);
+}
+
+// Evict LRU plans held only by the cache until `need` bytes fit.  ctx->mu held.
+bool make_room(pinv_context* c, size_t need) {
+  if (c->used + need <= c->budget) return true;
+  for (auto it = c->lru.end(); it != c->lru.begin();) {
+    --it;
+    pinv_plan* p = *it;
+    if (p->refs.load() == 1 && p->cached) {   // only the cache holds it
+      c->cache.erase(p->key);
+      it = c->lru.erase(it);
+      c->used -= p->bytes;
+      free_plan_memory(p);
+      delete p;
+      if (c->used + need <= c->budget) return true;
+    }
+  }
+  return c->used + need <= c->budget;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C-ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* pinv_status_string(pinv_status s) {
+  switch (s) {
+    case PINV_OK: return "ok";
+    case PINV_ERR_INVALID: return "invalid argument";
+    case PINV_ERR_NOMEM: return "out of device memory or budget";
+    case PINV_ERR_NOT_PD: return "shifted Gram matrix is not positive definite";
+    case PINV_ERR_DEVICE: return "device error";
+    case PINV_ERR_BUSY: return "busy";
+    case PINV_ERR_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* pinv_last_error(void) { return g_last_error.c_str(); }
+
+pinv_status pinv_context_create(int device, size_t budget, pinv_context** out) {
+  if (!out) return fail(PINV_ERR_INVALID, "out is NULL");
+  int n = 0;
+  HIPCHK(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) return fail(PINV_ERR_INVALID, "no such device");
+  HIPCHK(hipSetDevice(device));
+  size_t fr = 0, tot = 0;
+  HIPCHK(hipMemGetInfo(&fr, &tot));
+  pinv_context* c = new pinv_context();
+  c->device = device;
+  c->budget = budget ? budget : (size_t)(0.9 * (double)fr);
+  *out = c;
+  return PINV_OK;
+}
+
+pinv_status pinv_context_destroy(pinv_context* c) {
+  if (!c) return fail(PINV_ERR_INVALID, "context is NULL");
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  {
+    std::lock_guard<std::mutex> g(c->mu);
+    for (pinv_plan* p : c->lru) {
+      free_plan_memory(p);
+      delete p;
+    }
+    c->lru.clear();
+    c->cache.clear();
+  }
+  delete c;
+  return PINV_OK;
+}
+
+pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build_opts* o,
+                       void* stream, pinv_plan** out) {
+  if (!c || !o || !out) return fail(PINV_ERR_INVALID, "NULL argument");
+  Dims d;
+  pinv_status st = validate(e, &d);
+  if (st != PINV_OK) return st;
+  if (o->prec != PINV_FP64 && o->prec != PINV_FP32 && o->prec != PINV_BF16X3)
+    return fail(PINV_ERR_INVALID, "unknown precision");
+  if (o->prec == PINV_BF16X3) return fail(PINV_ERR_UNSUPPORTED, "BF16X3 plans are not built yet");
+  if (o->reserved != 0) return fail(PINV_ERR_INVALID, "reserved must be 0");
+  if (!(o->lambda >= 0.0) || !isfinite(o->lambda)) return fail(PINV_ERR_INVALID, "lambda must be finite and >= 0");
+  double lam = o->lambda;
+  if (o->lambda_mode == PINV_LAMBDA_REL_MEAN_DIAG) {
+    // trace(E^H E) = K * S * sum_v sum_c |C_c(v)|^2 since every phase factor has modulus 1
+    double cp = 0.0;
+    if (e->coil) {
+      for (size_t i = 0; i < (size_t)d.C * d.V; ++i)
+        cp += e->coil[2 * i] * e->coil[2 * i] + e->coil[2 * i + 1] * e->coil[2 * i + 1];
+    } else {
+      cp = (double)d.V;
+    }
+    lam = o->lambda * (double)d.K * d.S * cp / (double)d.N;
+  } else if (o->lambda_mode != PINV_LAMBDA_ABS) {
+    return fail(PINV_ERR_INVALID, "unknown lambda_mode");
+  }
+  if (lam == 0.0 && d.M < d.N)
+    return fail(PINV_ERR_INVALID, "lambda = 0 needs M >= N (full column rank)");
+  const bool keep_gram = (o->flags & PINV_FLAG_KEEP_GRAM) != 0;
+  const uint64_t key = plan_key(e, d, lam, o->prec) ^ (keep_gram ? 0x9e3779b97f4a7c15ull : 0);
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(c->device));
+
+  const bool uncached = (o->flags & PINV_FLAG_UNCACHED) != 0;
+  std::lock_guard<std::mutex> g(c->mu);
+  auto hit = uncached ? c->cache.end() : c->cache.find(key);
+  if (hit != c->cache.end()) {
+    pinv_plan* p = hit->second;
+    p->refs++;
+    c->lru.erase(p->lru_it);
+    c->lru.push_front(p);
+    p->lru_it = c->lru.begin();
+    *out = p;
+    return PINV_OK;
+  }
+  const size_t foot = plan_footprint(d, o->prec, keep_gram);
+  if (!make_room(c, foot))
+    return fail(PINV_ERR_NOMEM, "plan footprint " + std::to_string(foot) +
+                                    " B exceeds the free budget");
+
+  pinv_plan* p = new pinv_plan();
+  p->ctx = c;
+  p->key = key;
+  p->prec = o->prec;
+  p->N = d.N;
+  p->M = d.M;
+  p->K = d.K;
+  p->C = d.C;
+  p->S = d.S;
+  p->V = d.V;
+  p->nx = d.nx;
+  p->ny = d.ny;
+  p->lam = lam;
+  std::vector<void*>& host_keep = p->host_stage;
+  auto cleanup = [&](pinv_status rs) {
+    (void)hipStreamSynchronize(s);
+    free_plan_memory(p);
+    delete p;
+    return rs;
+  };
+
+  HostTables ht;
+  build_tables(e, d, &ht);
+  const size_t N = d.N, M = d.M;
+  const bool f64 = o->prec == PINV_FP64;
+  const size_t cs = f64 ? 16 : 8;
+  void *G = nullptr, *L64 = nullptr, *W = nullptr;
+  hipError_t he;
+#define BCHK(expr)                                                                    \
+  do {                                                                                \
+    he = (expr);                                                                      \
+    if (he != hipSuccess) {                                                           \
+      fail(he == hipErrorOutOfMemory ? PINV_ERR_NOMEM : PINV_ERR_DEVICE,              \
+           std::string(#expr) + ": " + hipGetErrorString(he));                        \
+      if (G) (void)hipFreeAsync(G, s);                                                \
+      if (L64 && L64 != p->Linv) (void)hipFreeAsync(L64, s);                          \
+      if (W) (void)hipFreeAsync(W, s);                                                \
+      return cleanup(he == hipErrorOutOfMemory ? PINV_ERR_NOMEM : PINV_ERR_DEVICE);   \
+    }                                                                                 \
+  } while (0)
+
+  st = upload_tables<double>(ht, d, s, &p->tab64, &p->e64, &host_keep);
+  if (st != PINV_OK) return cleanup(st);
+  if (!f64) {
+    st = upload_tables<float>(ht, d, s, &p->tab32, &p->e32, &host_keep);
+    if (st != PINV_OK) return cleanup(st);
+  }
+  for (auto& ev : p->ev) BCHK(hipEventCreate(&ev));
+  BCHK(hipMalloc((void**)&p->info, sizeof(int)));
+  BCHK(hipMemsetAsync(p->info, 0, sizeof(int), s));
+  BCHK(hipMalloc(&p->R, cs * N * M));
+  BCHK(hipMalloc(&p->Linv, cs * N * N));
+  if (keep_gram) BCHK(hipMalloc(&p->gram, 16 * N * N));
+  BCHK(hipMallocAsync(&G, 16 * N * N, s));
+  if (f64) {
+    L64 = p->Linv;
+  } else {
+    BCHK(hipMallocAsync(&L64, 16 * N * N, s));
+  }
+  BCHK(hipMemsetAsync(L64, 0, 16 * N * N, s));
+  BCHK(hipMallocAsync(&W, cs * N * M, s));
+
+  // 1. Gram (a3) with E generated per tile (a2)
+  BCHK(hipEventRecord(p->ev[0], s));
+  if (f64)
+    BCHK(launch_gram<double>(p->e64, (double*)G, 0, s));
+  else
+    BCHK(launch_gram<float>(p->e32, (double*)G, 2048, s));
+  if (keep_gram) BCHK(hipMemcpyAsync(p->gram, G, 16 * N * N, hipMemcpyDeviceToDevice, s));
+  BCHK(hipEventRecord(p->ev[1], s));
+  // 2. shift + blocked Cholesky with L^-1 (a4), FP64
+  BCHK(launch_cholinv((double*)G, (double*)L64, d.N, lam, p->info, s));
+  if (!f64) BCHK(launch_to_f32((const double*)L64, (float*)p->Linv, N * N, s));
+  BCHK(hipEventRecord(p->ev[2], s));
+  // 3. W = L^-1 E^H, R = L^-H W (a5)
+  if (f64) {
+    BCHK(launch_trmm_w<double>(p->e64, (const double*)p->Linv, (double*)W, s));
+    BCHK(hipEventRecord(p->ev[3], s));
+    BCHK(launch_trmm_r<double>((const double*)p->Linv, (const double*)W, (double*)p->R, d.N, d.M, s));
+  } else {
+    BCHK(launch_trmm_w<float>(p->e32, (const float*)p->Linv, (float*)W, s));
+    BCHK(hipEventRecord(p->ev[3], s));
+    BCHK(launch_trmm_r<float>((const float*)p->Linv, (const float*)W, (float*)p->R, d.N, d.M, s));
+  }
+  BCHK(hipEventRecord(p->ev[4], s));
+  BCHK(hipFreeAsync(W, s));
+  W = nullptr;
+  BCHK(hipFreeAsync(G, s));
+  G = nullptr;
+  if (!f64) {
+    BCHK(hipFreeAsync(L64, s));
+  }
+  L64 = nullptr;
+#undef BCHK
+  // the pinned staging buffers stay with the plan until its build has finished
+
+  p->bytes = plan_resident(d, o->prec, keep_gram);
+  c->used += p->bytes;
+  if (uncached) {
+    p->refs = 1;   // the caller only
+    p->cached = false;
+  } else {
+    p->refs = 2;   // the cache and the caller
+    p->cached = true;
+    c->cache[key] = p;
+    c->lru.push_front(p);
+    p->lru_it = c->lru.begin();
+  }
+  *out = p;
+  return PINV_OK;
+}
+
+pinv_status pinv_plan_wait(pinv_plan* p) {
+  if (!p) return fail(PINV_ERR_INVALID, "plan is NULL");
+  if (!p->waited) {
+    HIPCHK(hipSetDevice(p->ctx->device));
+    HIPCHK(hipEventSynchronize(p->ev[4]));
+    HIPCHK(hipMemcpy(&p->info_host, p->info, sizeof(int), hipMemcpyDeviceToHost));
+    for (int i = 0; i < 4; ++i) HIPCHK(hipEventElapsedTime(&p->stage_ms[i], p->ev[i], p->ev[i + 1]));
+    p->status = p->info_host ? PINV_ERR_NOT_PD : PINV_OK;
+    p->waited = true;
+    free_host_stage(p);
+  }
+  if (p->status == PINV_ERR_NOT_PD)
+    return fail(PINV_ERR_NOT_PD, "Cholesky pivot <= 0 or NaN at column " +
+                                     std::to_string(p->info_host - 1));
+  return p->status;
+}
+
+// Refinement scratch and steps for one item (FP32 plan: complex64 data/images).
+static pinv_status refine_f32(pinv_plan* p, const void* data, int F, void* image, int steps,
+                              hipStream_t s) {
+  if (steps <= 0 || F <= 0) return PINV_OK;
+  const size_t N = p->N, M = p->M;
+  void *rd = nullptr, *r32 = nullptr, *t32 = nullptr;
+  HIPCHK(hipMallocAsync(&rd, 16 * (size_t)F * M, s));
+  HIPCHK(hipMallocAsync(&r32, 8 * (size_t)F * N, s));
+  HIPCHK(hipMallocAsync(&t32, 8 * (size_t)F * N, s));
+  for (int it = 0; it < steps; ++it) {
+    // rd = d - E x   (FP64, E regenerated from FP64 tables)
+    HIPCHK((launch_forward<double, float, float>(p->e64, (const float*)image, F, (const float*)data,
+                                                 (double*)rd, s)));
+    // r = E^H rd - lam x
+    HIPCHK((launch_adjoint<double, float, float>(p->e64, (const double*)rd, F, (const float*)image,
+                                                 p->lam, (float*)r32, s)));
+    // x += L^-H L^-1 r
+    HIPCHK((launch_tri_frames<float, 0, float>((const float*)p->Linv, (const float*)r32, F, p->N,
+                                               (float*)t32, s)));
+    HIPCHK((launch_tri_frames<float, 1, float>((const float*)p->Linv, (const float*)t32, F, p->N,
+                                               (float*)image, s)));
+  }
+  HIPCHK(hipFreeAsync(rd, s));
+  HIPCHK(hipFreeAsync(r32, s));
+  HIPCHK(hipFreeAsync(t32, s));
+  return PINV_OK;
+}
+
+static pinv_status refine_f64(pinv_plan* p, const void* data, int F, void* image, int steps,
+                              hipStream_t s) {
+  if (steps <= 0 || F <= 0) return PINV_OK;
+  const size_t N = p->N, M = p->M;
+  void *rd = nullptr, *r = nullptr, *t = nullptr;
+  HIPCHK(hipMallocAsync(&rd, 16 * (size_t)F * M, s));
+  HIPCHK(hipMallocAsync(&r, 16 * (size_t)F * N, s));
+  HIPCHK(hipMallocAsync(&t, 16 * (size_t)F * N, s));
+  for (int it = 0; it < steps; ++it) {
+    HIPCHK((launch_forward<double, double, double>(p->e64, (const double*)image, F,
+                                                   (const double*)data, (double*)rd, s)));
+    HIPCHK((launch_adjoint<double, double, double>(p->e64, (const double*)rd, F,
+                                                   (const double*)image, p->lam, (double*)r, s)));
+    HIPCHK((launch_tri_frames<double, 0, double>((const double*)p->Linv, (const double*)r, F, p->N,
+                                                 (double*)t, s)));
+    HIPCHK((launch_tri_frames<double, 1, double>((const double*)p->Linv, (const double*)t, F, p->N,
+                                                 (double*)image, s)));
+  }
+  HIPCHK(hipFreeAsync(rd, s));
+  HIPCHK(hipFreeAsync(r, s));
+  HIPCHK(hipFreeAsync(t, s));
+  return PINV_OK;
+}
+
+pinv_status pinv_apply_grouped(pinv_context* c, int32_t n, const pinv_apply_item* items,
+                               int32_t refine_steps, void* stream) {
+  if (!c || (n > 0 && !items) || n < 0) return fail(PINV_ERR_INVALID, "bad arguments");
+  if (refine_steps < 0 || refine_steps > 4) return fail(PINV_ERR_INVALID, "refine_steps in 0..4");
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(c->device));
+  for (int i = 0; i < n; ++i) {
+    const pinv_plan* p = (const pinv_plan*)items[i].plan;
+    if (!p || p->ctx != c) return fail(PINV_ERR_INVALID, "item " + std::to_string(i) + ": bad plan");
+    if (items[i].F < 0 || items[i].F > (1 << 24))
+      return fail(PINV_ERR_INVALID, "item " + std::to_string(i) + ": F out of range");
+    if (items[i].F > 0 && (!items[i].data || !items[i].image))
+      return fail(PINV_ERR_INVALID, "item " + std::to_string(i) + ": NULL buffer");
+    HIPCHK(hipStreamWaitEvent(s, p->ev[4], 0));
+  }
+  // grouped launches over runs of equal precision, up to kMaxGroup items each
+  int i = 0;
+  while (i < n) {
+    const int prec = ((const pinv_plan*)items[i].plan)->prec;
+    ApplyBatch b;
+    b.n = 0;
+    int tiles = 0;
+    while (i < n && b.n < kMaxGroup && ((const pinv_plan*)items[i].plan)->prec == prec) {
+      const pinv_plan* p = (const pinv_plan*)items[i].plan;
+      if (items[i].F > 0) {
+        ApplyItemDev& it = b.it[b.n++];
+        it.D = items[i].data;
+        it.R = p->R;
+        it.X = items[i].image;
+        it.F = (int)items[i].F;
+        it.N = p->N;
+        it.M = p->M;
+        it.tile0 = tiles;
+        tiles += prec == PINV_FP64 ? apply_tiles<double>(it.F, it.N) : apply_tiles<float>(it.F, it.N);
+      }
+      ++i;
+    }
+    if (b.n == 0) continue;
+    if (prec == PINV_FP64)
+      HIPCHK(launch_apply<double>(b, tiles, s));
+    else
+      HIPCHK(launch_apply<float>(b, tiles, s));
+  }
+  if (refine_steps > 0) {
+    for (int j = 0; j < n; ++j) {
+      pinv_plan* p = (pinv_plan*)items[j].plan;
+      pinv_status st = p->prec == PINV_FP64
+                           ? refine_f64(p, items[j].data, (int)items[j].F, items[j].image, refine_steps, s)
+                           : refine_f32(p, items[j].data, (int)items[j].F, items[j].image, refine_steps, s);
+      if (st != PINV_OK) return st;
+    }
+  }
+  return PINV_OK;
+}
+
+pinv_status pinv_apply(pinv_context* c, const pinv_plan* p, const void* data, int64_t F, void* image,
+                       int32_t refine_steps, void* stream) {
+  pinv_apply_item it{p, data, image, F};
+  return pinv_apply_grouped(c, 1, &it, refine_steps, stream);
+}
+
+pinv_status pinv_forward(pinv_context* c, const pinv_plan* pc, const void* image, int64_t F,
+                         void* data, void* stream) {
+  if (!c || !pc || F < 0 || (F > 0 && (!image || !data))) return fail(PINV_ERR_INVALID, "bad arguments");
+  pinv_plan* p = (pinv_plan*)pc;
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(c->device));
+  if (F == 0) return PINV_OK;
+  if (p->prec == PINV_FP64) {
+    HIPCHK((launch_forward<double, double, double>(p->e64, (const double*)image, (int)F, nullptr,
+                                                   (double*)data, s)));
+  } else {
+    HIPCHK((launch_forward<float, float, float>(p->e32, (const float*)image, (int)F, nullptr,
+                                                (float*)data, s)));
+  }
+  return PINV_OK;
+}
+
+pinv_status pinv_plan_info_get(const pinv_plan* p, pinv_plan_info* out) {
+  if (!p || !out) return fail(PINV_ERR_INVALID, "NULL argument");
+  out->N = p->N;
+  out->M = p->M;
+  out->lambda_abs = p->lam;
+  out->prec = p->prec;
+  out->ready = p->waited && p->status == PINV_OK;
+  out->key = p->key;
+  out->device_bytes = p->bytes;
+  for (int i = 0; i < 4; ++i) out->stage_ms[i] = p->waited ? p->stage_ms[i] : 0.f;
+  return PINV_OK;
+}
+
+pinv_status pinv_plan_buffers(const pinv_plan* p, void** R, void** Linv, void** gram) {
+  if (!p) return fail(PINV_ERR_INVALID, "plan is NULL");
+  if (R) *R = p->R;
+  if (Linv) *Linv = p->Linv;
+  if (gram) *gram = p->gram;
+  return PINV_OK;
+}
+
+pinv_status pinv_plan_copy_buffer(const pinv_plan* p, int32_t which, void* dst, size_t bytes,
+                                  void* stream) {
+  if (!p || !dst) return fail(PINV_ERR_INVALID, "NULL argument");
+  const size_t cs = p->prec == PINV_FP64 ? 16 : 8;
+  const void* src = nullptr;
+  size_t want = 0;
+  if (which == 0) {
+    src = p->R;
+    want = cs * (size_t)p->N * p->M;
+  } else if (which == 1) {
+    src = p->Linv;
+    want = cs * (size_t)p->N * p->N;
+  } else if (which == 2) {
+    src = p->gram;
+    want = 16 * (size_t)p->N * p->N;
+  } else {
+    return fail(PINV_ERR_INVALID, "which must be 0, 1 or 2");
+  }
+  if (!src) return fail(PINV_ERR_INVALID, "buffer not held by this plan");
+  if (bytes != want) return fail(PINV_ERR_INVALID, "size mismatch: want " + std::to_string(want));
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(p->ctx->device));
+  HIPCHK(hipStreamWaitEvent(s, p->ev[4], 0));
+  HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s));
+  return PINV_OK;
+}
+
+pinv_status pinv_plan_release(pinv_plan* p) {
+  if (!p) return fail(PINV_ERR_INVALID, "plan is NULL");
+  pinv_context* c = p->ctx;
+  std::lock_guard<std::mutex> g(c->mu);
+  const int left = --p->refs;
+  if (left <= 0) {
+    if (p->cached) {
+      c->cache.erase(p->key);
+      c->lru.erase(p->lru_it);
+    }
+    c->used -= p->bytes;
+    free_plan_memory(p);
+    delete p;
+  }
+  return PINV_OK;
+}
+
+pinv_status pinv_cache_trim(pinv_context* c, size_t* freed) {
+  if (!c) return fail(PINV_ERR_INVALID, "context is NULL");
+  std::lock_guard<std::mutex> g(c->mu);
+  const size_t before = c->used;
+  make_room(c, (size_t)-1 / 2);
+  if (freed) *freed = before - c->used;
+  return PINV_OK;
+}
+
+pinv_status pinv_context_usage(const pinv_context* c, size_t* used, size_t* budget, int32_t* n) {
+  if (!c) return fail(PINV_ERR_INVALID, "context is NULL");
+  if (used) *used = c->used;
+  if (budget) *budget = c->budget;
+  if (n) *n = (int32_t)c->cache.size();
+  return PINV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,400 @@
+// Device-side building blocks for the Pinv-Recon hot path on gfx950.
+//
+// Everything here is a template over the arithmetic type T (float or double).
+// Complex matrices live in HBM as interleaved (re, im) pairs, row-major.
+//
+//  * EncDev / egen: one element of the encoding matrix E from separable tables
+//    (paper Eq. 2 and the product form of Sec. 3.3):
+//        E[(c,i),(s,v)] = C_c(v) * Px[i,ix] * Py[i,iy] * Q[i,s] * exp(-i 2 pi B0(v) t_i)
+//    with Px[i,ix] = exp(-i 2 pi kx_i x_ix), Py[i,iy] = exp(-i 2 pi ky_i y_iy),
+//    Q[i,s] = exp(-i 2 pi f_s t_i), rows m = c*K + i, columns n = s*V + iy*nx + ix.
+//  * Tile: a block tile of C = op(A) op(B) on MFMA 16x16x4 (f32 or f64), four
+//    real products per complex product ("4M"), operands staged in LDS as split
+//    real/imaginary planes laid out [k][outer].
+//  * Loaders fill one BK-deep chunk of an operand into registers (fetch) and then
+//    into LDS (store); the mainloop double-buffers LDS so the next chunk's global
+//    loads or E generation overlap the current chunk's MFMAs.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pinv {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Acc;
+template <> struct Acc<float> { typedef f32x4 type; };
+template <> struct Acc<double> { typedef f64x4 type; };
+
+__device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f64x4 mfma4(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <typename T> struct cx { T re, im; };
+
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+
+__device__ __forceinline__ void sincospi_t(float x, float* s, float* c) { sincospif(x, s, c); }
+__device__ __forceinline__ void sincospi_t(double x, double* s, double* c) { sincospi(x, s, c); }
+
+// ---------------------------------------------------------------------------
+// Encoding tables on the device
+// ---------------------------------------------------------------------------
+template <typename T> struct EncDev {
+  const T* px;    // [K][nx] complex
+  const T* py;    // [K][ny] complex
+  const T* q;     // [K][S] complex, or null when S == 1 and f_0 == 0
+  const T* coil;  // [C][V] complex, or null for one unit coil
+  const T* b0;    // [V] Hz, or null
+  const T* t;     // [K] s, or null
+  int nx, ny, S, C, K, V;
+  int M, N;       // M = C*K rows, N = S*V columns
+};
+
+// Element E[m, n] given the decomposed indices.  `coilv` is C_c(v) (or 1).
+template <typename T>
+__device__ __forceinline__ cx<T> egen(const EncDev<T>& e, int i, int s, int v, int ix, int iy,
+                                      cx<T> coilv) {
+  const cx<T>* px = reinterpret_cast<const cx<T>*>(e.px);
+  const cx<T>* py = reinterpret_cast<const cx<T>*>(e.py);
+  cx<T> p = cmul(px[(size_t)i * e.nx + ix], py[(size_t)i * e.ny + iy]);
+  if (e.q) p = cmul(p, reinterpret_cast<const cx<T>*>(e.q)[(size_t)i * e.S + s]);
+  if (e.b0) {
+    T sn, cs;
+    sincospi_t(T(-2) * e.b0[v] * e.t[i], &sn, &cs);
+    p = cmul(p, cx<T>{cs, sn});
+  }
+  if (e.coil) p = cmul(p, coilv);
+  return p;
+}
+
+// ---------------------------------------------------------------------------
+// Tile configuration
+// ---------------------------------------------------------------------------
+template <typename T_, int BM_, int BN_, int BK_> struct TileCfg {
+  typedef T_ T;
+  static constexpr int BM = BM_, BN = BN_, BK = BK_;
+  static constexpr int NT = 256;                 // 4 wavefronts in a 2x2 grid
+  static constexpr int WTM = BM / 2, WTN = BN / 2;
+  static constexpr int MB = WTM / 16, NB = WTN / 16;
+  static constexpr int PAD = sizeof(T) == 4 ? 16 : 8;
+  static constexpr int LDA = BM + PAD, LDB = BN + PAD;
+  static constexpr int A_PLANE = BK * LDA, B_PLANE = BK * LDB;
+  static constexpr int STAGE = 2 * A_PLANE + 2 * B_PLANE;   // elements of T
+  static constexpr int SMEM_ELEMS = 2 * STAGE;
+  static_assert(BM % 32 == 0 && BN % 32 == 0 && BK % 4 == 0, "tile shape");
+};
+
+template <class Cfg> struct AccTile {
+  typename Acc<typename Cfg::T>::type re[Cfg::MB][Cfg::NB];
+  typename Acc<typename Cfg::T>::type im[Cfg::MB][Cfg::NB];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int a = 0; a < Cfg::MB; ++a)
+#pragma unroll
+      for (int b = 0; b < Cfg::NB; ++b) {
+        re[a][b] = typename Acc<typename Cfg::T>::type{0, 0, 0, 0};
+        im[a][b] = typename Acc<typename Cfg::T>::type{0, 0, 0, 0};
+      }
+  }
+};
+
+// One BK chunk of MFMAs from LDS.  sA = [re plane | im plane] of op(A) as
+// [k][m], sB likewise [k][n].  Lane l supplies A[m = l%16][k = l/16] and
+// B[k = l/16][n = l%16] for each 16x16x4 product.
+template <class Cfg>
+__device__ __forceinline__ void tile_compute(const typename Cfg::T* __restrict__ sA,
+                                             const typename Cfg::T* __restrict__ sB,
+                                             AccTile<Cfg>& acc) {
+  typedef typename Cfg::T T;
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  const int wr = wid >> 1, wc = wid & 1;
+  const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int kk = 0; kk < Cfg::BK / 4; ++kk) {
+    T ar[Cfg::MB], ai[Cfg::MB], nai[Cfg::MB], br[Cfg::NB], bi[Cfg::NB];
+    const int krow = kk * 4 + lk;
+#pragma unroll
+    for (int a = 0; a < Cfg::MB; ++a) {
+      const int off = krow * Cfg::LDA + wr * Cfg::WTM + a * 16 + lr;
+      ar[a] = sA[off];
+      ai[a] = sA[Cfg::A_PLANE + off];
+      nai[a] = -ai[a];
+    }
+#pragma unroll
+    for (int b = 0; b < Cfg::NB; ++b) {
+      const int off = krow * Cfg::LDB + wc * Cfg::WTN + b * 16 + lr;
+      br[b] = sB[off];
+      bi[b] = sB[Cfg::B_PLANE + off];
+    }
+#pragma unroll
+    for (int a = 0; a < Cfg::MB; ++a)
+#pragma unroll
+      for (int b = 0; b < Cfg::NB; ++b) {
+        acc.re[a][b] = mfma4(ar[a], br[b], acc.re[a][b]);
+        acc.re[a][b] = mfma4(nai[a], bi[b], acc.re[a][b]);
+        acc.im[a][b] = mfma4(ar[a], bi[b], acc.im[a][b]);
+        acc.im[a][b] = mfma4(ai[a], br[b], acc.im[a][b]);
+      }
+  }
+}
+
+// Double-buffered mainloop over k in [kbeg, kend).  Loaders zero-fill k >= kend.
+template <class Cfg, class LA, class LB>
+__device__ __forceinline__ void mainloop(LA& la, LB& lb, int kbeg, int kend, AccTile<Cfg>& acc,
+                                         typename Cfg::T* smem) {
+  if (kend <= kbeg) return;
+  typedef typename Cfg::T T;
+  T* stage0 = smem;
+  T* stage1 = smem + Cfg::STAGE;
+  const int nch = (kend - kbeg + Cfg::BK - 1) / Cfg::BK;
+  la.fetch(kbeg, kend);
+  lb.fetch(kbeg, kend);
+  la.store(stage0);
+  lb.store(stage0 + 2 * Cfg::A_PLANE);
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    T* cur = (c & 1) ? stage1 : stage0;
+    T* nxt = (c & 1) ? stage0 : stage1;
+    const bool more = c + 1 < nch;
+    if (more) {
+      la.fetch(kbeg + (c + 1) * Cfg::BK, kend);
+      lb.fetch(kbeg + (c + 1) * Cfg::BK, kend);
+    }
+    tile_compute<Cfg>(cur, cur + 2 * Cfg::A_PLANE, acc);
+    if (more) {
+      la.store(nxt);
+      lb.store(nxt + 2 * Cfg::A_PLANE);
+    }
+    __syncthreads();
+  }
+}
+
+// Visit every accumulator element: f(row, col, re, im) with tile-local row/col.
+// Output layout of the 16x16 result: column = lane % 16 for both types; the
+// row of accumulator register r is 4*(lane/16) + r for the f32 instruction and
+// lane/16 + 4*r for the f64 one.
+template <class Cfg, class F>
+__device__ __forceinline__ void acc_foreach(const AccTile<Cfg>& acc, F&& f) {
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  const int wr = wid >> 1, wc = wid & 1;
+  constexpr bool f64 = sizeof(typename Cfg::T) == 8;
+#pragma unroll
+  for (int a = 0; a < Cfg::MB; ++a)
+#pragma unroll
+    for (int b = 0; b < Cfg::NB; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = wr * Cfg::WTM + a * 16 + (f64 ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r);
+        const int col = wc * Cfg::WTN + b * 16 + (lane & 15);
+        f(row, col, acc.re[a][b][r], acc.im[a][b][r]);
+      }
+}
+
+// ---------------------------------------------------------------------------
+// Loaders.  OUTER = BM (A operand) or BN (B operand).  Each writes its chunk to
+// LDS planes s[0 .. BK*LD) (real) and s[BK*LD .. 2*BK*LD) (imaginary), at
+// s[k*LD + o].
+// ---------------------------------------------------------------------------
+
+// Dense complex storage with k contiguous: element (o, k) at p[o*ld + k].
+template <class Cfg, int OUTER, int LD, typename S, bool CONJ>
+struct LoadDenseKC {
+  typedef typename Cfg::T T;
+  static constexpr int TPR = Cfg::BK;                // one complex per thread per row
+  static constexpr int RPP = Cfg::NT / TPR;          // rows per pass
+  static constexpr int PASSES = OUTER / RPP;
+  static_assert(OUTER % RPP == 0, "loader shape");
+  const cx<S>* p;
+  int64_t ld;
+  int o0, oend;
+  T re[PASSES], im[PASSES];
+  __device__ __forceinline__ void fetch(int k0, int kend) {
+    const int kk = threadIdx.x % TPR;
+    const int k = k0 + kk;
+#pragma unroll
+    for (int j = 0; j < PASSES; ++j) {
+      const int o = o0 + threadIdx.x / TPR + j * RPP;
+      if (o < oend && k < kend) {
+        cx<S> v = p[(int64_t)o * ld + k];
+        re[j] = T(v.re);
+        im[j] = CONJ ? -T(v.im) : T(v.im);
+      } else {
+        re[j] = T(0);
+        im[j] = T(0);
+      }
+    }
+  }
+  __device__ __forceinline__ void store(T* s) {
+    const int kk = threadIdx.x % TPR;
+#pragma unroll
+    for (int j = 0; j < PASSES; ++j) {
+      const int o = threadIdx.x / TPR + j * RPP;
+      s[kk * LD + o] = re[j];
+      s[Cfg::BK * LD + kk * LD + o] = im[j];
+    }
+  }
+};
+
+// Dense complex storage with the outer index contiguous: element (o, k) at p[k*ld + o].
+template <class Cfg, int OUTER, int LD, typename S, bool CONJ>
+struct LoadDenseOC {
+  typedef typename Cfg::T T;
+  static constexpr int KPP = Cfg::NT / OUTER;        // k rows per pass
+  static constexpr int PASSES = Cfg::BK / KPP;
+  static_assert(Cfg::NT % OUTER == 0 && Cfg::BK % KPP == 0, "loader shape");
+  const cx<S>* p;
+  int64_t ld;
+  int o0, oend;
+  T re[PASSES], im[PASSES];
+  __device__ __forceinline__ void fetch(int k0, int kend) {
+    const int o = o0 + threadIdx.x % OUTER;
+#pragma unroll
+    for (int j = 0; j < PASSES; ++j) {
+      const int k = k0 + threadIdx.x / OUTER + j * KPP;
+      if (o < oend && k < kend) {
+        cx<S> v = p[(int64_t)k * ld + o];
+        re[j] = T(v.re);
+        im[j] = CONJ ? -T(v.im) : T(v.im);
+      } else {
+        re[j] = T(0);
+        im[j] = T(0);
+      }
+    }
+  }
+  __device__ __forceinline__ void store(T* s) {
+    const int o = threadIdx.x % OUTER;
+#pragma unroll
+    for (int j = 0; j < PASSES; ++j) {
+      const int kk = threadIdx.x / OUTER + j * KPP;
+      s[kk * LD + o] = re[j];
+      s[Cfg::BK * LD + kk * LD + o] = im[j];
+    }
+  }
+};
+
+// Generated operand, outer index = column n of E, k = row m of E:
+// element (o, k) = E[k, o] (or its conjugate).  Each thread keeps one column.
+template <class Cfg, int OUTER, int LD, bool CONJ>
+struct LoadGenCol {
+  typedef typename Cfg::T T;
+  static constexpr int KPP = Cfg::NT / OUTER;
+  static constexpr int PASSES = Cfg::BK / KPP;
+  static_assert(Cfg::NT % OUTER == 0 && Cfg::BK % KPP == 0, "loader shape");
+  EncDev<T> e;
+  bool valid;
+  int s, v, ix, iy;
+  T re[PASSES], im[PASSES];
+  __device__ __forceinline__ void init(const EncDev<T>& enc, int o0) {
+    e = enc;
+    const int n = o0 + threadIdx.x % OUTER;
+    valid = n < e.N;
+    const int nn = valid ? n : 0;
+    s = nn / e.V;
+    v = nn - s * e.V;
+    iy = v / e.nx;
+    ix = v - iy * e.nx;
+  }
+  __device__ __forceinline__ void fetch(int k0, int kend) {
+    int m = k0 + threadIdx.x / OUTER;
+    int c = m / e.K;
+    int i = m - c * e.K;
+#pragma unroll
+    for (int j = 0; j < PASSES; ++j) {
+      if (valid && m < kend) {
+        cx<T> cv{T(1), T(0)};
+        if (e.coil) cv = reinterpret_cast<const cx<T>*>(e.coil)[(size_t)c * e.V + v];
+        cx<T> el = egen(e, i, s, v, ix, iy, cv);
+        re[j] = el.re;
+        im[j] = CONJ ? -el.im : el.im;
+      } else {
+        re[j] = T(0);
+        im[j] = T(0);
+      }
+      m += KPP;
+      i += KPP;
+      while (i >= e.K) { i -= e.K; ++c; }
+    }
+  }
+  __device__ __forceinline__ void store(T* s_) {
+    const int o = threadIdx.x % OUTER;
+#pragma unroll
+    for (int j = 0; j < PASSES; ++j) {
+      const int kk = threadIdx.x / OUTER + j * KPP;
+      s_[kk * LD + o] = re[j];
+      s_[Cfg::BK * LD + kk * LD + o] = im[j];
+    }
+  }
+};
+
+// Generated operand, outer index = row m of E, k = column n of E:
+// element (o, k) = E[o, k] (or its conjugate).  Each thread keeps one row.
+template <class Cfg, int OUTER, int LD, bool CONJ>
+struct LoadGenRow {
+  typedef typename Cfg::T T;
+  static constexpr int KPP = Cfg::NT / OUTER;
+  static constexpr int PASSES = Cfg::BK / KPP;
+  static_assert(Cfg::NT % OUTER == 0 && Cfg::BK % KPP == 0, "loader shape");
+  EncDev<T> e;
+  bool valid;
+  int c, i;
+  T re[PASSES], im[PASSES];
+  __device__ __forceinline__ void init(const EncDev<T>& enc, int o0) {
+    e = enc;
+    const int m = o0 + threadIdx.x % OUTER;
+    valid = m < e.M;
+    const int mm = valid ? m : 0;
+    c = mm / e.K;
+    i = mm - c * e.K;
+  }
+  __device__ __forceinline__ void fetch(int k0, int kend) {
+    int n = k0 + threadIdx.x / OUTER;
+    int s = n / e.V;
+    int v = n - s * e.V;
+    int iy = v / e.nx;
+    int ix = v - iy * e.nx;
+#pragma unroll
+    for (int j = 0; j < PASSES; ++j) {
+      if (valid && n < kend) {
+        cx<T> cv{T(1), T(0)};
+        if (e.coil) cv = reinterpret_cast<const cx<T>*>(e.coil)[(size_t)c * e.V + v];
+        cx<T> el = egen(e, i, s, v, ix, iy, cv);
+        re[j] = el.re;
+        im[j] = CONJ ? -el.im : el.im;
+      } else {
+        re[j] = T(0);
+        im[j] = T(0);
+      }
+      n += KPP;
+      ix += KPP;
+      while (ix >= e.nx) {
+        ix -= e.nx;
+        if (++iy == e.ny) {
+          iy = 0;
+          ++s;
+        }
+      }
+      v = iy * e.nx + ix;
+    }
+  }
+  __device__ __forceinline__ void store(T* s_) {
+    const int o = threadIdx.x % OUTER;
+#pragma unroll
+    for (int j = 0; j < PASSES; ++j) {
+      const int kk = threadIdx.x / OUTER + j * KPP;
+      s_[kk * LD + o] = re[j];
+      s_[Cfg::BK * LD + kk * LD + o] = im[j];
+    }
+  }
+};
+
+}  // namespace pinv

@@ -1,0 +1,224 @@
+"""Thin ctypes binding of libpinv (include/pinv.h): argument marshalling only.
+
+Every function here forwards to the C entry point of the same name.  Device
+buffers are passed as torch tensors (their data_ptr) and streams as
+torch.cuda streams; torch only provides device memory and streams.  There is
+no fallback: importing this module raises if libpinv.so has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpinv.so")
+
+OK, ERR_INVALID, ERR_NOMEM, ERR_NOT_PD, ERR_DEVICE, ERR_BUSY, ERR_UNSUPPORTED = range(7)
+FP64, FP32, BF16X3 = 0, 1, 2
+LAMBDA_ABS, LAMBDA_REL_MEAN_DIAG = 0, 1
+FLAG_KEEP_GRAM = 1
+FLAG_UNCACHED = 2
+BUF_R, BUF_LINV, BUF_GRAM = 0, 1, 2
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it first "
+                      "(python -c 'import __graft_entry__ as g; g.build()')")
+_lib = ctypes.CDLL(LIB_PATH)
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class pinv_encoding(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nk", ctypes.c_int64),
+                ("k", _dp), ("t", _dp), ("ncoil", ctypes.c_int32), ("coil", _dp),
+                ("b0_hz", _dp), ("nspecies", ctypes.c_int32), ("species_hz", _dp)]
+
+
+class pinv_build_opts(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.c_double), ("lambda_mode", ctypes.c_int32),
+                ("prec", ctypes.c_int32), ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class pinv_plan_info(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int64), ("M", ctypes.c_int64), ("lambda_abs", ctypes.c_double),
+                ("prec", ctypes.c_int32), ("ready", ctypes.c_int32), ("key", ctypes.c_uint64),
+                ("device_bytes", ctypes.c_size_t), ("stage_ms", ctypes.c_float * 4)]
+
+
+class pinv_apply_item(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("data", ctypes.c_void_p), ("image", ctypes.c_void_p),
+                ("F", ctypes.c_int64)]
+
+
+_vp = ctypes.c_void_p
+_sigs = {
+    "pinv_context_create": [ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(_vp)],
+    "pinv_context_destroy": [_vp],
+    "pinv_build": [_vp, ctypes.POINTER(pinv_encoding), ctypes.POINTER(pinv_build_opts), _vp,
+                   ctypes.POINTER(_vp)],
+    "pinv_plan_wait": [_vp],
+    "pinv_apply": [_vp, _vp, _vp, ctypes.c_int64, _vp, ctypes.c_int32, _vp],
+    "pinv_apply_grouped": [_vp, ctypes.c_int32, ctypes.POINTER(pinv_apply_item), ctypes.c_int32, _vp],
+    "pinv_forward": [_vp, _vp, _vp, ctypes.c_int64, _vp, _vp],
+    "pinv_plan_info_get": [_vp, ctypes.POINTER(pinv_plan_info)],
+    "pinv_plan_buffers": [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp)],
+    "pinv_plan_copy_buffer": [_vp, ctypes.c_int32, _vp, ctypes.c_size_t, _vp],
+    "pinv_plan_release": [_vp],
+    "pinv_cache_trim": [_vp, ctypes.POINTER(ctypes.c_size_t)],
+    "pinv_context_usage": [_vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
+                           ctypes.POINTER(ctypes.c_int32)],
+}
+for _name, _args in _sigs.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = ctypes.c_int
+_lib.pinv_status_string.argtypes = [ctypes.c_int]
+_lib.pinv_status_string.restype = ctypes.c_char_p
+_lib.pinv_last_error.argtypes = []
+_lib.pinv_last_error.restype = ctypes.c_char_p
+
+EXPORTED = sorted(list(_sigs) + ["pinv_status_string", "pinv_last_error"])
+
+
+class PinvError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = _lib.pinv_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {_lib.pinv_status_string(status).decode()} ({msg})")
+
+
+def _check(st: int, where: str):
+    if st != OK:
+        raise PinvError(st, where)
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(_dp)
+
+
+# ----------------------------------------------------------------------------
+# entry points
+# ----------------------------------------------------------------------------
+
+def pinv_context_create(device: int = 0, hbm_budget_bytes: int = 0) -> int:
+    out = _vp()
+    _check(_lib.pinv_context_create(device, hbm_budget_bytes, ctypes.byref(out)), "pinv_context_create")
+    return out.value
+
+
+def pinv_context_destroy(ctx: int) -> None:
+    _check(_lib.pinv_context_destroy(ctx), "pinv_context_destroy")
+
+
+def _encoding_struct(enc):
+    """Marshal an encoding (synth.Encoding-like object) into pinv_encoding.
+    Returns the struct and the arrays it points into (keep them alive)."""
+    k = np.ascontiguousarray(enc.k, dtype=np.float64)
+    keep = [k]
+    t = None if enc.t is None else np.ascontiguousarray(enc.t, dtype=np.float64)
+    coil = None
+    if enc.coil is not None:
+        c = np.ascontiguousarray(enc.coil, dtype=np.complex128)
+        coil = np.ascontiguousarray(c.view(np.float64))
+    b0 = None if enc.b0_hz is None else np.ascontiguousarray(enc.b0_hz, dtype=np.float64)
+    sp = None if enc.species_hz is None else np.ascontiguousarray(enc.species_hz, dtype=np.float64)
+    keep += [t, coil, b0, sp]
+    s = pinv_encoding(nx=enc.nx, ny=enc.ny, nk=k.shape[0], k=_ptr(k), t=_ptr(t),
+                      ncoil=1 if coil is None else enc.coil.shape[0], coil=_ptr(coil),
+                      b0_hz=_ptr(b0), nspecies=1 if sp is None else len(sp), species_hz=_ptr(sp))
+    return s, keep
+
+
+def pinv_build(ctx: int, enc, lam: float, lambda_mode: int = LAMBDA_REL_MEAN_DIAG,
+               prec: int = FP32, flags: int = 0, stream=None) -> int:
+    s, keep = _encoding_struct(enc)
+    o = pinv_build_opts(lambda_=lam, lambda_mode=lambda_mode, prec=prec, flags=flags, reserved=0)
+    out = _vp()
+    st = _lib.pinv_build(ctx, ctypes.byref(s), ctypes.byref(o), _stream_ptr(stream), ctypes.byref(out))
+    del keep
+    _check(st, "pinv_build")
+    return out.value
+
+
+def pinv_plan_wait(plan: int) -> None:
+    _check(_lib.pinv_plan_wait(plan), "pinv_plan_wait")
+
+
+def pinv_plan_wait_status(plan: int) -> int:
+    return _lib.pinv_plan_wait(plan)
+
+
+def pinv_apply(ctx: int, plan: int, data, image, refine_steps: int = 0, stream=None) -> None:
+    """data: device tensor [F, M], image: device tensor [F, N] (complex64 or complex128)."""
+    F = data.shape[0]
+    _check(_lib.pinv_apply(ctx, plan, data.data_ptr(), F, image.data_ptr(), refine_steps,
+                           _stream_ptr(stream)), "pinv_apply")
+
+
+def pinv_apply_grouped(ctx: int, items: Sequence[tuple], refine_steps: int = 0, stream=None) -> None:
+    """items: sequence of (plan, data tensor, image tensor)."""
+    arr = (pinv_apply_item * len(items))()
+    for i, (plan, d, x) in enumerate(items):
+        arr[i] = pinv_apply_item(plan, d.data_ptr(), x.data_ptr(), d.shape[0])
+    _check(_lib.pinv_apply_grouped(ctx, len(items), arr, refine_steps, _stream_ptr(stream)),
+           "pinv_apply_grouped")
+
+
+def pinv_forward(ctx: int, plan: int, image, data, stream=None) -> None:
+    _check(_lib.pinv_forward(ctx, plan, image.data_ptr(), image.shape[0], data.data_ptr(),
+                             _stream_ptr(stream)), "pinv_forward")
+
+
+def pinv_plan_info_get(plan: int) -> dict:
+    i = pinv_plan_info()
+    _check(_lib.pinv_plan_info_get(plan, ctypes.byref(i)), "pinv_plan_info_get")
+    return dict(N=i.N, M=i.M, lambda_abs=i.lambda_abs, prec=i.prec, ready=bool(i.ready),
+                key=i.key, device_bytes=i.device_bytes, stage_ms=list(i.stage_ms))
+
+
+def pinv_plan_buffers(plan: int):
+    r, l, g = _vp(), _vp(), _vp()
+    _check(_lib.pinv_plan_buffers(plan, ctypes.byref(r), ctypes.byref(l), ctypes.byref(g)),
+           "pinv_plan_buffers")
+    return r.value, l.value, g.value
+
+
+def pinv_plan_copy_buffer(plan: int, which: int, dst, stream=None) -> None:
+    nbytes = dst.numel() * dst.element_size()
+    _check(_lib.pinv_plan_copy_buffer(plan, which, dst.data_ptr(), nbytes, _stream_ptr(stream)),
+           "pinv_plan_copy_buffer")
+
+
+def pinv_plan_release(plan: int) -> None:
+    _check(_lib.pinv_plan_release(plan), "pinv_plan_release")
+
+
+def pinv_cache_trim(ctx: int) -> int:
+    f = ctypes.c_size_t()
+    _check(_lib.pinv_cache_trim(ctx, ctypes.byref(f)), "pinv_cache_trim")
+    return f.value
+
+
+def pinv_context_usage(ctx: int):
+    u, b, n = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_int32()
+    _check(_lib.pinv_context_usage(ctx, ctypes.byref(u), ctypes.byref(b), ctypes.byref(n)),
+           "pinv_context_usage")
+    return u.value, b.value, n.value
+
+
+def pinv_status_string(s: int) -> str:
+    return _lib.pinv_status_string(s).decode()
+
+
+def pinv_last_error() -> str:
+    return _lib.pinv_last_error().decode(errors="replace")

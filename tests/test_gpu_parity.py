@@ -1,0 +1,228 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle.
+
+Shapes span several 64/128 tiles with ragged tails (N = 480 and 288, M = 2100
+and 1000) and include the species and off-resonance factors.  Tolerances:
+
+* FP64 plans: every stage within 1e-9 relative (Frobenius) of the oracle; the
+  FP64 forward error of the Cholesky route is ~kappa(G_l) * 1e-16 with
+  kappa <= 1e4 here.
+* FP32 plans: Gram entries within 2048 * u32 = 1.2e-4 of max|G|: each Gram
+  entry is a sum of FP32 products accumulated in FP32 over segments of 2048
+  rows (then carried in FP64), and a sum of L terms bounded by max|G| carries
+  at most about L*u32*max|G| of rounding.  Images after two refinement steps
+  within 1e-5 (the target for the FP32 path); before refinement within
+  kappa(G_l) * 1e-6.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2410_06129_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_2410_06129_amd import pinv
+    return pinv
+
+
+@pytest.fixture(scope="module")
+def ctx(P):
+    assert torch.cuda.is_available()
+    c = P.pinv_context_create(0)
+    yield c
+    P.pinv_context_destroy(c)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def frame_rel(a, b):
+    return np.linalg.norm(a - b, axis=1) / np.linalg.norm(b, axis=1)
+
+
+CASES = {
+    "ragged_c3": dict(seed=101, nx=24, ny=20, C=3, K=700, F=5),
+    "species_b0": dict(seed=102, nx=12, ny=12, C=2, K=500, F=4, species=[0.0, 150.0], b0=True),
+}
+
+_oracle_cache = {}
+
+
+def oracle_case(name):
+    if name not in _oracle_cache:
+        kw = dict(CASES[name])
+        w = synth.small_case(**kw)
+        b = oracle.Build(w.enc, rel=1e-3)
+        d0 = oracle.forward(w.enc, w.images)
+        sig = np.sqrt(np.mean(np.abs(d0) ** 2))
+        d = d0 + sig * 10 ** (-30 / 20) * w.noise
+        x = b.reconstruct(d)
+        Lo_inv = oracle.forward_substitution(b.L, np.eye(b.L.shape[0]))
+        R = b.recon_matrix()
+        ev = np.linalg.eigvalsh(b.G + b.lam * np.eye(b.G.shape[0]))
+        _oracle_cache[name] = dict(w=w, b=b, d=d, x=x, Linv=Lo_inv, R=R, kappa=ev[-1] / ev[0])
+    return _oracle_cache[name]
+
+
+def to_dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a).astype(dtype)).cuda()
+
+
+def build(P, ctx, enc, prec, flags=0, lam=1e-3, mode=None):
+    mode = P.LAMBDA_REL_MEAN_DIAG if mode is None else mode
+    plan = P.pinv_build(ctx, enc, lam, mode, prec, flags)
+    P.pinv_plan_wait(plan)
+    return plan
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fp64_stages_match_oracle(P, ctx, name):
+    o = oracle_case(name)
+    enc, N, M = o["w"].enc, o["w"].enc.N, o["w"].enc.M
+    plan = build(P, ctx, enc, P.FP64, flags=P.FLAG_KEEP_GRAM)
+    info = P.pinv_plan_info_get(plan)
+    assert info["N"] == N and info["M"] == M
+    assert abs(info["lambda_abs"] - o["b"].lam) <= 1e-12 * o["b"].lam
+    G = torch.empty((N, N), dtype=torch.complex128, device="cuda")
+    P.pinv_plan_copy_buffer(plan, P.BUF_GRAM, G)
+    Li = torch.empty((N, N), dtype=torch.complex128, device="cuda")
+    P.pinv_plan_copy_buffer(plan, P.BUF_LINV, Li)
+    R = torch.empty((N, M), dtype=torch.complex128, device="cuda")
+    P.pinv_plan_copy_buffer(plan, P.BUF_R, R)
+    torch.cuda.synchronize()
+    G = np.tril(G.cpu().numpy())
+    Go = np.tril(o["b"].G)
+    assert np.max(np.abs(G - Go)) <= 1e-12 * np.max(np.abs(Go))
+    assert rel(np.tril(Li.cpu().numpy()), o["Linv"]) < 1e-9
+    assert rel(R.cpu().numpy(), o["R"]) < 1e-9
+    d = to_dev(o["d"], np.complex128)
+    x = torch.empty((d.shape[0], N), dtype=torch.complex128, device="cuda")
+    P.pinv_apply(ctx, plan, d, x)
+    torch.cuda.synchronize()
+    err = frame_rel(x.cpu().numpy(), o["x"])
+    assert err.max() < 1e-9, err
+    P.pinv_plan_release(plan)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fp32_path_matches_oracle(P, ctx, name):
+    o = oracle_case(name)
+    enc, N, M = o["w"].enc, o["w"].enc.N, o["w"].enc.M
+    plan = build(P, ctx, enc, P.FP32, flags=P.FLAG_KEEP_GRAM)
+    G = torch.empty((N, N), dtype=torch.complex128, device="cuda")
+    P.pinv_plan_copy_buffer(plan, P.BUF_GRAM, G)
+    torch.cuda.synchronize()
+    G = np.tril(G.cpu().numpy())
+    Go = np.tril(o["b"].G)
+    gerr = np.max(np.abs(G - Go)) / np.max(np.abs(Go))
+    assert gerr < 2048 * 2.0 ** -24, gerr
+    d = to_dev(o["d"], np.complex64)
+    x0 = torch.empty((d.shape[0], N), dtype=torch.complex64, device="cuda")
+    P.pinv_apply(ctx, plan, d, x0, refine_steps=0)
+    x2 = torch.empty_like(x0)
+    P.pinv_apply(ctx, plan, d, x2, refine_steps=2)
+    torch.cuda.synchronize()
+    e0 = frame_rel(x0.cpu().numpy().astype(np.complex128), o["x"])
+    e2 = frame_rel(x2.cpu().numpy().astype(np.complex128), o["x"])
+    print(f"{name}: kappa={o['kappa']:.3g} gram_err={gerr:.2e} err0={e0.max():.2e} err2={e2.max():.2e}")
+    assert e0.max() < o["kappa"] * 1e-6
+    assert e2.max() < 1e-5
+    P.pinv_plan_release(plan)
+
+
+def test_cartesian_lambda0_inverse_dft(P, ctx):
+    n = 16
+    enc = synth.Encoding(n, n, synth.cartesian_full(n, n))
+    plan = P.pinv_build(ctx, enc, 0.0, P.LAMBDA_ABS, P.FP64)
+    P.pinv_plan_wait(plan)
+    d = synth.unit_complex_noise((3, n * n), np.random.default_rng(9))
+    dd = to_dev(d, np.complex128)
+    x = torch.empty((3, n * n), dtype=torch.complex128, device="cuda")
+    P.pinv_apply(ctx, plan, dd, x)
+    torch.cuda.synchronize()
+    x = x.cpu().numpy()
+    for f in range(3):
+        ref = np.fft.fftshift(np.fft.ifft2(np.fft.ifftshift(d[f].reshape(n, n)))).ravel()
+        assert rel(x[f], ref) < 1e-12
+    P.pinv_plan_release(plan)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_forward_matches_oracle(P, ctx, prec):
+    o = oracle_case("species_b0")
+    enc = o["w"].enc
+    p = P.FP64 if prec == "fp64" else P.FP32
+    dt = np.complex128 if prec == "fp64" else np.complex64
+    plan = build(P, ctx, enc, p)
+    x = to_dev(o["w"].images, dt)
+    d = torch.empty((x.shape[0], enc.M), dtype=x.dtype, device="cuda")
+    P.pinv_forward(ctx, plan, x, d)
+    torch.cuda.synchronize()
+    ref = oracle.forward(enc, o["w"].images)
+    err = frame_rel(d.cpu().numpy().astype(np.complex128), ref).max()
+    assert err < (1e-12 if prec == "fp64" else 2e-6), err
+    P.pinv_plan_release(plan)
+
+
+def test_not_positive_definite_is_reported(P, ctx):
+    # four samples at k = 0 on a 2x2 grid: E is all ones, G = 4*ones, rank 1
+    enc = synth.Encoding(2, 2, np.zeros((4, 2)))
+    for prec in (P.FP64, P.FP32):
+        plan = P.pinv_build(ctx, enc, 0.0, P.LAMBDA_ABS, prec)
+        st = P.pinv_plan_wait_status(plan)
+        assert st == P.ERR_NOT_PD
+        assert "column 1" in P.pinv_last_error()
+        P.pinv_plan_release(plan)
+
+
+def test_invalid_arguments(P, ctx):
+    enc = synth.Encoding(8, 8, np.zeros((10, 2)))
+    with pytest.raises(P.PinvError) as ei:
+        P.pinv_build(ctx, enc, 0.0, P.LAMBDA_ABS, P.FP64)      # M < N with lambda = 0
+    assert ei.value.status == P.ERR_INVALID
+    with pytest.raises(P.PinvError):
+        P.pinv_build(ctx, enc, -1.0, P.LAMBDA_ABS, P.FP64)
+
+
+def test_zero_frames_and_grouped_equals_single(P, ctx):
+    o1, o2 = oracle_case("ragged_c3"), oracle_case("species_b0")
+    p1 = build(P, ctx, o1["w"].enc, P.FP32)
+    p2 = build(P, ctx, o2["w"].enc, P.FP32)
+    d1, d2 = to_dev(o1["d"], np.complex64), to_dev(o2["d"], np.complex64)
+    x1 = torch.zeros((d1.shape[0], o1["w"].enc.N), dtype=torch.complex64, device="cuda")
+    x2 = torch.zeros((d2.shape[0], o2["w"].enc.N), dtype=torch.complex64, device="cuda")
+    P.pinv_apply(ctx, p1, d1, x1)
+    P.pinv_apply(ctx, p2, d2, x2)
+    g1, g2 = torch.zeros_like(x1), torch.zeros_like(x2)
+    P.pinv_apply_grouped(ctx, [(p1, d1, g1), (p2, d2, g2)])
+    e = torch.empty((0, o1["w"].enc.M), dtype=torch.complex64, device="cuda")
+    ex = torch.empty((0, o1["w"].enc.N), dtype=torch.complex64, device="cuda")
+    P.pinv_apply(ctx, p1, e, ex)
+    torch.cuda.synchronize()
+    assert torch.equal(g1, x1) and torch.equal(g2, x2)
+    # a frame's result does not depend on the other frames in the batch
+    s1 = torch.zeros((1, o1["w"].enc.N), dtype=torch.complex64, device="cuda")
+    P.pinv_apply(ctx, p1, d1[2:3].contiguous(), s1)
+    torch.cuda.synchronize()
+    assert torch.equal(s1[0], x1[2])
+    P.pinv_plan_release(p1)
+    P.pinv_plan_release(p2)
+
+
+def test_cache_hit_and_release(P, ctx):
+    o = oracle_case("species_b0")
+    a = build(P, ctx, o["w"].enc, P.FP32)
+    b = P.pinv_build(ctx, o["w"].enc, 1e-3, P.LAMBDA_REL_MEAN_DIAG, P.FP32)
+    assert a == b
+    used, budget, n = P.pinv_context_usage(ctx)
+    assert n >= 1 and used <= budget
+    P.pinv_plan_release(a)
+    P.pinv_plan_release(b)
+    freed = P.pinv_cache_trim(ctx)
+    assert freed > 0
