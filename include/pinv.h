@@ -80,8 +80,11 @@ typedef struct {
   const double *species_hz;   /* [S] species frequencies in Hz, or NULL (=> S == 1 at 0 Hz) */
 } pinv_encoding;
 
-#define PINV_FLAG_KEEP_GRAM 1   /* keep a copy of E^H E (lower, FP64) for inspection */
+#define PINV_FLAG_KEEP_GRAM 1   /* accepted for compatibility: every plan keeps E^H E */
 #define PINV_FLAG_UNCACHED 2    /* build a fresh plan outside the cache (freed on its last release) */
+#define PINV_FLAG_GRAM_FULL 4   /* form E^H E over all M = C*nk rows in the plan's precision
+                                   instead of the default FP64 (F^H F) o (coil cross-products),
+                                   which is exact because every coil shares the trajectory (Eq. 11) */
 
 typedef struct {
   double lambda;              /* >= 0; meaning set by lambda_mode */
@@ -164,7 +167,7 @@ pinv_status pinv_plan_info_get(const pinv_plan *p, pinv_plan_info *out);
 /* Device pointers held by a ready plan (any may be NULL on output):
  *   R     [N][M] complex, the reconstruction matrix
  *   Linv  [N][N] complex, L^-1 (lower; FP32 plans hold it as complex64)
- *   gram  [N][N] complex128, E^H E (lower part valid; only with PINV_FLAG_KEEP_GRAM)
+ *   gram  [N][N] complex128, E^H E (full Hermitian; used by the refinement residual)
  * The memory stays owned by the plan. */
 pinv_status pinv_plan_buffers(const pinv_plan *p, void **R, void **Linv, void **gram);
 

@@ -50,7 +50,8 @@ struct pinv_plan {
   EncDev<double> e64{};
   void* R = nullptr;
   void* Linv = nullptr;      // complex64 for FP32/BF16X3 plans, complex128 for FP64
-  void* gram = nullptr;      // only with PINV_FLAG_KEEP_GRAM
+  void* gram = nullptr;      // full Hermitian E^H E in FP64 (refinement residuals)
+  bool gram_exact = true;    // false when the Gram was formed over M rows in FP32
   int* info = nullptr;
   std::vector<void*> host_stage;   // pinned staging of the tables, freed once the build is done
   size_t bytes = 0;
@@ -248,7 +249,7 @@ void free_plan_memory(pinv_plan* p) {
     if (e) (void)hipEventDestroy(e);
 }
 
-size_t plan_footprint(const Dims& d, int prec, bool keep_gram) {
+size_t plan_footprint(const Dims& d, int prec) {
   const size_t N = d.N, M = d.M;
   const size_t cs = prec == PINV_FP64 ? 16 : 8;
   size_t b = 0;
@@ -257,15 +258,15 @@ size_t plan_footprint(const Dims& d, int prec, bool keep_gram) {
   b += cs * N * N;              // L^-1 kept
   b += cs * N * M;              // W
   b += cs * N * M;              // R
-  if (keep_gram) b += 16 * N * N;
+  b += 16 * N * N;              // the Gram kept for refinement
   b += 64ull << 20;             // tables and slack
   return b;
 }
 
-size_t plan_resident(const Dims& d, int prec, bool keep_gram) {
+size_t plan_resident(const Dims& d, int prec) {
   const size_t N = d.N, M = d.M;
   const size_t cs = prec == PINV_FP64 ? 16 : 8;
-  return cs * N * M + cs * N * N + (keep_gram ? 16 * N * N : 0) + (16ull << 20);
+  return cs * N * M + cs * N * N + 16 * N * N + (16ull << 20);
 }
 
 // Evict LRU plans held only by the cache until `need` bytes fit.  ctx->mu held.
@@ -367,8 +368,8 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
   }
   if (lam == 0.0 && d.M < d.N)
     return fail(PINV_ERR_INVALID, "lambda = 0 needs M >= N (full column rank)");
-  const bool keep_gram = (o->flags & PINV_FLAG_KEEP_GRAM) != 0;
-  const uint64_t key = plan_key(e, d, lam, o->prec) ^ (keep_gram ? 0x9e3779b97f4a7c15ull : 0);
+  const bool gram_full = (o->flags & PINV_FLAG_GRAM_FULL) != 0;
+  const uint64_t key = plan_key(e, d, lam, o->prec) ^ (gram_full ? 0xc2b2ae3d27d4eb4full : 0);
   hipStream_t s = (hipStream_t)stream;
   HIPCHK(hipSetDevice(c->device));
 
@@ -384,7 +385,7 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
     *out = p;
     return PINV_OK;
   }
-  const size_t foot = plan_footprint(d, o->prec, keep_gram);
+  const size_t foot = plan_footprint(d, o->prec);
   if (!make_room(c, foot))
     return fail(PINV_ERR_NOMEM, "plan footprint " + std::to_string(foot) +
                                     " B exceeds the free budget");
@@ -441,7 +442,8 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
   BCHK(hipMemsetAsync(p->info, 0, sizeof(int), s));
   BCHK(hipMalloc(&p->R, cs * N * M));
   BCHK(hipMalloc(&p->Linv, cs * N * N));
-  if (keep_gram) BCHK(hipMalloc(&p->gram, 16 * N * N));
+  BCHK(hipMalloc(&p->gram, 16 * N * N));
+  p->gram_exact = !(gram_full && !f64);
   BCHK(hipMallocAsync(&G, 16 * N * N, s));
   if (f64) {
     L64 = p->Linv;
@@ -453,11 +455,14 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
 
   // 1. Gram (a3) with E generated per tile (a2)
   BCHK(hipEventRecord(p->ev[0], s));
-  if (f64)
+  if (!gram_full)
+    BCHK(launch_gram_shared<double>(p->e64, (double*)G, s));   // FP64 F^H F, coil products (Eq. 11)
+  else if (f64)
     BCHK(launch_gram<double>(p->e64, (double*)G, 0, s));
   else
     BCHK(launch_gram<float>(p->e32, (double*)G, 2048, s));
-  if (keep_gram) BCHK(hipMemcpyAsync(p->gram, G, 16 * N * N, hipMemcpyDeviceToDevice, s));
+  BCHK(hipMemcpyAsync(p->gram, G, 16 * N * N, hipMemcpyDeviceToDevice, s));
+  BCHK(launch_herm_fill((double*)p->gram, d.N, s));
   BCHK(hipEventRecord(p->ev[1], s));
   // 2. shift + blocked Cholesky with L^-1 (a4), FP64
   BCHK(launch_cholinv((double*)G, (double*)L64, d.N, lam, p->info, s));
@@ -485,7 +490,7 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
 #undef BCHK
   // the pinned staging buffers stay with the plan until its build has finished
 
-  p->bytes = plan_resident(d, o->prec, keep_gram);
+  p->bytes = plan_resident(d, o->prec);
   c->used += p->bytes;
   if (uncached) {
     p->refs = 1;   // the caller only
@@ -518,57 +523,45 @@ pinv_status pinv_plan_wait(pinv_plan* p) {
   return p->status;
 }
 
-// Refinement scratch and steps for one item (FP32 plan: complex64 data/images).
-static pinv_status refine_f32(pinv_plan* p, const void* data, int F, void* image, int steps,
-                              hipStream_t s) {
+// Iterative refinement on the normal equations (Eq. 6) for one item:
+//   r = E^H d - (G + lam I) x   in FP64  (b = E^H d formed once, E regenerated in FP64)
+//   x += L^-H L^-1 r            (the plan's factor)
+// When the plan's Gram is not exact to FP64 (FP32 Gram over all rows) the
+// residual is formed as E^H (d - E x) - lam x instead.
+extern "C++" {
+template <typename TS>   // storage type of data/images and of the plan's L^-1
+static pinv_status refine_item(pinv_plan* p, const void* data, int F, void* image, int steps,
+                               hipStream_t s) {
   if (steps <= 0 || F <= 0) return PINV_OK;
   const size_t N = p->N, M = p->M;
-  void *rd = nullptr, *r32 = nullptr, *t32 = nullptr;
-  HIPCHK(hipMallocAsync(&rd, 16 * (size_t)F * M, s));
-  HIPCHK(hipMallocAsync(&r32, 8 * (size_t)F * N, s));
-  HIPCHK(hipMallocAsync(&t32, 8 * (size_t)F * N, s));
-  for (int it = 0; it < steps; ++it) {
-    // rd = d - E x   (FP64, E regenerated from FP64 tables)
-    HIPCHK((launch_forward<double, float, float>(p->e64, (const float*)image, F, (const float*)data,
-                                                 (double*)rd, s)));
-    // r = E^H rd - lam x
-    HIPCHK((launch_adjoint<double, float, float>(p->e64, (const double*)rd, F, (const float*)image,
-                                                 p->lam, (float*)r32, s)));
-    // x += L^-H L^-1 r
-    HIPCHK((launch_tri_frames<float, 0, float>((const float*)p->Linv, (const float*)r32, F, p->N,
-                                               (float*)t32, s)));
-    HIPCHK((launch_tri_frames<float, 1, float>((const float*)p->Linv, (const float*)t32, F, p->N,
-                                               (float*)image, s)));
+  const TS* d = (const TS*)data;
+  TS* x = (TS*)image;
+  void *b = nullptr, *rd = nullptr, *r = nullptr, *t = nullptr;
+  HIPCHK(hipMallocAsync(&r, 2 * sizeof(TS) * (size_t)F * N, s));
+  HIPCHK(hipMallocAsync(&t, 2 * sizeof(TS) * (size_t)F * N, s));
+  if (p->gram_exact) {
+    HIPCHK(hipMallocAsync(&b, 16 * (size_t)F * N, s));
+    HIPCHK((launch_adjoint<double, TS, TS, double>(p->e64, d, F, (const TS*)nullptr, 0.0, (double*)b, s)));
+  } else {
+    HIPCHK(hipMallocAsync(&rd, 16 * (size_t)F * M, s));
   }
-  HIPCHK(hipFreeAsync(rd, s));
-  HIPCHK(hipFreeAsync(r32, s));
-  HIPCHK(hipFreeAsync(t32, s));
+  for (int it = 0; it < steps; ++it) {
+    if (p->gram_exact) {
+      HIPCHK((launch_resid<TS, TS>((const double*)p->gram, (const double*)b, x, F, p->N, p->lam,
+                                   (TS*)r, s)));
+    } else {
+      HIPCHK((launch_forward<double, TS, TS>(p->e64, x, F, d, (double*)rd, s)));
+      HIPCHK((launch_adjoint<double, double, TS, TS>(p->e64, (const double*)rd, F, x, p->lam,
+                                                     (TS*)r, s)));
+    }
+    HIPCHK((launch_tri_frames<TS, 0, TS>((const TS*)p->Linv, (const TS*)r, F, p->N, (TS*)t, s)));
+    HIPCHK((launch_tri_frames<TS, 1, TS>((const TS*)p->Linv, (const TS*)t, F, p->N, x, s)));
+  }
+  for (void* q : {b, rd, r, t})
+    if (q) HIPCHK(hipFreeAsync(q, s));
   return PINV_OK;
 }
-
-static pinv_status refine_f64(pinv_plan* p, const void* data, int F, void* image, int steps,
-                              hipStream_t s) {
-  if (steps <= 0 || F <= 0) return PINV_OK;
-  const size_t N = p->N, M = p->M;
-  void *rd = nullptr, *r = nullptr, *t = nullptr;
-  HIPCHK(hipMallocAsync(&rd, 16 * (size_t)F * M, s));
-  HIPCHK(hipMallocAsync(&r, 16 * (size_t)F * N, s));
-  HIPCHK(hipMallocAsync(&t, 16 * (size_t)F * N, s));
-  for (int it = 0; it < steps; ++it) {
-    HIPCHK((launch_forward<double, double, double>(p->e64, (const double*)image, F,
-                                                   (const double*)data, (double*)rd, s)));
-    HIPCHK((launch_adjoint<double, double, double>(p->e64, (const double*)rd, F,
-                                                   (const double*)image, p->lam, (double*)r, s)));
-    HIPCHK((launch_tri_frames<double, 0, double>((const double*)p->Linv, (const double*)r, F, p->N,
-                                                 (double*)t, s)));
-    HIPCHK((launch_tri_frames<double, 1, double>((const double*)p->Linv, (const double*)t, F, p->N,
-                                                 (double*)image, s)));
-  }
-  HIPCHK(hipFreeAsync(rd, s));
-  HIPCHK(hipFreeAsync(r, s));
-  HIPCHK(hipFreeAsync(t, s));
-  return PINV_OK;
-}
+}  // extern "C++"
 
 pinv_status pinv_apply_grouped(pinv_context* c, int32_t n, const pinv_apply_item* items,
                                int32_t refine_steps, void* stream) {
@@ -616,9 +609,10 @@ pinv_status pinv_apply_grouped(pinv_context* c, int32_t n, const pinv_apply_item
   if (refine_steps > 0) {
     for (int j = 0; j < n; ++j) {
       pinv_plan* p = (pinv_plan*)items[j].plan;
-      pinv_status st = p->prec == PINV_FP64
-                           ? refine_f64(p, items[j].data, (int)items[j].F, items[j].image, refine_steps, s)
-                           : refine_f32(p, items[j].data, (int)items[j].F, items[j].image, refine_steps, s);
+      pinv_status st =
+          p->prec == PINV_FP64
+              ? refine_item<double>(p, items[j].data, (int)items[j].F, items[j].image, refine_steps, s)
+              : refine_item<float>(p, items[j].data, (int)items[j].F, items[j].image, refine_steps, s);
       if (st != PINV_OK) return st;
     }
   }

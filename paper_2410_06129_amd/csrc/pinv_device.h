@@ -58,23 +58,6 @@ template <typename T> struct EncDev {
   int M, N;       // M = C*K rows, N = S*V columns
 };
 
-// Element E[m, n] given the decomposed indices.  `coilv` is C_c(v) (or 1).
-template <typename T>
-__device__ __forceinline__ cx<T> egen(const EncDev<T>& e, int i, int s, int v, int ix, int iy,
-                                      cx<T> coilv) {
-  const cx<T>* px = reinterpret_cast<const cx<T>*>(e.px);
-  const cx<T>* py = reinterpret_cast<const cx<T>*>(e.py);
-  cx<T> p = cmul(px[(size_t)i * e.nx + ix], py[(size_t)i * e.ny + iy]);
-  if (e.q) p = cmul(p, reinterpret_cast<const cx<T>*>(e.q)[(size_t)i * e.S + s]);
-  if (e.b0) {
-    T sn, cs;
-    sincospi_t(T(-2) * e.b0[v] * e.t[i], &sn, &cs);
-    p = cmul(p, cx<T>{cs, sn});
-  }
-  if (e.coil) p = cmul(p, coilv);
-  return p;
-}
-
 // ---------------------------------------------------------------------------
 // Tile configuration
 // ---------------------------------------------------------------------------
@@ -108,11 +91,13 @@ template <class Cfg> struct AccTile {
 
 // One BK chunk of MFMAs from LDS.  sA = [re plane | im plane] of op(A) as
 // [k][m], sB likewise [k][n].  Lane l supplies A[m = l%16][k = l/16] and
-// B[k = l/16][n = l%16] for each 16x16x4 product.
-template <class Cfg>
+// B[k = l/16][n = l%16] for each 16x16x4 product.  After the MFMAs of k-step
+// kk the hook `between(kk)` runs, so the loaders' element math for the next
+// chunk is interleaved with this chunk's matrix products.
+template <class Cfg, class Hook>
 __device__ __forceinline__ void tile_compute(const typename Cfg::T* __restrict__ sA,
                                              const typename Cfg::T* __restrict__ sB,
-                                             AccTile<Cfg>& acc) {
+                                             AccTile<Cfg>& acc, Hook&& between) {
   typedef typename Cfg::T T;
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
@@ -144,20 +129,30 @@ __device__ __forceinline__ void tile_compute(const typename Cfg::T* __restrict__
         acc.im[a][b] = mfma4(ar[a], bi[b], acc.im[a][b]);
         acc.im[a][b] = mfma4(ai[a], br[b], acc.im[a][b]);
       }
+    between(kk);
   }
 }
 
 // Double-buffered mainloop over k in [kbeg, kend).  Loaders zero-fill k >= kend.
+// Loader protocol: fetch(k0, kend) issues the global loads of a chunk,
+// finish<STEP, STEPS>() turns loaded values into operand values (the E
+// element products for generated operands), store(s) writes them to LDS.
 template <class Cfg, class LA, class LB>
 __device__ __forceinline__ void mainloop(LA& la, LB& lb, int kbeg, int kend, AccTile<Cfg>& acc,
                                          typename Cfg::T* smem) {
   if (kend <= kbeg) return;
   typedef typename Cfg::T T;
+  constexpr int STEPS = Cfg::BK / 4;
   T* stage0 = smem;
   T* stage1 = smem + Cfg::STAGE;
   const int nch = (kend - kbeg + Cfg::BK - 1) / Cfg::BK;
   la.fetch(kbeg, kend);
   lb.fetch(kbeg, kend);
+#pragma unroll
+  for (int q = 0; q < STEPS; ++q) {
+    la.finish(q, STEPS);
+    lb.finish(q, STEPS);
+  }
   la.store(stage0);
   lb.store(stage0 + 2 * Cfg::A_PLANE);
   __syncthreads();
@@ -169,13 +164,27 @@ __device__ __forceinline__ void mainloop(LA& la, LB& lb, int kbeg, int kend, Acc
       la.fetch(kbeg + (c + 1) * Cfg::BK, kend);
       lb.fetch(kbeg + (c + 1) * Cfg::BK, kend);
     }
-    tile_compute<Cfg>(cur, cur + 2 * Cfg::A_PLANE, acc);
+    tile_compute<Cfg>(cur, cur + 2 * Cfg::A_PLANE, acc, [&](int kk) {
+      la.finish(kk, STEPS);
+      lb.finish(kk, STEPS);
+    });
     if (more) {
       la.store(nxt);
       lb.store(nxt + 2 * Cfg::A_PLANE);
     }
     __syncthreads();
   }
+}
+
+// Tile-local coordinates of accumulator (a, b, r) for this lane.
+template <class Cfg>
+__device__ __forceinline__ void acc_coord(int a, int b, int r, int* row, int* col) {
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  const int wr = wid >> 1, wc = wid & 1;
+  constexpr bool f64 = sizeof(typename Cfg::T) == 8;
+  *row = wr * Cfg::WTM + a * 16 + (f64 ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r);
+  *col = wc * Cfg::WTN + b * 16 + (lane & 15);
 }
 
 // Visit every accumulator element: f(row, col, re, im) with tile-local row/col.
@@ -234,6 +243,7 @@ struct LoadDenseKC {
       }
     }
   }
+  __device__ __forceinline__ void finish(int, int) {}
   __device__ __forceinline__ void store(T* s) {
     const int kk = threadIdx.x % TPR;
 #pragma unroll
@@ -271,6 +281,7 @@ struct LoadDenseOC {
       }
     }
   }
+  __device__ __forceinline__ void finish(int, int) {}
   __device__ __forceinline__ void store(T* s) {
     const int o = threadIdx.x % OUTER;
 #pragma unroll
@@ -281,6 +292,38 @@ struct LoadDenseOC {
     }
   }
 };
+
+// Raw factors of one generated element, loaded in fetch() and multiplied in
+// finish(): E = Px * Py [* Q] [* exp(-i 2 pi B0 t)] [* coil].
+template <typename T> struct GenRaw {
+  cx<T> px, py, q, coil;
+  T b0t;
+};
+
+template <typename T>
+__device__ __forceinline__ void gen_load(const EncDev<T>& e, int i, int s, int v, int ix, int iy,
+                                         int c, GenRaw<T>& r) {
+  const cx<T>* px = reinterpret_cast<const cx<T>*>(e.px);
+  const cx<T>* py = reinterpret_cast<const cx<T>*>(e.py);
+  r.px = px[(size_t)i * e.nx + ix];
+  r.py = py[(size_t)i * e.ny + iy];
+  if (e.q) r.q = reinterpret_cast<const cx<T>*>(e.q)[(size_t)i * e.S + s];
+  if (e.b0) r.b0t = e.b0[v] * e.t[i];
+  if (e.coil) r.coil = reinterpret_cast<const cx<T>*>(e.coil)[(size_t)c * e.V + v];
+}
+
+template <typename T>
+__device__ __forceinline__ cx<T> gen_product(const EncDev<T>& e, const GenRaw<T>& r) {
+  cx<T> p = cmul(r.px, r.py);
+  if (e.q) p = cmul(p, r.q);
+  if (e.b0) {
+    T sn, cs;
+    sincospi_t(T(-2) * r.b0t, &sn, &cs);
+    p = cmul(p, cx<T>{cs, sn});
+  }
+  if (e.coil) p = cmul(p, r.coil);
+  return p;
+}
 
 // Generated operand, outer index = column n of E, k = row m of E:
 // element (o, k) = E[k, o] (or its conjugate).  Each thread keeps one column.
@@ -293,6 +336,8 @@ struct LoadGenCol {
   EncDev<T> e;
   bool valid;
   int s, v, ix, iy;
+  bool ok[PASSES];
+  GenRaw<T> raw[PASSES];
   T re[PASSES], im[PASSES];
   __device__ __forceinline__ void init(const EncDev<T>& enc, int o0) {
     e = enc;
@@ -310,19 +355,25 @@ struct LoadGenCol {
     int i = m - c * e.K;
 #pragma unroll
     for (int j = 0; j < PASSES; ++j) {
-      if (valid && m < kend) {
-        cx<T> cv{T(1), T(0)};
-        if (e.coil) cv = reinterpret_cast<const cx<T>*>(e.coil)[(size_t)c * e.V + v];
-        cx<T> el = egen(e, i, s, v, ix, iy, cv);
-        re[j] = el.re;
-        im[j] = CONJ ? -el.im : el.im;
-      } else {
-        re[j] = T(0);
-        im[j] = T(0);
-      }
+      ok[j] = valid && m < kend;
+      gen_load(e, ok[j] ? i : 0, s, v, ix, iy, ok[j] ? c : 0, raw[j]);
       m += KPP;
       i += KPP;
-      while (i >= e.K) { i -= e.K; ++c; }
+#pragma unroll
+      for (int q = 0; q < KPP; ++q)
+        if (i >= e.K) {
+          i -= e.K;
+          ++c;
+        }
+    }
+  }
+  __device__ __forceinline__ void finish(int step, int steps) {
+#pragma unroll
+    for (int j = 0; j < PASSES; ++j) {
+      if ((j * steps) / PASSES != step) continue;
+      const cx<T> el = gen_product(e, raw[j]);
+      re[j] = ok[j] ? el.re : T(0);
+      im[j] = ok[j] ? (CONJ ? -el.im : el.im) : T(0);
     }
   }
   __device__ __forceinline__ void store(T* s_) {
@@ -347,6 +398,8 @@ struct LoadGenRow {
   EncDev<T> e;
   bool valid;
   int c, i;
+  bool ok[PASSES];
+  GenRaw<T> raw[PASSES];
   T re[PASSES], im[PASSES];
   __device__ __forceinline__ void init(const EncDev<T>& enc, int o0) {
     e = enc;
@@ -358,32 +411,36 @@ struct LoadGenRow {
   }
   __device__ __forceinline__ void fetch(int k0, int kend) {
     int n = k0 + threadIdx.x / OUTER;
-    int s = n / e.V;
-    int v = n - s * e.V;
-    int iy = v / e.nx;
-    int ix = v - iy * e.nx;
+    const int nn = n < e.N ? n : 0;
+    int s = nn / e.V;
+    const int v0 = nn - s * e.V;
+    int iy = v0 / e.nx;
+    int ix = v0 - iy * e.nx;
 #pragma unroll
     for (int j = 0; j < PASSES; ++j) {
-      if (valid && n < kend) {
-        cx<T> cv{T(1), T(0)};
-        if (e.coil) cv = reinterpret_cast<const cx<T>*>(e.coil)[(size_t)c * e.V + v];
-        cx<T> el = egen(e, i, s, v, ix, iy, cv);
-        re[j] = el.re;
-        im[j] = CONJ ? -el.im : el.im;
-      } else {
-        re[j] = T(0);
-        im[j] = T(0);
-      }
+      ok[j] = valid && n < kend;
+      const bool in = n < e.N;
+      gen_load(e, i, in ? s : 0, in ? iy * e.nx + ix : 0, in ? ix : 0, in ? iy : 0, c, raw[j]);
       n += KPP;
       ix += KPP;
-      while (ix >= e.nx) {
-        ix -= e.nx;
-        if (++iy == e.ny) {
-          iy = 0;
-          ++s;
+#pragma unroll
+      for (int q = 0; q < KPP; ++q)
+        if (ix >= e.nx) {
+          ix -= e.nx;
+          if (++iy == e.ny) {
+            iy = 0;
+            ++s;
+          }
         }
-      }
-      v = iy * e.nx + ix;
+    }
+  }
+  __device__ __forceinline__ void finish(int step, int steps) {
+#pragma unroll
+    for (int j = 0; j < PASSES; ++j) {
+      if ((j * steps) / PASSES != step) continue;
+      const cx<T> el = gen_product(e, raw[j]);
+      re[j] = ok[j] ? el.re : T(0);
+      im[j] = ok[j] ? (CONJ ? -el.im : el.im) : T(0);
     }
   }
   __device__ __forceinline__ void store(T* s_) {

@@ -25,6 +25,7 @@ struct ApplyBatch {     // passed by value as a kernel argument
 };
 
 template <typename T> hipError_t launch_gram(const EncDev<T>& e, double* G, int flush, hipStream_t s);
+template <typename T> hipError_t launch_gram_shared(const EncDev<T>& e, double* G, hipStream_t s);
 hipError_t launch_cholinv(double* A, double* Li, int N, double lam, int* info, hipStream_t s);
 template <typename T> hipError_t launch_trmm_w(const EncDev<T>& e, const T* Li, T* W, hipStream_t s);
 template <typename T>
@@ -34,9 +35,13 @@ template <typename T> hipError_t launch_apply(const ApplyBatch& b, int total_til
 template <typename T, typename SX, typename SD>
 hipError_t launch_forward(const EncDev<T>& e, const SX* X, int F, const SD* Din, T* Dout,
                           hipStream_t s);
-template <typename T, typename SX, typename SO>
-hipError_t launch_adjoint(const EncDev<T>& e, const T* D, int F, const SX* X, double lam, SO* Z,
+template <typename T, typename SD, typename SX, typename SO>
+hipError_t launch_adjoint(const EncDev<T>& e, const SD* D, int F, const SX* X, double lam, SO* Z,
                           hipStream_t s);
+template <typename SX, typename SO>
+hipError_t launch_resid(const double* G, const double* b, const SX* X, int F, int N, double lam,
+                        SO* Out, hipStream_t s);
+hipError_t launch_herm_fill(double* G, int N, hipStream_t s);
 template <typename T, int MODE, typename SO>
 hipError_t launch_tri_frames(const T* Li, const T* In, int F, int N, SO* Out, hipStream_t s);
 hipError_t launch_to_f32(const double* in, float* out, size_t n_complex, hipStream_t s);

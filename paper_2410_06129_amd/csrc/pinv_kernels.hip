@@ -74,33 +74,143 @@ __global__ __launch_bounds__(256) void k_gram(EncDev<typename Cfg::T> e, double*
 }
 
 // ---------------------------------------------------------------------------
-// Cholesky diagonal block (FP64, one workgroup): A_kk + lam I = L_kk L_kk^H,
-// then L_kk^-1 by in-place triangular inversion.  The block is square nbk<=64.
+// Gram through the shared trajectory (Eq. 11): every coil's rows are the
+// coil-free encoding F (Fourier, species and off-resonance factors) scaled by
+// the coil map, E_c = F diag(C_c), so
+//     G[a][b] = sum_c conj(C_c(v_a)) C_c(v_b) (F^H F)[a][b].
+// F^H F is accumulated over the K rows of one coil on MFMA (F generated per
+// tile), the coil cross-product is formed in the epilogue from coil columns
+// staged in LDS.  `e` must describe F (no coil table, C = 1, M = K); `coil`
+// is the [C][V] coil table (or null for one unit coil).
 // ---------------------------------------------------------------------------
+template <class Cfg>
+__global__ __launch_bounds__(256) void k_gram_shared(EncDev<typename Cfg::T> e,
+                                                     const typename Cfg::T* __restrict__ coil,
+                                                     int C, double* __restrict__ G) {
+  typedef typename Cfg::T T;
+  static_assert(Cfg::BM == Cfg::BN, "square tiles");
+  int bi, bj;
+  tri_index(blockIdx.x, &bi, &bj);
+  const int N = e.N, V = e.V;
+  LoadGenCol<Cfg, Cfg::BM, Cfg::LDA, true> la;
+  LoadGenCol<Cfg, Cfg::BN, Cfg::LDB, false> lb;
+  la.init(e, bi * Cfg::BM);
+  lb.init(e, bj * Cfg::BN);
+  T* smem = smem_base<Cfg>();
+  AccTile<Cfg> acc;
+  acc.zero();
+  mainloop<Cfg>(la, lb, 0, e.M, acc, smem);
+  const int r0 = bi * Cfg::BM, c0 = bj * Cfg::BN;
+  // coil cross-products for this lane's elements
+  cx<double> sv[Cfg::MB][Cfg::NB][4];
+#pragma unroll
+  for (int a = 0; a < Cfg::MB; ++a)
+#pragma unroll
+    for (int b = 0; b < Cfg::NB; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sv[a][b][r] = cx<double>{coil ? 0.0 : 1.0, 0.0};
+  if (coil) {
+    // stage coil values of the tile's rows and columns, CC coils at a time
+    constexpr int CC = (Cfg::SMEM_ELEMS * sizeof(T)) / (sizeof(cx<T>) * (Cfg::BM + Cfg::BN));
+    static_assert(CC >= 1, "no room for coil staging");
+    cx<T>* sa = reinterpret_cast<cx<T>*>(smem);          // [CC][BM]
+    cx<T>* sb = sa + CC * Cfg::BM;                       // [CC][BN]
+    const cx<T>* cc = reinterpret_cast<const cx<T>*>(coil);
+    for (int c0c = 0; c0c < C; c0c += CC) {
+      const int nc = min(CC, C - c0c);
+      for (int idx = threadIdx.x; idx < nc * (Cfg::BM + Cfg::BN); idx += Cfg::NT) {
+        const int c = idx / (Cfg::BM + Cfg::BN), o = idx - c * (Cfg::BM + Cfg::BN);
+        const int g = o < Cfg::BM ? r0 + o : c0 + (o - Cfg::BM);
+        cx<T> v{T(0), T(0)};
+        if (g < N) v = cc[(size_t)(c0c + c) * V + (g % V)];
+        if (o < Cfg::BM) sa[c * Cfg::BM + o] = v; else sb[c * Cfg::BN + (o - Cfg::BM)] = v;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int a = 0; a < Cfg::MB; ++a)
+#pragma unroll
+        for (int b = 0; b < Cfg::NB; ++b)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            int row, col;
+            acc_coord<Cfg>(a, b, r, &row, &col);
+            cx<double> s = sv[a][b][r];
+            for (int c = 0; c < nc; ++c) {
+              const cx<T> x = sa[c * Cfg::BM + row], y = sb[c * Cfg::BN + col];
+              // conj(x) * y
+              s.re += (double)x.re * (double)y.re + (double)x.im * (double)y.im;
+              s.im += (double)x.re * (double)y.im - (double)x.im * (double)y.re;
+            }
+            sv[a][b][r] = s;
+          }
+      __syncthreads();
+    }
+  }
+  cx<double>* Gc = reinterpret_cast<cx<double>*>(G);
+#pragma unroll
+  for (int a = 0; a < Cfg::MB; ++a)
+#pragma unroll
+    for (int b = 0; b < Cfg::NB; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int row, col;
+        acc_coord<Cfg>(a, b, r, &row, &col);
+        row += r0;
+        col += c0;
+        if (row < N && col < N) {
+          const double fr = (double)acc.re[a][b][r], fi = (double)acc.im[a][b][r];
+          const cx<double> s = sv[a][b][r];
+          Gc[(size_t)row * N + col] = cx<double>{fr * s.re - fi * s.im, fr * s.im + fi * s.re};
+        }
+      }
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky diagonal block (FP64, one workgroup).  Gaussian elimination of the
+// augmented block [A_kk + lam I | I] without pivoting: at column j every row
+// i > j subtracts mu_ij = A_ij / A_jj times row j, on the full block of A
+// (A_il -= mu_ij A_jl, l > j) and on the identity part (B_ic -= mu_ij B_jc,
+// c <= j).  Rows are read contiguously (row j), so the 64 lanes of a wave hit
+// distinct LDS banks.  The pivots are D_j of A = Lt D Lt^H (Lt unit lower),
+// so L = Lt D^1/2 and L^-1 = D^-1/2 Lt^-1 = D^-1/2 B.  One barrier per column.
+// Only L_kk^-1 is stored: the panel, trailing and inverse updates need no L_kk.
+// ---------------------------------------------------------------------------
+constexpr int kDiagSmem = (2 * 64 * 64) * 16 + 64 * 8;
+
 __global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ A, double* __restrict__ Li,
                                                    int N, int nb, int k, double lam,
                                                    int* __restrict__ info) {
   if (*info) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  cx<double>* S = reinterpret_cast<cx<double>*>(smem_raw);      // [nb][nb]
-  cx<double>* tmp = S + 64 * 64;                                  // [64]
+  cx<double>* Am = reinterpret_cast<cx<double>*>(smem_raw);   // [64][64] full Hermitian block
+  cx<double>* Bm = Am + 64 * 64;                               // [64][64] unit lower
+  double* dpiv = reinterpret_cast<double*>(Bm + 64 * 64);     // [64]
   __shared__ int fail;
   const int tid = threadIdx.x;
   const int k0 = k * nb;
   const int nbk = min(nb, N - k0);
-  cx<double>* Ac = reinterpret_cast<cx<double>*>(A);
+  const cx<double>* Ac = reinterpret_cast<const cx<double>*>(A);
   cx<double>* Lc = reinterpret_cast<cx<double>*>(Li);
-  for (int idx = tid; idx < nbk * nbk; idx += 256) {
-    const int i = idx / nbk, j = idx - (idx / nbk) * nbk;
-    cx<double> v = (j <= i) ? Ac[(size_t)(k0 + i) * N + k0 + j] : cx<double>{0.0, 0.0};
+  for (int idx = tid; idx < 64 * 64; idx += 256) {
+    const int i = idx >> 6, j = idx & 63;
+    cx<double> v{0.0, 0.0};
+    if (i < nbk && j < nbk) {
+      // the lower triangle is authoritative; mirror it into the upper one
+      if (j <= i) {
+        v = Ac[(size_t)(k0 + i) * N + k0 + j];
+      } else {
+        const cx<double> u = Ac[(size_t)(k0 + j) * N + k0 + i];
+        v = cx<double>{u.re, -u.im};
+      }
+    }
     if (i == j) v = cx<double>{v.re + lam, 0.0};
-    S[i * 64 + j] = v;
+    Am[idx] = v;
+    Bm[idx] = cx<double>{i == j ? 1.0 : 0.0, 0.0};
   }
   if (tid == 0) fail = 0;
   __syncthreads();
-  // right-looking unblocked factorisation
   for (int j = 0; j < nbk; ++j) {
-    const double piv = S[j * 64 + j].re;
+    const double piv = Am[j * 64 + j].re;
     if (!(piv > 0.0)) {     // also catches NaN
       if (tid == 0) {
         atomicCAS(info, 0, k0 + j + 1);
@@ -108,59 +218,37 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ A, doubl
       }
       break;
     }
-    const double d = sqrt(piv);
-    const double inv = 1.0 / d;
-    for (int i = j + 1 + tid; i < nbk; i += 256) {
-      cx<double> v = S[i * 64 + j];
-      S[i * 64 + j] = cx<double>{v.re * inv, v.im * inv};
-    }
-    __syncthreads();
-    if (tid == 0) S[j * 64 + j] = cx<double>{d, 0.0};
+    const double inv = 1.0 / piv;
+    if (tid == 0) dpiv[j] = piv;
     const int w = nbk - j - 1;
-    for (int idx = tid; idx < w * w; idx += 256) {
-      const int i = j + 1 + idx / w, l = j + 1 + (idx - (idx / w) * w);
-      if (l <= i) {
-        cx<double> a = S[i * 64 + j], b = S[l * 64 + j];
-        cx<double> c = S[i * 64 + l];
-        // c -= a * conj(b)
-        S[i * 64 + l] = cx<double>{c.re - (a.re * b.re + a.im * b.im),
-                                   c.im - (a.im * b.re - a.re * b.im)};
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int idx = tid + q * 256;
+      if (idx < w * 64) {
+        const int i = j + 1 + (idx >> 6), c = idx & 63;
+        const cx<double> aij = Am[i * 64 + j];
+        const cx<double> mu{aij.re * inv, aij.im * inv};
+        cx<double>* M = (c <= j) ? Bm : Am;     // B part left of the pivot, A part right of it
+        const cx<double> r = M[j * 64 + c];
+        cx<double> o = M[i * 64 + c];
+        o.re -= mu.re * r.re - mu.im * r.im;
+        o.im -= mu.re * r.im + mu.im * r.re;
+        M[i * 64 + c] = o;
       }
     }
     __syncthreads();
   }
   __syncthreads();
   if (fail) return;
-  // store L_kk (lower; zero above)
   for (int idx = tid; idx < nbk * nbk; idx += 256) {
-    const int i = idx / nbk, j = idx - (idx / nbk) * nbk;
-    Ac[(size_t)(k0 + i) * N + k0 + j] = (j <= i) ? S[i * 64 + j] : cx<double>{0.0, 0.0};
-  }
-  __syncthreads();
-  // in-place inversion, last column first: with T = inverse of the trailing
-  // block (already in place), column j becomes -T * L[j+1:, j] / L[j][j].
-  for (int j = nbk - 1; j >= 0; --j) {
-    const double ljj = S[j * 64 + j].re;
-    const double ijj = 1.0 / ljj;
-    // tmp[i] = sum_{l=j+1..i} T[i][l] * L[l][j],  i in (j, nbk)
-    for (int i = j + 1 + tid; i < nbk; i += 256) {
-      cx<double> s{0.0, 0.0};
-      for (int l = j + 1; l <= i; ++l) {
-        cx<double> t = S[i * 64 + l], x = S[l * 64 + j];
-        s.re += t.re * x.re - t.im * x.im;
-        s.im += t.re * x.im + t.im * x.re;
-      }
-      tmp[i] = s;
+    const int i = idx / nbk, c = idx - (idx / nbk) * nbk;
+    cx<double> v{0.0, 0.0};
+    if (c <= i) {
+      const double sc = 1.0 / sqrt(dpiv[i]);
+      const cx<double> b = Bm[i * 64 + c];
+      v = cx<double>{b.re * sc, b.im * sc};
     }
-    __syncthreads();
-    for (int i = j + 1 + tid; i < nbk; i += 256)
-      S[i * 64 + j] = cx<double>{-tmp[i].re * ijj, -tmp[i].im * ijj};
-    if (tid == 0) S[j * 64 + j] = cx<double>{ijj, 0.0};
-    __syncthreads();
-  }
-  for (int idx = tid; idx < nbk * nbk; idx += 256) {
-    const int i = idx / nbk, j = idx - (idx / nbk) * nbk;
-    Lc[(size_t)(k0 + i) * N + k0 + j] = (j <= i) ? S[i * 64 + j] : cx<double>{0.0, 0.0};
+    Lc[(size_t)(k0 + i) * N + k0 + c] = v;
   }
 }
 
@@ -431,18 +519,17 @@ __global__ __launch_bounds__(256) void k_forward(EncDev<typename Cfg::T> e, cons
 
 // Adjoint Z[f][n] = sum_m D[f][m] conj(E[m][n]);  with X given, Z -= lam * X.
 // The result is written with storage type SO.
-template <class Cfg, typename SX, typename SO>
-__global__ __launch_bounds__(256) void k_adjoint(EncDev<typename Cfg::T> e,
-                                                 const typename Cfg::T* __restrict__ D, int F,
-                                                 const SX* __restrict__ X, double lam,
+template <class Cfg, typename SD, typename SX, typename SO>
+__global__ __launch_bounds__(256) void k_adjoint(EncDev<typename Cfg::T> e, const SD* __restrict__ D,
+                                                 int F, const SX* __restrict__ X, double lam,
                                                  SO* __restrict__ Z) {
   typedef typename Cfg::T T;
   const int N = e.N, M = e.M;
   const int nbj = (N + Cfg::BN - 1) / Cfg::BN;
   const int t = blockIdx.x;
   const int bi = t / nbj, bj = t % nbj;
-  LoadDenseKC<Cfg, Cfg::BM, Cfg::LDA, T, false> la;
-  la.p = reinterpret_cast<const cx<T>*>(D);
+  LoadDenseKC<Cfg, Cfg::BM, Cfg::LDA, SD, false> la;
+  la.p = reinterpret_cast<const cx<SD>*>(D);
   la.ld = M;
   la.o0 = bi * Cfg::BM;
   la.oend = F;
@@ -518,6 +605,58 @@ __global__ __launch_bounds__(256) void k_tri_frames(const typename Cfg::T* __res
   });
 }
 
+// Normal-equation residual through the Gram (Eq. 6):
+//   Out[f][a] = b[f][a] - sum_n G[a][n] X[f][n] - lam X[f][a]
+// with G the full Hermitian FP64 Gram [N][N] and b = E^H d in FP64.
+template <class Cfg, typename SX, typename SO>
+__global__ __launch_bounds__(256) void k_resid(const double* __restrict__ G,
+                                               const double* __restrict__ b,
+                                               const SX* __restrict__ X, int F, int N, double lam,
+                                               SO* __restrict__ Out) {
+  typedef typename Cfg::T T;
+  const int nbj = (N + Cfg::BN - 1) / Cfg::BN;
+  const int t = blockIdx.x;
+  const int bi = t / nbj, bj = t % nbj;
+  LoadDenseKC<Cfg, Cfg::BM, Cfg::LDA, SX, false> la;     // X[f][n]
+  la.p = reinterpret_cast<const cx<SX>*>(X);
+  la.ld = N;
+  la.o0 = bi * Cfg::BM;
+  la.oend = F;
+  LoadDenseKC<Cfg, Cfg::BN, Cfg::LDB, double, false> lb;  // (o=a, k=n) at G[a][n]
+  lb.p = reinterpret_cast<const cx<double>*>(G);
+  lb.ld = N;
+  lb.o0 = bj * Cfg::BN;
+  lb.oend = N;
+  AccTile<Cfg> acc;
+  acc.zero();
+  mainloop<Cfg>(la, lb, 0, N, acc, smem_base<Cfg>());
+  cx<SO>* O = reinterpret_cast<cx<SO>*>(Out);
+  const cx<double>* bc = reinterpret_cast<const cx<double>*>(b);
+  const cx<SX>* Xc = reinterpret_cast<const cx<SX>*>(X);
+  const int r0 = bi * Cfg::BM, c0 = bj * Cfg::BN;
+  acc_foreach<Cfg>(acc, [&](int r, int c, T re, T im) {
+    const int row = r0 + r, col = c0 + c;
+    if (row < F && col < N) {
+      const size_t o = (size_t)row * N + col;
+      const cx<double> bb = bc[o];
+      const cx<SX> x = Xc[o];
+      O[o] = cx<SO>{SO(bb.re - (double)re - lam * (double)x.re),
+                    SO(bb.im - (double)im - lam * (double)x.im)};
+    }
+  });
+}
+
+// Fill the strict upper triangle of an N x N complex matrix from its lower part.
+__global__ void k_herm_fill(double* __restrict__ G, int N) {
+  cx<double>* g = reinterpret_cast<cx<double>*>(G);
+  const int col = blockIdx.x * 16 + (threadIdx.x & 15);
+  const int row = blockIdx.y * 16 + (threadIdx.x >> 4);
+  if (row < N && col < N && row < col) {
+    const cx<double> v = g[(size_t)col * N + row];
+    g[(size_t)row * N + col] = cx<double>{v.re, -v.im};
+  }
+}
+
 // Elementwise FP64 -> FP32 complex copy (n complex values).
 __global__ void k_to_f32(const double* __restrict__ in, float* __restrict__ out, size_t n2) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n2;
@@ -531,6 +670,10 @@ __global__ void k_to_f32(const double* __restrict__ in, float* __restrict__ out,
 typedef TileCfg<float, 128, 128, 8> F32Cfg;
 typedef TileCfg<double, 64, 64, 8> F64Cfg;
 
+template <typename T> struct GramCfgOf;     // square tiles for the triangular Gram grid
+template <> struct GramCfgOf<float> { typedef TileCfg<float, 128, 128, 8> type; };
+template <> struct GramCfgOf<double> { typedef TileCfg<double, 64, 64, 8> type; };
+
 template <class Cfg> static size_t smem_bytes() { return Cfg::SMEM_ELEMS * sizeof(typename Cfg::T); }
 
 template <typename T> struct PickCfg;
@@ -541,7 +684,7 @@ static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 
 template <typename T>
 hipError_t launch_gram(const EncDev<T>& e, double* G, int flush, hipStream_t s) {
-  typedef typename PickCfg<T>::type Cfg;
+  typedef typename GramCfgOf<T>::type Cfg;
   const int nb = cdiv(e.N, Cfg::BM);
   const int tiles = nb * (nb + 1) / 2;
   if (flush <= 0 || sizeof(T) == 8) flush = e.M;
@@ -550,10 +693,24 @@ hipError_t launch_gram(const EncDev<T>& e, double* G, int flush, hipStream_t s) 
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_gram_shared(const EncDev<T>& e, double* G, hipStream_t s) {
+  typedef typename GramCfgOf<T>::type Cfg;
+  EncDev<T> f = e;       // the coil-free encoding F over one coil's K rows
+  f.coil = nullptr;
+  f.C = 1;
+  f.M = e.K;
+  const int nb = cdiv(e.N, Cfg::BM);
+  const int tiles = nb * (nb + 1) / 2;
+  hipLaunchKernelGGL(k_gram_shared<Cfg>, dim3(tiles), dim3(256), smem_bytes<Cfg>(), s, f, e.coil,
+                     e.coil ? e.C : 1, G);
+  return hipGetLastError();
+}
+
 hipError_t launch_cholinv(double* A, double* Li, int N, double lam, int* info, hipStream_t s) {
   const int nb = 64;
   const int nblk = cdiv(N, nb);
-  const size_t diag_smem = (64 * 64 + 64) * sizeof(cx<double>);
+  const size_t diag_smem = kDiagSmem;
   static bool attr = false;
   if (!attr) {
     hipError_t err = hipFuncSetAttribute((const void*)k_chol_diag,
@@ -617,14 +774,31 @@ hipError_t launch_forward(const EncDev<T>& e, const SX* X, int F, const SD* Din,
   return hipGetLastError();
 }
 
-template <typename T, typename SX, typename SO>
-hipError_t launch_adjoint(const EncDev<T>& e, const T* D, int F, const SX* X, double lam, SO* Z,
+template <typename T, typename SD, typename SX, typename SO>
+hipError_t launch_adjoint(const EncDev<T>& e, const SD* D, int F, const SX* X, double lam, SO* Z,
                           hipStream_t s) {
   typedef typename PickCfg<T>::type Cfg;
   const int tiles = cdiv(F, Cfg::BM) * cdiv(e.N, Cfg::BN);
   if (tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_adjoint<Cfg, SX, SO>), dim3(tiles), dim3(256), smem_bytes<Cfg>(), s, e, D,
-                     F, X, lam, Z);
+  hipLaunchKernelGGL((k_adjoint<Cfg, SD, SX, SO>), dim3(tiles), dim3(256), smem_bytes<Cfg>(), s, e,
+                     D, F, X, lam, Z);
+  return hipGetLastError();
+}
+
+template <typename SX, typename SO>
+hipError_t launch_resid(const double* G, const double* b, const SX* X, int F, int N, double lam,
+                        SO* Out, hipStream_t s) {
+  typedef F64Cfg Cfg;
+  const int tiles = cdiv(F, Cfg::BM) * cdiv(N, Cfg::BN);
+  if (tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_resid<Cfg, SX, SO>), dim3(tiles), dim3(256), smem_bytes<Cfg>(), s, G, b, X,
+                     F, N, lam, Out);
+  return hipGetLastError();
+}
+
+hipError_t launch_herm_fill(double* G, int N, hipStream_t s) {
+  dim3 grid(cdiv(N, 16), cdiv(N, 16));
+  hipLaunchKernelGGL(k_herm_fill, grid, dim3(256), 0, s, G, N);
   return hipGetLastError();
 }
 
@@ -649,6 +823,8 @@ hipError_t launch_to_f32(const double* in, float* out, size_t n_complex, hipStre
 // explicit instantiations
 template hipError_t launch_gram<float>(const EncDev<float>&, double*, int, hipStream_t);
 template hipError_t launch_gram<double>(const EncDev<double>&, double*, int, hipStream_t);
+template hipError_t launch_gram_shared<float>(const EncDev<float>&, double*, hipStream_t);
+template hipError_t launch_gram_shared<double>(const EncDev<double>&, double*, hipStream_t);
 template hipError_t launch_trmm_w<float>(const EncDev<float>&, const float*, float*, hipStream_t);
 template hipError_t launch_trmm_w<double>(const EncDev<double>&, const double*, double*, hipStream_t);
 template hipError_t launch_trmm_r<float>(const float*, const float*, float*, int, int, hipStream_t);
@@ -663,13 +839,20 @@ template hipError_t launch_forward<double, double, double>(const EncDev<double>&
                                                            const double*, double*, hipStream_t);
 template hipError_t launch_forward<double, float, float>(const EncDev<double>&, const float*, int,
                                                          const float*, double*, hipStream_t);
-template hipError_t launch_adjoint<double, float, float>(const EncDev<double>&, const double*, int,
-                                                         const float*, double, float*, hipStream_t);
-template hipError_t launch_adjoint<double, double, double>(const EncDev<double>&, const double*, int,
-                                                           const double*, double, double*,
-                                                           hipStream_t);
-template hipError_t launch_adjoint<float, float, float>(const EncDev<float>&, const float*, int,
-                                                        const float*, double, float*, hipStream_t);
+template hipError_t launch_adjoint<double, double, float, float>(const EncDev<double>&, const double*,
+                                                                int, const float*, double, float*,
+                                                                hipStream_t);
+template hipError_t launch_adjoint<double, double, double, double>(const EncDev<double>&,
+                                                                   const double*, int,
+                                                                   const double*, double, double*,
+                                                                   hipStream_t);
+template hipError_t launch_adjoint<double, float, float, double>(const EncDev<double>&, const float*,
+                                                                 int, const float*, double,
+                                                                 double*, hipStream_t);
+template hipError_t launch_resid<float, float>(const double*, const double*, const float*, int, int,
+                                               double, float*, hipStream_t);
+template hipError_t launch_resid<double, double>(const double*, const double*, const double*, int,
+                                                 int, double, double*, hipStream_t);
 template hipError_t launch_tri_frames<float, 0, float>(const float*, const float*, int, int, float*,
                                                        hipStream_t);
 template hipError_t launch_tri_frames<float, 1, float>(const float*, const float*, int, int, float*,

@@ -21,6 +21,7 @@ FP64, FP32, BF16X3 = 0, 1, 2
 LAMBDA_ABS, LAMBDA_REL_MEAN_DIAG = 0, 1
 FLAG_KEEP_GRAM = 1
 FLAG_UNCACHED = 2
+FLAG_GRAM_FULL = 4
 BUF_R, BUF_LINV, BUF_GRAM = 0, 1, 2
 
 if not os.path.exists(LIB_PATH):

@@ -6,12 +6,14 @@ and 1000) and include the species and off-resonance factors.  Tolerances:
 * FP64 plans: every stage within 1e-9 relative (Frobenius) of the oracle; the
   FP64 forward error of the Cholesky route is ~kappa(G_l) * 1e-16 with
   kappa <= 1e4 here.
-* FP32 plans: Gram entries within 2048 * u32 = 1.2e-4 of max|G|: each Gram
-  entry is a sum of FP32 products accumulated in FP32 over segments of 2048
-  rows (then carried in FP64), and a sum of L terms bounded by max|G| carries
-  at most about L*u32*max|G| of rounding.  Images after two refinement steps
-  within 1e-5 (the target for the FP32 path); before refinement within
-  kappa(G_l) * 1e-6.
+* Default Gram (FP64 F^H F times the coil cross-products, exact because every
+  coil shares the trajectory): within 1e-12 of max|G| for every plan.
+* Full-M Gram in FP32 (PINV_FLAG_GRAM_FULL): within 2048 * u32 = 1.2e-4 of
+  max|G|: each entry is a sum of FP32 products accumulated in FP32 over
+  segments of 2048 rows (then carried in FP64), and a sum of L terms bounded
+  by max|G| carries at most about L*u32*max|G| of rounding.
+* FP32 plans: images after two refinement steps within 1e-5 (the target for
+  the FP32 path); before refinement within kappa(G_l) * 1e-6.
 """
 import numpy as np
 import pytest
@@ -121,7 +123,7 @@ def test_fp32_path_matches_oracle(P, ctx, name):
     G = np.tril(G.cpu().numpy())
     Go = np.tril(o["b"].G)
     gerr = np.max(np.abs(G - Go)) / np.max(np.abs(Go))
-    assert gerr < 2048 * 2.0 ** -24, gerr
+    assert gerr < 1e-12, gerr
     d = to_dev(o["d"], np.complex64)
     x0 = torch.empty((d.shape[0], N), dtype=torch.complex64, device="cuda")
     P.pinv_apply(ctx, plan, d, x0, refine_steps=0)
@@ -133,6 +135,29 @@ def test_fp32_path_matches_oracle(P, ctx, name):
     print(f"{name}: kappa={o['kappa']:.3g} gram_err={gerr:.2e} err0={e0.max():.2e} err2={e2.max():.2e}")
     assert e0.max() < o["kappa"] * 1e-6
     assert e2.max() < 1e-5
+    P.pinv_plan_release(plan)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_full_gram_matches_oracle(P, ctx, name, prec):
+    """The Gram over all M rows in the plan's precision (no shared-trajectory shortcut)."""
+    o = oracle_case(name)
+    enc, N = o["w"].enc, o["w"].enc.N
+    p = P.FP64 if prec == "fp64" else P.FP32
+    plan = build(P, ctx, enc, p, flags=P.FLAG_KEEP_GRAM | P.FLAG_GRAM_FULL)
+    G = torch.empty((N, N), dtype=torch.complex128, device="cuda")
+    P.pinv_plan_copy_buffer(plan, P.BUF_GRAM, G)
+    d = to_dev(o["d"], np.complex128 if prec == "fp64" else np.complex64)
+    x = torch.empty((d.shape[0], N), dtype=d.dtype, device="cuda")
+    P.pinv_apply(ctx, plan, d, x, refine_steps=0 if prec == "fp64" else 2)
+    torch.cuda.synchronize()
+    G = np.tril(G.cpu().numpy())
+    Go = np.tril(o["b"].G)
+    gerr = np.max(np.abs(G - Go)) / np.max(np.abs(Go))
+    assert gerr < (1e-12 if prec == "fp64" else 2048 * 2.0 ** -24), gerr
+    err = frame_rel(x.cpu().numpy().astype(np.complex128), o["x"]).max()
+    assert err < (1e-9 if prec == "fp64" else 1e-5), err
     P.pinv_plan_release(plan)
 
 
