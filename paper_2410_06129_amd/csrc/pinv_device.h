@@ -58,6 +58,13 @@ template <typename T> struct EncDev {
   int M, N;       // M = C*K rows, N = S*V columns
 };
 
+// Which optional factors an encoding has; generated-operand kernels are
+// specialised on this so that absent factors cost neither loads nor registers.
+enum { FEAT_Q = 1, FEAT_B0 = 2, FEAT_COIL = 4 };
+template <typename T> inline int enc_features(const EncDev<T>& e) {
+  return (e.q ? FEAT_Q : 0) | (e.b0 ? FEAT_B0 : 0) | (e.coil ? FEAT_COIL : 0);
+}
+
 // ---------------------------------------------------------------------------
 // Tile configuration
 // ---------------------------------------------------------------------------
@@ -300,34 +307,35 @@ template <typename T> struct GenRaw {
   T b0t;
 };
 
-template <typename T>
+template <int FEAT, typename T>
 __device__ __forceinline__ void gen_load(const EncDev<T>& e, int i, int s, int v, int ix, int iy,
                                          int c, GenRaw<T>& r) {
   const cx<T>* px = reinterpret_cast<const cx<T>*>(e.px);
   const cx<T>* py = reinterpret_cast<const cx<T>*>(e.py);
   r.px = px[(size_t)i * e.nx + ix];
   r.py = py[(size_t)i * e.ny + iy];
-  if (e.q) r.q = reinterpret_cast<const cx<T>*>(e.q)[(size_t)i * e.S + s];
-  if (e.b0) r.b0t = e.b0[v] * e.t[i];
-  if (e.coil) r.coil = reinterpret_cast<const cx<T>*>(e.coil)[(size_t)c * e.V + v];
+  if constexpr ((FEAT & FEAT_Q) != 0) r.q = reinterpret_cast<const cx<T>*>(e.q)[(size_t)i * e.S + s];
+  if constexpr ((FEAT & FEAT_B0) != 0) r.b0t = e.b0[v] * e.t[i];
+  if constexpr ((FEAT & FEAT_COIL) != 0)
+    r.coil = reinterpret_cast<const cx<T>*>(e.coil)[(size_t)c * e.V + v];
 }
 
-template <typename T>
-__device__ __forceinline__ cx<T> gen_product(const EncDev<T>& e, const GenRaw<T>& r) {
+template <int FEAT, typename T>
+__device__ __forceinline__ cx<T> gen_product(const GenRaw<T>& r) {
   cx<T> p = cmul(r.px, r.py);
-  if (e.q) p = cmul(p, r.q);
-  if (e.b0) {
+  if constexpr ((FEAT & FEAT_Q) != 0) p = cmul(p, r.q);
+  if constexpr ((FEAT & FEAT_B0) != 0) {
     T sn, cs;
     sincospi_t(T(-2) * r.b0t, &sn, &cs);
     p = cmul(p, cx<T>{cs, sn});
   }
-  if (e.coil) p = cmul(p, r.coil);
+  if constexpr ((FEAT & FEAT_COIL) != 0) p = cmul(p, r.coil);
   return p;
 }
 
 // Generated operand, outer index = column n of E, k = row m of E:
 // element (o, k) = E[k, o] (or its conjugate).  Each thread keeps one column.
-template <class Cfg, int OUTER, int LD, bool CONJ>
+template <class Cfg, int OUTER, int LD, bool CONJ, int FEAT>
 struct LoadGenCol {
   typedef typename Cfg::T T;
   static constexpr int KPP = Cfg::NT / OUTER;
@@ -356,7 +364,7 @@ struct LoadGenCol {
 #pragma unroll
     for (int j = 0; j < PASSES; ++j) {
       ok[j] = valid && m < kend;
-      gen_load(e, ok[j] ? i : 0, s, v, ix, iy, ok[j] ? c : 0, raw[j]);
+      gen_load<FEAT>(e, ok[j] ? i : 0, s, v, ix, iy, ok[j] ? c : 0, raw[j]);
       m += KPP;
       i += KPP;
 #pragma unroll
@@ -371,7 +379,7 @@ struct LoadGenCol {
 #pragma unroll
     for (int j = 0; j < PASSES; ++j) {
       if ((j * steps) / PASSES != step) continue;
-      const cx<T> el = gen_product(e, raw[j]);
+      const cx<T> el = gen_product<FEAT>(raw[j]);
       re[j] = ok[j] ? el.re : T(0);
       im[j] = ok[j] ? (CONJ ? -el.im : el.im) : T(0);
     }
@@ -389,7 +397,7 @@ struct LoadGenCol {
 
 // Generated operand, outer index = row m of E, k = column n of E:
 // element (o, k) = E[o, k] (or its conjugate).  Each thread keeps one row.
-template <class Cfg, int OUTER, int LD, bool CONJ>
+template <class Cfg, int OUTER, int LD, bool CONJ, int FEAT>
 struct LoadGenRow {
   typedef typename Cfg::T T;
   static constexpr int KPP = Cfg::NT / OUTER;
@@ -420,7 +428,7 @@ struct LoadGenRow {
     for (int j = 0; j < PASSES; ++j) {
       ok[j] = valid && n < kend;
       const bool in = n < e.N;
-      gen_load(e, i, in ? s : 0, in ? iy * e.nx + ix : 0, in ? ix : 0, in ? iy : 0, c, raw[j]);
+      gen_load<FEAT>(e, i, in ? s : 0, in ? iy * e.nx + ix : 0, in ? ix : 0, in ? iy : 0, c, raw[j]);
       n += KPP;
       ix += KPP;
 #pragma unroll
@@ -438,7 +446,7 @@ struct LoadGenRow {
 #pragma unroll
     for (int j = 0; j < PASSES; ++j) {
       if ((j * steps) / PASSES != step) continue;
-      const cx<T> el = gen_product(e, raw[j]);
+      const cx<T> el = gen_product<FEAT>(raw[j]);
       re[j] = ok[j] ? el.re : T(0);
       im[j] = ok[j] ? (CONJ ? -el.im : el.im) : T(0);
     }

@@ -9,6 +9,8 @@
 //   forward     D = X E^T  (data = E image, Eq. 1), optionally d - E x
 //   adjoint     Z = D conj(E), optionally minus lam x                 (Eq. 6 residual)
 //   tri_apply   products with L^-1 and L^-H for the refinement correction
+#include <type_traits>
+
 #include "pinv_internal.h"
 
 namespace pinv {
@@ -36,16 +38,16 @@ __device__ __forceinline__ void tri_index(int t, int* bi, int* bj) {
 // FP32 tiles flush their FP32 partial sums into the FP64 Gram every `flush`
 // rows so the long sum over M is carried in FP64.
 // ---------------------------------------------------------------------------
-template <class Cfg>
-__global__ __launch_bounds__(256) void k_gram(EncDev<typename Cfg::T> e, double* __restrict__ G,
+template <class Cfg, int FEAT>
+__global__ __launch_bounds__(256, 2) void k_gram(EncDev<typename Cfg::T> e, double* __restrict__ G,
                                               int flush) {
   typedef typename Cfg::T T;
   static_assert(Cfg::BM == Cfg::BN, "square tiles");
   int bi, bj;
   tri_index(blockIdx.x, &bi, &bj);
   const int N = e.N;
-  LoadGenCol<Cfg, Cfg::BM, Cfg::LDA, true> la;
-  LoadGenCol<Cfg, Cfg::BN, Cfg::LDB, false> lb;
+  LoadGenCol<Cfg, Cfg::BM, Cfg::LDA, true, FEAT> la;
+  LoadGenCol<Cfg, Cfg::BN, Cfg::LDB, false, FEAT> lb;
   la.init(e, bi * Cfg::BM);
   lb.init(e, bj * Cfg::BN);
   T* smem = smem_base<Cfg>();
@@ -83,8 +85,8 @@ __global__ __launch_bounds__(256) void k_gram(EncDev<typename Cfg::T> e, double*
 // staged in LDS.  `e` must describe F (no coil table, C = 1, M = K); `coil`
 // is the [C][V] coil table (or null for one unit coil).
 // ---------------------------------------------------------------------------
-template <class Cfg>
-__global__ __launch_bounds__(256) void k_gram_shared(EncDev<typename Cfg::T> e,
+template <class Cfg, int FEAT>
+__global__ __launch_bounds__(256, 2) void k_gram_shared(EncDev<typename Cfg::T> e,
                                                      const typename Cfg::T* __restrict__ coil,
                                                      int C, double* __restrict__ G) {
   typedef typename Cfg::T T;
@@ -92,8 +94,8 @@ __global__ __launch_bounds__(256) void k_gram_shared(EncDev<typename Cfg::T> e,
   int bi, bj;
   tri_index(blockIdx.x, &bi, &bj);
   const int N = e.N, V = e.V;
-  LoadGenCol<Cfg, Cfg::BM, Cfg::LDA, true> la;
-  LoadGenCol<Cfg, Cfg::BN, Cfg::LDB, false> lb;
+  LoadGenCol<Cfg, Cfg::BM, Cfg::LDA, true, FEAT> la;
+  LoadGenCol<Cfg, Cfg::BN, Cfg::LDB, false, FEAT> lb;
   la.init(e, bi * Cfg::BM);
   lb.init(e, bj * Cfg::BN);
   T* smem = smem_base<Cfg>();
@@ -101,68 +103,54 @@ __global__ __launch_bounds__(256) void k_gram_shared(EncDev<typename Cfg::T> e,
   acc.zero();
   mainloop<Cfg>(la, lb, 0, e.M, acc, smem);
   const int r0 = bi * Cfg::BM, c0 = bj * Cfg::BN;
-  // coil cross-products for this lane's elements
-  cx<double> sv[Cfg::MB][Cfg::NB][4];
-#pragma unroll
-  for (int a = 0; a < Cfg::MB; ++a)
-#pragma unroll
-    for (int b = 0; b < Cfg::NB; ++b)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) sv[a][b][r] = cx<double>{coil ? 0.0 : 1.0, 0.0};
-  if (coil) {
-    // stage coil values of the tile's rows and columns, CC coils at a time
-    constexpr int CC = (Cfg::SMEM_ELEMS * sizeof(T)) / (sizeof(cx<T>) * (Cfg::BM + Cfg::BN));
-    static_assert(CC >= 1, "no room for coil staging");
-    cx<T>* sa = reinterpret_cast<cx<T>*>(smem);          // [CC][BM]
-    cx<T>* sb = sa + CC * Cfg::BM;                       // [CC][BN]
-    const cx<T>* cc = reinterpret_cast<const cx<T>*>(coil);
-    for (int c0c = 0; c0c < C; c0c += CC) {
-      const int nc = min(CC, C - c0c);
-      for (int idx = threadIdx.x; idx < nc * (Cfg::BM + Cfg::BN); idx += Cfg::NT) {
-        const int c = idx / (Cfg::BM + Cfg::BN), o = idx - c * (Cfg::BM + Cfg::BN);
-        const int g = o < Cfg::BM ? r0 + o : c0 + (o - Cfg::BM);
-        cx<T> v{T(0), T(0)};
-        if (g < N) v = cc[(size_t)(c0c + c) * V + (g % V)];
-        if (o < Cfg::BM) sa[c * Cfg::BM + o] = v; else sb[c * Cfg::BN + (o - Cfg::BM)] = v;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int a = 0; a < Cfg::MB; ++a)
-#pragma unroll
-        for (int b = 0; b < Cfg::NB; ++b)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            int row, col;
-            acc_coord<Cfg>(a, b, r, &row, &col);
-            cx<double> s = sv[a][b][r];
-            for (int c = 0; c < nc; ++c) {
-              const cx<T> x = sa[c * Cfg::BM + row], y = sb[c * Cfg::BN + col];
-              // conj(x) * y
-              s.re += (double)x.re * (double)y.re + (double)x.im * (double)y.im;
-              s.im += (double)x.re * (double)y.im - (double)x.im * (double)y.re;
-            }
-            sv[a][b][r] = s;
-          }
-      __syncthreads();
-    }
-  }
   cx<double>* Gc = reinterpret_cast<cx<double>*>(G);
-#pragma unroll
-  for (int a = 0; a < Cfg::MB; ++a)
-#pragma unroll
-    for (int b = 0; b < Cfg::NB; ++b)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        int row, col;
-        acc_coord<Cfg>(a, b, r, &row, &col);
-        row += r0;
-        col += c0;
-        if (row < N && col < N) {
-          const double fr = (double)acc.re[a][b][r], fi = (double)acc.im[a][b][r];
-          const cx<double> s = sv[a][b][r];
-          Gc[(size_t)row * N + col] = cx<double>{fr * s.re - fi * s.im, fr * s.im + fi * s.re};
-        }
+  if (!coil) {
+    acc_foreach<Cfg>(acc, [&](int r, int c, T re, T im) {
+      const int row = r0 + r, col = c0 + c;
+      if (row < N && col < N) Gc[(size_t)row * N + col] = cx<double>{(double)re, (double)im};
+    });
+    return;
+  }
+  // coil cross-products: stage the coil values of the tile's rows and columns,
+  // CC coils at a time, and accumulate F^H F * sum_c conj(C_c(v_a)) C_c(v_b)
+  // into G (written by the first chunk, updated by later ones)
+  constexpr int CC = (Cfg::SMEM_ELEMS * sizeof(T)) / (sizeof(cx<T>) * (Cfg::BM + Cfg::BN));
+  static_assert(CC >= 1, "no room for coil staging");
+  cx<T>* sa = reinterpret_cast<cx<T>*>(smem);          // [CC][BM]
+  cx<T>* sb = sa + CC * Cfg::BM;                       // [CC][BN]
+  const cx<T>* cc = reinterpret_cast<const cx<T>*>(coil);
+  for (int c0c = 0; c0c < C; c0c += CC) {
+    const int nc = min(CC, C - c0c);
+    for (int idx = threadIdx.x; idx < nc * (Cfg::BM + Cfg::BN); idx += Cfg::NT) {
+      const int c = idx / (Cfg::BM + Cfg::BN), o = idx - c * (Cfg::BM + Cfg::BN);
+      const int g = o < Cfg::BM ? r0 + o : c0 + (o - Cfg::BM);
+      cx<T> v{T(0), T(0)};
+      if (g < N) v = cc[(size_t)(c0c + c) * V + (g % V)];
+      if (o < Cfg::BM) sa[c * Cfg::BM + o] = v; else sb[c * Cfg::BN + (o - Cfg::BM)] = v;
+    }
+    __syncthreads();
+    acc_foreach<Cfg>(acc, [&](int r, int c, T re, T im) {
+      const int row = r0 + r, col = c0 + c;
+      double sr = 0.0, si = 0.0;
+      for (int q = 0; q < nc; ++q) {
+        const cx<T> x = sa[q * Cfg::BM + r], y = sb[q * Cfg::BN + c];
+        sr += (double)x.re * (double)y.re + (double)x.im * (double)y.im;   // conj(x) * y
+        si += (double)x.re * (double)y.im - (double)x.im * (double)y.re;
       }
+      if (row < N && col < N) {
+        const double fr = (double)re, fi = (double)im;
+        cx<double> v{fr * sr - fi * si, fr * si + fi * sr};
+        cx<double>* g = Gc + (size_t)row * N + col;
+        if (c0c > 0) {
+          const cx<double> o = *g;
+          v.re += o.re;
+          v.im += o.im;
+        }
+        *g = v;
+      }
+    });
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -221,15 +209,17 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ A, doubl
     const double inv = 1.0 / piv;
     if (tid == 0) dpiv[j] = piv;
     const int w = nbk - j - 1;
+    // every slot of this thread has column c = tid % 64: read row j once
+    const int c = tid & 63;
+    cx<double>* M = (c <= j) ? Bm : Am;     // B part left of the pivot, A part right of it
+    const cx<double> r = M[j * 64 + c];
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int idx = tid + q * 256;
       if (idx < w * 64) {
-        const int i = j + 1 + (idx >> 6), c = idx & 63;
+        const int i = j + 1 + (idx >> 6);
         const cx<double> aij = Am[i * 64 + j];
         const cx<double> mu{aij.re * inv, aij.im * inv};
-        cx<double>* M = (c <= j) ? Bm : Am;     // B part left of the pivot, A part right of it
-        const cx<double> r = M[j * 64 + c];
         cx<double> o = M[i * 64 + c];
         o.re -= mu.re * r.re - mu.im * r.im;
         o.im -= mu.re * r.im + mu.im * r.re;
@@ -381,7 +371,7 @@ __global__ __launch_bounds__(256) void k_chol_trailing(double* __restrict__ A, d
 // ---------------------------------------------------------------------------
 // W = L^-1 E^H : W[i][m] = sum_{n <= i} Li[i][n] conj(E[m][n])
 // ---------------------------------------------------------------------------
-template <class Cfg>
+template <class Cfg, int FEAT>
 __global__ __launch_bounds__(256) void k_trmm_w(EncDev<typename Cfg::T> e,
                                                 const typename Cfg::T* __restrict__ Li,
                                                 typename Cfg::T* __restrict__ W) {
@@ -395,7 +385,7 @@ __global__ __launch_bounds__(256) void k_trmm_w(EncDev<typename Cfg::T> e,
   la.ld = N;
   la.o0 = bi * Cfg::BM;
   la.oend = N;
-  LoadGenRow<Cfg, Cfg::BN, Cfg::LDB, true> lb;
+  LoadGenRow<Cfg, Cfg::BN, Cfg::LDB, true, FEAT> lb;
   lb.init(e, bj * Cfg::BN);
   AccTile<Cfg> acc;
   acc.zero();
@@ -481,8 +471,8 @@ __global__ __launch_bounds__(256) void k_apply(const ApplyBatch batch) {
 // Forward model D[f][m] = sum_n X[f][n] E[m][n]  (S = storage type of X).
 // With `sub` set the result is Dout = Din - E x (refinement residual).
 // ---------------------------------------------------------------------------
-template <class Cfg, typename SX, typename SD>
-__global__ __launch_bounds__(256) void k_forward(EncDev<typename Cfg::T> e, const SX* __restrict__ X,
+template <class Cfg, int FEAT, typename SX, typename SD>
+__global__ __launch_bounds__(256, 2) void k_forward(EncDev<typename Cfg::T> e, const SX* __restrict__ X,
                                                  int F, const SD* __restrict__ Din,
                                                  typename Cfg::T* __restrict__ Dout) {
   typedef typename Cfg::T T;
@@ -495,7 +485,7 @@ __global__ __launch_bounds__(256) void k_forward(EncDev<typename Cfg::T> e, cons
   la.ld = N;
   la.o0 = bi * Cfg::BM;
   la.oend = F;
-  LoadGenRow<Cfg, Cfg::BN, Cfg::LDB, false> lb;
+  LoadGenRow<Cfg, Cfg::BN, Cfg::LDB, false, FEAT> lb;
   lb.init(e, bj * Cfg::BN);
   AccTile<Cfg> acc;
   acc.zero();
@@ -519,8 +509,8 @@ __global__ __launch_bounds__(256) void k_forward(EncDev<typename Cfg::T> e, cons
 
 // Adjoint Z[f][n] = sum_m D[f][m] conj(E[m][n]);  with X given, Z -= lam * X.
 // The result is written with storage type SO.
-template <class Cfg, typename SD, typename SX, typename SO>
-__global__ __launch_bounds__(256) void k_adjoint(EncDev<typename Cfg::T> e, const SD* __restrict__ D,
+template <class Cfg, int FEAT, typename SD, typename SX, typename SO>
+__global__ __launch_bounds__(256, 2) void k_adjoint(EncDev<typename Cfg::T> e, const SD* __restrict__ D,
                                                  int F, const SX* __restrict__ X, double lam,
                                                  SO* __restrict__ Z) {
   typedef typename Cfg::T T;
@@ -533,7 +523,7 @@ __global__ __launch_bounds__(256) void k_adjoint(EncDev<typename Cfg::T> e, cons
   la.ld = M;
   la.o0 = bi * Cfg::BM;
   la.oend = F;
-  LoadGenCol<Cfg, Cfg::BN, Cfg::LDB, true> lb;
+  LoadGenCol<Cfg, Cfg::BN, Cfg::LDB, true, FEAT> lb;
   lb.init(e, bj * Cfg::BN);
   AccTile<Cfg> acc;
   acc.zero();
@@ -682,6 +672,20 @@ template <> struct PickCfg<double> { typedef F64Cfg type; };
 
 static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 
+// Calls f(std::integral_constant<int, FEAT>) for the runtime feature mask.
+template <class F> static hipError_t with_feat(int feat, F&& f) {
+  switch (feat & 7) {
+    case 0: return f(std::integral_constant<int, 0>{});
+    case 1: return f(std::integral_constant<int, 1>{});
+    case 2: return f(std::integral_constant<int, 2>{});
+    case 3: return f(std::integral_constant<int, 3>{});
+    case 4: return f(std::integral_constant<int, 4>{});
+    case 5: return f(std::integral_constant<int, 5>{});
+    case 6: return f(std::integral_constant<int, 6>{});
+    default: return f(std::integral_constant<int, 7>{});
+  }
+}
+
 template <typename T>
 hipError_t launch_gram(const EncDev<T>& e, double* G, int flush, hipStream_t s) {
   typedef typename GramCfgOf<T>::type Cfg;
@@ -689,8 +693,11 @@ hipError_t launch_gram(const EncDev<T>& e, double* G, int flush, hipStream_t s) 
   const int tiles = nb * (nb + 1) / 2;
   if (flush <= 0 || sizeof(T) == 8) flush = e.M;
   flush = ((flush + Cfg::BK - 1) / Cfg::BK) * Cfg::BK;
-  hipLaunchKernelGGL(k_gram<Cfg>, dim3(tiles), dim3(256), smem_bytes<Cfg>(), s, e, G, flush);
-  return hipGetLastError();
+  return with_feat(enc_features(e), [&](auto fc) {
+    hipLaunchKernelGGL((k_gram<Cfg, decltype(fc)::value>), dim3(tiles), dim3(256), smem_bytes<Cfg>(),
+                       s, e, G, flush);
+    return hipGetLastError();
+  });
 }
 
 template <typename T>
@@ -702,9 +709,11 @@ hipError_t launch_gram_shared(const EncDev<T>& e, double* G, hipStream_t s) {
   f.M = e.K;
   const int nb = cdiv(e.N, Cfg::BM);
   const int tiles = nb * (nb + 1) / 2;
-  hipLaunchKernelGGL(k_gram_shared<Cfg>, dim3(tiles), dim3(256), smem_bytes<Cfg>(), s, f, e.coil,
-                     e.coil ? e.C : 1, G);
-  return hipGetLastError();
+  return with_feat(enc_features(f) & 3, [&](auto fc) {
+    hipLaunchKernelGGL((k_gram_shared<Cfg, decltype(fc)::value & 3>), dim3(tiles), dim3(256),
+                       smem_bytes<Cfg>(), s, f, e.coil, e.coil ? e.C : 1, G);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_cholinv(double* A, double* Li, int N, double lam, int* info, hipStream_t s) {
@@ -737,8 +746,11 @@ template <typename T>
 hipError_t launch_trmm_w(const EncDev<T>& e, const T* Li, T* W, hipStream_t s) {
   typedef typename PickCfg<T>::type Cfg;
   const int tiles = cdiv(e.N, Cfg::BM) * cdiv(e.M, Cfg::BN);
-  hipLaunchKernelGGL(k_trmm_w<Cfg>, dim3(tiles), dim3(256), smem_bytes<Cfg>(), s, e, Li, W);
-  return hipGetLastError();
+  return with_feat(enc_features(e), [&](auto fc) {
+    hipLaunchKernelGGL((k_trmm_w<Cfg, decltype(fc)::value>), dim3(tiles), dim3(256),
+                       smem_bytes<Cfg>(), s, e, Li, W);
+    return hipGetLastError();
+  });
 }
 
 template <typename T>
@@ -769,9 +781,11 @@ hipError_t launch_forward(const EncDev<T>& e, const SX* X, int F, const SD* Din,
   typedef typename PickCfg<T>::type Cfg;
   const int tiles = cdiv(F, Cfg::BM) * cdiv(e.M, Cfg::BN);
   if (tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_forward<Cfg, SX, SD>), dim3(tiles), dim3(256), smem_bytes<Cfg>(), s, e, X,
-                     F, Din, Dout);
-  return hipGetLastError();
+  return with_feat(enc_features(e), [&](auto fc) {
+    hipLaunchKernelGGL((k_forward<Cfg, decltype(fc)::value, SX, SD>), dim3(tiles), dim3(256),
+                       smem_bytes<Cfg>(), s, e, X, F, Din, Dout);
+    return hipGetLastError();
+  });
 }
 
 template <typename T, typename SD, typename SX, typename SO>
@@ -780,9 +794,11 @@ hipError_t launch_adjoint(const EncDev<T>& e, const SD* D, int F, const SX* X, d
   typedef typename PickCfg<T>::type Cfg;
   const int tiles = cdiv(F, Cfg::BM) * cdiv(e.N, Cfg::BN);
   if (tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_adjoint<Cfg, SD, SX, SO>), dim3(tiles), dim3(256), smem_bytes<Cfg>(), s, e,
-                     D, F, X, lam, Z);
-  return hipGetLastError();
+  return with_feat(enc_features(e), [&](auto fc) {
+    hipLaunchKernelGGL((k_adjoint<Cfg, decltype(fc)::value, SD, SX, SO>), dim3(tiles), dim3(256),
+                       smem_bytes<Cfg>(), s, e, D, F, X, lam, Z);
+    return hipGetLastError();
+  });
 }
 
 template <typename SX, typename SO>
