@@ -63,6 +63,94 @@ def cpu_baseline(w) -> dict:
                       f"{flops:.3g} complex-equivalent flops in {dt:.2f} s"}
 
 
+def serving(args) -> dict:
+    """Replay the seeded serving trace (Poisson arrivals; sizes 32^2..128^2 with
+    probabilities .4/.3/.2/.1; 1, 8 or 16 coils; spiral of 2N samples per coil;
+    70% of requests reuse an earlier encoding; 50-2000 frames) through the
+    server, once with FP32 plans + refinement and once with plain FP64 plans.
+    Latency = completion - scheduled arrival (queueing included)."""
+    import threading
+    import torch
+    from paper_2410_06129_amd import pinv as P
+    from paper_2410_06129_amd import synth
+
+    trace = synth.serving_trace(rate_per_s=args.rate, duration_s=args.duration)
+    encs = {}
+    for r in trace:
+        if r.enc_id not in encs:
+            encs[r.enc_id] = synth.serving_encoding(r.n, r.coils, r.enc_id)
+    res = {"requests": len(trace), "rate_per_s": args.rate, "duration_s": args.duration}
+    for label, prec, cdt, refine in (("fp32_refined", P.FP32, torch.complex64, args.serve_refine),
+                                     ("fp64", P.FP64, torch.complex128, 0)):
+        ctx = P.pinv_context_create(0)
+        free, total = torch.cuda.mem_get_info()
+        srv = P.pinv_server_create(ctx, 0, hbm_budget_bytes=int(free * args.plan_frac),
+                                   max_group=16, max_inflight=2, max_builds=1)
+        data_cap = int(free * (0.85 - args.plan_frac))
+        live = {}            # tag -> (data, image, bytes)
+        lock = threading.Lock()
+        in_bytes = [0]
+        sched = {}
+        done = []
+        t0 = time.perf_counter()
+
+        def reap():
+            for c in P.pinv_server_poll(srv, 1024):
+                done.append((c, time.perf_counter() - t0))
+                with lock:
+                    d = live.pop(c["tag"])
+                    in_bytes[0] -= d[2]
+
+        flops_offered = 0.0
+        for r in trace:
+            enc = encs[r.enc_id]
+            N, M, F = enc.N, enc.M, r.frames
+            while time.perf_counter() - t0 < r.arrival_s:
+                reap()
+                time.sleep(0.001)
+            nbytes = (M + N) * F * (8 if prec == P.FP32 else 16)
+            while True:        # back-pressure on request buffers (counts as queueing)
+                reap()
+                with lock:
+                    if in_bytes[0] + nbytes <= data_cap or not live:
+                        break
+                time.sleep(0.002)
+            g = torch.Generator(device="cuda").manual_seed(r.rid)
+            d = torch.randn((F, M), dtype=cdt, device="cuda", generator=g)
+            x = torch.empty((F, N), dtype=cdt, device="cuda")
+            torch.cuda.current_stream().synchronize()
+            with lock:
+                live[r.rid] = (d, x, nbytes)
+                in_bytes[0] += nbytes
+            sched[r.rid] = r.arrival_s
+            P.pinv_server_submit(srv, enc, d, x, 1e-3, P.LAMBDA_REL_MEAN_DIAG, prec,
+                                 refine_steps=refine, tag=r.rid)
+            flops_offered += 8.0 * N * M * F + (12.0 * M * N * N + 4.0 * N ** 3 / 3 if r.new_build else 0)
+            log(f"[{label}] t={time.perf_counter() - t0:7.2f}s submitted {r.rid} n={r.n} C={r.coils} "
+                f"F={F} new={r.new_build}; done {len(done)}")
+        while len(done) < len(trace):
+            reap()
+            time.sleep(0.002)
+        t_end = time.perf_counter() - t0
+        st = P.pinv_server_stats_get(srv)
+        P.pinv_server_destroy(srv)
+        live.clear()
+        P.pinv_context_destroy(ctx)
+        torch.cuda.empty_cache()
+        lat = np.array([tw - sched[c["tag"]] for c, tw in done])
+        ok = all(c["status"] == P.OK for c, _ in done)
+        res[label] = {"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+                      "mean_s": float(lat.mean()), "throughput_req_per_s": len(trace) / t_end,
+                      "makespan_s": t_end, "all_ok": ok,
+                      "offered_tflops": flops_offered / args.duration / 1e12,
+                      "served_tflops": flops_offered / t_end / 1e12,
+                      "builds": st["builds"], "hits": st["hits"], "evictions": st["evictions"],
+                      "batches": st["batches"], "peak_plan_bytes": st["peak_used"],
+                      "invariant_violations": st["invariant_violations"]}
+        log(f"[{label}] {res[label]}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +160,14 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp64-reps", type=int, default=2)
+    ap.add_argument("--serving", action="store_true", help="run the serving-mix trace instead")
+    ap.add_argument("--rate", type=float, default=4.0)
+    ap.add_argument("--duration", type=float, default=120.0)
+    ap.add_argument("--serve-refine", type=int, default=1)
+    ap.add_argument("--plan-frac", type=float, default=0.6)
+    ap.add_argument("--build-only", type=int, nargs=2, metavar=("SIDE", "COILS"),
+                    help="build one plan for a SIDE^2 image with COILS coils (spiral 2N per coil)")
+    ap.add_argument("--precisions", default="fp32,fp64")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested); the multi-GPU "
@@ -84,6 +180,46 @@ def main():
     from paper_2410_06129_amd import synth
 
     torch.cuda.init()
+    if args.build_only:
+        side, coils = args.build_only
+        enc = synth.serving_encoding(side, coils, 0)
+        N, M = enc.N, enc.M
+        ctx = P.pinv_context_create(0)
+        out = {"metric": "R-build TFLOP/s (complex-equivalent 12MN^2 + 4N^3/3)", "unit": "TFLOP/s",
+               "config": {"workload": f"{side}x{side} image, {coils} coils, spiral {2 * N} per coil",
+                          "N": N, "M": M}, "builds": {}}
+        flops = 12.0 * M * N * N + 4.0 * N ** 3 / 3.0
+        for name in args.precisions.split(","):
+            prec = {"fp32": P.FP32, "fp64": P.FP64}[name]
+            times = []
+            for rep in range(max(1, args.steps)):
+                log(f"build {name} rep {rep} N={N} M={M}")
+                p = P.pinv_build(ctx, enc, 1e-3, P.LAMBDA_REL_MEAN_DIAG, prec, P.FLAG_UNCACHED)
+                P.pinv_plan_wait(p)
+                times.append(P.pinv_plan_info_get(p)["stage_ms"])
+                P.pinv_plan_release(p)
+            st = np.median(np.array(times), axis=0)
+            out["builds"][name] = {"stage_ms": {"gram": st[0], "chol_inv": st[1], "trmm_w": st[2],
+                                                "trmm_r": st[3]},
+                                   "build_ms": float(st.sum()),
+                                   "tflops": flops / (st.sum() * 1e-3) / 1e12,
+                                   "trmm_tflops": 8.0 * M * N * N / ((st[2] + st[3]) * 1e-3) / 1e12}
+            for k in list(out["builds"][name]["stage_ms"]):
+                out["builds"][name]["stage_ms"][k] = float(out["builds"][name]["stage_ms"][k])
+            log(json.dumps(out["builds"][name]))
+        out["value"] = out["builds"].get("fp32", out["builds"][next(iter(out["builds"]))])["tflops"]
+        P.pinv_context_destroy(ctx)
+        print(json.dumps(out), flush=True)
+        return
+    if args.serving:
+        res = serving(args)
+        out = {"metric": "serving p50/p99 latency (s) and throughput, FP32+refinement vs plain FP64",
+               "value": res["fp32_refined"]["p99_s"], "unit": "s", "n_gpus": 1,
+               "higher_is_better": False, "data": "synthetic", "dtype": "f32",
+               "config": {"workload": f"serving mix, Poisson {args.rate}/s over {args.duration} s"},
+               "serving": res}
+        print(json.dumps(out), flush=True)
+        return
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     w = synth.config2(F=args.frames)

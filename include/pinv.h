@@ -140,6 +140,14 @@ pinv_status pinv_build(pinv_context *ctx, const pinv_encoding *e, const pinv_bui
  * (OK, NOT_PD with the failing column in pinv_last_error, DEVICE). */
 pinv_status pinv_plan_wait(pinv_plan *p);
 
+/* Non-blocking: PINV_OK if the plan's build has finished successfully,
+ * PINV_ERR_BUSY while it is still running, otherwise its failure status. */
+pinv_status pinv_plan_query(pinv_plan *p);
+
+/* The cache key pinv_build would give this encoding and options (host only). */
+pinv_status pinv_encoding_key(const pinv_encoding *e, const pinv_build_opts *o, uint64_t *key,
+                              size_t *plan_bytes);
+
 /* image[f] = R data[f] for F frames (Eq. 3), enqueued on `hip_stream` behind
  * the plan's build.  data: device [F][M], image: device [F][N], dtype of the
  * plan (see conventions).  refine_steps (0..4) adds iterative refinement on
@@ -188,6 +196,69 @@ pinv_status pinv_cache_trim(pinv_context *ctx, size_t *freed);
 /* Budget accounting: bytes in use by plans and the budget. */
 pinv_status pinv_context_usage(const pinv_context *ctx, size_t *used, size_t *budget,
                                int32_t *cached_plans);
+
+/* ------------------------------------------------------------------------
+ * Serving: a continuous-batching request loop on one device.
+ *
+ * R depends on the encoding only (Sec. 4.5; Sec. 5), so the server keeps
+ * built plans in an LRU cache keyed by encoding (pinv_encoding_key), admits a
+ * new build only while its device footprint fits `hbm_budget_bytes`
+ * (evicting least-recently-used plans that no queued or running request
+ * holds), and packs the applies of every request whose plan is ready into
+ * grouped launches (pinv_apply_grouped).  Builds and applies run on two
+ * internal HIP streams, so requests arriving while others run overlap on the
+ * device.  Each request's result is the same as pinv_apply of its plan on its
+ * data alone.  A worker thread runs the scheduler; all calls are thread-safe.
+ * Times are seconds on a host monotonic clock from server creation.
+ * ------------------------------------------------------------------------ */
+typedef struct pinv_server pinv_server;
+
+typedef struct {
+  size_t hbm_budget_bytes;    /* device bytes for plans (resident and build workspace), > 0 */
+  int32_t max_group;          /* requests per grouped apply, 1..32 */
+  int32_t max_inflight;       /* grouped applies in flight, >= 1 */
+  int32_t max_builds;         /* concurrent builds, >= 1 */
+  int32_t reserved;           /* 0 */
+} pinv_server_opts;
+
+typedef struct {
+  const pinv_encoding *enc;   /* host; copied at submit */
+  pinv_build_opts opts;       /* build options of the request's plan */
+  const void *data;           /* device [F][M], caller-owned until completion */
+  void *image;                /* device [F][N], caller-owned until completion */
+  int64_t F;                  /* frames >= 0 */
+  int32_t refine_steps;       /* 0..4, as in pinv_apply */
+  int32_t reserved;           /* 0 */
+  uint64_t tag;               /* returned in the completion */
+} pinv_request;
+
+typedef struct {
+  uint64_t ticket, tag;
+  int32_t status;             /* pinv_status of the request */
+  int32_t built;              /* 1 if this request triggered its plan's build */
+  double t_arrival, t_dispatch, t_done;   /* submit, grouped-apply issue, completion seen */
+} pinv_completion;
+
+typedef struct {
+  uint64_t builds, build_failures, evictions, hits, batches, items, completed;
+  uint64_t invariant_violations;   /* budget exceeded or a held plan evicted: always 0 */
+  size_t used, peak_used, budget;
+  int32_t cached_plans, pending, running;
+} pinv_server_stats;
+
+/* Errors: INVALID, DEVICE. */
+pinv_status pinv_server_create(pinv_context *ctx, int device, const pinv_server_opts *o,
+                               pinv_server **out);
+/* Queue one request; *ticket identifies it.  Errors: INVALID (as pinv_build). */
+pinv_status pinv_server_submit(pinv_server *s, const pinv_request *r, uint64_t *ticket);
+/* Take up to `max` completions (in completion order); *n = how many. */
+pinv_status pinv_server_poll(pinv_server *s, pinv_completion *out, int32_t max, int32_t *n);
+/* Wait until no request is queued or running (timeout_s <= 0: no limit);
+ * BUSY on timeout. */
+pinv_status pinv_server_drain(pinv_server *s, double timeout_s);
+pinv_status pinv_server_stats_get(pinv_server *s, pinv_server_stats *out);
+/* Stop the worker, wait for device work, release every plan the server holds. */
+pinv_status pinv_server_destroy(pinv_server *s);
 
 const char *pinv_status_string(pinv_status s);
 const char *pinv_last_error(void);   /* thread-local detail of the last failure */

@@ -9,7 +9,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpinv.so")
-SOURCES = ["pinv_kernels.hip", "pinv_api.hip"]
+SOURCES = ["pinv_kernels.hip", "pinv_api.hip", "pinv_serve.hip"]
+SIM_LIB = os.path.join(HERE, "libpinv_schedsim.so")
 HEADERS = ["pinv_device.h", "pinv_internal.h"]
 
 
@@ -52,12 +53,28 @@ def build(verbose: bool = False, jobs: int = 2) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout.decode(errors="replace"))
     os.replace(tmp, LIB)
+    build_sim(verbose)
     for o in objs:
         try:
             os.remove(o)
         except OSError:
             pass
     return LIB
+
+
+def build_sim(verbose: bool = False) -> str:
+    """The serving scheduler on a simulated device (host C++ only, for CPU tests)."""
+    cxx = shutil.which("g++") or "g++"
+    tmp = SIM_LIB + ".tmp"
+    cmd = [cxx, "-O2", "-std=c++17", "-fPIC", "-shared", "-Wall",
+           os.path.join(CSRC, "sched_sim.cpp"), "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
+    if r.returncode != 0:
+        raise RuntimeError("g++ failed:\n" + r.stdout.decode(errors="replace"))
+    os.replace(tmp, SIM_LIB)
+    return SIM_LIB
 
 
 if __name__ == "__main__":

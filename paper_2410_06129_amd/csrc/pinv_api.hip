@@ -341,11 +341,11 @@ pinv_status pinv_context_destroy(pinv_context* c) {
   return PINV_OK;
 }
 
-pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build_opts* o,
-                       void* stream, pinv_plan** out) {
-  if (!c || !o || !out) return fail(PINV_ERR_INVALID, "NULL argument");
-  Dims d;
-  pinv_status st = validate(e, &d);
+// Validate a build request and derive the absolute shift and the cache key.
+static pinv_status check_build(const pinv_encoding* e, const pinv_build_opts* o, Dims* d,
+                               double* lam_out, uint64_t* key_out) {
+  if (!o) return fail(PINV_ERR_INVALID, "NULL options");
+  pinv_status st = validate(e, d);
   if (st != PINV_OK) return st;
   if (o->prec != PINV_FP64 && o->prec != PINV_FP32 && o->prec != PINV_BF16X3)
     return fail(PINV_ERR_INVALID, "unknown precision");
@@ -357,19 +357,44 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
     // trace(E^H E) = K * S * sum_v sum_c |C_c(v)|^2 since every phase factor has modulus 1
     double cp = 0.0;
     if (e->coil) {
-      for (size_t i = 0; i < (size_t)d.C * d.V; ++i)
+      for (size_t i = 0; i < (size_t)d->C * d->V; ++i)
         cp += e->coil[2 * i] * e->coil[2 * i] + e->coil[2 * i + 1] * e->coil[2 * i + 1];
     } else {
-      cp = (double)d.V;
+      cp = (double)d->V;
     }
-    lam = o->lambda * (double)d.K * d.S * cp / (double)d.N;
+    lam = o->lambda * (double)d->K * d->S * cp / (double)d->N;
   } else if (o->lambda_mode != PINV_LAMBDA_ABS) {
     return fail(PINV_ERR_INVALID, "unknown lambda_mode");
   }
-  if (lam == 0.0 && d.M < d.N)
+  if (lam == 0.0 && d->M < d->N)
     return fail(PINV_ERR_INVALID, "lambda = 0 needs M >= N (full column rank)");
   const bool gram_full = (o->flags & PINV_FLAG_GRAM_FULL) != 0;
-  const uint64_t key = plan_key(e, d, lam, o->prec) ^ (gram_full ? 0xc2b2ae3d27d4eb4full : 0);
+  *lam_out = lam;
+  *key_out = plan_key(e, *d, lam, o->prec) ^ (gram_full ? 0xc2b2ae3d27d4eb4full : 0);
+  return PINV_OK;
+}
+
+pinv_status pinv_encoding_key(const pinv_encoding* e, const pinv_build_opts* o, uint64_t* key,
+                              size_t* plan_bytes) {
+  Dims d;
+  double lam;
+  uint64_t k;
+  pinv_status st = check_build(e, o, &d, &lam, &k);
+  if (st != PINV_OK) return st;
+  if (key) *key = k;
+  if (plan_bytes) *plan_bytes = plan_footprint(d, o->prec);
+  return PINV_OK;
+}
+
+pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build_opts* o,
+                       void* stream, pinv_plan** out) {
+  if (!c || !o || !out) return fail(PINV_ERR_INVALID, "NULL argument");
+  Dims d;
+  double lam;
+  uint64_t key;
+  pinv_status st = check_build(e, o, &d, &lam, &key);
+  if (st != PINV_OK) return st;
+  const bool gram_full = (o->flags & PINV_FLAG_GRAM_FULL) != 0;
   hipStream_t s = (hipStream_t)stream;
   HIPCHK(hipSetDevice(c->device));
 
@@ -521,6 +546,15 @@ pinv_status pinv_plan_wait(pinv_plan* p) {
     return fail(PINV_ERR_NOT_PD, "Cholesky pivot <= 0 or NaN at column " +
                                      std::to_string(p->info_host - 1));
   return p->status;
+}
+
+pinv_status pinv_plan_query(pinv_plan* p) {
+  if (!p) return fail(PINV_ERR_INVALID, "plan is NULL");
+  if (p->waited) return p->status == PINV_OK ? PINV_OK : pinv_plan_wait(p);
+  hipError_t q = hipEventQuery(p->ev[4]);
+  if (q == hipErrorNotReady) return PINV_ERR_BUSY;
+  if (q != hipSuccess) return fail(PINV_ERR_DEVICE, std::string("hipEventQuery: ") + hipGetErrorString(q));
+  return pinv_plan_wait(p);
 }
 
 // Iterative refinement on the normal equations (Eq. 6) for one item:

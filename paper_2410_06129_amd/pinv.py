@@ -54,6 +54,35 @@ class pinv_apply_item(ctypes.Structure):
                 ("F", ctypes.c_int64)]
 
 
+class pinv_server_opts(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_group", ctypes.c_int32),
+                ("max_inflight", ctypes.c_int32), ("max_builds", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class pinv_request(ctypes.Structure):
+    _fields_ = [("enc", ctypes.POINTER(pinv_encoding)), ("opts", pinv_build_opts),
+                ("data", ctypes.c_void_p), ("image", ctypes.c_void_p), ("F", ctypes.c_int64),
+                ("refine_steps", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("tag", ctypes.c_uint64)]
+
+
+class pinv_completion(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("tag", ctypes.c_uint64), ("status", ctypes.c_int32),
+                ("built", ctypes.c_int32), ("t_arrival", ctypes.c_double),
+                ("t_dispatch", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class pinv_server_stats(ctypes.Structure):
+    _fields_ = [("builds", ctypes.c_uint64), ("build_failures", ctypes.c_uint64),
+                ("evictions", ctypes.c_uint64), ("hits", ctypes.c_uint64),
+                ("batches", ctypes.c_uint64), ("items", ctypes.c_uint64),
+                ("completed", ctypes.c_uint64), ("invariant_violations", ctypes.c_uint64),
+                ("used", ctypes.c_size_t), ("peak_used", ctypes.c_size_t),
+                ("budget", ctypes.c_size_t), ("cached_plans", ctypes.c_int32),
+                ("pending", ctypes.c_int32), ("running", ctypes.c_int32)]
+
+
 _vp = ctypes.c_void_p
 _sigs = {
     "pinv_context_create": [ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(_vp)],
@@ -71,6 +100,16 @@ _sigs = {
     "pinv_cache_trim": [_vp, ctypes.POINTER(ctypes.c_size_t)],
     "pinv_context_usage": [_vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
                            ctypes.POINTER(ctypes.c_int32)],
+    "pinv_plan_query": [_vp],
+    "pinv_encoding_key": [ctypes.POINTER(pinv_encoding), ctypes.POINTER(pinv_build_opts),
+                          ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_size_t)],
+    "pinv_server_create": [_vp, ctypes.c_int, ctypes.POINTER(pinv_server_opts), ctypes.POINTER(_vp)],
+    "pinv_server_submit": [_vp, ctypes.POINTER(pinv_request), ctypes.POINTER(ctypes.c_uint64)],
+    "pinv_server_poll": [_vp, ctypes.POINTER(pinv_completion), ctypes.c_int32,
+                         ctypes.POINTER(ctypes.c_int32)],
+    "pinv_server_drain": [_vp, ctypes.c_double],
+    "pinv_server_stats_get": [_vp, ctypes.POINTER(pinv_server_stats)],
+    "pinv_server_destroy": [_vp],
 }
 for _name, _args in _sigs.items():
     _f = getattr(_lib, _name)
@@ -223,3 +262,70 @@ def pinv_status_string(s: int) -> str:
 
 def pinv_last_error() -> str:
     return _lib.pinv_last_error().decode(errors="replace")
+
+
+def pinv_plan_query(plan: int) -> int:
+    """Non-blocking build state: OK, ERR_BUSY, or the failure status."""
+    return _lib.pinv_plan_query(plan)
+
+
+def pinv_encoding_key(enc, lam: float, lambda_mode: int = LAMBDA_REL_MEAN_DIAG, prec: int = FP32,
+                      flags: int = 0):
+    s, keep = _encoding_struct(enc)
+    o = pinv_build_opts(lambda_=lam, lambda_mode=lambda_mode, prec=prec, flags=flags, reserved=0)
+    k, b = ctypes.c_uint64(), ctypes.c_size_t()
+    st = _lib.pinv_encoding_key(ctypes.byref(s), ctypes.byref(o), ctypes.byref(k), ctypes.byref(b))
+    del keep
+    _check(st, "pinv_encoding_key")
+    return k.value, b.value
+
+
+# ----------------------------------------------------------------------------
+# serving
+# ----------------------------------------------------------------------------
+
+def pinv_server_create(ctx: int, device: int = 0, hbm_budget_bytes: int = 0, max_group: int = 32,
+                       max_inflight: int = 2, max_builds: int = 1) -> int:
+    o = pinv_server_opts(hbm_budget_bytes=hbm_budget_bytes, max_group=max_group,
+                         max_inflight=max_inflight, max_builds=max_builds, reserved=0)
+    out = _vp()
+    _check(_lib.pinv_server_create(ctx, device, ctypes.byref(o), ctypes.byref(out)), "pinv_server_create")
+    return out.value
+
+
+def pinv_server_submit(server: int, enc, data, image, lam: float = 1e-3,
+                       lambda_mode: int = LAMBDA_REL_MEAN_DIAG, prec: int = FP32, flags: int = 0,
+                       refine_steps: int = 0, tag: int = 0) -> int:
+    """data/image: device tensors [F, M] / [F, N], kept alive by the caller until completion."""
+    s, keep = _encoding_struct(enc)
+    o = pinv_build_opts(lambda_=lam, lambda_mode=lambda_mode, prec=prec, flags=flags, reserved=0)
+    r = pinv_request(enc=ctypes.pointer(s), opts=o, data=data.data_ptr(), image=image.data_ptr(),
+                     F=data.shape[0], refine_steps=refine_steps, reserved=0, tag=tag)
+    t = ctypes.c_uint64()
+    st = _lib.pinv_server_submit(server, ctypes.byref(r), ctypes.byref(t))
+    del keep
+    _check(st, "pinv_server_submit")
+    return t.value
+
+
+def pinv_server_poll(server: int, max_n: int = 256):
+    arr = (pinv_completion * max_n)()
+    n = ctypes.c_int32()
+    _check(_lib.pinv_server_poll(server, arr, max_n, ctypes.byref(n)), "pinv_server_poll")
+    return [dict(ticket=c.ticket, tag=c.tag, status=c.status, built=bool(c.built),
+                 t_arrival=c.t_arrival, t_dispatch=c.t_dispatch, t_done=c.t_done)
+            for c in arr[:n.value]]
+
+
+def pinv_server_drain(server: int, timeout_s: float = 0.0) -> int:
+    return _lib.pinv_server_drain(server, timeout_s)
+
+
+def pinv_server_stats_get(server: int) -> dict:
+    s = pinv_server_stats()
+    _check(_lib.pinv_server_stats_get(server, ctypes.byref(s)), "pinv_server_stats_get")
+    return {f: getattr(s, f) for f, _ in pinv_server_stats._fields_}
+
+
+def pinv_server_destroy(server: int) -> None:
+    _check(_lib.pinv_server_destroy(server), "pinv_server_destroy")

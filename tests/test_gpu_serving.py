@@ -1,0 +1,99 @@
+"""Serving on the GPU through the C-ABI server: every request completes, plans
+are reused by encoding, and each request's image equals what building its
+plan and applying it alone gives (the grouped launches run each item's tiles
+exactly as a single apply does, so equality is bitwise)."""
+import numpy as np
+import pytest
+
+from paper_2410_06129_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_2410_06129_amd import pinv
+    return pinv
+
+
+def encodings():
+    out = []
+    for j, (nx, ny, C, K) in enumerate([(16, 16, 1, 600), (24, 20, 3, 700), (20, 20, 2, 900)]):
+        w = synth.small_case(seed=300 + j, nx=nx, ny=ny, C=C, K=K, F=1)
+        out.append(w.enc)
+    return out
+
+
+@pytest.mark.parametrize("prec,refine", [("fp32", 1), ("fp64", 0)])
+def test_mix_equals_alone(P, prec, refine):
+    p = P.FP32 if prec == "fp32" else P.FP64
+    cdt = torch.complex64 if prec == "fp32" else torch.complex128
+    encs = encodings()
+    rng = np.random.default_rng(11)
+    ctx = P.pinv_context_create(0)
+    srv = P.pinv_server_create(ctx, 0, hbm_budget_bytes=8 << 30, max_group=8, max_inflight=2,
+                               max_builds=1)
+    reqs = []
+    try:
+        for t in range(14):
+            e = int(rng.integers(0, len(encs)))
+            F = int(rng.integers(1, 40))
+            g = torch.Generator(device="cuda").manual_seed(1000 + t)
+            d = torch.randn((F, encs[e].M), dtype=cdt, device="cuda", generator=g)
+            x = torch.zeros((F, encs[e].N), dtype=cdt, device="cuda")
+            P.pinv_server_submit(srv, encs[e], d, x, 1e-3, P.LAMBDA_REL_MEAN_DIAG, p,
+                                 refine_steps=refine, tag=t)
+            reqs.append((e, d, x))
+        assert P.pinv_server_drain(srv, 120.0) == P.OK
+        done = P.pinv_server_poll(srv, 64)
+        stats = P.pinv_server_stats_get(srv)
+    finally:
+        P.pinv_server_destroy(srv)
+    assert sorted(c["tag"] for c in done) == list(range(14))
+    assert all(c["status"] == P.OK for c in done)
+    assert all(c["t_arrival"] <= c["t_dispatch"] <= c["t_done"] for c in done)
+    used = {e for e, _, _ in reqs}
+    assert stats["builds"] == len(used)
+    assert stats["hits"] == 14 - len(used)
+    assert stats["invariant_violations"] == 0 and stats["peak_used"] <= stats["budget"]
+    # alone: a fresh plan per encoding, one apply per request
+    plans = {}
+    try:
+        for e in used:
+            plans[e] = P.pinv_build(ctx, encs[e], 1e-3, P.LAMBDA_REL_MEAN_DIAG, p, P.FLAG_UNCACHED)
+            P.pinv_plan_wait(plans[e])
+        for e, d, x in reqs:
+            y = torch.zeros_like(x)
+            P.pinv_apply(ctx, plans[e], d, y, refine_steps=refine)
+            torch.cuda.synchronize()
+            assert torch.equal(x, y)
+    finally:
+        for q in plans.values():
+            P.pinv_plan_release(q)
+        P.pinv_context_destroy(ctx)
+
+
+def test_budget_forces_eviction(P):
+    encs = encodings()
+    ctx = P.pinv_context_create(0)
+    sizes = [P.pinv_encoding_key(e, 1e-3, prec=P.FP32)[1] for e in encs]
+    # room for the largest build but not for two plans' footprints together
+    budget = max(sizes) + min(sizes) // 2
+    srv = P.pinv_server_create(ctx, 0, hbm_budget_bytes=budget, max_group=4)
+    keep = []
+    try:
+        for t, e in enumerate([0, 1, 2, 0, 1, 2]):
+            d = torch.ones((2, encs[e].M), dtype=torch.complex64, device="cuda")
+            x = torch.zeros((2, encs[e].N), dtype=torch.complex64, device="cuda")
+            keep.append((d, x))
+            P.pinv_server_submit(srv, encs[e], d, x, 1e-3, prec=P.FP32, tag=t)
+        assert P.pinv_server_drain(srv, 120.0) == P.OK
+        done = P.pinv_server_poll(srv, 16)
+        st = P.pinv_server_stats_get(srv)
+    finally:
+        P.pinv_server_destroy(srv)
+        P.pinv_context_destroy(ctx)
+    assert len(done) == 6 and all(c["status"] == P.OK for c in done)
+    assert st["evictions"] >= 1 and st["peak_used"] <= budget
+    assert st["invariant_violations"] == 0
