@@ -139,9 +139,13 @@ def serving(args) -> dict:
         torch.cuda.empty_cache()
         lat = np.array([tw - sched[c["tag"]] for c, tw in done])
         ok = all(c["status"] == P.OK for c, _ in done)
+        fails = {}
+        for c, _ in done:
+            if c["status"] != P.OK:
+                fails[P.pinv_status_string(c["status"])] = fails.get(P.pinv_status_string(c["status"]), 0) + 1
         res[label] = {"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
                       "mean_s": float(lat.mean()), "throughput_req_per_s": len(trace) / t_end,
-                      "makespan_s": t_end, "all_ok": ok,
+                      "makespan_s": t_end, "all_ok": ok, "failures": fails,
                       "offered_tflops": flops_offered / args.duration / 1e12,
                       "served_tflops": flops_offered / t_end / 1e12,
                       "builds": st["builds"], "hits": st["hits"], "evictions": st["evictions"],

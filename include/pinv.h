@@ -190,6 +190,10 @@ pinv_status pinv_plan_copy_buffer(const pinv_plan *p, int32_t which, void *dst, 
  * cache frees the plan once its enqueued work has completed. */
 pinv_status pinv_plan_release(pinv_plan *p);
 
+/* Release device memory held by the stream-ordered allocator's pool after
+ * completed work (build workspace, refinement scratch) back to the device. */
+pinv_status pinv_context_trim(pinv_context *ctx);
+
 /* Evict every cached plan no caller holds; returns the bytes freed in *freed. */
 pinv_status pinv_cache_trim(pinv_context *ctx, size_t *freed);
 

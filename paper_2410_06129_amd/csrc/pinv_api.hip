@@ -531,11 +531,25 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
   return PINV_OK;
 }
 
+// Return memory that stream-ordered frees (build workspace, refinement
+// scratch) left in the device's default pool, so later allocations can use it.
+static void trim_pool(int device) {
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) (void)hipMemPoolTrimTo(pool, 0);
+}
+
+extern "C" pinv_status pinv_context_trim(pinv_context* c) {
+  if (!c) return fail(PINV_ERR_INVALID, "context is NULL");
+  trim_pool(c->device);
+  return PINV_OK;
+}
+
 pinv_status pinv_plan_wait(pinv_plan* p) {
   if (!p) return fail(PINV_ERR_INVALID, "plan is NULL");
   if (!p->waited) {
     HIPCHK(hipSetDevice(p->ctx->device));
     HIPCHK(hipEventSynchronize(p->ev[4]));
+    trim_pool(p->ctx->device);
     HIPCHK(hipMemcpy(&p->info_host, p->info, sizeof(int), hipMemcpyDeviceToHost));
     for (int i = 0; i < 4; ++i) HIPCHK(hipEventElapsedTime(&p->stage_ms[i], p->ev[i], p->ev[i + 1]));
     p->status = p->info_host ? PINV_ERR_NOT_PD : PINV_OK;

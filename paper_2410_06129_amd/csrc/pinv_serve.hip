@@ -4,6 +4,7 @@
 // are cached.  A worker thread ticks the scheduler; callers submit requests
 // and poll completions from any thread.
 #include <hip/hip_runtime.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <atomic>
@@ -69,9 +70,16 @@ struct HipBackend {
   int start_build(const Request& r, pinv_plan** h) {
     pinv_build_opts o = r.opts;
     o.flags |= PINV_FLAG_UNCACHED;
-    return pinv_build(ctx, &r.enc->e, &o, build_stream, h);
+    const pinv_status s = pinv_build(ctx, &r.enc->e, &o, build_stream, h);
+    if (s != PINV_OK) fprintf(stderr, "pinv server: build failed: %s\n", pinv_last_error());
+    return s;
   }
-  int build_state(pinv_plan* h) { return pinv_plan_query(h); }
+  int build_state(pinv_plan* h) {
+    const pinv_status s = pinv_plan_query(h);
+    if (s != PINV_OK && s != PINV_ERR_BUSY)
+      fprintf(stderr, "pinv server: build failed: %s\n", pinv_last_error());
+    return s;
+  }
   size_t resident_bytes(pinv_plan* h) {
     pinv_plan_info i;
     return pinv_plan_info_get(h, &i) == PINV_OK ? i.device_bytes : 0;
@@ -88,7 +96,10 @@ struct HipBackend {
         ++i;
       }
       const pinv_status s = pinv_apply_grouped(ctx, (int32_t)v.size(), v.data(), refine, apply_stream);
-      if (s != PINV_OK) return s;
+      if (s != PINV_OK) {
+        fprintf(stderr, "pinv server: apply failed: %s\n", pinv_last_error());
+        return s;
+      }
     }
     if (hipEventCreateWithFlags(&b->ev, hipEventDisableTiming) != hipSuccess) return PINV_ERR_DEVICE;
     if (hipEventRecord(b->ev, apply_stream) != hipSuccess) return PINV_ERR_DEVICE;
@@ -99,6 +110,7 @@ struct HipBackend {
     if (q == hipErrorNotReady) return false;
     (void)hipEventDestroy(b.ev);
     b.ev = nullptr;
+    (void)pinv_context_trim(ctx);   // refinement scratch back to the device
     return true;
   }
   void release(pinv_plan* h) { pinv_plan_release(h); }

@@ -101,6 +101,7 @@ _sigs = {
     "pinv_context_usage": [_vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
                            ctypes.POINTER(ctypes.c_int32)],
     "pinv_plan_query": [_vp],
+    "pinv_context_trim": [_vp],
     "pinv_encoding_key": [ctypes.POINTER(pinv_encoding), ctypes.POINTER(pinv_build_opts),
                           ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_size_t)],
     "pinv_server_create": [_vp, ctypes.c_int, ctypes.POINTER(pinv_server_opts), ctypes.POINTER(_vp)],
@@ -267,6 +268,10 @@ def pinv_last_error() -> str:
 def pinv_plan_query(plan: int) -> int:
     """Non-blocking build state: OK, ERR_BUSY, or the failure status."""
     return _lib.pinv_plan_query(plan)
+
+
+def pinv_context_trim(ctx: int) -> None:
+    _check(_lib.pinv_context_trim(ctx), "pinv_context_trim")
 
 
 def pinv_encoding_key(enc, lam: float, lambda_mode: int = LAMBDA_REL_MEAN_DIAG, prec: int = FP32,

@@ -174,6 +174,18 @@ def test_p5_closed_form_diagonal(kw):
     assert np.linalg.eigvalsh(G).min() > -1e-10 * np.max(want)
 
 
+def test_lambda_definition_on_cartesian():
+    """rel * trace(E^H E)/N: with G = N I (fully sampled Cartesian) the shift is rel * N exactly,
+    and with C coils of known power it is rel * K * sum_c |C_c|^2 averaged over voxels."""
+    n = 6
+    b = oracle.Build(cartesian_enc(n), rel=0.25)
+    assert b.lam == pytest.approx(0.25 * n * n, rel=1e-14)
+    enc = tiny_enc(seed=24, C=3)
+    G = oracle.gram(enc)
+    want = 1e-3 * enc.K * np.sum(np.abs(enc.coil) ** 2) / enc.V
+    assert oracle.lambda_abs(G, 1e-3) == pytest.approx(want, rel=1e-12)
+
+
 # --- P6: coil-sum identity (Eq. 11) --------------------------------------------
 
 def test_p6_coil_sum_identity():
