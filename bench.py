@@ -63,6 +63,33 @@ def cpu_baseline(w) -> dict:
                       f"{flops:.3g} complex-equivalent flops in {dt:.2f} s"}
 
 
+def kernel_source_hash() -> str:
+    """Hash of the device sources; counter readings are valid only for this hash."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("pinv_device.h", "pinv_kernels.hip"):
+        with open(os.path.join(ROOT, "paper_2410_06129_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from profiles/pmc_traffic.json (FETCH_SIZE
+    and WRITE_SIZE counter runs, scaled by a plain copy of known size), or None
+    if no reading exists for the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_hash") != kernel_source_hash() or kernel not in rec.get("kernels", {}):
+        return None
+    k = rec["kernels"][kernel]
+    return {"bytes_per_launch": k["fetch_bytes"] + k["write_bytes"], "fetch_bytes": k["fetch_bytes"],
+            "write_bytes": k["write_bytes"], "algorithmic_bytes": k.get("algorithmic_bytes"),
+            "source": "profiles/pmc_traffic.json"}
+
+
 def serving(args) -> dict:
     """Replay the seeded serving trace (Poisson arrivals; sizes 32^2..128^2 with
     probabilities .4/.3/.2/.1; 1, 8 or 16 coils; spiral of 2N samples per coil;
@@ -80,8 +107,12 @@ def serving(args) -> dict:
         if r.enc_id not in encs:
             encs[r.enc_id] = synth.serving_encoding(r.n, r.coils, r.enc_id)
     res = {"requests": len(trace), "rate_per_s": args.rate, "duration_s": args.duration}
-    for label, prec, cdt, refine in (("fp32_refined", P.FP32, torch.complex64, args.serve_refine),
-                                     ("fp64", P.FP64, torch.complex128, 0)):
+    variants = {"fp32_refined": (P.FP32, torch.complex64, args.serve_refine),
+                "fp64": (P.FP64, torch.complex128, 0),
+                "fp32_unrefined": (P.FP32, torch.complex64, 0),
+                "bf16x3_refined": (P.BF16X3, torch.complex64, args.serve_refine)}
+    for label in args.serve_variants.split(","):
+        prec, cdt, refine = variants[label]
         ctx = P.pinv_context_create(0)
         free, total = torch.cuda.mem_get_info()
         srv = P.pinv_server_create(ctx, 0, hbm_budget_bytes=int(free * args.plan_frac),
@@ -137,14 +168,15 @@ def serving(args) -> dict:
         live.clear()
         P.pinv_context_destroy(ctx)
         torch.cuda.empty_cache()
-        lat = np.array([tw - sched[c["tag"]] for c, tw in done])
+        lat = np.array([tw - sched[c["tag"]] for c, tw in done if c["status"] == P.OK])
         ok = all(c["status"] == P.OK for c, _ in done)
         fails = {}
         for c, _ in done:
             if c["status"] != P.OK:
                 fails[P.pinv_status_string(c["status"])] = fails.get(P.pinv_status_string(c["status"]), 0) + 1
         res[label] = {"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
-                      "mean_s": float(lat.mean()), "throughput_req_per_s": len(trace) / t_end,
+                      "mean_s": float(lat.mean()), "completed_ok": int(len(lat)),
+                      "refine_steps": refine, "throughput_req_per_s": len(lat) / t_end,
                       "makespan_s": t_end, "all_ok": ok, "failures": fails,
                       "offered_tflops": flops_offered / args.duration / 1e12,
                       "served_tflops": flops_offered / t_end / 1e12,
@@ -153,6 +185,69 @@ def serving(args) -> dict:
                       "invariant_violations": st["invariant_violations"]}
         log(f"[{label}] {res[label]}")
     return res
+
+
+def precision_study(args) -> dict:
+    """96x96, 16 coils, 8192-sample spiral per coil (M=131072), 500 frames:
+    relative image error of FP32 and BF16-split plans against the plain FP64
+    GPU path (itself checked against the oracle) for lambda in
+    {1e-4, 1e-3, 1e-2} * mean diag and 0-2 refinement steps, with kappa(G_l)
+    from power iteration on the plan's FP64 Gram."""
+    import torch
+    from paper_2410_06129_amd import pinv as P
+    from paper_2410_06129_amd import synth
+
+    w = synth.config3(F=args.frames_study)
+    enc = w.enc
+    N, M, F = enc.N, enc.M, w.images.shape[0]
+    dev = torch.device("cuda:0")
+    ctx = P.pinv_context_create(0)
+    out = {"workload": w.name, "N": N, "M": M, "F": F, "by_lambda": {}}
+    x_true = torch.from_numpy(w.images).to(dev)
+    d64 = None
+    for rel in (1e-4, 1e-3, 1e-2):
+        p64 = P.pinv_build(ctx, enc, rel, P.LAMBDA_REL_MEAN_DIAG, P.FP64, P.FLAG_UNCACHED)
+        P.pinv_plan_wait(p64)
+        if d64 is None:
+            d64 = torch.empty((F, M), dtype=torch.complex128, device=dev)
+            P.pinv_forward(ctx, p64, x_true, d64)
+            noise = torch.from_numpy(w.noise).to(dev)
+            d64 += torch.sqrt(torch.mean(torch.abs(d64) ** 2)) * 10 ** (-w.snr_db / 20) * noise
+            del noise
+            d32 = d64.to(torch.complex64)
+        info = P.pinv_plan_info_get(p64)
+        G = torch.empty((N, N), dtype=torch.complex128, device=dev)
+        P.pinv_plan_copy_buffer(p64, P.BUF_GRAM, G)
+        v = torch.randn((N, 1), dtype=torch.complex128, device=dev)
+        for _ in range(30):
+            v = G @ v
+            v = v / torch.linalg.vector_norm(v)
+        smax = float(torch.real(torch.vdot(v[:, 0], (G @ v)[:, 0])))
+        del G
+        kappa = (smax + info["lambda_abs"]) / info["lambda_abs"]
+        x64 = torch.empty((F, N), dtype=torch.complex128, device=dev)
+        P.pinv_apply(ctx, p64, d64, x64)
+        torch.cuda.synchronize()
+        ref_norm = torch.linalg.vector_norm(x64, dim=1)
+        entry = {"kappa": kappa, "fp64_build_ms": sum(info["stage_ms"])}
+        for name, prec in (("fp32", P.FP32), ("bf16x3", P.BF16X3)):
+            p = P.pinv_build(ctx, enc, rel, P.LAMBDA_REL_MEAN_DIAG, prec, P.FLAG_UNCACHED)
+            P.pinv_plan_wait(p)
+            entry[name + "_build_ms"] = sum(P.pinv_plan_info_get(p)["stage_ms"])
+            x = torch.empty((F, N), dtype=torch.complex64, device=dev)
+            errs = {}
+            for r in range(3):
+                P.pinv_apply(ctx, p, d32, x, refine_steps=r)
+                torch.cuda.synchronize()
+                e = torch.linalg.vector_norm(x.to(torch.complex128) - x64, dim=1) / ref_norm
+                errs[str(r)] = {"max": float(e.max()), "median": float(e.median())}
+            entry[name] = errs
+            P.pinv_plan_release(p)
+            log(f"lambda {rel:g} {name}: {errs}")
+        P.pinv_plan_release(p64)
+        out["by_lambda"][f"{rel:g}"] = entry
+    P.pinv_context_destroy(ctx)
+    return out
 
 
 def main():
@@ -169,9 +264,14 @@ def main():
     ap.add_argument("--duration", type=float, default=120.0)
     ap.add_argument("--serve-refine", type=int, default=1)
     ap.add_argument("--plan-frac", type=float, default=0.6)
+    ap.add_argument("--serve-variants", default="fp32_refined,fp64,fp32_unrefined,bf16x3_refined")
+    ap.add_argument("--pmc-calibrate", action="store_true",
+                    help="run a plain 2 GiB device copy first (reference for HBM byte counters)")
     ap.add_argument("--build-only", type=int, nargs=2, metavar=("SIDE", "COILS"),
                     help="build one plan for a SIDE^2 image with COILS coils (spiral 2N per coil)")
     ap.add_argument("--precisions", default="fp32,fp64")
+    ap.add_argument("--precision-study", action="store_true")
+    ap.add_argument("--frames-study", type=int, default=500)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested); the multi-GPU "
@@ -184,6 +284,12 @@ def main():
     from paper_2410_06129_amd import synth
 
     torch.cuda.init()
+    if args.precision_study:
+        res = precision_study(args)
+        print(json.dumps({"metric": "relative image error vs plain FP64 GPU path", "unit": "rel",
+                          "higher_is_better": False, "data": "synthetic",
+                          "config": {"workload": res["workload"]}, "study": res}), flush=True)
+        return
     if args.build_only:
         side, coils = args.build_only
         enc = synth.serving_encoding(side, coils, 0)
@@ -194,7 +300,7 @@ def main():
                           "N": N, "M": M}, "builds": {}}
         flops = 12.0 * M * N * N + 4.0 * N ** 3 / 3.0
         for name in args.precisions.split(","):
-            prec = {"fp32": P.FP32, "fp64": P.FP64}[name]
+            prec = {"fp32": P.FP32, "fp64": P.FP64, "bf16x3": P.BF16X3}[name]
             times = []
             for rep in range(max(1, args.steps)):
                 log(f"build {name} rep {rep} N={N} M={M}")
@@ -226,6 +332,12 @@ def main():
         return
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
+    if args.pmc_calibrate:
+        src = torch.ones((1 << 29,), dtype=torch.float32, device=dev)     # 2 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = synth.config2(F=args.frames)
     enc = w.enc
     N, M, F = enc.N, enc.M, w.images.shape[0]
@@ -315,6 +427,24 @@ def main():
     build_ms = float(st_mean.sum())
     log(f"stage ms (gram, chol+inv, W, R): {np.round(st_mean, 3)}; step {ms_step:.2f} ms")
 
+    # --- BF16-split plan on the same workload ---
+    b3 = P.pinv_build(ctx, enc, w.rel_lambda, P.LAMBDA_REL_MEAN_DIAG, P.BF16X3, P.FLAG_UNCACHED)
+    P.pinv_plan_wait(b3)
+    b3_stage = P.pinv_plan_info_get(b3)["stage_ms"]
+    b3_err = {}
+    for r in range(0, 3):
+        P.pinv_apply(ctx, b3, d32, x32, refine_steps=r)
+        torch.cuda.synchronize()
+        b3_err[str(r)] = rel_err(x32)[0]
+    b3_apply = []
+    for _ in range(3):
+        e0.record(stream)
+        P.pinv_apply(ctx, b3, d32, x32, refine_steps=0)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        b3_apply.append(e0.elapsed_time(e1))
+    P.pinv_plan_release(b3)
+
     # --- plain FP64 GPU comparator ---
     f64_build, f64_apply = [], []
     for _ in range(args.fp64_reps):
@@ -340,7 +470,7 @@ def main():
     kms, kfl = kern[name]
     achieved = kfl / (kms * 1e-3) / 1e12
     roof = {"kernel": name, "bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA,
-            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA, "traffic": None,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA, "traffic": measured_traffic(name),
             "per_kernel_tflops": {k: v[1] / (v[0] * 1e-3) / 1e12 for k, v in kern.items()}}
 
     out = {
@@ -363,6 +493,12 @@ def main():
                      "apply_frames_per_s": F / (f64_apply_ms * 1e-3)},
         "roofline": roof,
     }
+    out["bf16x3"] = {"build_ms": float(sum(b3_stage)),
+                     "stage_ms": {"gram": b3_stage[0], "chol_inv": b3_stage[1], "trmm_w": b3_stage[2],
+                                  "trmm_r": b3_stage[3]},
+                     "build_tflops": flops_build / (sum(b3_stage) * 1e-3) / 1e12,
+                     "apply_frames_per_s": F / (np.median(b3_apply) * 1e-3),
+                     "rel_err_by_refine_steps": b3_err}
     out["speedup_vs_fp64_gpu"] = {"build": f64_build_ms / build_ms,
                                   "apply": f64_apply_ms / float(np.median(apply_ms))}
     P.pinv_plan_release(p64)

@@ -93,6 +93,42 @@ def encoding_rows(enc, m0: int, m1: int) -> np.ndarray:
     return np.concatenate(blocks, axis=1)
 
 
+def encoding_columns(enc, cols, m0: int = 0, m1: int = None) -> np.ndarray:
+    """Columns `cols` of E over rows m0..m1-1 (all rows by default), [rows, len(cols)];
+    the same element definition as encoding_rows, evaluated for chosen columns."""
+    V, S, K, C = _dims(enc)
+    m1 = C * K if m1 is None else m1
+    cols = np.asarray(cols)
+    s_idx = cols // V
+    v_idx = cols % V
+    X, Y = voxel_positions(enc.nx, enc.ny)
+    m = np.arange(m0, m1)
+    c = m // K
+    i = m % K
+    species = np.zeros(S) if enc.species_hz is None else np.asarray(enc.species_hz, float)
+    b0 = np.zeros(V) if enc.b0_hz is None else np.asarray(enc.b0_hz, float)
+    t = np.zeros(K) if enc.t is None else np.asarray(enc.t, float)
+    turns = (enc.k[i, 0][:, None] * X[v_idx][None, :] + enc.k[i, 1][:, None] * Y[v_idx][None, :]
+             + (species[s_idx][None, :] + b0[v_idx][None, :]) * t[i][:, None])
+    frac = turns - np.round(turns)
+    out = np.cos(2.0 * math.pi * frac) - 1j * np.sin(2.0 * math.pi * frac)
+    if enc.coil is not None:
+        out = out * enc.coil[c[:, None], v_idx[None, :]]
+    return out
+
+
+def gram_entries(enc, a, b, block: int = 65536) -> np.ndarray:
+    """G[a_j, b_j] = sum_m conj(E[m, a_j]) E[m, b_j] for index pairs (a_j, b_j)."""
+    V, S, K, C = _dims(enc)
+    a = np.asarray(a)
+    b = np.asarray(b)
+    out = np.zeros(len(a), dtype=np.complex128)
+    for m0 in range(0, C * K, block):
+        m1 = min(C * K, m0 + block)
+        out += np.sum(encoding_columns(enc, a, m0, m1).conj() * encoding_columns(enc, b, m0, m1), axis=0)
+    return out
+
+
 def encoding_matrix(enc) -> np.ndarray:
     """The whole E, [M, N] (small cases only)."""
     V, S, K, C = _dims(enc)

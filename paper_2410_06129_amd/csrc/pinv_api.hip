@@ -349,7 +349,6 @@ static pinv_status check_build(const pinv_encoding* e, const pinv_build_opts* o,
   if (st != PINV_OK) return st;
   if (o->prec != PINV_FP64 && o->prec != PINV_FP32 && o->prec != PINV_BF16X3)
     return fail(PINV_ERR_INVALID, "unknown precision");
-  if (o->prec == PINV_BF16X3) return fail(PINV_ERR_UNSUPPORTED, "BF16X3 plans are not built yet");
   if (o->reserved != 0) return fail(PINV_ERR_INVALID, "reserved must be 0");
   if (!(o->lambda >= 0.0) || !isfinite(o->lambda)) return fail(PINV_ERR_INVALID, "lambda must be finite and >= 0");
   double lam = o->lambda;
@@ -498,6 +497,10 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
     BCHK(launch_trmm_w<double>(p->e64, (const double*)p->Linv, (double*)W, s));
     BCHK(hipEventRecord(p->ev[3], s));
     BCHK(launch_trmm_r<double>((const double*)p->Linv, (const double*)W, (double*)p->R, d.N, d.M, s));
+  } else if (o->prec == PINV_BF16X3) {
+    BCHK(launch_trmm_w_b3(p->e32, (const float*)p->Linv, (float*)W, s));
+    BCHK(hipEventRecord(p->ev[3], s));
+    BCHK(launch_trmm_r_b3((const float*)p->Linv, (const float*)W, (float*)p->R, d.N, d.M, s));
   } else {
     BCHK(launch_trmm_w<float>(p->e32, (const float*)p->Linv, (float*)W, s));
     BCHK(hipEventRecord(p->ev[3], s));
@@ -644,13 +647,17 @@ pinv_status pinv_apply_grouped(pinv_context* c, int32_t n, const pinv_apply_item
         it.N = p->N;
         it.M = p->M;
         it.tile0 = tiles;
-        tiles += prec == PINV_FP64 ? apply_tiles<double>(it.F, it.N) : apply_tiles<float>(it.F, it.N);
+        tiles += prec == PINV_FP64     ? apply_tiles<double>(it.F, it.N)
+                 : prec == PINV_BF16X3 ? apply_tiles_b3(it.F, it.N)
+                                       : apply_tiles<float>(it.F, it.N);
       }
       ++i;
     }
     if (b.n == 0) continue;
     if (prec == PINV_FP64)
       HIPCHK(launch_apply<double>(b, tiles, s));
+    else if (prec == PINV_BF16X3)
+      HIPCHK(launch_apply_b3(b, tiles, s));
     else
       HIPCHK(launch_apply<float>(b, tiles, s));
   }

@@ -145,8 +145,17 @@ __device__ __forceinline__ void tile_compute(const typename Cfg::T* __restrict__
 // finish<STEP, STEPS>() turns loaded values into operand values (the E
 // element products for generated operands), store(s) writes them to LDS.
 template <class Cfg, class LA, class LB>
+__device__ __forceinline__ void mainloop_b3(LA& la, LB& lb, int kbeg, int kend, AccTile<Cfg>& acc,
+                                            float* smem_f);
+template <class Cfg, class = void> struct IsB3;
+
+template <class Cfg, class LA, class LB>
 __device__ __forceinline__ void mainloop(LA& la, LB& lb, int kbeg, int kend, AccTile<Cfg>& acc,
                                          typename Cfg::T* smem) {
+  if constexpr (IsB3<Cfg>::value) {
+    mainloop_b3<Cfg>(la, lb, kbeg, kend, acc, smem);
+    return;
+  } else {
   if (kend <= kbeg) return;
   typedef typename Cfg::T T;
   constexpr int STEPS = Cfg::BK / 4;
@@ -179,6 +188,129 @@ __device__ __forceinline__ void mainloop(LA& la, LB& lb, int kbeg, int kend, Acc
       la.store(nxt);
       lb.store(nxt + 2 * Cfg::A_PLANE);
     }
+    __syncthreads();
+  }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// BF16x3 ("BF16 split") products.  Each FP32 operand value x is split into
+// hi = bf16(x) and lo = bf16(x - hi); a real product is hi*hi + hi*lo + lo*hi
+// on v_mfma_f32_16x16x32_bf16 with FP32 accumulation (relative error ~2^-16
+// per product, the lo*lo term dropped).  LDS holds four bf16 planes per
+// operand (re_hi, re_lo, im_hi, im_lo) laid out [outer][k] so a lane reads its
+// eight consecutive k values with one 16-byte load; one chunk is BK = 32, a
+// single MFMA k-step.  The LDS stage is single-buffered: the next chunk's
+// global loads are in flight while the current chunk's MFMAs run.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f32x4 mfma_b16(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ bf16x8 neg_b16(bf16x8 v) {
+  u32x4 u = __builtin_bit_cast(u32x4, v);
+  u ^= 0x80008000u;
+  return __builtin_bit_cast(bf16x8, u);
+}
+__device__ __forceinline__ void split_b16(float x, __bf16* hi, __bf16* lo) {
+  const __bf16 h = (__bf16)x;
+  *hi = h;
+  *lo = (__bf16)(x - (float)h);
+}
+
+template <int BM_, int BN_> struct TileCfgB3 {
+  typedef float T;
+  static constexpr bool B3 = true;
+  static constexpr int BM = BM_, BN = BN_, BK = 32;
+  static constexpr int NT = 256;
+  static constexpr int WTM = BM / 2, WTN = BN / 2;
+  static constexpr int MB = WTM / 16, NB = WTN / 16;
+  static constexpr int LDK = BK + 8;               // bf16 per LDS row (80 bytes)
+  static constexpr int LDA = 0, LDB = 0;            // FP32 layouts unused
+  static constexpr int A_PLANE = BM * LDK, B_PLANE = BN * LDK;   // bf16 elements
+  static constexpr int SMEM_BYTES = (4 * A_PLANE + 4 * B_PLANE) * 2;
+  static constexpr int SMEM_ELEMS = SMEM_BYTES / 4;
+};
+
+template <class Cfg, class> struct IsB3 { static constexpr bool value = false; };
+template <class Cfg> struct IsB3<Cfg, decltype((void)Cfg::B3)> { static constexpr bool value = Cfg::B3; };
+
+template <class Cfg, class Hook>
+__device__ __forceinline__ void tile_compute_b3(const __bf16* __restrict__ sA,
+                                                const __bf16* __restrict__ sB, AccTile<Cfg>& acc,
+                                                Hook&& between) {
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  const int wr = wid >> 1, wc = wid & 1;
+  const int lr = lane & 15, kb = 8 * (lane >> 4);
+  bf16x8 b[Cfg::NB][4];
+#pragma unroll
+  for (int j = 0; j < Cfg::NB; ++j) {
+    const int off = (wc * Cfg::WTN + j * 16 + lr) * Cfg::LDK + kb;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) b[j][p] = *reinterpret_cast<const bf16x8*>(sB + p * Cfg::B_PLANE + off);
+  }
+#pragma unroll
+  for (int i = 0; i < Cfg::MB; ++i) {
+    const int off = (wr * Cfg::WTM + i * 16 + lr) * Cfg::LDK + kb;
+    const bf16x8 arh = *reinterpret_cast<const bf16x8*>(sA + 0 * Cfg::A_PLANE + off);
+    const bf16x8 arl = *reinterpret_cast<const bf16x8*>(sA + 1 * Cfg::A_PLANE + off);
+    const bf16x8 aih = *reinterpret_cast<const bf16x8*>(sA + 2 * Cfg::A_PLANE + off);
+    const bf16x8 ail = *reinterpret_cast<const bf16x8*>(sA + 3 * Cfg::A_PLANE + off);
+    const bf16x8 naih = neg_b16(aih), nail = neg_b16(ail);
+#pragma unroll
+    for (int j = 0; j < Cfg::NB; ++j) {
+      f32x4 cr = acc.re[i][j], ci = acc.im[i][j];
+      cr = mfma_b16(arh, b[j][0], cr);
+      cr = mfma_b16(arh, b[j][1], cr);
+      cr = mfma_b16(arl, b[j][0], cr);
+      cr = mfma_b16(naih, b[j][2], cr);
+      cr = mfma_b16(naih, b[j][3], cr);
+      cr = mfma_b16(nail, b[j][2], cr);
+      ci = mfma_b16(arh, b[j][2], ci);
+      ci = mfma_b16(arh, b[j][3], ci);
+      ci = mfma_b16(arl, b[j][2], ci);
+      ci = mfma_b16(aih, b[j][0], ci);
+      ci = mfma_b16(aih, b[j][1], ci);
+      ci = mfma_b16(ail, b[j][0], ci);
+      acc.re[i][j] = cr;
+      acc.im[i][j] = ci;
+    }
+    between(i);
+  }
+}
+
+template <class Cfg, class LA, class LB>
+__device__ __forceinline__ void mainloop_b3(LA& la, LB& lb, int kbeg, int kend, AccTile<Cfg>& acc,
+                                            float* smem_f) {
+  if (kend <= kbeg) return;
+  __bf16* sA = reinterpret_cast<__bf16*>(smem_f);
+  __bf16* sB = sA + 4 * Cfg::A_PLANE;
+  const int nch = (kend - kbeg + Cfg::BK - 1) / Cfg::BK;
+  la.fetch(kbeg, kend);
+  lb.fetch(kbeg, kend);
+#pragma unroll
+  for (int q = 0; q < Cfg::MB; ++q) {
+    la.finish(q, Cfg::MB);
+    lb.finish(q, Cfg::MB);
+  }
+  for (int c = 0; c < nch; ++c) {
+    la.template store_b3<Cfg::LDK, Cfg::A_PLANE>(sA);
+    lb.template store_b3<Cfg::LDK, Cfg::B_PLANE>(sB);
+    __syncthreads();
+    const bool more = c + 1 < nch;
+    if (more) {
+      la.fetch(kbeg + (c + 1) * Cfg::BK, kend);
+      lb.fetch(kbeg + (c + 1) * Cfg::BK, kend);
+    }
+    tile_compute_b3<Cfg>(sA, sB, acc, [&](int i) {
+      if (more) {
+        la.finish(i, Cfg::MB);
+        lb.finish(i, Cfg::MB);
+      }
+    });
     __syncthreads();
   }
 }
@@ -251,6 +383,16 @@ struct LoadDenseKC {
     }
   }
   __device__ __forceinline__ void finish(int, int) {}
+  template <int LDK, int P>
+  __device__ __forceinline__ void store_b3(__bf16* s) {
+    const int kk = threadIdx.x % TPR;
+#pragma unroll
+    for (int j = 0; j < PASSES; ++j) {
+      const int o = threadIdx.x / TPR + j * RPP;
+      split_b16(re[j], s + o * LDK + kk, s + P + o * LDK + kk);
+      split_b16(im[j], s + 2 * P + o * LDK + kk, s + 3 * P + o * LDK + kk);
+    }
+  }
   __device__ __forceinline__ void store(T* s) {
     const int kk = threadIdx.x % TPR;
 #pragma unroll
@@ -289,6 +431,16 @@ struct LoadDenseOC {
     }
   }
   __device__ __forceinline__ void finish(int, int) {}
+  template <int LDK, int P>
+  __device__ __forceinline__ void store_b3(__bf16* s) {
+    const int o = threadIdx.x % OUTER;
+#pragma unroll
+    for (int j = 0; j < PASSES; ++j) {
+      const int kk = threadIdx.x / OUTER + j * KPP;
+      split_b16(re[j], s + o * LDK + kk, s + P + o * LDK + kk);
+      split_b16(im[j], s + 2 * P + o * LDK + kk, s + 3 * P + o * LDK + kk);
+    }
+  }
   __device__ __forceinline__ void store(T* s) {
     const int o = threadIdx.x % OUTER;
 #pragma unroll
@@ -384,6 +536,16 @@ struct LoadGenCol {
       im[j] = ok[j] ? (CONJ ? -el.im : el.im) : T(0);
     }
   }
+  template <int LDK, int P>
+  __device__ __forceinline__ void store_b3(__bf16* s) {
+    const int o = threadIdx.x % OUTER;
+#pragma unroll
+    for (int j = 0; j < PASSES; ++j) {
+      const int kk = threadIdx.x / OUTER + j * KPP;
+      split_b16(re[j], s + o * LDK + kk, s + P + o * LDK + kk);
+      split_b16(im[j], s + 2 * P + o * LDK + kk, s + 3 * P + o * LDK + kk);
+    }
+  }
   __device__ __forceinline__ void store(T* s_) {
     const int o = threadIdx.x % OUTER;
 #pragma unroll
@@ -449,6 +611,16 @@ struct LoadGenRow {
       const cx<T> el = gen_product<FEAT>(raw[j]);
       re[j] = ok[j] ? el.re : T(0);
       im[j] = ok[j] ? (CONJ ? -el.im : el.im) : T(0);
+    }
+  }
+  template <int LDK, int P>
+  __device__ __forceinline__ void store_b3(__bf16* s) {
+    const int o = threadIdx.x % OUTER;
+#pragma unroll
+    for (int j = 0; j < PASSES; ++j) {
+      const int kk = threadIdx.x / OUTER + j * KPP;
+      split_b16(re[j], s + o * LDK + kk, s + P + o * LDK + kk);
+      split_b16(im[j], s + 2 * P + o * LDK + kk, s + 3 * P + o * LDK + kk);
     }
   }
   __device__ __forceinline__ void store(T* s_) {

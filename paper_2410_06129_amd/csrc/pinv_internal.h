@@ -44,6 +44,10 @@ hipError_t launch_resid(const double* G, const double* b, const SX* X, int F, in
 hipError_t launch_herm_fill(double* G, int N, hipStream_t s);
 template <typename T, int MODE, typename SO>
 hipError_t launch_tri_frames(const T* Li, const T* In, int F, int N, SO* Out, hipStream_t s);
+hipError_t launch_trmm_w_b3(const EncDev<float>& e, const float* Li, float* W, hipStream_t s);
+hipError_t launch_trmm_r_b3(const float* Li, const float* W, float* R, int N, int M, hipStream_t s);
+int apply_tiles_b3(int F, int N);
+hipError_t launch_apply_b3(const ApplyBatch& b, int total_tiles, hipStream_t s);
 hipError_t launch_to_f32(const double* in, float* out, size_t n_complex, hipStream_t s);
 
 }  // namespace pinv

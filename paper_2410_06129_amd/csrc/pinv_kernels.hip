@@ -154,24 +154,29 @@ __global__ __launch_bounds__(256, 2) void k_gram_shared(EncDev<typename Cfg::T> 
 }
 
 // ---------------------------------------------------------------------------
-// Cholesky diagonal block (FP64, one workgroup).  Gaussian elimination of the
-// augmented block [A_kk + lam I | I] without pivoting: at column j every row
-// i > j subtracts mu_ij = A_ij / A_jj times row j, on the full block of A
-// (A_il -= mu_ij A_jl, l > j) and on the identity part (B_ic -= mu_ij B_jc,
-// c <= j).  Rows are read contiguously (row j), so the 64 lanes of a wave hit
-// distinct LDS banks.  The pivots are D_j of A = Lt D Lt^H (Lt unit lower),
-// so L = Lt D^1/2 and L^-1 = D^-1/2 Lt^-1 = D^-1/2 B.  One barrier per column.
-// Only L_kk^-1 is stored: the panel, trailing and inverse updates need no L_kk.
+// Cholesky diagonal block (FP64, one workgroup).  Hermitian elimination of the
+// augmented block [A_kk + lam I | I] without pivoting, lower triangle only: at
+// column j every row i > j takes mu_ij = A_ij / A_jj and updates
+//     A_il -= mu_ij conj(A_lj)   for j < l <= i      (Schur complement, lower part)
+//     B_ic -= mu_ij B_jc         for c <= j          (B = Lt^-1, unit lower)
+// Reading row j of A as the conjugate of column j keeps the updated matrix
+// exactly Hermitian and its diagonal real; updating a full, unsymmetric copy
+// lets the two triangles drift apart and fails on ill-conditioned blocks.
+// The pivots are D_j of A = Lt D Lt^H, so L^-1 = D^-1/2 Lt^-1 = D^-1/2 B.
+// One barrier per column.  A is stored with row stride 65 so that the single
+// column read per lane and column j are spread over the LDS banks.  Only
+// L_kk^-1 is stored: the panel, trailing and inverse updates need no L_kk.
 // ---------------------------------------------------------------------------
-constexpr int kDiagSmem = (2 * 64 * 64) * 16 + 64 * 8;
+constexpr int kDiagLdA = 65;
+constexpr int kDiagSmem = (64 * kDiagLdA + 64 * 64) * 16 + 64 * 8;
 
 __global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ A, double* __restrict__ Li,
                                                    int N, int nb, int k, double lam,
                                                    int* __restrict__ info) {
   if (*info) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  cx<double>* Am = reinterpret_cast<cx<double>*>(smem_raw);   // [64][64] full Hermitian block
-  cx<double>* Bm = Am + 64 * 64;                               // [64][64] unit lower
+  cx<double>* Am = reinterpret_cast<cx<double>*>(smem_raw);   // [64][65], lower part used
+  cx<double>* Bm = Am + 64 * kDiagLdA;                         // [64][64] unit lower
   double* dpiv = reinterpret_cast<double*>(Bm + 64 * 64);     // [64]
   __shared__ int fail;
   const int tid = threadIdx.x;
@@ -182,23 +187,16 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ A, doubl
   for (int idx = tid; idx < 64 * 64; idx += 256) {
     const int i = idx >> 6, j = idx & 63;
     cx<double> v{0.0, 0.0};
-    if (i < nbk && j < nbk) {
-      // the lower triangle is authoritative; mirror it into the upper one
-      if (j <= i) {
-        v = Ac[(size_t)(k0 + i) * N + k0 + j];
-      } else {
-        const cx<double> u = Ac[(size_t)(k0 + j) * N + k0 + i];
-        v = cx<double>{u.re, -u.im};
-      }
-    }
+    if (i < nbk && j <= i) v = Ac[(size_t)(k0 + i) * N + k0 + j];
     if (i == j) v = cx<double>{v.re + lam, 0.0};
-    Am[idx] = v;
+    Am[i * kDiagLdA + j] = v;
     Bm[idx] = cx<double>{i == j ? 1.0 : 0.0, 0.0};
   }
   if (tid == 0) fail = 0;
   __syncthreads();
+  const int c = tid & 63;      // every slot of this thread works on column c
   for (int j = 0; j < nbk; ++j) {
-    const double piv = Am[j * 64 + j].re;
+    const double piv = Am[j * kDiagLdA + j].re;
     if (!(piv > 0.0)) {     // also catches NaN
       if (tid == 0) {
         atomicCAS(info, 0, k0 + j + 1);
@@ -209,21 +207,27 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ A, doubl
     const double inv = 1.0 / piv;
     if (tid == 0) dpiv[j] = piv;
     const int w = nbk - j - 1;
-    // every slot of this thread has column c = tid % 64: read row j once
-    const int c = tid & 63;
-    cx<double>* M = (c <= j) ? Bm : Am;     // B part left of the pivot, A part right of it
-    const cx<double> r = M[j * 64 + c];
+    cx<double> r;
+    if (c <= j) {
+      r = Bm[j * 64 + c];
+    } else {
+      const cx<double> a = Am[c * kDiagLdA + j];   // row j of A = conj(column j)
+      r = cx<double>{a.re, -a.im};
+    }
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int idx = tid + q * 256;
       if (idx < w * 64) {
         const int i = j + 1 + (idx >> 6);
-        const cx<double> aij = Am[i * 64 + j];
-        const cx<double> mu{aij.re * inv, aij.im * inv};
-        cx<double> o = M[i * 64 + c];
-        o.re -= mu.re * r.re - mu.im * r.im;
-        o.im -= mu.re * r.im + mu.im * r.re;
-        M[i * 64 + c] = o;
+        if (c <= i) {
+          const cx<double> aij = Am[i * kDiagLdA + j];
+          const cx<double> mu{aij.re * inv, aij.im * inv};
+          cx<double>* o = (c <= j) ? &Bm[i * 64 + c] : &Am[i * kDiagLdA + c];
+          cx<double> v = *o;
+          v.re -= mu.re * r.re - mu.im * r.im;
+          v.im -= mu.re * r.im + mu.im * r.re;
+          *o = v;
+        }
       }
     }
     __syncthreads();
@@ -231,14 +235,14 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ A, doubl
   __syncthreads();
   if (fail) return;
   for (int idx = tid; idx < nbk * nbk; idx += 256) {
-    const int i = idx / nbk, c = idx - (idx / nbk) * nbk;
+    const int i = idx / nbk, cc = idx - (idx / nbk) * nbk;
     cx<double> v{0.0, 0.0};
-    if (c <= i) {
+    if (cc <= i) {
       const double sc = 1.0 / sqrt(dpiv[i]);
-      const cx<double> b = Bm[i * 64 + c];
-      v = cx<double>{b.re * sc, b.im * sc};
+      const cx<double> bb = Bm[i * 64 + cc];
+      v = cx<double>{bb.re * sc, bb.im * sc};
     }
-    Lc[(size_t)(k0 + i) * N + k0 + c] = v;
+    Lc[(size_t)(k0 + i) * N + k0 + cc] = v;
   }
 }
 
@@ -666,6 +670,15 @@ template <> struct GramCfgOf<double> { typedef TileCfg<double, 64, 64, 8> type; 
 
 template <class Cfg> static size_t smem_bytes() { return Cfg::SMEM_ELEMS * sizeof(typename Cfg::T); }
 
+typedef TileCfgB3<128, 128> B3Cfg;
+
+// Kernels whose LDS exceeds the default 64 KB limit need the attribute once.
+template <class K> static hipError_t allow_smem(K kernel, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
+}
+
 template <typename T> struct PickCfg;
 template <> struct PickCfg<float> { typedef F32Cfg type; };
 template <> struct PickCfg<double> { typedef F64Cfg type; };
@@ -825,6 +838,51 @@ hipError_t launch_tri_frames(const T* Li, const T* In, int F, int N, SO* Out, hi
   if (tiles == 0) return hipSuccess;
   hipLaunchKernelGGL((k_tri_frames<Cfg, MODE, SO>), dim3(tiles), dim3(256), smem_bytes<Cfg>(), s,
                      Li, In, F, N, Out);
+  return hipGetLastError();
+}
+
+// BF16x3 variants of the FP32-typed products (same kernels, split-precision mainloop)
+hipError_t launch_trmm_w_b3(const EncDev<float>& e, const float* Li, float* W, hipStream_t s) {
+  typedef B3Cfg Cfg;
+  const int tiles = cdiv(e.N, Cfg::BM) * cdiv(e.M, Cfg::BN);
+  return with_feat(enc_features(e), [&](auto fc) {
+    auto kern = k_trmm_w<Cfg, decltype(fc)::value>;
+    static bool ok = false;
+    if (!ok) {
+      hipError_t err = allow_smem(kern, smem_bytes<Cfg>());
+      if (err != hipSuccess) return err;
+      ok = true;
+    }
+    hipLaunchKernelGGL(kern, dim3(tiles), dim3(256), smem_bytes<Cfg>(), s, e, Li, W);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_trmm_r_b3(const float* Li, const float* W, float* R, int N, int M, hipStream_t s) {
+  typedef B3Cfg Cfg;
+  static bool ok = false;
+  if (!ok) {
+    hipError_t err = allow_smem(k_trmm_r<Cfg>, smem_bytes<Cfg>());
+    if (err != hipSuccess) return err;
+    ok = true;
+  }
+  const int tiles = cdiv(N, Cfg::BM) * cdiv(M, Cfg::BN);
+  hipLaunchKernelGGL(k_trmm_r<Cfg>, dim3(tiles), dim3(256), smem_bytes<Cfg>(), s, Li, W, R, N, M);
+  return hipGetLastError();
+}
+
+int apply_tiles_b3(int F, int N) { return cdiv(F, B3Cfg::BM) * cdiv(N, B3Cfg::BN); }
+
+hipError_t launch_apply_b3(const ApplyBatch& b, int total_tiles, hipStream_t s) {
+  typedef B3Cfg Cfg;
+  if (total_tiles <= 0) return hipSuccess;
+  static bool ok = false;
+  if (!ok) {
+    hipError_t err = allow_smem(k_apply<Cfg>, smem_bytes<Cfg>());
+    if (err != hipSuccess) return err;
+    ok = true;
+  }
+  hipLaunchKernelGGL(k_apply<Cfg>, dim3(total_tiles), dim3(256), smem_bytes<Cfg>(), s, b);
   return hipGetLastError();
 }
 

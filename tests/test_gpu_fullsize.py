@@ -1,0 +1,130 @@
+"""Parity at the workloads' full sizes, in the launch configuration the bench
+times (FP32 plans, 1000/200 frames in one apply call, one refinement step).
+
+* 32x32 single-coil radial (N=1024, M=2048), FP64: every stage against the full
+  oracle (G within 1e-12 of max|G|, L^-1, R and the image within 1e-9).
+* 64x64, 8 coils, M=32768, 1000 frames and the 5-species + B0 workload
+  (N=5120, M=49152, 200 frames): sampled Gram entries against the oracle's
+  explicit E columns, within M * 2^-53 of max diag (the worst-case rounding of
+  the oracle's own FP64 sum over M rows), and for sampled frames the
+  normal-equation residual E^H(d - E x) - lam x formed by the oracle in FP64.
+  Its normwise backward error ||r|| / ((max diag + lam) ||x||) bounds the
+  relative forward error from below, so it must be <= the forward-error
+  targets: 1e-5 for refined FP32, 1e-10 for FP64.  Frame data are seeded
+  complex Gaussian draws (the residual identity holds for any data).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2410_06129_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_2410_06129_amd import pinv
+    return pinv
+
+
+@pytest.fixture(scope="module")
+def ctx(P):
+    c = P.pinv_context_create(0)
+    yield c
+    P.pinv_context_destroy(c)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def test_config1_every_stage(P, ctx):
+    w = synth.config1()
+    enc = w.enc
+    N, M = enc.N, enc.M
+    ob = oracle.Build(enc, rel=w.rel_lambda)
+    d0 = oracle.forward(enc, w.images)
+    d = d0 + np.sqrt(np.mean(np.abs(d0) ** 2)) * 10 ** (-w.snr_db / 20) * w.noise
+    x_ref = ob.reconstruct(d)
+    R_ref = ob.recon_matrix()
+    Li_ref = oracle.forward_substitution(ob.L, np.eye(N))
+    plan = P.pinv_build(ctx, enc, w.rel_lambda, P.LAMBDA_REL_MEAN_DIAG, P.FP64, P.FLAG_UNCACHED)
+    P.pinv_plan_wait(plan)
+    G = torch.empty((N, N), dtype=torch.complex128, device="cuda")
+    Li = torch.empty_like(G)
+    R = torch.empty((N, M), dtype=torch.complex128, device="cuda")
+    P.pinv_plan_copy_buffer(plan, P.BUF_GRAM, G)
+    P.pinv_plan_copy_buffer(plan, P.BUF_LINV, Li)
+    P.pinv_plan_copy_buffer(plan, P.BUF_R, R)
+    dd = torch.from_numpy(d).cuda()
+    x = torch.empty((1, N), dtype=torch.complex128, device="cuda")
+    P.pinv_apply(ctx, plan, dd, x)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(G.cpu().numpy() - ob.G)) <= 1e-12 * np.max(np.abs(ob.G))
+    assert rel(np.tril(Li.cpu().numpy()), Li_ref) < 1e-9
+    assert rel(R.cpu().numpy(), R_ref) < 1e-9
+    assert rel(x.cpu().numpy(), x_ref) < 1e-9
+    P.pinv_plan_release(plan)
+    # the FP32 path with one refinement step on the same input
+    p32 = P.pinv_build(ctx, enc, w.rel_lambda, P.LAMBDA_REL_MEAN_DIAG, P.FP32, P.FLAG_UNCACHED)
+    x32 = torch.empty((1, N), dtype=torch.complex64, device="cuda")
+    P.pinv_apply(ctx, p32, dd.to(torch.complex64), x32, refine_steps=1)
+    torch.cuda.synchronize()
+    assert rel(x32.cpu().numpy().astype(np.complex128), x_ref) < 1e-5
+    P.pinv_plan_release(p32)
+
+
+def _sampled_checks(P, ctx, enc, rel_lam, F, frames, seed):
+    N, M = enc.N, enc.M
+    rng = np.random.default_rng(seed)
+    d = synth.random_frames((F, M), rng)
+    p32 = P.pinv_build(ctx, enc, rel_lam, P.LAMBDA_REL_MEAN_DIAG, P.FP32, P.FLAG_UNCACHED)
+    p64 = P.pinv_build(ctx, enc, rel_lam, P.LAMBDA_REL_MEAN_DIAG, P.FP64, P.FLAG_UNCACHED)
+    P.pinv_plan_wait(p32)
+    P.pinv_plan_wait(p64)
+    lam = P.pinv_plan_info_get(p32)["lambda_abs"]
+    G = torch.empty((N, N), dtype=torch.complex128, device="cuda")
+    P.pinv_plan_copy_buffer(p32, P.BUF_GRAM, G)
+    d32 = torch.from_numpy(d.astype(np.complex64)).cuda()
+    x32 = torch.empty((F, N), dtype=torch.complex64, device="cuda")
+    P.pinv_apply(ctx, p32, d32, x32, refine_steps=1)
+    d64 = torch.from_numpy(d).cuda()
+    x64 = torch.empty((F, N), dtype=torch.complex128, device="cuda")
+    P.pinv_apply(ctx, p64, d64, x64)
+    torch.cuda.synchronize()
+    # sampled Gram entries: diagonal, near-diagonal and random pairs
+    a = np.concatenate([rng.integers(0, N, 96), np.arange(0, N, max(1, N // 32))])
+    b = np.concatenate([rng.integers(0, N, 96), np.minimum(np.arange(0, N, max(1, N // 32)) + 1, N - 1)])
+    a = np.concatenate([a, a[:32]])
+    b = np.concatenate([b, a[:32]])
+    g_ref = oracle.gram_entries(enc, a, b)
+    g = G.cpu().numpy()[a, b]
+    dmax = float(np.max(oracle.gram_entries(enc, a[-32:], a[-32:]).real))
+    assert np.max(np.abs(g - g_ref)) <= M * 2.0 ** -53 * dmax
+    # residual of the normal equations for sampled frames
+    xs32 = x32[frames].cpu().numpy().astype(np.complex128)
+    xs64 = x64[frames].cpu().numpy()
+    ds = d[frames]
+    scale = dmax + lam
+    for xs, tol in ((xs32, 1e-5), (xs64, 1e-10)):
+        r = oracle.adjoint(enc, ds - oracle.forward(enc, xs)) - lam * xs
+        eta = np.linalg.norm(r, axis=1) / (scale * np.linalg.norm(xs, axis=1))
+        assert eta.max() <= tol, eta
+    # and the two device paths agree on every frame
+    e = (torch.linalg.vector_norm(x32.to(torch.complex128) - x64, dim=1)
+         / torch.linalg.vector_norm(x64, dim=1)).max().item()
+    assert e < 1e-5, e
+    P.pinv_plan_release(p32)
+    P.pinv_plan_release(p64)
+
+
+def test_config2_full_size_sampled(P, ctx):
+    w = synth.config2(F=1)
+    _sampled_checks(P, ctx, w.enc, w.rel_lambda, 1000, [0, 499, 999], seed=2024)
+
+
+def test_config4_full_size_sampled(P, ctx):
+    w = synth.config4(F=1)
+    _sampled_checks(P, ctx, w.enc, w.rel_lambda, 200, [0, 199], seed=4048)

@@ -161,6 +161,59 @@ def test_full_gram_matches_oracle(P, ctx, name, prec):
     P.pinv_plan_release(plan)
 
 
+@pytest.mark.parametrize("name", list(CASES))
+def test_bf16x3_path_matches_oracle(P, ctx, name):
+    """BF16-split products (hi*hi + hi*lo + lo*hi, ~2^-16 per product) for W, R and the
+    apply; FP64 factor; refinement with FP64 residuals and the FP32 factor.  Targets:
+    before refinement within kappa * 1e-4, after two steps within 3e-3 (the BF16-split
+    target) -- in practice FP32-level since the correction uses the FP32 factor."""
+    o = oracle_case(name)
+    enc, N = o["w"].enc, o["w"].enc.N
+    plan = build(P, ctx, enc, P.BF16X3)
+    d = to_dev(o["d"], np.complex64)
+    x0 = torch.empty((d.shape[0], N), dtype=torch.complex64, device="cuda")
+    P.pinv_apply(ctx, plan, d, x0, refine_steps=0)
+    x2 = torch.empty_like(x0)
+    P.pinv_apply(ctx, plan, d, x2, refine_steps=2)
+    torch.cuda.synchronize()
+    e0 = frame_rel(x0.cpu().numpy().astype(np.complex128), o["x"])
+    e2 = frame_rel(x2.cpu().numpy().astype(np.complex128), o["x"])
+    print(f"{name}: bf16x3 err0={e0.max():.2e} err2={e2.max():.2e}")
+    assert e0.max() < o["kappa"] * 1e-4
+    assert e2.max() < 3e-3
+    P.pinv_plan_release(plan)
+
+
+def test_single_coil_spiral_factor(P, ctx):
+    """Single-coil spirals of the serving mix (K = 2N): the Gram is numerically
+    rank deficient and its diagonal blocks are ill-conditioned (a regression case
+    for the diagonal-block elimination).  32x32: L^-1 against the oracle; 64x64:
+    the build succeeds and the FP64 images satisfy the normal equations
+    (backward error <= 1e-10, residual formed by the oracle)."""
+    enc = synth.serving_encoding(32, 1, 3)
+    N = enc.N
+    ob = oracle.Build(enc, rel=1e-3)
+    Lo_inv = oracle.forward_substitution(ob.L, np.eye(N))
+    plan = build(P, ctx, enc, P.FP64)
+    Li = torch.empty((N, N), dtype=torch.complex128, device="cuda")
+    P.pinv_plan_copy_buffer(plan, P.BUF_LINV, Li)
+    torch.cuda.synchronize()
+    assert rel(np.tril(Li.cpu().numpy()), Lo_inv) < 1e-9
+    P.pinv_plan_release(plan)
+    enc = synth.serving_encoding(64, 1, 9)
+    plan = build(P, ctx, enc, P.FP64)
+    lam = P.pinv_plan_info_get(plan)["lambda_abs"]
+    d = synth.random_frames((2, enc.M), np.random.default_rng(9))
+    x = torch.empty((2, enc.N), dtype=torch.complex128, device="cuda")
+    P.pinv_apply(ctx, plan, to_dev(d, np.complex128), x)
+    torch.cuda.synchronize()
+    xs = x.cpu().numpy()
+    r = oracle.adjoint(enc, d - oracle.forward(enc, xs)) - lam * xs
+    eta = np.linalg.norm(r, axis=1) / ((enc.K + lam) * np.linalg.norm(xs, axis=1))
+    assert eta.max() < 1e-10, eta
+    P.pinv_plan_release(plan)
+
+
 def test_cartesian_lambda0_inverse_dft(P, ctx):
     n = 16
     enc = synth.Encoding(n, n, synth.cartesian_full(n, n))

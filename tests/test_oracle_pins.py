@@ -203,6 +203,16 @@ def test_p6_coil_sum_identity():
     assert rel(bs, b) < 1e-14
 
 
+def test_column_accessor_matches_rows():
+    enc = tiny_enc(seed=25, C=3, species=[0.0, 90.0], b0=True)
+    E = oracle.encoding_matrix(enc)
+    cols = [0, 7, 29, 31, 59]
+    assert np.max(np.abs(oracle.encoding_columns(enc, cols) - E[:, cols])) < 1e-14
+    G = E.conj().T @ E
+    a, b = [3, 40, 59], [1, 40, 12]
+    assert np.max(np.abs(oracle.gram_entries(enc, a, b, block=17) - G[a, b])) < 1e-12 * np.abs(G).max()
+
+
 def test_forward_is_adjoint_of_adjoint():
     enc = tiny_enc(seed=15, C=2, species=[0.0, 80.0, 200.0], b0=True)
     rng = np.random.default_rng(2)
