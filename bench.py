@@ -90,6 +90,64 @@ def measured_traffic(kernel: str):
             "source": "profiles/pmc_traffic.json"}
 
 
+PMC_KERNELS = {"trmm_w": "k_trmm_w<pinv::TileCfg<float", "trmm_r": "k_trmm_r<pinv::TileCfg<float",
+               "apply": "k_apply<pinv::TileCfg<float"}
+
+
+def algorithmic_bytes(N: int, M: int, F: int) -> dict:
+    """Compulsory HBM bytes per launch (complex64): L^-1 lower triangle, W and R
+    once each; for the apply D, R and X once."""
+    tri = 8.0 * N * N / 2
+    return {"trmm_w": tri + 8.0 * N * M, "trmm_r": tri + 16.0 * N * M,
+            "apply": 8.0 * F * M + 8.0 * N * M + 8.0 * F * N}
+
+
+def pmc_summary(dirs, frames: int) -> dict:
+    """Per-launch HBM bytes of the dominant FP32 kernels from two rocprofv3 counter
+    runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), scaled by what the same
+    counters read for the plain 2 GiB copy that --pmc-calibrate runs first."""
+    import sqlite3
+
+    def read(db, counter):
+        con = sqlite3.connect(db)
+        rows = con.execute("select kernel_name, value from counters_collection where counter_name = ?",
+                           (counter,)).fetchall()
+        con.close()
+        return rows
+
+    from paper_2410_06129_amd import synth
+    enc = synth.config2(F=1).enc
+    N, M = enc.N, enc.M
+    alg = algorithmic_bytes(N, M, frames)
+    vals = {}
+    for counter, d in zip(("FETCH_SIZE", "WRITE_SIZE"), dirs):
+        rows = read(os.path.join(d, "run_results.db"), counter)
+        copy = max(v for n, v in rows if "copyBuffer" in n)
+        per = {}
+        for key, pat in PMC_KERNELS.items():
+            xs = [v for n, v in rows if pat in n]
+            per[key] = sum(xs) / len(xs) if xs else None
+        vals[counter] = (copy, per)
+    copy_bytes = 2.0 ** 31
+    fscale = copy_bytes / (vals["FETCH_SIZE"][0] * 1024.0)
+    wscale = copy_bytes / (vals["WRITE_SIZE"][0] * 1024.0)
+    rec = {"source_hash": kernel_source_hash(),
+           "workload": f"64x64 image, 8 coils, M={M}, {frames} frames",
+           "commands": [f"rocprofv3 --pmc {c} -d <out> -o run -- python3 bench.py --steps 1 --warmup 0 "
+                        "--fp64-reps 1 --no-cpu-baseline --pmc-calibrate" for c in ("FETCH_SIZE", "WRITE_SIZE")],
+           "calibration": {"kernel": "__amd_rocclr_copyBuffer (2 GiB device copy)",
+                           "fetch_kib": vals["FETCH_SIZE"][0], "write_kib": vals["WRITE_SIZE"][0],
+                           "fetch_scale": fscale, "write_scale": wscale},
+           "kernels": {}}
+    for key in PMC_KERNELS:
+        fk, wk = vals["FETCH_SIZE"][1][key], vals["WRITE_SIZE"][1][key]
+        if fk is None or wk is None:
+            continue
+        rec["kernels"][key] = {"fetch_kib": fk, "write_kib": wk, "fetch_bytes": fk * 1024.0 * fscale,
+                               "write_bytes": wk * 1024.0 * wscale, "algorithmic_bytes": alg[key]}
+    return rec
+
+
 def serving(args) -> dict:
     """Replay the seeded serving trace (Poisson arrivals; sizes 32^2..128^2 with
     probabilities .4/.3/.2/.1; 1, 8 or 16 coils; spiral of 2N samples per coil;
@@ -267,6 +325,8 @@ def main():
     ap.add_argument("--serve-variants", default="fp32_refined,fp64,fp32_unrefined,bf16x3_refined")
     ap.add_argument("--pmc-calibrate", action="store_true",
                     help="run a plain 2 GiB device copy first (reference for HBM byte counters)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/pmc_traffic.json from two rocprofv3 --pmc output folders")
     ap.add_argument("--build-only", type=int, nargs=2, metavar=("SIDE", "COILS"),
                     help="build one plan for a SIDE^2 image with COILS coils (spiral 2N per coil)")
     ap.add_argument("--precisions", default="fp32,fp64")
@@ -278,6 +338,12 @@ def main():
               "sharding of this path is a design note, not a measured configuration.",
               file=sys.stderr)
         sys.exit(2)
+    if args.pmc_summary:
+        rec = pmc_summary(args.pmc_summary, args.frames)
+        with open(os.path.join(ROOT, "profiles", "pmc_traffic.json"), "w") as fh:
+            json.dump(rec, fh, indent=1)
+        print(json.dumps(rec), flush=True)
+        return
 
     import torch
     from paper_2410_06129_amd import pinv as P
@@ -469,8 +535,10 @@ def main():
     name = max(kern, key=lambda k: kern[k][0])
     kms, kfl = kern[name]
     achieved = kfl / (kms * 1e-3) / 1e12
+    tr = measured_traffic(name)
     roof = {"kernel": name, "bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA,
-            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA, "traffic": measured_traffic(name),
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA,
+            "traffic": tr["bytes_per_launch"] if tr else None, "traffic_detail": tr,
             "per_kernel_tflops": {k: v[1] / (v[0] * 1e-3) / 1e12 for k, v in kern.items()}}
 
     out = {

@@ -348,6 +348,29 @@ __device__ __forceinline__ void acc_foreach(const AccTile<Cfg>& acc, F&& f) {
       }
 }
 
+// The same walk with writable accumulator entries (used to start a tile from
+// existing output values).
+template <class Cfg, class F>
+__device__ __forceinline__ void acc_foreach_mut(AccTile<Cfg>& acc, F&& f) {
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  const int wr = wid >> 1, wc = wid & 1;
+  constexpr bool f64 = sizeof(typename Cfg::T) == 8;
+#pragma unroll
+  for (int a = 0; a < Cfg::MB; ++a)
+#pragma unroll
+    for (int b = 0; b < Cfg::NB; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = wr * Cfg::WTM + a * 16 + (f64 ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r);
+        const int col = wc * Cfg::WTN + b * 16 + (lane & 15);
+        typename Cfg::T re = acc.re[a][b][r], im = acc.im[a][b][r];
+        f(row, col, re, im);
+        acc.re[a][b][r] = re;
+        acc.im[a][b][r] = im;
+      }
+}
+
 // ---------------------------------------------------------------------------
 // Loaders.  OUTER = BM (A operand) or BN (B operand).  Each writes its chunk to
 // LDS planes s[0 .. BK*LD) (real) and s[BK*LD .. 2*BK*LD) (imaginary), at

@@ -155,94 +155,111 @@ __global__ __launch_bounds__(256, 2) void k_gram_shared(EncDev<typename Cfg::T> 
 
 // ---------------------------------------------------------------------------
 // Cholesky diagonal block (FP64, one workgroup).  Hermitian elimination of the
-// augmented block [A_kk + lam I | I] without pivoting, lower triangle only: at
-// column j every row i > j takes mu_ij = A_ij / A_jj and updates
-//     A_il -= mu_ij conj(A_lj)   for j < l <= i      (Schur complement, lower part)
-//     B_ic -= mu_ij B_jc         for c <= j          (B = Lt^-1, unit lower)
-// Reading row j of A as the conjugate of column j keeps the updated matrix
-// exactly Hermitian and its diagonal real; updating a full, unsymmetric copy
-// lets the two triangles drift apart and fails on ill-conditioned blocks.
-// The pivots are D_j of A = Lt D Lt^H, so L^-1 = D^-1/2 Lt^-1 = D^-1/2 B.
-// One barrier per column.  A is stored with row stride 65 so that the single
-// column read per lane and column j are spread over the LDS banks.  Only
+// augmented block [A_kk + lam I | I] without pivoting: at column j every row
+// i > j subtracts A_ij / A_jj times row j, on the lower triangle of A and on
+// B = Lt^-1 (unit lower), where A = Lt D Lt^H.  Row j of A is read as the
+// conjugate of column j, so the updated matrix stays exactly Hermitian with a
+// real diagonal; updating a full, unsymmetric copy lets the two triangles
+// drift apart and fails on ill-conditioned blocks.  The pivots are D, and
+// L^-1 = D^-1/2 Lt^-1 = D^-1/2 B.
+//
+// Storage: one complex per (row, column) in registers.  Column c of row i
+// holds A_ic while c is still to be eliminated and B_ic once it has been
+// (A_ic is dead from then on, and B_ic is zero before); B_ii = 1 is implicit.
+// Lane c of every wave owns column c, wave w owns rows w, w + NW, ... (four
+// rows per thread at NW = 16, so the waves of a SIMD hide each other's LDS
+// and barrier latency).  With the pivot folded into a per-lane factor rp_c
+// (row j of B, of 1, or of A, divided by A_jj) each entry costs one complex
+// multiply-add.  Column j+1 and
+// row j+1 are published for the next step as soon as they are final, into the
+// other half of a double-buffered LDS pair: one barrier per column.  Only
 // L_kk^-1 is stored: the panel, trailing and inverse updates need no L_kk.
 // ---------------------------------------------------------------------------
-constexpr int kDiagLdA = 65;
-constexpr int kDiagSmem = (64 * kDiagLdA + 64 * 64) * 16 + 64 * 8;
+constexpr int kDiagWaves = 16;
+constexpr int kDiagThreads = 64 * kDiagWaves;
+constexpr int kDiagSmem = 0;
 
-__global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ A, double* __restrict__ Li,
-                                                   int N, int nb, int k, double lam,
-                                                   int* __restrict__ info) {
+__global__ __launch_bounds__(kDiagThreads) void k_chol_diag(double* __restrict__ A,
+                                                            double* __restrict__ Li, int N, int nb,
+                                                            int k, double lam,
+                                                            int* __restrict__ info) {
   if (*info) return;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  cx<double>* Am = reinterpret_cast<cx<double>*>(smem_raw);   // [64][65], lower part used
-  cx<double>* Bm = Am + 64 * kDiagLdA;                         // [64][64] unit lower
-  double* dpiv = reinterpret_cast<double*>(Bm + 64 * 64);     // [64]
-  __shared__ int fail;
+  constexpr int NW = kDiagWaves, RPT = 64 / kDiagWaves;
+  __shared__ cx<double> colA[2][64];
+  __shared__ cx<double> rowZ[2][64];
+  __shared__ double dpiv[64];
   const int tid = threadIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int c = tid & 63;
   const int k0 = k * nb;
   const int nbk = min(nb, N - k0);
   const cx<double>* Ac = reinterpret_cast<const cx<double>*>(A);
   cx<double>* Lc = reinterpret_cast<cx<double>*>(Li);
-  for (int idx = tid; idx < 64 * 64; idx += 256) {
-    const int i = idx >> 6, j = idx & 63;
+  cx<double> z[RPT];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int i = w + NW * q;
     cx<double> v{0.0, 0.0};
-    if (i < nbk && j <= i) v = Ac[(size_t)(k0 + i) * N + k0 + j];
-    if (i == j) v = cx<double>{v.re + lam, 0.0};
-    Am[i * kDiagLdA + j] = v;
-    Bm[idx] = cx<double>{i == j ? 1.0 : 0.0, 0.0};
+    if (i < nbk && c <= i) v = Ac[(size_t)(k0 + i) * N + k0 + c];
+    if (i == c) v = cx<double>{v.re + lam, 0.0};
+    z[q] = v;
   }
-  if (tid == 0) fail = 0;
+  if (c == 0) {
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) colA[0][w + NW * q] = z[q];
+  }
   __syncthreads();
-  const int c = tid & 63;      // every slot of this thread works on column c
+  bool failed = false;
   for (int j = 0; j < nbk; ++j) {
-    const double piv = Am[j * kDiagLdA + j].re;
-    if (!(piv > 0.0)) {     // also catches NaN
-      if (tid == 0) {
-        atomicCAS(info, 0, k0 + j + 1);
-        fail = 1;
-      }
+    const int p = j & 1;
+    const double piv = colA[p][j].re;   // the same value for every thread
+    if (!(piv > 0.0)) {                 // also catches NaN
+      if (tid == 0) atomicCAS(info, 0, k0 + j + 1);
+      failed = true;
       break;
     }
     const double inv = 1.0 / piv;
     if (tid == 0) dpiv[j] = piv;
-    const int w = nbk - j - 1;
-    cx<double> r;
-    if (c <= j) {
-      r = Bm[j * 64 + c];
+    cx<double> rp;
+    if (c < j) {
+      const cx<double> t = rowZ[p][c];
+      rp = cx<double>{t.re * inv, t.im * inv};
+    } else if (c == j) {
+      rp = cx<double>{inv, 0.0};
     } else {
-      const cx<double> a = Am[c * kDiagLdA + j];   // row j of A = conj(column j)
-      r = cx<double>{a.re, -a.im};
+      const cx<double> t = colA[p][c];   // row j of A = conj(column j)
+      rp = cx<double>{t.re * inv, -t.im * inv};
     }
+    const bool cj = (c == j);
+    cx<double> col[RPT];   // all loads in flight before the first use
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int idx = tid + q * 256;
-      if (idx < w * 64) {
-        const int i = j + 1 + (idx >> 6);
-        if (c <= i) {
-          const cx<double> aij = Am[i * kDiagLdA + j];
-          const cx<double> mu{aij.re * inv, aij.im * inv};
-          cx<double>* o = (c <= j) ? &Bm[i * 64 + c] : &Am[i * kDiagLdA + c];
-          cx<double> v = *o;
-          v.re -= mu.re * r.re - mu.im * r.im;
-          v.im -= mu.re * r.im + mu.im * r.re;
-          *o = v;
-        }
+    for (int q = 0; q < RPT; ++q) col[q] = colA[p][w + NW * q];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int i = w + NW * q;
+      if (i > j) {   // uniform over the wave
+        const cx<double> a = col[q];
+        cx<double> o = cj ? cx<double>{0.0, 0.0} : z[q];
+        o.re -= a.re * rp.re - a.im * rp.im;
+        o.im -= a.re * rp.im + a.im * rp.re;
+        z[q] = o;
+        if (c == j + 1) colA[p ^ 1][i] = o;
+        if (i == j + 1) rowZ[p ^ 1][c] = o;
       }
     }
     __syncthreads();
   }
-  __syncthreads();
-  if (fail) return;
-  for (int idx = tid; idx < nbk * nbk; idx += 256) {
-    const int i = idx / nbk, cc = idx - (idx / nbk) * nbk;
-    cx<double> v{0.0, 0.0};
-    if (cc <= i) {
+  if (failed) return;
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int i = w + NW * q;
+    if (i < nbk && c < nbk) {
       const double sc = 1.0 / sqrt(dpiv[i]);
-      const cx<double> bb = Bm[i * 64 + cc];
-      v = cx<double>{bb.re * sc, bb.im * sc};
+      cx<double> v{0.0, 0.0};
+      if (c < i) v = cx<double>{z[q].re * sc, z[q].im * sc};
+      else if (c == i) v = cx<double>{sc, 0.0};
+      Lc[(size_t)(k0 + i) * N + k0 + c] = v;
     }
-    Lc[(size_t)(k0 + i) * N + k0 + cc] = v;
   }
 }
 
@@ -312,6 +329,8 @@ __global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ A, doub
 
 // Step k trailing update.  Tiles [0, nherk): A_ij -= L_ik L_jk^H for
 // k < j <= i; tiles [nherk, ...): B_ij -= L_ik Y_kj for i > k, j <= k.
+// The accumulators start from -(old tile), loaded together with the first
+// operand chunk, and the tile is stored negated: no read after the products.
 __global__ __launch_bounds__(256) void k_chol_trailing(double* __restrict__ A, double* __restrict__ Li,
                                                        int N, int k, const int* __restrict__ info) {
   if (*info) return;
@@ -321,26 +340,37 @@ __global__ __launch_bounds__(256) void k_chol_trailing(double* __restrict__ A, d
   const int rem = nblk - k - 1;
   const int nherk = rem * (rem + 1) / 2;
   const int t = blockIdx.x;
+  const bool herk = t < nherk;
   const cx<double>* Ac = reinterpret_cast<const cx<double>*>(A);
   const cx<double>* Lc = reinterpret_cast<const cx<double>*>(Li);
   double* smem = smem_base<Cfg>();
-  AccTile<Cfg> acc;
-  acc.zero();
   const int kw = min(N, (k + 1) * nb) - k * nb;
   int r0, c0;
-  double* out;
-  LoadDenseKC<Cfg, 64, Cfg::LDA, double, false> la;      // L_ik[m][l] at A[(i*nb+m)*N + k*nb + l]
-  la.ld = N;
-  la.oend = N;
-  if (t < nherk) {
+  if (herk) {
     int ti, tj;
     tri_index(t, &ti, &tj);
-    const int i = k + 1 + ti, j = k + 1 + tj;
-    r0 = i * nb;
-    c0 = j * nb;
-    out = A;
-    la.p = Ac + k * nb;
-    la.o0 = r0;
+    r0 = (k + 1 + ti) * nb;
+    c0 = (k + 1 + tj) * nb;
+  } else {
+    const int u = t - nherk;
+    r0 = (k + 1 + u / (k + 1)) * nb;
+    c0 = (u % (k + 1)) * nb;
+  }
+  cx<double>* O = reinterpret_cast<cx<double>*>(herk ? A : Li);
+  AccTile<Cfg> acc;
+  acc_foreach_mut<Cfg>(acc, [&](int r, int c, double& re, double& im) {
+    const int row = r0 + r, col = c0 + c;
+    cx<double> o{0.0, 0.0};
+    if (row < N && col < N) o = O[(size_t)row * N + col];
+    re = -o.re;
+    im = -o.im;
+  });
+  LoadDenseKC<Cfg, 64, Cfg::LDA, double, false> la;      // L_ik[m][l] at A[(i*nb+m)*N + k*nb + l]
+  la.p = Ac + k * nb;
+  la.ld = N;
+  la.o0 = r0;
+  la.oend = N;
+  if (herk) {
     LoadDenseKC<Cfg, 64, Cfg::LDB, double, true> lb;     // conj(L_jk[n][l])
     lb.p = Ac + k * nb;
     lb.ld = N;
@@ -348,13 +378,6 @@ __global__ __launch_bounds__(256) void k_chol_trailing(double* __restrict__ A, d
     lb.oend = N;
     mainloop<Cfg>(la, lb, 0, kw, acc, smem);
   } else {
-    const int u = t - nherk;
-    const int i = k + 1 + u / (k + 1), j = u % (k + 1);
-    r0 = i * nb;
-    c0 = j * nb;
-    out = Li;
-    la.p = Ac + k * nb;
-    la.o0 = r0;
     LoadDenseOC<Cfg, 64, Cfg::LDB, double, false> lb;    // Y_kj[l][n] at Li[(k*nb+l)*N + j*nb + n]
     lb.p = Lc + (size_t)(k * nb) * N;
     lb.ld = N;
@@ -362,13 +385,9 @@ __global__ __launch_bounds__(256) void k_chol_trailing(double* __restrict__ A, d
     lb.oend = min(N, c0 + nb);
     mainloop<Cfg>(la, lb, 0, kw, acc, smem);
   }
-  cx<double>* O = reinterpret_cast<cx<double>*>(out);
   acc_foreach<Cfg>(acc, [&](int r, int c, double re, double im) {
     const int row = r0 + r, col = c0 + c;
-    if (row < N && col < N) {
-      cx<double> o = O[(size_t)row * N + col];
-      O[(size_t)row * N + col] = cx<double>{o.re - re, o.im - im};
-    }
+    if (row < N && col < N) O[(size_t)row * N + col] = cx<double>{-re, -im};
   });
 }
 
@@ -733,15 +752,8 @@ hipError_t launch_cholinv(double* A, double* Li, int N, double lam, int* info, h
   const int nb = 64;
   const int nblk = cdiv(N, nb);
   const size_t diag_smem = kDiagSmem;
-  static bool attr = false;
-  if (!attr) {
-    hipError_t err = hipFuncSetAttribute((const void*)k_chol_diag,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)diag_smem);
-    if (err != hipSuccess) return err;
-    attr = true;
-  }
   for (int k = 0; k < nblk; ++k) {
-    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), diag_smem, s, A, Li, N, nb, k, lam, info);
+    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(kDiagThreads), diag_smem, s, A, Li, N, nb, k, lam, info);
     const int ntiles = nblk - 1;   // (nblk-k-1) panel + k inverse blocks
     if (ntiles > 0)
       hipLaunchKernelGGL(k_chol_panel, dim3(ntiles), dim3(256), smem_bytes<CholCfg>(), s, A, Li, N,
