@@ -156,12 +156,18 @@ __device__ __forceinline__ void mainloop(LA& la, LB& lb, int kbeg, int kend, Acc
     mainloop_b3<Cfg>(la, lb, kbeg, kend, acc, smem);
     return;
   } else {
-  if (kend <= kbeg) return;
   typedef typename Cfg::T T;
   constexpr int STEPS = Cfg::BK / 4;
   T* stage0 = smem;
   T* stage1 = smem + Cfg::STAGE;
-  const int nch = (kend - kbeg + Cfg::BK - 1) / Cfg::BK;
+  // FP32 tiles run at least one chunk (an empty range loads zeros): with no
+  // path around the MFMAs the compiler keeps the accumulators in AGPRs only,
+  // where an early return made it hold a zeroed VGPR copy and halved the
+  // occupancy.  FP64 tiles allocate better with the early return.
+  if constexpr (sizeof(T) == 8) {
+    if (kend <= kbeg) return;
+  }
+  const int nch = max(1, (kend - kbeg + Cfg::BK - 1) / Cfg::BK);
   la.fetch(kbeg, kend);
   lb.fetch(kbeg, kend);
 #pragma unroll
@@ -172,7 +178,8 @@ __device__ __forceinline__ void mainloop(LA& la, LB& lb, int kbeg, int kend, Acc
   la.store(stage0);
   lb.store(stage0 + 2 * Cfg::A_PLANE);
   __syncthreads();
-  for (int c = 0; c < nch; ++c) {
+  int c = 0;
+  do {
     T* cur = (c & 1) ? stage1 : stage0;
     T* nxt = (c & 1) ? stage0 : stage1;
     const bool more = c + 1 < nch;
@@ -189,7 +196,7 @@ __device__ __forceinline__ void mainloop(LA& la, LB& lb, int kbeg, int kend, Acc
       lb.store(nxt + 2 * Cfg::A_PLANE);
     }
     __syncthreads();
-  }
+  } while (++c < nch);
   }
 }
 
@@ -377,6 +384,17 @@ __device__ __forceinline__ void acc_foreach_mut(AccTile<Cfg>& acc, F&& f) {
 // s[k*LD + o].
 // ---------------------------------------------------------------------------
 
+// Dense loaders.  fetch() issues one load per pass from a clamped, always
+// in-bounds address and records which passes are in range; the range mask and
+// the optional conjugation are applied when the values are written to LDS, so
+// no instruction between fetch() and store() waits on the loads and the next
+// chunk's loads stay in flight under the current chunk's MFMAs.
+template <typename T, typename S, bool CONJ>
+__device__ __forceinline__ void dense_value(const cx<S>& v, bool ok, T& re, T& im) {
+  re = ok ? T(v.re) : T(0);
+  im = ok ? (CONJ ? -T(v.im) : T(v.im)) : T(0);
+}
+
 // Dense complex storage with k contiguous: element (o, k) at p[o*ld + k].
 template <class Cfg, int OUTER, int LD, typename S, bool CONJ>
 struct LoadDenseKC {
@@ -388,21 +406,17 @@ struct LoadDenseKC {
   const cx<S>* p;
   int64_t ld;
   int o0, oend;
-  T re[PASSES], im[PASSES];
+  cx<S> v[PASSES];
+  bool ok[PASSES];
   __device__ __forceinline__ void fetch(int k0, int kend) {
-    const int kk = threadIdx.x % TPR;
-    const int k = k0 + kk;
+    const int k = k0 + (int)(threadIdx.x % TPR);
+    const int kc = max(0, min(k, kend - 1));
 #pragma unroll
     for (int j = 0; j < PASSES; ++j) {
-      const int o = o0 + threadIdx.x / TPR + j * RPP;
-      if (o < oend && k < kend) {
-        cx<S> v = p[(int64_t)o * ld + k];
-        re[j] = T(v.re);
-        im[j] = CONJ ? -T(v.im) : T(v.im);
-      } else {
-        re[j] = T(0);
-        im[j] = T(0);
-      }
+      const int o = o0 + (int)(threadIdx.x / TPR) + j * RPP;
+      ok[j] = o < oend && k < kend;
+      const int oc = max(0, min(o, oend - 1));
+      v[j] = p[(int64_t)oc * ld + kc];
     }
   }
   __device__ __forceinline__ void finish(int, int) {}
@@ -412,8 +426,10 @@ struct LoadDenseKC {
 #pragma unroll
     for (int j = 0; j < PASSES; ++j) {
       const int o = threadIdx.x / TPR + j * RPP;
-      split_b16(re[j], s + o * LDK + kk, s + P + o * LDK + kk);
-      split_b16(im[j], s + 2 * P + o * LDK + kk, s + 3 * P + o * LDK + kk);
+      T re, im;
+      dense_value<T, S, CONJ>(v[j], ok[j], re, im);
+      split_b16(re, s + o * LDK + kk, s + P + o * LDK + kk);
+      split_b16(im, s + 2 * P + o * LDK + kk, s + 3 * P + o * LDK + kk);
     }
   }
   __device__ __forceinline__ void store(T* s) {
@@ -421,8 +437,10 @@ struct LoadDenseKC {
 #pragma unroll
     for (int j = 0; j < PASSES; ++j) {
       const int o = threadIdx.x / TPR + j * RPP;
-      s[kk * LD + o] = re[j];
-      s[Cfg::BK * LD + kk * LD + o] = im[j];
+      T re, im;
+      dense_value<T, S, CONJ>(v[j], ok[j], re, im);
+      s[kk * LD + o] = re;
+      s[Cfg::BK * LD + kk * LD + o] = im;
     }
   }
 };
@@ -437,20 +455,17 @@ struct LoadDenseOC {
   const cx<S>* p;
   int64_t ld;
   int o0, oend;
-  T re[PASSES], im[PASSES];
+  cx<S> v[PASSES];
+  bool ok[PASSES];
   __device__ __forceinline__ void fetch(int k0, int kend) {
-    const int o = o0 + threadIdx.x % OUTER;
+    const int o = o0 + (int)(threadIdx.x % OUTER);
+    const int oc = max(0, min(o, oend - 1));
 #pragma unroll
     for (int j = 0; j < PASSES; ++j) {
-      const int k = k0 + threadIdx.x / OUTER + j * KPP;
-      if (o < oend && k < kend) {
-        cx<S> v = p[(int64_t)k * ld + o];
-        re[j] = T(v.re);
-        im[j] = CONJ ? -T(v.im) : T(v.im);
-      } else {
-        re[j] = T(0);
-        im[j] = T(0);
-      }
+      const int k = k0 + (int)(threadIdx.x / OUTER) + j * KPP;
+      ok[j] = o < oend && k < kend;
+      const int kc = max(0, min(k, kend - 1));
+      v[j] = p[(int64_t)kc * ld + oc];
     }
   }
   __device__ __forceinline__ void finish(int, int) {}
@@ -460,8 +475,10 @@ struct LoadDenseOC {
 #pragma unroll
     for (int j = 0; j < PASSES; ++j) {
       const int kk = threadIdx.x / OUTER + j * KPP;
-      split_b16(re[j], s + o * LDK + kk, s + P + o * LDK + kk);
-      split_b16(im[j], s + 2 * P + o * LDK + kk, s + 3 * P + o * LDK + kk);
+      T re, im;
+      dense_value<T, S, CONJ>(v[j], ok[j], re, im);
+      split_b16(re, s + o * LDK + kk, s + P + o * LDK + kk);
+      split_b16(im, s + 2 * P + o * LDK + kk, s + 3 * P + o * LDK + kk);
     }
   }
   __device__ __forceinline__ void store(T* s) {
@@ -469,8 +486,10 @@ struct LoadDenseOC {
 #pragma unroll
     for (int j = 0; j < PASSES; ++j) {
       const int kk = threadIdx.x / OUTER + j * KPP;
-      s[kk * LD + o] = re[j];
-      s[Cfg::BK * LD + kk * LD + o] = im[j];
+      T re, im;
+      dense_value<T, S, CONJ>(v[j], ok[j], re, im);
+      s[kk * LD + o] = re;
+      s[Cfg::BK * LD + kk * LD + o] = im;
     }
   }
 };
