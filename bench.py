@@ -148,6 +148,53 @@ def pmc_summary(dirs, frames: int) -> dict:
     return rec
 
 
+def metric_timings(P, ctx, plan, enc, stream, dev, reps: int = 3) -> dict:
+    """SRF (Eq. 9) and noise matrix (Eq. 10) of an FP32 plan: median HIP-event
+    time per call on the launch stream, with the rate against each kernel's
+    bound (HBM bytes 8NM for the maps, complex-equivalent flops for the full
+    matrices: 8MN^2 for R E, 4MN^2 for the Hermitian R R^H)."""
+    import torch
+    N, M, C = enc.N, enc.M, enc.C
+    rng = np.random.default_rng(99)
+    a = rng.standard_normal((C, C)) + 1j * rng.standard_normal((C, C))
+    psi_c = a @ a.conj().T + C * np.eye(C)
+    out_d = torch.empty((N,), dtype=torch.complex64, device=dev)
+    out_f = torch.empty((N, N), dtype=torch.complex64, device=dev)
+    out_r = torch.empty((N,), dtype=torch.float32, device=dev)
+    runs = {
+        "srf_map": (lambda: P.pinv_srf(ctx, plan, out_d, P.METRIC_DIAG), "GB/s", 8.0 * N * M),
+        "srf_matrix": (lambda: P.pinv_srf(ctx, plan, out_f, P.METRIC_FULL), "TFLOP/s", 8.0 * M * N * N),
+        "noise_map_white": (lambda: P.pinv_noise(ctx, plan, out_r, mode=P.METRIC_DIAG), "GB/s",
+                            8.0 * N * M),
+        "noise_map_coils": (lambda: P.pinv_noise(ctx, plan, out_r, coil_cov=psi_c, mode=P.METRIC_DIAG),
+                            "GB/s", 8.0 * N * M),
+        "noise_matrix_white": (lambda: P.pinv_noise(ctx, plan, out_f, mode=P.METRIC_FULL), "TFLOP/s",
+                               4.0 * M * N * N),
+        "noise_matrix_coils": (lambda: P.pinv_noise(ctx, plan, out_f, coil_cov=psi_c,
+                                                    mode=P.METRIC_FULL), "TFLOP/s", 4.0 * M * N * N),
+    }
+    res = {}
+    for name, (fn, unit, work) in runs.items():
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = float(np.median(ts))
+        rate = work / (ms * 1e-3) / (1e9 if unit == "GB/s" else 1e12)
+        res[name] = {"ms": ms, unit: rate}
+        log(f"metric {name}: {ms:.3f} ms, {rate:.1f} {unit}")
+    P.pinv_srf(ctx, plan, out_d, P.METRIC_DIAG)
+    srf = out_d.cpu().numpy().real
+    res["srf_map_range"] = [float(srf.min()), float(srf.max())]
+    return res
+
+
 def serving(args) -> dict:
     """Replay the seeded serving trace (Poisson arrivals; sizes 32^2..128^2 with
     probabilities .4/.3/.2/.1; 1, 8 or 16 coils; spiral of 2N samples per coil;
@@ -460,6 +507,7 @@ def main():
         torch.cuda.synchronize()
         apply_ms.append(e0.elapsed_time(e1))
         refine_ms.append(e1.elapsed_time(e2) - e0.elapsed_time(e1))
+    metrics = metric_timings(P, ctx, p32, enc, stream, dev)
     P.pinv_plan_release(p32)
 
     # --- timed steps ---
@@ -567,6 +615,7 @@ def main():
                      "build_tflops": flops_build / (sum(b3_stage) * 1e-3) / 1e12,
                      "apply_frames_per_s": F / (np.median(b3_apply) * 1e-3),
                      "rel_err_by_refine_steps": b3_err}
+    out["metrics_fp32_plan"] = metrics
     out["speedup_vs_fp64_gpu"] = {"build": f64_build_ms / build_ms,
                                   "apply": f64_apply_ms / float(np.median(apply_ms))}
     P.pinv_plan_release(p64)

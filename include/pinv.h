@@ -164,6 +164,36 @@ pinv_status pinv_apply(pinv_context *ctx, const pinv_plan *p, const void *data, 
 pinv_status pinv_apply_grouped(pinv_context *ctx, int32_t n, const pinv_apply_item *items,
                                int32_t refine_steps, void *hip_stream);
 
+/* Shapes of the image-quality metrics. */
+typedef enum { PINV_METRIC_DIAG = 0, PINV_METRIC_FULL = 1 } pinv_metric_mode;
+
+/* Spatial response function of the plan's reconstruction (Sec. 2.4, Eq. 9):
+ * SRF = R E, with E regenerated from the plan's tables as in the build.
+ * PINV_METRIC_DIAG writes the N diagonal entries (the SRF map; the caller
+ * reshapes column order n = s*V + iy*nx + ix to the grid); PINV_METRIC_FULL
+ * writes the N x N matrix, row-major.  Entries are complex: complex128 for FP64
+ * plans, complex64 otherwise (for an exact R the matrix is Hermitian and the
+ * diagonal real, so imaginary parts of the map are rounding-level).
+ * out: device, caller-owned, N or N*N entries.  Ordered on hip_stream after
+ * the plan's build.  Errors: INVALID (NULL, bad mode, plan of another
+ * context), DEVICE. */
+pinv_status pinv_srf(pinv_context *ctx, const pinv_plan *p, int32_t mode, void *out,
+                     void *hip_stream);
+
+/* Noise matrix of the reconstruction (Sec. 2.4, Eq. 10): X = R Psi R^H for
+ * data noise that is white over samples and correlated over coils,
+ * Psi = Psi_c (kron) I_K.  coil_cov: host [C][C] complex128 interleaved,
+ * row-major, Hermitian positive definite, copied before return; NULL means
+ * Psi = I.  PINV_METRIC_DIAG writes diag(X), N real values (double for FP64
+ * plans, float otherwise; the noise map is their square root).
+ * PINV_METRIC_FULL writes X, N x N complex, row-major; with a coil covariance
+ * it allocates an N x M work array on hip_stream's memory pool for the call.
+ * With coil_cov the call synchronises hip_stream once (the covariance factor is
+ * staged through pinned host memory).  Errors: INVALID (NULL, bad mode,
+ * coil_cov not Hermitian positive definite), NOMEM, DEVICE. */
+pinv_status pinv_noise(pinv_context *ctx, const pinv_plan *p, const double *coil_cov, int32_t mode,
+                       void *out, void *hip_stream);
+
 /* Forward model data[f] = E image[f] (Eq. 1) in the plan's precision, with E
  * generated on the fly.  image: device [F][N], data: device [F][M]. */
 pinv_status pinv_forward(pinv_context *ctx, const pinv_plan *p, const void *image, int64_t F,

@@ -26,7 +26,8 @@ Each function names the passage it follows.  Pins for every step live in
 tests/test_oracle_pins.py (Cartesian inverse DFT, DFT special cases for the
 species and off-resonance factors, SVD filter factors, Moore-Penrose
 conditions, conjugate-phase limit, closed-form diagonal, coil-sum identity,
-normal-equation residual, push-through identity, eigen route, SRF identity).
+normal-equation residual, push-through identity, eigen route, SRF identity,
+noise matrix for white and coil-correlated noise).
 """
 from __future__ import annotations
 
@@ -282,6 +283,20 @@ def srf_matrix(R: np.ndarray, E: np.ndarray) -> np.ndarray:
 def noise_matrix(R: np.ndarray, psi: np.ndarray) -> np.ndarray:
     """X = R Psi R^H for a data-noise covariance Psi [M, M] (Eq. 10)."""
     return R @ psi @ R.conj().T
+
+
+def coil_noise_covariance(psi_c: np.ndarray, K: int) -> np.ndarray:
+    """Data-noise covariance [M, M] for noise that is white over the K samples
+    and correlated over coils with covariance psi_c [C, C]: entry
+    ((c, i), (c', i')) is psi_c[c, c'] when i == i', else 0, with rows in the
+    coil-major order m = c*K + i of E.  This is the Psi of Eq. 10."""
+    psi_c = np.asarray(psi_c, dtype=np.complex128)
+    C = psi_c.shape[0]
+    psi = np.zeros((C * K, C * K), dtype=np.complex128)
+    for c in range(C):
+        for c2 in range(C):
+            psi[c * K:(c + 1) * K, c2 * K:(c2 + 1) * K] = psi_c[c, c2] * np.eye(K)
+    return psi
 
 
 def relative_error(x: np.ndarray, ref: np.ndarray) -> np.ndarray:

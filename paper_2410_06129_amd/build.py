@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpinv.so")
-SOURCES = ["pinv_kernels.hip", "pinv_api.hip", "pinv_serve.hip"]
+SOURCES = ["pinv_kernels.hip", "pinv_metrics.hip", "pinv_api.hip", "pinv_serve.hip"]
 SIM_LIB = os.path.join(HERE, "libpinv_schedsim.so")
 HEADERS = ["pinv_device.h", "pinv_internal.h"]
 

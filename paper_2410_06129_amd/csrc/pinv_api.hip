@@ -4,7 +4,9 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <atomic>
+#include <cmath>
 #include <cstdio>
 #include <list>
 #include <mutex>
@@ -695,6 +697,132 @@ pinv_status pinv_forward(pinv_context* c, const pinv_plan* pc, const void* image
                                                 (float*)data, s)));
   }
   return PINV_OK;
+}
+
+extern "C++" {
+// Coil noise covariance factor Psi_c = Lc Lc^H (C x C, complex, row-major
+// interleaved, Lc lower).  False unless Psi_c is Hermitian positive definite.
+static bool coil_cholesky(const double* psi, int C, std::vector<double>& L) {
+  double amax = 0.0;
+  for (int i = 0; i < 2 * C * C; ++i) amax = std::max(amax, std::fabs(psi[i]));
+  if (!(amax > 0.0) || !std::isfinite(amax)) return false;
+  for (int a = 0; a < C; ++a)
+    for (int b = 0; b < C; ++b) {
+      const double dr = psi[2 * (a * C + b)] - psi[2 * (b * C + a)];
+      const double di = psi[2 * (a * C + b) + 1] + psi[2 * (b * C + a) + 1];
+      if (std::hypot(dr, di) > 1e-12 * amax) return false;
+    }
+  L.assign(2 * C * C, 0.0);
+  for (int j = 0; j < C; ++j) {
+    double d = psi[2 * (j * C + j)];
+    for (int k = 0; k < j; ++k)
+      d -= L[2 * (j * C + k)] * L[2 * (j * C + k)] + L[2 * (j * C + k) + 1] * L[2 * (j * C + k) + 1];
+    if (!(d > 0.0)) return false;
+    const double ljj = std::sqrt(d);
+    L[2 * (j * C + j)] = ljj;
+    for (int i = j + 1; i < C; ++i) {
+      double sr = psi[2 * (i * C + j)], si = psi[2 * (i * C + j) + 1];
+      for (int k = 0; k < j; ++k) {   // s -= L[i][k] conj(L[j][k])
+        const double ar = L[2 * (i * C + k)], ai = L[2 * (i * C + k) + 1];
+        const double br = L[2 * (j * C + k)], bi = L[2 * (j * C + k) + 1];
+        sr -= ar * br + ai * bi;
+        si -= ai * br - ar * bi;
+      }
+      L[2 * (i * C + j)] = sr / ljj;
+      L[2 * (i * C + j) + 1] = si / ljj;
+    }
+  }
+  return true;
+}
+
+static pinv_status metric_args(pinv_context* c, const pinv_plan* p, int32_t mode, void* out) {
+  if (!c || !p || !out) return fail(PINV_ERR_INVALID, "NULL argument");
+  if (p->ctx != c) return fail(PINV_ERR_INVALID, "plan belongs to another context");
+  if (mode != PINV_METRIC_DIAG && mode != PINV_METRIC_FULL)
+    return fail(PINV_ERR_INVALID, "mode must be PINV_METRIC_DIAG or PINV_METRIC_FULL");
+  return PINV_OK;
+}
+}  // extern "C++"
+
+pinv_status pinv_srf(pinv_context* c, const pinv_plan* pc, int32_t mode, void* out, void* stream) {
+  const pinv_status st = metric_args(c, pc, mode, out);
+  if (st != PINV_OK) return st;
+  const pinv_plan* p = pc;
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(hipStreamWaitEvent(s, p->ev[4], 0));
+  if (p->prec == PINV_FP64) {
+    if (mode == PINV_METRIC_DIAG)
+      HIPCHK(launch_srf_diag<double>(p->e64, (const double*)p->R, (double*)out, s));
+    else
+      HIPCHK(launch_srf_full<double>(p->e64, (const double*)p->R, (double*)out, s));
+  } else {
+    if (mode == PINV_METRIC_DIAG)
+      HIPCHK(launch_srf_diag<float>(p->e32, (const float*)p->R, (float*)out, s));
+    else
+      HIPCHK(launch_srf_full<float>(p->e32, (const float*)p->R, (float*)out, s));
+  }
+  return PINV_OK;
+}
+
+extern "C++" {
+namespace {
+template <typename T>
+pinv_status noise_impl(const pinv_plan* p, const T* Lc, int32_t mode, T* out, hipStream_t s) {
+  const T* R = (const T*)p->R;
+  if (mode == PINV_METRIC_DIAG) {
+    HIPCHK(launch_noise_diag<T>(R, p->N, p->K, p->C, Lc, out, s));
+    return PINV_OK;
+  }
+  if (!Lc) {
+    HIPCHK(launch_noise_full<T>(R, p->N, p->M, out, s));
+    return PINV_OK;
+  }
+  void* Rt = nullptr;
+  HIPCHK(hipMallocAsync(&Rt, (size_t)p->N * p->M * 2 * sizeof(T), s));
+  hipError_t e = launch_noise_mix<T>(R, p->N, p->K, p->C, Lc, (T*)Rt, s);
+  if (e == hipSuccess) e = launch_noise_full<T>((const T*)Rt, p->N, p->M, out, s);
+  const hipError_t f = hipFreeAsync(Rt, s);
+  HIPCHK(e);
+  HIPCHK(f);
+  return PINV_OK;
+}
+}  // namespace
+}  // extern "C++"
+
+pinv_status pinv_noise(pinv_context* c, const pinv_plan* pc, const double* coil_cov, int32_t mode,
+                       void* out, void* stream) {
+  const pinv_status st = metric_args(c, pc, mode, out);
+  if (st != PINV_OK) return st;
+  const pinv_plan* p = pc;
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(hipStreamWaitEvent(s, p->ev[4], 0));
+  const bool f64 = p->prec == PINV_FP64;
+  const size_t rs = f64 ? 8 : 4;
+  void* dL = nullptr;
+  if (coil_cov) {
+    std::vector<double> L;
+    if (!coil_cholesky(coil_cov, p->C, L))
+      return fail(PINV_ERR_INVALID, "coil_cov is not Hermitian positive definite");
+    const size_t bytes = L.size() * rs;
+    void* host = nullptr;
+    HIPCHK(hipHostMalloc(&host, bytes, hipHostMallocDefault));
+    for (size_t i = 0; i < L.size(); ++i) {
+      if (f64) ((double*)host)[i] = L[i];
+      else ((float*)host)[i] = (float)L[i];
+    }
+    hipError_t e = hipMallocAsync(&dL, bytes, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dL, host, bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);   // the staging buffer is freed next
+    (void)hipHostFree(host);
+    if (e != hipSuccess && dL) (void)hipFreeAsync(dL, s);
+    HIPCHK(e);
+  }
+  const pinv_status r = f64 ? noise_impl<double>(p, (const double*)dL, mode, (double*)out, s)
+                            : noise_impl<float>(p, (const float*)dL, mode, (float*)out, s);
+  if (dL) HIPCHK(hipFreeAsync(dL, s));
+  return r;
 }
 
 pinv_status pinv_plan_info_get(const pinv_plan* p, pinv_plan_info* out) {

@@ -529,7 +529,11 @@ __device__ __forceinline__ cx<T> gen_product(const GenRaw<T>& r) {
 
 // Generated operand, outer index = column n of E, k = row m of E:
 // element (o, k) = E[k, o] (or its conjugate).  Each thread keeps one column.
-template <class Cfg, int OUTER, int LD, bool CONJ, int FEAT>
+// ALIGNED (K a multiple of BK, chunks starting at multiples of BK): every row
+// of a chunk lies in one coil, so the coil and off-resonance factors are
+// loaded once per chunk or per tile and the per-sample tables advance by a
+// constant stride instead of being re-indexed element by element.
+template <class Cfg, int OUTER, int LD, bool CONJ, int FEAT, bool ALIGNED = false>
 struct LoadGenCol {
   typedef typename Cfg::T T;
   static constexpr int KPP = Cfg::NT / OUTER;
@@ -538,6 +542,7 @@ struct LoadGenCol {
   EncDev<T> e;
   bool valid;
   int s, v, ix, iy;
+  T b0v;
   bool ok[PASSES];
   GenRaw<T> raw[PASSES];
   T re[PASSES], im[PASSES];
@@ -550,8 +555,31 @@ struct LoadGenCol {
     v = nn - s * e.V;
     iy = v / e.nx;
     ix = v - iy * e.nx;
+    if constexpr (ALIGNED && (FEAT & FEAT_B0) != 0) b0v = e.b0[v];
   }
   __device__ __forceinline__ void fetch(int k0, int kend) {
+    if constexpr (ALIGNED) {
+      // k0 is a multiple of BK, so the chunk's rows share one coil and the
+      // sample index stays below K; the coil index is clamped for chunks past M
+      const int c = k0 / e.K;
+      const int i0 = k0 - c * e.K + (int)(threadIdx.x / OUTER);
+      const cx<T>* px = reinterpret_cast<const cx<T>*>(e.px) + (size_t)i0 * e.nx + ix;
+      const cx<T>* py = reinterpret_cast<const cx<T>*>(e.py) + (size_t)i0 * e.ny + iy;
+      cx<T> coil{T(1), T(0)};
+      if constexpr ((FEAT & FEAT_COIL) != 0)
+        coil = reinterpret_cast<const cx<T>*>(e.coil)[(size_t)min(c, e.C - 1) * e.V + v];
+#pragma unroll
+      for (int j = 0; j < PASSES; ++j) {
+        ok[j] = valid && k0 + (int)(threadIdx.x / OUTER) + j * KPP < kend;
+        raw[j].px = px[(size_t)j * KPP * e.nx];
+        raw[j].py = py[(size_t)j * KPP * e.ny];
+        if constexpr ((FEAT & FEAT_Q) != 0)
+          raw[j].q = reinterpret_cast<const cx<T>*>(e.q)[(size_t)(i0 + j * KPP) * e.S + s];
+        if constexpr ((FEAT & FEAT_B0) != 0) raw[j].b0t = b0v * e.t[i0 + j * KPP];
+        if constexpr ((FEAT & FEAT_COIL) != 0) raw[j].coil = coil;
+      }
+      return;
+    }
     int m = k0 + threadIdx.x / OUTER;
     int c = m / e.K;
     int i = m - c * e.K;
@@ -601,7 +629,11 @@ struct LoadGenCol {
 
 // Generated operand, outer index = row m of E, k = column n of E:
 // element (o, k) = E[o, k] (or its conjugate).  Each thread keeps one row.
-template <class Cfg, int OUTER, int LD, bool CONJ, int FEAT>
+// ALIGNED (nx a multiple of BK, chunks starting at multiples of BK): every
+// column of a chunk lies in one image row of one species, so Py, Q and the
+// sample's time are loaded once per chunk or per tile, and Px and the coil map
+// advance by a constant stride.
+template <class Cfg, int OUTER, int LD, bool CONJ, int FEAT, bool ALIGNED = false>
 struct LoadGenRow {
   typedef typename Cfg::T T;
   static constexpr int KPP = Cfg::NT / OUTER;
@@ -610,6 +642,7 @@ struct LoadGenRow {
   EncDev<T> e;
   bool valid;
   int c, i;
+  T ti;
   bool ok[PASSES];
   GenRaw<T> raw[PASSES];
   T re[PASSES], im[PASSES];
@@ -620,8 +653,33 @@ struct LoadGenRow {
     const int mm = valid ? m : 0;
     c = mm / e.K;
     i = mm - c * e.K;
+    if constexpr (ALIGNED && (FEAT & FEAT_B0) != 0) ti = e.t[i];
   }
   __device__ __forceinline__ void fetch(int k0, int kend) {
+    if constexpr (ALIGNED) {
+      // indices come from the chunk start clamped to the last full chunk, so
+      // every table access stays in bounds; ok[] masks columns >= kend
+      const int n0 = min(k0, e.N - Cfg::BK) + (int)(threadIdx.x / OUTER);
+      const int s = n0 / e.V;
+      const int v0 = n0 - s * e.V;
+      const int iy = v0 / e.nx;
+      const int ix0 = v0 - iy * e.nx;
+      const cx<T> py = reinterpret_cast<const cx<T>*>(e.py)[(size_t)i * e.ny + iy];
+      cx<T> q{T(1), T(0)};
+      if constexpr ((FEAT & FEAT_Q) != 0) q = reinterpret_cast<const cx<T>*>(e.q)[(size_t)i * e.S + s];
+      const cx<T>* px = reinterpret_cast<const cx<T>*>(e.px) + (size_t)i * e.nx + ix0;
+      const cx<T>* coil = reinterpret_cast<const cx<T>*>(e.coil) + (size_t)c * e.V + v0;
+#pragma unroll
+      for (int j = 0; j < PASSES; ++j) {
+        ok[j] = valid && k0 + (int)(threadIdx.x / OUTER) + j * KPP < kend;
+        raw[j].px = px[j * KPP];
+        raw[j].py = py;
+        if constexpr ((FEAT & FEAT_Q) != 0) raw[j].q = q;
+        if constexpr ((FEAT & FEAT_B0) != 0) raw[j].b0t = e.b0[v0 + j * KPP] * ti;
+        if constexpr ((FEAT & FEAT_COIL) != 0) raw[j].coil = coil[j * KPP];
+      }
+      return;
+    }
     int n = k0 + threadIdx.x / OUTER;
     const int nn = n < e.N ? n : 0;
     int s = nn / e.V;

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "pinv_device.h"
 
@@ -49,5 +50,77 @@ hipError_t launch_trmm_r_b3(const float* Li, const float* W, float* R, int N, in
 int apply_tiles_b3(int F, int N);
 hipError_t launch_apply_b3(const ApplyBatch& b, int total_tiles, hipStream_t s);
 hipError_t launch_to_f32(const double* in, float* out, size_t n_complex, hipStream_t s);
+template <typename T> hipError_t launch_srf_diag(const EncDev<T>& e, const T* R, T* out, hipStream_t s);
+template <typename T> hipError_t launch_srf_full(const EncDev<T>& e, const T* R, T* out, hipStream_t s);
+template <typename T>
+hipError_t launch_noise_mix(const T* R, int N, int K, int C, const T* Lc, T* Rt, hipStream_t s);
+template <typename T>
+hipError_t launch_noise_diag(const T* R, int N, int K, int C, const T* Lc, T* out, hipStream_t s);
+template <typename T> hipError_t launch_noise_full(const T* A, int N, int M, T* X, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Tile kernels: shared device helpers and launch configuration
+// ---------------------------------------------------------------------------
+template <class Cfg>
+__device__ __forceinline__ typename Cfg::T* smem_base() {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  return reinterpret_cast<typename Cfg::T*>(smem_raw);
+}
+
+// Lower-triangular tile index -> (bi, bj), bi >= bj.
+__device__ __forceinline__ void tri_index(int t, int* bi, int* bj) {
+  int i = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+  while ((i + 1) * (i + 2) / 2 <= t) ++i;
+  while (i * (i + 1) / 2 > t) --i;
+  *bi = i;
+  *bj = t - i * (i + 1) / 2;
+}
+
+typedef TileCfg<float, 128, 128, 8> F32Cfg;
+typedef TileCfg<double, 64, 64, 8> F64Cfg;
+
+template <typename T> struct GramCfgOf;     // square tiles for the triangular Gram grid
+template <> struct GramCfgOf<float> { typedef TileCfg<float, 128, 128, 8> type; };
+template <> struct GramCfgOf<double> { typedef TileCfg<double, 64, 64, 8> type; };
+
+template <class Cfg> static size_t smem_bytes() { return Cfg::SMEM_ELEMS * sizeof(typename Cfg::T); }
+
+typedef TileCfgB3<128, 128> B3Cfg;
+
+// Kernels whose LDS exceeds the default 64 KB limit need the attribute once.
+template <class K> static hipError_t allow_smem(K kernel, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
+}
+
+template <typename T> struct PickCfg;
+template <> struct PickCfg<float> { typedef F32Cfg type; };
+template <> struct PickCfg<double> { typedef F64Cfg type; };
+
+static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+// Calls f(std::integral_constant<int, FEAT>) for the runtime feature mask.
+template <class F> static hipError_t with_feat(int feat, F&& f) {
+  switch (feat & 7) {
+    case 0: return f(std::integral_constant<int, 0>{});
+    case 1: return f(std::integral_constant<int, 1>{});
+    case 2: return f(std::integral_constant<int, 2>{});
+    case 3: return f(std::integral_constant<int, 3>{});
+    case 4: return f(std::integral_constant<int, 4>{});
+    case 5: return f(std::integral_constant<int, 5>{});
+    case 6: return f(std::integral_constant<int, 6>{});
+    default: return f(std::integral_constant<int, 7>{});
+  }
+}
+
+// As with_feat, plus std::bool_constant<aligned> for the generated loaders'
+// aligned chunk path (the launcher states the alignment condition).
+template <class F> static hipError_t with_feat_al(int feat, bool aligned, F&& f) {
+  return with_feat(feat, [&](auto fc) {
+    return aligned ? f(fc, std::true_type{}) : f(fc, std::false_type{});
+  });
+}
+
 
 }  // namespace pinv

@@ -16,29 +16,11 @@
 namespace pinv {
 
 // ---------------------------------------------------------------------------
-// generic tile driver
-// ---------------------------------------------------------------------------
-template <class Cfg>
-__device__ __forceinline__ typename Cfg::T* smem_base() {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  return reinterpret_cast<typename Cfg::T*>(smem_raw);
-}
-
-// Lower-triangular tile index -> (bi, bj), bi >= bj.
-__device__ __forceinline__ void tri_index(int t, int* bi, int* bj) {
-  int i = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
-  while ((i + 1) * (i + 2) / 2 <= t) ++i;
-  while (i * (i + 1) / 2 > t) --i;
-  *bi = i;
-  *bj = t - i * (i + 1) / 2;
-}
-
-// ---------------------------------------------------------------------------
 // Gram: G[n1][n2] = sum_m conj(E[m][n1]) E[m][n2] for tiles bi >= bj.
 // FP32 tiles flush their FP32 partial sums into the FP64 Gram every `flush`
 // rows so the long sum over M is carried in FP64.
 // ---------------------------------------------------------------------------
-template <class Cfg, int FEAT>
+template <class Cfg, int FEAT, bool AL>
 __global__ __launch_bounds__(256, 2) void k_gram(EncDev<typename Cfg::T> e, double* __restrict__ G,
                                               int flush) {
   typedef typename Cfg::T T;
@@ -46,8 +28,8 @@ __global__ __launch_bounds__(256, 2) void k_gram(EncDev<typename Cfg::T> e, doub
   int bi, bj;
   tri_index(blockIdx.x, &bi, &bj);
   const int N = e.N;
-  LoadGenCol<Cfg, Cfg::BM, Cfg::LDA, true, FEAT> la;
-  LoadGenCol<Cfg, Cfg::BN, Cfg::LDB, false, FEAT> lb;
+  LoadGenCol<Cfg, Cfg::BM, Cfg::LDA, true, FEAT, AL> la;
+  LoadGenCol<Cfg, Cfg::BN, Cfg::LDB, false, FEAT, AL> lb;
   la.init(e, bi * Cfg::BM);
   lb.init(e, bj * Cfg::BN);
   T* smem = smem_base<Cfg>();
@@ -85,7 +67,7 @@ __global__ __launch_bounds__(256, 2) void k_gram(EncDev<typename Cfg::T> e, doub
 // staged in LDS.  `e` must describe F (no coil table, C = 1, M = K); `coil`
 // is the [C][V] coil table (or null for one unit coil).
 // ---------------------------------------------------------------------------
-template <class Cfg, int FEAT>
+template <class Cfg, int FEAT, bool AL>
 __global__ __launch_bounds__(256, 2) void k_gram_shared(EncDev<typename Cfg::T> e,
                                                      const typename Cfg::T* __restrict__ coil,
                                                      int C, double* __restrict__ G) {
@@ -94,8 +76,8 @@ __global__ __launch_bounds__(256, 2) void k_gram_shared(EncDev<typename Cfg::T> 
   int bi, bj;
   tri_index(blockIdx.x, &bi, &bj);
   const int N = e.N, V = e.V;
-  LoadGenCol<Cfg, Cfg::BM, Cfg::LDA, true, FEAT> la;
-  LoadGenCol<Cfg, Cfg::BN, Cfg::LDB, false, FEAT> lb;
+  LoadGenCol<Cfg, Cfg::BM, Cfg::LDA, true, FEAT, AL> la;
+  LoadGenCol<Cfg, Cfg::BN, Cfg::LDB, false, FEAT, AL> lb;
   la.init(e, bi * Cfg::BM);
   lb.init(e, bj * Cfg::BN);
   T* smem = smem_base<Cfg>();
@@ -394,7 +376,7 @@ __global__ __launch_bounds__(256) void k_chol_trailing(double* __restrict__ A, d
 // ---------------------------------------------------------------------------
 // W = L^-1 E^H : W[i][m] = sum_{n <= i} Li[i][n] conj(E[m][n])
 // ---------------------------------------------------------------------------
-template <class Cfg, int FEAT>
+template <class Cfg, int FEAT, bool AL>
 __global__ __launch_bounds__(256) void k_trmm_w(EncDev<typename Cfg::T> e,
                                                 const typename Cfg::T* __restrict__ Li,
                                                 typename Cfg::T* __restrict__ W) {
@@ -408,7 +390,7 @@ __global__ __launch_bounds__(256) void k_trmm_w(EncDev<typename Cfg::T> e,
   la.ld = N;
   la.o0 = bi * Cfg::BM;
   la.oend = N;
-  LoadGenRow<Cfg, Cfg::BN, Cfg::LDB, true, FEAT> lb;
+  LoadGenRow<Cfg, Cfg::BN, Cfg::LDB, true, FEAT, AL> lb;
   lb.init(e, bj * Cfg::BN);
   AccTile<Cfg> acc;
   acc.zero();
@@ -494,7 +476,7 @@ __global__ __launch_bounds__(256) void k_apply(const ApplyBatch batch) {
 // Forward model D[f][m] = sum_n X[f][n] E[m][n]  (S = storage type of X).
 // With `sub` set the result is Dout = Din - E x (refinement residual).
 // ---------------------------------------------------------------------------
-template <class Cfg, int FEAT, typename SX, typename SD>
+template <class Cfg, int FEAT, typename SX, typename SD, bool AL>
 __global__ __launch_bounds__(256, 2) void k_forward(EncDev<typename Cfg::T> e, const SX* __restrict__ X,
                                                  int F, const SD* __restrict__ Din,
                                                  typename Cfg::T* __restrict__ Dout) {
@@ -508,7 +490,7 @@ __global__ __launch_bounds__(256, 2) void k_forward(EncDev<typename Cfg::T> e, c
   la.ld = N;
   la.o0 = bi * Cfg::BM;
   la.oend = F;
-  LoadGenRow<Cfg, Cfg::BN, Cfg::LDB, false, FEAT> lb;
+  LoadGenRow<Cfg, Cfg::BN, Cfg::LDB, false, FEAT, AL> lb;
   lb.init(e, bj * Cfg::BN);
   AccTile<Cfg> acc;
   acc.zero();
@@ -532,7 +514,7 @@ __global__ __launch_bounds__(256, 2) void k_forward(EncDev<typename Cfg::T> e, c
 
 // Adjoint Z[f][n] = sum_m D[f][m] conj(E[m][n]);  with X given, Z -= lam * X.
 // The result is written with storage type SO.
-template <class Cfg, int FEAT, typename SD, typename SX, typename SO>
+template <class Cfg, int FEAT, typename SD, typename SX, typename SO, bool AL>
 __global__ __launch_bounds__(256, 2) void k_adjoint(EncDev<typename Cfg::T> e, const SD* __restrict__ D,
                                                  int F, const SX* __restrict__ X, double lam,
                                                  SO* __restrict__ Z) {
@@ -546,7 +528,7 @@ __global__ __launch_bounds__(256, 2) void k_adjoint(EncDev<typename Cfg::T> e, c
   la.ld = M;
   la.o0 = bi * Cfg::BM;
   la.oend = F;
-  LoadGenCol<Cfg, Cfg::BN, Cfg::LDB, true, FEAT> lb;
+  LoadGenCol<Cfg, Cfg::BN, Cfg::LDB, true, FEAT, AL> lb;
   lb.init(e, bj * Cfg::BN);
   AccTile<Cfg> acc;
   acc.zero();
@@ -680,44 +662,6 @@ __global__ void k_to_f32(const double* __restrict__ in, float* __restrict__ out,
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
-typedef TileCfg<float, 128, 128, 8> F32Cfg;
-typedef TileCfg<double, 64, 64, 8> F64Cfg;
-
-template <typename T> struct GramCfgOf;     // square tiles for the triangular Gram grid
-template <> struct GramCfgOf<float> { typedef TileCfg<float, 128, 128, 8> type; };
-template <> struct GramCfgOf<double> { typedef TileCfg<double, 64, 64, 8> type; };
-
-template <class Cfg> static size_t smem_bytes() { return Cfg::SMEM_ELEMS * sizeof(typename Cfg::T); }
-
-typedef TileCfgB3<128, 128> B3Cfg;
-
-// Kernels whose LDS exceeds the default 64 KB limit need the attribute once.
-template <class K> static hipError_t allow_smem(K kernel, size_t bytes) {
-  if (bytes <= 65536) return hipSuccess;
-  return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)bytes);
-}
-
-template <typename T> struct PickCfg;
-template <> struct PickCfg<float> { typedef F32Cfg type; };
-template <> struct PickCfg<double> { typedef F64Cfg type; };
-
-static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
-
-// Calls f(std::integral_constant<int, FEAT>) for the runtime feature mask.
-template <class F> static hipError_t with_feat(int feat, F&& f) {
-  switch (feat & 7) {
-    case 0: return f(std::integral_constant<int, 0>{});
-    case 1: return f(std::integral_constant<int, 1>{});
-    case 2: return f(std::integral_constant<int, 2>{});
-    case 3: return f(std::integral_constant<int, 3>{});
-    case 4: return f(std::integral_constant<int, 4>{});
-    case 5: return f(std::integral_constant<int, 5>{});
-    case 6: return f(std::integral_constant<int, 6>{});
-    default: return f(std::integral_constant<int, 7>{});
-  }
-}
-
 template <typename T>
 hipError_t launch_gram(const EncDev<T>& e, double* G, int flush, hipStream_t s) {
   typedef typename GramCfgOf<T>::type Cfg;
@@ -725,9 +669,9 @@ hipError_t launch_gram(const EncDev<T>& e, double* G, int flush, hipStream_t s) 
   const int tiles = nb * (nb + 1) / 2;
   if (flush <= 0 || sizeof(T) == 8) flush = e.M;
   flush = ((flush + Cfg::BK - 1) / Cfg::BK) * Cfg::BK;
-  return with_feat(enc_features(e), [&](auto fc) {
-    hipLaunchKernelGGL((k_gram<Cfg, decltype(fc)::value>), dim3(tiles), dim3(256), smem_bytes<Cfg>(),
-                       s, e, G, flush);
+  return with_feat_al(enc_features(e), e.K % Cfg::BK == 0, [&](auto fc, auto al) {
+    hipLaunchKernelGGL((k_gram<Cfg, decltype(fc)::value, decltype(al)::value>), dim3(tiles),
+                       dim3(256), smem_bytes<Cfg>(), s, e, G, flush);
     return hipGetLastError();
   });
 }
@@ -741,9 +685,9 @@ hipError_t launch_gram_shared(const EncDev<T>& e, double* G, hipStream_t s) {
   f.M = e.K;
   const int nb = cdiv(e.N, Cfg::BM);
   const int tiles = nb * (nb + 1) / 2;
-  return with_feat(enc_features(f) & 3, [&](auto fc) {
-    hipLaunchKernelGGL((k_gram_shared<Cfg, decltype(fc)::value & 3>), dim3(tiles), dim3(256),
-                       smem_bytes<Cfg>(), s, f, e.coil, e.coil ? e.C : 1, G);
+  return with_feat_al(enc_features(f) & 3, f.K % Cfg::BK == 0, [&](auto fc, auto al) {
+    hipLaunchKernelGGL((k_gram_shared<Cfg, decltype(fc)::value & 3, decltype(al)::value>),
+                       dim3(tiles), dim3(256), smem_bytes<Cfg>(), s, f, e.coil, e.coil ? e.C : 1, G);
     return hipGetLastError();
   });
 }
@@ -771,9 +715,9 @@ template <typename T>
 hipError_t launch_trmm_w(const EncDev<T>& e, const T* Li, T* W, hipStream_t s) {
   typedef typename PickCfg<T>::type Cfg;
   const int tiles = cdiv(e.N, Cfg::BM) * cdiv(e.M, Cfg::BN);
-  return with_feat(enc_features(e), [&](auto fc) {
-    hipLaunchKernelGGL((k_trmm_w<Cfg, decltype(fc)::value>), dim3(tiles), dim3(256),
-                       smem_bytes<Cfg>(), s, e, Li, W);
+  return with_feat_al(enc_features(e), e.nx % Cfg::BK == 0, [&](auto fc, auto al) {
+    hipLaunchKernelGGL((k_trmm_w<Cfg, decltype(fc)::value, decltype(al)::value>), dim3(tiles),
+                       dim3(256), smem_bytes<Cfg>(), s, e, Li, W);
     return hipGetLastError();
   });
 }
@@ -806,9 +750,9 @@ hipError_t launch_forward(const EncDev<T>& e, const SX* X, int F, const SD* Din,
   typedef typename PickCfg<T>::type Cfg;
   const int tiles = cdiv(F, Cfg::BM) * cdiv(e.M, Cfg::BN);
   if (tiles == 0) return hipSuccess;
-  return with_feat(enc_features(e), [&](auto fc) {
-    hipLaunchKernelGGL((k_forward<Cfg, decltype(fc)::value, SX, SD>), dim3(tiles), dim3(256),
-                       smem_bytes<Cfg>(), s, e, X, F, Din, Dout);
+  return with_feat_al(enc_features(e), e.nx % Cfg::BK == 0, [&](auto fc, auto al) {
+    hipLaunchKernelGGL((k_forward<Cfg, decltype(fc)::value, SX, SD, decltype(al)::value>),
+                       dim3(tiles), dim3(256), smem_bytes<Cfg>(), s, e, X, F, Din, Dout);
     return hipGetLastError();
   });
 }
@@ -819,9 +763,9 @@ hipError_t launch_adjoint(const EncDev<T>& e, const SD* D, int F, const SX* X, d
   typedef typename PickCfg<T>::type Cfg;
   const int tiles = cdiv(F, Cfg::BM) * cdiv(e.N, Cfg::BN);
   if (tiles == 0) return hipSuccess;
-  return with_feat(enc_features(e), [&](auto fc) {
-    hipLaunchKernelGGL((k_adjoint<Cfg, decltype(fc)::value, SD, SX, SO>), dim3(tiles), dim3(256),
-                       smem_bytes<Cfg>(), s, e, D, F, X, lam, Z);
+  return with_feat_al(enc_features(e), e.K % Cfg::BK == 0, [&](auto fc, auto al) {
+    hipLaunchKernelGGL((k_adjoint<Cfg, decltype(fc)::value, SD, SX, SO, decltype(al)::value>),
+                       dim3(tiles), dim3(256), smem_bytes<Cfg>(), s, e, D, F, X, lam, Z);
     return hipGetLastError();
   });
 }
@@ -857,8 +801,8 @@ hipError_t launch_tri_frames(const T* Li, const T* In, int F, int N, SO* Out, hi
 hipError_t launch_trmm_w_b3(const EncDev<float>& e, const float* Li, float* W, hipStream_t s) {
   typedef B3Cfg Cfg;
   const int tiles = cdiv(e.N, Cfg::BM) * cdiv(e.M, Cfg::BN);
-  return with_feat(enc_features(e), [&](auto fc) {
-    auto kern = k_trmm_w<Cfg, decltype(fc)::value>;
+  return with_feat_al(enc_features(e), e.nx % Cfg::BK == 0, [&](auto fc, auto al) {
+    auto kern = k_trmm_w<Cfg, decltype(fc)::value, decltype(al)::value>;
     static bool ok = false;
     if (!ok) {
       hipError_t err = allow_smem(kern, smem_bytes<Cfg>());

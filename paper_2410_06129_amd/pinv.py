@@ -23,6 +23,7 @@ FLAG_KEEP_GRAM = 1
 FLAG_UNCACHED = 2
 FLAG_GRAM_FULL = 4
 BUF_R, BUF_LINV, BUF_GRAM = 0, 1, 2
+METRIC_DIAG, METRIC_FULL = 0, 1
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it first "
@@ -93,6 +94,8 @@ _sigs = {
     "pinv_apply": [_vp, _vp, _vp, ctypes.c_int64, _vp, ctypes.c_int32, _vp],
     "pinv_apply_grouped": [_vp, ctypes.c_int32, ctypes.POINTER(pinv_apply_item), ctypes.c_int32, _vp],
     "pinv_forward": [_vp, _vp, _vp, ctypes.c_int64, _vp, _vp],
+    "pinv_srf": [_vp, _vp, ctypes.c_int32, _vp, _vp],
+    "pinv_noise": [_vp, _vp, _vp, ctypes.c_int32, _vp, _vp],
     "pinv_plan_info_get": [_vp, ctypes.POINTER(pinv_plan_info)],
     "pinv_plan_buffers": [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp)],
     "pinv_plan_copy_buffer": [_vp, ctypes.c_int32, _vp, ctypes.c_size_t, _vp],
@@ -218,6 +221,24 @@ def pinv_apply_grouped(ctx: int, items: Sequence[tuple], refine_steps: int = 0, 
 def pinv_forward(ctx: int, plan: int, image, data, stream=None) -> None:
     _check(_lib.pinv_forward(ctx, plan, image.data_ptr(), image.shape[0], data.data_ptr(),
                              _stream_ptr(stream)), "pinv_forward")
+
+
+def pinv_srf(ctx: int, plan: int, out, mode: int = METRIC_DIAG, stream=None) -> None:
+    """SRF = R E (Eq. 9): its diagonal (mode METRIC_DIAG, out [N]) or the
+    full matrix (METRIC_FULL, out [N, N]); complex, in the plan's precision."""
+    _check(_lib.pinv_srf(ctx, plan, mode, out.data_ptr(), _stream_ptr(stream)), "pinv_srf")
+
+
+def pinv_noise(ctx: int, plan: int, out, coil_cov=None, mode: int = METRIC_DIAG,
+               stream=None) -> None:
+    """Noise matrix X = R (Psi_c kron I) R^H (Eq. 10): diag(X) (METRIC_DIAG, real
+    out [N]) or X (METRIC_FULL, complex out [N, N]).  coil_cov: [C, C] Hermitian
+    positive definite, or None for white noise."""
+    cov = None
+    if coil_cov is not None:
+        cov = np.ascontiguousarray(np.asarray(coil_cov, dtype=np.complex128))
+    _check(_lib.pinv_noise(ctx, plan, None if cov is None else cov.ctypes.data, mode,
+                           out.data_ptr(), _stream_ptr(stream)), "pinv_noise")
 
 
 def pinv_plan_info_get(plan: int) -> dict:

@@ -2,7 +2,12 @@
 times (FP32 plans, 1000/200 frames in one apply call, one refinement step).
 
 * 32x32 single-coil radial (N=1024, M=2048), FP64: every stage against the full
-  oracle (G within 1e-12 of max|G|, L^-1, R and the image within 1e-9).
+  oracle (G within 1e-12 of max|G|, L^-1, R, the image, the SRF matrix and the
+  white-noise matrix within 1e-9).
+* 64x64, 8 coils (FP32 plan, as the bench times the metrics): the SRF map lies
+  in (0, 1] up to the FP32 plan's error, the noise map is positive, and it
+  equals the diagonal of the noise matrix within M * u32 (FP32 summation of
+  M positive terms on the matrix side).
 * 64x64, 8 coils, M=32768, 1000 frames and the 5-species + B0 workload
   (N=5120, M=49152, 200 frames): sampled Gram entries against the oracle's
   explicit E columns, within M * 2^-53 of max diag (the worst-case rounding of
@@ -66,6 +71,15 @@ def test_config1_every_stage(P, ctx):
     assert rel(np.tril(Li.cpu().numpy()), Li_ref) < 1e-9
     assert rel(R.cpu().numpy(), R_ref) < 1e-9
     assert rel(x.cpu().numpy(), x_ref) < 1e-9
+    # image metrics (Eq. 9, Eq. 10) of the FP64 plan against the oracle's R
+    E = oracle.encoding_matrix(enc)
+    srf = torch.empty((N, N), dtype=torch.complex128, device="cuda")
+    X = torch.empty((N, N), dtype=torch.complex128, device="cuda")
+    P.pinv_srf(ctx, plan, srf, P.METRIC_FULL)
+    P.pinv_noise(ctx, plan, X, mode=P.METRIC_FULL)
+    torch.cuda.synchronize()
+    assert rel(srf.cpu().numpy(), oracle.srf_matrix(R_ref, E)) < 1e-9
+    assert rel(X.cpu().numpy(), oracle.noise_matrix(R_ref, np.eye(M))) < 1e-9
     P.pinv_plan_release(plan)
     # the FP32 path with one refinement step on the same input
     p32 = P.pinv_build(ctx, enc, w.rel_lambda, P.LAMBDA_REL_MEAN_DIAG, P.FP32, P.FLAG_UNCACHED)
@@ -128,3 +142,32 @@ def test_config2_full_size_sampled(P, ctx):
 def test_config4_full_size_sampled(P, ctx):
     w = synth.config4(F=1)
     _sampled_checks(P, ctx, w.enc, w.rel_lambda, 200, [0, 199], seed=4048)
+
+
+def test_config2_metric_properties(P, ctx):
+    w = synth.config2(F=1)
+    enc = w.enc
+    N = enc.N
+    p = P.pinv_build(ctx, enc, w.rel_lambda, P.LAMBDA_REL_MEAN_DIAG, P.FP32, P.FLAG_UNCACHED)
+    P.pinv_plan_wait(p)
+    try:
+        srf = torch.empty((N,), dtype=torch.complex64, device="cuda")
+        nd = torch.empty((N,), dtype=torch.float32, device="cuda")
+        X = torch.empty((N, N), dtype=torch.complex64, device="cuda")
+        P.pinv_srf(ctx, p, srf, P.METRIC_DIAG)
+        P.pinv_noise(ctx, p, nd, mode=P.METRIC_DIAG)
+        P.pinv_noise(ctx, p, X, mode=P.METRIC_FULL)
+        torch.cuda.synchronize()
+    finally:
+        P.pinv_plan_release(p)
+    s = srf.cpu().numpy()
+    assert np.all(s.real > 0) and np.all(s.real <= 1 + 1e-2)
+    assert np.max(np.abs(s.imag)) < 1e-2
+    n = nd.cpu().numpy().astype(np.float64)
+    Xd = np.diagonal(X.cpu().numpy()).real.astype(np.float64)
+    assert np.all(n > 0)
+    # the map sums |R[n][m]|^2 in FP64; the matrix diagonal is an FP32 MFMA sum
+    # of the same M positive terms, within the recursive-summation bound M * u32
+    tol = enc.M * 2.0 ** -24
+    assert abs(n.sum() - Xd.sum()) <= tol * n.sum()
+    assert np.max(np.abs(n - Xd) / n) <= tol

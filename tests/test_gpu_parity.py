@@ -1,7 +1,8 @@
 """Parity of the HIP path (through the C-ABI) with the FP64 oracle.
 
-Shapes span several 64/128 tiles with ragged tails (N = 480 and 288, M = 2100
-and 1000) and include the species and off-resonance factors.  Tolerances:
+Shapes span several 64/128 tiles with ragged tails (N = 480, 288, 640, 256;
+M = 2100, 1000, 1408, 1024), include the species and off-resonance factors, and
+cover both the general and the aligned chunk paths of the generated loaders.  Tolerances:
 
 * FP64 plans: every stage within 1e-9 relative (Frobenius) of the oracle; the
   FP64 forward error of the Cholesky route is ~kappa(G_l) * 1e-16 with
@@ -51,6 +52,11 @@ def frame_rel(a, b):
 CASES = {
     "ragged_c3": dict(seed=101, nx=24, ny=20, C=3, K=700, F=5),
     "species_b0": dict(seed=102, nx=12, ny=12, C=2, K=500, F=4, species=[0.0, 150.0], b0=True),
+    # nx and K multiples of 32: the generated loaders' aligned chunk paths (FP32,
+    # FP64 and BF16-split tiles), still ragged against the 64/128 tiles (N = 640)
+    "aligned_c2": dict(seed=103, nx=32, ny=20, C=2, K=704, F=3),
+    "aligned_species_b0": dict(seed=104, nx=16, ny=8, C=2, K=512, F=3, species=[0.0, 150.0],
+                               b0=True),
 }
 
 _oracle_cache = {}

@@ -292,6 +292,34 @@ def test_noise_matrix_white_noise():
     assert rel(X, Gi - lam * Gi @ Gi) < 1e-11
 
 
+def random_hpd(C, rng):
+    a = rng.standard_normal((C, C)) + 1j * rng.standard_normal((C, C))
+    return a @ a.conj().T + C * np.eye(C)
+
+
+def test_noise_matrix_coil_covariance():
+    """Coil-correlated noise, Psi = Psi_c (x) I_K (Eq. 10): X equals
+    G_l^-1 (E^H Psi E) G_l^-1, with E^H Psi E summed over coil blocks
+    sum_{c,c'} Psi_c[c,c'] E_c^H E_c' and the inverse from numpy."""
+    enc = tiny_enc(seed=22, C=3, K=30)
+    lam = 0.25
+    E = oracle.encoding_matrix(enc)
+    K, C = enc.K, enc.C
+    psi_c = random_hpd(C, np.random.default_rng(7))
+    X = oracle.noise_matrix(oracle.Build(enc, lam=lam).recon_matrix(),
+                            oracle.coil_noise_covariance(psi_c, K))
+    blocks = [E[c * K:(c + 1) * K] for c in range(C)]
+    EPE = sum(psi_c[c, c2] * blocks[c].conj().T @ blocks[c2] for c in range(C) for c2 in range(C))
+    Gi = np.linalg.inv(E.conj().T @ E + lam * np.eye(E.shape[1]))
+    assert rel(X, Gi @ EPE @ Gi) < 1e-11
+    d = np.diagonal(X)
+    assert np.all(d.real > 0) and np.max(np.abs(d.imag)) < 1e-12 * np.max(d.real)
+    # Psi_c = I reduces to the white-noise case
+    Xw = oracle.noise_matrix(oracle.Build(enc, lam=lam).recon_matrix(),
+                             oracle.coil_noise_covariance(np.eye(C), K))
+    assert rel(Xw, Gi - lam * Gi @ Gi) < 1e-11
+
+
 # --- Cholesky failure and determinism ------------------------------------------
 
 def test_not_pd_without_regularisation_when_underdetermined():
