@@ -5,7 +5,10 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <type_traits>
+#include <utility>
 
 #include "pinv_device.h"
 
@@ -16,7 +19,11 @@ struct ApplyItemDev {
   const void* R;   // [N][M]
   void* X;         // [F][N]
   int F, N, M;
-  int tile0;       // first tile of this item in the grouped launch
+  int tile0;       // first tile of this item in the grouped launch (set by the launcher)
+  int ntile;       // tiles of one split (set by the launcher)
+  int splits;      // contraction splits over M (set by the launcher from F, N, M alone)
+  int kchunk;      // rows of M per split
+  void* work;      // [splits][F][N] partial sums when splits > 1
 };
 
 constexpr int kMaxGroup = 32;
@@ -111,6 +118,68 @@ template <class F> static hipError_t with_feat(int feat, F&& f) {
     case 5: return f(std::integral_constant<int, 5>{});
     case 6: return f(std::integral_constant<int, 6>{});
     default: return f(std::integral_constant<int, 7>{});
+  }
+}
+
+// Workgroups of `kernel` resident on the current device at once (occupancy
+// per CU times the CU count), cached per kernel and device.
+template <class K> static int resident_blocks(K kernel, int threads, size_t smem) {
+  static std::mutex mu;
+  static std::map<std::pair<const void*, int>, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1;
+  const auto key = std::make_pair((const void*)kernel, dev);
+  {
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+  }
+  int cus = 0, per = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, smem) != hipSuccess)
+    return 1;
+  const int r = std::max(1, per) * std::max(1, cus);
+  std::lock_guard<std::mutex> g(mu);
+  cache[key] = r;
+  return r;
+}
+
+// Split factor s of a contraction of `kchunks` chunks over a grid of `tiles`
+// workgroups with `slots` resident at once: the s (1..4, at least 16 chunks
+// per split) with the fewest full-length rounds ceil(tiles * s / slots) / s.
+static inline int pick_split(long tiles, int slots, int kchunks) {
+  int best = 1;
+  double best_cost = (double)((tiles + slots - 1) / slots);
+  for (int s = 2; s <= 4 && kchunks / s >= 16; ++s) {
+    const double cost = (double)((tiles * s + slots - 1) / slots) / s;
+    if (cost < best_cost - 1e-9) {
+      best = s;
+      best_cost = cost;
+    }
+  }
+  return best;
+}
+
+// Z = sum_s work[s] (in split order) - lam X, elementwise over n complex values.
+template <typename T, typename SX, typename SO>
+__global__ __launch_bounds__(256) void k_split_reduce(const T* __restrict__ work, int splits,
+                                                      int64_t n, const SX* __restrict__ X,
+                                                      double lam, SO* __restrict__ Z) {
+  const cx<T>* W = reinterpret_cast<const cx<T>*>(work);
+  const cx<SX>* Xc = reinterpret_cast<const cx<SX>*>(X);
+  cx<SO>* O = reinterpret_cast<cx<SO>*>(Z);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    T zr = W[i].re, zi = W[i].im;
+    for (int s = 1; s < splits; ++s) {
+      zr += W[(int64_t)s * n + i].re;
+      zi += W[(int64_t)s * n + i].im;
+    }
+    if (Xc) {
+      zr -= T(lam) * T(Xc[i].re);
+      zi -= T(lam) * T(Xc[i].im);
+    }
+    O[i] = cx<SO>{SO(zr), SO(zi)};
   }
 }
 

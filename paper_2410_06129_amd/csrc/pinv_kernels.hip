@@ -437,6 +437,10 @@ __global__ __launch_bounds__(256) void k_trmm_r(const typename Cfg::T* __restric
 // ---------------------------------------------------------------------------
 // Apply (grouped): for each item, X[f][n] = sum_m D[f][m] R[n][m]
 // ---------------------------------------------------------------------------
+// An item whose tile grid alone would leave the GPU partly idle is split over
+// M (the split depends only on the item's F, N and M, so a result is the same
+// alone and in any group); its splits write partial tiles to item.work and
+// k_apply_reduce adds them in split order.
 template <class Cfg>
 __global__ __launch_bounds__(256) void k_apply(const ApplyBatch batch) {
   typedef typename Cfg::T T;
@@ -448,9 +452,12 @@ __global__ __launch_bounds__(256) void k_apply(const ApplyBatch batch) {
     if (batch.it[mid].tile0 <= t) lo = mid; else hi = mid - 1;
   }
   const ApplyItemDev it = batch.it[lo];
-  const int u = t - it.tile0;
+  const int u0 = t - it.tile0;
+  const int split = u0 / it.ntile;
+  const int u = u0 - split * it.ntile;
   const int nbj = (it.N + Cfg::BN - 1) / Cfg::BN;
   const int bi = u / nbj, bj = u % nbj;
+  const int k0 = split * it.kchunk, k1 = min(it.M, k0 + it.kchunk);
   LoadDenseKC<Cfg, Cfg::BM, Cfg::LDA, T, false> la;   // D[f][m]
   la.p = reinterpret_cast<const cx<T>*>(it.D);
   la.ld = it.M;
@@ -463,13 +470,35 @@ __global__ __launch_bounds__(256) void k_apply(const ApplyBatch batch) {
   lb.oend = it.N;
   AccTile<Cfg> acc;
   acc.zero();
-  mainloop<Cfg>(la, lb, 0, it.M, acc, smem_base<Cfg>());
-  cx<T>* O = reinterpret_cast<cx<T>*>(it.X);
+  mainloop<Cfg>(la, lb, k0, k1, acc, smem_base<Cfg>());
+  cx<T>* O = it.splits > 1
+                 ? reinterpret_cast<cx<T>*>(it.work) + (size_t)split * it.F * it.N
+                 : reinterpret_cast<cx<T>*>(it.X);
   const int r0 = bi * Cfg::BM, c0 = bj * Cfg::BN;
   acc_foreach<Cfg>(acc, [&](int r, int c, T re, T im) {
     const int row = r0 + r, col = c0 + c;
     if (row < it.F && col < it.N) O[(size_t)row * it.N + col] = cx<T>{re, im};
   });
+}
+
+// X = sum_s work[s] in split order, for the split items of a grouped apply
+// (blockIdx.y = item).
+template <typename T>
+__global__ __launch_bounds__(256) void k_apply_reduce(const ApplyBatch batch) {
+  const ApplyItemDev& it = batch.it[blockIdx.y];
+  if (it.splits <= 1) return;
+  const int64_t n = (int64_t)it.F * it.N;
+  const cx<T>* W = reinterpret_cast<const cx<T>*>(it.work);
+  cx<T>* X = reinterpret_cast<cx<T>*>(it.X);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    T zr = W[i].re, zi = W[i].im;
+    for (int s = 1; s < it.splits; ++s) {
+      zr += W[(int64_t)s * n + i].re;
+      zi += W[(int64_t)s * n + i].im;
+    }
+    X[i] = cx<T>{zr, zi};
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -514,15 +543,22 @@ __global__ __launch_bounds__(256, 2) void k_forward(EncDev<typename Cfg::T> e, c
 
 // Adjoint Z[f][n] = sum_m D[f][m] conj(E[m][n]);  with X given, Z -= lam * X.
 // The result is written with storage type SO.
+// With a split of the contraction (ksplit > 1, `work` non-null) workgroup
+// blockIdx = split * tiles + tile sums rows m in [split*kchunk, +kchunk) and
+// stores its raw partial tile to work[split]; k_split_reduce then adds the
+// partials in split order (deterministic) and applies the -lam x term.
 template <class Cfg, int FEAT, typename SD, typename SX, typename SO, bool AL>
 __global__ __launch_bounds__(256, 2) void k_adjoint(EncDev<typename Cfg::T> e, const SD* __restrict__ D,
                                                  int F, const SX* __restrict__ X, double lam,
-                                                 SO* __restrict__ Z) {
+                                                 SO* __restrict__ Z, int tiles, int kchunk,
+                                                 typename Cfg::T* __restrict__ work) {
   typedef typename Cfg::T T;
   const int N = e.N, M = e.M;
   const int nbj = (N + Cfg::BN - 1) / Cfg::BN;
-  const int t = blockIdx.x;
+  const int split = blockIdx.x / tiles;
+  const int t = blockIdx.x - split * tiles;
   const int bi = t / nbj, bj = t % nbj;
+  const int k0 = split * kchunk, k1 = min(M, k0 + kchunk);
   LoadDenseKC<Cfg, Cfg::BM, Cfg::LDA, SD, false> la;
   la.p = reinterpret_cast<const cx<SD>*>(D);
   la.ld = M;
@@ -532,10 +568,18 @@ __global__ __launch_bounds__(256, 2) void k_adjoint(EncDev<typename Cfg::T> e, c
   lb.init(e, bj * Cfg::BN);
   AccTile<Cfg> acc;
   acc.zero();
-  mainloop<Cfg>(la, lb, 0, M, acc, smem_base<Cfg>());
+  mainloop<Cfg>(la, lb, k0, k1, acc, smem_base<Cfg>());
+  const int r0 = bi * Cfg::BM, c0 = bj * Cfg::BN;
+  if (work) {
+    cx<T>* W = reinterpret_cast<cx<T>*>(work) + (size_t)split * F * N;
+    acc_foreach<Cfg>(acc, [&](int r, int c, T re, T im) {
+      const int row = r0 + r, col = c0 + c;
+      if (row < F && col < N) W[(size_t)row * N + col] = cx<T>{re, im};
+    });
+    return;
+  }
   cx<SO>* O = reinterpret_cast<cx<SO>*>(Z);
   const cx<SX>* Xc = reinterpret_cast<const cx<SX>*>(X);
-  const int r0 = bi * Cfg::BM, c0 = bj * Cfg::BN;
   acc_foreach<Cfg>(acc, [&](int r, int c, T re, T im) {
     const int row = r0 + r, col = c0 + c;
     if (row < F && col < N) {
@@ -736,12 +780,56 @@ int apply_tiles(int F, int N) {
   return cdiv(F, Cfg::BM) * cdiv(N, Cfg::BN);
 }
 
+// Grouped apply with per-item contraction splits: sets each item's split,
+// tile range and partial-sum workspace, runs the tiles, then the reduction.
+template <class Cfg>
+static hipError_t run_apply(ApplyBatch b, hipStream_t s) {
+  typedef typename Cfg::T T;
+  const int slots = resident_blocks(k_apply<Cfg>, 256, smem_bytes<Cfg>());
+  int tiles = 0, nsplit = 0;
+  size_t work_elems = 0;
+  for (int i = 0; i < b.n; ++i) {
+    ApplyItemDev& it = b.it[i];
+    const int nchunks = cdiv(it.M, Cfg::BK);
+    it.ntile = cdiv(it.F, Cfg::BM) * cdiv(it.N, Cfg::BN);
+    it.splits = pick_split(it.ntile, slots, nchunks);
+    it.kchunk = cdiv(nchunks, it.splits) * Cfg::BK;
+    it.tile0 = tiles;
+    it.work = nullptr;
+    tiles += it.ntile * it.splits;
+    if (it.splits > 1) {
+      work_elems += (size_t)it.splits * it.F * it.N;
+      ++nsplit;
+    }
+  }
+  if (tiles <= 0) return hipSuccess;
+  void* work = nullptr;
+  if (nsplit) {
+    hipError_t err = hipMallocAsync(&work, work_elems * 2 * sizeof(T), s);
+    if (err != hipSuccess) return err;
+    size_t off = 0;
+    for (int i = 0; i < b.n; ++i)
+      if (b.it[i].splits > 1) {
+        b.it[i].work = (cx<T>*)work + off;
+        off += (size_t)b.it[i].splits * b.it[i].F * b.it[i].N;
+      }
+  }
+  hipLaunchKernelGGL(k_apply<Cfg>, dim3(tiles), dim3(256), smem_bytes<Cfg>(), s, b);
+  hipError_t err = hipGetLastError();
+  if (nsplit) {
+    if (err == hipSuccess) {
+      hipLaunchKernelGGL(k_apply_reduce<T>, dim3(1024, b.n), dim3(256), 0, s, b);
+      err = hipGetLastError();
+    }
+    const hipError_t ferr = hipFreeAsync(work, s);
+    if (err == hipSuccess) err = ferr;
+  }
+  return err;
+}
+
 template <typename T>
-hipError_t launch_apply(const ApplyBatch& b, int total_tiles, hipStream_t s) {
-  typedef typename PickCfg<T>::type Cfg;
-  if (total_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_apply<Cfg>, dim3(total_tiles), dim3(256), smem_bytes<Cfg>(), s, b);
-  return hipGetLastError();
+hipError_t launch_apply(const ApplyBatch& b, int, hipStream_t s) {
+  return run_apply<typename PickCfg<T>::type>(b, s);
 }
 
 template <typename T, typename SX, typename SD>
@@ -764,9 +852,32 @@ hipError_t launch_adjoint(const EncDev<T>& e, const SD* D, int F, const SX* X, d
   const int tiles = cdiv(F, Cfg::BM) * cdiv(e.N, Cfg::BN);
   if (tiles == 0) return hipSuccess;
   return with_feat_al(enc_features(e), e.K % Cfg::BK == 0, [&](auto fc, auto al) {
-    hipLaunchKernelGGL((k_adjoint<Cfg, decltype(fc)::value, SD, SX, SO, decltype(al)::value>),
-                       dim3(tiles), dim3(256), smem_bytes<Cfg>(), s, e, D, F, X, lam, Z);
-    return hipGetLastError();
+    auto kern = k_adjoint<Cfg, decltype(fc)::value, SD, SX, SO, decltype(al)::value>;
+    // split the M contraction when one pass of the tile grid would leave the
+    // GPU partly idle (the grid's last round is what the split fills)
+    const int nchunks = cdiv(e.M, Cfg::BK);
+    const int splits = pick_split(tiles, resident_blocks(kern, 256, smem_bytes<Cfg>()), nchunks);
+    if (splits == 1) {
+      hipLaunchKernelGGL(kern, dim3(tiles), dim3(256), smem_bytes<Cfg>(), s, e, D, F, X, lam, Z,
+                         tiles, nchunks * Cfg::BK, (T*)nullptr);
+      return hipGetLastError();
+    }
+    const int kchunk = cdiv(nchunks, splits) * Cfg::BK;
+    const int64_t n = (int64_t)F * e.N;
+    void* work = nullptr;
+    hipError_t err = hipMallocAsync(&work, (size_t)splits * n * 2 * sizeof(T), s);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(kern, dim3(tiles * splits), dim3(256), smem_bytes<Cfg>(), s, e, D, F, X, lam,
+                       Z, tiles, kchunk, (T*)work);
+    err = hipGetLastError();
+    if (err == hipSuccess) {
+      const int blocks = (int)std::min<int64_t>((n + 255) / 256, 1 << 16);
+      hipLaunchKernelGGL((k_split_reduce<T, SX, SO>), dim3(blocks), dim3(256), 0, s,
+                         (const T*)work, splits, n, X, lam, Z);
+      err = hipGetLastError();
+    }
+    const hipError_t ferr = hipFreeAsync(work, s);
+    return err != hipSuccess ? err : ferr;
   });
 }
 
@@ -829,17 +940,15 @@ hipError_t launch_trmm_r_b3(const float* Li, const float* W, float* R, int N, in
 
 int apply_tiles_b3(int F, int N) { return cdiv(F, B3Cfg::BM) * cdiv(N, B3Cfg::BN); }
 
-hipError_t launch_apply_b3(const ApplyBatch& b, int total_tiles, hipStream_t s) {
+hipError_t launch_apply_b3(const ApplyBatch& b, int, hipStream_t s) {
   typedef B3Cfg Cfg;
-  if (total_tiles <= 0) return hipSuccess;
   static bool ok = false;
   if (!ok) {
     hipError_t err = allow_smem(k_apply<Cfg>, smem_bytes<Cfg>());
     if (err != hipSuccess) return err;
     ok = true;
   }
-  hipLaunchKernelGGL(k_apply<Cfg>, dim3(total_tiles), dim3(256), smem_bytes<Cfg>(), s, b);
-  return hipGetLastError();
+  return run_apply<Cfg>(b, s);
 }
 
 hipError_t launch_to_f32(const double* in, float* out, size_t n_complex, hipStream_t s) {

@@ -165,11 +165,16 @@ __global__ __launch_bounds__(256) void k_noise_diag(const T* __restrict__ R, int
 // tile is used).
 template <class Cfg>
 __global__ __launch_bounds__(256, 2) void k_noise_full(const typename Cfg::T* __restrict__ A, int N,
-                                                       int M, typename Cfg::T* __restrict__ X) {
+                                                       int M, typename Cfg::T* __restrict__ X,
+                                                       int tiles, int kchunk) {
   typedef typename Cfg::T T;
   static_assert(Cfg::BM == Cfg::BN, "square tiles");
+  // with a split of the M contraction, X points at work[split] (partial sums)
+  const int split = blockIdx.x / tiles;
   int bi, bj;
-  tri_index(blockIdx.x, &bi, &bj);
+  tri_index(blockIdx.x - split * tiles, &bi, &bj);
+  X += (size_t)split * N * N * 2;
+  const int k0 = split * kchunk, k1 = min(M, k0 + kchunk);
   LoadDenseKC<Cfg, Cfg::BM, Cfg::LDA, T, false> la;   // A[n][m]
   la.p = reinterpret_cast<const cx<T>*>(A);
   la.ld = M;
@@ -182,7 +187,7 @@ __global__ __launch_bounds__(256, 2) void k_noise_full(const typename Cfg::T* __
   lb.oend = N;
   AccTile<Cfg> acc;
   acc.zero();
-  mainloop<Cfg>(la, lb, 0, M, acc, smem_base<Cfg>());
+  mainloop<Cfg>(la, lb, k0, k1, acc, smem_base<Cfg>());
   cx<T>* O = reinterpret_cast<cx<T>*>(X);
   const int r0 = bi * Cfg::BM, c0 = bj * Cfg::BN;
   acc_foreach<Cfg>(acc, [&](int r, int c, T re, T im) {
@@ -241,11 +246,33 @@ template <typename T>
 hipError_t launch_noise_full(const T* A, int N, int M, T* X, hipStream_t s) {
   typedef typename PickCfg<T>::type Cfg;
   const int nb = cdiv(N, Cfg::BM);
+  const int tiles = nb * (nb + 1) / 2;
   hipError_t err = allow_smem(k_noise_full<Cfg>, smem_bytes<Cfg>());
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(k_noise_full<Cfg>, dim3(nb * (nb + 1) / 2), dim3(256), smem_bytes<Cfg>(), s, A,
-                     N, M, X);
-  return hipGetLastError();
+  const int nchunks = cdiv(M, Cfg::BK);
+  const int splits = pick_split(tiles, resident_blocks(k_noise_full<Cfg>, 256, smem_bytes<Cfg>()),
+                                nchunks);
+  const int kchunk = cdiv(nchunks, splits) * Cfg::BK;
+  if (splits == 1) {
+    hipLaunchKernelGGL(k_noise_full<Cfg>, dim3(tiles), dim3(256), smem_bytes<Cfg>(), s, A, N, M, X,
+                       tiles, kchunk);
+    return hipGetLastError();
+  }
+  const int64_t n = (int64_t)N * N;
+  void* work = nullptr;
+  err = hipMallocAsync(&work, (size_t)splits * n * 2 * sizeof(T), s);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k_noise_full<Cfg>, dim3(tiles * splits), dim3(256), smem_bytes<Cfg>(), s, A, N,
+                     M, (T*)work, tiles, kchunk);
+  err = hipGetLastError();
+  if (err == hipSuccess) {
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 1 << 16);
+    hipLaunchKernelGGL((k_split_reduce<T, T, T>), dim3(blocks), dim3(256), 0, s, (const T*)work,
+                       splits, n, (const T*)nullptr, 0.0, X);
+    err = hipGetLastError();
+  }
+  const hipError_t ferr = hipFreeAsync(work, s);
+  return err != hipSuccess ? err : ferr;
 }
 
 template hipError_t launch_srf_diag<float>(const EncDev<float>&, const float*, float*, hipStream_t);
