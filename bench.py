@@ -397,6 +397,9 @@ def main():
     from paper_2410_06129_amd import synth
 
     torch.cuda.init()
+    # a dedicated (default-priority) stream: the library and torch's own work are
+    # issued on it, and HIP events time it
+    torch.cuda.set_stream(torch.cuda.Stream(device=torch.device("cuda:0")))
     if args.precision_study:
         res = precision_study(args)
         print(json.dumps({"metric": "relative image error vs plain FP64 GPU path", "unit": "rel",

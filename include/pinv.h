@@ -258,8 +258,11 @@ typedef struct {
 typedef struct {
   const pinv_encoding *enc;   /* host; copied at submit */
   pinv_build_opts opts;       /* build options of the request's plan */
-  const void *data;           /* device [F][M], caller-owned until completion */
-  void *image;                /* device [F][N], caller-owned until completion */
+  const void *data;           /* device [F][M], caller-owned until completion; written
+                                 and complete before submit (the server's streams are not
+                                 ordered after the caller's streams) */
+  void *image;                /* device [F][N], caller-owned until completion; no work of
+                                 the caller may still be pending on it at submit */
   int64_t F;                  /* frames >= 0 */
   int32_t refine_steps;       /* 0..4, as in pinv_apply */
   int32_t reserved;           /* 0 */

@@ -67,6 +67,8 @@ struct pinv_plan {
 
 struct pinv_context {
   int device = 0;
+  hipStream_t aux = nullptr;      // look-ahead stream, kept off the last CUs (blocking)
+  hipStream_t aux_nb = nullptr;   // look-ahead stream for builds on the null stream
   size_t budget = 0;
   size_t used = 0;
   std::mutex mu;
@@ -311,6 +313,28 @@ const char* pinv_status_string(pinv_status s) {
 
 const char* pinv_last_error(void) { return g_last_error.c_str(); }
 
+// The factorisation's look-ahead stream runs the bulk of each trailing update
+// beside the next diagonal block, panel and look-ahead tiles.  It is kept off
+// the last 32 CUs, so the one-workgroup diagonal kernel and the short panel
+// launches on the build stream always find free CUs instead of queueing behind
+// the bulk update's workgroups.  A CU-masked stream is a blocking stream, which
+// the null stream would serialise against, so builds issued on the null stream
+// use a second, unmasked non-blocking stream instead.
+static bool create_aux_streams(int device, pinv_context* c) {
+  if (hipStreamCreateWithFlags(&c->aux_nb, hipStreamNonBlocking) != hipSuccess) return false;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+      cus >= 128) {
+    std::vector<uint32_t> mask((cus + 31) / 32, 0u);
+    for (int i = 0; i < cus - 32; ++i) mask[i / 32] |= 1u << (i % 32);
+    if (hipExtStreamCreateWithCUMask(&c->aux, (uint32_t)mask.size(), mask.data()) == hipSuccess)
+      return true;
+    (void)hipGetLastError();
+  }
+  c->aux = c->aux_nb;
+  return true;
+}
+
 pinv_status pinv_context_create(int device, size_t budget, pinv_context** out) {
   if (!out) return fail(PINV_ERR_INVALID, "out is NULL");
   int n = 0;
@@ -322,6 +346,10 @@ pinv_status pinv_context_create(int device, size_t budget, pinv_context** out) {
   pinv_context* c = new pinv_context();
   c->device = device;
   c->budget = budget ? budget : (size_t)(0.9 * (double)fr);
+  if (!create_aux_streams(device, c)) {
+    delete c;
+    return fail(PINV_ERR_DEVICE, "cannot create the auxiliary stream");
+  }
   *out = c;
   return PINV_OK;
 }
@@ -339,6 +367,8 @@ pinv_status pinv_context_destroy(pinv_context* c) {
     c->lru.clear();
     c->cache.clear();
   }
+  if (c->aux && c->aux != c->aux_nb) (void)hipStreamDestroy(c->aux);
+  if (c->aux_nb) (void)hipStreamDestroy(c->aux_nb);
   delete c;
   return PINV_OK;
 }
@@ -491,7 +521,8 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
   BCHK(launch_herm_fill((double*)p->gram, d.N, s));
   BCHK(hipEventRecord(p->ev[1], s));
   // 2. shift + blocked Cholesky with L^-1 (a4), FP64
-  BCHK(launch_cholinv((double*)G, (double*)L64, d.N, lam, p->info, s));
+  BCHK(launch_cholinv((double*)G, (double*)L64, d.N, lam, p->info, s,
+                      s ? p->ctx->aux : p->ctx->aux_nb));
   if (!f64) BCHK(launch_to_f32((const double*)L64, (float*)p->Linv, N * N, s));
   BCHK(hipEventRecord(p->ev[2], s));
   // 3. W = L^-1 E^H, R = L^-H W (a5)

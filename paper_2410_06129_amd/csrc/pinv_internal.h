@@ -34,7 +34,8 @@ struct ApplyBatch {     // passed by value as a kernel argument
 
 template <typename T> hipError_t launch_gram(const EncDev<T>& e, double* G, int flush, hipStream_t s);
 template <typename T> hipError_t launch_gram_shared(const EncDev<T>& e, double* G, hipStream_t s);
-hipError_t launch_cholinv(double* A, double* Li, int N, double lam, int* info, hipStream_t s);
+hipError_t launch_cholinv(double* A, double* Li, int N, double lam, int* info, hipStream_t s,
+                          hipStream_t aux);
 template <typename T> hipError_t launch_trmm_w(const EncDev<T>& e, const T* Li, T* W, hipStream_t s);
 template <typename T>
 hipError_t launch_trmm_r(const T* Li, const T* W, T* R, int N, int M, hipStream_t s);

@@ -309,34 +309,50 @@ __global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ A, doub
   });
 }
 
-// Step k trailing update.  Tiles [0, nherk): A_ij -= L_ik L_jk^H for
-// k < j <= i; tiles [nherk, ...): B_ij -= L_ik Y_kj for i > k, j <= k.
+// Step k trailing update: A_ij -= L_ik L_jk^H for k < j <= i ("herk" tiles)
+// and B_ij -= L_ik Y_kj for i > k, j <= k (inverse tiles).  `part` selects
+// the tiles of one launch:
+//   0  all of them;
+//   1  the look-ahead set: block column k+1 of A and block row k+1 of B, all
+//      that step k+1's diagonal block and panel read;
+//   2  the rest (A columns >= k+2, B rows >= k+2), which can run beside
+//      step k+1's diagonal and panel kernels.
 // The accumulators start from -(old tile), loaded together with the first
 // operand chunk, and the tile is stored negated: no read after the products.
 __global__ __launch_bounds__(256) void k_chol_trailing(double* __restrict__ A, double* __restrict__ Li,
-                                                       int N, int k, const int* __restrict__ info) {
+                                                       int N, int k, const int* __restrict__ info,
+                                                       int part) {
   if (*info) return;
   typedef CholCfg Cfg;
   const int nb = 64;
   const int nblk = (N + nb - 1) / nb;
   const int rem = nblk - k - 1;
-  const int nherk = rem * (rem + 1) / 2;
   const int t = blockIdx.x;
-  const bool herk = t < nherk;
   const cx<double>* Ac = reinterpret_cast<const cx<double>*>(A);
   const cx<double>* Lc = reinterpret_cast<const cx<double>*>(Li);
   double* smem = smem_base<Cfg>();
   const int kw = min(N, (k + 1) * nb) - k * nb;
+  bool herk;
   int r0, c0;
-  if (herk) {
-    int ti, tj;
-    tri_index(t, &ti, &tj);
-    r0 = (k + 1 + ti) * nb;
-    c0 = (k + 1 + tj) * nb;
+  if (part == 1) {
+    herk = t < rem;
+    r0 = herk ? (k + 1 + t) * nb : (k + 1) * nb;
+    c0 = herk ? (k + 1) * nb : (t - rem) * nb;
   } else {
-    const int u = t - nherk;
-    r0 = (k + 1 + u / (k + 1)) * nb;
-    c0 = (u % (k + 1)) * nb;
+    const int first = part == 2 ? k + 2 : k + 1;   // first trailing block row/column
+    const int r = nblk - first;
+    const int nherk = r * (r + 1) / 2;
+    herk = t < nherk;
+    if (herk) {
+      int ti, tj;
+      tri_index(t, &ti, &tj);
+      r0 = (first + ti) * nb;
+      c0 = (first + tj) * nb;
+    } else {
+      const int u = t - nherk;
+      r0 = (first + u / (k + 1)) * nb;
+      c0 = (u % (k + 1)) * nb;
+    }
   }
   cx<double>* O = reinterpret_cast<cx<double>*>(herk ? A : Li);
   AccTile<Cfg> acc;
@@ -736,22 +752,68 @@ hipError_t launch_gram_shared(const EncDev<T>& e, double* G, hipStream_t s) {
   });
 }
 
-hipError_t launch_cholinv(double* A, double* Li, int N, double lam, int* info, hipStream_t s) {
+// With an auxiliary stream `aux` the factorisation looks ahead one step: on
+// s, step k's look-ahead tiles (part 1) then step k+1's diagonal block and
+// panel; on aux, step k's remaining tiles (part 2) beside them.  Events order
+// part 2 of step k after step k's panel, and step k+1's part 1 after step k's
+// part 2 (which updated the blocks it reads and writes).  Without aux, one
+// launch per step does all trailing tiles on s.
+hipError_t launch_cholinv(double* A, double* Li, int N, double lam, int* info, hipStream_t s,
+                          hipStream_t aux) {
   const int nb = 64;
   const int nblk = cdiv(N, nb);
   const size_t diag_smem = kDiagSmem;
-  for (int k = 0; k < nblk; ++k) {
-    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(kDiagThreads), diag_smem, s, A, Li, N, nb, k, lam, info);
+  const size_t sm = smem_bytes<CholCfg>();
+  hipEvent_t ev_panel = nullptr, ev_rest = nullptr;
+  if (aux) {
+    hipError_t err = hipEventCreateWithFlags(&ev_panel, hipEventDisableTiming);
+    if (err == hipSuccess) err = hipEventCreateWithFlags(&ev_rest, hipEventDisableTiming);
+    if (err != hipSuccess) {
+      if (ev_panel) (void)hipEventDestroy(ev_panel);
+      return err;
+    }
+  }
+  hipError_t err = hipSuccess;
+  bool rest_pending = false;
+  for (int k = 0; k < nblk && err == hipSuccess; ++k) {
+    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(kDiagThreads), diag_smem, s, A, Li, N, nb, k, lam,
+                       info);
     const int ntiles = nblk - 1;   // (nblk-k-1) panel + k inverse blocks
     if (ntiles > 0)
-      hipLaunchKernelGGL(k_chol_panel, dim3(ntiles), dim3(256), smem_bytes<CholCfg>(), s, A, Li, N,
-                         k, (const int*)info);
+      hipLaunchKernelGGL(k_chol_panel, dim3(ntiles), dim3(256), sm, s, A, Li, N, k, (const int*)info);
     const int rem = nblk - k - 1;
-    const int tt = rem * (rem + 1) / 2 + rem * (k + 1);
-    if (tt > 0)
-      hipLaunchKernelGGL(k_chol_trailing, dim3(tt), dim3(256), smem_bytes<CholCfg>(), s, A, Li, N,
-                         k, (const int*)info);
+    if (rem <= 0) break;
+    if (!aux) {
+      hipLaunchKernelGGL(k_chol_trailing, dim3(rem * (rem + 1) / 2 + rem * (k + 1)), dim3(256), sm, s,
+                         A, Li, N, k, (const int*)info, 0);
+      err = hipGetLastError();
+      continue;
+    }
+    // part 2 of step k (aux) after step k's panel and after part 2 of step k-1
+    if ((err = hipEventRecord(ev_panel, s)) != hipSuccess) break;
+    if ((err = hipStreamWaitEvent(aux, ev_panel, 0)) != hipSuccess) break;
+    // part 1 of step k (s) after part 2 of step k-1
+    if (rest_pending && (err = hipStreamWaitEvent(s, ev_rest, 0)) != hipSuccess) break;
+    hipLaunchKernelGGL(k_chol_trailing, dim3(rem + (k + 1)), dim3(256), sm, s, A, Li, N, k,
+                       (const int*)info, 1);
+    const int r2 = rem - 1;
+    if (r2 > 0) {
+      hipLaunchKernelGGL(k_chol_trailing, dim3(r2 * (r2 + 1) / 2 + r2 * (k + 1)), dim3(256), sm, aux,
+                         A, Li, N, k, (const int*)info, 2);
+      if ((err = hipEventRecord(ev_rest, aux)) != hipSuccess) break;
+      rest_pending = true;
+    } else {
+      rest_pending = false;
+    }
+    err = hipGetLastError();
   }
+  if (aux) {
+    // everything after the factorisation on s sees the last part-2 updates
+    if (err == hipSuccess && rest_pending) err = hipStreamWaitEvent(s, ev_rest, 0);
+    (void)hipEventDestroy(ev_panel);
+    (void)hipEventDestroy(ev_rest);
+  }
+  if (err != hipSuccess) return err;
   return hipGetLastError();
 }
 

@@ -190,6 +190,29 @@ def test_bf16x3_path_matches_oracle(P, ctx, name):
     P.pinv_plan_release(plan)
 
 
+@pytest.mark.parametrize("name", ["ragged_c3", "aligned_c2"])
+def test_factor_on_a_side_stream(P, ctx, name):
+    """A build issued on a non-default stream runs the factorisation's bulk
+    trailing updates on the library's CU-restricted look-ahead stream (builds on
+    the null stream use an unrestricted one); L^-1 and R must match the oracle
+    either way."""
+    o = oracle_case(name)
+    enc, N, M = o["w"].enc, o["w"].enc.N, o["w"].enc.M
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        plan = P.pinv_build(ctx, enc, o["w"].rel_lambda, P.LAMBDA_REL_MEAN_DIAG, P.FP64,
+                            P.FLAG_UNCACHED, stream=side)
+        P.pinv_plan_wait(plan)
+        Li = torch.empty((N, N), dtype=torch.complex128, device="cuda")
+        R = torch.empty((N, M), dtype=torch.complex128, device="cuda")
+        P.pinv_plan_copy_buffer(plan, P.BUF_LINV, Li, stream=side)
+        P.pinv_plan_copy_buffer(plan, P.BUF_R, R, stream=side)
+        side.synchronize()
+    P.pinv_plan_release(plan)
+    assert rel(np.tril(Li.cpu().numpy()), o["Linv"]) < 1e-9
+    assert rel(R.cpu().numpy(), o["R"]) < 1e-9
+
+
 def test_single_coil_spiral_factor(P, ctx):
     """Single-coil spirals of the serving mix (K = 2N): the Gram is numerically
     rank deficient and its diagonal blocks are ill-conditioned (a regression case

@@ -42,6 +42,7 @@ def test_mix_equals_alone(P, prec, refine):
             g = torch.Generator(device="cuda").manual_seed(1000 + t)
             d = torch.randn((F, encs[e].M), dtype=cdt, device="cuda", generator=g)
             x = torch.zeros((F, encs[e].N), dtype=cdt, device="cuda")
+            torch.cuda.synchronize()   # inputs ready before the server's streams see them
             P.pinv_server_submit(srv, encs[e], d, x, 1e-3, P.LAMBDA_REL_MEAN_DIAG, p,
                                  refine_steps=refine, tag=t)
             reqs.append((e, d, x))
@@ -86,6 +87,7 @@ def test_budget_forces_eviction(P):
         for t, e in enumerate([0, 1, 2, 0, 1, 2]):
             d = torch.ones((2, encs[e].M), dtype=torch.complex64, device="cuda")
             x = torch.zeros((2, encs[e].N), dtype=torch.complex64, device="cuda")
+            torch.cuda.synchronize()
             keep.append((d, x))
             P.pinv_server_submit(srv, encs[e], d, x, 1e-3, prec=P.FP32, tag=t)
         assert P.pinv_server_drain(srv, 120.0) == P.OK
