@@ -68,23 +68,36 @@ template <typename T> inline int enc_features(const EncDev<T>& e) {
 // ---------------------------------------------------------------------------
 // Tile configuration
 // ---------------------------------------------------------------------------
-template <typename T_, int BM_, int BN_, int BK_> struct TileCfg {
+// M3: complex products with three real products (Gauss):
+//   t1 = ar br, t2 = ai bi, t3 = (ar + ai)(br + bi);  re = t1 - t2, im = t3 - t1 - t2
+// (a third LDS plane holds re + im of each operand value); otherwise four
+// real products (4M).
+template <typename T_, int BM_, int BN_, int BK_, bool M3_ = false> struct TileCfg {
   typedef T_ T;
   static constexpr int BM = BM_, BN = BN_, BK = BK_;
+  static constexpr bool M3 = M3_;
+  static constexpr int PLANES = M3 ? 3 : 2;
   static constexpr int NT = 256;                 // 4 wavefronts in a 2x2 grid
   static constexpr int WTM = BM / 2, WTN = BN / 2;
   static constexpr int MB = WTM / 16, NB = WTN / 16;
   static constexpr int PAD = sizeof(T) == 4 ? 16 : 8;
   static constexpr int LDA = BM + PAD, LDB = BN + PAD;
   static constexpr int A_PLANE = BK * LDA, B_PLANE = BK * LDB;
-  static constexpr int STAGE = 2 * A_PLANE + 2 * B_PLANE;   // elements of T
+  static constexpr int STAGE = PLANES * A_PLANE + PLANES * B_PLANE;   // elements of T
   static constexpr int SMEM_ELEMS = 2 * STAGE;
   static_assert(BM % 32 == 0 && BN % 32 == 0 && BK % 4 == 0, "tile shape");
 };
 
+template <class Cfg, class = void> struct IsM3 { static constexpr bool value = false; };
+template <class Cfg> struct IsM3<Cfg, decltype((void)Cfg::M3)> { static constexpr bool value = Cfg::M3; };
+
+// 4M tiles accumulate re and im directly; M3 tiles accumulate t1 in `re`,
+// t3 in `im` and t2 in `t2`, and acc_foreach forms re = t1 - t2 and
+// im = t3 - t1 - t2 element by element (no second copy of the tile).
 template <class Cfg> struct AccTile {
   typename Acc<typename Cfg::T>::type re[Cfg::MB][Cfg::NB];
   typename Acc<typename Cfg::T>::type im[Cfg::MB][Cfg::NB];
+  typename Acc<typename Cfg::T>::type t2[Cfg::MB][Cfg::NB];
   __device__ __forceinline__ void zero() {
 #pragma unroll
     for (int a = 0; a < Cfg::MB; ++a)
@@ -92,9 +105,11 @@ template <class Cfg> struct AccTile {
       for (int b = 0; b < Cfg::NB; ++b) {
         re[a][b] = typename Acc<typename Cfg::T>::type{0, 0, 0, 0};
         im[a][b] = typename Acc<typename Cfg::T>::type{0, 0, 0, 0};
+        if constexpr (IsM3<Cfg>::value) t2[a][b] = typename Acc<typename Cfg::T>::type{0, 0, 0, 0};
       }
   }
 };
+
 
 // One BK chunk of MFMAs from LDS.  sA = [re plane | im plane] of op(A) as
 // [k][m], sB likewise [k][n].  Lane l supplies A[m = l%16][k = l/16] and
@@ -112,8 +127,35 @@ __device__ __forceinline__ void tile_compute(const typename Cfg::T* __restrict__
   const int lr = lane & 15, lk = lane >> 4;
 #pragma unroll
   for (int kk = 0; kk < Cfg::BK / 4; ++kk) {
-    T ar[Cfg::MB], ai[Cfg::MB], nai[Cfg::MB], br[Cfg::NB], bi[Cfg::NB];
     const int krow = kk * 4 + lk;
+    if constexpr (IsM3<Cfg>::value) {
+      T ar[Cfg::MB], ai[Cfg::MB], as[Cfg::MB], br[Cfg::NB], bi[Cfg::NB], bs[Cfg::NB];
+#pragma unroll
+      for (int a = 0; a < Cfg::MB; ++a) {
+        const int off = krow * Cfg::LDA + wr * Cfg::WTM + a * 16 + lr;
+        ar[a] = sA[off];
+        ai[a] = sA[Cfg::A_PLANE + off];
+        as[a] = sA[2 * Cfg::A_PLANE + off];
+      }
+#pragma unroll
+      for (int b = 0; b < Cfg::NB; ++b) {
+        const int off = krow * Cfg::LDB + wc * Cfg::WTN + b * 16 + lr;
+        br[b] = sB[off];
+        bi[b] = sB[Cfg::B_PLANE + off];
+        bs[b] = sB[2 * Cfg::B_PLANE + off];
+      }
+#pragma unroll
+      for (int a = 0; a < Cfg::MB; ++a)
+#pragma unroll
+        for (int b = 0; b < Cfg::NB; ++b) {
+          acc.re[a][b] = mfma4(ar[a], br[b], acc.re[a][b]);
+          acc.t2[a][b] = mfma4(ai[a], bi[b], acc.t2[a][b]);
+          acc.im[a][b] = mfma4(as[a], bs[b], acc.im[a][b]);
+        }
+      between(kk);
+      continue;
+    }
+    T ar[Cfg::MB], ai[Cfg::MB], nai[Cfg::MB], br[Cfg::NB], bi[Cfg::NB];
 #pragma unroll
     for (int a = 0; a < Cfg::MB; ++a) {
       const int off = krow * Cfg::LDA + wr * Cfg::WTM + a * 16 + lr;
@@ -176,7 +218,7 @@ __device__ __forceinline__ void mainloop(LA& la, LB& lb, int kbeg, int kend, Acc
     lb.finish(q, STEPS);
   }
   la.store(stage0);
-  lb.store(stage0 + 2 * Cfg::A_PLANE);
+  lb.store(stage0 + Cfg::PLANES * Cfg::A_PLANE);
   __syncthreads();
   int c = 0;
   do {
@@ -187,13 +229,13 @@ __device__ __forceinline__ void mainloop(LA& la, LB& lb, int kbeg, int kend, Acc
       la.fetch(kbeg + (c + 1) * Cfg::BK, kend);
       lb.fetch(kbeg + (c + 1) * Cfg::BK, kend);
     }
-    tile_compute<Cfg>(cur, cur + 2 * Cfg::A_PLANE, acc, [&](int kk) {
+    tile_compute<Cfg>(cur, cur + Cfg::PLANES * Cfg::A_PLANE, acc, [&](int kk) {
       la.finish(kk, STEPS);
       lb.finish(kk, STEPS);
     });
     if (more) {
       la.store(nxt);
-      lb.store(nxt + 2 * Cfg::A_PLANE);
+      lb.store(nxt + Cfg::PLANES * Cfg::A_PLANE);
     }
     __syncthreads();
   } while (++c < nch);
@@ -351,7 +393,15 @@ __device__ __forceinline__ void acc_foreach(const AccTile<Cfg>& acc, F&& f) {
       for (int r = 0; r < 4; ++r) {
         const int row = wr * Cfg::WTM + a * 16 + (f64 ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r);
         const int col = wc * Cfg::WTN + b * 16 + (lane & 15);
-        f(row, col, acc.re[a][b][r], acc.im[a][b][r]);
+        if constexpr (IsM3<Cfg>::value) {
+          const typename Cfg::T t1 = acc.re[a][b][r], t3 = acc.im[a][b][r], t2 = acc.t2[a][b][r];
+          f(row, col, t1 - t2, t3 - t1 - t2);
+          // keep the scheduler from hoisting every accumulator read ahead of the
+          // stores (that would need a VGPR copy of the whole tile)
+          __builtin_amdgcn_sched_barrier(0);
+        } else {
+          f(row, col, acc.re[a][b][r], acc.im[a][b][r]);
+        }
       }
 }
 
@@ -359,6 +409,7 @@ __device__ __forceinline__ void acc_foreach(const AccTile<Cfg>& acc, F&& f) {
 // existing output values).
 template <class Cfg, class F>
 __device__ __forceinline__ void acc_foreach_mut(AccTile<Cfg>& acc, F&& f) {
+  static_assert(!IsM3<Cfg>::value, "4M tiles only: the walk reads and writes re and im directly");
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
   const int wr = wid >> 1, wc = wid & 1;
@@ -441,6 +492,7 @@ struct LoadDenseKC {
       dense_value<T, S, CONJ>(v[j], ok[j], re, im);
       s[kk * LD + o] = re;
       s[Cfg::BK * LD + kk * LD + o] = im;
+      if constexpr (IsM3<Cfg>::value) s[2 * Cfg::BK * LD + kk * LD + o] = re + im;
     }
   }
 };
@@ -490,6 +542,7 @@ struct LoadDenseOC {
       dense_value<T, S, CONJ>(v[j], ok[j], re, im);
       s[kk * LD + o] = re;
       s[Cfg::BK * LD + kk * LD + o] = im;
+      if constexpr (IsM3<Cfg>::value) s[2 * Cfg::BK * LD + kk * LD + o] = re + im;
     }
   }
 };
@@ -623,6 +676,7 @@ struct LoadGenCol {
       const int kk = threadIdx.x / OUTER + j * KPP;
       s_[kk * LD + o] = re[j];
       s_[Cfg::BK * LD + kk * LD + o] = im[j];
+      if constexpr (IsM3<Cfg>::value) s_[2 * Cfg::BK * LD + kk * LD + o] = re[j] + im[j];
     }
   }
 };
@@ -730,6 +784,7 @@ struct LoadGenRow {
       const int kk = threadIdx.x / OUTER + j * KPP;
       s_[kk * LD + o] = re[j];
       s_[Cfg::BK * LD + kk * LD + o] = im[j];
+      if constexpr (IsM3<Cfg>::value) s_[2 * Cfg::BK * LD + kk * LD + o] = re[j] + im[j];
     }
   }
 };
