@@ -350,6 +350,16 @@ pinv_status pinv_context_create(int device, size_t budget, pinv_context** out) {
     delete c;
     return fail(PINV_ERR_DEVICE, "cannot create the auxiliary stream");
   }
+  // Keep freed stream-ordered allocations (build workspaces, scratch) mapped
+  // across synchronisations: the pool's default release threshold of 0 hands
+  // them back at every synchronising call, and the next build then pays for
+  // mapping W afresh inside its first kernel.  Memory goes back to the device
+  // only through the explicit trims (pinv_plan_wait, pinv_context_trim).
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+    uint64_t keep = UINT64_MAX;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+  }
   *out = c;
   return PINV_OK;
 }

@@ -84,11 +84,13 @@ __device__ __forceinline__ void tri_index(int t, int* bi, int* bj) {
   *bj = t - i * (i + 1) / 2;
 }
 
-typedef TileCfg<float, 128, 128, 8, true> F32Cfg;   // 3M complex products
+// FP32 tiles: 3M complex products on 128x64 tiles (a 64x32 tile per wave keeps
+// the three accumulator sets at 96 registers, so two workgroups fit per CU)
+typedef TileCfg<float, 128, 64, 8, true> F32Cfg;
 typedef TileCfg<double, 64, 64, 8> F64Cfg;
 
 template <typename T> struct GramCfgOf;     // square tiles for the triangular Gram grid
-template <> struct GramCfgOf<float> { typedef TileCfg<float, 128, 128, 8, true> type; };
+template <> struct GramCfgOf<float> { typedef TileCfg<float, 128, 128, 8, false> type; };
 template <> struct GramCfgOf<double> { typedef TileCfg<double, 64, 64, 8> type; };
 
 template <class Cfg> static size_t smem_bytes() { return Cfg::SMEM_ELEMS * sizeof(typename Cfg::T); }

@@ -244,7 +244,7 @@ hipError_t launch_noise_diag(const T* R, int N, int K, int C, const T* Lc, T* ou
 
 template <typename T>
 hipError_t launch_noise_full(const T* A, int N, int M, T* X, hipStream_t s) {
-  typedef typename PickCfg<T>::type Cfg;
+  typedef typename GramCfgOf<T>::type Cfg;   // square tiles for the triangular grid
   const int nb = cdiv(N, Cfg::BM);
   const int tiles = nb * (nb + 1) / 2;
   hipError_t err = allow_smem(k_noise_full<Cfg>, smem_bytes<Cfg>());
