@@ -88,10 +88,14 @@ __device__ __forceinline__ void tri_index(int t, int* bi, int* bj) {
 // the three accumulator sets at 96 registers, so two workgroups fit per CU)
 typedef TileCfg<float, 128, 64, 8, true> F32Cfg;
 typedef TileCfg<double, 64, 64, 8> F64Cfg;
+// FP64 tiles with 3M products, for the FP64 work of FP32-class plans (Gram,
+// refinement residuals), where 3M's rounding (a few units of 2^-53 more in the
+// imaginary part) is far below what that work needs
+typedef TileCfg<double, 64, 64, 8, true> F64Cfg3;
 
 template <typename T> struct GramCfgOf;     // square tiles for the triangular Gram grid
 template <> struct GramCfgOf<float> { typedef TileCfg<float, 128, 128, 8, false> type; };
-template <> struct GramCfgOf<double> { typedef TileCfg<double, 64, 64, 8> type; };
+template <> struct GramCfgOf<double> { typedef F64Cfg3 type; };
 
 template <class Cfg> static size_t smem_bytes() { return Cfg::SMEM_ELEMS * sizeof(typename Cfg::T); }
 

@@ -917,7 +917,7 @@ hipError_t launch_forward(const EncDev<T>& e, const SX* X, int F, const SD* Din,
 template <typename T, typename SD, typename SX, typename SO>
 hipError_t launch_adjoint(const EncDev<T>& e, const SD* D, int F, const SX* X, double lam, SO* Z,
                           hipStream_t s) {
-  typedef typename PickCfg<T>::type Cfg;
+  typedef typename std::conditional<std::is_same<T, double>::value, F64Cfg3, F32Cfg>::type Cfg;
   const int tiles = cdiv(F, Cfg::BM) * cdiv(e.N, Cfg::BN);
   if (tiles == 0) return hipSuccess;
   return with_feat_al(enc_features(e), e.K % Cfg::BK == 0, [&](auto fc, auto al) {
@@ -953,7 +953,7 @@ hipError_t launch_adjoint(const EncDev<T>& e, const SD* D, int F, const SX* X, d
 template <typename SX, typename SO>
 hipError_t launch_resid(const double* G, const double* b, const SX* X, int F, int N, double lam,
                         SO* Out, hipStream_t s) {
-  typedef F64Cfg Cfg;
+  typedef F64Cfg3 Cfg;
   const int tiles = cdiv(F, Cfg::BM) * cdiv(N, Cfg::BN);
   if (tiles == 0) return hipSuccess;
   hipLaunchKernelGGL((k_resid<Cfg, SX, SO>), dim3(tiles), dim3(256), smem_bytes<Cfg>(), s, G, b, X,
