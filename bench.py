@@ -542,6 +542,8 @@ def main():
     ms_step = 1e3 * dt / args.steps
     value = (flops_build + flops_apply) / (ms_step * 1e-3) / 1e12
     build_ms = float(st_mean.sum())
+    for i, st in enumerate(stages):
+        log(f"step {i} stage ms (gram, chol+inv, W, R): {np.round(st, 3)}")
     log(f"stage ms (gram, chol+inv, W, R): {np.round(st_mean, 3)}; step {ms_step:.2f} ms")
 
     # --- BF16-split plan on the same workload ---

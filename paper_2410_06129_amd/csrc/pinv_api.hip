@@ -69,6 +69,7 @@ struct pinv_context {
   int device = 0;
   hipStream_t aux = nullptr;      // look-ahead stream, kept off the last CUs (blocking)
   hipStream_t aux_nb = nullptr;   // look-ahead stream for builds on the null stream
+  hipMemPool_t build_pool = nullptr;   // build workspaces (Gram, FP64 factor, W)
   size_t budget = 0;
   size_t used = 0;
   std::mutex mu;
@@ -356,10 +357,23 @@ pinv_status pinv_context_create(int device, size_t budget, pinv_context** out) {
   // mapping W afresh inside its first kernel.  Memory goes back to the device
   // only through the explicit trims (pinv_plan_wait, pinv_context_trim).
   hipMemPool_t pool;
-  if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
-    uint64_t keep = UINT64_MAX;
+  uint64_t keep = UINT64_MAX;
+  if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess)
     (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
-  }
+  // Build workspaces come from a pool of their own, so the per-call scratch of
+  // applies and refinement (default pool) cannot split a freed multi-GB
+  // workspace and force the next build to map a new one.
+  hipMemPoolProps props;
+  memset(&props, 0, sizeof(props));
+  props.allocType = hipMemAllocationTypePinned;
+  props.handleTypes = hipMemHandleTypeNone;
+  props.location.type = hipMemLocationTypeDevice;
+  props.location.id = device;
+  props.maxSize = tot;
+  if (hipMemPoolCreate(&c->build_pool, &props) == hipSuccess)
+    (void)hipMemPoolSetAttribute(c->build_pool, hipMemPoolAttrReleaseThreshold, &keep);
+  else
+    c->build_pool = nullptr, (void)hipGetLastError();
   *out = c;
   return PINV_OK;
 }
@@ -377,6 +391,7 @@ pinv_status pinv_context_destroy(pinv_context* c) {
     c->lru.clear();
     c->cache.clear();
   }
+  if (c->build_pool) (void)hipMemPoolDestroy(c->build_pool);
   if (c->aux && c->aux != c->aux_nb) (void)hipStreamDestroy(c->aux);
   if (c->aux_nb) (void)hipStreamDestroy(c->aux_nb);
   delete c;
@@ -425,6 +440,37 @@ pinv_status pinv_encoding_key(const pinv_encoding* e, const pinv_build_opts* o, 
   if (key) *key = k;
   if (plan_bytes) *plan_bytes = plan_footprint(d, o->prec);
   return PINV_OK;
+}
+
+// Return memory that stream-ordered frees (build workspace, refinement
+// scratch) left in the device's default pool, so that allocations outside the
+// pool (plan buffers, the caller's tensors) can use it.  Only done when less
+// than a quarter of the device is free: re-mapping a freed multi-GB workspace
+// costs the next build milliseconds inside its first kernel.
+static void trim_pool(pinv_context* c, bool force = false) {
+  size_t fr = 0, tot = 0;
+  if (!force && hipMemGetInfo(&fr, &tot) == hipSuccess && fr >= tot / 4) return;
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, c->device) == hipSuccess) (void)hipMemPoolTrimTo(pool, 0);
+  if (c->build_pool) (void)hipMemPoolTrimTo(c->build_pool, 0);
+}
+
+// A build workspace, stream-ordered on s, from the context's build pool.
+static hipError_t workspace_alloc(void** ptr, size_t bytes, pinv_context* c, hipStream_t s) {
+  return c->build_pool ? hipMallocFromPoolAsync(ptr, bytes, c->build_pool, s)
+                       : hipMallocAsync(ptr, bytes, s);
+}
+
+// A plan buffer (outside the stream-ordered pool); when the device is out of
+// memory, freed pool memory is handed back and the allocation tried once more.
+static hipError_t plan_malloc(void** ptr, size_t bytes, pinv_context* c) {
+  hipError_t e = hipMalloc(ptr, bytes);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    trim_pool(c, true);
+    e = hipMalloc(ptr, bytes);
+  }
+  return e;
 }
 
 pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build_opts* o,
@@ -506,18 +552,18 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
   for (auto& ev : p->ev) BCHK(hipEventCreate(&ev));
   BCHK(hipMalloc((void**)&p->info, sizeof(int)));
   BCHK(hipMemsetAsync(p->info, 0, sizeof(int), s));
-  BCHK(hipMalloc(&p->R, cs * N * M));
-  BCHK(hipMalloc(&p->Linv, cs * N * N));
-  BCHK(hipMalloc(&p->gram, 16 * N * N));
+  BCHK(plan_malloc(&p->R, cs * N * M, c));
+  BCHK(plan_malloc(&p->Linv, cs * N * N, c));
+  BCHK(plan_malloc(&p->gram, 16 * N * N, c));
   p->gram_exact = !(gram_full && !f64);
-  BCHK(hipMallocAsync(&G, 16 * N * N, s));
+  BCHK(workspace_alloc(&G, 16 * N * N, c, s));
   if (f64) {
     L64 = p->Linv;
   } else {
-    BCHK(hipMallocAsync(&L64, 16 * N * N, s));
+    BCHK(workspace_alloc(&L64, 16 * N * N, c, s));
   }
   BCHK(hipMemsetAsync(L64, 0, 16 * N * N, s));
-  BCHK(hipMallocAsync(&W, cs * N * M, s));
+  BCHK(workspace_alloc(&W, cs * N * M, c, s));
 
   // 1. Gram (a3) with E generated per tile (a2)
   BCHK(hipEventRecord(p->ev[0], s));
@@ -577,16 +623,9 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
   return PINV_OK;
 }
 
-// Return memory that stream-ordered frees (build workspace, refinement
-// scratch) left in the device's default pool, so later allocations can use it.
-static void trim_pool(int device) {
-  hipMemPool_t pool;
-  if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) (void)hipMemPoolTrimTo(pool, 0);
-}
-
 extern "C" pinv_status pinv_context_trim(pinv_context* c) {
   if (!c) return fail(PINV_ERR_INVALID, "context is NULL");
-  trim_pool(c->device);
+  trim_pool(c, true);
   return PINV_OK;
 }
 
@@ -595,7 +634,7 @@ pinv_status pinv_plan_wait(pinv_plan* p) {
   if (!p->waited) {
     HIPCHK(hipSetDevice(p->ctx->device));
     HIPCHK(hipEventSynchronize(p->ev[4]));
-    trim_pool(p->ctx->device);
+    trim_pool(p->ctx);
     HIPCHK(hipMemcpy(&p->info_host, p->info, sizeof(int), hipMemcpyDeviceToHost));
     for (int i = 0; i < 4; ++i) HIPCHK(hipEventElapsedTime(&p->stage_ms[i], p->ev[i], p->ev[i + 1]));
     p->status = p->info_host ? PINV_ERR_NOT_PD : PINV_OK;
