@@ -55,7 +55,7 @@ struct pinv_plan {
   void* gram = nullptr;      // full Hermitian E^H E in FP64 (refinement residuals)
   bool gram_exact = true;    // false when the Gram was formed over M rows in FP32
   int* info = nullptr;
-  std::vector<void*> host_stage;   // pinned staging of the tables, freed once the build is done
+  bool pooled = false;             // device buffers from the context's plan pool
   size_t bytes = 0;
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   bool waited = false;
@@ -70,6 +70,13 @@ struct pinv_context {
   hipStream_t aux = nullptr;      // look-ahead stream, kept off the last CUs (blocking)
   hipStream_t aux_nb = nullptr;   // look-ahead stream for builds on the null stream
   hipMemPool_t build_pool = nullptr;   // build workspaces (Gram, FP64 factor, W)
+  hipMemPool_t plan_pool = nullptr;    // plan buffers (R, L^-1, Gram, tables)
+  // pinned staging for table uploads, reused by every build of the context:
+  // stage_ev marks the completion of the last copies out of it
+  std::mutex stage_mu;
+  void* stage = nullptr;
+  size_t stage_bytes = 0;
+  hipEvent_t stage_ev = nullptr;
   size_t budget = 0;
   size_t used = 0;
   std::mutex mu;
@@ -200,10 +207,20 @@ void build_tables(const pinv_encoding* e, const Dims& d, HostTables* h) {
   }
 }
 
-// Upload tables as type T into one device allocation; fill the EncDev view.
+// Bytes of the tables as type T in one device buffer (each table 256-aligned).
 template <typename T>
-pinv_status upload_tables(const HostTables& h, const Dims& d, hipStream_t s, void** dev,
-                          EncDev<T>* ev, std::vector<void*>* host_keep) {
+size_t tables_bytes(const HostTables& h) {
+  size_t tot = 0;
+  for (size_t n : {h.px.size(), h.py.size(), h.q.size(), h.coil.size(), h.b0.size(), h.t.size()})
+    tot += align256(n * sizeof(T));
+  return tot;
+}
+
+// Converts the tables to T into `host` (pinned staging, tables_bytes<T> long)
+// and copies them to `dev` on s.
+template <typename T>
+pinv_status upload_tables(const HostTables& h, const Dims& d, hipStream_t s, void* host, void* dev,
+                          EncDev<T>* ev) {
   const size_t n_px = h.px.size(), n_py = h.py.size(), n_q = h.q.size(), n_c = h.coil.size(),
                n_b = h.b0.size(), n_t = h.t.size();
   size_t off[6], tot = 0;
@@ -212,17 +229,13 @@ pinv_status upload_tables(const HostTables& h, const Dims& d, hipStream_t s, voi
     off[i] = tot;
     tot += align256(ns[i] * sizeof(T));
   }
-  void* host = nullptr;
-  HIPCHK(hipHostMalloc(&host, tot, hipHostMallocDefault));
-  host_keep->push_back(host);
   const std::vector<double>* src[6] = {&h.px, &h.py, &h.q, &h.coil, &h.b0, &h.t};
   for (int i = 0; i < 6; ++i) {
     T* dst = (T*)((char*)host + off[i]);
     for (size_t j = 0; j < ns[i]; ++j) dst[j] = (T)(*src[i])[j];
   }
-  HIPCHK(hipMalloc(dev, tot));
-  HIPCHK(hipMemcpyAsync(*dev, host, tot, hipMemcpyHostToDevice, s));
-  char* b = (char*)*dev;
+  HIPCHK(hipMemcpyAsync(dev, host, tot, hipMemcpyHostToDevice, s));
+  char* b = (char*)dev;
   ev->px = (const T*)(b + off[0]);
   ev->py = (const T*)(b + off[1]);
   ev->q = n_q ? (const T*)(b + off[2]) : nullptr;
@@ -240,16 +253,18 @@ pinv_status upload_tables(const HostTables& h, const Dims& d, hipStream_t s, voi
   return PINV_OK;
 }
 
-void free_host_stage(pinv_plan* p) {
-  for (void* h : p->host_stage) (void)hipHostFree(h);
-  p->host_stage.clear();
-}
-
 void free_plan_memory(pinv_plan* p) {
   if (p->ev[4]) (void)hipEventSynchronize(p->ev[4]);
-  free_host_stage(p);
-  for (void* q : {p->tab32, p->tab64, p->R, p->Linv, p->gram, (void*)p->info})
-    if (q) (void)hipFree(q);
+  if (p->pooled) {
+    // the buffers may still be read by work on any stream: wait for the device
+    // (as a non-pooled free would), then return them to the plan pool
+    (void)hipDeviceSynchronize();
+    for (void* q : {p->tab32, p->tab64, p->R, p->Linv, p->gram, (void*)p->info})
+      if (q) (void)hipFreeAsync(q, nullptr);
+  } else {
+    for (void* q : {p->tab32, p->tab64, p->R, p->Linv, p->gram, (void*)p->info})
+      if (q) (void)hipFree(q);
+  }
   for (auto& e : p->ev)
     if (e) (void)hipEventDestroy(e);
 }
@@ -374,6 +389,14 @@ pinv_status pinv_context_create(int device, size_t budget, pinv_context** out) {
     (void)hipMemPoolSetAttribute(c->build_pool, hipMemPoolAttrReleaseThreshold, &keep);
   else
     c->build_pool = nullptr, (void)hipGetLastError();
+  if (hipMemPoolCreate(&c->plan_pool, &props) == hipSuccess)
+    (void)hipMemPoolSetAttribute(c->plan_pool, hipMemPoolAttrReleaseThreshold, &keep);
+  else
+    c->plan_pool = nullptr, (void)hipGetLastError();
+  if (hipEventCreateWithFlags(&c->stage_ev, hipEventDisableTiming) != hipSuccess) {
+    pinv_context_destroy(c);
+    return fail(PINV_ERR_DEVICE, "cannot create the staging event");
+  }
   *out = c;
   return PINV_OK;
 }
@@ -392,6 +415,9 @@ pinv_status pinv_context_destroy(pinv_context* c) {
     c->cache.clear();
   }
   if (c->build_pool) (void)hipMemPoolDestroy(c->build_pool);
+  if (c->plan_pool) (void)hipMemPoolDestroy(c->plan_pool);
+  if (c->stage_ev) (void)hipEventDestroy(c->stage_ev);
+  if (c->stage) (void)hipHostFree(c->stage);
   if (c->aux && c->aux != c->aux_nb) (void)hipStreamDestroy(c->aux);
   if (c->aux_nb) (void)hipStreamDestroy(c->aux_nb);
   delete c;
@@ -453,6 +479,7 @@ static void trim_pool(pinv_context* c, bool force = false) {
   hipMemPool_t pool;
   if (hipDeviceGetDefaultMemPool(&pool, c->device) == hipSuccess) (void)hipMemPoolTrimTo(pool, 0);
   if (c->build_pool) (void)hipMemPoolTrimTo(c->build_pool, 0);
+  if (c->plan_pool) (void)hipMemPoolTrimTo(c->plan_pool, 0);
 }
 
 // A build workspace, stream-ordered on s, from the context's build pool.
@@ -461,14 +488,19 @@ static hipError_t workspace_alloc(void** ptr, size_t bytes, pinv_context* c, hip
                        : hipMallocAsync(ptr, bytes, s);
 }
 
-// A plan buffer (outside the stream-ordered pool); when the device is out of
+// A plan buffer, stream-ordered on s from the context's plan pool (plain
+// hipMalloc if the pool could not be created); when the device is out of
 // memory, freed pool memory is handed back and the allocation tried once more.
-static hipError_t plan_malloc(void** ptr, size_t bytes, pinv_context* c) {
-  hipError_t e = hipMalloc(ptr, bytes);
+static hipError_t plan_malloc(void** ptr, size_t bytes, pinv_context* c, hipStream_t s) {
+  auto once = [&]() {
+    return c->plan_pool ? hipMallocFromPoolAsync(ptr, bytes, c->plan_pool, s) : hipMalloc(ptr, bytes);
+  };
+  hipError_t e = once();
   if (e == hipErrorOutOfMemory) {
     (void)hipGetLastError();
+    (void)hipStreamSynchronize(s);
     trim_pool(c, true);
-    e = hipMalloc(ptr, bytes);
+    e = once();
   }
   return e;
 }
@@ -515,7 +547,6 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
   p->nx = d.nx;
   p->ny = d.ny;
   p->lam = lam;
-  std::vector<void*>& host_keep = p->host_stage;
   auto cleanup = [&](pinv_status rs) {
     (void)hipStreamSynchronize(s);
     free_plan_memory(p);
@@ -543,18 +574,35 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
     }                                                                                 \
   } while (0)
 
-  st = upload_tables<double>(ht, d, s, &p->tab64, &p->e64, &host_keep);
-  if (st != PINV_OK) return cleanup(st);
-  if (!f64) {
-    st = upload_tables<float>(ht, d, s, &p->tab32, &p->e32, &host_keep);
-    if (st != PINV_OK) return cleanup(st);
+  // Plan buffers come stream-ordered from the context's plan pool and the
+  // tables are staged through its reusable pinned buffer: a build in steady
+  // state maps no new memory while earlier work still runs on the device.
+  p->pooled = c->plan_pool != nullptr;
+  const size_t b64 = tables_bytes<double>(ht), b32 = f64 ? 0 : tables_bytes<float>(ht);
+  BCHK(plan_malloc(&p->tab64, b64, c, s));
+  if (!f64) BCHK(plan_malloc(&p->tab32, b32, c, s));
+  {
+    std::lock_guard<std::mutex> g(c->stage_mu);
+    BCHK(hipEventSynchronize(c->stage_ev));   // earlier copies out of the staging buffer are done
+    if (c->stage_bytes < b64 + b32) {
+      if (c->stage) (void)hipHostFree(c->stage);
+      c->stage = nullptr;
+      c->stage_bytes = 0;
+      BCHK(hipHostMalloc(&c->stage, b64 + b32, hipHostMallocDefault));
+      c->stage_bytes = b64 + b32;
+    }
+    st = upload_tables<double>(ht, d, s, c->stage, p->tab64, &p->e64);
+    if (st == PINV_OK && !f64)
+      st = upload_tables<float>(ht, d, s, (char*)c->stage + b64, p->tab32, &p->e32);
+    if (st == PINV_OK) BCHK(hipEventRecord(c->stage_ev, s));
   }
+  if (st != PINV_OK) return cleanup(st);
   for (auto& ev : p->ev) BCHK(hipEventCreate(&ev));
-  BCHK(hipMalloc((void**)&p->info, sizeof(int)));
+  BCHK(plan_malloc((void**)&p->info, sizeof(int), c, s));
   BCHK(hipMemsetAsync(p->info, 0, sizeof(int), s));
-  BCHK(plan_malloc(&p->R, cs * N * M, c));
-  BCHK(plan_malloc(&p->Linv, cs * N * N, c));
-  BCHK(plan_malloc(&p->gram, 16 * N * N, c));
+  BCHK(plan_malloc(&p->R, cs * N * M, c, s));
+  BCHK(plan_malloc(&p->Linv, cs * N * N, c, s));
+  BCHK(plan_malloc(&p->gram, 16 * N * N, c, s));
   p->gram_exact = !(gram_full && !f64);
   BCHK(workspace_alloc(&G, 16 * N * N, c, s));
   if (f64) {
@@ -639,7 +687,6 @@ pinv_status pinv_plan_wait(pinv_plan* p) {
     for (int i = 0; i < 4; ++i) HIPCHK(hipEventElapsedTime(&p->stage_ms[i], p->ev[i], p->ev[i + 1]));
     p->status = p->info_host ? PINV_ERR_NOT_PD : PINV_OK;
     p->waited = true;
-    free_host_stage(p);
   }
   if (p->status == PINV_ERR_NOT_PD)
     return fail(PINV_ERR_NOT_PD, "Cholesky pivot <= 0 or NaN at column " +
