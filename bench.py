@@ -359,7 +359,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--frames", type=int, default=1000)
     ap.add_argument("--tol", type=float, default=1e-5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -519,23 +519,36 @@ def main():
         P.pinv_apply(ctx, p, d32, x32, refine_steps=refine)
         return p
 
-    for _ in range(args.warmup):
-        p = step()
-        P.pinv_plan_wait(p)
-        P.pinv_plan_release(p)
+    def run_steps(n, stages=None):
+        # A plan lives until the next step is enqueued: the host waits for its
+        # build (the next step already queued behind it), reads its stage
+        # times and releases it, stream-ordered after its apply.  The plan
+        # pool then recycles plan memory as a long-running user's would.
+        prev = None
+        for i in range(n):
+            p = step()
+            if stages is not None:
+                log(f"step {i} enqueued")
+            if prev is not None:
+                P.pinv_plan_wait(prev)
+                if stages is not None:
+                    stages.append(P.pinv_plan_info_get(prev)["stage_ms"])
+                P.pinv_plan_release(prev)
+            prev = p
+        return prev
+
+    last = run_steps(args.warmup)
     torch.cuda.synchronize()
-    plans = []
+    if last is not None:
+        P.pinv_plan_release(last)
+    stages = []
     t0 = time.perf_counter()
-    for i in range(args.steps):
-        plans.append(step())
-        log(f"step {i} enqueued")
+    last = run_steps(args.steps, stages)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    stages = []
-    for p in plans:
-        P.pinv_plan_wait(p)
-        stages.append(P.pinv_plan_info_get(p)["stage_ms"])
-        P.pinv_plan_release(p)
+    P.pinv_plan_wait(last)
+    stages.append(P.pinv_plan_info_get(last)["stage_ms"])
+    P.pinv_plan_release(last)
     stages = np.array(stages)
     st_mean = stages.mean(axis=0)
     err_final = rel_err(x32)

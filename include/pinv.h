@@ -195,7 +195,8 @@ pinv_status pinv_noise(pinv_context *ctx, const pinv_plan *p, const double *coil
                        void *out, void *hip_stream);
 
 /* Forward model data[f] = E image[f] (Eq. 1) in the plan's precision, with E
- * generated on the fly.  image: device [F][N], data: device [F][M]. */
+ * generated on the fly.  image: device [F][N], data: device [F][M].  Enqueued
+ * on `hip_stream` behind the upload of the plan's tables. */
 pinv_status pinv_forward(pinv_context *ctx, const pinv_plan *p, const void *image, int64_t F,
                          void *data, void *hip_stream);
 
@@ -206,7 +207,9 @@ pinv_status pinv_plan_info_get(const pinv_plan *p, pinv_plan_info *out);
  *   R     [N][M] complex, the reconstruction matrix
  *   Linv  [N][N] complex, L^-1 (lower; FP32 plans hold it as complex64)
  *   gram  [N][N] complex128, E^H E (full Hermitian; used by the refinement residual)
- * The memory stays owned by the plan. */
+ * The memory stays owned by the plan.  Work the caller enqueues on these
+ * pointers itself is not tracked by the plan: it must have completed, or be
+ * ordered before a later library call on the plan, when the plan is released. */
 pinv_status pinv_plan_buffers(const pinv_plan *p, void **R, void **Linv, void **gram);
 
 /* Copy one of the plan's buffers (0 = R, 1 = L^-1, 2 = Gram) into caller
@@ -217,7 +220,9 @@ pinv_status pinv_plan_copy_buffer(const pinv_plan *p, int32_t which, void *dst, 
                                   void *hip_stream);
 
 /* Drop one reference.  The last reference held by neither a caller nor the
- * cache frees the plan once its enqueued work has completed. */
+ * cache frees the plan without waiting on the host: the frees are enqueued on
+ * the context's release stream behind the build and behind every apply,
+ * forward, metric and copy enqueued on the plan, on whatever stream. */
 pinv_status pinv_plan_release(pinv_plan *p);
 
 /* Release device memory held by the stream-ordered allocator's pool after

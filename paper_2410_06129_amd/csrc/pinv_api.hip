@@ -58,6 +58,11 @@ struct pinv_plan {
   bool pooled = false;             // device buffers from the context's plan pool
   size_t bytes = 0;
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  // One event per use of the plan that may still be in flight (applies,
+  // metrics, copies on any stream).  A release orders the frees after the
+  // build and after all of them, so it never waits on the host.
+  std::mutex use_mu;
+  std::vector<hipEvent_t> uses;
   bool waited = false;
   pinv_status status = PINV_OK;
   int info_host = 0;
@@ -69,6 +74,7 @@ struct pinv_context {
   int device = 0;
   hipStream_t aux = nullptr;      // look-ahead stream, kept off the last CUs (blocking)
   hipStream_t aux_nb = nullptr;   // look-ahead stream for builds on the null stream
+  hipStream_t free_s = nullptr;   // stream-ordered release of plan buffers
   hipMemPool_t build_pool = nullptr;   // build workspaces (Gram, FP64 factor, W)
   hipMemPool_t plan_pool = nullptr;    // plan buffers (R, L^-1, Gram, tables)
   // pinned staging for table uploads, reused by every build of the context:
@@ -253,20 +259,48 @@ pinv_status upload_tables(const HostTables& h, const Dims& d, hipStream_t s, voi
   return PINV_OK;
 }
 
-void free_plan_memory(pinv_plan* p) {
-  if (p->ev[4]) (void)hipEventSynchronize(p->ev[4]);
-  if (p->pooled) {
-    // the buffers may still be read by work on any stream: wait for the device
-    // (as a non-pooled free would), then return them to the plan pool
-    (void)hipDeviceSynchronize();
-    for (void* q : {p->tab32, p->tab64, p->R, p->Linv, p->gram, (void*)p->info})
-      if (q) (void)hipFreeAsync(q, nullptr);
-  } else {
-    for (void* q : {p->tab32, p->tab64, p->R, p->Linv, p->gram, (void*)p->info})
-      if (q) (void)hipFree(q);
+// Record that work just enqueued on `s` reads the plan.  Events whose work
+// has finished are re-recorded; one still pending is never overwritten, so a
+// stream handle that was destroyed and handed out again cannot hide work.
+hipError_t note_use(const pinv_plan* pc, hipStream_t s) {
+  pinv_plan* p = (pinv_plan*)pc;
+  std::lock_guard<std::mutex> g(p->use_mu);
+  hipEvent_t ev = nullptr;
+  for (hipEvent_t e : p->uses)
+    if (hipEventQuery(e) == hipSuccess) {
+      ev = e;
+      break;
+    }
+  (void)hipGetLastError();
+  if (!ev) {
+    const hipError_t r = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (r != hipSuccess) return r;
+    p->uses.push_back(ev);
   }
-  for (auto& e : p->ev)
+  return hipEventRecord(ev, s);
+}
+
+// Return a plan's buffers.  Pooled buffers are freed stream-ordered on the
+// context's release stream after the build and every recorded use, so the
+// host does not wait and the pool can hand the memory to the next build
+// without mapping more.  Buffers from hipMalloc (no plan pool) are freed
+// after the device has finished with them.
+void free_plan_memory(pinv_plan* p) {
+  pinv_context* c = p->ctx;
+  void* const bufs[] = {p->tab32, p->tab64, p->R, p->Linv, p->gram, (void*)p->info};
+  bool ordered = p->pooled && c->free_s;
+  if (ordered) {
+    for (hipEvent_t e : p->ev)
+      if (e) ordered = ordered && hipStreamWaitEvent(c->free_s, e, 0) == hipSuccess;
+    for (hipEvent_t e : p->uses) ordered = ordered && hipStreamWaitEvent(c->free_s, e, 0) == hipSuccess;
+  }
+  if (!ordered) (void)hipDeviceSynchronize();
+  for (void* q : bufs)
+    if (q) (void)(p->pooled ? hipFreeAsync(q, ordered ? c->free_s : nullptr) : hipFree(q));
+  for (hipEvent_t e : p->ev)
     if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : p->uses) (void)hipEventDestroy(e);
+  p->uses.clear();
 }
 
 size_t plan_footprint(const Dims& d, int prec) {
@@ -338,6 +372,7 @@ const char* pinv_last_error(void) { return g_last_error.c_str(); }
 // use a second, unmasked non-blocking stream instead.
 static bool create_aux_streams(int device, pinv_context* c) {
   if (hipStreamCreateWithFlags(&c->aux_nb, hipStreamNonBlocking) != hipSuccess) return false;
+  if (hipStreamCreateWithFlags(&c->free_s, hipStreamNonBlocking) != hipSuccess) return false;
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
       cus >= 128) {
@@ -363,8 +398,8 @@ pinv_status pinv_context_create(int device, size_t budget, pinv_context** out) {
   c->device = device;
   c->budget = budget ? budget : (size_t)(0.9 * (double)fr);
   if (!create_aux_streams(device, c)) {
-    delete c;
-    return fail(PINV_ERR_DEVICE, "cannot create the auxiliary stream");
+    pinv_context_destroy(c);
+    return fail(PINV_ERR_DEVICE, "cannot create the auxiliary streams");
   }
   // Keep freed stream-ordered allocations (build workspaces, scratch) mapped
   // across synchronisations: the pool's default release threshold of 0 hands
@@ -414,12 +449,14 @@ pinv_status pinv_context_destroy(pinv_context* c) {
     c->lru.clear();
     c->cache.clear();
   }
+  if (c->free_s) (void)hipStreamSynchronize(c->free_s);
   if (c->build_pool) (void)hipMemPoolDestroy(c->build_pool);
   if (c->plan_pool) (void)hipMemPoolDestroy(c->plan_pool);
   if (c->stage_ev) (void)hipEventDestroy(c->stage_ev);
   if (c->stage) (void)hipHostFree(c->stage);
   if (c->aux && c->aux != c->aux_nb) (void)hipStreamDestroy(c->aux);
   if (c->aux_nb) (void)hipStreamDestroy(c->aux_nb);
+  if (c->free_s) (void)hipStreamDestroy(c->free_s);
   delete c;
   return PINV_OK;
 }
@@ -800,6 +837,8 @@ pinv_status pinv_apply_grouped(pinv_context* c, int32_t n, const pinv_apply_item
       if (st != PINV_OK) return st;
     }
   }
+  for (int j = 0; j < n; ++j)
+    if (items[j].F > 0) HIPCHK(note_use((const pinv_plan*)items[j].plan, s));
   return PINV_OK;
 }
 
@@ -816,6 +855,7 @@ pinv_status pinv_forward(pinv_context* c, const pinv_plan* pc, const void* image
   hipStream_t s = (hipStream_t)stream;
   HIPCHK(hipSetDevice(c->device));
   if (F == 0) return PINV_OK;
+  HIPCHK(hipStreamWaitEvent(s, p->ev[0], 0));   // the tables are on the device
   if (p->prec == PINV_FP64) {
     HIPCHK((launch_forward<double, double, double>(p->e64, (const double*)image, (int)F, nullptr,
                                                    (double*)data, s)));
@@ -823,6 +863,7 @@ pinv_status pinv_forward(pinv_context* c, const pinv_plan* pc, const void* image
     HIPCHK((launch_forward<float, float, float>(p->e32, (const float*)image, (int)F, nullptr,
                                                 (float*)data, s)));
   }
+  HIPCHK(note_use(p, s));
   return PINV_OK;
 }
 
@@ -889,6 +930,7 @@ pinv_status pinv_srf(pinv_context* c, const pinv_plan* pc, int32_t mode, void* o
     else
       HIPCHK(launch_srf_full<float>(p->e32, (const float*)p->R, (float*)out, s));
   }
+  HIPCHK(note_use(p, s));
   return PINV_OK;
 }
 
@@ -949,6 +991,7 @@ pinv_status pinv_noise(pinv_context* c, const pinv_plan* pc, const double* coil_
   const pinv_status r = f64 ? noise_impl<double>(p, (const double*)dL, mode, (double*)out, s)
                             : noise_impl<float>(p, (const float*)dL, mode, (float*)out, s);
   if (dL) HIPCHK(hipFreeAsync(dL, s));
+  if (r == PINV_OK) HIPCHK(note_use(p, s));
   return r;
 }
 
@@ -997,6 +1040,7 @@ pinv_status pinv_plan_copy_buffer(const pinv_plan* p, int32_t which, void* dst, 
   HIPCHK(hipSetDevice(p->ctx->device));
   HIPCHK(hipStreamWaitEvent(s, p->ev[4], 0));
   HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s));
+  HIPCHK(note_use(p, s));
   return PINV_OK;
 }
 
@@ -1006,6 +1050,7 @@ pinv_status pinv_plan_release(pinv_plan* p) {
   std::lock_guard<std::mutex> g(c->mu);
   const int left = --p->refs;
   if (left <= 0) {
+    (void)hipSetDevice(c->device);
     if (p->cached) {
       c->cache.erase(p->key);
       c->lru.erase(p->lru_it);

@@ -322,6 +322,35 @@ def test_zero_frames_and_grouped_equals_single(P, ctx):
     P.pinv_plan_release(p2)
 
 
+def test_release_is_ordered_after_pending_applies(P, ctx):
+    """Releasing a plan does not wait on the host; its buffers go back to the
+    plan pool behind every apply enqueued on it.  An apply still queued on a
+    side stream when the plan is released, with a new build of the same size
+    issued right after, must give the same image bit for bit."""
+    encs = [synth.serving_encoding(48, 8, i) for i in (1, 2)]
+    N, M, F = encs[0].N, encs[0].M, 600
+    rng = np.random.default_rng(7)
+    d = to_dev(rng.standard_normal((F, M)) + 1j * rng.standard_normal((F, M)), np.complex64)
+    p1 = build(P, ctx, encs[0], P.FP32, P.FLAG_UNCACHED)
+    want = torch.empty((F, N), dtype=torch.complex64, device="cuda")
+    P.pinv_apply(ctx, p1, d, want, refine_steps=1)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    xs = [torch.zeros((F, N), dtype=torch.complex64, device="cuda") for _ in range(3)]
+    torch.cuda.synchronize()
+    for x in xs:
+        P.pinv_apply(ctx, p1, d, x, refine_steps=1, stream=side)
+    P.pinv_plan_release(p1)
+    p2 = P.pinv_build(ctx, encs[1], 1e-3, P.LAMBDA_REL_MEAN_DIAG, P.FP32, P.FLAG_UNCACHED)
+    y = torch.empty((F, N), dtype=torch.complex64, device="cuda")
+    P.pinv_apply(ctx, p2, d, y)
+    torch.cuda.synchronize()
+    P.pinv_plan_wait(p2)
+    P.pinv_plan_release(p2)
+    for x in xs:
+        assert torch.equal(x, want)
+
+
 def test_cache_hit_and_release(P, ctx):
     o = oracle_case("species_b0")
     a = build(P, ctx, o["w"].enc, P.FP32)
