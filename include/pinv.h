@@ -85,6 +85,15 @@ typedef struct {
 #define PINV_FLAG_GRAM_FULL 4   /* form E^H E over all M = C*nk rows in the plan's precision
                                    instead of the default FP64 (F^H F) o (coil cross-products),
                                    which is exact because every coil shares the trajectory (Eq. 11) */
+#define PINV_FLAG_NO_R 8        /* factor-only plan: Gram, shift and Cholesky with L^-1, but no W
+                                   and no R.  Applies solve the normal equations directly,
+                                   image = L^-H L^-1 (sum_c E_c^H data_c), with E regenerated per
+                                   tile (Sec. 2, direct solution without explicit inversion; the
+                                   coil-wise adjoint after Eq. 11).  Holds N*N instead of N*M + N*N
+                                   complex values and skips 8MN^2 build flops; each frame costs the
+                                   same 8NM as R*data plus 8N^2 for the two triangular products.
+                                   SRF, noise matrix and the R buffer are unavailable.  Not with
+                                   PINV_BF16X3 (the split products only form W and R). */
 
 typedef struct {
   double lambda;              /* >= 0; meaning set by lambda_mode */
@@ -102,7 +111,9 @@ typedef struct {
   uint64_t key;               /* cache key (hash of encoding, shift and precision) */
   size_t device_bytes;        /* device memory the plan holds */
   float stage_ms[4];          /* Gram, Cholesky+inverse, W = L^-1 E^H, R = L^-H W
-                                 (HIP event times on the build stream; valid when ready) */
+                                 (HIP event times on the build stream; valid when ready;
+                                 the last two are 0 for factor-only plans) */
+  int32_t has_r;              /* 0 for plans built with PINV_FLAG_NO_R */
 } pinv_plan_info;
 
 typedef struct {
@@ -150,7 +161,9 @@ pinv_status pinv_encoding_key(const pinv_encoding *e, const pinv_build_opts *o, 
 
 /* image[f] = R data[f] for F frames (Eq. 3), enqueued on `hip_stream` behind
  * the plan's build.  data: device [F][M], image: device [F][N], dtype of the
- * plan (see conventions).  refine_steps (0..4) adds iterative refinement on
+ * plan (see conventions).  A factor-only plan (PINV_FLAG_NO_R) gives
+ * image = L^-H L^-1 E^H data instead, E^H data formed with E generated in the
+ * plan's precision.  refine_steps (0..4) adds iterative refinement on
  * the normal equations (Eq. 6): r = E^H (d - E x) - lambda x in FP64 with E
  * regenerated in FP64, then x += L^-H L^-1 r.  The result for a frame does not
  * depend on F or on the other frames.  Errors: INVALID, NOMEM (scratch), DEVICE. */
@@ -176,7 +189,7 @@ typedef enum { PINV_METRIC_DIAG = 0, PINV_METRIC_FULL = 1 } pinv_metric_mode;
  * diagonal real, so imaginary parts of the map are rounding-level).
  * out: device, caller-owned, N or N*N entries.  Ordered on hip_stream after
  * the plan's build.  Errors: INVALID (NULL, bad mode, plan of another
- * context), DEVICE. */
+ * context), UNSUPPORTED (factor-only plan), DEVICE. */
 pinv_status pinv_srf(pinv_context *ctx, const pinv_plan *p, int32_t mode, void *out,
                      void *hip_stream);
 
@@ -190,7 +203,8 @@ pinv_status pinv_srf(pinv_context *ctx, const pinv_plan *p, int32_t mode, void *
  * it allocates an N x M work array on hip_stream's memory pool for the call.
  * With coil_cov the call synchronises hip_stream once (the covariance factor is
  * staged through pinned host memory).  Errors: INVALID (NULL, bad mode,
- * coil_cov not Hermitian positive definite), NOMEM, DEVICE. */
+ * coil_cov not Hermitian positive definite), UNSUPPORTED (factor-only plan),
+ * NOMEM, DEVICE. */
 pinv_status pinv_noise(pinv_context *ctx, const pinv_plan *p, const double *coil_cov, int32_t mode,
                        void *out, void *hip_stream);
 

@@ -54,6 +54,7 @@ struct pinv_plan {
   void* Linv = nullptr;      // complex64 for FP32/BF16X3 plans, complex128 for FP64
   void* gram = nullptr;      // full Hermitian E^H E in FP64 (refinement residuals)
   bool gram_exact = true;    // false when the Gram was formed over M rows in FP32
+  bool no_r = false;         // factor-only plan: no W, no R (applies solve with L^-1)
   int* info = nullptr;
   bool pooled = false;             // device buffers from the context's plan pool
   size_t bytes = 0;
@@ -303,24 +304,26 @@ void free_plan_memory(pinv_plan* p) {
   p->uses.clear();
 }
 
-size_t plan_footprint(const Dims& d, int prec) {
+size_t plan_footprint(const Dims& d, int prec, bool no_r) {
   const size_t N = d.N, M = d.M;
   const size_t cs = prec == PINV_FP64 ? 16 : 8;
   size_t b = 0;
   b += 16 * N * N;              // Gram / factor workspace (FP64)
   b += 16 * N * N;              // L^-1 in FP64 during the factorisation
   b += cs * N * N;              // L^-1 kept
-  b += cs * N * M;              // W
-  b += cs * N * M;              // R
+  if (!no_r) {
+    b += cs * N * M;            // W
+    b += cs * N * M;            // R
+  }
   b += 16 * N * N;              // the Gram kept for refinement
   b += 64ull << 20;             // tables and slack
   return b;
 }
 
-size_t plan_resident(const Dims& d, int prec) {
+size_t plan_resident(const Dims& d, int prec, bool no_r) {
   const size_t N = d.N, M = d.M;
   const size_t cs = prec == PINV_FP64 ? 16 : 8;
-  return cs * N * M + cs * N * N + 16 * N * N + (16ull << 20);
+  return (no_r ? 0 : cs * N * M) + cs * N * N + 16 * N * N + (16ull << 20);
 }
 
 // Evict LRU plans held only by the cache until `need` bytes fit.  ctx->mu held.
@@ -470,6 +473,8 @@ static pinv_status check_build(const pinv_encoding* e, const pinv_build_opts* o,
   if (o->prec != PINV_FP64 && o->prec != PINV_FP32 && o->prec != PINV_BF16X3)
     return fail(PINV_ERR_INVALID, "unknown precision");
   if (o->reserved != 0) return fail(PINV_ERR_INVALID, "reserved must be 0");
+  if (o->flags & ~(PINV_FLAG_KEEP_GRAM | PINV_FLAG_UNCACHED | PINV_FLAG_GRAM_FULL | PINV_FLAG_NO_R))
+    return fail(PINV_ERR_INVALID, "unknown flag bits");
   if (!(o->lambda >= 0.0) || !isfinite(o->lambda)) return fail(PINV_ERR_INVALID, "lambda must be finite and >= 0");
   double lam = o->lambda;
   if (o->lambda_mode == PINV_LAMBDA_REL_MEAN_DIAG) {
@@ -488,8 +493,12 @@ static pinv_status check_build(const pinv_encoding* e, const pinv_build_opts* o,
   if (lam == 0.0 && d->M < d->N)
     return fail(PINV_ERR_INVALID, "lambda = 0 needs M >= N (full column rank)");
   const bool gram_full = (o->flags & PINV_FLAG_GRAM_FULL) != 0;
+  const bool no_r = (o->flags & PINV_FLAG_NO_R) != 0;
+  if (no_r && o->prec == PINV_BF16X3)
+    return fail(PINV_ERR_INVALID, "PINV_FLAG_NO_R with PINV_BF16X3: the split products only form W and R");
   *lam_out = lam;
-  *key_out = plan_key(e, *d, lam, o->prec) ^ (gram_full ? 0xc2b2ae3d27d4eb4full : 0);
+  *key_out = plan_key(e, *d, lam, o->prec) ^ (gram_full ? 0xc2b2ae3d27d4eb4full : 0) ^
+             (no_r ? 0x9e3779b97f4a7c15ull : 0);
   return PINV_OK;
 }
 
@@ -501,7 +510,7 @@ pinv_status pinv_encoding_key(const pinv_encoding* e, const pinv_build_opts* o, 
   pinv_status st = check_build(e, o, &d, &lam, &k);
   if (st != PINV_OK) return st;
   if (key) *key = k;
-  if (plan_bytes) *plan_bytes = plan_footprint(d, o->prec);
+  if (plan_bytes) *plan_bytes = plan_footprint(d, o->prec, (o->flags & PINV_FLAG_NO_R) != 0);
   return PINV_OK;
 }
 
@@ -566,7 +575,8 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
     *out = p;
     return PINV_OK;
   }
-  const size_t foot = plan_footprint(d, o->prec);
+  const bool no_r = (o->flags & PINV_FLAG_NO_R) != 0;
+  const size_t foot = plan_footprint(d, o->prec, no_r);
   if (!make_room(c, foot))
     return fail(PINV_ERR_NOMEM, "plan footprint " + std::to_string(foot) +
                                     " B exceeds the free budget");
@@ -584,6 +594,7 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
   p->nx = d.nx;
   p->ny = d.ny;
   p->lam = lam;
+  p->no_r = no_r;
   auto cleanup = [&](pinv_status rs) {
     (void)hipStreamSynchronize(s);
     free_plan_memory(p);
@@ -637,7 +648,7 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
   for (auto& ev : p->ev) BCHK(hipEventCreate(&ev));
   BCHK(plan_malloc((void**)&p->info, sizeof(int), c, s));
   BCHK(hipMemsetAsync(p->info, 0, sizeof(int), s));
-  BCHK(plan_malloc(&p->R, cs * N * M, c, s));
+  if (!no_r) BCHK(plan_malloc(&p->R, cs * N * M, c, s));
   BCHK(plan_malloc(&p->Linv, cs * N * N, c, s));
   BCHK(plan_malloc(&p->gram, 16 * N * N, c, s));
   p->gram_exact = !(gram_full && !f64);
@@ -648,7 +659,7 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
     BCHK(workspace_alloc(&L64, 16 * N * N, c, s));
   }
   BCHK(hipMemsetAsync(L64, 0, 16 * N * N, s));
-  BCHK(workspace_alloc(&W, cs * N * M, c, s));
+  if (!no_r) BCHK(workspace_alloc(&W, cs * N * M, c, s));
 
   // 1. Gram (a3) with E generated per tile (a2)
   BCHK(hipEventRecord(p->ev[0], s));
@@ -666,8 +677,10 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
                       s ? p->ctx->aux : p->ctx->aux_nb));
   if (!f64) BCHK(launch_to_f32((const double*)L64, (float*)p->Linv, N * N, s));
   BCHK(hipEventRecord(p->ev[2], s));
-  // 3. W = L^-1 E^H, R = L^-H W (a5)
-  if (f64) {
+  // 3. W = L^-1 E^H, R = L^-H W (a5); a factor-only plan stops at L^-1
+  if (no_r) {
+    BCHK(hipEventRecord(p->ev[3], s));
+  } else if (f64) {
     BCHK(launch_trmm_w<double>(p->e64, (const double*)p->Linv, (double*)W, s));
     BCHK(hipEventRecord(p->ev[3], s));
     BCHK(launch_trmm_r<double>((const double*)p->Linv, (const double*)W, (double*)p->R, d.N, d.M, s));
@@ -681,7 +694,7 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
     BCHK(launch_trmm_r<float>((const float*)p->Linv, (const float*)W, (float*)p->R, d.N, d.M, s));
   }
   BCHK(hipEventRecord(p->ev[4], s));
-  BCHK(hipFreeAsync(W, s));
+  if (W) BCHK(hipFreeAsync(W, s));
   W = nullptr;
   BCHK(hipFreeAsync(G, s));
   G = nullptr;
@@ -692,7 +705,7 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
 #undef BCHK
   // the pinned staging buffers stay with the plan until its build has finished
 
-  p->bytes = plan_resident(d, o->prec);
+  p->bytes = plan_resident(d, o->prec, no_r);
   c->used += p->bytes;
   if (uncached) {
     p->refs = 1;   // the caller only
@@ -722,6 +735,7 @@ pinv_status pinv_plan_wait(pinv_plan* p) {
     trim_pool(p->ctx);
     HIPCHK(hipMemcpy(&p->info_host, p->info, sizeof(int), hipMemcpyDeviceToHost));
     for (int i = 0; i < 4; ++i) HIPCHK(hipEventElapsedTime(&p->stage_ms[i], p->ev[i], p->ev[i + 1]));
+    if (p->no_r) p->stage_ms[2] = p->stage_ms[3] = 0.f;   // no W or R was formed
     p->status = p->info_host ? PINV_ERR_NOT_PD : PINV_OK;
     p->waited = true;
   }
@@ -778,6 +792,29 @@ static pinv_status refine_item(pinv_plan* p, const void* data, int F, void* imag
     if (q) HIPCHK(hipFreeAsync(q, s));
   return PINV_OK;
 }
+
+// Factor-only plans solve the normal equations per frame without R:
+//   b = E^H d = sum_c E_c^H d_c   (E generated per tile in the plan's precision)
+//   x = L^-H (L^-1 b)
+// b is formed in `image`, L^-1 b in a scratch array, L^-H (L^-1 b) back in `image`.
+template <typename TS>
+static pinv_status solve_item(pinv_plan* p, const void* data, int F, void* image, hipStream_t s) {
+  const size_t N = p->N;
+  TS* x = (TS*)image;
+  void* t = nullptr;
+  HIPCHK(hipMallocAsync(&t, 2 * sizeof(TS) * (size_t)F * N, s));
+  hipError_t e;
+  if constexpr (sizeof(TS) == 8)
+    e = launch_adjoint<double, double, double, double>(p->e64, (const double*)data, F, nullptr, 0.0, x, s);
+  else
+    e = launch_adjoint<float, float, float, float>(p->e32, (const float*)data, F, nullptr, 0.0, x, s);
+  if (e == hipSuccess) e = launch_tri_frames<TS, 0, TS>((const TS*)p->Linv, x, F, p->N, (TS*)t, s);
+  if (e == hipSuccess) e = launch_tri_frames<TS, 2, TS>((const TS*)p->Linv, (const TS*)t, F, p->N, x, s);
+  const hipError_t f = hipFreeAsync(t, s);
+  HIPCHK(e);
+  HIPCHK(f);
+  return PINV_OK;
+}
 }  // extern "C++"
 
 pinv_status pinv_apply_grouped(pinv_context* c, int32_t n, const pinv_apply_item* items,
@@ -804,7 +841,7 @@ pinv_status pinv_apply_grouped(pinv_context* c, int32_t n, const pinv_apply_item
     int tiles = 0;
     while (i < n && b.n < kMaxGroup && ((const pinv_plan*)items[i].plan)->prec == prec) {
       const pinv_plan* p = (const pinv_plan*)items[i].plan;
-      if (items[i].F > 0) {
+      if (items[i].F > 0 && !p->no_r) {
         ApplyItemDev& it = b.it[b.n++];
         it.D = items[i].data;
         it.R = p->R;
@@ -826,6 +863,14 @@ pinv_status pinv_apply_grouped(pinv_context* c, int32_t n, const pinv_apply_item
       HIPCHK(launch_apply_b3(b, tiles, s));
     else
       HIPCHK(launch_apply<float>(b, tiles, s));
+  }
+  for (int j = 0; j < n; ++j) {
+    pinv_plan* p = (pinv_plan*)items[j].plan;
+    if (!p->no_r || items[j].F <= 0) continue;
+    const pinv_status st =
+        p->prec == PINV_FP64 ? solve_item<double>(p, items[j].data, (int)items[j].F, items[j].image, s)
+                             : solve_item<float>(p, items[j].data, (int)items[j].F, items[j].image, s);
+    if (st != PINV_OK) return st;
   }
   if (refine_steps > 0) {
     for (int j = 0; j < n; ++j) {
@@ -908,6 +953,7 @@ static pinv_status metric_args(pinv_context* c, const pinv_plan* p, int32_t mode
   if (p->ctx != c) return fail(PINV_ERR_INVALID, "plan belongs to another context");
   if (mode != PINV_METRIC_DIAG && mode != PINV_METRIC_FULL)
     return fail(PINV_ERR_INVALID, "mode must be PINV_METRIC_DIAG or PINV_METRIC_FULL");
+  if (p->no_r) return fail(PINV_ERR_UNSUPPORTED, "the plan was built without R (PINV_FLAG_NO_R)");
   return PINV_OK;
 }
 }  // extern "C++"
@@ -1005,6 +1051,7 @@ pinv_status pinv_plan_info_get(const pinv_plan* p, pinv_plan_info* out) {
   out->key = p->key;
   out->device_bytes = p->bytes;
   for (int i = 0; i < 4; ++i) out->stage_ms[i] = p->waited ? p->stage_ms[i] : 0.f;
+  out->has_r = p->no_r ? 0 : 1;
   return PINV_OK;
 }
 

@@ -611,9 +611,10 @@ __global__ __launch_bounds__(256, 2) void k_adjoint(EncDev<typename Cfg::T> e, c
   });
 }
 
-// Triangular products on frame blocks (refinement correction):
+// Triangular products on frame blocks (refinement correction, factor-only solves):
 //   mode 0: Y[f][i] = sum_{n <= i} Xin[f][n] Li[i][n]          (L^-1 x, per frame)
 //   mode 1: X[f][i] += sum_{n >= i} Yin[f][n] conj(Li[n][i])   (L^-H y, accumulated)
+//   mode 2: X[f][i] = sum_{n >= i} Yin[f][n] conj(Li[n][i])    (L^-H y)
 template <class Cfg, int MODE, typename SO>
 __global__ __launch_bounds__(256) void k_tri_frames(const typename Cfg::T* __restrict__ Li,
                                                     const typename Cfg::T* __restrict__ In, int F,
@@ -650,7 +651,7 @@ __global__ __launch_bounds__(256) void k_tri_frames(const typename Cfg::T* __res
     const int row = r0 + r, col = c0 + c;
     if (row < F && col < N) {
       const size_t o = (size_t)row * N + col;
-      if (MODE == 0) {
+      if (MODE != 1) {
         O[o] = cx<SO>{SO(re), SO(im)};
       } else {
         cx<SO> x = O[o];
@@ -1057,6 +1058,9 @@ template hipError_t launch_adjoint<double, double, double, double>(const EncDev<
 template hipError_t launch_adjoint<double, float, float, double>(const EncDev<double>&, const float*,
                                                                  int, const float*, double,
                                                                  double*, hipStream_t);
+template hipError_t launch_adjoint<float, float, float, float>(const EncDev<float>&, const float*, int,
+                                                               const float*, double, float*,
+                                                               hipStream_t);
 template hipError_t launch_resid<float, float>(const double*, const double*, const float*, int, int,
                                                double, float*, hipStream_t);
 template hipError_t launch_resid<double, double>(const double*, const double*, const double*, int,
@@ -1069,5 +1073,9 @@ template hipError_t launch_tri_frames<double, 0, double>(const double*, const do
                                                          double*, hipStream_t);
 template hipError_t launch_tri_frames<double, 1, double>(const double*, const double*, int, int,
                                                          double*, hipStream_t);
+template hipError_t launch_tri_frames<double, 2, double>(const double*, const double*, int, int,
+                                                         double*, hipStream_t);
+template hipError_t launch_tri_frames<float, 2, float>(const float*, const float*, int, int, float*,
+                                                       hipStream_t);
 
 }  // namespace pinv

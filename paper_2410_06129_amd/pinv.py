@@ -22,6 +22,7 @@ LAMBDA_ABS, LAMBDA_REL_MEAN_DIAG = 0, 1
 FLAG_KEEP_GRAM = 1
 FLAG_UNCACHED = 2
 FLAG_GRAM_FULL = 4
+FLAG_NO_R = 8
 BUF_R, BUF_LINV, BUF_GRAM = 0, 1, 2
 METRIC_DIAG, METRIC_FULL = 0, 1
 
@@ -47,7 +48,8 @@ class pinv_build_opts(ctypes.Structure):
 class pinv_plan_info(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int64), ("M", ctypes.c_int64), ("lambda_abs", ctypes.c_double),
                 ("prec", ctypes.c_int32), ("ready", ctypes.c_int32), ("key", ctypes.c_uint64),
-                ("device_bytes", ctypes.c_size_t), ("stage_ms", ctypes.c_float * 4)]
+                ("device_bytes", ctypes.c_size_t), ("stage_ms", ctypes.c_float * 4),
+                ("has_r", ctypes.c_int32)]
 
 
 class pinv_apply_item(ctypes.Structure):
@@ -245,7 +247,8 @@ def pinv_plan_info_get(plan: int) -> dict:
     i = pinv_plan_info()
     _check(_lib.pinv_plan_info_get(plan, ctypes.byref(i)), "pinv_plan_info_get")
     return dict(N=i.N, M=i.M, lambda_abs=i.lambda_abs, prec=i.prec, ready=bool(i.ready),
-                key=i.key, device_bytes=i.device_bytes, stage_ms=list(i.stage_ms))
+                key=i.key, device_bytes=i.device_bytes, stage_ms=list(i.stage_ms),
+                has_r=bool(i.has_r))
 
 
 def pinv_plan_buffers(plan: int):

@@ -45,3 +45,23 @@ def test_status_strings_without_device():
     from paper_2410_06129_amd import pinv
     assert pinv.pinv_status_string(pinv.ERR_NOT_PD).startswith("shifted Gram")
     assert pinv.pinv_status_string(0) == "ok"
+
+
+def test_build_options_without_device():
+    """pinv_encoding_key validates build options and sizes the plan on the host.
+    A factor-only plan (FLAG_NO_R) has its own cache key and needs neither W nor
+    R: 2 * 8 * N * M bytes less for FP32 plans."""
+    ensure_built()
+    from paper_2410_06129_amd import pinv, synth
+    enc = synth.small_case(seed=5, nx=12, ny=10, C=2, K=300, F=1).enc
+    k_r, b_r = pinv.pinv_encoding_key(enc, 1e-3, prec=pinv.FP32)
+    k_n, b_n = pinv.pinv_encoding_key(enc, 1e-3, prec=pinv.FP32, flags=pinv.FLAG_NO_R)
+    assert k_r != k_n
+    assert b_r - b_n == 2 * 8 * enc.N * enc.M
+    for prec, flags in ((pinv.BF16X3, pinv.FLAG_NO_R), (pinv.FP32, 64)):
+        try:
+            pinv.pinv_encoding_key(enc, 1e-3, prec=prec, flags=flags)
+        except pinv.PinvError as e:
+            assert e.status == pinv.ERR_INVALID
+        else:
+            raise AssertionError(f"prec {prec} flags {flags} accepted")

@@ -322,6 +322,70 @@ def test_zero_frames_and_grouped_equals_single(P, ctx):
     P.pinv_plan_release(p2)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_factor_only_plan_matches_oracle(P, ctx, name, prec):
+    """A plan built with FLAG_NO_R keeps L^-1 and the Gram but no R; its applies
+    solve x = L^-H L^-1 (E^H d) with E regenerated per tile, which equals R d.
+    Same bars as the R path: FP64 1e-9; FP32 kappa * 1e-6 unrefined and 1e-5
+    after two refinement steps.  The metrics need R and are refused."""
+    o = oracle_case(name)
+    enc, N, M = o["w"].enc, o["w"].enc.N, o["w"].enc.M
+    pr = P.FP64 if prec == "fp64" else P.FP32
+    cdt = np.complex128 if prec == "fp64" else np.complex64
+    plan = build(P, ctx, enc, pr, flags=P.FLAG_NO_R | P.FLAG_UNCACHED)
+    full = build(P, ctx, enc, pr, flags=P.FLAG_UNCACHED)
+    try:
+        info, finfo = P.pinv_plan_info_get(plan), P.pinv_plan_info_get(full)
+        assert not info["has_r"] and finfo["has_r"]
+        assert info["stage_ms"][2] == 0.0 and info["stage_ms"][3] == 0.0
+        assert info["device_bytes"] < finfo["device_bytes"]
+        assert info["key"] != finfo["key"]
+        d = to_dev(o["d"], cdt)
+        F = d.shape[0]
+        x0 = torch.full((F, N), float("nan"), dtype=d.dtype, device="cuda")
+        x2 = torch.full((F, N), float("nan"), dtype=d.dtype, device="cuda")
+        torch.cuda.synchronize()
+        P.pinv_apply(ctx, plan, d, x0, refine_steps=0)
+        P.pinv_apply(ctx, plan, d, x2, refine_steps=2)
+        # grouped with an R plan: each item as alone
+        g0, g1 = torch.zeros_like(x0), torch.zeros_like(x0)
+        r0 = torch.zeros_like(x0)
+        P.pinv_apply(ctx, full, d, r0)
+        P.pinv_apply_grouped(ctx, [(full, d, g0), (plan, d, g1)])
+        torch.cuda.synchronize()
+        assert torch.equal(g1, x0) and torch.equal(g0, r0)
+        e0 = frame_rel(x0.cpu().numpy().astype(np.complex128), o["x"])
+        e2 = frame_rel(x2.cpu().numpy().astype(np.complex128), o["x"])
+        print(f"{name} {prec}: kappa={o['kappa']:.3g} err0={e0.max():.2e} err2={e2.max():.2e}")
+        if prec == "fp64":
+            assert e0.max() < 1e-9 and e2.max() < 1e-9
+        else:
+            assert e0.max() < o["kappa"] * 1e-6
+            assert e2.max() < 1e-5
+        out = torch.zeros((N,), dtype=d.dtype, device="cuda")
+        with pytest.raises(P.PinvError) as ei:
+            P.pinv_srf(ctx, plan, out, P.METRIC_DIAG)
+        assert ei.value.status == P.ERR_UNSUPPORTED
+        with pytest.raises(P.PinvError) as ei:
+            P.pinv_noise(ctx, plan, out.real.contiguous(), mode=P.METRIC_DIAG)
+        assert ei.value.status == P.ERR_UNSUPPORTED
+        Rb = torch.zeros((N, M), dtype=d.dtype, device="cuda")
+        with pytest.raises(P.PinvError) as ei:
+            P.pinv_plan_copy_buffer(plan, P.BUF_R, Rb)
+        assert ei.value.status == P.ERR_INVALID
+    finally:
+        P.pinv_plan_release(plan)
+        P.pinv_plan_release(full)
+
+
+def test_factor_only_rejects_bf16x3(P, ctx):
+    enc = oracle_case("species_b0")["w"].enc
+    with pytest.raises(P.PinvError) as ei:
+        P.pinv_build(ctx, enc, 1e-3, P.LAMBDA_REL_MEAN_DIAG, P.BF16X3, P.FLAG_NO_R)
+    assert ei.value.status == P.ERR_INVALID
+
+
 def test_release_is_ordered_after_pending_applies(P, ctx):
     """Releasing a plan does not wait on the host; its buffers go back to the
     plan pool behind every apply enqueued on it.  An apply still queued on a
