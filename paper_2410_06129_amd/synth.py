@@ -14,8 +14,10 @@ Conventions (paper Sec. 2, Eq. 2 and Sec. 3.3):
   * data row index m = c*K + i (coil-major).
   * sample time t_i = i*dwell (seconds), time origin at the first sample.
 
-Seeds follow numpy.random.default_rng(1000*cfg + j) with j = 1 phantom,
-2 coils, 3 B0, 4 noise, 5 dynamics, 6 serving trace.
+Seeds follow numpy.random.default_rng(1000*wid + j), where wid numbers the
+workload (1 radial 32x32, 2 spiral 64x64 with 8 coils, 3 spiral 96x96 with 16
+coils, 4 five-species 32x32, 5 serving trace) and j = 1 phantom, 2 coils, 3 B0,
+4 noise, 5 dynamics, 6 serving trace.
 """
 from __future__ import annotations
 
@@ -30,8 +32,8 @@ GOLDEN_ANGLE = math.pi * (math.sqrt(5.0) - 1.0) / 2.0  # ~111.246 degrees
 SEED_PHANTOM, SEED_COILS, SEED_B0, SEED_NOISE, SEED_DYN, SEED_TRACE = 1, 2, 3, 4, 5, 6
 
 
-def rng_for(cfg: int, j: int) -> np.random.Generator:
-    return np.random.default_rng(1000 * cfg + j)
+def rng_for(wid: int, j: int) -> np.random.Generator:
+    return np.random.default_rng(1000 * wid + j)
 
 
 @dataclasses.dataclass
@@ -228,57 +230,57 @@ class Workload:
     snr_db: float = 30.0
 
 
-def config1(F: int = 1) -> Workload:
+def radial_32x32_c1(F: int = 1) -> Workload:
     """32x32 single coil, 16 golden-angle spokes x 128 samples (M=2048), FP64."""
-    cfg = 1
+    wid = 1
     k = golden_radial(32, 16, 128)
     enc = Encoding(32, 32, k)
-    x = ellipse_phantom(32, 32, rng_for(cfg, SEED_PHANTOM))
+    x = ellipse_phantom(32, 32, rng_for(wid, SEED_PHANTOM))
     imgs = np.repeat(x[None, :], F, axis=0) if F > 1 else x[None, :]
-    noise = unit_complex_noise((F, enc.M), rng_for(cfg, SEED_NOISE))
-    return Workload("cfg1_fp64_32x32_radial16x128_c1", enc, 1e-3, imgs, noise)
+    noise = unit_complex_noise((F, enc.M), rng_for(wid, SEED_NOISE))
+    return Workload("fp64_32x32_radial16x128_c1", enc, 1e-3, imgs, noise)
 
 
-def _spiral_multicoil(cfg: int, n: int, C: int, K: int, F: int, name: str,
+def _spiral_multicoil(wid: int, n: int, C: int, K: int, F: int, name: str,
                       rel: float = 1e-3) -> Workload:
     k = vd_spiral(n, K)
-    coil = coil_maps(n, n, C, rng_for(cfg, SEED_COILS))
+    coil = coil_maps(n, n, C, rng_for(wid, SEED_COILS))
     enc = Encoding(n, n, k, coil=coil)
-    x = ellipse_phantom(n, n, rng_for(cfg, SEED_PHANTOM))
-    imgs = dynamic_frames(x, F, rng_for(cfg, SEED_DYN))
-    noise = unit_complex_noise((F, enc.M), rng_for(cfg, SEED_NOISE))
+    x = ellipse_phantom(n, n, rng_for(wid, SEED_PHANTOM))
+    imgs = dynamic_frames(x, F, rng_for(wid, SEED_DYN))
+    noise = unit_complex_noise((F, enc.M), rng_for(wid, SEED_NOISE))
     return Workload(name, enc, rel, imgs, noise)
 
 
-def config2(F: int = 1000) -> Workload:
+def spiral_64x64_c8(F: int = 1000) -> Workload:
     """64x64 (N=4096), 8 coils, 4096-sample VD spiral per coil (M=32768), F frames."""
-    return _spiral_multicoil(2, 64, 8, 4096, F, "cfg2_64x64_c8_spiral4096_f1000")
+    return _spiral_multicoil(2, 64, 8, 4096, F, "64x64_c8_spiral4096_f1000")
 
 
-def config3(F: int = 500, rel: float = 1e-3) -> Workload:
+def spiral_96x96_c16(F: int = 500, rel: float = 1e-3) -> Workload:
     """96x96 (N=9216), 16 coils, 8192-sample spiral per coil (M=131072), F frames."""
-    return _spiral_multicoil(3, 96, 16, 8192, F, "cfg3_96x96_c16_spiral8192_f500", rel)
+    return _spiral_multicoil(3, 96, 16, 8192, F, "96x96_c16_spiral8192_f500", rel)
 
 
-def config4(F: int = 200) -> Workload:
+def species5_32x32_c8(F: int = 200) -> Workload:
     """5 species {0,120,260,390,520} Hz x 32x32 (N=5120), 8 coils, 6144-sample
     single-shot spiral at 4 us dwell (M=49152), B0 within +-30 Hz, F frames."""
-    cfg, n, C, K = 4, 32, 8, 6144
+    wid, n, C, K = 4, 32, 8, 6144
     k = vd_spiral(n, K, turns=8.0)
     t = sample_times(K, 4e-6)
-    coil = coil_maps(n, n, C, rng_for(cfg, SEED_COILS))
-    b0 = b0_map(n, n, rng_for(cfg, SEED_B0))
+    coil = coil_maps(n, n, C, rng_for(wid, SEED_COILS))
+    b0 = b0_map(n, n, rng_for(wid, SEED_B0))
     species = np.array([0.0, 120.0, 260.0, 390.0, 520.0])
     enc = Encoding(n, n, k, t=t, coil=coil, b0_hz=b0, species_hz=species)
-    rp = rng_for(cfg, SEED_PHANTOM)
+    rp = rng_for(wid, SEED_PHANTOM)
     maps = [ellipse_phantom(n, n, rp) for _ in range(len(species))]
-    rd = rng_for(cfg, SEED_DYN)
+    rd = rng_for(wid, SEED_DYN)
     kappa = rd.uniform(0.005, 0.03, size=len(species))
     f = np.arange(F, dtype=np.float64)
     imgs = np.concatenate([np.exp(-kappa[s] * f)[:, None] * maps[s][None, :]
                            for s in range(len(species))], axis=1)
-    noise = unit_complex_noise((F, enc.M), rng_for(cfg, SEED_NOISE))
-    return Workload("cfg4_species5_32x32_c8_spiral6144_b0_f200", enc, 1e-3, imgs, noise)
+    noise = unit_complex_noise((F, enc.M), rng_for(wid, SEED_NOISE))
+    return Workload("species5_32x32_c8_spiral6144_b0_f200", enc, 1e-3, imgs, noise)
 
 
 def small_case(seed: int, nx: int, ny: int, C: int, K: int, F: int, species=None,
@@ -323,13 +325,13 @@ class Request:
     frames: int
 
 
-def serving_trace(rate_per_s: float = 4.0, duration_s: float = 120.0, cfg: int = 5,
+def serving_trace(rate_per_s: float = 4.0, duration_s: float = 120.0, wid: int = 5,
                   sides=(32, 64, 96, 128), probs=(0.4, 0.3, 0.2, 0.1),
                   coil_choices=(1, 8, 16), reuse: float = 0.7,
                   frames_range=(50, 2000)) -> List[Request]:
     """Poisson arrivals; each request draws an image side and coil count for a
     new encoding (30%) or reuses one issued earlier (70%)."""
-    rng = rng_for(cfg, SEED_TRACE)
+    rng = rng_for(wid, SEED_TRACE)
     t = 0.0
     out: List[Request] = []
     encs: List[tuple] = []
@@ -352,10 +354,10 @@ def serving_trace(rate_per_s: float = 4.0, duration_s: float = 120.0, cfg: int =
     return out
 
 
-def serving_encoding(n: int, coils: int, enc_id: int, cfg: int = 5) -> Encoding:
+def serving_encoding(n: int, coils: int, enc_id: int, wid: int = 5) -> Encoding:
     """Encoding of a serving request: n x n grid, spiral of 2*n*n samples per coil."""
     K = 2 * n * n
     k = vd_spiral(n, K)
-    rng = np.random.default_rng(1000 * cfg + 100 + enc_id)
+    rng = np.random.default_rng(1000 * wid + 100 + enc_id)
     coil = coil_maps(n, n, coils, rng) if coils > 1 else None
     return Encoding(n, n, k, coil=coil)

@@ -46,7 +46,7 @@ def rel(a, b):
 
 
 def test_config1_every_stage(P, ctx):
-    w = synth.config1()
+    w = synth.radial_32x32_c1()
     enc = w.enc
     N, M = enc.N, enc.M
     ob = oracle.Build(enc, rel=w.rel_lambda)
@@ -135,17 +135,17 @@ def _sampled_checks(P, ctx, enc, rel_lam, F, frames, seed):
 
 
 def test_config2_full_size_sampled(P, ctx):
-    w = synth.config2(F=1)
+    w = synth.spiral_64x64_c8(F=1)
     _sampled_checks(P, ctx, w.enc, w.rel_lambda, 1000, [0, 499, 999], seed=2024)
 
 
 def test_config4_full_size_sampled(P, ctx):
-    w = synth.config4(F=1)
+    w = synth.species5_32x32_c8(F=1)
     _sampled_checks(P, ctx, w.enc, w.rel_lambda, 200, [0, 199], seed=4048)
 
 
 def test_config2_metric_properties(P, ctx):
-    w = synth.config2(F=1)
+    w = synth.spiral_64x64_c8(F=1)
     enc = w.enc
     N = enc.N
     p = P.pinv_build(ctx, enc, w.rel_lambda, P.LAMBDA_REL_MEAN_DIAG, P.FP32, P.FLAG_UNCACHED)

@@ -6,7 +6,7 @@ from paper_2410_06129_amd import synth
 
 
 def test_seeds_reproduce_bit_exactly():
-    a, b = synth.config1(), synth.config1()
+    a, b = synth.radial_32x32_c1(), synth.radial_32x32_c1()
     assert np.array_equal(a.enc.k, b.enc.k)
     assert np.array_equal(a.images, b.images)
     assert np.array_equal(a.noise, b.noise)
@@ -22,9 +22,9 @@ def test_trajectories_inside_band(traj, n):
 
 
 def test_config_shapes():
-    w1 = synth.config1()
+    w1 = synth.radial_32x32_c1()
     assert (w1.enc.N, w1.enc.M) == (1024, 2048)
-    w4 = synth.config4(F=3)
+    w4 = synth.species5_32x32_c8(F=3)
     assert (w4.enc.N, w4.enc.M, w4.enc.S) == (5120, 49152, 5)
     assert np.max(np.abs(w4.enc.b0_hz)) == pytest.approx(30.0)
     assert w4.images.shape == (3, 5120)
