@@ -222,6 +222,8 @@ def serving(args) -> dict:
         srv = P.pinv_server_create(ctx, 0, hbm_budget_bytes=int(free * args.plan_frac),
                                    max_group=16, max_inflight=2, max_builds=1)
         data_cap = int(free * (0.85 - args.plan_frac))
+        log(f"[{label}] device free {free / 2**30:.1f} of {total / 2**30:.1f} GiB; plan budget "
+            f"{free * args.plan_frac / 2**30:.1f} GiB, data cap {data_cap / 2**30:.1f} GiB")
         live = {}            # tag -> (data, image, bytes)
         lock = threading.Lock()
         in_bytes = [0]

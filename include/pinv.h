@@ -239,8 +239,11 @@ pinv_status pinv_plan_copy_buffer(const pinv_plan *p, int32_t which, void *dst, 
  * forward, metric and copy enqueued on the plan, on whatever stream. */
 pinv_status pinv_plan_release(pinv_plan *p);
 
-/* Release device memory held by the stream-ordered allocator's pool after
- * completed work (build workspace, refinement scratch) back to the device. */
+/* Hand device memory that the context's stream-ordered pools keep after
+ * completed work (refinement scratch, build workspaces, buffers of released
+ * plans) back to the device.  The library does this by itself for scratch and
+ * workspaces when less than a quarter of the device is free, and for all of it
+ * when a plan or workspace allocation fails. */
 pinv_status pinv_context_trim(pinv_context *ctx);
 
 /* Evict every cached plan no caller holds; returns the bytes freed in *freed. */
@@ -259,8 +262,11 @@ pinv_status pinv_context_usage(const pinv_context *ctx, size_t *used, size_t *bu
  * (evicting least-recently-used plans that no queued or running request
  * holds), and packs the applies of every request whose plan is ready into
  * grouped launches (pinv_apply_grouped).  Builds and applies run on two
- * internal HIP streams, so requests arriving while others run overlap on the
- * device.  Each request's result is the same as pinv_apply of its plan on its
+ * HIP streams of the library's own, so requests arriving while others run
+ * overlap on the device.  The library creates its streams (these two and the
+ * factorisation's look-ahead stream) once per device and keeps them until the
+ * process ends, so their mapping onto the process's few hardware queues does
+ * not change as contexts and servers come and go.  Each request's result is the same as pinv_apply of its plan on its
  * data alone.  A worker thread runs the scheduler; all calls are thread-safe.
  * Times are seconds on a host monotonic clock from server creation.
  * ------------------------------------------------------------------------ */

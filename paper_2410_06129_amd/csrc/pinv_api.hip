@@ -75,7 +75,14 @@ struct pinv_context {
   int device = 0;
   hipStream_t aux = nullptr;      // look-ahead stream, kept off the last CUs (blocking)
   hipStream_t aux_nb = nullptr;   // look-ahead stream for builds on the null stream
-  hipStream_t free_s = nullptr;   // stream-ordered release of plan buffers
+  // Buffers of released plans whose last uses may still run: freed into the
+  // plan pool once all their events have completed (see free_plan_memory).
+  struct PendingFree {
+    std::vector<void*> bufs;
+    std::vector<hipEvent_t> evs;
+  };
+  std::mutex free_mu;
+  std::vector<PendingFree> pending;
   hipMemPool_t build_pool = nullptr;   // build workspaces (Gram, FP64 factor, W)
   hipMemPool_t plan_pool = nullptr;    // plan buffers (R, L^-1, Gram, tables)
   // pinned staging for table uploads, reused by every build of the context:
@@ -281,27 +288,62 @@ hipError_t note_use(const pinv_plan* pc, hipStream_t s) {
   return hipEventRecord(ev, s);
 }
 
-// Return a plan's buffers.  Pooled buffers are freed stream-ordered on the
-// context's release stream after the build and every recorded use, so the
-// host does not wait and the pool can hand the memory to the next build
-// without mapping more.  Buffers from hipMalloc (no plan pool) are freed
-// after the device has finished with them.
+// Return a plan's buffers.  Pooled buffers, with the build's and every
+// recorded use's events, go on the context's pending list without waiting on
+// the host or on any stream; drain_frees hands them to the plan pool once
+// those events have completed, on the stream of the allocation that needs
+// the memory, where the pool can reuse it at once.  No stream waits on the
+// events: with few hardware queues per process a wait would also hold back
+// unrelated work sharing the waiting stream's queue.  Buffers from hipMalloc
+// (no plan pool) are freed after the device has finished with them.
 void free_plan_memory(pinv_plan* p) {
   pinv_context* c = p->ctx;
   void* const bufs[] = {p->tab32, p->tab64, p->R, p->Linv, p->gram, (void*)p->info};
-  bool ordered = p->pooled && c->free_s;
-  if (ordered) {
-    for (hipEvent_t e : p->ev)
-      if (e) ordered = ordered && hipStreamWaitEvent(c->free_s, e, 0) == hipSuccess;
-    for (hipEvent_t e : p->uses) ordered = ordered && hipStreamWaitEvent(c->free_s, e, 0) == hipSuccess;
+  if (p->pooled) {
+    pinv_context::PendingFree f;
+    for (void* q : bufs)
+      if (q) f.bufs.push_back(q);
+    for (hipEvent_t& e : p->ev)
+      if (e) f.evs.push_back(e), e = nullptr;
+    for (hipEvent_t e : p->uses) f.evs.push_back(e);
+    p->uses.clear();
+    std::lock_guard<std::mutex> g(c->free_mu);
+    c->pending.push_back(std::move(f));
+    return;
   }
-  if (!ordered) (void)hipDeviceSynchronize();
+  (void)hipDeviceSynchronize();
   for (void* q : bufs)
-    if (q) (void)(p->pooled ? hipFreeAsync(q, ordered ? c->free_s : nullptr) : hipFree(q));
+    if (q) (void)hipFree(q);
   for (hipEvent_t e : p->ev)
     if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : p->uses) (void)hipEventDestroy(e);
   p->uses.clear();
+}
+
+// Free the pending buffers whose events have all completed (all of them, after
+// waiting on the host, with `wait`) into the plan pool, stream-ordered on s.
+void drain_frees(pinv_context* c, hipStream_t s, bool wait) {
+  std::lock_guard<std::mutex> g(c->free_mu);
+  for (size_t i = 0; i < c->pending.size();) {
+    pinv_context::PendingFree& f = c->pending[i];
+    bool done = true;
+    for (hipEvent_t e : f.evs) {
+      if (wait) {
+        (void)hipEventSynchronize(e);
+      } else if (hipEventQuery(e) != hipSuccess) {
+        done = false;
+        break;
+      }
+    }
+    (void)hipGetLastError();
+    if (!done) {
+      ++i;
+      continue;
+    }
+    for (void* q : f.bufs) (void)hipFreeAsync(q, s);
+    for (hipEvent_t e : f.evs) (void)hipEventDestroy(e);
+    c->pending.erase(c->pending.begin() + i);
+  }
 }
 
 size_t plan_footprint(const Dims& d, int prec, bool no_r) {
@@ -366,26 +408,59 @@ const char* pinv_status_string(pinv_status s) {
 
 const char* pinv_last_error(void) { return g_last_error.c_str(); }
 
-// The factorisation's look-ahead stream runs the bulk of each trailing update
-// beside the next diagonal block, panel and look-ahead tiles.  It is kept off
-// the last 32 CUs, so the one-workgroup diagonal kernel and the short panel
-// launches on the build stream always find free CUs instead of queueing behind
-// the bulk update's workgroups.  A CU-masked stream is a blocking stream, which
-// the null stream would serialise against, so builds issued on the null stream
-// use a second, unmasked non-blocking stream instead.
-static bool create_aux_streams(int device, pinv_context* c) {
-  if (hipStreamCreateWithFlags(&c->aux_nb, hipStreamNonBlocking) != hipSuccess) return false;
-  if (hipStreamCreateWithFlags(&c->free_s, hipStreamNonBlocking) != hipSuccess) return false;
+// Streams the library creates for itself, one set per device, kept for the
+// life of the process.  HIP maps streams onto a few hardware queues per
+// process (four by default); streams created and destroyed with every context
+// or server landed on different queues each time, and a server whose build
+// and apply streams ended up sharing one queue served half as fast.  Created
+// once, in a fixed order, the mapping stays put.
+//  * aux: the factorisation's look-ahead stream.  It runs the bulk of each
+//    trailing update beside the next diagonal block, panel and look-ahead
+//    tiles, kept off the last 32 CUs so the one-workgroup diagonal kernel and
+//    the short panel launches on the build stream always find free CUs.  A
+//    CU-masked stream is a blocking stream, which the null stream would
+//    serialise against, so builds issued on the null stream use aux_nb.
+//  * aux_nb: unmasked, non-blocking: look-ahead for null-stream builds, the
+//    serving loop's build stream, and frees with no allocating stream.
+//  * apply: the serving loop's apply stream.
+struct DeviceStreams {
+  hipStream_t aux = nullptr, aux_nb = nullptr, apply = nullptr;
+};
+
+static bool device_streams(int device, DeviceStreams* out) {
+  static std::mutex mu;
+  static std::unordered_map<int, DeviceStreams> streams;
+  std::lock_guard<std::mutex> g(mu);
+  auto it = streams.find(device);
+  if (it != streams.end()) {
+    *out = it->second;
+    return true;
+  }
+  DeviceStreams d;
+  if (hipStreamCreateWithFlags(&d.aux_nb, hipStreamNonBlocking) != hipSuccess) return false;
+  if (hipStreamCreateWithFlags(&d.apply, hipStreamNonBlocking) != hipSuccess) return false;
+  d.aux = d.aux_nb;
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
       cus >= 128) {
     std::vector<uint32_t> mask((cus + 31) / 32, 0u);
     for (int i = 0; i < cus - 32; ++i) mask[i / 32] |= 1u << (i % 32);
-    if (hipExtStreamCreateWithCUMask(&c->aux, (uint32_t)mask.size(), mask.data()) == hipSuccess)
-      return true;
-    (void)hipGetLastError();
+    if (hipExtStreamCreateWithCUMask(&d.aux, (uint32_t)mask.size(), mask.data()) != hipSuccess) {
+      (void)hipGetLastError();
+      d.aux = d.aux_nb;
+    }
   }
-  c->aux = c->aux_nb;
+  streams[device] = d;
+  *out = d;
+  return true;
+}
+
+// The serving loop's build and apply streams on `device` (library-internal).
+extern "C++" bool pinv_serving_streams(int device, hipStream_t* build, hipStream_t* apply) {
+  DeviceStreams d;
+  if (!device_streams(device, &d)) return false;
+  *build = d.aux_nb;
+  *apply = d.apply;
   return true;
 }
 
@@ -400,10 +475,13 @@ pinv_status pinv_context_create(int device, size_t budget, pinv_context** out) {
   pinv_context* c = new pinv_context();
   c->device = device;
   c->budget = budget ? budget : (size_t)(0.9 * (double)fr);
-  if (!create_aux_streams(device, c)) {
+  DeviceStreams ds;
+  if (!device_streams(device, &ds)) {
     pinv_context_destroy(c);
-    return fail(PINV_ERR_DEVICE, "cannot create the auxiliary streams");
+    return fail(PINV_ERR_DEVICE, "cannot create the library's streams");
   }
+  c->aux = ds.aux;
+  c->aux_nb = ds.aux_nb;
   // Keep freed stream-ordered allocations (build workspaces, scratch) mapped
   // across synchronisations: the pool's default release threshold of 0 hands
   // them back at every synchronising call, and the next build then pays for
@@ -452,15 +530,15 @@ pinv_status pinv_context_destroy(pinv_context* c) {
     c->lru.clear();
     c->cache.clear();
   }
-  if (c->free_s) (void)hipStreamSynchronize(c->free_s);
+  if (c->aux_nb) {
+    drain_frees(c, c->aux_nb, true);
+    (void)hipStreamSynchronize(c->aux_nb);
+  }
   if (c->build_pool) (void)hipMemPoolDestroy(c->build_pool);
   if (c->plan_pool) (void)hipMemPoolDestroy(c->plan_pool);
   if (c->stage_ev) (void)hipEventDestroy(c->stage_ev);
   if (c->stage) (void)hipHostFree(c->stage);
-  if (c->aux && c->aux != c->aux_nb) (void)hipStreamDestroy(c->aux);
-  if (c->aux_nb) (void)hipStreamDestroy(c->aux_nb);
-  if (c->free_s) (void)hipStreamDestroy(c->free_s);
-  delete c;
+  delete c;   // the library's streams stay for the next context
   return PINV_OK;
 }
 
@@ -514,24 +592,46 @@ pinv_status pinv_encoding_key(const pinv_encoding* e, const pinv_build_opts* o, 
   return PINV_OK;
 }
 
-// Return memory that stream-ordered frees (build workspace, refinement
-// scratch) left in the device's default pool, so that allocations outside the
-// pool (plan buffers, the caller's tensors) can use it.  Only done when less
-// than a quarter of the device is free: re-mapping a freed multi-GB workspace
-// costs the next build milliseconds inside its first kernel.
-static void trim_pool(pinv_context* c, bool force = false) {
+// Return memory that stream-ordered frees left in the pools to the device, so
+// that allocations outside them (the caller's tensors) can use it: per-call
+// scratch (the device's default pool) and build workspaces (the build pool),
+// and with `plans` also freed plan buffers (the plan pool).  Unforced, only
+// when less than a quarter of the device is free: re-mapping a freed multi-GB
+// buffer costs the next build milliseconds inside its first kernel and slows
+// whatever else runs meanwhile.  Plan memory is handed back only on request or
+// when a plan or workspace allocation fails, so later plans reuse it.
+static void trim_pool(pinv_context* c, bool force, bool plans) {
   size_t fr = 0, tot = 0;
   if (!force && hipMemGetInfo(&fr, &tot) == hipSuccess && fr >= tot / 4) return;
   hipMemPool_t pool;
   if (hipDeviceGetDefaultMemPool(&pool, c->device) == hipSuccess) (void)hipMemPoolTrimTo(pool, 0);
   if (c->build_pool) (void)hipMemPoolTrimTo(c->build_pool, 0);
-  if (c->plan_pool) (void)hipMemPoolTrimTo(c->plan_pool, 0);
+  if (plans && c->plan_pool) {
+    // released plans whose work has finished go back as well
+    drain_frees(c, c->aux_nb, false);
+    (void)hipStreamSynchronize(c->aux_nb);
+    (void)hipMemPoolTrimTo(c->plan_pool, 0);
+  }
 }
+
+// Scratch and workspaces back to the device under memory pressure (the
+// serving loop calls this after each batch).
+extern "C++" void pinv_context_trim_scratch(pinv_context* c) { trim_pool(c, false, false); }
 
 // A build workspace, stream-ordered on s, from the context's build pool.
 static hipError_t workspace_alloc(void** ptr, size_t bytes, pinv_context* c, hipStream_t s) {
-  return c->build_pool ? hipMallocFromPoolAsync(ptr, bytes, c->build_pool, s)
-                       : hipMallocAsync(ptr, bytes, s);
+  auto once = [&]() {
+    return c->build_pool ? hipMallocFromPoolAsync(ptr, bytes, c->build_pool, s)
+                         : hipMallocAsync(ptr, bytes, s);
+  };
+  hipError_t e = once();
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    (void)hipStreamSynchronize(s);
+    trim_pool(c, true, true);
+    e = once();
+  }
+  return e;
 }
 
 // A plan buffer, stream-ordered on s from the context's plan pool (plain
@@ -541,11 +641,14 @@ static hipError_t plan_malloc(void** ptr, size_t bytes, pinv_context* c, hipStre
   auto once = [&]() {
     return c->plan_pool ? hipMallocFromPoolAsync(ptr, bytes, c->plan_pool, s) : hipMalloc(ptr, bytes);
   };
+  drain_frees(c, s, false);   // released plans' memory, reusable on s at once
   hipError_t e = once();
   if (e == hipErrorOutOfMemory) {
     (void)hipGetLastError();
     (void)hipStreamSynchronize(s);
-    trim_pool(c, true);
+    drain_frees(c, s, true);
+    (void)hipStreamSynchronize(s);
+    trim_pool(c, true, true);
     e = once();
   }
   return e;
@@ -723,7 +826,7 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
 
 extern "C" pinv_status pinv_context_trim(pinv_context* c) {
   if (!c) return fail(PINV_ERR_INVALID, "context is NULL");
-  trim_pool(c, true);
+  trim_pool(c, true, true);
   return PINV_OK;
 }
 
@@ -732,7 +835,7 @@ pinv_status pinv_plan_wait(pinv_plan* p) {
   if (!p->waited) {
     HIPCHK(hipSetDevice(p->ctx->device));
     HIPCHK(hipEventSynchronize(p->ev[4]));
-    trim_pool(p->ctx);
+    trim_pool(p->ctx, false, false);
     HIPCHK(hipMemcpy(&p->info_host, p->info, sizeof(int), hipMemcpyDeviceToHost));
     for (int i = 0; i < 4; ++i) HIPCHK(hipEventElapsedTime(&p->stage_ms[i], p->ev[i], p->ev[i + 1]));
     if (p->no_r) p->stage_ms[2] = p->stage_ms[3] = 0.f;   // no W or R was formed

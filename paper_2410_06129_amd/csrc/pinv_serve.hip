@@ -19,6 +19,12 @@
 #include "../../include/pinv.h"
 #include "pinv_sched.h"
 
+// Library-internal (pinv_api.hip): scratch and build workspaces back to the
+// device when memory is short; the device's build and apply streams for
+// serving, created once per process.
+void pinv_context_trim_scratch(pinv_context* c);
+bool pinv_serving_streams(int device, hipStream_t* build, hipStream_t* apply);
+
 namespace {
 
 // An encoding with its arrays copied (requests outlive the caller's buffers).
@@ -110,7 +116,7 @@ struct HipBackend {
     if (q == hipErrorNotReady) return false;
     (void)hipEventDestroy(b.ev);
     b.ev = nullptr;
-    (void)pinv_context_trim(ctx);   // refinement scratch back to the device
+    pinv_context_trim_scratch(ctx);   // refinement scratch back under memory pressure
     return true;
   }
   void release(pinv_plan* h) { pinv_plan_release(h); }
@@ -164,8 +170,7 @@ pinv_status pinv_server_create(pinv_context* ctx, int device, const pinv_server_
   s->ctx = ctx;
   s->device = device;
   s->be.ctx = ctx;
-  if (hipStreamCreateWithFlags(&s->be.build_stream, hipStreamNonBlocking) != hipSuccess ||
-      hipStreamCreateWithFlags(&s->be.apply_stream, hipStreamNonBlocking) != hipSuccess) {
+  if (!pinv_serving_streams(device, &s->be.build_stream, &s->be.apply_stream)) {
     delete s;
     return PINV_ERR_DEVICE;
   }
@@ -264,9 +269,7 @@ pinv_status pinv_server_destroy(pinv_server* s) {
   (void)hipStreamSynchronize(s->be.apply_stream);
   (void)hipStreamSynchronize(s->be.build_stream);
   s->sch.reset();   // releases every plan it holds
-  (void)hipStreamDestroy(s->be.apply_stream);
-  (void)hipStreamDestroy(s->be.build_stream);
-  delete s;
+  delete s;         // the streams are the library's, kept for the next server
   return PINV_OK;
 }
 
