@@ -234,9 +234,9 @@ pinv_status pinv_plan_copy_buffer(const pinv_plan *p, int32_t which, void *dst, 
                                   void *hip_stream);
 
 /* Drop one reference.  The last reference held by neither a caller nor the
- * cache frees the plan without waiting on the host: the frees are enqueued on
- * the context's release stream behind the build and behind every apply,
- * forward, metric and copy enqueued on the plan, on whatever stream. */
+ * cache frees the plan without waiting on the host: its buffers return to the
+ * context's plan pool once the build and every apply, forward, metric and copy
+ * enqueued on the plan, on whatever stream, have completed. */
 pinv_status pinv_plan_release(pinv_plan *p);
 
 /* Hand device memory that the context's stream-ordered pools keep after
