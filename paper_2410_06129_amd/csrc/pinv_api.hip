@@ -8,6 +8,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <list>
 #include <mutex>
 #include <string>
@@ -427,10 +428,30 @@ struct DeviceStreams {
   hipStream_t aux = nullptr, aux_nb = nullptr, apply = nullptr;
 };
 
+static std::mutex g_streams_mu;
+static std::unordered_map<int, DeviceStreams>* g_streams = nullptr;
+
+// Process exit: hand the streams back before the HIP runtime tears down (the
+// handler is registered after the runtime has initialised, so it runs first).
+static void destroy_device_streams() {
+  std::lock_guard<std::mutex> g(g_streams_mu);
+  if (!g_streams) return;
+  for (auto& kv : *g_streams) {
+    (void)hipSetDevice(kv.first);
+    if (kv.second.aux != kv.second.aux_nb) (void)hipStreamDestroy(kv.second.aux);
+    (void)hipStreamDestroy(kv.second.aux_nb);
+    (void)hipStreamDestroy(kv.second.apply);
+  }
+  g_streams->clear();
+}
+
 static bool device_streams(int device, DeviceStreams* out) {
-  static std::mutex mu;
-  static std::unordered_map<int, DeviceStreams> streams;
-  std::lock_guard<std::mutex> g(mu);
+  std::lock_guard<std::mutex> g(g_streams_mu);
+  if (!g_streams) {
+    g_streams = new std::unordered_map<int, DeviceStreams>();
+    std::atexit(destroy_device_streams);
+  }
+  auto& streams = *g_streams;
   auto it = streams.find(device);
   if (it != streams.end()) {
     *out = it->second;
