@@ -847,6 +847,7 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
 
 extern "C" pinv_status pinv_context_trim(pinv_context* c) {
   if (!c) return fail(PINV_ERR_INVALID, "context is NULL");
+  HIPCHK(hipSetDevice(c->device));
   trim_pool(c, true, true);
   return PINV_OK;
 }
@@ -1235,6 +1236,7 @@ pinv_status pinv_plan_release(pinv_plan* p) {
 
 pinv_status pinv_cache_trim(pinv_context* c, size_t* freed) {
   if (!c) return fail(PINV_ERR_INVALID, "context is NULL");
+  HIPCHK(hipSetDevice(c->device));
   std::lock_guard<std::mutex> g(c->mu);
   const size_t before = c->used;
   make_room(c, (size_t)-1 / 2);
