@@ -12,7 +12,8 @@ times (FP32 plans, 1000/200 frames in one apply call, one refinement step).
   (N=5120, M=49152, 200 frames): sampled Gram entries against the oracle's
   explicit E columns, within M * 2^-53 of max diag (the worst-case rounding of
   the oracle's own FP64 sum over M rows), and for sampled frames the
-  normal-equation residual E^H(d - E x) - lam x formed by the oracle in FP64.
+  normal-equation residual E^H(d - E x) - lam x formed by the oracle in FP64,
+  for the FP32 plan, the FP32 factor-only plan (no R) and the FP64 plan.
   Its normwise backward error ||r|| / ((max diag + lam) ||x||) bounds the
   relative forward error from below, so it must be <= the forward-error
   targets: 1e-5 for refined FP32, 1e-10 for FP64.  Frame data are seeded
@@ -45,7 +46,7 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def test_config1_every_stage(P, ctx):
+def test_radial32_every_stage(P, ctx):
     w = synth.radial_32x32_c1()
     enc = w.enc
     N, M = enc.N, enc.M
@@ -96,14 +97,19 @@ def _sampled_checks(P, ctx, enc, rel_lam, F, frames, seed):
     d = synth.random_frames((F, M), rng)
     p32 = P.pinv_build(ctx, enc, rel_lam, P.LAMBDA_REL_MEAN_DIAG, P.FP32, P.FLAG_UNCACHED)
     p64 = P.pinv_build(ctx, enc, rel_lam, P.LAMBDA_REL_MEAN_DIAG, P.FP64, P.FLAG_UNCACHED)
+    pfo = P.pinv_build(ctx, enc, rel_lam, P.LAMBDA_REL_MEAN_DIAG, P.FP32,
+                       P.FLAG_UNCACHED | P.FLAG_NO_R)
     P.pinv_plan_wait(p32)
     P.pinv_plan_wait(p64)
+    P.pinv_plan_wait(pfo)
     lam = P.pinv_plan_info_get(p32)["lambda_abs"]
     G = torch.empty((N, N), dtype=torch.complex128, device="cuda")
     P.pinv_plan_copy_buffer(p32, P.BUF_GRAM, G)
     d32 = torch.from_numpy(d.astype(np.complex64)).cuda()
     x32 = torch.empty((F, N), dtype=torch.complex64, device="cuda")
     P.pinv_apply(ctx, p32, d32, x32, refine_steps=1)
+    xfo = torch.empty((F, N), dtype=torch.complex64, device="cuda")
+    P.pinv_apply(ctx, pfo, d32, xfo, refine_steps=1)
     d64 = torch.from_numpy(d).cuda()
     x64 = torch.empty((F, N), dtype=torch.complex128, device="cuda")
     P.pinv_apply(ctx, p64, d64, x64)
@@ -120,31 +126,34 @@ def _sampled_checks(P, ctx, enc, rel_lam, F, frames, seed):
     # residual of the normal equations for sampled frames
     xs32 = x32[frames].cpu().numpy().astype(np.complex128)
     xs64 = x64[frames].cpu().numpy()
+    xsfo = xfo[frames].cpu().numpy().astype(np.complex128)
     ds = d[frames]
     scale = dmax + lam
-    for xs, tol in ((xs32, 1e-5), (xs64, 1e-10)):
+    for xs, tol in ((xs32, 1e-5), (xs64, 1e-10), (xsfo, 1e-5)):
         r = oracle.adjoint(enc, ds - oracle.forward(enc, xs)) - lam * xs
         eta = np.linalg.norm(r, axis=1) / (scale * np.linalg.norm(xs, axis=1))
         assert eta.max() <= tol, eta
-    # and the two device paths agree on every frame
-    e = (torch.linalg.vector_norm(x32.to(torch.complex128) - x64, dim=1)
-         / torch.linalg.vector_norm(x64, dim=1)).max().item()
-    assert e < 1e-5, e
+    # and the device paths (R, factor-only, FP64) agree on every frame
+    for x in (x32, xfo):
+        e = (torch.linalg.vector_norm(x.to(torch.complex128) - x64, dim=1)
+             / torch.linalg.vector_norm(x64, dim=1)).max().item()
+        assert e < 1e-5, e
     P.pinv_plan_release(p32)
     P.pinv_plan_release(p64)
+    P.pinv_plan_release(pfo)
 
 
-def test_config2_full_size_sampled(P, ctx):
+def test_spiral64_c8_full_size_sampled(P, ctx):
     w = synth.spiral_64x64_c8(F=1)
     _sampled_checks(P, ctx, w.enc, w.rel_lambda, 1000, [0, 499, 999], seed=2024)
 
 
-def test_config4_full_size_sampled(P, ctx):
+def test_species5_full_size_sampled(P, ctx):
     w = synth.species5_32x32_c8(F=1)
     _sampled_checks(P, ctx, w.enc, w.rel_lambda, 200, [0, 199], seed=4048)
 
 
-def test_config2_metric_properties(P, ctx):
+def test_spiral64_c8_metric_properties(P, ctx):
     w = synth.spiral_64x64_c8(F=1)
     enc = w.enc
     N = enc.N

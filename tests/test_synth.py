@@ -21,7 +21,7 @@ def test_trajectories_inside_band(traj, n):
     assert np.all(k >= -n / 2) and np.all(k < n / 2)
 
 
-def test_config_shapes():
+def test_workload_shapes():
     w1 = synth.radial_32x32_c1()
     assert (w1.enc.N, w1.enc.M) == (1024, 2048)
     w4 = synth.species5_32x32_c8(F=3)
@@ -32,7 +32,7 @@ def test_config_shapes():
     assert k.shape == (4096, 2)
 
 
-def test_configs_overdetermined():
+def test_workloads_overdetermined():
     for n, C, K in [(32, 1, 2048), (64, 8, 4096), (96, 16, 8192), (32, 8, 6144)]:
         assert C * K >= 2 * n * n or (n == 32 and C == 8)
 
