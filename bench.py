@@ -511,6 +511,24 @@ def main():
         torch.cuda.synchronize()
         apply_ms.append(e0.elapsed_time(e1))
         refine_ms.append(e1.elapsed_time(e2) - e0.elapsed_time(e1))
+    # applies of a few frames stream R once (HBM-bound): GB/s against 8 TB/s;
+    # 17 and 32 frames take the MFMA tiles
+    small_f = {}
+    for Fs in (1, 4, 16, 17, 32):
+        ds, xs = d32[:Fs].contiguous(), torch.empty((Fs, N), dtype=torch.complex64, device=dev)
+        ts = []
+        for _ in range(5):
+            e0.record(stream)
+            P.pinv_apply(ctx, p32, ds, xs)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = float(np.median(ts))
+        nbytes = 8.0 * (N * M + Fs * M + Fs * N)
+        small_f[str(Fs)] = {"ms": ms, "GB/s": nbytes / (ms * 1e-3) / 1e9,
+                            "hbm_frac": nbytes / (ms * 1e-3) / 8e12,
+                            "path": "rows" if Fs <= 16 else "mfma"}
+    log(f"small-F applies: {small_f}")
     metrics = metric_timings(P, ctx, p32, enc, stream, dev)
     P.pinv_plan_release(p32)
 
@@ -656,6 +674,7 @@ def main():
         "stage_ms": {"gram": st_mean[0], "chol_inv": st_mean[1], "trmm_w": st_mean[2],
                      "trmm_r": st_mean[3]},
         "apply_frames_per_s": F / (np.median(apply_ms) * 1e-3),
+        "apply_small_frames": small_f,
         "apply_refined_frames_per_s": F / ((np.median(apply_ms) + np.median(refine_ms)) * 1e-3),
         "rel_err_vs_fp64_gpu": {"max": err_final[0], "median": err_final[1],
                                 "by_refine_steps": {str(k): v[0] for k, v in err_table.items()}},

@@ -165,8 +165,11 @@ pinv_status pinv_encoding_key(const pinv_encoding *e, const pinv_build_opts *o, 
  * image = L^-H L^-1 E^H data instead, E^H data formed with E generated in the
  * plan's precision.  refine_steps (0..4) adds iterative refinement on
  * the normal equations (Eq. 6): r = E^H (d - E x) - lambda x in FP64 with E
- * regenerated in FP64, then x += L^-H L^-1 r.  The result for a frame does not
- * depend on F or on the other frames.  Errors: INVALID, NOMEM (scratch), DEVICE. */
+ * regenerated in FP64, then x += L^-H L^-1 r.  Applies of at most 16 frames
+ * stream R row by row (one pass over R, bound by HBM bandwidth); more frames
+ * run as MFMA tiles.  The two round differently; within either, the result
+ * for a frame does not depend on the other frames.  Errors: INVALID, NOMEM
+ * (scratch), DEVICE. */
 pinv_status pinv_apply(pinv_context *ctx, const pinv_plan *p, const void *data, int64_t F,
                        void *image, int32_t refine_steps, void *hip_stream);
 

@@ -966,7 +966,7 @@ pinv_status pinv_apply_grouped(pinv_context* c, int32_t n, const pinv_apply_item
     int tiles = 0;
     while (i < n && b.n < kMaxGroup && ((const pinv_plan*)items[i].plan)->prec == prec) {
       const pinv_plan* p = (const pinv_plan*)items[i].plan;
-      if (items[i].F > 0 && !p->no_r) {
+      if (items[i].F > kRowApplyMaxF && !p->no_r) {
         ApplyItemDev& it = b.it[b.n++];
         it.D = items[i].data;
         it.R = p->R;
@@ -988,6 +988,18 @@ pinv_status pinv_apply_grouped(pinv_context* c, int32_t n, const pinv_apply_item
       HIPCHK(launch_apply_b3(b, tiles, s));
     else
       HIPCHK(launch_apply<float>(b, tiles, s));
+  }
+  // a few frames: stream R row by row (bound by HBM bandwidth, not MFMA)
+  for (int j = 0; j < n; ++j) {
+    const pinv_plan* p = (const pinv_plan*)items[j].plan;
+    const int F = (int)items[j].F;
+    if (p->no_r || F <= 0 || F > kRowApplyMaxF) continue;
+    if (p->prec == PINV_FP64)
+      HIPCHK(launch_apply_rows<double>((const double*)p->R, (const double*)items[j].data,
+                                       (double*)items[j].image, p->N, p->M, F, s));
+    else
+      HIPCHK(launch_apply_rows<float>((const float*)p->R, (const float*)items[j].data,
+                                      (float*)items[j].image, p->N, p->M, F, s));
   }
   for (int j = 0; j < n; ++j) {
     pinv_plan* p = (pinv_plan*)items[j].plan;

@@ -41,6 +41,10 @@ template <typename T>
 hipError_t launch_trmm_r(const T* Li, const T* W, T* R, int N, int M, hipStream_t s);
 template <typename T> int apply_tiles(int F, int N);
 template <typename T> hipError_t launch_apply(const ApplyBatch& b, int total_tiles, hipStream_t s);
+// Applies of at most kRowApplyMaxF frames stream R row by row (HBM-bound).
+constexpr int kRowApplyMaxF = 16;
+template <typename T>
+hipError_t launch_apply_rows(const T* R, const T* D, T* X, int N, int M, int F, hipStream_t s);
 template <typename T, typename SX, typename SD>
 hipError_t launch_forward(const EncDev<T>& e, const SX* X, int F, const SD* Din, T* Dout,
                           hipStream_t s);

@@ -611,6 +611,77 @@ __global__ __launch_bounds__(256, 2) void k_adjoint(EncDev<typename Cfg::T> e, c
   });
 }
 
+// Apply for a few frames: X[f][n] = sum_m D[f][m] R[n][m], each wavefront
+// streaming RW rows of R.  At small F each element of R feeds only F
+// multiply-adds, so the apply is bound by memory bandwidth, not by MFMA: rows
+// stream through wide coalesced loads (two complex64 per lane and load when
+// VEC = 2), and each data element loaded serves RW rows, which keeps the
+// data's cache traffic (F / RW times that of R) below R's own.  Every wave
+// reduces its lane partial sums in a fixed butterfly order, so a result
+// depends only on its own row and frame.
+template <typename T, int FM, int RW, int VEC>
+__global__ __launch_bounds__(256) void k_apply_rows(const T* __restrict__ R, const T* __restrict__ D,
+                                                    T* __restrict__ X, int N, int M, int F) {
+  const int lane = threadIdx.x & 63;
+  const int n0 = (blockIdx.x * 4 + (int)(threadIdx.x >> 6)) * RW;
+  if (n0 >= N) return;   // the whole wavefront leaves; no barrier follows
+  const cx<T>* r[RW];
+#pragma unroll
+  for (int j = 0; j < RW; ++j)   // rows past N re-read row N-1 and are not written
+    r[j] = reinterpret_cast<const cx<T>*>(R) + (size_t)min(n0 + j, N - 1) * M;
+  const cx<T>* d = reinterpret_cast<const cx<T>*>(D);
+  T ar[RW][FM], ai[RW][FM];
+#pragma unroll
+  for (int j = 0; j < RW; ++j)
+#pragma unroll
+    for (int f = 0; f < FM; ++f) ar[j][f] = ai[j][f] = T(0);
+  for (int m0 = lane * VEC; m0 < M; m0 += 64 * VEC) {
+    cx<T> rv[RW][VEC];
+#pragma unroll
+    for (int j = 0; j < RW; ++j) {
+      if constexpr (VEC == 2) {
+        // M even and 16-byte aligned rows (checked by the launcher): m0 + 1 < M
+        const float4 q = *reinterpret_cast<const float4*>(r[j] + m0);
+        rv[j][0] = cx<T>{q.x, q.y};
+        rv[j][1] = cx<T>{q.z, q.w};
+      } else {
+        rv[j][0] = r[j][m0];
+      }
+    }
+#pragma unroll
+    for (int f = 0; f < FM; ++f) {
+      if (f >= F) break;
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        const cx<T> dv = d[(size_t)f * M + m0 + v];
+#pragma unroll
+        for (int j = 0; j < RW; ++j) {
+          ar[j][f] += dv.re * rv[j][v].re - dv.im * rv[j][v].im;
+          ai[j][f] += dv.re * rv[j][v].im + dv.im * rv[j][v].re;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < RW; ++j)
+#pragma unroll
+    for (int f = 0; f < FM; ++f) {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        ar[j][f] += __shfl_xor(ar[j][f], off);
+        ai[j][f] += __shfl_xor(ai[j][f], off);
+      }
+    }
+  if (lane == 0) {
+    cx<T>* x = reinterpret_cast<cx<T>*>(X);
+#pragma unroll
+    for (int j = 0; j < RW; ++j)
+#pragma unroll
+      for (int f = 0; f < FM; ++f)
+        if (f < F && n0 + j < N) x[(size_t)f * N + n0 + j] = cx<T>{ar[j][f], ai[j][f]};
+  }
+}
+
 // Triangular products on frame blocks (refinement correction, factor-only solves):
 //   mode 0: Y[f][i] = sum_{n <= i} Xin[f][n] Li[i][n]          (L^-1 x, per frame)
 //   mode 1: X[f][i] += sum_{n >= i} Yin[f][n] conj(Li[n][i])   (L^-H y, accumulated)
@@ -968,6 +1039,34 @@ hipError_t launch_herm_fill(double* G, int N, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_apply_rows(const T* R, const T* D, T* X, int N, int M, int F, hipStream_t s) {
+  if (F <= 0 || N <= 0) return hipSuccess;
+  if (F > kRowApplyMaxF) return hipErrorInvalidValue;
+  const bool vec = M % 2 == 0 && ((uintptr_t)R % 16) == 0 && ((uintptr_t)D % 16) == 0;
+  auto go = [&](auto fm, auto rw) {
+    constexpr int FM = decltype(fm)::value, RW = decltype(rw)::value;
+    const dim3 grid(cdiv(N, 4 * RW)), block(256);
+    if constexpr (sizeof(T) == 4) {
+      if (vec) {
+        hipLaunchKernelGGL((k_apply_rows<T, FM, RW, 2>), grid, block, 0, s, R, D, X, N, M, F);
+        return hipGetLastError();
+      }
+    }
+    hipLaunchKernelGGL((k_apply_rows<T, FM, RW, 1>), grid, block, 0, s, R, D, X, N, M, F);
+    return hipGetLastError();
+  };
+  // rows per wave: as many as keep the accumulators (2 FM RW values) within
+  // 64 registers
+  using std::integral_constant;
+  constexpr int W = sizeof(T) == 4 ? 4 : 2;
+  if (F <= 1) return go(integral_constant<int, 1>(), integral_constant<int, 1>());
+  if (F <= 2) return go(integral_constant<int, 2>(), integral_constant<int, W>());
+  if (F <= 4) return go(integral_constant<int, 4>(), integral_constant<int, W>());
+  if (F <= 8) return go(integral_constant<int, 8>(), integral_constant<int, W / 2 * 2 == 4 ? 4 : 2>());
+  return go(integral_constant<int, 16>(), integral_constant<int, W / 2>());
+}
+
 template <typename T, int MODE, typename SO>
 hipError_t launch_tri_frames(const T* Li, const T* In, int F, int N, SO* Out, hipStream_t s) {
   typedef typename PickCfg<T>::type Cfg;
@@ -1041,6 +1140,10 @@ template hipError_t launch_trmm_r<double>(const double*, const double*, double*,
 template int apply_tiles<float>(int, int);
 template int apply_tiles<double>(int, int);
 template hipError_t launch_apply<float>(const ApplyBatch&, int, hipStream_t);
+template hipError_t launch_apply_rows<float>(const float*, const float*, float*, int, int, int,
+                                             hipStream_t);
+template hipError_t launch_apply_rows<double>(const double*, const double*, double*, int, int, int,
+                                              hipStream_t);
 template hipError_t launch_apply<double>(const ApplyBatch&, int, hipStream_t);
 template hipError_t launch_forward<float, float, float>(const EncDev<float>&, const float*, int,
                                                         const float*, float*, hipStream_t);

@@ -415,6 +415,34 @@ def test_release_is_ordered_after_pending_applies(P, ctx):
         assert torch.equal(x, want)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_apply_paths_match_oracle(P, ctx, prec):
+    """Applies of at most 16 frames stream R row by row; more frames run as MFMA
+    tiles (ragged against 128-frame tiles here).  Both against the oracle's
+    images, at the R path's tolerances, on 1, 16, 17 and 150 frames."""
+    o = oracle_case("ragged_c3")
+    w, N, M = o["w"], o["w"].enc.N, o["w"].enc.M
+    rng = np.random.default_rng(31)
+    Fmax = 150
+    d = rng.standard_normal((Fmax, M)) + 1j * rng.standard_normal((Fmax, M))
+    x_ref = d @ o["R"].T          # the oracle's R applied frame by frame
+    pr, cdt = (P.FP64, np.complex128) if prec == "fp64" else (P.FP32, np.complex64)
+    plan = build(P, ctx, w.enc, pr, flags=P.FLAG_UNCACHED)
+    try:
+        for F in (1, 16, 17, Fmax):
+            dd = to_dev(d[:F], cdt)
+            x = torch.full((F, N), float("nan"), dtype=dd.dtype, device="cuda")
+            torch.cuda.synchronize()
+            P.pinv_apply(ctx, plan, dd, x)
+            torch.cuda.synchronize()
+            err = frame_rel(x.cpu().numpy().astype(np.complex128), x_ref[:F])
+            tol = 1e-9 if prec == "fp64" else o["kappa"] * 1e-6
+            print(f"{prec} F={F}: max err {err.max():.2e}")
+            assert err.max() < tol, (F, err.max())
+    finally:
+        P.pinv_plan_release(plan)
+
+
 def test_cache_hit_and_release(P, ctx):
     o = oracle_case("species_b0")
     a = build(P, ctx, o["w"].enc, P.FP32)
