@@ -13,6 +13,10 @@ What it computes (paper Sec. 2.2, Eq. 6 and Eq. 8):
     x   = L^-H L^-1 E^H d            (regularised least-squares image)
     R   = L^-H L^-1 E^H              (the reconstruction matrix, formed for small N)
 
+and, for fewer samples than unknowns, the right pseudoinverse (Sec. 2.2)
+
+    R   = E^H (E E^H + lam I)^-1     (RightBuild; minimum-norm solution at lam = 0)
+
 The encoding element (paper Eq. 2 and the generalised product form of Sec. 3.3,
 with the sign convention exp(-i 2 pi ...) used throughout this project):
 
@@ -269,6 +273,43 @@ class Build:
 
 def reconstruct(enc, d: np.ndarray, rel: float = None, lam: float = None) -> np.ndarray:
     return Build(enc, rel=rel, lam=lam).reconstruct(d)
+
+
+# ----------------------------------------------------------------------------
+# underdetermined problems: the right pseudoinverse  (Sec. 2.2)
+# ----------------------------------------------------------------------------
+
+def gram_rows(enc) -> np.ndarray:
+    """G' = E E^H, [M, M]: the samples' Gram matrix (small M only)."""
+    E = encoding_matrix(enc)
+    return E @ E.conj().T
+
+
+class RightBuild:
+    """Fewer samples than unknowns (M < N): R = E^H (E E^H + lam I)^-1, the
+    minimum-norm solution for lam = 0 (Sec. 2.2), through the Cholesky factor
+    of the M x M matrix E E^H + lam I = L' L'^H.  The shift is given in
+    absolute terms or as rel * trace(E E^H) / N, the same trace as E^H E's, so
+    for lam > 0 this R equals Build's (push-through identity)."""
+
+    def __init__(self, enc, rel: float = None, lam: float = None):
+        self.enc = enc
+        self.Gr = gram_rows(enc)
+        if (rel is None) == (lam is None):
+            raise ValueError("give exactly one of rel or lam")
+        N = _dims(enc)[0] * _dims(enc)[1]
+        self.lam = float(rel * np.trace(self.Gr).real / N) if lam is None else float(lam)
+        M = self.Gr.shape[0]
+        self.L = cholesky(self.Gr + self.lam * np.eye(M))
+
+    def recon_matrix(self) -> np.ndarray:
+        """R = E^H L'^-H L'^-1 = (L'^-H L'^-1 E)^H, [N, M]."""
+        return solve_normal(self.L, encoding_matrix(self.enc)).conj().T
+
+    def reconstruct(self, d: np.ndarray) -> np.ndarray:
+        """Images x = E^H (E E^H + lam I)^-1 d for frames d [F, M] -> [F, N]."""
+        y = solve_normal(self.L, np.atleast_2d(d).T)   # [M, F]
+        return adjoint(self.enc, y.T)
 
 
 # ----------------------------------------------------------------------------

@@ -248,6 +248,44 @@ def test_p8_push_through():
     assert rel(R, R2) < 1e-12
 
 
+# --- P8b: the right pseudoinverse for fewer samples than unknowns (Sec. 2.2) ---
+
+def test_p8b_right_pinv_equals_left_with_shift():
+    """M < N with lam > 0: E^H (E E^H + lam I)^-1 through the M x M factor equals
+    (E^H E + lam I)^-1 E^H through the N x N factor (two independent routes)."""
+    enc = tiny_enc(seed=23, C=2, K=9, species=[0.0, 140.0])      # M = 18 < N = 60
+    rb = oracle.RightBuild(enc, rel=1e-2)
+    lb = oracle.Build(enc, lam=rb.lam)
+    assert rb.Gr.shape == (18, 18)
+    assert abs(rb.lam - 1e-2 * np.trace(lb.G).real / 60) < 1e-12 * rb.lam
+    assert rel(rb.recon_matrix(), lb.recon_matrix()) < 1e-10
+    rng = np.random.default_rng(5)
+    d = rng.standard_normal((3, 18)) + 1j * rng.standard_normal((3, 18))
+    assert rel(rb.reconstruct(d), d @ rb.recon_matrix().T) < 1e-12
+
+
+def test_p8c_right_pinv_minimum_norm_at_zero_shift():
+    """lam = 0, full row rank: R is the Moore-Penrose pseudoinverse (numpy's SVD
+    pinv and the four Penrose conditions); R d reproduces the data exactly and
+    lies in the range of E^H (the minimum-norm solution)."""
+    enc = tiny_enc(seed=24, C=1, K=12)       # M = 12 < N = 30
+    E = oracle.encoding_matrix(enc)
+    R = oracle.RightBuild(enc, lam=0.0).recon_matrix()
+    assert rel(R, np.linalg.pinv(E)) < 1e-9
+    assert rel(E @ R @ E, E) < 1e-10
+    assert rel(R @ E @ R, R) < 1e-10
+    ER, RE = E @ R, R @ E
+    assert np.linalg.norm(ER - ER.conj().T) < 1e-10 * np.linalg.norm(ER)
+    assert np.linalg.norm(RE - RE.conj().T) < 1e-10 * np.linalg.norm(RE)
+    rng = np.random.default_rng(6)
+    d = rng.standard_normal(12) + 1j * rng.standard_normal(12)
+    x = R @ d
+    assert rel(E @ x, d) < 1e-10
+    # orthogonal to the null space of E: projection onto range(E^H) keeps x
+    Q, _ = np.linalg.qr(E.conj().T)
+    assert rel(Q @ (Q.conj().T @ x), x) < 1e-10
+
+
 # --- P9: decomposition independence: eigen route (Eq. 7) -----------------------
 
 def test_p9_eigen_route():
