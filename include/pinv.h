@@ -114,6 +114,8 @@ typedef struct {
                                  (HIP event times on the build stream; valid when ready;
                                  the last two are 0 for factor-only plans) */
   int32_t has_r;              /* 0 for plans built with PINV_FLAG_NO_R */
+  int64_t gram_order;         /* N, or M when M < N (the samples' Gram E E^H, right
+                                 pseudoinverse R = E^H (E E^H + lambda I)^-1, Sec. 2.2) */
 } pinv_plan_info;
 
 typedef struct {
@@ -136,14 +138,21 @@ pinv_status pinv_context_create(int device, size_t hbm_budget_bytes, pinv_contex
 pinv_status pinv_context_destroy(pinv_context *ctx);
 
 /* Build (or fetch from the cache) R for encoding `e` (Eq. 6, Eq. 8).
- * Enqueues on `hip_stream` and returns at once with a new reference to the
- * plan in *out (release it with pinv_plan_release).  A plan with the same key
- * already in the cache is returned without new work.  Admission: if the plan's
- * footprint exceeds the free budget, least-recently-used cached plans that no
- * caller holds are evicted; if that is not enough, NOMEM.
- * Errors: INVALID (bad encoding, lambda < 0, lambda == 0 with M < N),
- * NOMEM, DEVICE.  A non-positive-definite shifted Gram is reported by
- * pinv_plan_wait as NOT_PD. */
+ * With at least as many samples as unknowns (M >= N), R = (E^H E + lambda I)^-1
+ * E^H through the N x N Gram.  With fewer (M < N) the build takes the right
+ * pseudoinverse R = E^H (E E^H + lambda I)^-1 through the M x M samples' Gram
+ * (Sec. 2.2): the same R for lambda > 0, and the minimum-norm solution for
+ * lambda = 0; such plans (gram_order = M) take no refinement steps, no
+ * PINV_FLAG_NO_R or PINV_FLAG_GRAM_FULL and no PINV_BF16X3, their L^-1 and Gram
+ * buffers are M x M, and their stage times put W, Z = L'^-H W and R = Z^H
+ * in the last stage.  Enqueues on `hip_stream` and returns at once with a new
+ * reference to the plan in *out (release it with pinv_plan_release).  A plan
+ * with the same key already in the cache is returned without new work.
+ * Admission: if the plan's footprint exceeds the free budget,
+ * least-recently-used cached plans that no caller holds are evicted; if that
+ * is not enough, NOMEM.  Errors: INVALID (bad encoding, lambda < 0, flag
+ * combinations above), UNSUPPORTED (BF16X3 with M < N), NOMEM, DEVICE.  A
+ * non-positive-definite shifted Gram is reported by pinv_plan_wait as NOT_PD. */
 pinv_status pinv_build(pinv_context *ctx, const pinv_encoding *e, const pinv_build_opts *o,
                        void *hip_stream, pinv_plan **out);
 
@@ -165,7 +174,8 @@ pinv_status pinv_encoding_key(const pinv_encoding *e, const pinv_build_opts *o, 
  * image = L^-H L^-1 E^H data instead, E^H data formed with E generated in the
  * plan's precision.  refine_steps (0..4) adds iterative refinement on
  * the normal equations (Eq. 6): r = E^H (d - E x) - lambda x in FP64 with E
- * regenerated in FP64, then x += L^-H L^-1 r.  Applies of at most 16 frames
+ * regenerated in FP64, then x += L^-H L^-1 r (not for plans with M < N:
+ * UNSUPPORTED).  Applies of at most 16 frames
  * stream R row by row (one pass over R, bound by HBM bandwidth); more frames
  * run as MFMA tiles.  The two round differently; within either, the result
  * for a frame does not depend on the other frames.  Errors: INVALID, NOMEM

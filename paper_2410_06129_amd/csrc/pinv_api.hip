@@ -56,6 +56,8 @@ struct pinv_plan {
   void* gram = nullptr;      // full Hermitian E^H E in FP64 (refinement residuals)
   bool gram_exact = true;    // false when the Gram was formed over M rows in FP32
   bool no_r = false;         // factor-only plan: no W, no R (applies solve with L^-1)
+  bool right = false;        // M < N: Gram, factor and L^-1 are the samples' (M x M)
+  int G = 0;                 // order of the Gram and the factor: N, or M when right
   int* info = nullptr;
   bool pooled = false;             // device buffers from the context's plan pool
   size_t bytes = 0;
@@ -349,24 +351,28 @@ void drain_frees(pinv_context* c, hipStream_t s, bool wait) {
 
 size_t plan_footprint(const Dims& d, int prec, bool no_r) {
   const size_t N = d.N, M = d.M;
+  const bool right = d.M < d.N;
+  const size_t Gd = right ? M : N;   // order of the Gram and the factor
   const size_t cs = prec == PINV_FP64 ? 16 : 8;
   size_t b = 0;
-  b += 16 * N * N;              // Gram / factor workspace (FP64)
-  b += 16 * N * N;              // L^-1 in FP64 during the factorisation
-  b += cs * N * N;              // L^-1 kept
+  b += 16 * Gd * Gd;            // Gram / factor workspace (FP64)
+  b += 16 * Gd * Gd;            // L^-1 in FP64 during the factorisation
+  b += cs * Gd * Gd;            // L^-1 kept
   if (!no_r) {
-    b += cs * N * M;            // W
+    b += cs * N * M;            // W (and Z for the right pseudoinverse)
+    if (right) b += cs * N * M;
     b += cs * N * M;            // R
   }
-  b += 16 * N * N;              // the Gram kept for refinement
+  b += 16 * Gd * Gd;            // the Gram kept
   b += 64ull << 20;             // tables and slack
   return b;
 }
 
 size_t plan_resident(const Dims& d, int prec, bool no_r) {
   const size_t N = d.N, M = d.M;
+  const size_t Gd = d.M < d.N ? M : N;
   const size_t cs = prec == PINV_FP64 ? 16 : 8;
-  return (no_r ? 0 : cs * N * M) + cs * N * N + 16 * N * N + (16ull << 20);
+  return (no_r ? 0 : cs * N * M) + cs * Gd * Gd + 16 * Gd * Gd + (16ull << 20);
 }
 
 // Evict LRU plans held only by the cache until `need` bytes fit.  ctx->mu held.
@@ -589,12 +595,16 @@ static pinv_status check_build(const pinv_encoding* e, const pinv_build_opts* o,
   } else if (o->lambda_mode != PINV_LAMBDA_ABS) {
     return fail(PINV_ERR_INVALID, "unknown lambda_mode");
   }
-  if (lam == 0.0 && d->M < d->N)
-    return fail(PINV_ERR_INVALID, "lambda = 0 needs M >= N (full column rank)");
   const bool gram_full = (o->flags & PINV_FLAG_GRAM_FULL) != 0;
   const bool no_r = (o->flags & PINV_FLAG_NO_R) != 0;
   if (no_r && o->prec == PINV_BF16X3)
     return fail(PINV_ERR_INVALID, "PINV_FLAG_NO_R with PINV_BF16X3: the split products only form W and R");
+  if (d->M < d->N) {   // right pseudoinverse through the samples' Gram
+    if (no_r) return fail(PINV_ERR_INVALID, "PINV_FLAG_NO_R needs M >= N (the unknowns' Gram)");
+    if (o->prec == PINV_BF16X3)
+      return fail(PINV_ERR_UNSUPPORTED, "PINV_BF16X3 with M < N (right pseudoinverse)");
+    if (gram_full) return fail(PINV_ERR_INVALID, "PINV_FLAG_GRAM_FULL needs M >= N");
+  }
   *lam_out = lam;
   *key_out = plan_key(e, *d, lam, o->prec) ^ (gram_full ? 0xc2b2ae3d27d4eb4full : 0) ^
              (no_r ? 0x9e3779b97f4a7c15ull : 0);
@@ -719,6 +729,8 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
   p->ny = d.ny;
   p->lam = lam;
   p->no_r = no_r;
+  p->right = d.M < d.N;
+  p->G = p->right ? d.M : d.N;
   auto cleanup = [&](pinv_status rs) {
     (void)hipStreamSynchronize(s);
     free_plan_memory(p);
@@ -731,7 +743,8 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
   const size_t N = d.N, M = d.M;
   const bool f64 = o->prec == PINV_FP64;
   const size_t cs = f64 ? 16 : 8;
-  void *G = nullptr, *L64 = nullptr, *W = nullptr;
+  void *G = nullptr, *L64 = nullptr, *W = nullptr, *Z = nullptr;
+  const size_t Gd = p->G;   // order of the Gram and the factor
   hipError_t he;
 #define BCHK(expr)                                                                    \
   do {                                                                                \
@@ -742,6 +755,7 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
       if (G) (void)hipFreeAsync(G, s);                                                \
       if (L64 && L64 != p->Linv) (void)hipFreeAsync(L64, s);                          \
       if (W) (void)hipFreeAsync(W, s);                                                \
+      if (Z) (void)hipFreeAsync(Z, s);                                                \
       return cleanup(he == hipErrorOutOfMemory ? PINV_ERR_NOMEM : PINV_ERR_DEVICE);   \
     }                                                                                 \
   } while (0)
@@ -773,37 +787,49 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
   BCHK(plan_malloc((void**)&p->info, sizeof(int), c, s));
   BCHK(hipMemsetAsync(p->info, 0, sizeof(int), s));
   if (!no_r) BCHK(plan_malloc(&p->R, cs * N * M, c, s));
-  BCHK(plan_malloc(&p->Linv, cs * N * N, c, s));
-  BCHK(plan_malloc(&p->gram, 16 * N * N, c, s));
+  BCHK(plan_malloc(&p->Linv, cs * Gd * Gd, c, s));
+  BCHK(plan_malloc(&p->gram, 16 * Gd * Gd, c, s));
   p->gram_exact = !(gram_full && !f64);
-  BCHK(workspace_alloc(&G, 16 * N * N, c, s));
+  BCHK(workspace_alloc(&G, 16 * Gd * Gd, c, s));
   if (f64) {
     L64 = p->Linv;
   } else {
-    BCHK(workspace_alloc(&L64, 16 * N * N, c, s));
+    BCHK(workspace_alloc(&L64, 16 * Gd * Gd, c, s));
   }
-  BCHK(hipMemsetAsync(L64, 0, 16 * N * N, s));
+  BCHK(hipMemsetAsync(L64, 0, 16 * Gd * Gd, s));
   if (!no_r) BCHK(workspace_alloc(&W, cs * N * M, c, s));
+  if (p->right) BCHK(workspace_alloc(&Z, cs * N * M, c, s));
 
   // 1. Gram (a3) with E generated per tile (a2)
   BCHK(hipEventRecord(p->ev[0], s));
-  if (!gram_full)
+  if (p->right)
+    BCHK(launch_gram_rows(p->e64, (double*)G, s));   // FP64 E E^H over the N unknowns
+  else if (!gram_full)
     BCHK(launch_gram_shared<double>(p->e64, (double*)G, s));   // FP64 F^H F, coil products (Eq. 11)
   else if (f64)
     BCHK(launch_gram<double>(p->e64, (double*)G, 0, s));
   else
     BCHK(launch_gram<float>(p->e32, (double*)G, 2048, s));
-  BCHK(hipMemcpyAsync(p->gram, G, 16 * N * N, hipMemcpyDeviceToDevice, s));
-  BCHK(launch_herm_fill((double*)p->gram, d.N, s));
+  BCHK(hipMemcpyAsync(p->gram, G, 16 * Gd * Gd, hipMemcpyDeviceToDevice, s));
+  BCHK(launch_herm_fill((double*)p->gram, (int)Gd, s));
   BCHK(hipEventRecord(p->ev[1], s));
   // 2. shift + blocked Cholesky with L^-1 (a4), FP64
-  BCHK(launch_cholinv((double*)G, (double*)L64, d.N, lam, p->info, s,
+  BCHK(launch_cholinv((double*)G, (double*)L64, (int)Gd, lam, p->info, s,
                       s ? p->ctx->aux : p->ctx->aux_nb));
-  if (!f64) BCHK(launch_to_f32((const double*)L64, (float*)p->Linv, N * N, s));
+  if (!f64) BCHK(launch_to_f32((const double*)L64, (float*)p->Linv, Gd * Gd, s));
   BCHK(hipEventRecord(p->ev[2], s));
-  // 3. W = L^-1 E^H, R = L^-H W (a5); a factor-only plan stops at L^-1
+  // 3. W = L^-1 E^H, R = L^-H W (a5); a factor-only plan stops at L^-1.  With
+  // fewer samples than unknowns, W' = L'^-1 E, Z = L'^-H W' and R = Z^H.
   if (no_r) {
     BCHK(hipEventRecord(p->ev[3], s));
+  } else if (p->right) {
+    BCHK(hipEventRecord(p->ev[3], s));
+    if (f64)
+      BCHK(launch_right_pinv<double>(p->e64, (const double*)p->Linv, (double*)W, (double*)Z,
+                                     (double*)p->R, s));
+    else
+      BCHK(launch_right_pinv<float>(p->e32, (const float*)p->Linv, (float*)W, (float*)Z,
+                                    (float*)p->R, s));
   } else if (f64) {
     BCHK(launch_trmm_w<double>(p->e64, (const double*)p->Linv, (double*)W, s));
     BCHK(hipEventRecord(p->ev[3], s));
@@ -820,6 +846,8 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
   BCHK(hipEventRecord(p->ev[4], s));
   if (W) BCHK(hipFreeAsync(W, s));
   W = nullptr;
+  if (Z) BCHK(hipFreeAsync(Z, s));
+  Z = nullptr;
   BCHK(hipFreeAsync(G, s));
   G = nullptr;
   if (!f64) {
@@ -946,6 +974,10 @@ pinv_status pinv_apply_grouped(pinv_context* c, int32_t n, const pinv_apply_item
                                int32_t refine_steps, void* stream) {
   if (!c || (n > 0 && !items) || n < 0) return fail(PINV_ERR_INVALID, "bad arguments");
   if (refine_steps < 0 || refine_steps > 4) return fail(PINV_ERR_INVALID, "refine_steps in 0..4");
+  if (refine_steps > 0)
+    for (int i = 0; i < n; ++i)
+      if (items[i].plan && ((const pinv_plan*)items[i].plan)->right)
+        return fail(PINV_ERR_UNSUPPORTED, "refinement of a plan with M < N (right pseudoinverse)");
   hipStream_t s = (hipStream_t)stream;
   HIPCHK(hipSetDevice(c->device));
   for (int i = 0; i < n; ++i) {
@@ -1189,6 +1221,7 @@ pinv_status pinv_plan_info_get(const pinv_plan* p, pinv_plan_info* out) {
   out->device_bytes = p->bytes;
   for (int i = 0; i < 4; ++i) out->stage_ms[i] = p->waited ? p->stage_ms[i] : 0.f;
   out->has_r = p->no_r ? 0 : 1;
+  out->gram_order = p->G;
   return PINV_OK;
 }
 
@@ -1211,10 +1244,10 @@ pinv_status pinv_plan_copy_buffer(const pinv_plan* p, int32_t which, void* dst, 
     want = cs * (size_t)p->N * p->M;
   } else if (which == 1) {
     src = p->Linv;
-    want = cs * (size_t)p->N * p->N;
+    want = cs * (size_t)p->G * p->G;
   } else if (which == 2) {
     src = p->gram;
-    want = 16 * (size_t)p->N * p->N;
+    want = 16 * (size_t)p->G * p->G;
   } else {
     return fail(PINV_ERR_INVALID, "which must be 0, 1 or 2");
   }

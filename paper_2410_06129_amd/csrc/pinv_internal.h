@@ -41,6 +41,11 @@ template <typename T>
 hipError_t launch_trmm_r(const T* Li, const T* W, T* R, int N, int M, hipStream_t s);
 template <typename T> int apply_tiles(int F, int N);
 template <typename T> hipError_t launch_apply(const ApplyBatch& b, int total_tiles, hipStream_t s);
+// Fewer samples than unknowns: the samples' Gram E E^H (FP64, M x M), and
+// R = (L'^-H L'^-1 E)^H from the inverse factor L'^-1 (W, Z: M x N workspaces).
+hipError_t launch_gram_rows(const EncDev<double>& e, double* G, hipStream_t s);
+template <typename T>
+hipError_t launch_right_pinv(const EncDev<T>& e, const T* Li, T* W, T* Z, T* R, hipStream_t s);
 // Applies of at most kRowApplyMaxF frames stream R row by row (HBM-bound).
 constexpr int kRowApplyMaxF = 16;
 template <typename T>

@@ -58,6 +58,34 @@ __global__ __launch_bounds__(256, 2) void k_gram(EncDev<typename Cfg::T> e, doub
 }
 
 // ---------------------------------------------------------------------------
+// Fewer samples than unknowns (Sec. 2.2, right pseudoinverse): the samples'
+// Gram G'[m][m'] = sum_n E[m][n] conj(E[m'][n]) over the N unknowns, lower
+// triangle of M x M tiles, E generated row-wise on both sides, FP64.
+// ---------------------------------------------------------------------------
+template <class Cfg, int FEAT, bool AL>
+__global__ __launch_bounds__(256, 2) void k_gram_rows(EncDev<typename Cfg::T> e,
+                                                   double* __restrict__ G) {
+  typedef typename Cfg::T T;
+  static_assert(Cfg::BM == Cfg::BN, "square tiles");
+  int bi, bj;
+  tri_index(blockIdx.x, &bi, &bj);
+  const int M = e.M;
+  LoadGenRow<Cfg, Cfg::BM, Cfg::LDA, false, FEAT, AL> la;
+  LoadGenRow<Cfg, Cfg::BN, Cfg::LDB, true, FEAT, AL> lb;
+  la.init(e, bi * Cfg::BM);
+  lb.init(e, bj * Cfg::BN);
+  AccTile<Cfg> acc;
+  acc.zero();
+  mainloop<Cfg>(la, lb, 0, e.N, acc, smem_base<Cfg>());
+  cx<double>* Gc = reinterpret_cast<cx<double>*>(G);
+  const int r0 = bi * Cfg::BM, c0 = bj * Cfg::BN;
+  acc_foreach<Cfg>(acc, [&](int r, int c, T re, T im) {
+    const int row = r0 + r, col = c0 + c;
+    if (row < M && col < M) Gc[(size_t)row * M + col] = cx<double>{(double)re, (double)im};
+  });
+}
+
+// ---------------------------------------------------------------------------
 // Gram through the shared trajectory (Eq. 11): every coil's rows are the
 // coil-free encoding F (Fourier, species and off-resonance factors) scaled by
 // the coil map, E_c = F diag(C_c), so
@@ -418,6 +446,58 @@ __global__ __launch_bounds__(256) void k_trmm_w(EncDev<typename Cfg::T> e,
     const int row = r0 + r, col = c0 + c;
     if (row < N && col < M) O[(size_t)row * M + col] = cx<T>{re, im};
   });
+}
+
+// Right pseudoinverse, first product: W'[i][n] = sum_{m <= i} Li'[i][m] E[m][n]
+// with L' the factor of the samples' Gram (M x M) and E generated column-wise.
+template <class Cfg, int FEAT, bool AL>
+__global__ __launch_bounds__(256) void k_trmm_w_rows(EncDev<typename Cfg::T> e,
+                                                     const typename Cfg::T* __restrict__ Li,
+                                                     typename Cfg::T* __restrict__ W) {
+  typedef typename Cfg::T T;
+  const int N = e.N, M = e.M;
+  const int nbi = (M + Cfg::BM - 1) / Cfg::BM, nbj = (N + Cfg::BN - 1) / Cfg::BN;
+  const int t = blockIdx.x;
+  const int bi = nbi - 1 - t / nbj, bj = t % nbj;   // longest K ranges first
+  LoadDenseKC<Cfg, Cfg::BM, Cfg::LDA, T, false> la;
+  la.p = reinterpret_cast<const cx<T>*>(Li);
+  la.ld = M;
+  la.o0 = bi * Cfg::BM;
+  la.oend = M;
+  LoadGenCol<Cfg, Cfg::BN, Cfg::LDB, false, FEAT, AL> lb;
+  lb.init(e, bj * Cfg::BN);
+  AccTile<Cfg> acc;
+  acc.zero();
+  mainloop<Cfg>(la, lb, 0, min(M, (bi + 1) * Cfg::BM), acc, smem_base<Cfg>());
+  cx<T>* O = reinterpret_cast<cx<T>*>(W);
+  const int r0 = bi * Cfg::BM, c0 = bj * Cfg::BN;
+  acc_foreach<Cfg>(acc, [&](int r, int c, T re, T im) {
+    const int row = r0 + r, col = c0 + c;
+    if (row < M && col < N) O[(size_t)row * N + col] = cx<T>{re, im};
+  });
+}
+
+// R[n][m] = conj(Z[m][n]) through 32 x 32 LDS tiles (Z: M x N, R: N x M).
+template <typename T>
+__global__ __launch_bounds__(256) void k_conj_transpose(const T* __restrict__ Z, T* __restrict__ R,
+                                                        int M, int N) {
+  __shared__ cx<T> tile[32][33];
+  const int n0 = blockIdx.x * 32, m0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8 threads
+  const cx<T>* z = reinterpret_cast<const cx<T>*>(Z);
+  cx<T>* r = reinterpret_cast<cx<T>*>(R);
+  for (int j = ty; j < 32; j += 8) {
+    const int m = m0 + j, n = n0 + tx;
+    if (m < M && n < N) tile[j][tx] = z[(size_t)m * N + n];
+  }
+  __syncthreads();
+  for (int j = ty; j < 32; j += 8) {
+    const int n = n0 + j, m = m0 + tx;
+    if (m < M && n < N) {
+      const cx<T> v = tile[tx][j];
+      r[(size_t)n * M + m] = cx<T>{v.re, -v.im};
+    }
+  }
 }
 
 // R = L^-H W : R[i][m] = sum_{n >= i} conj(Li[n][i]) W[n][m]
@@ -808,6 +888,34 @@ hipError_t launch_gram(const EncDev<T>& e, double* G, int flush, hipStream_t s) 
   });
 }
 
+hipError_t launch_gram_rows(const EncDev<double>& e, double* G, hipStream_t s) {
+  typedef GramCfgOf<double>::type Cfg;
+  const int nb = cdiv(e.M, Cfg::BM);
+  const int tiles = nb * (nb + 1) / 2;
+  return with_feat_al(enc_features(e), e.nx % Cfg::BK == 0, [&](auto fc, auto al) {
+    hipLaunchKernelGGL((k_gram_rows<Cfg, decltype(fc)::value, decltype(al)::value>), dim3(tiles),
+                       dim3(256), smem_bytes<Cfg>(), s, e, G);
+    return hipGetLastError();
+  });
+}
+
+template <typename T>
+hipError_t launch_right_pinv(const EncDev<T>& e, const T* Li, T* W, T* Z, T* R, hipStream_t s) {
+  typedef typename PickCfg<T>::type Cfg;
+  const int tiles = cdiv(e.M, Cfg::BM) * cdiv(e.N, Cfg::BN);
+  hipError_t err = with_feat_al(enc_features(e), e.K % Cfg::BK == 0, [&](auto fc, auto al) {
+    hipLaunchKernelGGL((k_trmm_w_rows<Cfg, decltype(fc)::value, decltype(al)::value>), dim3(tiles),
+                       dim3(256), smem_bytes<Cfg>(), s, e, Li, W);
+    return hipGetLastError();
+  });
+  if (err != hipSuccess) return err;
+  err = launch_trmm_r<T>(Li, W, Z, e.M, e.N, s);   // Z = L'^-H W' (M x N)
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k_conj_transpose<T>, dim3(cdiv(e.N, 32), cdiv(e.M, 32)), dim3(256), 0, s, Z, R,
+                     e.M, e.N);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_gram_shared(const EncDev<T>& e, double* G, hipStream_t s) {
   typedef typename GramCfgOf<T>::type Cfg;
@@ -1132,6 +1240,10 @@ hipError_t launch_to_f32(const double* in, float* out, size_t n_complex, hipStre
 template hipError_t launch_gram<float>(const EncDev<float>&, double*, int, hipStream_t);
 template hipError_t launch_gram<double>(const EncDev<double>&, double*, int, hipStream_t);
 template hipError_t launch_gram_shared<float>(const EncDev<float>&, double*, hipStream_t);
+template hipError_t launch_right_pinv<float>(const EncDev<float>&, const float*, float*, float*,
+                                             float*, hipStream_t);
+template hipError_t launch_right_pinv<double>(const EncDev<double>&, const double*, double*, double*,
+                                              double*, hipStream_t);
 template hipError_t launch_gram_shared<double>(const EncDev<double>&, double*, hipStream_t);
 template hipError_t launch_trmm_w<float>(const EncDev<float>&, const float*, float*, hipStream_t);
 template hipError_t launch_trmm_w<double>(const EncDev<double>&, const double*, double*, hipStream_t);

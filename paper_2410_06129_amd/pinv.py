@@ -49,7 +49,7 @@ class pinv_plan_info(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int64), ("M", ctypes.c_int64), ("lambda_abs", ctypes.c_double),
                 ("prec", ctypes.c_int32), ("ready", ctypes.c_int32), ("key", ctypes.c_uint64),
                 ("device_bytes", ctypes.c_size_t), ("stage_ms", ctypes.c_float * 4),
-                ("has_r", ctypes.c_int32)]
+                ("has_r", ctypes.c_int32), ("gram_order", ctypes.c_int64)]
 
 
 class pinv_apply_item(ctypes.Structure):
@@ -248,7 +248,7 @@ def pinv_plan_info_get(plan: int) -> dict:
     _check(_lib.pinv_plan_info_get(plan, ctypes.byref(i)), "pinv_plan_info_get")
     return dict(N=i.N, M=i.M, lambda_abs=i.lambda_abs, prec=i.prec, ready=bool(i.ready),
                 key=i.key, device_bytes=i.device_bytes, stage_ms=list(i.stage_ms),
-                has_r=bool(i.has_r))
+                has_r=bool(i.has_r), gram_order=i.gram_order)
 
 
 def pinv_plan_buffers(plan: int):

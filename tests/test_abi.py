@@ -65,3 +65,26 @@ def test_build_options_without_device():
             assert e.status == pinv.ERR_INVALID
         else:
             raise AssertionError(f"prec {prec} flags {flags} accepted")
+
+
+def test_right_pseudoinverse_options_without_device():
+    """Fewer samples than unknowns: the plan is sized on the M x M samples' Gram
+    (Sec. 2.2); lambda = 0 is accepted (minimum-norm solution); factor-only,
+    full-Gram and BF16X3 plans are refused."""
+    ensure_built()
+    from paper_2410_06129_amd import pinv, synth
+    enc = synth.small_case(seed=6, nx=16, ny=12, C=2, K=40, F=1).enc     # M = 80 < N = 192
+    N, M = enc.N, enc.M
+    _, b = pinv.pinv_encoding_key(enc, 1e-3, prec=pinv.FP32)
+    G = 16 * M * M
+    assert b == 3 * G + 8 * M * M + 3 * 8 * N * M + (64 << 20)
+    pinv.pinv_encoding_key(enc, 0.0, lambda_mode=pinv.LAMBDA_ABS, prec=pinv.FP64)
+    for prec, flags, want in ((pinv.FP32, pinv.FLAG_NO_R, pinv.ERR_INVALID),
+                              (pinv.FP32, pinv.FLAG_GRAM_FULL, pinv.ERR_INVALID),
+                              (pinv.BF16X3, 0, pinv.ERR_UNSUPPORTED)):
+        try:
+            pinv.pinv_encoding_key(enc, 1e-3, prec=prec, flags=flags)
+        except pinv.PinvError as e:
+            assert e.status == want
+        else:
+            raise AssertionError(f"prec {prec} flags {flags} accepted")

@@ -289,10 +289,16 @@ def test_not_positive_definite_is_reported(P, ctx):
 
 
 def test_invalid_arguments(P, ctx):
+    # M < N with lambda = 0 takes the right pseudoinverse; ten identical samples
+    # (k = 0) make E E^H rank one, which the factorisation reports
     enc = synth.Encoding(8, 8, np.zeros((10, 2)))
-    with pytest.raises(P.PinvError) as ei:
-        P.pinv_build(ctx, enc, 0.0, P.LAMBDA_ABS, P.FP64)      # M < N with lambda = 0
-    assert ei.value.status == P.ERR_INVALID
+    p = P.pinv_build(ctx, enc, 0.0, P.LAMBDA_ABS, P.FP64, P.FLAG_UNCACHED)
+    try:
+        with pytest.raises(P.PinvError) as ei:
+            P.pinv_plan_wait(p)
+        assert ei.value.status == P.ERR_NOT_PD
+    finally:
+        P.pinv_plan_release(p)
     with pytest.raises(P.PinvError):
         P.pinv_build(ctx, enc, -1.0, P.LAMBDA_ABS, P.FP64)
 
