@@ -311,7 +311,7 @@ __global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ A, doub
     lb.o0 = 0;
     lb.oend = kend;
     // la indexes rows absolutely: shift its base to column k*nb of row 0
-    mainloop<Cfg>(la, lb, 0, kend, acc, smem);
+    mainloop<Cfg, false>(la, lb, 0, kend, acc, smem);
   } else {
     const int j = t - npanel;   // j < k
     r0 = k * nb;
@@ -327,7 +327,7 @@ __global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ A, doub
     lb.ld = N;
     lb.o0 = 0;
     lb.oend = nb;
-    mainloop<Cfg>(la, lb, 0, kend, acc, smem);
+    mainloop<Cfg, false>(la, lb, 0, kend, acc, smem);
   }
   __syncthreads();
   cx<double>* O = reinterpret_cast<cx<double>*>(out);
@@ -402,14 +402,14 @@ __global__ __launch_bounds__(256) void k_chol_trailing(double* __restrict__ A, d
     lb.ld = N;
     lb.o0 = c0;
     lb.oend = N;
-    mainloop<Cfg>(la, lb, 0, kw, acc, smem);
+    mainloop<Cfg, false>(la, lb, 0, kw, acc, smem);
   } else {
     LoadDenseOC<Cfg, 64, Cfg::LDB, double, false> lb;    // Y_kj[l][n] at Li[(k*nb+l)*N + j*nb + n]
     lb.p = Lc + (size_t)(k * nb) * N;
     lb.ld = N;
     lb.o0 = c0;
     lb.oend = min(N, c0 + nb);
-    mainloop<Cfg>(la, lb, 0, kw, acc, smem);
+    mainloop<Cfg, false>(la, lb, 0, kw, acc, smem);
   }
   acc_foreach<Cfg>(acc, [&](int r, int c, double re, double im) {
     const int row = r0 + r, col = c0 + c;
