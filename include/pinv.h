@@ -51,7 +51,7 @@ typedef enum {
   PINV_ERR_NOT_PD = 3,      /* a Cholesky pivot was <= 0 or NaN (message names the column) */
   PINV_ERR_DEVICE = 4,      /* a HIP runtime error */
   PINV_ERR_BUSY = 5,        /* the plan is still building (non-blocking query) */
-  PINV_ERR_UNSUPPORTED = 6  /* a valid request this build does not implement */
+  PINV_ERR_UNSUPPORTED = 6  /* a valid request this library does not implement */
 } pinv_status;
 
 typedef enum {
