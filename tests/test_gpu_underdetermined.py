@@ -113,6 +113,31 @@ def test_right_pinv_minimum_norm_at_zero_shift(P, ctx):
     assert np.linalg.norm(E @ R - np.eye(M)) < max(1e-9, kappa * 1e-14) * np.sqrt(M)
 
 
+def test_overdiscretised_grid(P, ctx):
+    """Overdiscretisation: a 24 x 20 grid (N = 480) over the k-space extent of a
+    12 x 10 one, 2 coils x 100 samples (M = 200 < N), takes the right
+    pseudoinverse; FP64 image and R against the oracle's RightBuild."""
+    rng = np.random.default_rng(141)
+    k = synth.vd_spiral(12, 100)
+    enc = synth.Encoding(24, 20, k, coil=synth.coil_maps(24, 20, 2, rng))
+    N, M = enc.N, enc.M
+    ob = oracle.RightBuild(enc, rel=1e-3)
+    p = build(P, ctx, enc, P.FP64, 1e-3, P.LAMBDA_REL_MEAN_DIAG)
+    d = rng.standard_normal((4, M)) + 1j * rng.standard_normal((4, M))
+    try:
+        assert P.pinv_plan_info_get(p)["gram_order"] == M
+        R = torch.empty((N, M), dtype=torch.complex128, device="cuda")
+        P.pinv_plan_copy_buffer(p, P.BUF_R, R)
+        dd = torch.from_numpy(d).cuda()
+        x = torch.empty((4, N), dtype=torch.complex128, device="cuda")
+        P.pinv_apply(ctx, p, dd, x)
+        torch.cuda.synchronize()
+    finally:
+        P.pinv_plan_release(p)
+    assert rel(R.cpu().numpy(), ob.recon_matrix()) < 1e-9
+    assert rel(x.cpu().numpy(), ob.reconstruct(d)) < 1e-9
+
+
 def test_right_pinv_refused_options(P, ctx):
     enc = synth.small_case(**CASES["aligned_c2"]).enc
     for prec, flags, want in ((P.BF16X3, P.FLAG_UNCACHED, P.ERR_UNSUPPORTED),
