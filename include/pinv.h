@@ -142,8 +142,8 @@ pinv_status pinv_context_destroy(pinv_context *ctx);
  * E^H through the N x N Gram.  With fewer (M < N) the build takes the right
  * pseudoinverse R = E^H (E E^H + lambda I)^-1 through the M x M samples' Gram
  * (Sec. 2.2): the same R for lambda > 0, and the minimum-norm solution for
- * lambda = 0; such plans (gram_order = M) take no refinement steps, no
- * PINV_FLAG_NO_R or PINV_FLAG_GRAM_FULL and no PINV_BF16X3, their L^-1 and Gram
+ * lambda = 0; such plans (gram_order = M) take no PINV_FLAG_NO_R or
+ * PINV_FLAG_GRAM_FULL and no PINV_BF16X3, their L^-1 and Gram
  * buffers are M x M, and their stage times put W, Z = L'^-H W and R = Z^H
  * in the last stage.  Enqueues on `hip_stream` and returns at once with a new
  * reference to the plan in *out (release it with pinv_plan_release).  A plan
@@ -174,8 +174,9 @@ pinv_status pinv_encoding_key(const pinv_encoding *e, const pinv_build_opts *o, 
  * image = L^-H L^-1 E^H data instead, E^H data formed with E generated in the
  * plan's precision.  refine_steps (0..4) adds iterative refinement on
  * the normal equations (Eq. 6): r = E^H (d - E x) - lambda x in FP64 with E
- * regenerated in FP64, then x += L^-H L^-1 r (not for plans with M < N:
- * UNSUPPORTED).  Applies of at most 16 frames
+ * regenerated in FP64, then x += L^-H L^-1 r.  Plans with M < N refine on the
+ * sample side instead: y = G'^-1 d with G' = E E^H + lambda I refined against
+ * the FP64 G', then x = E^H y with E in FP64.  Applies of at most 16 frames
  * stream R row by row (one pass over R, bound by HBM bandwidth); more frames
  * run as MFMA tiles.  The two round differently; within either, the result
  * for a frame does not depend on the other frames.  Errors: INVALID, NOMEM

@@ -968,16 +968,49 @@ static pinv_status solve_item(pinv_plan* p, const void* data, int F, void* image
   HIPCHK(f);
   return PINV_OK;
 }
+
+// Right-pseudoinverse plans (M < N) refine on the sample side: with
+// G' = E E^H + lam I = L' L'^H and x = E^H y,
+//   y = L'^-H L'^-1 d,   then per step   r = d - G' y (FP64 G', FP64 d),
+//   y += L'^-H L'^-1 r,  and finally     x = E^H y (E regenerated in FP64).
+template <typename TS>
+static pinv_status solve_right_item(pinv_plan* p, const void* data, int F, void* image, int steps,
+                                    hipStream_t s) {
+  const size_t M = p->M;
+  const TS* d = (const TS*)data;
+  const TS* Li = (const TS*)p->Linv;
+  void *y = nullptr, *t = nullptr, *r = nullptr, *d64 = nullptr;
+  hipError_t e = hipMallocAsync(&y, 2 * sizeof(TS) * (size_t)F * M, s);
+  if (e == hipSuccess) e = hipMallocAsync(&t, 2 * sizeof(TS) * (size_t)F * M, s);
+  if (e == hipSuccess) e = hipMallocAsync(&r, 2 * sizeof(TS) * (size_t)F * M, s);
+  if (e == hipSuccess && sizeof(TS) == 4) e = hipMallocAsync(&d64, 16 * (size_t)F * M, s);
+  if (e == hipSuccess) e = launch_tri_frames<TS, 0, TS>(Li, d, F, p->M, (TS*)t, s);
+  if (e == hipSuccess) e = launch_tri_frames<TS, 2, TS>(Li, (const TS*)t, F, p->M, (TS*)y, s);
+  const double* b = nullptr;
+  if constexpr (sizeof(TS) == 4) {
+    if (e == hipSuccess) e = launch_to_f64((const float*)d, (double*)d64, (size_t)F * M, s);
+    b = (const double*)d64;
+  } else {
+    b = (const double*)d;
+  }
+  for (int it = 0; it < steps && e == hipSuccess; ++it) {
+    e = launch_resid<TS, TS>((const double*)p->gram, b, (const TS*)y, F, p->M, p->lam, (TS*)r, s);
+    if (e == hipSuccess) e = launch_tri_frames<TS, 0, TS>(Li, (const TS*)r, F, p->M, (TS*)t, s);
+    if (e == hipSuccess) e = launch_tri_frames<TS, 1, TS>(Li, (const TS*)t, F, p->M, (TS*)y, s);
+  }
+  if (e == hipSuccess)
+    e = launch_adjoint<double, TS, TS, TS>(p->e64, (const TS*)y, F, nullptr, 0.0, (TS*)image, s);
+  for (void* q : {y, t, r, d64})
+    if (q) (void)hipFreeAsync(q, s);
+  HIPCHK(e);
+  return PINV_OK;
+}
 }  // extern "C++"
 
 pinv_status pinv_apply_grouped(pinv_context* c, int32_t n, const pinv_apply_item* items,
                                int32_t refine_steps, void* stream) {
   if (!c || (n > 0 && !items) || n < 0) return fail(PINV_ERR_INVALID, "bad arguments");
   if (refine_steps < 0 || refine_steps > 4) return fail(PINV_ERR_INVALID, "refine_steps in 0..4");
-  if (refine_steps > 0)
-    for (int i = 0; i < n; ++i)
-      if (items[i].plan && ((const pinv_plan*)items[i].plan)->right)
-        return fail(PINV_ERR_UNSUPPORTED, "refinement of a plan with M < N (right pseudoinverse)");
   hipStream_t s = (hipStream_t)stream;
   HIPCHK(hipSetDevice(c->device));
   for (int i = 0; i < n; ++i) {
@@ -998,7 +1031,7 @@ pinv_status pinv_apply_grouped(pinv_context* c, int32_t n, const pinv_apply_item
     int tiles = 0;
     while (i < n && b.n < kMaxGroup && ((const pinv_plan*)items[i].plan)->prec == prec) {
       const pinv_plan* p = (const pinv_plan*)items[i].plan;
-      if (items[i].F > kRowApplyMaxF && !p->no_r) {
+      if (items[i].F > kRowApplyMaxF && !p->no_r && !(p->right && refine_steps > 0)) {
         ApplyItemDev& it = b.it[b.n++];
         it.D = items[i].data;
         it.R = p->R;
@@ -1025,7 +1058,7 @@ pinv_status pinv_apply_grouped(pinv_context* c, int32_t n, const pinv_apply_item
   for (int j = 0; j < n; ++j) {
     const pinv_plan* p = (const pinv_plan*)items[j].plan;
     const int F = (int)items[j].F;
-    if (p->no_r || F <= 0 || F > kRowApplyMaxF) continue;
+    if (p->no_r || F <= 0 || F > kRowApplyMaxF || (p->right && refine_steps > 0)) continue;
     if (p->prec == PINV_FP64)
       HIPCHK(launch_apply_rows<double>((const double*)p->R, (const double*)items[j].data,
                                        (double*)items[j].image, p->N, p->M, F, s));
@@ -1044,6 +1077,17 @@ pinv_status pinv_apply_grouped(pinv_context* c, int32_t n, const pinv_apply_item
   if (refine_steps > 0) {
     for (int j = 0; j < n; ++j) {
       pinv_plan* p = (pinv_plan*)items[j].plan;
+      if (p->right) {
+        if (items[j].F <= 0) continue;
+        const pinv_status st =
+            p->prec == PINV_FP64
+                ? solve_right_item<double>(p, items[j].data, (int)items[j].F, items[j].image,
+                                           refine_steps, s)
+                : solve_right_item<float>(p, items[j].data, (int)items[j].F, items[j].image,
+                                          refine_steps, s);
+        if (st != PINV_OK) return st;
+        continue;
+      }
       pinv_status st =
           p->prec == PINV_FP64
               ? refine_item<double>(p, items[j].data, (int)items[j].F, items[j].image, refine_steps, s)

@@ -67,6 +67,7 @@ hipError_t launch_trmm_r_b3(const float* Li, const float* W, float* R, int N, in
 int apply_tiles_b3(int F, int N);
 hipError_t launch_apply_b3(const ApplyBatch& b, int total_tiles, hipStream_t s);
 hipError_t launch_to_f32(const double* in, float* out, size_t n_complex, hipStream_t s);
+hipError_t launch_to_f64(const float* in, double* out, size_t n_complex, hipStream_t s);
 template <typename T> hipError_t launch_srf_diag(const EncDev<T>& e, const T* R, T* out, hipStream_t s);
 template <typename T> hipError_t launch_srf_full(const EncDev<T>& e, const T* R, T* out, hipStream_t s);
 template <typename T>

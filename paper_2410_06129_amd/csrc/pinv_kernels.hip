@@ -871,6 +871,13 @@ __global__ void k_to_f32(const double* __restrict__ in, float* __restrict__ out,
     out[i] = (float)in[i];
 }
 
+// Elementwise FP32 -> FP64 complex copy (n complex values).
+__global__ void k_to_f64(const float* __restrict__ in, double* __restrict__ out, size_t n2) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n2;
+       i += (size_t)gridDim.x * blockDim.x)
+    out[i] = (double)in[i];
+}
+
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
@@ -1228,6 +1235,14 @@ hipError_t launch_apply_b3(const ApplyBatch& b, int, hipStream_t s) {
   return run_apply<Cfg>(b, s);
 }
 
+hipError_t launch_to_f64(const float* in, double* out, size_t n_complex, hipStream_t s) {
+  const size_t n2 = 2 * n_complex;
+  int blocks = (int)std::min<size_t>(4096, (n2 + 255) / 256);
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_to_f64, dim3(blocks), dim3(256), 0, s, in, out, n2);
+  return hipGetLastError();
+}
+
 hipError_t launch_to_f32(const double* in, float* out, size_t n_complex, hipStream_t s) {
   const size_t n2 = 2 * n_complex;
   int blocks = (int)std::min<size_t>(4096, (n2 + 255) / 256);
@@ -1273,6 +1288,9 @@ template hipError_t launch_adjoint<double, double, double, double>(const EncDev<
 template hipError_t launch_adjoint<double, float, float, double>(const EncDev<double>&, const float*,
                                                                  int, const float*, double,
                                                                  double*, hipStream_t);
+template hipError_t launch_adjoint<double, float, float, float>(const EncDev<double>&, const float*,
+                                                                int, const float*, double, float*,
+                                                                hipStream_t);
 template hipError_t launch_adjoint<float, float, float, float>(const EncDev<float>&, const float*, int,
                                                                const float*, double, float*,
                                                                hipStream_t);
