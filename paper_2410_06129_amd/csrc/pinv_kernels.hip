@@ -1198,12 +1198,9 @@ hipError_t launch_trmm_w_b3(const EncDev<float>& e, const float* Li, float* W, h
   const int tiles = cdiv(e.N, Cfg::BM) * cdiv(e.M, Cfg::BN);
   return with_feat_al(enc_features(e), e.nx % Cfg::BK == 0, [&](auto fc, auto al) {
     auto kern = k_trmm_w<Cfg, decltype(fc)::value, decltype(al)::value>;
-    static bool ok = false;
-    if (!ok) {
-      hipError_t err = allow_smem(kern, smem_bytes<Cfg>());
-      if (err != hipSuccess) return err;
-      ok = true;
-    }
+    // once per kernel (thread-safe static initialisation)
+    static const hipError_t attr = allow_smem(kern, smem_bytes<Cfg>());
+    if (attr != hipSuccess) return attr;
     hipLaunchKernelGGL(kern, dim3(tiles), dim3(256), smem_bytes<Cfg>(), s, e, Li, W);
     return hipGetLastError();
   });
@@ -1211,12 +1208,8 @@ hipError_t launch_trmm_w_b3(const EncDev<float>& e, const float* Li, float* W, h
 
 hipError_t launch_trmm_r_b3(const float* Li, const float* W, float* R, int N, int M, hipStream_t s) {
   typedef B3Cfg Cfg;
-  static bool ok = false;
-  if (!ok) {
-    hipError_t err = allow_smem(k_trmm_r<Cfg>, smem_bytes<Cfg>());
-    if (err != hipSuccess) return err;
-    ok = true;
-  }
+  static const hipError_t attr = allow_smem(k_trmm_r<Cfg>, smem_bytes<Cfg>());
+  if (attr != hipSuccess) return attr;
   const int tiles = cdiv(N, Cfg::BM) * cdiv(M, Cfg::BN);
   hipLaunchKernelGGL(k_trmm_r<Cfg>, dim3(tiles), dim3(256), smem_bytes<Cfg>(), s, Li, W, R, N, M);
   return hipGetLastError();
@@ -1226,12 +1219,8 @@ int apply_tiles_b3(int F, int N) { return cdiv(F, B3Cfg::BM) * cdiv(N, B3Cfg::BN
 
 hipError_t launch_apply_b3(const ApplyBatch& b, int, hipStream_t s) {
   typedef B3Cfg Cfg;
-  static bool ok = false;
-  if (!ok) {
-    hipError_t err = allow_smem(k_apply<Cfg>, smem_bytes<Cfg>());
-    if (err != hipSuccess) return err;
-    ok = true;
-  }
+  static const hipError_t attr = allow_smem(k_apply<Cfg>, smem_bytes<Cfg>());
+  if (attr != hipSuccess) return attr;
   return run_apply<Cfg>(b, s);
 }
 
