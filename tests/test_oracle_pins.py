@@ -414,3 +414,40 @@ def test_planted_transpose_in_cholesky_is_caught(monkeypatch):
     R_svd = (Vh.conj().T * (s / (s * s + 0.3))) @ U.conj().T
     R = po.Build(enc, lam=0.3).recon_matrix()
     assert rel(R, R_svd) > 1e-6
+
+
+# --- golden fixture: the oracle's values for two tiny encodings -----------------
+
+def test_oracle_matches_golden_fixture():
+    """tests/golden/oracle_tiny.json holds the oracle's Gram, shift, factor, R,
+    images and SRF diagonal for two tiny encodings (written by
+    tests/golden/make_golden.py, from oracle/ only, to 12 digits).  Recomputing
+    them from the stored encodings must agree: a change to the oracle's
+    conventions that the other pins miss still shows here."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_tiny.json")
+    with open(path) as fh:
+        rec = json.load(fh)
+
+    def c(a):
+        a = np.asarray(a, dtype=float)
+        return a[..., 0] + 1j * a[..., 1]
+
+    for name, case in rec["cases"].items():
+        e = case["encoding"]
+        enc = synth.Encoding(e["nx"], e["ny"], np.asarray(e["k"]),
+                             t=None if e["t"] is None else np.asarray(e["t"]),
+                             coil=None if e["coil"] is None else c(e["coil"]),
+                             b0_hz=None if e["b0_hz"] is None else np.asarray(e["b0_hz"]),
+                             species_hz=None if e["species_hz"] is None else np.asarray(e["species_hz"]))
+        v = case["values"]
+        b = oracle.Build(enc, rel=1e-2) if enc.M >= enc.N else oracle.RightBuild(enc, rel=1e-2)
+        G = b.G if enc.M >= enc.N else b.Gr
+        assert abs(b.lam - v["lam"]) <= 1e-12 * v["lam"], name
+        R = b.recon_matrix()
+        E = oracle.encoding_matrix(enc)
+        d = c(v["d"])
+        for got, want in ((G, v["G"]), (b.L, v["L"]), (R, v["R"]), (b.reconstruct(d), v["x"]),
+                          (np.diagonal(oracle.srf_matrix(R, E)), v["srf_diag"])):
+            assert rel(got, c(want)) < 1e-10, name
