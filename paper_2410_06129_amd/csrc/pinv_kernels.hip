@@ -1023,11 +1023,13 @@ hipError_t launch_trmm_r(const T* Li, const T* W, T* R, int N, int M, hipStream_
   return hipGetLastError();
 }
 
-// The apply keeps 128x128 tiles: its D operand is re-read once per tile column,
-// and with the contraction split the grid fills the GPU at one workgroup per
-// CU (measured 8.1 ms against 8.3 ms for 128x64 at 1000 frames, N = 4096).
+// The apply uses the same 128x64 3M tiles as the triangular products: with
+// the raised wave priority over the matrix products, their occupancy of two
+// workgroups per CU beats 128x128 at one (7.76 against 8.04 ms at 1000
+// frames, N = 4096, M = 32768; without the priority raise 128x128 had been
+// ahead, 8.1 against 8.3 ms).
 template <typename T> struct ApplyCfgOf;
-template <> struct ApplyCfgOf<float> { typedef TileCfg<float, 128, 128, 8, true> type; };
+template <> struct ApplyCfgOf<float> { typedef F32Cfg type; };
 template <> struct ApplyCfgOf<double> { typedef F64Cfg type; };
 
 template <typename T>
