@@ -512,11 +512,11 @@ def main():
         apply_ms.append(e0.elapsed_time(e1))
         refine_ms.append(e1.elapsed_time(e2) - e0.elapsed_time(e1))
     # applies of a few frames stream R once (HBM-bound): GB/s against 8 TB/s;
-    # 17 and 32 frames take the MFMA tiles
+    # 9 and 32 frames take the MFMA tiles
     small_f = {}
     # (left out of the counter runs, whose per-kernel averages must cover the
     # 1000-frame applies only)
-    for Fs in (() if args.pmc_calibrate else (1, 4, 16, 17, 32)):
+    for Fs in (() if args.pmc_calibrate else (1, 4, 8, 9, 32)):
         ds, xs = d32[:Fs].contiguous(), torch.empty((Fs, N), dtype=torch.complex64, device=dev)
         ts = []
         for _ in range(5):
@@ -529,7 +529,7 @@ def main():
         nbytes = 8.0 * (N * M + Fs * M + Fs * N)
         small_f[str(Fs)] = {"ms": ms, "GB/s": nbytes / (ms * 1e-3) / 1e9,
                             "hbm_frac": nbytes / (ms * 1e-3) / 8e12,
-                            "path": "rows" if Fs <= 16 else "mfma"}
+                            "path": "rows" if Fs <= 8 else "mfma"}
     log(f"small-F applies: {small_f}")
     metrics = metric_timings(P, ctx, p32, enc, stream, dev)
     P.pinv_plan_release(p32)

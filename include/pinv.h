@@ -176,7 +176,7 @@ pinv_status pinv_encoding_key(const pinv_encoding *e, const pinv_build_opts *o, 
  * the normal equations (Eq. 6): r = E^H (d - E x) - lambda x in FP64 with E
  * regenerated in FP64, then x += L^-H L^-1 r.  Plans with M < N refine on the
  * sample side instead: y = G'^-1 d with G' = E E^H + lambda I refined against
- * the FP64 G', then x = E^H y with E in FP64.  Applies of at most 16 frames
+ * the FP64 G', then x = E^H y with E in FP64.  Applies of at most 8 frames
  * stream R row by row (one pass over R, bound by HBM bandwidth); more frames
  * run as MFMA tiles.  The two round differently; within either, the result
  * for a frame does not depend on the other frames.  Errors: INVALID, NOMEM

@@ -1180,8 +1180,7 @@ hipError_t launch_apply_rows(const T* R, const T* D, T* X, int N, int M, int F, 
   if (F <= 1) return go(integral_constant<int, 1>(), integral_constant<int, 1>());
   if (F <= 2) return go(integral_constant<int, 2>(), integral_constant<int, W>());
   if (F <= 4) return go(integral_constant<int, 4>(), integral_constant<int, W>());
-  if (F <= 8) return go(integral_constant<int, 8>(), integral_constant<int, W / 2 * 2 == 4 ? 4 : 2>());
-  return go(integral_constant<int, 16>(), integral_constant<int, W / 2>());
+  return go(integral_constant<int, 8>(), integral_constant<int, W / 2 * 2 == 4 ? 4 : 2>());
 }
 
 template <typename T, int MODE, typename SO>
