@@ -8,6 +8,7 @@
  *     R     = (E^H E + lambda I)^-1 E^H                (Eq. 6, normal equations)
  *     E^H E + lambda I = L L^H,  R = L^-H L^-1 E^H     (Eq. 8, Cholesky route)
  *     image = R data                                   (Eq. 3)
+ *     R     = E^H (E E^H + lambda I)^-1 when M < N     (Sec. 2.2, right pseudoinverse)
  *
  * `lambda` here is the diagonal shift itself (the paper writes it lambda^2).
  * R depends on the encoding only, so it is built once and applied to any
@@ -56,7 +57,8 @@ typedef enum {
 
 typedef enum {
   PINV_FP64 = 0,    /* everything in FP64 (complex128 data and images) */
-  PINV_FP32 = 1,    /* Gram, R and apply on FP32 MFMA; factorisation in FP64 */
+  PINV_FP32 = 1,    /* W, R and apply on FP32 MFMA; the Gram (default form) and the
+                       factorisation in FP64 */
   PINV_BF16X3 = 2   /* as FP32 but products as three BF16 MFMAs (hi*hi + hi*lo + lo*hi) */
 } pinv_precision;
 
