@@ -973,6 +973,8 @@ static pinv_status solve_item(pinv_plan* p, const void* data, int F, void* image
 // G' = E E^H + lam I = L' L'^H and x = E^H y,
 //   y = L'^-H L'^-1 d,   then per step   r = d - G' y (FP64 G', FP64 d),
 //   y += L'^-H L'^-1 r,  and finally     x = E^H y (E regenerated in FP64).
+// y is kept in FP64 (the triangular products accumulate into it), so the
+// final product does not amplify a rounded y.
 template <typename TS>
 static pinv_status solve_right_item(pinv_plan* p, const void* data, int F, void* image, int steps,
                                     hipStream_t s) {
@@ -980,12 +982,12 @@ static pinv_status solve_right_item(pinv_plan* p, const void* data, int F, void*
   const TS* d = (const TS*)data;
   const TS* Li = (const TS*)p->Linv;
   void *y = nullptr, *t = nullptr, *r = nullptr, *d64 = nullptr;
-  hipError_t e = hipMallocAsync(&y, 2 * sizeof(TS) * (size_t)F * M, s);
+  hipError_t e = hipMallocAsync(&y, 16 * (size_t)F * M, s);
   if (e == hipSuccess) e = hipMallocAsync(&t, 2 * sizeof(TS) * (size_t)F * M, s);
   if (e == hipSuccess) e = hipMallocAsync(&r, 2 * sizeof(TS) * (size_t)F * M, s);
   if (e == hipSuccess && sizeof(TS) == 4) e = hipMallocAsync(&d64, 16 * (size_t)F * M, s);
   if (e == hipSuccess) e = launch_tri_frames<TS, 0, TS>(Li, d, F, p->M, (TS*)t, s);
-  if (e == hipSuccess) e = launch_tri_frames<TS, 2, TS>(Li, (const TS*)t, F, p->M, (TS*)y, s);
+  if (e == hipSuccess) e = launch_tri_frames<TS, 2, double>(Li, (const TS*)t, F, p->M, (double*)y, s);
   const double* b = nullptr;
   if constexpr (sizeof(TS) == 4) {
     if (e == hipSuccess) e = launch_to_f64((const float*)d, (double*)d64, (size_t)F * M, s);
@@ -994,12 +996,14 @@ static pinv_status solve_right_item(pinv_plan* p, const void* data, int F, void*
     b = (const double*)d;
   }
   for (int it = 0; it < steps && e == hipSuccess; ++it) {
-    e = launch_resid<TS, TS>((const double*)p->gram, b, (const TS*)y, F, p->M, p->lam, (TS*)r, s);
+    e = launch_resid<double, TS>((const double*)p->gram, b, (const double*)y, F, p->M, p->lam,
+                                 (TS*)r, s);
     if (e == hipSuccess) e = launch_tri_frames<TS, 0, TS>(Li, (const TS*)r, F, p->M, (TS*)t, s);
-    if (e == hipSuccess) e = launch_tri_frames<TS, 1, TS>(Li, (const TS*)t, F, p->M, (TS*)y, s);
+    if (e == hipSuccess)
+      e = launch_tri_frames<TS, 1, double>(Li, (const TS*)t, F, p->M, (double*)y, s);
   }
   if (e == hipSuccess)
-    e = launch_adjoint<double, TS, TS, TS>(p->e64, (const TS*)y, F, nullptr, 0.0, (TS*)image, s);
+    e = launch_adjoint<double, double, TS, TS>(p->e64, (const double*)y, F, nullptr, 0.0, (TS*)image, s);
   for (void* q : {y, t, r, d64})
     if (q) (void)hipFreeAsync(q, s);
   HIPCHK(e);

@@ -1288,6 +1288,12 @@ template hipError_t launch_resid<float, float>(const double*, const double*, con
                                                double, float*, hipStream_t);
 template hipError_t launch_resid<double, double>(const double*, const double*, const double*, int,
                                                  int, double, double*, hipStream_t);
+template hipError_t launch_resid<double, float>(const double*, const double*, const double*, int,
+                                                int, double, float*, hipStream_t);
+template hipError_t launch_tri_frames<float, 1, double>(const float*, const float*, int, int, double*,
+                                                        hipStream_t);
+template hipError_t launch_tri_frames<float, 2, double>(const float*, const float*, int, int, double*,
+                                                        hipStream_t);
 template hipError_t launch_tri_frames<float, 0, float>(const float*, const float*, int, int, float*,
                                                        hipStream_t);
 template hipError_t launch_tri_frames<float, 1, float>(const float*, const float*, int, int, float*,
