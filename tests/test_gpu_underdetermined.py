@@ -5,7 +5,8 @@ route with a shift and to the SVD pseudoinverse at zero shift).
 
 Tolerances: FP64 plans 1e-9 relative with a shift (kappa(E E^H + lam I) <= 1e5
 here) and kappa * 1e-14 at zero shift; FP32 plans kappa * 1e-6, as for the
-N x N route, and 1e-5 after two refinement steps (made on the sample side).  Shapes are ragged against the 64-wide FP64 and 128 x 64 FP32
+N x N route, and 1e-6 after two refinement steps (made on the sample side,
+with y held in FP64, so the limit is the FP32 rounding of the image, ~6e-8).  Shapes are ragged against the 64-wide FP64 and 128 x 64 FP32
 tiles, with the generated loaders' aligned (nx, K multiples of 8) and general
 paths, and with species and off-resonance factors.
 """
@@ -84,7 +85,7 @@ def test_right_pinv_matches_oracle(P, ctx, name, prec):
         P.pinv_plan_release(p)
     e_x2 = rel(x2.cpu().numpy().astype(np.complex128), ob.reconstruct(d))
     print(f"{name} {prec}: refined (2 steps) x {e_x2:.2e}")
-    assert e_x2 < (1e-9 if prec == "fp64" else 1e-5)
+    assert e_x2 < (1e-9 if prec == "fp64" else 1e-6)
     tol = 1e-9 if prec == "fp64" else kappa * 1e-6
     g = G.cpu().numpy()
     assert np.max(np.abs(np.tril(g) - np.tril(ob.Gr))) <= 1e-12 * np.max(np.abs(ob.Gr))
