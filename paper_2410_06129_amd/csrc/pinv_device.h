@@ -80,7 +80,9 @@ template <typename T_, int BM_, int BN_, int BK_, bool M3_ = false> struct TileC
   static constexpr int NT = 256;                 // 4 wavefronts in a 2x2 grid
   static constexpr int WTM = BM / 2, WTN = BN / 2;
   static constexpr int MB = WTM / 16, NB = WTN / 16;
-  static constexpr int PAD = sizeof(T) == 4 ? 16 : 8;
+  // FP64 3M tiles pad rows by 4 doubles: two stages then take 51 KB of LDS,
+  // so three workgroups fit in a CU's 160 KB
+  static constexpr int PAD = sizeof(T) == 4 ? 16 : (M3_ ? 4 : 8);
   static constexpr int LDA = BM + PAD, LDB = BN + PAD;
   static constexpr int A_PLANE = BK * LDA, B_PLANE = BK * LDB;
   static constexpr int STAGE = PLANES * A_PLANE + PLANES * B_PLANE;   // elements of T

@@ -15,6 +15,16 @@
 
 namespace pinv {
 
+// Workgroups per CU that a kernel's register budget is sized for: three for
+// FP64 3M tiles whose generated operand carries no species or off-resonance
+// factor (the refinement's FP64 products then fit 168 registers and their LDS
+// fits three times), two otherwise (the Gram's accumulators and the extra
+// factors spill at 168).
+template <class Cfg, int FEAT = 0> struct MinBlocks {
+  static constexpr int value =
+      (sizeof(typename Cfg::T) == 8 && IsM3<Cfg>::value && (FEAT & ~FEAT_COIL) == 0) ? 3 : 2;
+};
+
 // ---------------------------------------------------------------------------
 // Gram: G[n1][n2] = sum_m conj(E[m][n1]) E[m][n2] for tiles bi >= bj.
 // FP32 tiles flush their FP32 partial sums into the FP64 Gram every `flush`
@@ -644,7 +654,7 @@ __global__ __launch_bounds__(256, 2) void k_forward(EncDev<typename Cfg::T> e, c
 // stores its raw partial tile to work[split]; k_split_reduce then adds the
 // partials in split order (deterministic) and applies the -lam x term.
 template <class Cfg, int FEAT, typename SD, typename SX, typename SO, bool AL>
-__global__ __launch_bounds__(256, 2) void k_adjoint(EncDev<typename Cfg::T> e, const SD* __restrict__ D,
+__global__ __launch_bounds__(256, (MinBlocks<Cfg, FEAT>::value)) void k_adjoint(EncDev<typename Cfg::T> e, const SD* __restrict__ D,
                                                  int F, const SX* __restrict__ X, double lam,
                                                  SO* __restrict__ Z, int tiles, int kchunk,
                                                  typename Cfg::T* __restrict__ work) {
@@ -816,7 +826,7 @@ __global__ __launch_bounds__(256) void k_tri_frames(const typename Cfg::T* __res
 //   Out[f][a] = b[f][a] - sum_n G[a][n] X[f][n] - lam X[f][a]
 // with G the full Hermitian FP64 Gram [N][N] and b = E^H d in FP64.
 template <class Cfg, typename SX, typename SO>
-__global__ __launch_bounds__(256) void k_resid(const double* __restrict__ G,
+__global__ __launch_bounds__(256, MinBlocks<Cfg>::value) void k_resid(const double* __restrict__ G,
                                                const double* __restrict__ b,
                                                const SX* __restrict__ X, int F, int N, double lam,
                                                SO* __restrict__ Out) {
