@@ -782,8 +782,18 @@ __global__ __launch_bounds__(256) void k_tri_frames(const typename Cfg::T* __res
                                                     int N, SO* __restrict__ Out) {
   typedef typename Cfg::T T;
   const int nbj = (N + Cfg::BN - 1) / Cfg::BN;
-  const int t = blockIdx.x;
-  const int bi = t / nbj, bj = t % nbj;
+  const int nbi = (F + Cfg::BM - 1) / Cfg::BM;
+  // A tile's contraction length grows with its distance from the triangle's
+  // short end.  Rank r = 0 is the longest tile; the grid's first half takes
+  // ranks in descending length and its second half in ascending length, so
+  // workgroups t and t + half, which the dispatcher tends to place on one CU,
+  // carry one long and one short tile.
+  const int total = nbi * nbj, half = (total + 1) / 2;
+  const int t = (int)blockIdx.x;
+  const int r = t < half ? t : total - 1 + half - t;
+  const int jr = r / nbi;                       // 0 = longest block column
+  const int bi = r - jr * nbi;
+  const int bj = MODE == 0 ? nbj - 1 - jr : jr;
   LoadDenseKC<Cfg, Cfg::BM, Cfg::LDA, T, false> la;
   la.p = reinterpret_cast<const cx<T>*>(In);
   la.ld = N;
