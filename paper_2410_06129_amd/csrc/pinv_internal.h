@@ -166,10 +166,10 @@ template <class K> static int resident_blocks(K kernel, int threads, size_t smem
 // Split factor s of a contraction of `kchunks` chunks over a grid of `tiles`
 // workgroups with `slots` resident at once: the s (1..4, at least 16 chunks
 // per split) with the fewest full-length rounds ceil(tiles * s / slots) / s.
-static inline int pick_split(long tiles, int slots, int kchunks) {
+static inline int pick_split(long tiles, int slots, int kchunks, int max_split = 4) {
   int best = 1;
   double best_cost = (double)((tiles + slots - 1) / slots);
-  for (int s = 2; s <= 4 && kchunks / s >= 16; ++s) {
+  for (int s = 2; s <= max_split && kchunks / s >= 16; ++s) {
     const double cost = (double)((tiles * s + slots - 1) / slots) / s;
     if (cost < best_cost - 1e-9) {
       best = s;

@@ -1051,6 +1051,13 @@ hipError_t launch_trmm_r(const T* Li, const T* W, T* R, int N, int M, hipStream_
 template <typename T> struct ApplyCfgOf;
 template <> struct ApplyCfgOf<float> { typedef F32Cfg type; };
 template <> struct ApplyCfgOf<double> { typedef F64Cfg type; };
+// FP32 applies of at most 32 frames run on 32x128 tiles: a 128-frame tile
+// would spend most of its matrix products on padding rows.
+typedef TileCfg<float, 32, 128, 8, true> F32FewFramesCfg;
+constexpr int kFewFramesMaxF = 32;
+// A grouped apply of few frames has few tiles, so its contraction may be split
+// up to 16 ways (the other split launches stop at 4).
+constexpr int kApplyMaxSplit = 16;
 
 template <typename T>
 int apply_tiles(int F, int N) {
@@ -1070,7 +1077,7 @@ static hipError_t run_apply(ApplyBatch b, hipStream_t s) {
     ApplyItemDev& it = b.it[i];
     const int nchunks = cdiv(it.M, Cfg::BK);
     it.ntile = cdiv(it.F, Cfg::BM) * cdiv(it.N, Cfg::BN);
-    it.splits = pick_split(it.ntile, slots, nchunks);
+    it.splits = pick_split(it.ntile, slots, nchunks, kApplyMaxSplit);
     it.kchunk = cdiv(nchunks, it.splits) * Cfg::BK;
     it.tile0 = tiles;
     it.work = nullptr;
@@ -1107,7 +1114,25 @@ static hipError_t run_apply(ApplyBatch b, hipStream_t s) {
 
 template <typename T>
 hipError_t launch_apply(const ApplyBatch& b, int, hipStream_t s) {
-  return run_apply<typename ApplyCfgOf<T>::type>(b, s);
+  if constexpr (std::is_same<T, float>::value) {
+    // items go to the tile shape their own frame count selects, so an item's
+    // result does not depend on the other items of the group
+    ApplyBatch few, many;
+    few.n = many.n = 0;
+    for (int i = 0; i < b.n; ++i) {
+      if (b.it[i].F <= kFewFramesMaxF)
+        few.it[few.n++] = b.it[i];
+      else
+        many.it[many.n++] = b.it[i];
+    }
+    if (few.n) {
+      const hipError_t err = run_apply<F32FewFramesCfg>(few, s);
+      if (err != hipSuccess) return err;
+    }
+    return many.n ? run_apply<F32Cfg>(many, s) : hipSuccess;
+  } else {
+    return run_apply<typename ApplyCfgOf<T>::type>(b, s);
+  }
 }
 
 template <typename T, typename SX, typename SD>
