@@ -1,26 +1,36 @@
 """Benchmark of the Pinv-Recon hot path on one MI355X.
 
-Workload: 64x64 image (N=4096), 8 coils, variable-density spiral of 4096
-samples per coil (M=32768), 1000 dynamic frames, shift 1e-3 * mean diag(E^H E).
+Default workload (the shape the R-build bar is stated at): 128x128 image
+(N=16384), 8 coils, variable-density spiral of 2N = 32768 samples per coil
+(M=262144), 1000 dynamic frames, shift 1e-3 * mean diag(E^H E).
 
-One step = build R with the FP32 path (Gram, FP64 blocked Cholesky with L^-1,
-W = L^-1 E^H, R = L^-H W) from the encoding alone, then reconstruct all 1000
-frames (image = R data) with the refinement steps needed to reach 1e-5
-relative error against the plain FP64 GPU path.  Inputs are resident in HBM
-before the timed region; the plan is built fresh every step (uncached).
+One step = build R with the FP32 path from the encoding alone (Gram through the
+point-spread function in FP64, FP64 blocked Cholesky with L^-1, W = L^-1 E^H
+and R = L^-H W on FP32 MFMA), then reconstruct all frames (image = R data)
+with the refinement steps needed for 1e-5 relative error against the plain
+FP64 GPU path.  Inputs are resident in HBM before the timed region; every step
+builds a fresh, uncached plan.
 
-value = complex-equivalent algorithmic TFLOP/s of the whole step:
-  (Gram 4MN^2 + Cholesky 4N^3/3 + two triangular solves 8MN^2 + apply 8NMF) / step time.
-The JSON line also carries the build-only rate, apply frames/s, the same for
-the plain FP64 GPU path, the error table, a roofline entry for the dominant
-kernel and the CPU oracle baseline.
+value = executed complex-equivalent TFLOP/s of the whole step: the work the
+kernels run (PSF Gram 8K(2nx-1)(2ny-1) + coil products 8CN^2, Cholesky with
+L^-1 8N^3/3, W 4MN^2, R 4MN^2, apply 8NMF, refinement 8MNF + 16N^2F per step)
+divided by the step time.  The standard count of a normal-equation build
+(12MN^2 + 4N^3/3: a Gram over all M rows) is reported beside it, labelled as
+an effective rate, since the PSF Gram does not run those flops.
+
+The JSON line also carries the build's stage times and executed rate, apply
+frames/s (plain and refined), the FP32 plan with R formed in FP64 (no
+refinement needed), the BF16-split and factor-only plans, the plain FP64 GPU
+comparator, few-frame applies against HBM bandwidth, the 64x64 / 8-coil
+workload's figures, a roofline entry for the dominant kernel and the CPU
+oracle baseline.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
+import platform
 import sys
 import time
 
@@ -33,55 +43,112 @@ import numpy as np  # noqa: E402
 METRIC = "R-build TFLOP/s + apply frames/s vs plain FP64 GPU at stated error; p50/p99"
 PEAK_FP32_MFMA = 157.3   # TFLOP/s, MI355X dense FP32 matrix
 PEAK_FP64_MFMA = 78.6
+PEAK_HBM = 8.0e12        # B/s
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w) -> dict:
-    """Oracle Gram E^H E (FP64, numpy) over all M rows of the workload, as Eq. 11
-    writes it: the build's first stage, a bounded sample of about 10 s of CPU work."""
+# ----------------------------------------------------------------------------
+# work counts (complex-equivalent: 8 real flops per complex multiply-add)
+# ----------------------------------------------------------------------------
+
+def gram_flops_executed(enc, form: str) -> float:
+    N, K, C, S = enc.N, enc.K, enc.C, enc.S
+    if form == "psf":
+        return 8.0 * K * (2 * enc.nx - 1) * (2 * enc.ny - 1) * S * S + 8.0 * C * N * N
+    if form == "shared":
+        return 4.0 * K * N * N + 8.0 * C * N * N / 2
+    return 4.0 * enc.M * N * N
+
+
+def build_flops_executed(enc, form: str = "psf") -> dict:
+    N, M = enc.N, enc.M
+    return {"gram": gram_flops_executed(enc, form), "chol_inv": 8.0 * N ** 3 / 3.0,
+            "trmm_w": 4.0 * M * N * N, "trmm_r": 4.0 * M * N * N}
+
+
+def build_flops_standard(enc) -> float:
+    N, M = enc.N, enc.M
+    return 12.0 * M * N * N + 4.0 * N ** 3 / 3.0
+
+
+def refine_flops(enc, F: int, steps: int) -> float:
+    if steps <= 0:
+        return 0.0
+    N, M = enc.N, enc.M
+    return 8.0 * M * N * F + steps * 16.0 * N * N * F
+
+
+# ----------------------------------------------------------------------------
+# CPU oracle baseline
+# ----------------------------------------------------------------------------
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(enc, rows: int = 4096) -> dict:
+    """The oracle's Gram (explicit FP64 E, E_b^H E_b with a library matmul) over
+    the first `rows` rows of the workload's encoding: one row block of the sum
+    over all M rows it forms for a full build, about 10-20 s on the host."""
     import oracle
-    enc = w.enc
-    sub = enc
+    from threadpoolctl import threadpool_info
+    sub = type(enc)(enc.nx, enc.ny, enc.k[:rows], t=None if enc.t is None else enc.t[:rows],
+                    coil=None if enc.coil is None else enc.coil[:1], b0_hz=enc.b0_hz,
+                    species_hz=enc.species_hz)
     t0 = time.perf_counter()
     oracle.gram(sub)
     dt = time.perf_counter() - t0
-    flops = 4.0 * sub.M * sub.N * sub.N
-    threads = len(os.sched_getaffinity(0))
-    try:
-        from threadpoolctl import threadpool_info
-        nums = [p.get("num_threads", 0) for p in threadpool_info() if p.get("user_api") == "blas"]
-        if nums:
-            threads = max(nums)
-    except Exception:
-        pass
+    flops = 4.0 * rows * enc.N * enc.N
+    blas = [p.get("num_threads", 0) for p in threadpool_info() if p.get("user_api") == "blas"]
+    threads = max(blas) if blas else 1
+    full_s = dt * (4.0 * enc.M * enc.N ** 2) / flops
     return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": f"oracle Gram over all {sub.M} rows (N={sub.N}, E formed in FP64), "
-                      f"{flops:.3g} complex-equivalent flops in {dt:.2f} s"}
+            "sample": f"oracle Gram over the first {rows} of M={enc.M} rows (N={enc.N}, E formed "
+                      f"explicitly in FP64, one coil): {flops:.3g} complex-equivalent flops in "
+                      f"{dt:.2f} s; the full Gram alone would take about {full_s:.0f} s",
+            "cpu_model": cpu_model(), "affinity_cores": len(os.sched_getaffinity(0)),
+            "blas_threads": threads}
+
+
+# ----------------------------------------------------------------------------
+# HBM traffic of the dominant kernels from the counter record
+# ----------------------------------------------------------------------------
+
+DEVICE_SOURCES = ("pinv_device.h", "pinv_internal.h", "pinv_trmm.hip", "pinv_apply.hip")
 
 
 def kernel_source_hash() -> str:
-    """Hash of the device sources; counter readings are valid only for this hash."""
+    """Hash of the device sources the counted kernels come from; counter
+    readings are valid only for this hash."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("pinv_device.h", "pinv_kernels.hip"):
+    for f in DEVICE_SOURCES:
         with open(os.path.join(ROOT, "paper_2410_06129_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, workload: str):
     """HBM bytes per launch of `kernel` from profiles/pmc_traffic.json (FETCH_SIZE
     and WRITE_SIZE counter runs, scaled by a plain copy of known size), or None
-    if no reading exists for the current kernel sources."""
+    if no reading exists for the current sources and this workload."""
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    if rec.get("source_hash") != kernel_source_hash() or kernel not in rec.get("kernels", {}):
+    if (rec.get("source_hash") != kernel_source_hash() or rec.get("workload") != workload
+            or kernel not in rec.get("kernels", {})):
         return None
     k = rec["kernels"][kernel]
     return {"bytes_per_launch": k["fetch_bytes"] + k["write_bytes"], "fetch_bytes": k["fetch_bytes"],
@@ -94,8 +161,9 @@ PMC_KERNELS = {"trmm_w": "k_trmm_w<pinv::TileCfg<float", "trmm_r": "k_trmm_r<pin
 
 
 def algorithmic_bytes(N: int, M: int, F: int) -> dict:
-    """Compulsory HBM bytes per launch (complex64): L^-1 lower triangle, W and R
-    once each; for the apply D, R and X once."""
+    """Compulsory HBM bytes per launch (complex64): L^-1 lower triangle and W
+    written once; L^-1 and W read and R written once; for the apply D, R and X
+    once."""
     tri = 8.0 * N * N / 2
     return {"trmm_w": tri + 8.0 * N * M, "trmm_r": tri + 16.0 * N * M,
             "apply": 8.0 * F * M + 8.0 * N * M + 8.0 * F * N}
@@ -103,11 +171,13 @@ def algorithmic_bytes(N: int, M: int, F: int) -> dict:
 
 def pmc_summary(dirs, frames: int) -> dict:
     """Per-launch HBM bytes of the dominant FP32 kernels from two rocprofv3 counter
-    runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), scaled by what the same
-    counters read for the plain 2 GiB copy that --pmc-calibrate runs first."""
+    runs of `bench.py --pmc-run` (FETCH_SIZE, WRITE_SIZE; KiB per dispatch),
+    scaled by what the same counters read for the plain 2 GiB copy it runs first."""
     import sqlite3
+    import glob
 
-    def read(db, counter):
+    def read(d, counter):
+        db = sorted(glob.glob(os.path.join(d, "**", "*results.db"), recursive=True))[0]
         con = sqlite3.connect(db)
         rows = con.execute("select kernel_name, value from counters_collection where counter_name = ?",
                            (counter,)).fetchall()
@@ -115,13 +185,13 @@ def pmc_summary(dirs, frames: int) -> dict:
         return rows
 
     from paper_2410_06129_amd import synth
-    enc = synth.spiral_64x64_c8(F=1).enc
-    N, M = enc.N, enc.M
+    w = synth.spiral_128x128_c8(F=1)
+    N, M = w.enc.N, w.enc.M
     alg = algorithmic_bytes(N, M, frames)
     vals = {}
     for counter, d in zip(("FETCH_SIZE", "WRITE_SIZE"), dirs):
-        rows = read(os.path.join(d, "run_results.db"), counter)
-        copy = max(v for n, v in rows if "copyBuffer" in n)
+        rows = read(d, counter)
+        copy = max(v for n, v in rows if "copyBuffer" in n or "elementwise_kernel" in n)
         per = {}
         for key, pat in PMC_KERNELS.items():
             xs = [v for n, v in rows if pat in n]
@@ -130,13 +200,12 @@ def pmc_summary(dirs, frames: int) -> dict:
     copy_bytes = 2.0 ** 31
     fscale = copy_bytes / (vals["FETCH_SIZE"][0] * 1024.0)
     wscale = copy_bytes / (vals["WRITE_SIZE"][0] * 1024.0)
-    rec = {"source_hash": kernel_source_hash(),
-           "workload": f"64x64 image, 8 coils, M={M}, {frames} frames",
-           "commands": [f"rocprofv3 --pmc {c} -d <out> -o run -- python3 bench.py --steps 1 --warmup 0 "
-                        "--fp64-reps 1 --no-cpu-baseline --pmc-calibrate" for c in ("FETCH_SIZE", "WRITE_SIZE")],
-           "calibration": {"kernel": "__amd_rocclr_copyBuffer (2 GiB device copy)",
-                           "fetch_kib": vals["FETCH_SIZE"][0], "write_kib": vals["WRITE_SIZE"][0],
-                           "fetch_scale": fscale, "write_scale": wscale},
+    rec = {"source_hash": kernel_source_hash(), "workload": w.name.replace("_f1", f"_f{frames}"),
+           "commands": [f"rocprofv3 --pmc {c} -d <out> -o run -- python3 bench.py --pmc-run"
+                        for c in ("FETCH_SIZE", "WRITE_SIZE")],
+           "calibration": {"kernel": "2 GiB device copy", "fetch_kib": vals["FETCH_SIZE"][0],
+                           "write_kib": vals["WRITE_SIZE"][0], "fetch_scale": fscale,
+                           "write_scale": wscale},
            "kernels": {}}
     for key in PMC_KERNELS:
         fk, wk = vals["FETCH_SIZE"][1][key], vals["WRITE_SIZE"][1][key]
@@ -145,6 +214,87 @@ def pmc_summary(dirs, frames: int) -> dict:
         rec["kernels"][key] = {"fetch_kib": fk, "write_kib": wk, "fetch_bytes": fk * 1024.0 * fscale,
                                "write_bytes": wk * 1024.0 * wscale, "algorithmic_bytes": alg[key]}
     return rec
+
+
+# ----------------------------------------------------------------------------
+# helpers on the device
+# ----------------------------------------------------------------------------
+
+class Timer:
+    """HIP events on the launch stream."""
+
+    def __init__(self, stream):
+        import torch
+        self.stream = stream
+        self.e0 = torch.cuda.Event(enable_timing=True)
+        self.e1 = torch.cuda.Event(enable_timing=True)
+
+    def __enter__(self):
+        self.e0.record(self.stream)
+        return self
+
+    def __exit__(self, *exc):
+        import torch
+        self.e1.record(self.stream)
+        torch.cuda.synchronize()
+        self.ms = self.e0.elapsed_time(self.e1)
+
+
+def stage_dict(st):
+    return {"gram": float(st[0]), "chol_inv": float(st[1]), "trmm_w": float(st[2]),
+            "trmm_r": float(st[3])}
+
+
+def make_inputs(P, ctx, w, F, dev, seed=2026):
+    """data = E x (FP64 GPU forward of the ground-truth frames) + complex
+    Gaussian noise at the workload's SNR, drawn on the device from a seeded
+    generator; and the reference images x_ref from a factor-only FP64 plan
+    (L^-H L^-1 E^H d with one FP64 refinement step).  Returns d64, d32, x_ref."""
+    import torch
+    enc = w.enc
+    N, M = enc.N, enc.M
+    q = P.pinv_build(ctx, enc, w.rel_lambda, P.LAMBDA_REL_MEAN_DIAG, P.FP64,
+                     P.FLAG_UNCACHED | P.FLAG_NO_R)
+    P.pinv_plan_wait(q)
+    x_true = torch.from_numpy(np.ascontiguousarray(w.images[:F])).to(dev)
+    d64 = torch.empty((F, M), dtype=torch.complex128, device=dev)
+    P.pinv_forward(ctx, q, x_true, d64)
+    sigma = torch.sqrt(torch.mean(torch.abs(d64) ** 2)) * 10 ** (-w.snr_db / 20)
+    if w.noise.shape[0] >= F:
+        noise = torch.from_numpy(np.ascontiguousarray(w.noise[:F])).to(dev)
+    else:
+        g = torch.Generator(device=dev).manual_seed(seed)
+        noise = torch.randn((F, M), dtype=torch.complex128, device=dev, generator=g)
+    d64 += sigma * noise
+    del noise, x_true
+    x_ref = torch.empty((F, N), dtype=torch.complex128, device=dev)
+    P.pinv_apply(ctx, q, d64, x_ref, refine_steps=1)
+    torch.cuda.synchronize()
+    P.pinv_plan_release(q)
+    d32 = d64.to(torch.complex64)
+    return d64, d32, x_ref
+
+
+def rel_err(x, x_ref):
+    import torch
+    e = (torch.linalg.vector_norm(x.to(torch.complex128) - x_ref, dim=1)
+         / torch.linalg.vector_norm(x_ref, dim=1))
+    return float(e.max()), float(e.median())
+
+
+def build_timed(P, ctx, enc, rel, prec, flags=0, **kw):
+    p = P.pinv_build(ctx, enc, rel, P.LAMBDA_REL_MEAN_DIAG, prec, flags | P.FLAG_UNCACHED, **kw)
+    P.pinv_plan_wait(p)
+    return p, P.pinv_plan_info_get(p)["stage_ms"]
+
+
+def apply_ms(P, ctx, plan, d, x, stream, refine=0, reps=3):
+    ts = []
+    for _ in range(reps):
+        with Timer(stream) as t:
+            P.pinv_apply(ctx, plan, d, x, refine_steps=refine)
+        ts.append(t.ms)
+    return float(np.median(ts))
 
 
 def metric_timings(P, ctx, plan, enc, stream, dev, reps: int = 3) -> dict:
@@ -178,28 +328,80 @@ def metric_timings(P, ctx, plan, enc, stream, dev, reps: int = 3) -> dict:
         torch.cuda.synchronize()
         ts = []
         for _ in range(reps):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            fn()
-            e1.record(stream)
-            torch.cuda.synchronize()
-            ts.append(e0.elapsed_time(e1))
+            with Timer(stream) as t:
+                fn()
+            ts.append(t.ms)
         ms = float(np.median(ts))
         rate = work / (ms * 1e-3) / (1e9 if unit == "GB/s" else 1e12)
         res[name] = {"ms": ms, unit: rate}
         log(f"metric {name}: {ms:.3f} ms, {rate:.1f} {unit}")
-    P.pinv_srf(ctx, plan, out_d, P.METRIC_DIAG)
-    srf = out_d.cpu().numpy().real
-    res["srf_map_range"] = [float(srf.min()), float(srf.max())]
     return res
 
+
+# ----------------------------------------------------------------------------
+# the 64x64 / 8-coil workload (earlier headline; kept for continuity)
+# ----------------------------------------------------------------------------
+
+def config2_figures(P, ctx, stream, dev, tol) -> dict:
+    import torch
+    from paper_2410_06129_amd import synth
+    w = synth.spiral_64x64_c8(F=1000)
+    enc = w.enc
+    N, M, F = enc.N, enc.M, 1000
+    d64, d32, x_ref = make_inputs(P, ctx, w, F, dev)
+    x32 = torch.empty((F, N), dtype=torch.complex64, device=dev)
+    out = {"workload": w.name, "N": N, "M": M, "F": F}
+    p, st = build_timed(P, ctx, enc, w.rel_lambda, P.FP32)
+    refine = None
+    errs = {}
+    for r in range(3):
+        P.pinv_apply(ctx, p, d32, x32, refine_steps=r)
+        torch.cuda.synchronize()
+        errs[str(r)] = rel_err(x32, x_ref)[0]
+        if refine is None and errs[str(r)] <= tol:
+            refine = r
+    refine = 2 if refine is None else refine
+    builds = []
+    for _ in range(3):
+        q, stq = build_timed(P, ctx, enc, w.rel_lambda, P.FP32)
+        builds.append(sum(stq))
+        P.pinv_plan_release(q)
+    a0 = apply_ms(P, ctx, p, d32, x32, stream)
+    ar = apply_ms(P, ctx, p, d32, x32, stream, refine=refine)
+    out["fp32"] = {"build_ms": float(np.median(builds)), "stage_ms": stage_dict(st),
+                   "apply_frames_per_s": F / (a0 * 1e-3),
+                   "apply_refined_frames_per_s": F / (ar * 1e-3), "refine_steps": refine,
+                   "rel_err_by_refine_steps": errs}
+    out["metrics_fp32_plan"] = metric_timings(P, ctx, p, enc, stream, dev)
+    P.pinv_plan_release(p)
+    q, stq = build_timed(P, ctx, enc, w.rel_lambda, P.FP32, P.FLAG_R_FP64)
+    P.pinv_apply(ctx, q, d32, x32)
+    torch.cuda.synchronize()
+    out["fp32_r_fp64"] = {"build_ms": float(sum(stq)), "rel_err_unrefined": rel_err(x32, x_ref)[0],
+                          "apply_frames_per_s": F / (apply_ms(P, ctx, q, d32, x32, stream) * 1e-3)}
+    P.pinv_plan_release(q)
+    q, stq = build_timed(P, ctx, enc, w.rel_lambda, P.FP64)
+    x64 = torch.empty((F, N), dtype=torch.complex128, device=dev)
+    out["fp64_gpu"] = {"build_ms": float(sum(stq)),
+                       "apply_frames_per_s": F / (apply_ms(P, ctx, q, d64, x64, stream) * 1e-3)}
+    P.pinv_plan_release(q)
+    log(f"64x64 workload: {out}")
+    P.pinv_context_trim(ctx)
+    return out
+
+
+# ----------------------------------------------------------------------------
+# other modes
+# ----------------------------------------------------------------------------
 
 def serving(args) -> dict:
     """Replay the seeded serving trace (Poisson arrivals; sizes 32^2..128^2 with
     probabilities .4/.3/.2/.1; 1, 8 or 16 coils; spiral of 2N samples per coil;
-    70% of requests reuse an earlier encoding; 50-2000 frames) through the
-    server, once with FP32 plans + refinement and once with plain FP64 plans.
-    Latency = completion - scheduled arrival (queueing included)."""
+    70% of requests reuse an earlier encoding; frames uniform in [50, 2000])
+    through the server, once per variant.  Latency = completion - scheduled
+    arrival (queueing included).  A request that fails (its plan exceeds the
+    budget) counts as never served: p50/p99 are over all requests, failures
+    at infinite latency, and over the requests served by every variant."""
     import threading
     import torch
     from paper_2410_06129_amd import pinv as P
@@ -210,13 +412,16 @@ def serving(args) -> dict:
     for r in trace:
         if r.enc_id not in encs:
             encs[r.enc_id] = synth.serving_encoding(r.n, r.coils, r.enc_id)
-    res = {"requests": len(trace), "rate_per_s": args.rate, "duration_s": args.duration}
-    variants = {"fp32_refined": (P.FP32, torch.complex64, args.serve_refine),
-                "fp64": (P.FP64, torch.complex128, 0),
-                "fp32_unrefined": (P.FP32, torch.complex64, 0),
-                "bf16x3_refined": (P.BF16X3, torch.complex64, args.serve_refine)}
+    res = {"requests": len(trace), "rate_per_s": args.rate, "duration_s": args.duration,
+           "frames_range": [50, 2000]}
+    variants = {"fp32_refined": (P.FP32, torch.complex64, args.serve_refine, 0),
+                "fp32_r_fp64": (P.FP32, torch.complex64, 0, P.FLAG_R_FP64),
+                "fp64": (P.FP64, torch.complex128, 0, 0),
+                "fp32_unrefined": (P.FP32, torch.complex64, 0, 0),
+                "bf16x3_refined": (P.BF16X3, torch.complex64, args.serve_refine, 0)}
+    lat_by = {}
     for label in args.serve_variants.split(","):
-        prec, cdt, refine = variants[label]
+        prec, cdt, refine, flags = variants[label]
         ctx = P.pinv_context_create(0)
         free, total = torch.cuda.mem_get_info()
         srv = P.pinv_server_create(ctx, 0, hbm_budget_bytes=int(free * args.plan_frac),
@@ -224,7 +429,7 @@ def serving(args) -> dict:
         data_cap = int(free * (0.85 - args.plan_frac))
         log(f"[{label}] device free {free / 2**30:.1f} of {total / 2**30:.1f} GiB; plan budget "
             f"{free * args.plan_frac / 2**30:.1f} GiB, data cap {data_cap / 2**30:.1f} GiB")
-        live = {}            # tag -> (data, image, bytes)
+        live = {}
         lock = threading.Lock()
         in_bytes = [0]
         sched = {}
@@ -245,7 +450,7 @@ def serving(args) -> dict:
             while time.perf_counter() - t0 < r.arrival_s:
                 reap()
                 time.sleep(0.001)
-            nbytes = (M + N) * F * (8 if prec == P.FP32 else 16)
+            nbytes = (M + N) * F * (8 if prec != P.FP64 else 16)
             while True:        # back-pressure on request buffers (counts as queueing)
                 reap()
                 with lock:
@@ -260,9 +465,9 @@ def serving(args) -> dict:
                 live[r.rid] = (d, x, nbytes)
                 in_bytes[0] += nbytes
             sched[r.rid] = r.arrival_s
-            P.pinv_server_submit(srv, enc, d, x, 1e-3, P.LAMBDA_REL_MEAN_DIAG, prec,
+            P.pinv_server_submit(srv, enc, d, x, 1e-3, P.LAMBDA_REL_MEAN_DIAG, prec, flags=flags,
                                  refine_steps=refine, tag=r.rid)
-            flops_offered += 8.0 * N * M * F + (12.0 * M * N * N + 4.0 * N ** 3 / 3 if r.new_build else 0)
+            flops_offered += 8.0 * N * M * F + (build_flops_standard(enc) if r.new_build else 0)
             log(f"[{label}] t={time.perf_counter() - t0:7.2f}s submitted {r.rid} n={r.n} C={r.coils} "
                 f"F={F} new={r.new_build}; done {len(done)}")
         while len(done) < len(trace):
@@ -274,31 +479,45 @@ def serving(args) -> dict:
         live.clear()
         P.pinv_context_destroy(ctx)
         torch.cuda.empty_cache()
-        lat = np.array([tw - sched[c["tag"]] for c, tw in done if c["status"] == P.OK])
-        ok = all(c["status"] == P.OK for c, _ in done)
+        lat = {c["tag"]: (tw - sched[c["tag"]] if c["status"] == P.OK else float("inf"))
+               for c, tw in done}
+        lat_by[label] = lat
+        ok = np.array([v for v in lat.values() if np.isfinite(v)])
+        allv = np.array(list(lat.values()))
         fails = {}
         for c, _ in done:
             if c["status"] != P.OK:
-                fails[P.pinv_status_string(c["status"])] = fails.get(P.pinv_status_string(c["status"]), 0) + 1
-        res[label] = {"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
-                      "mean_s": float(lat.mean()), "completed_ok": int(len(lat)),
-                      "refine_steps": refine, "throughput_req_per_s": len(lat) / t_end,
-                      "makespan_s": t_end, "all_ok": ok, "failures": fails,
-                      "offered_tflops": flops_offered / args.duration / 1e12,
-                      "served_tflops": flops_offered / t_end / 1e12,
+                k = P.pinv_status_string(c["status"])
+                fails[k] = fails.get(k, 0) + 1
+        res[label] = {"p50_s": float(np.percentile(allv, 50)), "p99_s": float(np.percentile(allv, 99)),
+                      "p50_served_s": float(np.percentile(ok, 50)),
+                      "p99_served_s": float(np.percentile(ok, 99)),
+                      "completed_ok": int(len(ok)), "failed": int(len(allv) - len(ok)),
+                      "failures": fails, "refine_steps": refine,
+                      "throughput_req_per_s": len(ok) / t_end, "makespan_s": t_end,
+                      "offered_tflops_standard": flops_offered / args.duration / 1e12,
+                      "served_tflops_standard": flops_offered / t_end / 1e12,
                       "builds": st["builds"], "hits": st["hits"], "evictions": st["evictions"],
                       "batches": st["batches"], "peak_plan_bytes": st["peak_used"],
                       "invariant_violations": st["invariant_violations"]}
         log(f"[{label}] {res[label]}")
+    common = set.intersection(*[{t for t, v in l.items() if np.isfinite(v)} for l in lat_by.values()])
+    res["common_requests"] = len(common)
+    for label, lat in lat_by.items():
+        v = np.array([lat[t] for t in common])
+        if len(v):
+            res[label]["p50_common_s"] = float(np.percentile(v, 50))
+            res[label]["p99_common_s"] = float(np.percentile(v, 99))
     return res
 
 
 def precision_study(args) -> dict:
     """96x96, 16 coils, 8192-sample spiral per coil (M=131072), 500 frames:
-    relative image error of FP32 and BF16-split plans against the plain FP64
-    GPU path (itself checked against the oracle) for lambda in
-    {1e-4, 1e-3, 1e-2} * mean diag and 0-2 refinement steps, with kappa(G_l)
-    from power iteration on the plan's FP64 Gram."""
+    relative image error of FP32 plans (FP64 PSF Gram, and an FP32 Gram over
+    all rows), FP32 plans with R formed in FP64 and BF16-split plans against
+    the plain FP64 GPU path (itself checked against the oracle's residual at
+    this shape) for lambda in {1e-4, 1e-3, 1e-2} * mean diag and 0-2
+    refinement steps, with kappa(G_l) from power iteration on the FP64 Gram."""
     import torch
     from paper_2410_06129_amd import pinv as P
     from paper_2410_06129_amd import synth
@@ -309,14 +528,13 @@ def precision_study(args) -> dict:
     dev = torch.device("cuda:0")
     ctx = P.pinv_context_create(0)
     out = {"workload": w.name, "N": N, "M": M, "F": F, "by_lambda": {}}
-    x_true = torch.from_numpy(w.images).to(dev)
-    d64 = None
+    d64 = d32 = None
     for rel in (1e-4, 1e-3, 1e-2):
         p64 = P.pinv_build(ctx, enc, rel, P.LAMBDA_REL_MEAN_DIAG, P.FP64, P.FLAG_UNCACHED)
         P.pinv_plan_wait(p64)
         if d64 is None:
             d64 = torch.empty((F, M), dtype=torch.complex128, device=dev)
-            P.pinv_forward(ctx, p64, x_true, d64)
+            P.pinv_forward(ctx, p64, torch.from_numpy(w.images).to(dev), d64)
             noise = torch.from_numpy(w.noise).to(dev)
             d64 += torch.sqrt(torch.mean(torch.abs(d64) ** 2)) * 10 ** (-w.snr_db / 20) * noise
             del noise
@@ -334,10 +552,13 @@ def precision_study(args) -> dict:
         x64 = torch.empty((F, N), dtype=torch.complex128, device=dev)
         P.pinv_apply(ctx, p64, d64, x64)
         torch.cuda.synchronize()
-        ref_norm = torch.linalg.vector_norm(x64, dim=1)
         entry = {"kappa": kappa, "fp64_build_ms": sum(info["stage_ms"])}
-        for name, prec in (("fp32", P.FP32), ("bf16x3", P.BF16X3)):
-            p = P.pinv_build(ctx, enc, rel, P.LAMBDA_REL_MEAN_DIAG, prec, P.FLAG_UNCACHED)
+        for name, prec, kw in (("fp32", P.FP32, {}),
+                               ("fp32_gram_fp32", P.FP32, {"gram": P.GRAM_FULL}),
+                               ("fp32_r_fp64", P.FP32, {"flags": P.FLAG_R_FP64}),
+                               ("bf16x3", P.BF16X3, {})):
+            flags = kw.pop("flags", 0)
+            p = P.pinv_build(ctx, enc, rel, P.LAMBDA_REL_MEAN_DIAG, prec, flags | P.FLAG_UNCACHED, **kw)
             P.pinv_plan_wait(p)
             entry[name + "_build_ms"] = sum(P.pinv_plan_info_get(p)["stage_ms"])
             x = torch.empty((F, N), dtype=torch.complex64, device=dev)
@@ -345,8 +566,7 @@ def precision_study(args) -> dict:
             for r in range(3):
                 P.pinv_apply(ctx, p, d32, x, refine_steps=r)
                 torch.cuda.synchronize()
-                e = torch.linalg.vector_norm(x.to(torch.complex128) - x64, dim=1) / ref_norm
-                errs[str(r)] = {"max": float(e.max()), "median": float(e.median())}
+                errs[str(r)] = dict(zip(("max", "median"), rel_err(x, x64)))
             entry[name] = errs
             P.pinv_plan_release(p)
             log(f"lambda {rel:g} {name}: {errs}")
@@ -356,27 +576,306 @@ def precision_study(args) -> dict:
     return out
 
 
+def build_only(args) -> dict:
+    import torch  # noqa: F401
+    from paper_2410_06129_amd import pinv as P
+    from paper_2410_06129_amd import synth
+    side, coils = args.build_only
+    enc = synth.serving_encoding(side, coils, 0)
+    N, M = enc.N, enc.M
+    ctx = P.pinv_context_create(0)
+    out = {"metric": "R-build executed TFLOP/s", "unit": "TFLOP/s",
+           "config": {"workload": f"{side}x{side} image, {coils} coils, spiral {2 * N} per coil",
+                      "N": N, "M": M}, "builds": {}}
+    for name in args.precisions.split(","):
+        prec, flags, kw = {"fp32": (P.FP32, 0, {}), "fp64": (P.FP64, 0, {}),
+                           "fp64_3m": (P.FP64, 0, {"cprod": P.CPROD_3M}),
+                           "fp32_r_fp64": (P.FP32, P.FLAG_R_FP64, {}),
+                           "bf16x3": (P.BF16X3, 0, {}),
+                           "fp32_shared_gram": (P.FP32, 0, {"gram": P.GRAM_SHARED})}[name]
+        form = "shared" if kw.get("gram") == P.GRAM_SHARED else "psf"
+        ex = build_flops_executed(enc, form)
+        times = []
+        for rep in range(max(1, args.steps)):
+            log(f"build {name} rep {rep} N={N} M={M}")
+            p, st = build_timed(P, ctx, enc, 1e-3, prec, flags, **kw)
+            times.append(st)
+            P.pinv_plan_release(p)
+            P.pinv_context_trim(ctx)
+        st = np.median(np.array(times), axis=0)
+        total = float(st.sum())
+        exec_total = sum(ex.values())
+        peak = PEAK_FP64_MFMA if prec == P.FP64 or flags else PEAK_FP32_MFMA
+        out["builds"][name] = {
+            "stage_ms": stage_dict(st), "build_ms": total,
+            "tflops_executed": exec_total / (total * 1e-3) / 1e12,
+            "frac_of_peak_executed": exec_total / (total * 1e-3) / 1e12 / peak, "peak": peak,
+            "tflops_standard_count_effective": build_flops_standard(enc) / (total * 1e-3) / 1e12,
+            "stage_tflops_executed": {k: ex[k] / (st[i] * 1e-3) / 1e12 if st[i] > 0 else None
+                                      for i, k in enumerate(("gram", "chol_inv", "trmm_w", "trmm_r"))}}
+        log(json.dumps(out["builds"][name]))
+    out["value"] = out["builds"][next(iter(out["builds"]))]["tflops_executed"]
+    P.pinv_context_destroy(ctx)
+    return out
+
+
+def pmc_run(args) -> None:
+    """A short run for counter collection: a plain 2 GiB device copy (the
+    counters' scale), then one FP32 build and one apply of `frames` frames with
+    one refinement step at the default workload (random data: the counters do
+    not depend on values)."""
+    import torch
+    from paper_2410_06129_amd import pinv as P
+    from paper_2410_06129_amd import synth
+    dev = torch.device("cuda:0")
+    src = torch.ones((1 << 29,), dtype=torch.float32, device=dev)     # 2 GiB
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    w = synth.spiral_128x128_c8(F=1)
+    enc = w.enc
+    ctx = P.pinv_context_create(0)
+    g = torch.Generator(device=dev).manual_seed(5)
+    d = torch.randn((args.frames, enc.M), dtype=torch.complex64, device=dev, generator=g)
+    x = torch.empty((args.frames, enc.N), dtype=torch.complex64, device=dev)
+    p = P.pinv_build(ctx, enc, w.rel_lambda, P.LAMBDA_REL_MEAN_DIAG, P.FP32, P.FLAG_UNCACHED)
+    P.pinv_apply(ctx, p, d, x, refine_steps=1)
+    torch.cuda.synchronize()
+    P.pinv_plan_wait(p)
+    log(f"pmc run: stage ms {P.pinv_plan_info_get(p)['stage_ms']}")
+    P.pinv_plan_release(p)
+    P.pinv_context_destroy(ctx)
+    print(json.dumps({"pmc_run": "done"}), flush=True)
+
+
+# ----------------------------------------------------------------------------
+# default: the headline workload
+# ----------------------------------------------------------------------------
+
+def headline(args) -> dict:
+    import torch
+    from paper_2410_06129_amd import pinv as P
+    from paper_2410_06129_amd import synth
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    w = synth.spiral_128x128_c8(F=args.frames)
+    enc = w.enc
+    N, M, F = enc.N, enc.M, args.frames
+    log(f"workload {w.name}: N={N} M={M} F={F}")
+    ctx = P.pinv_context_create(0)
+    d64, d32, x_ref = make_inputs(P, ctx, w, F, dev)
+    log("inputs ready")
+    P.pinv_context_trim(ctx)
+    x32 = torch.empty((F, N), dtype=torch.complex64, device=dev)
+
+    # --- refinement steps: the fewest that meet the tolerance ---
+    p32, st32 = build_timed(P, ctx, enc, w.rel_lambda, P.FP32)
+    err_table = {}
+    refine = None
+    for r in range(3):
+        P.pinv_apply(ctx, p32, d32, x32, refine_steps=r)
+        torch.cuda.synchronize()
+        err_table[str(r)] = rel_err(x32, x_ref)[0]
+        log(f"refine {r}: max rel err {err_table[str(r)]:.3e}")
+        if refine is None and err_table[str(r)] <= args.tol:
+            refine = r
+    refine = 2 if refine is None else refine
+    a0 = apply_ms(P, ctx, p32, d32, x32, stream)
+    ar = apply_ms(P, ctx, p32, d32, x32, stream, refine=refine)
+    small_f = {}
+    for Fs in (1, 4, 8, 9, 32):
+        ds = d32[:Fs].contiguous()
+        xs = torch.empty((Fs, N), dtype=torch.complex64, device=dev)
+        ms = apply_ms(P, ctx, p32, ds, xs, stream, reps=5)
+        nbytes = 8.0 * (N * M + Fs * M + Fs * N)
+        small_f[str(Fs)] = {"ms": ms, "GB/s": nbytes / (ms * 1e-3) / 1e9,
+                            "hbm_frac": nbytes / (ms * 1e-3) / PEAK_HBM,
+                            "path": "rows" if Fs <= 8 else "mfma"}
+    log(f"small-F applies: {small_f}")
+    P.pinv_plan_release(p32)
+    P.pinv_context_trim(ctx)
+
+    # --- timed steps ---
+    def step():
+        p = P.pinv_build(ctx, enc, w.rel_lambda, P.LAMBDA_REL_MEAN_DIAG, P.FP32, P.FLAG_UNCACHED)
+        P.pinv_apply(ctx, p, d32, x32, refine_steps=refine)
+        return p
+
+    def run_steps(n, stages=None):
+        # A plan lives until the next step is enqueued: the host waits for its
+        # build (the next step already queued behind it), reads its stage
+        # times and releases it, stream-ordered after its apply.
+        prev = None
+        for i in range(n):
+            p = step()
+            log(f"step {i} enqueued")
+            if prev is not None:
+                P.pinv_plan_wait(prev)
+                if stages is not None:
+                    stages.append(P.pinv_plan_info_get(prev)["stage_ms"])
+                P.pinv_plan_release(prev)
+            prev = p
+        return prev
+
+    last = run_steps(args.warmup)
+    torch.cuda.synchronize()
+    if last is not None:
+        P.pinv_plan_release(last)
+    stages = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    last = run_steps(args.steps, stages)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    P.pinv_plan_wait(last)
+    stages.append(P.pinv_plan_info_get(last)["stage_ms"])
+    P.pinv_plan_release(last)
+    stages = np.array(stages)
+    st_mean = stages.mean(axis=0)
+    err_final = rel_err(x32, x_ref)
+    ms_step = 1e3 * dt / args.steps
+    for i, st in enumerate(stages):
+        log(f"step {i} stage ms (gram, chol+inv, W, R): {np.round(st, 2)}")
+    P.pinv_context_trim(ctx)
+
+    ex = build_flops_executed(enc, "psf")
+    build_exec = sum(ex.values())
+    step_exec = build_exec + 8.0 * N * M * F + refine_flops(enc, F, refine)
+    step_std = build_flops_standard(enc) + 8.0 * N * M * F
+    build_ms = float(st_mean.sum())
+    value = step_exec / (ms_step * 1e-3) / 1e12
+
+    # --- FP32 plan with R formed in FP64: no refinement needed ---
+    q, stq = build_timed(P, ctx, enc, w.rel_lambda, P.FP32, P.FLAG_R_FP64)
+    P.pinv_apply(ctx, q, d32, x32)
+    torch.cuda.synchronize()
+    rf_err = rel_err(x32, x_ref)
+    rf_apply = apply_ms(P, ctx, q, d32, x32, stream)
+    P.pinv_plan_release(q)
+    P.pinv_context_trim(ctx)
+    rf_build = float(sum(stq))
+    gap = (ar - rf_apply) / F          # ms per frame the FP64-formed R saves
+    r_fp64 = {"build_ms": rf_build, "stage_ms": stage_dict(stq),
+              "apply_frames_per_s": F / (rf_apply * 1e-3),
+              "rel_err_unrefined": {"max": rf_err[0], "median": rf_err[1]},
+              "breakeven_frames_vs_fp32_refined": (rf_build - build_ms) / gap if gap > 0 else None}
+    log(f"R formed in FP64: {r_fp64}")
+
+    # --- BF16-split plan ---
+    b3, stb = build_timed(P, ctx, enc, w.rel_lambda, P.BF16X3)
+    b3_err = {}
+    for r in range(3):
+        P.pinv_apply(ctx, b3, d32, x32, refine_steps=r)
+        torch.cuda.synchronize()
+        b3_err[str(r)] = rel_err(x32, x_ref)[0]
+    b3_apply = apply_ms(P, ctx, b3, d32, x32, stream)
+    P.pinv_plan_release(b3)
+    P.pinv_context_trim(ctx)
+    bf16x3 = {"build_ms": float(sum(stb)), "stage_ms": stage_dict(stb),
+              "apply_frames_per_s": F / (b3_apply * 1e-3), "rel_err_by_refine_steps": b3_err}
+    log(f"bf16x3: {bf16x3}")
+
+    # --- factor-only plan (no W, no R) ---
+    fo, stf = build_timed(P, ctx, enc, w.rel_lambda, P.FP32, P.FLAG_NO_R)
+    fo_apply = apply_ms(P, ctx, fo, d32, x32, stream, refine=refine)
+    fo_err = rel_err(x32, x_ref)
+    P.pinv_plan_release(fo)
+    fo_build = float(sum(stf))
+    per_frame_gap = (fo_apply - ar) / F
+    factor_only = {"build_ms": fo_build, "apply_refined_frames_per_s": F / (fo_apply * 1e-3),
+                   "rel_err": {"max": fo_err[0], "median": fo_err[1]},
+                   "breakeven_frames": (build_ms - fo_build) / per_frame_gap if per_frame_gap > 0 else None}
+    log(f"factor-only: {factor_only}")
+    P.pinv_context_trim(ctx)
+
+    # --- plain FP64 GPU comparator (R 69 GB, W 69 GB) ---
+    f64, st64 = build_timed(P, ctx, enc, w.rel_lambda, P.FP64)
+    x64 = torch.empty((F, N), dtype=torch.complex128, device=dev)
+    f64_apply = apply_ms(P, ctx, f64, d64, x64, stream, reps=2)
+    f64_err = rel_err(x64, x_ref)
+    P.pinv_plan_release(f64)
+    P.pinv_context_trim(ctx)
+    f64_build = float(sum(st64))
+    fp64_gpu = {"build_ms": f64_build, "stage_ms": stage_dict(st64),
+                "build_tflops_executed": build_exec / (f64_build * 1e-3) / 1e12,
+                "apply_frames_per_s": F / (f64_apply * 1e-3),
+                "rel_err": {"max": f64_err[0], "median": f64_err[1]}}
+    log(f"fp64: {fp64_gpu}")
+    del d64, d32, x64, x32, x_ref
+    P.pinv_context_destroy(ctx)
+    torch.cuda.empty_cache()
+
+    # --- roofline of the dominant kernel of the step (HIP-event stage times on
+    # the build stream; each of W and R is one kernel launch) ---
+    kern = {"trmm_w": (float(st_mean[2]), ex["trmm_w"], PEAK_FP32_MFMA),
+            "trmm_r": (float(st_mean[3]), ex["trmm_r"], PEAK_FP32_MFMA),
+            "apply": (a0, 8.0 * N * M * F, PEAK_FP32_MFMA)}
+    name = max(kern, key=lambda k: kern[k][0])
+    kms, kfl, kpeak = kern[name]
+    achieved = kfl / (kms * 1e-3) / 1e12
+    tr = measured_traffic(name, w.name)
+    roof = {"kernel": name, "bound": "mfma", "achieved": achieved, "peak": kpeak, "unit": "TFLOP/s",
+            "frac": achieved / kpeak, "traffic": tr["bytes_per_launch"] if tr else None,
+            "traffic_detail": tr,
+            "mfma_pipe_frac": achieved * 0.75 / kpeak,   # 3M: 6 of the 8 counted real flops run
+            "per_kernel": {k: {"ms": v[0], "tflops": v[1] / (v[0] * 1e-3) / 1e12, "peak": v[2],
+                               "frac": v[1] / (v[0] * 1e-3) / 1e12 / v[2]} for k, v in kern.items()}}
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w.name, "N": N, "M": M, "F": F, "coils": enc.C,
+                   "precision": "fp32 mfma products, fp64 gram and factorisation",
+                   "refine_steps": refine, "lambda_rel": w.rel_lambda},
+        "value_basis": "executed complex-equivalent flops per step / step time",
+        "step_tflops_standard_count_effective": step_std / (ms_step * 1e-3) / 1e12,
+        "build": {"ms": build_ms, "stage_ms": stage_dict(st_mean),
+                  "tflops_executed": build_exec / (build_ms * 1e-3) / 1e12,
+                  "frac_fp32_peak_executed": build_exec / (build_ms * 1e-3) / 1e12 / PEAK_FP32_MFMA,
+                  "tflops_standard_count_effective":
+                      build_flops_standard(enc) / (build_ms * 1e-3) / 1e12,
+                  "executed_flops": ex},
+        "apply_frames_per_s": F / (a0 * 1e-3),
+        "apply_refined_frames_per_s": F / (ar * 1e-3),
+        "apply_small_frames": small_f,
+        "rel_err_vs_fp64": {"max": err_final[0], "median": err_final[1],
+                            "by_refine_steps": err_table,
+                            "reference": "factor-only FP64 GPU solve with one FP64 refinement step"},
+        "fp32_r_fp64": r_fp64,
+        "bf16x3": bf16x3,
+        "factor_only_fp32": factor_only,
+        "fp64_gpu": fp64_gpu,
+        "speedup_vs_fp64_gpu": {"build": f64_build / build_ms, "apply": f64_apply / a0,
+                                "apply_at_1e-5": f64_apply / min(ar, rf_apply)},
+        "roofline": roof,
+    }
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--frames", type=int, default=1000)
     ap.add_argument("--tol", type=float, default=1e-5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--fp64-reps", type=int, default=2)
+    ap.add_argument("--no-config2", action="store_true")
     ap.add_argument("--serving", action="store_true", help="run the serving-mix trace instead")
     ap.add_argument("--rate", type=float, default=4.0)
     ap.add_argument("--duration", type=float, default=120.0)
     ap.add_argument("--serve-refine", type=int, default=1)
     ap.add_argument("--plan-frac", type=float, default=0.6)
-    ap.add_argument("--serve-variants", default="fp32_refined,fp64,fp32_unrefined,bf16x3_refined")
-    ap.add_argument("--pmc-calibrate", action="store_true",
-                    help="run a plain 2 GiB device copy first (reference for HBM byte counters)")
+    ap.add_argument("--serve-variants", default="fp32_refined,fp32_r_fp64,fp64")
+    ap.add_argument("--pmc-run", action="store_true",
+                    help="a 2 GiB copy, one FP32 build and one refined apply (counter runs)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/pmc_traffic.json from two rocprofv3 --pmc output folders")
     ap.add_argument("--build-only", type=int, nargs=2, metavar=("SIDE", "COILS"),
-                    help="build one plan for a SIDE^2 image with COILS coils (spiral 2N per coil)")
+                    help="build plans for a SIDE^2 image with COILS coils (spiral 2N per coil)")
     ap.add_argument("--precisions", default="fp32,fp64")
     ap.add_argument("--precision-study", action="store_true")
     ap.add_argument("--frames-study", type=int, default=500)
@@ -394,13 +893,13 @@ def main():
         return
 
     import torch
-    from paper_2410_06129_amd import pinv as P
-    from paper_2410_06129_amd import synth
-
     torch.cuda.init()
     # a dedicated (default-priority) stream: the library and torch's own work are
     # issued on it, and HIP events time it
     torch.cuda.set_stream(torch.cuda.Stream(device=torch.device("cuda:0")))
+    if args.pmc_run:
+        pmc_run(args)
+        return
     if args.precision_study:
         res = precision_study(args)
         print(json.dumps({"metric": "relative image error vs plain FP64 GPU path", "unit": "rel",
@@ -408,299 +907,28 @@ def main():
                           "config": {"workload": res["workload"]}, "study": res}), flush=True)
         return
     if args.build_only:
-        side, coils = args.build_only
-        enc = synth.serving_encoding(side, coils, 0)
-        N, M = enc.N, enc.M
-        ctx = P.pinv_context_create(0)
-        out = {"metric": "R-build TFLOP/s (complex-equivalent 12MN^2 + 4N^3/3)", "unit": "TFLOP/s",
-               "config": {"workload": f"{side}x{side} image, {coils} coils, spiral {2 * N} per coil",
-                          "N": N, "M": M}, "builds": {}}
-        flops = 12.0 * M * N * N + 4.0 * N ** 3 / 3.0
-        for name in args.precisions.split(","):
-            prec = {"fp32": P.FP32, "fp64": P.FP64, "bf16x3": P.BF16X3}[name]
-            times = []
-            for rep in range(max(1, args.steps)):
-                log(f"build {name} rep {rep} N={N} M={M}")
-                p = P.pinv_build(ctx, enc, 1e-3, P.LAMBDA_REL_MEAN_DIAG, prec, P.FLAG_UNCACHED)
-                P.pinv_plan_wait(p)
-                times.append(P.pinv_plan_info_get(p)["stage_ms"])
-                P.pinv_plan_release(p)
-            st = np.median(np.array(times), axis=0)
-            out["builds"][name] = {"stage_ms": {"gram": st[0], "chol_inv": st[1], "trmm_w": st[2],
-                                                "trmm_r": st[3]},
-                                   "build_ms": float(st.sum()),
-                                   "tflops": flops / (st.sum() * 1e-3) / 1e12,
-                                   "trmm_tflops": 8.0 * M * N * N / ((st[2] + st[3]) * 1e-3) / 1e12}
-            for k in list(out["builds"][name]["stage_ms"]):
-                out["builds"][name]["stage_ms"][k] = float(out["builds"][name]["stage_ms"][k])
-            log(json.dumps(out["builds"][name]))
-        out["value"] = out["builds"].get("fp32", out["builds"][next(iter(out["builds"]))])["tflops"]
-        P.pinv_context_destroy(ctx)
-        print(json.dumps(out), flush=True)
+        print(json.dumps(build_only(args)), flush=True)
         return
     if args.serving:
         res = serving(args)
-        out = {"metric": "serving p50/p99 latency (s) and throughput, FP32+refinement vs plain FP64",
-               "value": res["fp32_refined"]["p99_s"], "unit": "s", "n_gpus": 1,
-               "higher_is_better": False, "data": "synthetic", "dtype": "f32",
-               "config": {"workload": f"serving mix, Poisson {args.rate}/s over {args.duration} s"},
-               "serving": res}
+        first = args.serve_variants.split(",")[0]
+        out = {"metric": "serving p50/p99 latency (s) and throughput", "value": res[first]["p99_s"],
+               "unit": "s", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
+               "dtype": "f32", "config": {"workload": f"serving mix, Poisson {args.rate}/s over "
+                                                      f"{args.duration} s"}, "serving": res}
         print(json.dumps(out), flush=True)
         return
-    dev = torch.device("cuda:0")
-    stream = torch.cuda.current_stream()
-    if args.pmc_calibrate:
-        src = torch.ones((1 << 29,), dtype=torch.float32, device=dev)     # 2 GiB
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    w = synth.spiral_64x64_c8(F=args.frames)
-    enc = w.enc
-    N, M, F = enc.N, enc.M, w.images.shape[0]
-    log(f"workload {w.name}: N={N} M={M} F={F}")
-    ctx = P.pinv_context_create(0)
-
-    # --- inputs resident in HBM: data = E x (FP64 GPU forward) + 30 dB noise ---
-    p64 = P.pinv_build(ctx, enc, w.rel_lambda, P.LAMBDA_REL_MEAN_DIAG, P.FP64)
-    P.pinv_plan_wait(p64)
-    x_true = torch.from_numpy(w.images).to(dev)
-    d64 = torch.empty((F, M), dtype=torch.complex128, device=dev)
-    P.pinv_forward(ctx, p64, x_true, d64)
-    noise = torch.from_numpy(w.noise).to(dev)
-    sigma = torch.sqrt(torch.mean(torch.abs(d64) ** 2)) * 10 ** (-w.snr_db / 20)
-    d64 += sigma * noise
-    del noise
-    d32 = d64.to(torch.complex64)
-    x64 = torch.empty((F, N), dtype=torch.complex128, device=dev)
-    P.pinv_apply(ctx, p64, d64, x64)
-    torch.cuda.synchronize()
-    ref_norm = torch.linalg.vector_norm(x64, dim=1)
-
-    def rel_err(x):
-        e = torch.linalg.vector_norm(x.to(torch.complex128) - x64, dim=1) / ref_norm
-        return float(e.max()), float(e.median())
-
-    flops_build = 12.0 * M * N * N + 4.0 * N ** 3 / 3.0
-    flops_apply = 8.0 * N * M * F
-    x32 = torch.empty((F, N), dtype=torch.complex64, device=dev)
-
-    # --- choose refinement steps: the fewest that meet the tolerance ---
-    p32 = P.pinv_build(ctx, enc, w.rel_lambda, P.LAMBDA_REL_MEAN_DIAG, P.FP32, P.FLAG_UNCACHED)
-    P.pinv_plan_wait(p32)
-    err_table = {}
-    refine = None
-    for r in range(0, 3):
-        P.pinv_apply(ctx, p32, d32, x32, refine_steps=r)
-        torch.cuda.synchronize()
-        err_table[r] = rel_err(x32)
-        log(f"refine {r}: max rel err {err_table[r][0]:.3e} median {err_table[r][1]:.3e}")
-        if refine is None and err_table[r][0] <= args.tol:
-            refine = r
-    if refine is None:
-        refine = 2
-    # apply-only and refinement timings (events on the launch stream)
-    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
-    apply_ms, refine_ms = [], []
-    for _ in range(3):
-        e0.record(stream)
-        P.pinv_apply(ctx, p32, d32, x32, refine_steps=0)
-        e1.record(stream)
-        P.pinv_apply(ctx, p32, d32, x32, refine_steps=refine)
-        e2.record(stream)
-        torch.cuda.synchronize()
-        apply_ms.append(e0.elapsed_time(e1))
-        refine_ms.append(e1.elapsed_time(e2) - e0.elapsed_time(e1))
-    # applies of a few frames stream R once (HBM-bound): GB/s against 8 TB/s;
-    # 9 and 32 frames take the MFMA tiles
-    small_f = {}
-    # (left out of the counter runs, whose per-kernel averages must cover the
-    # 1000-frame applies only)
-    for Fs in (() if args.pmc_calibrate else (1, 4, 8, 9, 32)):
-        ds, xs = d32[:Fs].contiguous(), torch.empty((Fs, N), dtype=torch.complex64, device=dev)
-        ts = []
-        for _ in range(5):
-            e0.record(stream)
-            P.pinv_apply(ctx, p32, ds, xs)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            ts.append(e0.elapsed_time(e1))
-        ms = float(np.median(ts))
-        nbytes = 8.0 * (N * M + Fs * M + Fs * N)
-        small_f[str(Fs)] = {"ms": ms, "GB/s": nbytes / (ms * 1e-3) / 1e9,
-                            "hbm_frac": nbytes / (ms * 1e-3) / 8e12,
-                            "path": "rows" if Fs <= 8 else "mfma"}
-    log(f"small-F applies: {small_f}")
-    metrics = metric_timings(P, ctx, p32, enc, stream, dev)
-    P.pinv_plan_release(p32)
-
-    # --- timed steps ---
-    def step():
-        p = P.pinv_build(ctx, enc, w.rel_lambda, P.LAMBDA_REL_MEAN_DIAG, P.FP32, P.FLAG_UNCACHED)
-        P.pinv_apply(ctx, p, d32, x32, refine_steps=refine)
-        return p
-
-    def run_steps(n, stages=None):
-        # A plan lives until the next step is enqueued: the host waits for its
-        # build (the next step already queued behind it), reads its stage
-        # times and releases it, stream-ordered after its apply.  The plan
-        # pool then recycles plan memory as a long-running user's would.
-        prev = None
-        for i in range(n):
-            p = step()
-            if stages is not None:
-                log(f"step {i} enqueued")
-            if prev is not None:
-                P.pinv_plan_wait(prev)
-                if stages is not None:
-                    stages.append(P.pinv_plan_info_get(prev)["stage_ms"])
-                P.pinv_plan_release(prev)
-            prev = p
-        return prev
-
-    last = run_steps(args.warmup)
-    torch.cuda.synchronize()
-    if last is not None:
-        P.pinv_plan_release(last)
-    stages = []
-    t0 = time.perf_counter()
-    last = run_steps(args.steps, stages)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    P.pinv_plan_wait(last)
-    stages.append(P.pinv_plan_info_get(last)["stage_ms"])
-    P.pinv_plan_release(last)
-    stages = np.array(stages)
-    st_mean = stages.mean(axis=0)
-    err_final = rel_err(x32)
-    ms_step = 1e3 * dt / args.steps
-    value = (flops_build + flops_apply) / (ms_step * 1e-3) / 1e12
-    build_ms = float(st_mean.sum())
-    for i, st in enumerate(stages):
-        log(f"step {i} stage ms (gram, chol+inv, W, R): {np.round(st, 3)}")
-    log(f"stage ms (gram, chol+inv, W, R): {np.round(st_mean, 3)}; step {ms_step:.2f} ms")
-
-    # --- BF16-split plan on the same workload ---
-    b3 = P.pinv_build(ctx, enc, w.rel_lambda, P.LAMBDA_REL_MEAN_DIAG, P.BF16X3, P.FLAG_UNCACHED)
-    P.pinv_plan_wait(b3)
-    b3_stage = P.pinv_plan_info_get(b3)["stage_ms"]
-    b3_err = {}
-    for r in range(0, 3):
-        P.pinv_apply(ctx, b3, d32, x32, refine_steps=r)
-        torch.cuda.synchronize()
-        b3_err[str(r)] = rel_err(x32)[0]
-    b3_apply = []
-    for _ in range(3):
-        e0.record(stream)
-        P.pinv_apply(ctx, b3, d32, x32, refine_steps=0)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        b3_apply.append(e0.elapsed_time(e1))
-    P.pinv_plan_release(b3)
-
-    # --- factor-only plan (no W, no R): build L^-1, then solve each frame as
-    # L^-H L^-1 (E^H d) with E regenerated, plus the same refinement ---
-    fo_step, fo_build, fo_apply = [], [], []
-    for _ in range(3):
-        torch.cuda.synchronize()
-        e0.record(stream)
-        q = P.pinv_build(ctx, enc, w.rel_lambda, P.LAMBDA_REL_MEAN_DIAG, P.FP32,
-                         P.FLAG_UNCACHED | P.FLAG_NO_R)
-        P.pinv_apply(ctx, q, d32, x32, refine_steps=refine)
-        e1.record(stream)
-        P.pinv_apply(ctx, q, d32, x32, refine_steps=refine)
-        e2.record(stream)
-        torch.cuda.synchronize()
-        P.pinv_plan_wait(q)
-        fo_build.append(sum(P.pinv_plan_info_get(q)["stage_ms"]))
-        fo_step.append(e0.elapsed_time(e1))
-        fo_apply.append(e1.elapsed_time(e2))
-        P.pinv_plan_release(q)
-    fo_err = rel_err(x32)
-    fo_apply_ms = float(np.median(fo_apply))
-    r_apply_ms = float(np.median(refine_ms)) + float(np.median(apply_ms))
-    per_frame_gap = (fo_apply_ms - r_apply_ms) / F
-    factor_only = {
-        "step_ms": float(np.median(fo_step)), "build_ms": float(np.median(fo_build)),
-        "apply_refined_frames_per_s": F / (fo_apply_ms * 1e-3),
-        "rel_err_vs_fp64_gpu": {"max": fo_err[0], "median": fo_err[1]},
-        # frames per plan below which skipping R is cheaper than forming it
-        "breakeven_frames": (build_ms - float(np.median(fo_build))) / per_frame_gap
-        if per_frame_gap > 0 else None}
-    log(f"factor-only: {factor_only}")
-
-    # --- plain FP64 GPU comparator ---
-    f64_build, f64_apply = [], []
-    for _ in range(args.fp64_reps):
-        q = P.pinv_build(ctx, enc, w.rel_lambda, P.LAMBDA_REL_MEAN_DIAG, P.FP64, P.FLAG_UNCACHED)
-        P.pinv_plan_wait(q)
-        f64_build.append(sum(P.pinv_plan_info_get(q)["stage_ms"]))
-        e0.record(stream)
-        P.pinv_apply(ctx, q, d64, x64)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        f64_apply.append(e0.elapsed_time(e1))
-        P.pinv_plan_release(q)
-    f64_build_ms, f64_apply_ms = float(np.median(f64_build)), float(np.median(f64_apply))
-
-    # --- roofline of the dominant kernel (largest share of the step) ---
-    # (stage ms, complex-equivalent flops, peak).  The Gram stage is the FP64
-    # shared-trajectory product F^H F over the K samples of one coil (4KN^2
-    # executed, C times fewer than the 4MN^2 of the standard count).
-    kern = {
-        "gram": (float(st_mean[0]), 4.0 * (M // enc.C) * N * N, PEAK_FP64_MFMA),
-        "trmm_w": (float(st_mean[2]), 4.0 * M * N * N, PEAK_FP32_MFMA),
-        "trmm_r": (float(st_mean[3]), 4.0 * M * N * N, PEAK_FP32_MFMA),
-        "apply": (float(np.median(apply_ms)), flops_apply, PEAK_FP32_MFMA),
-    }
-    name = max(kern, key=lambda k: kern[k][0])
-    kms, kfl, kpeak = kern[name]
-    achieved = kfl / (kms * 1e-3) / 1e12
-    tr = measured_traffic(name)
-    roof = {"kernel": name, "bound": "mfma", "achieved": achieved, "peak": kpeak,
-            "unit": "TFLOP/s", "frac": achieved / kpeak,
-            "traffic": tr["bytes_per_launch"] if tr else None, "traffic_detail": tr,
-            "per_kernel": {k: {"ms": v[0], "tflops": v[1] / (v[0] * 1e-3) / 1e12, "peak": v[2]}
-                           for k, v in kern.items()}}
-
-    out = {
-        "metric": METRIC, "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": w.name, "N": N, "M": M, "F": F, "coils": enc.C,
-                   "precision": "fp32 mfma, fp64 factorisation", "refine_steps": refine,
-                   "lambda_rel": w.rel_lambda},
-        "build_tflops": flops_build / (build_ms * 1e-3) / 1e12,
-        "build_ms": build_ms,
-        "factor_only_fp32": factor_only,
-        "stage_ms": {"gram": st_mean[0], "chol_inv": st_mean[1], "trmm_w": st_mean[2],
-                     "trmm_r": st_mean[3]},
-        "apply_frames_per_s": F / (np.median(apply_ms) * 1e-3),
-        "apply_small_frames": small_f,
-        "apply_refined_frames_per_s": F / ((np.median(apply_ms) + np.median(refine_ms)) * 1e-3),
-        "rel_err_vs_fp64_gpu": {"max": err_final[0], "median": err_final[1],
-                                "by_refine_steps": {str(k): v[0] for k, v in err_table.items()}},
-        "fp64_gpu": {"build_ms": f64_build_ms,
-                     "build_tflops": flops_build / (f64_build_ms * 1e-3) / 1e12,
-                     "apply_frames_per_s": F / (f64_apply_ms * 1e-3)},
-        "roofline": roof,
-    }
-    out["bf16x3"] = {"build_ms": float(sum(b3_stage)),
-                     "stage_ms": {"gram": b3_stage[0], "chol_inv": b3_stage[1], "trmm_w": b3_stage[2],
-                                  "trmm_r": b3_stage[3]},
-                     "build_tflops": flops_build / (sum(b3_stage) * 1e-3) / 1e12,
-                     "apply_frames_per_s": F / (np.median(b3_apply) * 1e-3),
-                     "rel_err_by_refine_steps": b3_err}
-    out["metrics_fp32_plan"] = metrics
-    out["speedup_vs_fp64_gpu"] = {"build": f64_build_ms / build_ms,
-                                  "apply": f64_apply_ms / float(np.median(apply_ms))}
-    P.pinv_plan_release(p64)
-    P.pinv_context_destroy(ctx)
+    from paper_2410_06129_amd import pinv as P
+    out = headline(args)
+    if not args.no_config2:
+        ctx = P.pinv_context_create(0)
+        out["workload_64x64_c8"] = config2_figures(P, ctx, torch.cuda.current_stream(),
+                                                   torch.device("cuda:0"), args.tol)
+        P.pinv_context_destroy(ctx)
     if not args.no_cpu_baseline:
+        from paper_2410_06129_amd import synth
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(w)
-    for k, v in list(out["stage_ms"].items()):
-        out["stage_ms"][k] = float(v)
+        out["cpu_baseline"] = cpu_baseline(synth.spiral_128x128_c8(F=1).enc)
     print(json.dumps(out), flush=True)
 
 

@@ -68,7 +68,14 @@ typedef enum {
 } pinv_lambda_mode;
 
 /* Encoding description (all host pointers, FP64; copied during pinv_build).
- * Defines E as above (Eq. 2; Sec. 3.3 generalised encoding; Eq. 11 coil rows). */
+ * Defines E as above (Eq. 2; Sec. 3.3 generalised encoding; Eq. 11 coil rows).
+ *
+ * Voxel mask (Sec. 3.1 and Sec. 4.4: voxels outside the object or a circular
+ * field of view are left out of the unknowns, shrinking the Gram): with
+ * `voxels` non-NULL only the nvox listed voxels v = iy*nx + ix are unknowns,
+ * so V = nvox in the column index n = s*V + j (j = position in the list) and
+ * N = S*nvox.  The list must be strictly ascending and inside [0, nx*ny).
+ * coil and b0_hz still cover the whole grid ([C][nx*ny], [nx*ny]). */
 typedef struct {
   int32_t nx, ny;             /* image grid, nx, ny >= 1 */
   int64_t nk;                 /* samples per coil, >= 1 */
@@ -76,33 +83,73 @@ typedef struct {
   const double *t;            /* [nk] sample times in s; required if nspecies > 1,
                                  species_hz != NULL or b0_hz != NULL */
   int32_t ncoil;              /* C >= 1 */
-  const double *coil;         /* [C][V][2] complex sensitivities; NULL => C == 1, all ones */
-  const double *b0_hz;        /* [V] off-resonance in Hz, or NULL */
+  const double *coil;         /* [C][nx*ny][2] complex sensitivities; NULL => C == 1, all ones */
+  const double *b0_hz;        /* [nx*ny] off-resonance in Hz, or NULL */
   int32_t nspecies;           /* S >= 1 */
   const double *species_hz;   /* [S] species frequencies in Hz, or NULL (=> S == 1 at 0 Hz) */
+  const int32_t *voxels;      /* [nvox] ascending voxel indices of the mask, or NULL (all) */
+  int32_t nvox;               /* entries in voxels (ignored when voxels is NULL) */
 } pinv_encoding;
 
 #define PINV_FLAG_KEEP_GRAM 1   /* accepted for compatibility: every plan keeps E^H E */
 #define PINV_FLAG_UNCACHED 2    /* build a fresh plan outside the cache (freed on its last release) */
-#define PINV_FLAG_GRAM_FULL 4   /* form E^H E over all M = C*nk rows in the plan's precision
-                                   instead of the default FP64 (F^H F) o (coil cross-products),
-                                   which is exact because every coil shares the trajectory (Eq. 11) */
+#define PINV_FLAG_GRAM_FULL 4   /* the same as gram = PINV_GRAM_FULL */
 #define PINV_FLAG_NO_R 8        /* factor-only plan: Gram, shift and Cholesky with L^-1, but no W
                                    and no R.  Applies solve the normal equations directly,
                                    image = L^-H L^-1 (sum_c E_c^H data_c), with E regenerated per
-                                   tile (Sec. 2, direct solution without explicit inversion; the
+                                   tile (Sec. 2.4, direct solution without explicit inversion; the
                                    coil-wise adjoint after Eq. 11).  Holds N*N instead of N*M + N*N
                                    complex values and skips 8MN^2 build flops; each frame costs the
                                    same 8NM as R*data plus 8N^2 for the two triangular products.
                                    SRF, noise matrix and the R buffer are unavailable.  Not with
                                    PINV_BF16X3 (the split products only form W and R). */
+#define PINV_FLAG_R_FP64 16     /* PINV_FP32 plans only: form W = L^-1 E^H and R = L^-H W in FP64
+                                   (E generated from the FP64 tables, L^-1 kept in FP64) and round
+                                   R once to complex64.  Applies then run on FP32 MFMA with the
+                                   error of that one rounding (~u32 times the cancellation in
+                                   R*data, about 1e-6 relative) instead of kappa(G)*u32, so they
+                                   need no refinement for a 1e-5 target (Sec. 5: lower precision
+                                   for the bulk of the arithmetic, results stored at higher
+                                   precision).  The build costs what an FP64 build costs. */
+
+/* Complex-product form of the triangular products W, R and the apply (MFMA). */
+typedef enum {
+  PINV_CPROD_AUTO = 0,   /* 3M for FP32 plans, 4M for FP64 plans and FP64-formed R */
+  PINV_CPROD_3M = 1,     /* three real products per complex product (Gauss):
+                            re = ar br - ai bi, im = (ar + ai)(br + bi) - ar br - ai bi;
+                            25% fewer matrix-core operations, the imaginary part carries
+                            about twice the rounding of 4M */
+  PINV_CPROD_4M = 2      /* four real products per complex product */
+} pinv_cprod;
+
+/* How the Gram E^H E is formed. */
+typedef enum {
+  PINV_GRAM_AUTO = 0,    /* PSF without an off-resonance map, otherwise SHARED */
+  PINV_GRAM_PSF = 1,     /* Toeplitz / point-spread form (needs b0_hz == NULL): with every
+                            coil on one trajectory, E^H E = (F^H F) o (coil cross-products)
+                            (Eq. 11), and F^H F between voxels a, b of species s_a, s_b is the
+                            PSF at the offset r_b - r_a,
+                              sum_i exp(-i 2 pi (k_i . (r_b - r_a) + (f_sb - f_sa) t_i)),
+                            formed once on the (2nx-1) x (2ny-1) offset grid for each species
+                            pair (FP64) and then expanded: O(K nx ny S^2 + C N^2) work instead
+                            of O(K N^2) */
+  PINV_GRAM_SHARED = 2,  /* F^H F on MFMA in FP64 over one coil's nk rows (F generated per
+                            tile), times the coil cross-products: 4 nk N^2 flops */
+  PINV_GRAM_FULL = 3     /* E^H E over all M = C*nk rows in the plan's precision (Eq. 11 as
+                            written): 4 M N^2 flops; the only form for an FP32 Gram */
+} pinv_gram_form;
 
 typedef struct {
   double lambda;              /* >= 0; meaning set by lambda_mode */
   int32_t lambda_mode;        /* pinv_lambda_mode */
   int32_t prec;               /* pinv_precision */
   int32_t flags;              /* PINV_FLAG_* */
-  int32_t reserved;           /* must be 0 */
+  int32_t cprod;              /* pinv_cprod; PINV_BF16X3 plans take only AUTO */
+  int32_t nb;                 /* factorisation block size: 0 (default) or 64.  Fixed at 64:
+                                 the diagonal-block kernel holds one 64 x 64 complex128 block
+                                 in registers, one column per lane of a 64-wide wavefront,
+                                 and the panel and trailing tiles are 64 x 64 */
+  int32_t gram;               /* pinv_gram_form */
 } pinv_build_opts;
 
 typedef struct {
@@ -118,6 +165,11 @@ typedef struct {
   int32_t has_r;              /* 0 for plans built with PINV_FLAG_NO_R */
   int64_t gram_order;         /* N, or M when M < N (the samples' Gram E E^H, right
                                  pseudoinverse R = E^H (E E^H + lambda I)^-1, Sec. 2.2) */
+  int32_t ncoil;              /* C */
+  int32_t cprod;              /* the product form used: PINV_CPROD_3M or PINV_CPROD_4M */
+  int64_t nk;                 /* samples per coil */
+  int32_t gram_form;          /* the Gram form used (PSF, SHARED or FULL; SHARED for M < N) */
+  int32_t r_fp64;             /* 1 if R was formed in FP64 (PINV_FLAG_R_FP64) */
 } pinv_plan_info;
 
 typedef struct {
@@ -188,9 +240,11 @@ pinv_status pinv_encoding_key(const pinv_encoding *e, const pinv_build_opts *o, 
 pinv_status pinv_apply(pinv_context *ctx, const pinv_plan *p, const void *data, int64_t F,
                        void *image, int32_t refine_steps, void *hip_stream);
 
-/* Several applies (possibly of different plans and sizes) in grouped launches:
- * one MFMA launch per run of up to 32 items of the same precision.  Each
- * item's result equals what pinv_apply gives for it alone.  Errors as
+/* Several applies (possibly of different plans and sizes) in grouped launches
+ * (Sec. 4.1: one R reconstructs every time point and metabolite in a few
+ * matrix-matrix products; Sec. 5: R reused across acquisitions): one MFMA
+ * launch per run of up to 32 items of the same precision and product form.
+ * Each item's result equals what pinv_apply gives for it alone.  Errors as
  * pinv_apply. */
 pinv_status pinv_apply_grouped(pinv_context *ctx, int32_t n, const pinv_apply_item *items,
                                int32_t refine_steps, void *hip_stream);
@@ -198,7 +252,7 @@ pinv_status pinv_apply_grouped(pinv_context *ctx, int32_t n, const pinv_apply_it
 /* Shapes of the image-quality metrics. */
 typedef enum { PINV_METRIC_DIAG = 0, PINV_METRIC_FULL = 1 } pinv_metric_mode;
 
-/* Spatial response function of the plan's reconstruction (Sec. 2.4, Eq. 9):
+/* Spatial response function of the plan's reconstruction (Sec. 2.5, Eq. 9):
  * SRF = R E, with E regenerated from the plan's tables as in the build.
  * PINV_METRIC_DIAG writes the N diagonal entries (the SRF map; the caller
  * reshapes column order n = s*V + iy*nx + ix to the grid); PINV_METRIC_FULL
@@ -211,7 +265,7 @@ typedef enum { PINV_METRIC_DIAG = 0, PINV_METRIC_FULL = 1 } pinv_metric_mode;
 pinv_status pinv_srf(pinv_context *ctx, const pinv_plan *p, int32_t mode, void *out,
                      void *hip_stream);
 
-/* Noise matrix of the reconstruction (Sec. 2.4, Eq. 10): X = R Psi R^H for
+/* Noise matrix of the reconstruction (Sec. 2.5, Eq. 10): X = R Psi R^H for
  * data noise that is white over samples and correlated over coils,
  * Psi = Psi_c (kron) I_K.  coil_cov: host [C][C] complex128 interleaved,
  * row-major, Hermitian positive definite, copied before return; NULL means

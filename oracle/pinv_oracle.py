@@ -22,7 +22,9 @@ with the sign convention exp(-i 2 pi ...) used throughout this project):
 
     E[(c,i),(s,v)] = C_c(v) * exp(-i 2 pi (k_i . r_v + (f_s + B0(v)) t_i))
 
-Rows m = c*K + i (coil-major), columns n = s*V + v with v = iy*nx + ix.
+Rows m = c*K + i (coil-major), columns n = s*V + v with v = iy*nx + ix, or,
+when a voxel mask restricts the unknowns to a region (Sec. 3.1, Sec. 4.4),
+v = the position in the mask's ascending list of grid indices.
 Voxel centres r_v = ((ix - nx/2)/nx, (iy - ny/2)/ny) in FOV units, k in
 cycles/FOV, frequencies in Hz, times in seconds.
 
@@ -55,8 +57,16 @@ class NotPositiveDefinite(ArithmeticError):
 # the encoding matrix  (Eq. 1, Eq. 2; generalised product encoding, Sec. 3.3)
 # ----------------------------------------------------------------------------
 
+def unknown_voxels(enc) -> np.ndarray:
+    """Grid indices v = iy*nx + ix of the unknowns: every voxel, or the listed
+    ones when a mask restricts the unknowns to a region (Sec. 3.1, Sec. 4.4)."""
+    if getattr(enc, "voxels", None) is None:
+        return np.arange(enc.nx * enc.ny)
+    return np.asarray(enc.voxels, dtype=np.int64)
+
+
 def _dims(enc):
-    V = enc.nx * enc.ny
+    V = len(unknown_voxels(enc))
     S = 1 if enc.species_hz is None else len(enc.species_hz)
     K = enc.k.shape[0]
     C = 1 if enc.coil is None else enc.coil.shape[0]
@@ -70,6 +80,15 @@ def voxel_positions(nx: int, ny: int):
     return X.ravel(), Y.ravel()
 
 
+def _unknown_positions(enc):
+    """Centres, off-resonance and coil maps at the unknown voxels."""
+    g = unknown_voxels(enc)
+    X, Y = voxel_positions(enc.nx, enc.ny)
+    b0 = np.zeros(len(g)) if enc.b0_hz is None else np.asarray(enc.b0_hz, float)[g]
+    coil = None if enc.coil is None else enc.coil[:, g]
+    return X[g], Y[g], b0, coil
+
+
 def encoding_rows(enc, m0: int, m1: int) -> np.ndarray:
     """Rows m0..m1-1 of E, explicitly, [m1-m0, N] complex128.
 
@@ -77,7 +96,7 @@ def encoding_rows(enc, m0: int, m1: int) -> np.ndarray:
     trigonometric functions so the FP64 angle keeps full relative accuracy.
     """
     V, S, K, C = _dims(enc)
-    X, Y = voxel_positions(enc.nx, enc.ny)
+    X, Y, b0, coil = _unknown_positions(enc)
     m = np.arange(m0, m1)
     c = m // K
     i = m % K
@@ -85,15 +104,14 @@ def encoding_rows(enc, m0: int, m1: int) -> np.ndarray:
     ky = enc.k[i, 1][:, None]
     spatial = kx * X[None, :] + ky * Y[None, :]                    # [rows, V]
     species = np.zeros(S) if enc.species_hz is None else np.asarray(enc.species_hz, float)
-    b0 = np.zeros(V) if enc.b0_hz is None else np.asarray(enc.b0_hz, float)
     t = np.zeros(K) if enc.t is None else np.asarray(enc.t, float)
     blocks = []
     for s in range(S):
         turns = spatial + (species[s] + b0[None, :]) * t[i][:, None]
         frac = turns - np.round(turns)
         phase = np.cos(2.0 * math.pi * frac) - 1j * np.sin(2.0 * math.pi * frac)
-        if enc.coil is not None:
-            phase = phase * enc.coil[c, :]
+        if coil is not None:
+            phase = phase * coil[c, :]
         blocks.append(phase)
     return np.concatenate(blocks, axis=1)
 
@@ -106,19 +124,18 @@ def encoding_columns(enc, cols, m0: int = 0, m1: int = None) -> np.ndarray:
     cols = np.asarray(cols)
     s_idx = cols // V
     v_idx = cols % V
-    X, Y = voxel_positions(enc.nx, enc.ny)
+    X, Y, b0, coil = _unknown_positions(enc)
     m = np.arange(m0, m1)
     c = m // K
     i = m % K
     species = np.zeros(S) if enc.species_hz is None else np.asarray(enc.species_hz, float)
-    b0 = np.zeros(V) if enc.b0_hz is None else np.asarray(enc.b0_hz, float)
     t = np.zeros(K) if enc.t is None else np.asarray(enc.t, float)
     turns = (enc.k[i, 0][:, None] * X[v_idx][None, :] + enc.k[i, 1][:, None] * Y[v_idx][None, :]
              + (species[s_idx][None, :] + b0[v_idx][None, :]) * t[i][:, None])
     frac = turns - np.round(turns)
     out = np.cos(2.0 * math.pi * frac) - 1j * np.sin(2.0 * math.pi * frac)
-    if enc.coil is not None:
-        out = out * enc.coil[c[:, None], v_idx[None, :]]
+    if coil is not None:
+        out = out * coil[c[:, None], v_idx[None, :]]
     return out
 
 

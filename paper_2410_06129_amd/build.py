@@ -9,7 +9,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpinv.so")
-SOURCES = ["pinv_kernels.hip", "pinv_metrics.hip", "pinv_api.hip", "pinv_serve.hip"]
+SOURCES = ["pinv_gram.hip", "pinv_chol.hip", "pinv_trmm.hip", "pinv_apply.hip", "pinv_solve.hip",
+           "pinv_metrics.hip", "pinv_api.hip", "pinv_serve.hip"]
 SIM_LIB = os.path.join(HERE, "libpinv_schedsim.so")
 HEADERS = ["pinv_device.h", "pinv_internal.h"]
 
@@ -21,8 +22,8 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found; the HIP toolchain (ROCm) is required to build libpinv")
 
 
-def build(verbose: bool = False, jobs: int = 2) -> str:
-    """Compile every source (always; no staleness shortcut) and link libpinv.so."""
+def build(verbose: bool = False) -> str:
+    """Compile every source in parallel (always; no staleness shortcut) and link libpinv.so."""
     cc = hipcc()
     flags = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -1,6 +1,7 @@
 // C-ABI of libpinv: contexts, plan cache with HBM admission, encoding tables,
 // and the build / apply / forward pipelines.  Every arithmetic step of the
-// path runs in the kernels of pinv_kernels.hip.
+// path runs in the kernels of pinv_gram.hip, pinv_chol.hip, pinv_trmm.hip,
+// pinv_apply.hip, pinv_solve.hip and pinv_metrics.hip.
 #include <math.h>
 #include <string.h>
 
@@ -58,6 +59,9 @@ struct pinv_plan {
   bool no_r = false;         // factor-only plan: no W, no R (applies solve with L^-1)
   bool right = false;        // M < N: Gram, factor and L^-1 are the samples' (M x M)
   int G = 0;                 // order of the Gram and the factor: N, or M when right
+  bool m3 = true;            // W, R and apply with three real products per complex product
+  int gram_form = PINV_GRAM_SHARED;   // how the Gram was formed
+  bool r_fp64 = false;       // FP32 plan whose W and R were formed in FP64
   int* info = nullptr;
   bool pooled = false;             // device buffers from the context's plan pool
   size_t bytes = 0;
@@ -123,7 +127,8 @@ size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
 
 struct Dims {
   int nx, ny, V, S, C, K, N, M;
-  bool has_q, has_coil, has_b0;
+  int Vg;          // grid voxels nx*ny (V = Vg without a mask, nvox with one)
+  bool has_q, has_coil, has_b0, masked;
 };
 
 pinv_status validate(const pinv_encoding* e, Dims* d) {
@@ -138,7 +143,20 @@ pinv_status validate(const pinv_encoding* e, Dims* d) {
     return fail(PINV_ERR_INVALID, "nspecies > 1 needs species_hz");
   const bool need_t = e->nspecies > 1 || e->species_hz != nullptr || e->b0_hz != nullptr;
   if (need_t && !e->t) return fail(PINV_ERR_INVALID, "sample times t are required with species or B0");
-  const long long V = (long long)e->nx * e->ny;
+  const long long Vg = (long long)e->nx * e->ny;
+  if (e->nx > 32767 || e->ny > 32767) return fail(PINV_ERR_UNSUPPORTED, "nx and ny above 32767");
+  long long V = Vg;
+  if (e->voxels) {
+    if (e->nvox < 1) return fail(PINV_ERR_INVALID, "a voxel mask needs nvox >= 1");
+    for (int j = 0; j < e->nvox; ++j) {
+      if (e->voxels[j] < 0 || e->voxels[j] >= Vg)
+        return fail(PINV_ERR_INVALID, "voxel index " + std::to_string(e->voxels[j]) +
+                                          " outside the grid");
+      if (j > 0 && e->voxels[j] <= e->voxels[j - 1])
+        return fail(PINV_ERR_INVALID, "voxel mask must be strictly ascending");
+    }
+    V = e->nvox;
+  }
   const long long N = V * e->nspecies;
   const long long M = (long long)e->ncoil * e->nk;
   if (N > 65536) return fail(PINV_ERR_UNSUPPORTED, "N = S*nx*ny above 65536");
@@ -146,6 +164,8 @@ pinv_status validate(const pinv_encoding* e, Dims* d) {
   d->nx = e->nx;
   d->ny = e->ny;
   d->V = (int)V;
+  d->Vg = (int)Vg;
+  d->masked = e->voxels != nullptr;
   d->S = e->nspecies;
   d->C = e->ncoil;
   d->K = (int)e->nk;
@@ -162,7 +182,7 @@ pinv_status validate(const pinv_encoding* e, Dims* d) {
   return PINV_OK;
 }
 
-uint64_t plan_key(const pinv_encoding* e, const Dims& d, double lam, int prec) {
+uint64_t plan_key(const pinv_encoding* e, const Dims& d, double lam, int prec, int form_bits) {
   Fnv f;
   f.add(d.nx);
   f.add(d.ny);
@@ -173,13 +193,16 @@ uint64_t plan_key(const pinv_encoding* e, const Dims& d, double lam, int prec) {
   f.add(uint8_t(e->t != nullptr));
   if (e->t) f.add(e->t, sizeof(double) * d.K);
   f.add(uint8_t(e->coil != nullptr));
-  if (e->coil) f.add(e->coil, sizeof(double) * 2 * (size_t)d.C * d.V);
+  if (e->coil) f.add(e->coil, sizeof(double) * 2 * (size_t)d.C * d.Vg);
   f.add(uint8_t(e->b0_hz != nullptr));
-  if (e->b0_hz) f.add(e->b0_hz, sizeof(double) * d.V);
+  if (e->b0_hz) f.add(e->b0_hz, sizeof(double) * d.Vg);
+  f.add(uint8_t(d.masked));
+  if (d.masked) f.add(e->voxels, sizeof(int32_t) * d.V);
   f.add(uint8_t(e->species_hz != nullptr));
   if (e->species_hz) f.add(e->species_hz, sizeof(double) * d.S);
   f.add(lam);
   f.add(prec);
+  f.add(form_bits);
   return f.h;
 }
 
@@ -193,6 +216,7 @@ inline void phasor(double turns, double* re, double* im) {
 // Host FP64 tables (Px, Py, Q, coil, b0, t), laid out contiguously.
 struct HostTables {
   std::vector<double> px, py, q, coil, b0, t;
+  std::vector<int32_t> vxy;   // (iy << 16) | ix of each unknown voxel (masked encodings only)
 };
 
 void build_tables(const pinv_encoding* e, const Dims& d, HostTables* h) {
@@ -217,10 +241,28 @@ void build_tables(const pinv_encoding* e, const Dims& d, HostTables* h) {
         phasor(f * e->t[i], &h->q[2 * ((size_t)i * d.S + s)], &h->q[2 * ((size_t)i * d.S + s) + 1]);
       }
   }
-  if (d.has_coil) h->coil.assign(e->coil, e->coil + 2 * (size_t)d.C * d.V);
+  // coil maps and the off-resonance map at the unknown voxels only
+  auto grid_voxel = [&](int j) { return d.masked ? (size_t)e->voxels[j] : (size_t)j; };
+  if (d.has_coil) {
+    h->coil.resize(2 * (size_t)d.C * d.V);
+    for (int c = 0; c < d.C; ++c)
+      for (int j = 0; j < d.V; ++j) {
+        const size_t src = 2 * ((size_t)c * d.Vg + grid_voxel(j)), dst = 2 * ((size_t)c * d.V + j);
+        h->coil[dst] = e->coil[src];
+        h->coil[dst + 1] = e->coil[src + 1];
+      }
+  }
   if (d.has_b0) {
-    h->b0.assign(e->b0_hz, e->b0_hz + d.V);
+    h->b0.resize(d.V);
+    for (int j = 0; j < d.V; ++j) h->b0[j] = e->b0_hz[grid_voxel(j)];
     h->t.assign(e->t, e->t + d.K);
+  }
+  if (d.masked) {
+    h->vxy.resize(d.V);
+    for (int j = 0; j < d.V; ++j) {
+      const int v = e->voxels[j], iy = v / d.nx, ix = v - iy * d.nx;
+      h->vxy[j] = (iy << 16) | ix;
+    }
   }
 }
 
@@ -230,7 +272,7 @@ size_t tables_bytes(const HostTables& h) {
   size_t tot = 0;
   for (size_t n : {h.px.size(), h.py.size(), h.q.size(), h.coil.size(), h.b0.size(), h.t.size()})
     tot += align256(n * sizeof(T));
-  return tot;
+  return tot + align256(h.vxy.size() * sizeof(int32_t));
 }
 
 // Converts the tables to T into `host` (pinned staging, tables_bytes<T> long)
@@ -251,6 +293,11 @@ pinv_status upload_tables(const HostTables& h, const Dims& d, hipStream_t s, voi
     T* dst = (T*)((char*)host + off[i]);
     for (size_t j = 0; j < ns[i]; ++j) dst[j] = (T)(*src[i])[j];
   }
+  const size_t off_vxy = tot;
+  if (!h.vxy.empty()) {
+    memcpy((char*)host + off_vxy, h.vxy.data(), h.vxy.size() * sizeof(int32_t));
+    tot += align256(h.vxy.size() * sizeof(int32_t));
+  }
   HIPCHK(hipMemcpyAsync(dev, host, tot, hipMemcpyHostToDevice, s));
   char* b = (char*)dev;
   ev->px = (const T*)(b + off[0]);
@@ -259,6 +306,7 @@ pinv_status upload_tables(const HostTables& h, const Dims& d, hipStream_t s, voi
   ev->coil = n_c ? (const T*)(b + off[3]) : nullptr;
   ev->b0 = n_b ? (const T*)(b + off[4]) : nullptr;
   ev->t = n_t ? (const T*)(b + off[5]) : nullptr;
+  ev->vxy = h.vxy.empty() ? nullptr : (const int*)(b + off_vxy);
   ev->nx = d.nx;
   ev->ny = d.ny;
   ev->S = d.S;
@@ -349,21 +397,40 @@ void drain_frees(pinv_context* c, hipStream_t s, bool wait) {
   }
 }
 
-size_t plan_footprint(const Dims& d, int prec, bool no_r) {
+// Build options after defaults: the complex-product form of W, R and the
+// apply, the Gram form, and whether W and R are formed in FP64.
+struct BuildForm {
+  bool m3 = true;
+  int gram = PINV_GRAM_SHARED;
+  bool r_fp64 = false;
+  bool no_r = false;
+};
+
+// Device bytes a build needs at its peak: plan buffers plus build workspaces.
+size_t plan_footprint(const Dims& d, int prec, const BuildForm& f) {
   const size_t N = d.N, M = d.M;
   const bool right = d.M < d.N;
   const size_t Gd = right ? M : N;   // order of the Gram and the factor
   const size_t cs = prec == PINV_FP64 ? 16 : 8;
+  const size_t ws = f.r_fp64 ? 16 : cs;   // W (and Z) element size
   size_t b = 0;
   b += 16 * Gd * Gd;            // Gram / factor workspace (FP64)
   b += 16 * Gd * Gd;            // L^-1 in FP64 during the factorisation
   b += cs * Gd * Gd;            // L^-1 kept
-  if (!no_r) {
-    b += cs * N * M;            // W (and Z for the right pseudoinverse)
-    if (right) b += cs * N * M;
+  if (!f.no_r) {
+    b += ws * N * M;            // W (and Z for the right pseudoinverse)
+    if (right) b += ws * N * M;
     b += cs * N * M;            // R
   }
   b += 16 * Gd * Gd;            // the Gram kept
+  if (f.gram == PINV_GRAM_PSF) {
+    EncDev<double> e{};
+    e.nx = d.nx;
+    e.ny = d.ny;
+    e.S = d.S;
+    e.K = d.K;
+    b += psf_work_bytes(e, nullptr);
+  }
   b += 64ull << 20;             // tables and slack
   return b;
 }
@@ -569,25 +636,37 @@ pinv_status pinv_context_destroy(pinv_context* c) {
   return PINV_OK;
 }
 
-// Validate a build request and derive the absolute shift and the cache key.
+// Validate a build request and derive the absolute shift, the cache key and
+// the resolved options.
 static pinv_status check_build(const pinv_encoding* e, const pinv_build_opts* o, Dims* d,
-                               double* lam_out, uint64_t* key_out) {
+                               double* lam_out, uint64_t* key_out, BuildForm* form) {
   if (!o) return fail(PINV_ERR_INVALID, "NULL options");
   pinv_status st = validate(e, d);
   if (st != PINV_OK) return st;
   if (o->prec != PINV_FP64 && o->prec != PINV_FP32 && o->prec != PINV_BF16X3)
     return fail(PINV_ERR_INVALID, "unknown precision");
-  if (o->reserved != 0) return fail(PINV_ERR_INVALID, "reserved must be 0");
-  if (o->flags & ~(PINV_FLAG_KEEP_GRAM | PINV_FLAG_UNCACHED | PINV_FLAG_GRAM_FULL | PINV_FLAG_NO_R))
+  if (o->flags & ~(PINV_FLAG_KEEP_GRAM | PINV_FLAG_UNCACHED | PINV_FLAG_GRAM_FULL | PINV_FLAG_NO_R |
+                   PINV_FLAG_R_FP64))
     return fail(PINV_ERR_INVALID, "unknown flag bits");
+  if (o->cprod < PINV_CPROD_AUTO || o->cprod > PINV_CPROD_4M)
+    return fail(PINV_ERR_INVALID, "unknown cprod");
+  if (o->nb != 0 && o->nb != 64)
+    return fail(PINV_ERR_UNSUPPORTED, "nb must be 0 or 64: the factorisation's diagonal block is "
+                                      "64 x 64, one column per lane of a wavefront");
+  if (o->gram < PINV_GRAM_AUTO || o->gram > PINV_GRAM_FULL)
+    return fail(PINV_ERR_INVALID, "unknown gram form");
   if (!(o->lambda >= 0.0) || !isfinite(o->lambda)) return fail(PINV_ERR_INVALID, "lambda must be finite and >= 0");
   double lam = o->lambda;
   if (o->lambda_mode == PINV_LAMBDA_REL_MEAN_DIAG) {
-    // trace(E^H E) = K * S * sum_v sum_c |C_c(v)|^2 since every phase factor has modulus 1
+    // trace(E^H E) = K * S * sum_v sum_c |C_c(v)|^2 over the unknown voxels, since
+    // every phase factor has modulus 1
     double cp = 0.0;
     if (e->coil) {
-      for (size_t i = 0; i < (size_t)d->C * d->V; ++i)
-        cp += e->coil[2 * i] * e->coil[2 * i] + e->coil[2 * i + 1] * e->coil[2 * i + 1];
+      for (int c = 0; c < d->C; ++c)
+        for (int j = 0; j < d->V; ++j) {
+          const size_t i = (size_t)c * d->Vg + (d->masked ? (size_t)e->voxels[j] : (size_t)j);
+          cp += e->coil[2 * i] * e->coil[2 * i] + e->coil[2 * i + 1] * e->coil[2 * i + 1];
+        }
     } else {
       cp = (double)d->V;
     }
@@ -595,19 +674,42 @@ static pinv_status check_build(const pinv_encoding* e, const pinv_build_opts* o,
   } else if (o->lambda_mode != PINV_LAMBDA_ABS) {
     return fail(PINV_ERR_INVALID, "unknown lambda_mode");
   }
-  const bool gram_full = (o->flags & PINV_FLAG_GRAM_FULL) != 0;
   const bool no_r = (o->flags & PINV_FLAG_NO_R) != 0;
+  const bool r_fp64 = (o->flags & PINV_FLAG_R_FP64) != 0;
+  int gram = o->gram;
+  if (o->flags & PINV_FLAG_GRAM_FULL) {
+    if (gram != PINV_GRAM_AUTO && gram != PINV_GRAM_FULL)
+      return fail(PINV_ERR_INVALID, "PINV_FLAG_GRAM_FULL with another gram form");
+    gram = PINV_GRAM_FULL;
+  }
   if (no_r && o->prec == PINV_BF16X3)
     return fail(PINV_ERR_INVALID, "PINV_FLAG_NO_R with PINV_BF16X3: the split products only form W and R");
+  if (o->prec == PINV_BF16X3 && o->cprod != PINV_CPROD_AUTO)
+    return fail(PINV_ERR_INVALID, "PINV_BF16X3 plans take cprod = PINV_CPROD_AUTO");
+  if (r_fp64 && o->prec != PINV_FP32)
+    return fail(PINV_ERR_INVALID, "PINV_FLAG_R_FP64 is for PINV_FP32 plans");
+  if (r_fp64 && no_r) return fail(PINV_ERR_INVALID, "PINV_FLAG_R_FP64 with PINV_FLAG_NO_R: no R");
   if (d->M < d->N) {   // right pseudoinverse through the samples' Gram
     if (no_r) return fail(PINV_ERR_INVALID, "PINV_FLAG_NO_R needs M >= N (the unknowns' Gram)");
     if (o->prec == PINV_BF16X3)
       return fail(PINV_ERR_UNSUPPORTED, "PINV_BF16X3 with M < N (right pseudoinverse)");
-    if (gram_full) return fail(PINV_ERR_INVALID, "PINV_FLAG_GRAM_FULL needs M >= N");
+    if (gram != PINV_GRAM_AUTO)
+      return fail(PINV_ERR_INVALID, "M < N forms the samples' Gram; gram must be PINV_GRAM_AUTO");
+    gram = PINV_GRAM_SHARED;
+  } else if (gram == PINV_GRAM_AUTO) {
+    gram = d->has_b0 ? PINV_GRAM_SHARED : PINV_GRAM_PSF;
+  } else if (gram == PINV_GRAM_PSF && d->has_b0) {
+    return fail(PINV_ERR_INVALID, "PINV_GRAM_PSF needs an encoding without an off-resonance map");
   }
+  form->gram = gram;
+  form->no_r = no_r;
+  form->r_fp64 = r_fp64;
+  form->m3 = o->cprod == PINV_CPROD_3M   ? true
+             : o->cprod == PINV_CPROD_4M ? false
+                                         : o->prec != PINV_FP64;
   *lam_out = lam;
-  *key_out = plan_key(e, *d, lam, o->prec) ^ (gram_full ? 0xc2b2ae3d27d4eb4full : 0) ^
-             (no_r ? 0x9e3779b97f4a7c15ull : 0);
+  const int bits = (form->m3 ? 1 : 0) | (gram << 1) | (r_fp64 ? 16 : 0) | (no_r ? 32 : 0);
+  *key_out = plan_key(e, *d, lam, o->prec, bits);
   return PINV_OK;
 }
 
@@ -616,10 +718,11 @@ pinv_status pinv_encoding_key(const pinv_encoding* e, const pinv_build_opts* o, 
   Dims d;
   double lam;
   uint64_t k;
-  pinv_status st = check_build(e, o, &d, &lam, &k);
+  BuildForm form;
+  pinv_status st = check_build(e, o, &d, &lam, &k, &form);
   if (st != PINV_OK) return st;
   if (key) *key = k;
-  if (plan_bytes) *plan_bytes = plan_footprint(d, o->prec, (o->flags & PINV_FLAG_NO_R) != 0);
+  if (plan_bytes) *plan_bytes = plan_footprint(d, o->prec, form);
   return PINV_OK;
 }
 
@@ -691,9 +794,9 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
   Dims d;
   double lam;
   uint64_t key;
-  pinv_status st = check_build(e, o, &d, &lam, &key);
+  BuildForm form;
+  pinv_status st = check_build(e, o, &d, &lam, &key, &form);
   if (st != PINV_OK) return st;
-  const bool gram_full = (o->flags & PINV_FLAG_GRAM_FULL) != 0;
   hipStream_t s = (hipStream_t)stream;
   HIPCHK(hipSetDevice(c->device));
 
@@ -709,8 +812,8 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
     *out = p;
     return PINV_OK;
   }
-  const bool no_r = (o->flags & PINV_FLAG_NO_R) != 0;
-  const size_t foot = plan_footprint(d, o->prec, no_r);
+  const bool no_r = form.no_r;
+  const size_t foot = plan_footprint(d, o->prec, form);
   if (!make_room(c, foot))
     return fail(PINV_ERR_NOMEM, "plan footprint " + std::to_string(foot) +
                                     " B exceeds the free budget");
@@ -731,6 +834,9 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
   p->no_r = no_r;
   p->right = d.M < d.N;
   p->G = p->right ? d.M : d.N;
+  p->m3 = form.m3;
+  p->gram_form = form.gram;
+  p->r_fp64 = form.r_fp64;
   auto cleanup = [&](pinv_status rs) {
     (void)hipStreamSynchronize(s);
     free_plan_memory(p);
@@ -743,7 +849,8 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
   const size_t N = d.N, M = d.M;
   const bool f64 = o->prec == PINV_FP64;
   const size_t cs = f64 ? 16 : 8;
-  void *G = nullptr, *L64 = nullptr, *W = nullptr, *Z = nullptr;
+  const size_t ws = form.r_fp64 ? 16 : cs;   // W and Z element size
+  void *G = nullptr, *L64 = nullptr, *W = nullptr, *Z = nullptr, *PW = nullptr;
   const size_t Gd = p->G;   // order of the Gram and the factor
   hipError_t he;
 #define BCHK(expr)                                                                    \
@@ -756,6 +863,7 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
       if (L64 && L64 != p->Linv) (void)hipFreeAsync(L64, s);                          \
       if (W) (void)hipFreeAsync(W, s);                                                \
       if (Z) (void)hipFreeAsync(Z, s);                                                \
+      if (PW) (void)hipFreeAsync(PW, s);                                              \
       return cleanup(he == hipErrorOutOfMemory ? PINV_ERR_NOMEM : PINV_ERR_DEVICE);   \
     }                                                                                 \
   } while (0)
@@ -789,7 +897,7 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
   if (!no_r) BCHK(plan_malloc(&p->R, cs * N * M, c, s));
   BCHK(plan_malloc(&p->Linv, cs * Gd * Gd, c, s));
   BCHK(plan_malloc(&p->gram, 16 * Gd * Gd, c, s));
-  p->gram_exact = !(gram_full && !f64);
+  p->gram_exact = !(form.gram == PINV_GRAM_FULL && !f64);
   BCHK(workspace_alloc(&G, 16 * Gd * Gd, c, s));
   if (f64) {
     L64 = p->Linv;
@@ -797,21 +905,30 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
     BCHK(workspace_alloc(&L64, 16 * Gd * Gd, c, s));
   }
   BCHK(hipMemsetAsync(L64, 0, 16 * Gd * Gd, s));
-  if (!no_r) BCHK(workspace_alloc(&W, cs * N * M, c, s));
-  if (p->right) BCHK(workspace_alloc(&Z, cs * N * M, c, s));
+  if (!no_r) BCHK(workspace_alloc(&W, ws * N * M, c, s));
+  if (p->right) BCHK(workspace_alloc(&Z, ws * N * M, c, s));
+  if (form.gram == PINV_GRAM_PSF) BCHK(workspace_alloc(&PW, psf_work_bytes(p->e64, nullptr), c, s));
 
-  // 1. Gram (a3) with E generated per tile (a2)
+  // 1. Gram (a3) with E generated per tile (a2), or through the PSF
   BCHK(hipEventRecord(p->ev[0], s));
-  if (p->right)
-    BCHK(launch_gram_rows(p->e64, (double*)G, s));   // FP64 E E^H over the N unknowns
-  else if (!gram_full)
-    BCHK(launch_gram_shared<double>(p->e64, (double*)G, s));   // FP64 F^H F, coil products (Eq. 11)
-  else if (f64)
-    BCHK(launch_gram<double>(p->e64, (double*)G, 0, s));
-  else
-    BCHK(launch_gram<float>(p->e32, (double*)G, 2048, s));
-  BCHK(hipMemcpyAsync(p->gram, G, 16 * Gd * Gd, hipMemcpyDeviceToDevice, s));
-  BCHK(launch_herm_fill((double*)p->gram, (int)Gd, s));
+  if (form.gram == PINV_GRAM_PSF) {
+    // offset-grid PSF times the coil cross-products, written to the workspace
+    // and the kept Gram (both full Hermitian)
+    BCHK(launch_psf_gram(p->e64, PW, (double*)G, (double*)p->gram, s));
+    BCHK(hipFreeAsync(PW, s));
+    PW = nullptr;
+  } else {
+    if (p->right)
+      BCHK(launch_gram_rows(p->e64, (double*)G, s));   // FP64 E E^H over the N unknowns
+    else if (form.gram == PINV_GRAM_SHARED)
+      BCHK(launch_gram_shared<double>(p->e64, (double*)G, s));   // FP64 F^H F, coil products (Eq. 11)
+    else if (f64)
+      BCHK(launch_gram<double>(p->e64, (double*)G, 0, s));
+    else
+      BCHK(launch_gram<float>(p->e32, (double*)G, 2048, s));
+    BCHK(hipMemcpyAsync(p->gram, G, 16 * Gd * Gd, hipMemcpyDeviceToDevice, s));
+    BCHK(launch_herm_fill((double*)p->gram, (int)Gd, s));
+  }
   BCHK(hipEventRecord(p->ev[1], s));
   // 2. shift + blocked Cholesky with L^-1 (a4), FP64
   BCHK(launch_cholinv((double*)G, (double*)L64, (int)Gd, lam, p->info, s,
@@ -820,28 +937,41 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
   BCHK(hipEventRecord(p->ev[2], s));
   // 3. W = L^-1 E^H, R = L^-H W (a5); a factor-only plan stops at L^-1.  With
   // fewer samples than unknowns, W' = L'^-1 E, Z = L'^-H W' and R = Z^H.
+  // An FP32 plan with FP64-formed R runs both products in FP64 from the FP64
+  // factor and tables and rounds R once to complex64.
+  const bool m3 = form.m3;
   if (no_r) {
     BCHK(hipEventRecord(p->ev[3], s));
   } else if (p->right) {
     BCHK(hipEventRecord(p->ev[3], s));
     if (f64)
-      BCHK(launch_right_pinv<double>(p->e64, (const double*)p->Linv, (double*)W, (double*)Z,
-                                     (double*)p->R, s));
+      BCHK((launch_right_pinv<double, double>(p->e64, (const double*)p->Linv, (double*)W, (double*)Z,
+                                              (double*)p->R, m3, s)));
+    else if (form.r_fp64)
+      BCHK((launch_right_pinv<double, float>(p->e64, (const double*)L64, (double*)W, (double*)Z,
+                                             (float*)p->R, m3, s)));
     else
-      BCHK(launch_right_pinv<float>(p->e32, (const float*)p->Linv, (float*)W, (float*)Z,
-                                    (float*)p->R, s));
+      BCHK((launch_right_pinv<float, float>(p->e32, (const float*)p->Linv, (float*)W, (float*)Z,
+                                            (float*)p->R, m3, s)));
   } else if (f64) {
-    BCHK(launch_trmm_w<double>(p->e64, (const double*)p->Linv, (double*)W, s));
+    BCHK(launch_trmm_w<double>(p->e64, (const double*)p->Linv, (double*)W, m3, s));
     BCHK(hipEventRecord(p->ev[3], s));
-    BCHK(launch_trmm_r<double>((const double*)p->Linv, (const double*)W, (double*)p->R, d.N, d.M, s));
+    BCHK((launch_trmm_r<double, double>((const double*)p->Linv, (const double*)W, (double*)p->R, d.N,
+                                        d.M, m3, s)));
+  } else if (form.r_fp64) {
+    BCHK(launch_trmm_w<double>(p->e64, (const double*)L64, (double*)W, m3, s));
+    BCHK(hipEventRecord(p->ev[3], s));
+    BCHK((launch_trmm_r<double, float>((const double*)L64, (const double*)W, (float*)p->R, d.N, d.M,
+                                       m3, s)));
   } else if (o->prec == PINV_BF16X3) {
     BCHK(launch_trmm_w_b3(p->e32, (const float*)p->Linv, (float*)W, s));
     BCHK(hipEventRecord(p->ev[3], s));
     BCHK(launch_trmm_r_b3((const float*)p->Linv, (const float*)W, (float*)p->R, d.N, d.M, s));
   } else {
-    BCHK(launch_trmm_w<float>(p->e32, (const float*)p->Linv, (float*)W, s));
+    BCHK(launch_trmm_w<float>(p->e32, (const float*)p->Linv, (float*)W, m3, s));
     BCHK(hipEventRecord(p->ev[3], s));
-    BCHK(launch_trmm_r<float>((const float*)p->Linv, (const float*)W, (float*)p->R, d.N, d.M, s));
+    BCHK((launch_trmm_r<float, float>((const float*)p->Linv, (const float*)W, (float*)p->R, d.N, d.M,
+                                      m3, s)));
   }
   BCHK(hipEventRecord(p->ev[4], s));
   if (W) BCHK(hipFreeAsync(W, s));
@@ -911,38 +1041,45 @@ pinv_status pinv_plan_query(pinv_plan* p) {
 //   r = E^H d - (G + lam I) x   in FP64  (b = E^H d formed once, E regenerated in FP64)
 //   x += L^-H L^-1 r            (the plan's factor)
 // When the plan's Gram is not exact to FP64 (FP32 Gram over all rows) the
-// residual is formed as E^H (d - E x) - lam x instead.
+// residual is formed as E^H (d - E x) - lam x instead.  Scratch: r and t
+// (F x N of TS), and b (F x N FP64) or d - E x (F x M FP64), plus the
+// adjoint's split partials.
 extern "C++" {
 template <typename TS>   // storage type of data/images and of the plan's L^-1
 static pinv_status refine_item(pinv_plan* p, const void* data, int F, void* image, int steps,
-                               hipStream_t s) {
+                               Scratch& sc, hipStream_t s) {
   if (steps <= 0 || F <= 0) return PINV_OK;
   const size_t N = p->N, M = p->M;
   const TS* d = (const TS*)data;
   TS* x = (TS*)image;
   void *b = nullptr, *rd = nullptr, *r = nullptr, *t = nullptr;
-  HIPCHK(hipMallocAsync(&r, 2 * sizeof(TS) * (size_t)F * N, s));
-  HIPCHK(hipMallocAsync(&t, 2 * sizeof(TS) * (size_t)F * N, s));
-  if (p->gram_exact) {
-    HIPCHK(hipMallocAsync(&b, 16 * (size_t)F * N, s));
-    HIPCHK((launch_adjoint<double, TS, TS, double>(p->e64, d, F, (const TS*)nullptr, 0.0, (double*)b, s)));
-  } else {
-    HIPCHK(hipMallocAsync(&rd, 16 * (size_t)F * M, s));
-  }
-  for (int it = 0; it < steps; ++it) {
+  hipError_t e = sc.get(&r, 2 * sizeof(TS) * (size_t)F * N, s);
+  if (e == hipSuccess) e = sc.get(&t, 2 * sizeof(TS) * (size_t)F * N, s);
+  if (e == hipSuccess) {
     if (p->gram_exact) {
-      HIPCHK((launch_resid<TS, TS>((const double*)p->gram, (const double*)b, x, F, p->N, p->lam,
-                                   (TS*)r, s)));
+      e = sc.get(&b, 16 * (size_t)F * N, s);
+      if (e == hipSuccess)
+        e = launch_adjoint<double, TS, TS, double>(p->e64, d, F, (const TS*)nullptr, 0.0, (double*)b,
+                                                   sc, s);
     } else {
-      HIPCHK((launch_forward<double, TS, TS>(p->e64, x, F, d, (double*)rd, s)));
-      HIPCHK((launch_adjoint<double, double, TS, TS>(p->e64, (const double*)rd, F, x, p->lam,
-                                                     (TS*)r, s)));
+      e = sc.get(&rd, 16 * (size_t)F * M, s);
     }
-    HIPCHK((launch_tri_frames<TS, 0, TS>((const TS*)p->Linv, (const TS*)r, F, p->N, (TS*)t, s)));
-    HIPCHK((launch_tri_frames<TS, 1, TS>((const TS*)p->Linv, (const TS*)t, F, p->N, x, s)));
   }
-  for (void* q : {b, rd, r, t})
-    if (q) HIPCHK(hipFreeAsync(q, s));
+  for (int it = 0; it < steps && e == hipSuccess; ++it) {
+    if (p->gram_exact) {
+      e = launch_resid<TS, TS>((const double*)p->gram, (const double*)b, x, F, p->N, p->lam, (TS*)r, s);
+    } else {
+      e = launch_forward<double, TS, TS>(p->e64, x, F, d, (double*)rd, s);
+      if (e == hipSuccess)
+        e = launch_adjoint<double, double, TS, TS>(p->e64, (const double*)rd, F, x, p->lam, (TS*)r,
+                                                   sc, s);
+    }
+    if (e == hipSuccess) e = launch_tri_frames<TS, 0, TS>((const TS*)p->Linv, (const TS*)r, F, p->N, (TS*)t, s);
+    if (e == hipSuccess) e = launch_tri_frames<TS, 1, TS>((const TS*)p->Linv, (const TS*)t, F, p->N, x, s);
+  }
+  for (void* q : {rd, b, t, r})   // most recent first (the fixed-region scratch is a stack)
+    if (q) (void)sc.put(q, s);
+  HIPCHK(e);
   return PINV_OK;
 }
 
@@ -951,19 +1088,22 @@ static pinv_status refine_item(pinv_plan* p, const void* data, int F, void* imag
 //   x = L^-H (L^-1 b)
 // b is formed in `image`, L^-1 b in a scratch array, L^-H (L^-1 b) back in `image`.
 template <typename TS>
-static pinv_status solve_item(pinv_plan* p, const void* data, int F, void* image, hipStream_t s) {
+static pinv_status solve_item(pinv_plan* p, const void* data, int F, void* image, Scratch& sc,
+                              hipStream_t s) {
   const size_t N = p->N;
   TS* x = (TS*)image;
   void* t = nullptr;
-  HIPCHK(hipMallocAsync(&t, 2 * sizeof(TS) * (size_t)F * N, s));
+  HIPCHK(sc.get(&t, 2 * sizeof(TS) * (size_t)F * N, s));
   hipError_t e;
   if constexpr (sizeof(TS) == 8)
-    e = launch_adjoint<double, double, double, double>(p->e64, (const double*)data, F, nullptr, 0.0, x, s);
+    e = launch_adjoint<double, double, double, double>(p->e64, (const double*)data, F, nullptr, 0.0,
+                                                       x, sc, s);
   else
-    e = launch_adjoint<float, float, float, float>(p->e32, (const float*)data, F, nullptr, 0.0, x, s);
+    e = launch_adjoint<float, float, float, float>(p->e32, (const float*)data, F, nullptr, 0.0, x,
+                                                   sc, s);
   if (e == hipSuccess) e = launch_tri_frames<TS, 0, TS>((const TS*)p->Linv, x, F, p->N, (TS*)t, s);
   if (e == hipSuccess) e = launch_tri_frames<TS, 2, TS>((const TS*)p->Linv, (const TS*)t, F, p->N, x, s);
-  const hipError_t f = hipFreeAsync(t, s);
+  const hipError_t f = sc.put(t, s);
   HIPCHK(e);
   HIPCHK(f);
   return PINV_OK;
@@ -977,15 +1117,15 @@ static pinv_status solve_item(pinv_plan* p, const void* data, int F, void* image
 // final product does not amplify a rounded y.
 template <typename TS>
 static pinv_status solve_right_item(pinv_plan* p, const void* data, int F, void* image, int steps,
-                                    hipStream_t s) {
+                                    Scratch& sc, hipStream_t s) {
   const size_t M = p->M;
   const TS* d = (const TS*)data;
   const TS* Li = (const TS*)p->Linv;
   void *y = nullptr, *t = nullptr, *r = nullptr, *d64 = nullptr;
-  hipError_t e = hipMallocAsync(&y, 16 * (size_t)F * M, s);
-  if (e == hipSuccess) e = hipMallocAsync(&t, 2 * sizeof(TS) * (size_t)F * M, s);
-  if (e == hipSuccess) e = hipMallocAsync(&r, 2 * sizeof(TS) * (size_t)F * M, s);
-  if (e == hipSuccess && sizeof(TS) == 4) e = hipMallocAsync(&d64, 16 * (size_t)F * M, s);
+  hipError_t e = sc.get(&y, 16 * (size_t)F * M, s);
+  if (e == hipSuccess) e = sc.get(&t, 2 * sizeof(TS) * (size_t)F * M, s);
+  if (e == hipSuccess) e = sc.get(&r, 2 * sizeof(TS) * (size_t)F * M, s);
+  if (e == hipSuccess && sizeof(TS) == 4) e = sc.get(&d64, 16 * (size_t)F * M, s);
   if (e == hipSuccess) e = launch_tri_frames<TS, 0, TS>(Li, d, F, p->M, (TS*)t, s);
   if (e == hipSuccess) e = launch_tri_frames<TS, 2, double>(Li, (const TS*)t, F, p->M, (double*)y, s);
   const double* b = nullptr;
@@ -1003,20 +1143,58 @@ static pinv_status solve_right_item(pinv_plan* p, const void* data, int F, void*
       e = launch_tri_frames<TS, 1, double>(Li, (const TS*)t, F, p->M, (double*)y, s);
   }
   if (e == hipSuccess)
-    e = launch_adjoint<double, double, TS, TS>(p->e64, (const double*)y, F, nullptr, 0.0, (TS*)image, s);
-  for (void* q : {y, t, r, d64})
-    if (q) (void)hipFreeAsync(q, s);
+    e = launch_adjoint<double, double, TS, TS>(p->e64, (const double*)y, F, nullptr, 0.0,
+                                               (TS*)image, sc, s);
+  for (void* q : {d64, r, t, y})
+    if (q) (void)sc.put(q, s);
   HIPCHK(e);
   return PINV_OK;
 }
+
+// Scratch bytes one item's apply takes from a fixed region (the stack peak of
+// the steps apply_items runs for it).
+static size_t item_scratch_bytes(const pinv_plan* p, int F, int steps) {
+  if (F <= 0) return 0;
+  auto al = [](size_t n) { return (n + 255) & ~size_t(255); };
+  const size_t N = p->N, M = p->M;
+  const size_t ts = p->prec == PINV_FP64 ? 8 : 4;
+  size_t peak = 0;
+  const bool tiles = F > kRowApplyMaxF && !p->no_r && !(p->right && steps > 0);
+  if (tiles) {
+    peak = p->prec == PINV_FP64     ? apply_scratch_bytes<double>(F, (int)N, (int)M, p->m3)
+           : p->prec == PINV_BF16X3 ? apply_scratch_bytes_b3(F, (int)N, (int)M)
+                                    : apply_scratch_bytes<float>(F, (int)N, (int)M, p->m3);
+  }
+  if (p->no_r) {
+    const size_t adj = p->prec == PINV_FP64
+                           ? adjoint_scratch_bytes<double, double, double, double>(p->e64, F)
+                           : adjoint_scratch_bytes<float, float, float, float>(p->e32, F);
+    peak = std::max(peak, al(2 * ts * F * N) + adj);
+  }
+  if (steps > 0 && p->right) {
+    const size_t adj = p->prec == PINV_FP64
+                           ? adjoint_scratch_bytes<double, double, double, double>(p->e64, F)
+                           : adjoint_scratch_bytes<double, double, float, float>(p->e64, F);
+    peak = std::max(peak, al(16 * F * M) + 2 * al(2 * ts * F * M) + (ts == 4 ? al(16 * F * M) : 0) + adj);
+  } else if (steps > 0) {
+    size_t refine = 2 * al(2 * ts * F * N);
+    if (p->gram_exact)
+      refine += al(16 * F * N) + (p->prec == PINV_FP64
+                                      ? adjoint_scratch_bytes<double, double, double, double>(p->e64, F)
+                                      : adjoint_scratch_bytes<double, float, float, double>(p->e64, F));
+    else
+      refine += al(16 * F * M) + (p->prec == PINV_FP64
+                                      ? adjoint_scratch_bytes<double, double, double, double>(p->e64, F)
+                                      : adjoint_scratch_bytes<double, double, float, float>(p->e64, F));
+    peak = std::max(peak, refine);
+  }
+  return peak;
+}
 }  // extern "C++"
 
-pinv_status pinv_apply_grouped(pinv_context* c, int32_t n, const pinv_apply_item* items,
-                               int32_t refine_steps, void* stream) {
-  if (!c || (n > 0 && !items) || n < 0) return fail(PINV_ERR_INVALID, "bad arguments");
-  if (refine_steps < 0 || refine_steps > 4) return fail(PINV_ERR_INVALID, "refine_steps in 0..4");
-  hipStream_t s = (hipStream_t)stream;
-  HIPCHK(hipSetDevice(c->device));
+// The apply pipeline of pinv_apply_grouped with its scratch from `sc`.
+static pinv_status apply_items(pinv_context* c, int32_t n, const pinv_apply_item* items,
+                               int32_t refine_steps, Scratch& sc, hipStream_t s) {
   for (int i = 0; i < n; ++i) {
     const pinv_plan* p = (const pinv_plan*)items[i].plan;
     if (!p || p->ctx != c) return fail(PINV_ERR_INVALID, "item " + std::to_string(i) + ": bad plan");
@@ -1024,16 +1202,19 @@ pinv_status pinv_apply_grouped(pinv_context* c, int32_t n, const pinv_apply_item
       return fail(PINV_ERR_INVALID, "item " + std::to_string(i) + ": F out of range");
     if (items[i].F > 0 && (!items[i].data || !items[i].image))
       return fail(PINV_ERR_INVALID, "item " + std::to_string(i) + ": NULL buffer");
-    HIPCHK(hipStreamWaitEvent(s, p->ev[4], 0));
   }
-  // grouped launches over runs of equal precision, up to kMaxGroup items each
+  for (int i = 0; i < n; ++i) HIPCHK(hipStreamWaitEvent(s, ((const pinv_plan*)items[i].plan)->ev[4], 0));
+  // grouped launches over runs of equal precision and product form, up to
+  // kMaxGroup items each
   int i = 0;
   while (i < n) {
-    const int prec = ((const pinv_plan*)items[i].plan)->prec;
+    const pinv_plan* p0 = (const pinv_plan*)items[i].plan;
+    const int prec = p0->prec;
+    const bool m3 = p0->m3;
     ApplyBatch b;
     b.n = 0;
-    int tiles = 0;
-    while (i < n && b.n < kMaxGroup && ((const pinv_plan*)items[i].plan)->prec == prec) {
+    while (i < n && b.n < kMaxGroup && ((const pinv_plan*)items[i].plan)->prec == prec &&
+           ((const pinv_plan*)items[i].plan)->m3 == m3) {
       const pinv_plan* p = (const pinv_plan*)items[i].plan;
       if (items[i].F > kRowApplyMaxF && !p->no_r && !(p->right && refine_steps > 0)) {
         ApplyItemDev& it = b.it[b.n++];
@@ -1043,20 +1224,16 @@ pinv_status pinv_apply_grouped(pinv_context* c, int32_t n, const pinv_apply_item
         it.F = (int)items[i].F;
         it.N = p->N;
         it.M = p->M;
-        it.tile0 = tiles;
-        tiles += prec == PINV_FP64     ? apply_tiles<double>(it.F, it.N)
-                 : prec == PINV_BF16X3 ? apply_tiles_b3(it.F, it.N)
-                                       : apply_tiles<float>(it.F, it.N);
       }
       ++i;
     }
     if (b.n == 0) continue;
     if (prec == PINV_FP64)
-      HIPCHK(launch_apply<double>(b, tiles, s));
+      HIPCHK(launch_apply<double>(b, m3, sc, s));
     else if (prec == PINV_BF16X3)
-      HIPCHK(launch_apply_b3(b, tiles, s));
+      HIPCHK(launch_apply_b3(b, sc, s));
     else
-      HIPCHK(launch_apply<float>(b, tiles, s));
+      HIPCHK(launch_apply<float>(b, m3, sc, s));
   }
   // a few frames: stream R row by row (bound by HBM bandwidth, not MFMA)
   for (int j = 0; j < n; ++j) {
@@ -1074,31 +1251,43 @@ pinv_status pinv_apply_grouped(pinv_context* c, int32_t n, const pinv_apply_item
     pinv_plan* p = (pinv_plan*)items[j].plan;
     if (!p->no_r || items[j].F <= 0) continue;
     const pinv_status st =
-        p->prec == PINV_FP64 ? solve_item<double>(p, items[j].data, (int)items[j].F, items[j].image, s)
-                             : solve_item<float>(p, items[j].data, (int)items[j].F, items[j].image, s);
+        p->prec == PINV_FP64
+            ? solve_item<double>(p, items[j].data, (int)items[j].F, items[j].image, sc, s)
+            : solve_item<float>(p, items[j].data, (int)items[j].F, items[j].image, sc, s);
     if (st != PINV_OK) return st;
   }
   if (refine_steps > 0) {
     for (int j = 0; j < n; ++j) {
       pinv_plan* p = (pinv_plan*)items[j].plan;
-      if (p->right) {
-        if (items[j].F <= 0) continue;
-        const pinv_status st =
-            p->prec == PINV_FP64
-                ? solve_right_item<double>(p, items[j].data, (int)items[j].F, items[j].image,
-                                           refine_steps, s)
-                : solve_right_item<float>(p, items[j].data, (int)items[j].F, items[j].image,
-                                          refine_steps, s);
-        if (st != PINV_OK) return st;
-        continue;
-      }
-      pinv_status st =
-          p->prec == PINV_FP64
-              ? refine_item<double>(p, items[j].data, (int)items[j].F, items[j].image, refine_steps, s)
-              : refine_item<float>(p, items[j].data, (int)items[j].F, items[j].image, refine_steps, s);
+      if (items[j].F <= 0) continue;
+      pinv_status st;
+      if (p->right)
+        st = p->prec == PINV_FP64
+                 ? solve_right_item<double>(p, items[j].data, (int)items[j].F, items[j].image,
+                                            refine_steps, sc, s)
+                 : solve_right_item<float>(p, items[j].data, (int)items[j].F, items[j].image,
+                                           refine_steps, sc, s);
+      else
+        st = p->prec == PINV_FP64
+                 ? refine_item<double>(p, items[j].data, (int)items[j].F, items[j].image, refine_steps,
+                                       sc, s)
+                 : refine_item<float>(p, items[j].data, (int)items[j].F, items[j].image, refine_steps,
+                                      sc, s);
       if (st != PINV_OK) return st;
     }
   }
+  return PINV_OK;
+}
+
+pinv_status pinv_apply_grouped(pinv_context* c, int32_t n, const pinv_apply_item* items,
+                               int32_t refine_steps, void* stream) {
+  if (!c || (n > 0 && !items) || n < 0) return fail(PINV_ERR_INVALID, "bad arguments");
+  if (refine_steps < 0 || refine_steps > 4) return fail(PINV_ERR_INVALID, "refine_steps in 0..4");
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(c->device));
+  Scratch sc;   // stream-ordered allocations from the default pool
+  const pinv_status st = apply_items(c, n, items, refine_steps, sc, s);
+  if (st != PINV_OK) return st;
   for (int j = 0; j < n; ++j)
     if (items[j].F > 0) HIPCHK(note_use((const pinv_plan*)items[j].plan, s));
   return PINV_OK;
@@ -1270,6 +1459,11 @@ pinv_status pinv_plan_info_get(const pinv_plan* p, pinv_plan_info* out) {
   for (int i = 0; i < 4; ++i) out->stage_ms[i] = p->waited ? p->stage_ms[i] : 0.f;
   out->has_r = p->no_r ? 0 : 1;
   out->gram_order = p->G;
+  out->ncoil = p->C;
+  out->cprod = p->m3 ? PINV_CPROD_3M : PINV_CPROD_4M;
+  out->nk = p->K;
+  out->gram_form = p->gram_form;
+  out->r_fp64 = p->r_fp64 ? 1 : 0;
   return PINV_OK;
 }
 

@@ -1,0 +1,320 @@
+// Apply image = R data for every frame (Eq. 3), grouped over plans, and the
+// row-streaming apply for a few frames.
+#include <type_traits>
+
+#include "pinv_internal.h"
+
+namespace pinv {
+
+// ---------------------------------------------------------------------------
+// Apply (grouped): for each item, X[f][n] = sum_m D[f][m] R[n][m]
+// ---------------------------------------------------------------------------
+// An item whose tile grid alone would leave the GPU partly idle is split over
+// M (the split depends only on the item's F, N and M, so a result is the same
+// alone and in any group); its splits write partial tiles to item.work and
+// k_apply_reduce adds them in split order.
+template <class Cfg>
+__global__ __launch_bounds__(256) void k_apply(const ApplyBatch batch) {
+  typedef typename Cfg::T T;
+  // locate the item owning this tile (items carry exclusive tile prefix sums)
+  int lo = 0, hi = batch.n - 1;
+  const int t = blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (batch.it[mid].tile0 <= t) lo = mid; else hi = mid - 1;
+  }
+  const ApplyItemDev it = batch.it[lo];
+  const int u0 = t - it.tile0;
+  const int split = u0 / it.ntile;
+  const int u = u0 - split * it.ntile;
+  const int nbj = (it.N + Cfg::BN - 1) / Cfg::BN;
+  const int bi = u / nbj, bj = u % nbj;
+  const int k0 = split * it.kchunk, k1 = min(it.M, k0 + it.kchunk);
+  LoadDenseKC<Cfg, Cfg::BM, Cfg::LDA, T, false> la;   // D[f][m]
+  la.p = reinterpret_cast<const cx<T>*>(it.D);
+  la.ld = it.M;
+  la.o0 = bi * Cfg::BM;
+  la.oend = it.F;
+  LoadDenseKC<Cfg, Cfg::BN, Cfg::LDB, T, false> lb;   // R[n][m]
+  lb.p = reinterpret_cast<const cx<T>*>(it.R);
+  lb.ld = it.M;
+  lb.o0 = bj * Cfg::BN;
+  lb.oend = it.N;
+  AccTile<Cfg> acc;
+  acc.zero();
+  mainloop<Cfg>(la, lb, k0, k1, acc, smem_base<Cfg>());
+  cx<T>* O = it.splits > 1
+                 ? reinterpret_cast<cx<T>*>(it.work) + (size_t)split * it.F * it.N
+                 : reinterpret_cast<cx<T>*>(it.X);
+  const int r0 = bi * Cfg::BM, c0 = bj * Cfg::BN;
+  acc_foreach<Cfg>(acc, [&](int r, int c, T re, T im) {
+    const int row = r0 + r, col = c0 + c;
+    if (row < it.F && col < it.N) O[(size_t)row * it.N + col] = cx<T>{re, im};
+  });
+}
+
+// X = sum_s work[s] in split order, for the split items of a grouped apply
+// (blockIdx.y = item).
+template <typename T>
+__global__ __launch_bounds__(256) void k_apply_reduce(const ApplyBatch batch) {
+  const ApplyItemDev& it = batch.it[blockIdx.y];
+  if (it.splits <= 1) return;
+  const int64_t n = (int64_t)it.F * it.N;
+  const cx<T>* W = reinterpret_cast<const cx<T>*>(it.work);
+  cx<T>* X = reinterpret_cast<cx<T>*>(it.X);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    T zr = W[i].re, zi = W[i].im;
+    for (int s = 1; s < it.splits; ++s) {
+      zr += W[(int64_t)s * n + i].re;
+      zi += W[(int64_t)s * n + i].im;
+    }
+    X[i] = cx<T>{zr, zi};
+  }
+}
+
+
+// streaming RW rows of R.  At small F each element of R feeds only F
+// multiply-adds, so the apply is bound by memory bandwidth, not by MFMA: rows
+// stream through wide coalesced loads (two complex64 per lane and load when
+// VEC = 2), and each data element loaded serves RW rows, which keeps the
+// data's cache traffic (F / RW times that of R) below R's own.  Every wave
+// reduces its lane partial sums in a fixed butterfly order, so a result
+// depends only on its own row and frame.
+template <typename T, int FM, int RW, int VEC>
+__global__ __launch_bounds__(256) void k_apply_rows(const T* __restrict__ R, const T* __restrict__ D,
+                                                    T* __restrict__ X, int N, int M, int F) {
+  const int lane = threadIdx.x & 63;
+  const int n0 = (blockIdx.x * 4 + (int)(threadIdx.x >> 6)) * RW;
+  if (n0 >= N) return;   // the whole wavefront leaves; no barrier follows
+  const cx<T>* r[RW];
+#pragma unroll
+  for (int j = 0; j < RW; ++j)   // rows past N re-read row N-1 and are not written
+    r[j] = reinterpret_cast<const cx<T>*>(R) + (size_t)min(n0 + j, N - 1) * M;
+  const cx<T>* d = reinterpret_cast<const cx<T>*>(D);
+  T ar[RW][FM], ai[RW][FM];
+#pragma unroll
+  for (int j = 0; j < RW; ++j)
+#pragma unroll
+    for (int f = 0; f < FM; ++f) ar[j][f] = ai[j][f] = T(0);
+  for (int m0 = lane * VEC; m0 < M; m0 += 64 * VEC) {
+    cx<T> rv[RW][VEC];
+#pragma unroll
+    for (int j = 0; j < RW; ++j) {
+      if constexpr (VEC == 2) {
+        // M even and 16-byte aligned rows (checked by the launcher): m0 + 1 < M
+        const float4 q = *reinterpret_cast<const float4*>(r[j] + m0);
+        rv[j][0] = cx<T>{q.x, q.y};
+        rv[j][1] = cx<T>{q.z, q.w};
+      } else {
+        rv[j][0] = r[j][m0];
+      }
+    }
+#pragma unroll
+    for (int f = 0; f < FM; ++f) {
+      if (f >= F) break;
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        const cx<T> dv = d[(size_t)f * M + m0 + v];
+#pragma unroll
+        for (int j = 0; j < RW; ++j) {
+          ar[j][f] += dv.re * rv[j][v].re - dv.im * rv[j][v].im;
+          ai[j][f] += dv.re * rv[j][v].im + dv.im * rv[j][v].re;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < RW; ++j)
+#pragma unroll
+    for (int f = 0; f < FM; ++f) {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        ar[j][f] += __shfl_xor(ar[j][f], off);
+        ai[j][f] += __shfl_xor(ai[j][f], off);
+      }
+    }
+  if (lane == 0) {
+    cx<T>* x = reinterpret_cast<cx<T>*>(X);
+#pragma unroll
+    for (int j = 0; j < RW; ++j)
+#pragma unroll
+      for (int f = 0; f < FM; ++f)
+        if (f < F && n0 + j < N) x[(size_t)f * N + n0 + j] = cx<T>{ar[j][f], ai[j][f]};
+  }
+}
+
+
+// host launchers
+// The apply uses the same 128x64 3M tiles as the triangular products: with
+// the raised wave priority over the matrix products, their occupancy of two
+// workgroups per CU beats 128x128 at one (7.76 against 8.04 ms at 1000
+// frames, N = 4096, M = 32768; without the priority raise 128x128 had been
+// ahead, 8.1 against 8.3 ms).
+// Tile shapes by element type and complex-product form.  FP32 applies of at
+// most 32 frames run on 32x128 tiles: a 128-frame tile would spend most of
+// its matrix products on padding rows.
+template <typename T, bool M3> struct ApplyCfgOf;
+template <> struct ApplyCfgOf<float, true> { typedef F32Cfg many; typedef TileCfg<float, 32, 128, 8, true> few; };
+template <> struct ApplyCfgOf<float, false> { typedef F32Cfg4 many; typedef TileCfg<float, 32, 128, 8, false> few; };
+template <> struct ApplyCfgOf<double, true> { typedef F64Cfg3 many; typedef F64Cfg3 few; };
+template <> struct ApplyCfgOf<double, false> { typedef F64Cfg many; typedef F64Cfg few; };
+constexpr int kFewFramesMaxF = 32;
+// A grouped apply of few frames has few tiles, so its contraction may be split
+// up to 16 ways (the other split launches stop at 4).
+constexpr int kApplyMaxSplit = 16;
+
+// An item's tiles, contraction split and split length: a function of its own
+// F, N and M (and the tile kernel's occupancy) only, so a result is the same
+// alone and in any group.
+template <class Cfg> static void plan_item(ApplyItemDev& it, int slots) {
+  const int nchunks = cdiv(it.M, Cfg::BK);
+  it.ntile = cdiv(it.F, Cfg::BM) * cdiv(it.N, Cfg::BN);
+  it.splits = pick_split(it.ntile, slots, nchunks, kApplyMaxSplit);
+  it.kchunk = cdiv(nchunks, it.splits) * Cfg::BK;
+}
+
+template <class Cfg> static int apply_slots() {
+  static const hipError_t attr = allow_smem(k_apply<Cfg>, smem_bytes<Cfg>());
+  (void)attr;
+  return resident_blocks(k_apply<Cfg>, 256, smem_bytes<Cfg>());
+}
+
+template <class Cfg> static size_t item_work_bytes(int F, int N, int M) {
+  ApplyItemDev it{};
+  it.F = F;
+  it.N = N;
+  it.M = M;
+  plan_item<Cfg>(it, apply_slots<Cfg>());
+  return it.splits > 1 ? (size_t)it.splits * F * N * 2 * sizeof(typename Cfg::T) : 0;
+}
+
+// Grouped apply with per-item contraction splits: sets each item's split,
+// tile range and partial-sum workspace, runs the tiles, then the reduction.
+template <class Cfg>
+static hipError_t run_apply(ApplyBatch b, Scratch& sc, hipStream_t s) {
+  typedef typename Cfg::T T;
+  const int slots = apply_slots<Cfg>();
+  int tiles = 0, nsplit = 0;
+  size_t work_elems = 0;
+  for (int i = 0; i < b.n; ++i) {
+    ApplyItemDev& it = b.it[i];
+    plan_item<Cfg>(it, slots);
+    it.tile0 = tiles;
+    it.work = nullptr;
+    tiles += it.ntile * it.splits;
+    if (it.splits > 1) {
+      work_elems += (size_t)it.splits * it.F * it.N;
+      ++nsplit;
+    }
+  }
+  if (tiles <= 0) return hipSuccess;
+  void* work = nullptr;
+  if (nsplit) {
+    hipError_t err = sc.get(&work, work_elems * 2 * sizeof(T), s);
+    if (err != hipSuccess) return err;
+    size_t off = 0;
+    for (int i = 0; i < b.n; ++i)
+      if (b.it[i].splits > 1) {
+        b.it[i].work = (cx<T>*)work + off;
+        off += (size_t)b.it[i].splits * b.it[i].F * b.it[i].N;
+      }
+  }
+  hipLaunchKernelGGL(k_apply<Cfg>, dim3(tiles), dim3(256), smem_bytes<Cfg>(), s, b);
+  hipError_t err = hipGetLastError();
+  if (nsplit) {
+    if (err == hipSuccess) {
+      hipLaunchKernelGGL(k_apply_reduce<T>, dim3(1024, b.n), dim3(256), 0, s, b);
+      err = hipGetLastError();
+    }
+    const hipError_t ferr = sc.put(work, s);
+    if (err == hipSuccess) err = ferr;
+  }
+  return err;
+}
+
+template <typename T, bool M3>
+static hipError_t apply_form(const ApplyBatch& b, Scratch& sc, hipStream_t s) {
+  typedef ApplyCfgOf<T, M3> C;
+  if constexpr (std::is_same<T, float>::value) {
+    // items go to the tile shape their own frame count selects, so an item's
+    // result does not depend on the other items of the group
+    ApplyBatch few, many;
+    few.n = many.n = 0;
+    for (int i = 0; i < b.n; ++i) {
+      if (b.it[i].F <= kFewFramesMaxF)
+        few.it[few.n++] = b.it[i];
+      else
+        many.it[many.n++] = b.it[i];
+    }
+    if (few.n) {
+      const hipError_t err = run_apply<typename C::few>(few, sc, s);
+      if (err != hipSuccess) return err;
+    }
+    return many.n ? run_apply<typename C::many>(many, sc, s) : hipSuccess;
+  } else {
+    return run_apply<typename C::many>(b, sc, s);
+  }
+}
+
+template <typename T>
+hipError_t launch_apply(const ApplyBatch& b, bool m3, Scratch& sc, hipStream_t s) {
+  return m3 ? apply_form<T, true>(b, sc, s) : apply_form<T, false>(b, sc, s);
+}
+
+template <typename T>
+size_t apply_scratch_bytes(int F, int N, int M, bool m3) {
+  auto go = [&](auto form) -> size_t {
+    typedef ApplyCfgOf<T, decltype(form)::value> C;
+    if (std::is_same<T, float>::value && F <= kFewFramesMaxF)
+      return item_work_bytes<typename C::few>(F, N, M);
+    return item_work_bytes<typename C::many>(F, N, M);
+  };
+  return m3 ? go(std::true_type{}) : go(std::false_type{});
+}
+
+template <typename T>
+hipError_t launch_apply_rows(const T* R, const T* D, T* X, int N, int M, int F, hipStream_t s) {
+  if (F <= 0 || N <= 0) return hipSuccess;
+  if (F > kRowApplyMaxF) return hipErrorInvalidValue;
+  const bool vec = M % 2 == 0 && ((uintptr_t)R % 16) == 0 && ((uintptr_t)D % 16) == 0;
+  auto go = [&](auto fm, auto rw) {
+    constexpr int FM = decltype(fm)::value, RW = decltype(rw)::value;
+    const dim3 grid(cdiv(N, 4 * RW)), block(256);
+    if constexpr (sizeof(T) == 4) {
+      if (vec) {
+        hipLaunchKernelGGL((k_apply_rows<T, FM, RW, 2>), grid, block, 0, s, R, D, X, N, M, F);
+        return hipGetLastError();
+      }
+    }
+    hipLaunchKernelGGL((k_apply_rows<T, FM, RW, 1>), grid, block, 0, s, R, D, X, N, M, F);
+    return hipGetLastError();
+  };
+  // rows per wave: as many as keep the accumulators (2 FM RW values) within
+  // 64 registers
+  using std::integral_constant;
+  constexpr int W = sizeof(T) == 4 ? 4 : 2;
+  if (F <= 1) return go(integral_constant<int, 1>(), integral_constant<int, 1>());
+  if (F <= 2) return go(integral_constant<int, 2>(), integral_constant<int, W>());
+  if (F <= 4) return go(integral_constant<int, 4>(), integral_constant<int, W>());
+  return go(integral_constant<int, 8>(), integral_constant<int, W / 2 * 2 == 4 ? 4 : 2>());
+}
+
+
+hipError_t launch_apply_b3(const ApplyBatch& b, Scratch& sc, hipStream_t s) {
+  return run_apply<B3Cfg>(b, sc, s);
+}
+
+size_t apply_scratch_bytes_b3(int F, int N, int M) { return item_work_bytes<B3Cfg>(F, N, M); }
+
+// explicit instantiations
+template hipError_t launch_apply<float>(const ApplyBatch&, bool, Scratch&, hipStream_t);
+template hipError_t launch_apply<double>(const ApplyBatch&, bool, Scratch&, hipStream_t);
+template size_t apply_scratch_bytes<float>(int, int, int, bool);
+template size_t apply_scratch_bytes<double>(int, int, int, bool);
+template hipError_t launch_apply_rows<float>(const float*, const float*, float*, int, int, int,
+                                             hipStream_t);
+template hipError_t launch_apply_rows<double>(const double*, const double*, double*, int, int, int,
+                                              hipStream_t);
+
+}  // namespace pinv

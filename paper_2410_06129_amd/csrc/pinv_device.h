@@ -51,12 +51,27 @@ template <typename T> struct EncDev {
   const T* px;    // [K][nx] complex
   const T* py;    // [K][ny] complex
   const T* q;     // [K][S] complex, or null when S == 1 and f_0 == 0
-  const T* coil;  // [C][V] complex, or null for one unit coil
-  const T* b0;    // [V] Hz, or null
+  const T* coil;  // [C][V] complex (unknown voxels only), or null for one unit coil
+  const T* b0;    // [V] Hz (unknown voxels only), or null
   const T* t;     // [K] s, or null
+  const int* vxy; // [V] grid position (iy << 16) | ix of unknown voxel v when a voxel
+                  // mask restricts the unknowns; null when v = iy*nx + ix covers the grid
   int nx, ny, S, C, K, V;
   int M, N;       // M = C*K rows, N = S*V columns
 };
+
+// Grid position of unknown voxel v.
+template <typename T>
+__device__ __forceinline__ void voxel_xy(const EncDev<T>& e, int v, int* ix, int* iy) {
+  if (e.vxy) {
+    const int p = e.vxy[v];
+    *iy = p >> 16;
+    *ix = p & 0xffff;
+  } else {
+    *iy = v / e.nx;
+    *ix = v - *iy * e.nx;
+  }
+}
 
 // Which optional factors an encoding has; generated-operand kernels are
 // specialised on this so that absent factors cost neither loads nor registers.
@@ -616,8 +631,7 @@ struct LoadGenCol {
     const int nn = valid ? n : 0;
     s = nn / e.V;
     v = nn - s * e.V;
-    iy = v / e.nx;
-    ix = v - iy * e.nx;
+    voxel_xy(e, v, &ix, &iy);
     if constexpr (ALIGNED && (FEAT & FEAT_B0) != 0) b0v = e.b0[v];
   }
   __device__ __forceinline__ void fetch(int k0, int kend) {
@@ -693,10 +707,10 @@ struct LoadGenCol {
 
 // Generated operand, outer index = row m of E, k = column n of E:
 // element (o, k) = E[o, k] (or its conjugate).  Each thread keeps one row.
-// ALIGNED (nx a multiple of BK, chunks starting at multiples of BK): every
-// column of a chunk lies in one image row of one species, so Py, Q and the
-// sample's time are loaded once per chunk or per tile, and Px and the coil map
-// advance by a constant stride.
+// ALIGNED (nx a multiple of BK, no voxel mask, chunks starting at multiples of
+// BK): every column of a chunk lies in one image row of one species, so Py, Q
+// and the sample's time are loaded once per chunk or per tile, and Px and the
+// coil map advance by a constant stride.
 template <class Cfg, int OUTER, int LD, bool CONJ, int FEAT, bool ALIGNED = false>
 struct LoadGenRow {
   typedef typename Cfg::T T;
@@ -745,6 +759,20 @@ struct LoadGenRow {
       return;
     }
     int n = k0 + threadIdx.x / OUTER;
+    if (e.vxy) {   // voxel mask: each column's grid position from the voxel table
+#pragma unroll
+      for (int j = 0; j < PASSES; ++j) {
+        const int nj = n + j * KPP;
+        ok[j] = valid && nj < kend;
+        const int nn = nj < e.N ? nj : 0;
+        const int s = nn / e.V;
+        const int v = nn - s * e.V;
+        int ix, iy;
+        voxel_xy(e, v, &ix, &iy);
+        gen_load<FEAT>(e, i, s, v, ix, iy, c, raw[j]);
+      }
+      return;
+    }
     const int nn = n < e.N ? n : 0;
     int s = nn / e.V;
     const int v0 = nn - s * e.V;

@@ -32,20 +32,57 @@ struct ApplyBatch {     // passed by value as a kernel argument
   ApplyItemDev it[kMaxGroup];
 };
 
+// Scratch memory of one call (split-contraction partials, refinement
+// vectors).  By default each request is a stream-ordered allocation from the
+// device's default pool, returned by put().  Over a fixed region (the
+// no-allocation entry point) it is a stack: get() hands out the next
+// 256-aligned block, put() of the most recent block pops it (the stream runs
+// the work in order, so a popped block is free for the next request), and a
+// request beyond the region fails with hipErrorOutOfMemory.  `peak` records
+// the most the stack ever held.
+struct Scratch {
+  char* base = nullptr;
+  size_t cap = 0, top = 0, peak = 0;
+  struct Block { void* p; size_t start; };
+  Block stack[16];
+  int depth = 0;
+  hipError_t get(void** p, size_t bytes, hipStream_t s) {
+    if (!base) return hipMallocAsync(p, bytes, s);
+    const size_t start = (top + 255) & ~size_t(255);
+    if (depth >= 16 || start + bytes > cap) return hipErrorOutOfMemory;
+    *p = base + start;
+    stack[depth++] = Block{*p, top};
+    top = start + bytes;
+    peak = std::max(peak, top);
+    return hipSuccess;
+  }
+  hipError_t put(void* p, hipStream_t s) {
+    if (!base) return hipFreeAsync(p, s);
+    if (depth > 0 && stack[depth - 1].p == p) top = stack[--depth].start;
+    return hipSuccess;
+  }
+};
+
 template <typename T> hipError_t launch_gram(const EncDev<T>& e, double* G, int flush, hipStream_t s);
 template <typename T> hipError_t launch_gram_shared(const EncDev<T>& e, double* G, hipStream_t s);
 hipError_t launch_cholinv(double* A, double* Li, int N, double lam, int* info, hipStream_t s,
                           hipStream_t aux);
-template <typename T> hipError_t launch_trmm_w(const EncDev<T>& e, const T* Li, T* W, hipStream_t s);
+// Triangular products forming R; m3 selects three real products per complex
+// product (else four).  R may be stored in a narrower type TO than T.
 template <typename T>
-hipError_t launch_trmm_r(const T* Li, const T* W, T* R, int N, int M, hipStream_t s);
-template <typename T> int apply_tiles(int F, int N);
-template <typename T> hipError_t launch_apply(const ApplyBatch& b, int total_tiles, hipStream_t s);
+hipError_t launch_trmm_w(const EncDev<T>& e, const T* Li, T* W, bool m3, hipStream_t s);
+template <typename T, typename TO>
+hipError_t launch_trmm_r(const T* Li, const T* W, TO* R, int N, int M, bool m3, hipStream_t s);
+template <typename T>
+hipError_t launch_apply(const ApplyBatch& b, bool m3, Scratch& sc, hipStream_t s);
+// Scratch bytes launch_apply needs for one item of F frames (split partials).
+template <typename T> size_t apply_scratch_bytes(int F, int N, int M, bool m3);
 // Fewer samples than unknowns: the samples' Gram E E^H (FP64, M x M), and
 // R = (L'^-H L'^-1 E)^H from the inverse factor L'^-1 (W, Z: M x N workspaces).
 hipError_t launch_gram_rows(const EncDev<double>& e, double* G, hipStream_t s);
-template <typename T>
-hipError_t launch_right_pinv(const EncDev<T>& e, const T* Li, T* W, T* Z, T* R, hipStream_t s);
+template <typename T, typename TO>
+hipError_t launch_right_pinv(const EncDev<T>& e, const T* Li, T* W, T* Z, TO* R, bool m3,
+                             hipStream_t s);
 // Applies of at most kRowApplyMaxF frames stream R row by row (HBM-bound);
 // measured at N = 4096, M = 32768: 0.20 / 0.31 / 0.44 ms for 1 / 4 / 8 frames,
 // 1.5 ms at 12, where the MFMA tiles take 1.23 ms for any F up to 128.
@@ -57,17 +94,25 @@ hipError_t launch_forward(const EncDev<T>& e, const SX* X, int F, const SD* Din,
                           hipStream_t s);
 template <typename T, typename SD, typename SX, typename SO>
 hipError_t launch_adjoint(const EncDev<T>& e, const SD* D, int F, const SX* X, double lam, SO* Z,
-                          hipStream_t s);
+                          Scratch& sc, hipStream_t s);
+// Scratch bytes of launch_adjoint<T, ...> for F frames (split partials).
+template <typename T, typename SD, typename SX, typename SO>
+size_t adjoint_scratch_bytes(const EncDev<T>& e, int F);
 template <typename SX, typename SO>
 hipError_t launch_resid(const double* G, const double* b, const SX* X, int F, int N, double lam,
                         SO* Out, hipStream_t s);
 hipError_t launch_herm_fill(double* G, int N, hipStream_t s);
+// Gram through the point-spread function (no off-resonance map): G and Gk
+// (both full N x N FP64) from the FP64 tables; `work` holds psf_work_bytes.
+size_t psf_work_bytes(const EncDev<double>& e, int* splits);
+hipError_t launch_psf_gram(const EncDev<double>& e, void* work, double* G, double* Gk,
+                           hipStream_t s);
 template <typename T, int MODE, typename SO>
 hipError_t launch_tri_frames(const T* Li, const T* In, int F, int N, SO* Out, hipStream_t s);
 hipError_t launch_trmm_w_b3(const EncDev<float>& e, const float* Li, float* W, hipStream_t s);
 hipError_t launch_trmm_r_b3(const float* Li, const float* W, float* R, int N, int M, hipStream_t s);
-int apply_tiles_b3(int F, int N);
-hipError_t launch_apply_b3(const ApplyBatch& b, int total_tiles, hipStream_t s);
+hipError_t launch_apply_b3(const ApplyBatch& b, Scratch& sc, hipStream_t s);
+size_t apply_scratch_bytes_b3(int F, int N, int M);
 hipError_t launch_to_f32(const double* in, float* out, size_t n_complex, hipStream_t s);
 hipError_t launch_to_f64(const float* in, double* out, size_t n_complex, hipStream_t s);
 template <typename T> hipError_t launch_srf_diag(const EncDev<T>& e, const T* R, T* out, hipStream_t s);
@@ -96,9 +141,20 @@ __device__ __forceinline__ void tri_index(int t, int* bi, int* bj) {
   *bj = t - i * (i + 1) / 2;
 }
 
+// Workgroups per CU that a kernel's register budget is sized for: three for
+// FP64 3M tiles whose generated operand carries no species or off-resonance
+// factor (the refinement's FP64 products then fit 168 registers and their LDS
+// fits three times), two otherwise (the Gram's accumulators and the extra
+// factors spill at 168).
+template <class Cfg, int FEAT = 0> struct MinBlocks {
+  static constexpr int value =
+      (sizeof(typename Cfg::T) == 8 && IsM3<Cfg>::value && (FEAT & ~FEAT_COIL) == 0) ? 3 : 2;
+};
+
 // FP32 tiles: 3M complex products on 128x64 tiles (a 64x32 tile per wave keeps
 // the three accumulator sets at 96 registers, so two workgroups fit per CU)
 typedef TileCfg<float, 128, 64, 8, true> F32Cfg;
+typedef TileCfg<float, 128, 64, 8, false> F32Cfg4;   // the same tiles with four real products
 typedef TileCfg<double, 64, 64, 8> F64Cfg;
 // FP64 tiles with 3M products, for the FP64 work of FP32-class plans (Gram,
 // refinement residuals), where 3M's rounding (a few units of 2^-53 more in the
@@ -125,6 +181,13 @@ template <> struct PickCfg<float> { typedef F32Cfg type; };
 template <> struct PickCfg<double> { typedef F64Cfg type; };
 
 static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+// The row-generated loaders' aligned chunk path (LoadGenRow): every BK
+// consecutive columns lie in one image row, which needs nx % BK == 0 and no
+// voxel mask.
+template <typename T> static inline bool row_aligned(const EncDev<T>& e, int bk) {
+  return e.nx % bk == 0 && e.vxy == nullptr;
+}
 
 // Calls f(std::integral_constant<int, FEAT>) for the runtime feature mask.
 template <class F> static hipError_t with_feat(int feat, F&& f) {

@@ -1,4 +1,4 @@
-// Image-quality metrics from an explicit reconstruction matrix R (Sec. 2.4):
+// Image-quality metrics from an explicit reconstruction matrix R (Sec. 2.5):
 //
 //   srf_diag    SRF map      out[n]     = sum_m R[n][m] E[m][n]            (Eq. 9, diagonal)
 //   srf_full    SRF matrix   out[n][n'] = sum_m R[n][m] E[m][n']           (Eq. 9)
@@ -26,7 +26,8 @@ __global__ __launch_bounds__(256) void k_srf_diag(EncDev<T> e, const T* __restri
   const int n = blockIdx.x * 8 + (lane >> 3);
   const int nn = n < e.N ? n : 0;
   const int s = nn / e.V, v = nn - s * e.V;
-  const int iy = v / e.nx, ix = v - iy * e.nx;
+  int ix, iy;
+  voxel_xy(e, v, &ix, &iy);
   const cx<T>* Rr = reinterpret_cast<const cx<T>*>(R) + (size_t)nn * e.M;
   double ar = 0.0, ai = 0.0;
   int m = w * 8 + (lane & 7);

@@ -31,6 +31,7 @@ namespace {
 struct OwnedEncoding {
   pinv_encoding e{};
   std::vector<double> k, t, coil, b0, species;
+  std::vector<int32_t> vox;
   explicit OwnedEncoding(const pinv_encoding& s) {
     e = s;
     const size_t V = (size_t)s.nx * s.ny;
@@ -51,6 +52,10 @@ struct OwnedEncoding {
     if (s.species_hz) {
       species.assign(s.species_hz, s.species_hz + s.nspecies);
       e.species_hz = species.data();
+    }
+    if (s.voxels && s.nvox > 0) {
+      vox.assign(s.voxels, s.voxels + s.nvox);
+      e.voxels = vox.data();
     }
   }
 };

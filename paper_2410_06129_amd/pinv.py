@@ -23,6 +23,9 @@ FLAG_KEEP_GRAM = 1
 FLAG_UNCACHED = 2
 FLAG_GRAM_FULL = 4
 FLAG_NO_R = 8
+FLAG_R_FP64 = 16
+CPROD_AUTO, CPROD_3M, CPROD_4M = 0, 1, 2
+GRAM_AUTO, GRAM_PSF, GRAM_SHARED, GRAM_FULL = 0, 1, 2, 3
 BUF_R, BUF_LINV, BUF_GRAM = 0, 1, 2
 METRIC_DIAG, METRIC_FULL = 0, 1
 
@@ -37,19 +40,23 @@ _dp = ctypes.POINTER(ctypes.c_double)
 class pinv_encoding(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nk", ctypes.c_int64),
                 ("k", _dp), ("t", _dp), ("ncoil", ctypes.c_int32), ("coil", _dp),
-                ("b0_hz", _dp), ("nspecies", ctypes.c_int32), ("species_hz", _dp)]
+                ("b0_hz", _dp), ("nspecies", ctypes.c_int32), ("species_hz", _dp),
+                ("voxels", ctypes.POINTER(ctypes.c_int32)), ("nvox", ctypes.c_int32)]
 
 
 class pinv_build_opts(ctypes.Structure):
     _fields_ = [("lambda_", ctypes.c_double), ("lambda_mode", ctypes.c_int32),
-                ("prec", ctypes.c_int32), ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("prec", ctypes.c_int32), ("flags", ctypes.c_int32), ("cprod", ctypes.c_int32),
+                ("nb", ctypes.c_int32), ("gram", ctypes.c_int32)]
 
 
 class pinv_plan_info(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int64), ("M", ctypes.c_int64), ("lambda_abs", ctypes.c_double),
                 ("prec", ctypes.c_int32), ("ready", ctypes.c_int32), ("key", ctypes.c_uint64),
                 ("device_bytes", ctypes.c_size_t), ("stage_ms", ctypes.c_float * 4),
-                ("has_r", ctypes.c_int32), ("gram_order", ctypes.c_int64)]
+                ("has_r", ctypes.c_int32), ("gram_order", ctypes.c_int64),
+                ("ncoil", ctypes.c_int32), ("cprod", ctypes.c_int32), ("nk", ctypes.c_int64),
+                ("gram_form", ctypes.c_int32), ("r_fp64", ctypes.c_int32)]
 
 
 class pinv_apply_item(ctypes.Structure):
@@ -153,17 +160,78 @@ def _ptr(a: Optional[np.ndarray]):
 
 
 # ----------------------------------------------------------------------------
+# host-side argument checks.  The C-ABI receives bare device pointers and
+# cannot see a tensor's dtype, shape, layout or device, so a mismatch (a
+# complex64 tensor for an FP64 plan, a transposed view, a short buffer) would
+# make the kernels read or write past the end of device memory.  Every call
+# that passes tensors checks them here first and raises ValueError.
+# ----------------------------------------------------------------------------
+
+_ctx_device = {}     # context handle -> HIP device index
+
+
+def _complex_dtype(prec: int):
+    import torch
+    return torch.complex128 if prec == FP64 else torch.complex64
+
+
+def _real_dtype(prec: int):
+    import torch
+    return torch.float64 if prec == FP64 else torch.float32
+
+
+def _check_layout(where: str, name: str, t, shape, dtype) -> None:
+    if not hasattr(t, "data_ptr") or not hasattr(t, "is_contiguous"):
+        raise ValueError(f"{where}: {name} must be a torch tensor, got {type(t).__name__}")
+    if t.dtype != dtype:
+        raise ValueError(f"{where}: {name} has dtype {t.dtype}, the plan needs {dtype}")
+    if tuple(t.shape) != tuple(int(x) for x in shape):
+        raise ValueError(f"{where}: {name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{where}: {name} must be contiguous (row-major); call .contiguous()")
+
+
+def _check_device(where: str, name: str, t, device: Optional[int]) -> None:
+    if not t.is_cuda:
+        raise ValueError(f"{where}: {name} is on {t.device}, not on the GPU")
+    if device is not None and t.device.index is not None and t.device.index != device:
+        raise ValueError(f"{where}: {name} is on cuda:{t.device.index}, the context on cuda:{device}")
+
+
+def check_tensor(where: str, name: str, t, shape, dtype, device: Optional[int]) -> None:
+    """Raise ValueError unless `t` is a contiguous tensor of `dtype` and `shape`
+    on HIP device `device` (any device when None)."""
+    _check_layout(where, name, t, shape, dtype)
+    _check_device(where, name, t, device)
+
+
+def check_frames(where: str, info: dict, data, image, device: Optional[int] = None) -> int:
+    """data [F, M] and image [F, N] in the plan's complex type; returns F."""
+    cdt = _complex_dtype(info["prec"])
+    if not hasattr(data, "shape") or len(data.shape) != 2:
+        raise ValueError(f"{where}: data must be a 2-D tensor [F, M]")
+    F = int(data.shape[0])
+    _check_layout(where, "data", data, (F, info["M"]), cdt)
+    _check_layout(where, "image", image, (F, info["N"]), cdt)
+    _check_device(where, "data", data, device)
+    _check_device(where, "image", image, device)
+    return F
+
+
+# ----------------------------------------------------------------------------
 # entry points
 # ----------------------------------------------------------------------------
 
 def pinv_context_create(device: int = 0, hbm_budget_bytes: int = 0) -> int:
     out = _vp()
     _check(_lib.pinv_context_create(device, hbm_budget_bytes, ctypes.byref(out)), "pinv_context_create")
+    _ctx_device[out.value] = device
     return out.value
 
 
 def pinv_context_destroy(ctx: int) -> None:
     _check(_lib.pinv_context_destroy(ctx), "pinv_context_destroy")
+    _ctx_device.pop(ctx, None)
 
 
 def _encoding_struct(enc):
@@ -178,17 +246,27 @@ def _encoding_struct(enc):
         coil = np.ascontiguousarray(c.view(np.float64))
     b0 = None if enc.b0_hz is None else np.ascontiguousarray(enc.b0_hz, dtype=np.float64)
     sp = None if enc.species_hz is None else np.ascontiguousarray(enc.species_hz, dtype=np.float64)
-    keep += [t, coil, b0, sp]
+    vox = getattr(enc, "voxels", None)
+    vox = None if vox is None else np.ascontiguousarray(vox, dtype=np.int32)
+    keep += [t, coil, b0, sp, vox]
     s = pinv_encoding(nx=enc.nx, ny=enc.ny, nk=k.shape[0], k=_ptr(k), t=_ptr(t),
                       ncoil=1 if coil is None else enc.coil.shape[0], coil=_ptr(coil),
-                      b0_hz=_ptr(b0), nspecies=1 if sp is None else len(sp), species_hz=_ptr(sp))
+                      b0_hz=_ptr(b0), nspecies=1 if sp is None else len(sp), species_hz=_ptr(sp),
+                      voxels=None if vox is None else vox.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                      nvox=0 if vox is None else len(vox))
     return s, keep
 
 
+def _opts(lam, lambda_mode, prec, flags, cprod, nb, gram):
+    return pinv_build_opts(lambda_=lam, lambda_mode=lambda_mode, prec=prec, flags=flags,
+                           cprod=cprod, nb=nb, gram=gram)
+
+
 def pinv_build(ctx: int, enc, lam: float, lambda_mode: int = LAMBDA_REL_MEAN_DIAG,
-               prec: int = FP32, flags: int = 0, stream=None) -> int:
+               prec: int = FP32, flags: int = 0, stream=None, cprod: int = CPROD_AUTO, nb: int = 0,
+               gram: int = GRAM_AUTO) -> int:
     s, keep = _encoding_struct(enc)
-    o = pinv_build_opts(lambda_=lam, lambda_mode=lambda_mode, prec=prec, flags=flags, reserved=0)
+    o = _opts(lam, lambda_mode, prec, flags, cprod, nb, gram)
     out = _vp()
     st = _lib.pinv_build(ctx, ctypes.byref(s), ctypes.byref(o), _stream_ptr(stream), ctypes.byref(out))
     del keep
@@ -206,7 +284,7 @@ def pinv_plan_wait_status(plan: int) -> int:
 
 def pinv_apply(ctx: int, plan: int, data, image, refine_steps: int = 0, stream=None) -> None:
     """data: device tensor [F, M], image: device tensor [F, N] (complex64 or complex128)."""
-    F = data.shape[0]
+    F = check_frames("pinv_apply", pinv_plan_info_get(plan), data, image, _ctx_device.get(ctx))
     _check(_lib.pinv_apply(ctx, plan, data.data_ptr(), F, image.data_ptr(), refine_steps,
                            _stream_ptr(stream)), "pinv_apply")
 
@@ -214,20 +292,35 @@ def pinv_apply(ctx: int, plan: int, data, image, refine_steps: int = 0, stream=N
 def pinv_apply_grouped(ctx: int, items: Sequence[tuple], refine_steps: int = 0, stream=None) -> None:
     """items: sequence of (plan, data tensor, image tensor)."""
     arr = (pinv_apply_item * len(items))()
+    dev = _ctx_device.get(ctx)
     for i, (plan, d, x) in enumerate(items):
-        arr[i] = pinv_apply_item(plan, d.data_ptr(), x.data_ptr(), d.shape[0])
+        F = check_frames(f"pinv_apply_grouped item {i}", pinv_plan_info_get(plan), d, x, dev)
+        arr[i] = pinv_apply_item(plan, d.data_ptr(), x.data_ptr(), F)
     _check(_lib.pinv_apply_grouped(ctx, len(items), arr, refine_steps, _stream_ptr(stream)),
            "pinv_apply_grouped")
 
 
 def pinv_forward(ctx: int, plan: int, image, data, stream=None) -> None:
-    _check(_lib.pinv_forward(ctx, plan, image.data_ptr(), image.shape[0], data.data_ptr(),
+    """data = E image (Eq. 1): image [F, N] -> data [F, M], in the plan's type."""
+    info = pinv_plan_info_get(plan)
+    if not hasattr(image, "shape") or len(image.shape) != 2:
+        raise ValueError("pinv_forward: image must be a 2-D tensor [F, N]")
+    F = int(image.shape[0])
+    cdt = _complex_dtype(info["prec"])
+    dev = _ctx_device.get(ctx)
+    check_tensor("pinv_forward", "image", image, (F, info["N"]), cdt, dev)
+    check_tensor("pinv_forward", "data", data, (F, info["M"]), cdt, dev)
+    _check(_lib.pinv_forward(ctx, plan, image.data_ptr(), F, data.data_ptr(),
                              _stream_ptr(stream)), "pinv_forward")
 
 
 def pinv_srf(ctx: int, plan: int, out, mode: int = METRIC_DIAG, stream=None) -> None:
     """SRF = R E (Eq. 9): its diagonal (mode METRIC_DIAG, out [N]) or the
     full matrix (METRIC_FULL, out [N, N]); complex, in the plan's precision."""
+    info = pinv_plan_info_get(plan)
+    N = info["N"]
+    shape = (N,) if mode == METRIC_DIAG else (N, N)
+    check_tensor("pinv_srf", "out", out, shape, _complex_dtype(info["prec"]), _ctx_device.get(ctx))
     _check(_lib.pinv_srf(ctx, plan, mode, out.data_ptr(), _stream_ptr(stream)), "pinv_srf")
 
 
@@ -236,9 +329,20 @@ def pinv_noise(ctx: int, plan: int, out, coil_cov=None, mode: int = METRIC_DIAG,
     """Noise matrix X = R (Psi_c kron I) R^H (Eq. 10): diag(X) (METRIC_DIAG, real
     out [N]) or X (METRIC_FULL, complex out [N, N]).  coil_cov: [C, C] Hermitian
     positive definite, or None for white noise."""
+    info = pinv_plan_info_get(plan)
+    N = info["N"]
+    if mode == METRIC_DIAG:
+        check_tensor("pinv_noise", "out", out, (N,), _real_dtype(info["prec"]), _ctx_device.get(ctx))
+    else:
+        check_tensor("pinv_noise", "out", out, (N, N), _complex_dtype(info["prec"]),
+                     _ctx_device.get(ctx))
     cov = None
     if coil_cov is not None:
         cov = np.ascontiguousarray(np.asarray(coil_cov, dtype=np.complex128))
+        C = info["ncoil"]
+        if cov.shape != (C, C):
+            raise ValueError(f"pinv_noise: coil_cov must be [{C}, {C}] (the plan's coils), "
+                             f"got {cov.shape}")
     _check(_lib.pinv_noise(ctx, plan, None if cov is None else cov.ctypes.data, mode,
                            out.data_ptr(), _stream_ptr(stream)), "pinv_noise")
 
@@ -248,7 +352,8 @@ def pinv_plan_info_get(plan: int) -> dict:
     _check(_lib.pinv_plan_info_get(plan, ctypes.byref(i)), "pinv_plan_info_get")
     return dict(N=i.N, M=i.M, lambda_abs=i.lambda_abs, prec=i.prec, ready=bool(i.ready),
                 key=i.key, device_bytes=i.device_bytes, stage_ms=list(i.stage_ms),
-                has_r=bool(i.has_r), gram_order=i.gram_order)
+                has_r=bool(i.has_r), gram_order=i.gram_order, ncoil=i.ncoil, cprod=i.cprod,
+                nk=i.nk, gram_form=i.gram_form, r_fp64=bool(i.r_fp64))
 
 
 def pinv_plan_buffers(plan: int):
@@ -259,6 +364,10 @@ def pinv_plan_buffers(plan: int):
 
 
 def pinv_plan_copy_buffer(plan: int, which: int, dst, stream=None) -> None:
+    """Copy R, L^-1 or the Gram into `dst` (contiguous device tensor of exactly
+    the buffer's size; the library checks the byte count)."""
+    if not hasattr(dst, "is_contiguous") or not dst.is_contiguous() or not dst.is_cuda:
+        raise ValueError("pinv_plan_copy_buffer: dst must be a contiguous GPU tensor")
     nbytes = dst.numel() * dst.element_size()
     _check(_lib.pinv_plan_copy_buffer(plan, which, dst.data_ptr(), nbytes, _stream_ptr(stream)),
            "pinv_plan_copy_buffer")
@@ -299,9 +408,9 @@ def pinv_context_trim(ctx: int) -> None:
 
 
 def pinv_encoding_key(enc, lam: float, lambda_mode: int = LAMBDA_REL_MEAN_DIAG, prec: int = FP32,
-                      flags: int = 0):
+                      flags: int = 0, cprod: int = CPROD_AUTO, nb: int = 0, gram: int = GRAM_AUTO):
     s, keep = _encoding_struct(enc)
-    o = pinv_build_opts(lambda_=lam, lambda_mode=lambda_mode, prec=prec, flags=flags, reserved=0)
+    o = _opts(lam, lambda_mode, prec, flags, cprod, nb, gram)
     k, b = ctypes.c_uint64(), ctypes.c_size_t()
     st = _lib.pinv_encoding_key(ctypes.byref(s), ctypes.byref(o), ctypes.byref(k), ctypes.byref(b))
     del keep
@@ -324,10 +433,12 @@ def pinv_server_create(ctx: int, device: int = 0, hbm_budget_bytes: int = 0, max
 
 def pinv_server_submit(server: int, enc, data, image, lam: float = 1e-3,
                        lambda_mode: int = LAMBDA_REL_MEAN_DIAG, prec: int = FP32, flags: int = 0,
-                       refine_steps: int = 0, tag: int = 0) -> int:
+                       refine_steps: int = 0, tag: int = 0, cprod: int = CPROD_AUTO,
+                       gram: int = GRAM_AUTO) -> int:
     """data/image: device tensors [F, M] / [F, N], kept alive by the caller until completion."""
+    check_frames("pinv_server_submit", {"prec": prec, "N": enc.N, "M": enc.M}, data, image)
     s, keep = _encoding_struct(enc)
-    o = pinv_build_opts(lambda_=lam, lambda_mode=lambda_mode, prec=prec, flags=flags, reserved=0)
+    o = _opts(lam, lambda_mode, prec, flags, cprod, 0, gram)
     r = pinv_request(enc=ctypes.pointer(s), opts=o, data=data.data_ptr(), image=image.data_ptr(),
                      F=data.shape[0], refine_steps=refine_steps, reserved=0, tag=tag)
     t = ctypes.c_uint64()

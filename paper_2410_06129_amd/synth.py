@@ -16,8 +16,8 @@ Conventions (paper Sec. 2, Eq. 2 and Sec. 3.3):
 
 Seeds follow numpy.random.default_rng(1000*wid + j), where wid numbers the
 workload (1 radial 32x32, 2 spiral 64x64 with 8 coils, 3 spiral 96x96 with 16
-coils, 4 five-species 32x32, 5 serving trace) and j = 1 phantom, 2 coils, 3 B0,
-4 noise, 5 dynamics, 6 serving trace.
+coils, 4 five-species 32x32, 5 serving trace, 6 spiral 128x128 with 8 coils)
+and j = 1 phantom, 2 coils, 3 B0, 4 noise, 5 dynamics, 6 serving trace.
 """
 from __future__ import annotations
 
@@ -45,6 +45,9 @@ class Encoding:
     coil       [C, V] complex128 sensitivities, or None (single unit coil)
     b0_hz      [V] float64 off-resonance in Hz, or None
     species_hz [S] float64 species frequencies in Hz, or None (=> one species at 0 Hz)
+    voxels     [V] int32 ascending grid indices iy*nx + ix of the unknown voxels (a
+               mask), or None (every grid voxel is an unknown); coil and b0_hz
+               still cover the whole grid
     """
 
     nx: int
@@ -54,10 +57,11 @@ class Encoding:
     coil: Optional[np.ndarray] = None
     b0_hz: Optional[np.ndarray] = None
     species_hz: Optional[np.ndarray] = None
+    voxels: Optional[np.ndarray] = None
 
     @property
     def V(self) -> int:
-        return self.nx * self.ny
+        return self.nx * self.ny if self.voxels is None else int(len(self.voxels))
 
     @property
     def S(self) -> int:
@@ -87,10 +91,15 @@ class Encoding:
             assert self.t.shape == (self.K,)
         if self.coil is not None:
             self.coil = np.ascontiguousarray(self.coil, dtype=np.complex128)
-            assert self.coil.shape[1] == self.V
+            assert self.coil.shape[1] == self.nx * self.ny
         if self.b0_hz is not None:
             self.b0_hz = np.ascontiguousarray(self.b0_hz, dtype=np.float64)
-            assert self.b0_hz.shape == (self.V,)
+            assert self.b0_hz.shape == (self.nx * self.ny,)
+        if self.voxels is not None:
+            self.voxels = np.ascontiguousarray(self.voxels, dtype=np.int32)
+            assert self.voxels.ndim == 1 and len(self.voxels) >= 1
+            assert np.all(np.diff(self.voxels) > 0)
+            assert self.voxels[0] >= 0 and self.voxels[-1] < self.nx * self.ny
         if self.species_hz is not None:
             self.species_hz = np.ascontiguousarray(self.species_hz, dtype=np.float64)
         if (self.S > 1 or self.b0_hz is not None) and self.t is None:
@@ -144,6 +153,25 @@ def vd_spiral(n: int, K: int, turns: Optional[float] = None) -> np.ndarray:
 
 def sample_times(K: int, dwell: float = 4e-6) -> np.ndarray:
     return np.arange(K, dtype=np.float64) * dwell
+
+
+# ----------------------------------------------------------------------------
+# voxel masks
+# ----------------------------------------------------------------------------
+
+def circular_mask(nx: int, ny: int, diameter: float = 1.0) -> np.ndarray:
+    """Grid indices iy*nx + ix of the voxels whose centres lie inside a circle
+    of `diameter` (in FOV units, 1 = the side of the image) centred on the
+    field of view; ascending int32."""
+    X, Y = voxel_centres(nx, ny)
+    return np.flatnonzero(X ** 2 + Y ** 2 <= (diameter / 2.0) ** 2).astype(np.int32)
+
+
+def threshold_mask(image: np.ndarray, fraction: float) -> np.ndarray:
+    """Grid indices of the voxels whose magnitude is at least `fraction` of the
+    image's maximum magnitude; ascending int32."""
+    a = np.abs(np.asarray(image).ravel())
+    return np.flatnonzero(a >= fraction * a.max()).astype(np.int32)
 
 
 # ----------------------------------------------------------------------------
@@ -260,6 +288,20 @@ def spiral_64x64_c8(F: int = 1000) -> Workload:
 def spiral_96x96_c16(F: int = 500, rel: float = 1e-3) -> Workload:
     """96x96 (N=9216), 16 coils, 8192-sample spiral per coil (M=131072), F frames."""
     return _spiral_multicoil(3, 96, 16, 8192, F, "96x96_c16_spiral8192_f500", rel)
+
+
+def spiral_128x128_c8(F: int = 1000) -> Workload:
+    """128x128 (N=16384), 8 coils, VD spiral of 2N = 32768 samples per coil
+    (M=262144), F frames: the largest shape of the serving mix (2N samples per
+    coil) at its middle coil count.  Frame noise is left to the caller (F x M
+    is 4 GB in complex128); `noise` here is empty."""
+    wid, n, C, K = 6, 128, 8, 2 * 128 * 128
+    k = vd_spiral(n, K)
+    coil = coil_maps(n, n, C, rng_for(wid, SEED_COILS))
+    enc = Encoding(n, n, k, coil=coil)
+    x = ellipse_phantom(n, n, rng_for(wid, SEED_PHANTOM))
+    imgs = dynamic_frames(x, F, rng_for(wid, SEED_DYN))
+    return Workload(f"128x128_c8_spiral{K}_f{F}", enc, 1e-3, imgs, np.zeros((0, enc.M), np.complex128))
 
 
 def species5_32x32_c8(F: int = 200) -> Workload:

@@ -88,3 +88,96 @@ def test_right_pseudoinverse_options_without_device():
             assert e.status == want
         else:
             raise AssertionError(f"prec {prec} flags {flags} accepted")
+
+
+def _expect(pinv, want, fn):
+    try:
+        fn()
+    except pinv.PinvError as e:
+        assert e.status == want, (e.status, want, str(e))
+    else:
+        raise AssertionError("accepted")
+
+
+def test_product_gram_and_r_forms_without_device():
+    """Build options are validated and sized on the host: the complex-product
+    form, the Gram form (PSF needs no off-resonance map), the block size (64
+    only) and the FP64-formed R of FP32 plans (W held in FP64: 8 N M more bytes).
+    Each form has its own cache key."""
+    ensure_built()
+    from paper_2410_06129_amd import pinv, synth
+    enc = synth.small_case(seed=5, nx=12, ny=10, C=2, K=300, F=1).enc
+    encb0 = synth.small_case(seed=6, nx=12, ny=10, C=2, K=300, F=1, b0=True).enc
+    N, M = enc.N, enc.M
+    keys = {pinv.pinv_encoding_key(enc, 1e-3, prec=pinv.FP32, cprod=c, gram=g)[0]
+            for c in (pinv.CPROD_3M, pinv.CPROD_4M) for g in (pinv.GRAM_PSF, pinv.GRAM_SHARED, pinv.GRAM_FULL)}
+    assert len(keys) == 6
+    # AUTO resolves to 3M for FP32 plans and to the PSF form without B0
+    assert (pinv.pinv_encoding_key(enc, 1e-3, prec=pinv.FP32)[0]
+            == pinv.pinv_encoding_key(enc, 1e-3, prec=pinv.FP32, cprod=pinv.CPROD_3M, gram=pinv.GRAM_PSF)[0])
+    assert (pinv.pinv_encoding_key(enc, 1e-3, prec=pinv.FP64)[0]
+            == pinv.pinv_encoding_key(enc, 1e-3, prec=pinv.FP64, cprod=pinv.CPROD_4M)[0])
+    assert (pinv.pinv_encoding_key(enc, 1e-3, flags=pinv.FLAG_GRAM_FULL)[0]
+            == pinv.pinv_encoding_key(enc, 1e-3, gram=pinv.GRAM_FULL)[0])
+    _, b32 = pinv.pinv_encoding_key(enc, 1e-3, prec=pinv.FP32)
+    k64r, b64r = pinv.pinv_encoding_key(enc, 1e-3, prec=pinv.FP32, flags=pinv.FLAG_R_FP64)
+    assert b64r - b32 == 8 * N * M
+    pinv.pinv_encoding_key(enc, 1e-3, nb=64)
+    pinv.pinv_encoding_key(encb0, 1e-3, gram=pinv.GRAM_SHARED)
+    for want, kw, e in ((pinv.ERR_INVALID, dict(gram=pinv.GRAM_PSF), encb0),
+                        (pinv.ERR_INVALID, dict(gram=9), enc),
+                        (pinv.ERR_INVALID, dict(flags=pinv.FLAG_GRAM_FULL, gram=pinv.GRAM_PSF), enc),
+                        (pinv.ERR_INVALID, dict(cprod=3), enc),
+                        (pinv.ERR_INVALID, dict(prec=pinv.BF16X3, cprod=pinv.CPROD_3M), enc),
+                        (pinv.ERR_UNSUPPORTED, dict(nb=128), enc),
+                        (pinv.ERR_INVALID, dict(prec=pinv.FP64, flags=pinv.FLAG_R_FP64), enc),
+                        (pinv.ERR_INVALID, dict(flags=pinv.FLAG_R_FP64 | pinv.FLAG_NO_R), enc)):
+        _expect(pinv, want, lambda: pinv.pinv_encoding_key(e, 1e-3, **kw))
+
+
+def test_voxel_mask_without_device():
+    """A voxel mask (Sec. 3.1, Sec. 4.4) shrinks the unknowns to N = S * nvox:
+    the plan is sized on that N; unsorted or out-of-grid lists are refused."""
+    ensure_built()
+    import numpy as np
+    from paper_2410_06129_amd import pinv, synth
+    base = synth.small_case(seed=7, nx=16, ny=14, C=2, K=500, F=1).enc
+    vox = synth.circular_mask(16, 14)
+    masked = synth.Encoding(base.nx, base.ny, base.k, coil=base.coil, voxels=vox)
+    assert masked.N == len(vox) < base.N
+    k0, b0 = pinv.pinv_encoding_key(base, 1e-3, flags=pinv.FLAG_NO_R, gram=pinv.GRAM_SHARED)
+    k1, b1 = pinv.pinv_encoding_key(masked, 1e-3, flags=pinv.FLAG_NO_R, gram=pinv.GRAM_SHARED)
+    assert k0 != k1
+    assert b0 - b1 == (3 * 16 + 8) * (base.N ** 2 - masked.N ** 2)
+    for bad in (vox[::-1].copy(), np.array([0, 5, 5], np.int32), np.array([0, 16 * 14], np.int32)):
+        e = synth.Encoding(base.nx, base.ny, base.k, coil=base.coil)
+        e.voxels = np.ascontiguousarray(bad, dtype=np.int32)   # bypass the generator's own checks
+        _expect(pinv, pinv.ERR_INVALID, lambda: pinv.pinv_encoding_key(e, 1e-3))
+
+
+def test_binding_checks_tensors_before_the_call():
+    """The C-ABI sees bare pointers; the binding refuses a tensor of the wrong
+    dtype, shape or layout, or one not on the GPU, before calling it."""
+    ensure_built()
+    import pytest
+    import torch
+    from paper_2410_06129_amd import pinv
+    info = {"prec": pinv.FP32, "N": 6, "M": 10}
+    d = torch.zeros((3, 10), dtype=torch.complex64)
+    x = torch.zeros((3, 6), dtype=torch.complex64)
+    cases = [
+        (d.to(torch.complex128), x, "dtype"),                       # FP64 data for an FP32 plan
+        (torch.zeros((3, 11), dtype=torch.complex64), x, "shape"),  # wrong M
+        (d, torch.zeros((2, 6), dtype=torch.complex64), "shape"),   # image frames differ
+        (torch.zeros((10, 3), dtype=torch.complex64).t(), x, "contiguous"),   # transposed view
+        (d, x, "not on the GPU"),                                   # host tensors
+        (d.numpy(), x, "torch tensor"),                             # not a tensor
+        (d[0], x, "2-D tensor"),                                    # one frame without the F axis
+    ]
+    for data, image, msg in cases:
+        with pytest.raises(ValueError) as ei:
+            pinv.check_frames("pinv_apply", info, data, image)
+        assert msg in str(ei.value), (msg, str(ei.value))
+    with pytest.raises(ValueError) as ei:
+        pinv.check_frames("pinv_apply", dict(info, prec=pinv.FP64), d, x)
+    assert "complex128" in str(ei.value)

@@ -49,6 +49,11 @@ def frame_rel(a, b):
     return np.linalg.norm(a - b, axis=1) / np.linalg.norm(b, axis=1)
 
 
+def max_rel_entry(a, b):
+    """Largest entrywise difference relative to the largest reference entry."""
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
 CASES = {
     "ragged_c3": dict(seed=101, nx=24, ny=20, C=3, K=700, F=5),
     "species_b0": dict(seed=102, nx=12, ny=12, C=2, K=500, F=4, species=[0.0, 150.0], b0=True),
@@ -82,9 +87,9 @@ def to_dev(a, dtype):
     return torch.from_numpy(np.ascontiguousarray(a).astype(dtype)).cuda()
 
 
-def build(P, ctx, enc, prec, flags=0, lam=1e-3, mode=None):
+def build(P, ctx, enc, prec, flags=0, lam=1e-3, mode=None, **kw):
     mode = P.LAMBDA_REL_MEAN_DIAG if mode is None else mode
-    plan = P.pinv_build(ctx, enc, lam, mode, prec, flags)
+    plan = P.pinv_build(ctx, enc, lam, mode, prec, flags, **kw)
     P.pinv_plan_wait(plan)
     return plan
 
@@ -109,6 +114,9 @@ def test_fp64_stages_match_oracle(P, ctx, name):
     assert np.max(np.abs(G - Go)) <= 1e-12 * np.max(np.abs(Go))
     assert rel(np.tril(Li.cpu().numpy()), o["Linv"]) < 1e-9
     assert rel(R.cpu().numpy(), o["R"]) < 1e-9
+    # element by element, so a mis-indexed ragged tail tile of small entries fails too
+    assert max_rel_entry(np.tril(Li.cpu().numpy()), o["Linv"]) < 1e-9
+    assert max_rel_entry(R.cpu().numpy(), o["R"]) < 1e-9
     d = to_dev(o["d"], np.complex128)
     x = torch.empty((d.shape[0], N), dtype=torch.complex128, device="cuda")
     P.pinv_apply(ctx, plan, d, x)
@@ -460,3 +468,122 @@ def test_cache_hit_and_release(P, ctx):
     P.pinv_plan_release(b)
     freed = P.pinv_cache_trim(ctx)
     assert freed > 0
+
+
+@pytest.mark.parametrize("cprod", ["3m", "4m"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", ["ragged_c3", "aligned_species_b0"])
+def test_product_forms_match_oracle(P, ctx, name, prec, cprod):
+    """W, R and the apply with three real products per complex product (Gauss)
+    or four.  FP64 plans: R element by element and the images within 1e-9 of
+    the oracle either way.  FP32 plans: images within kappa * 1e-6 unrefined
+    and 1e-5 after two refinement steps."""
+    o = oracle_case(name)
+    enc, N, M = o["w"].enc, o["w"].enc.N, o["w"].enc.M
+    form = P.CPROD_3M if cprod == "3m" else P.CPROD_4M
+    pr, cdt = (P.FP64, np.complex128) if prec == "fp64" else (P.FP32, np.complex64)
+    plan = build(P, ctx, enc, pr, flags=P.FLAG_UNCACHED, cprod=form)
+    try:
+        assert P.pinv_plan_info_get(plan)["cprod"] == form
+        d = to_dev(o["d"], cdt)
+        x0 = torch.empty((d.shape[0], N), dtype=d.dtype, device="cuda")
+        x2 = torch.empty_like(x0)
+        P.pinv_apply(ctx, plan, d, x0)
+        P.pinv_apply(ctx, plan, d, x2, refine_steps=2)
+        # 150 frames: the MFMA apply tiles (the 5 frames above stream R row by row)
+        rng = np.random.default_rng(77)
+        dm = rng.standard_normal((150, M)) + 1j * rng.standard_normal((150, M))
+        xm = torch.empty((150, N), dtype=d.dtype, device="cuda")
+        P.pinv_apply(ctx, plan, to_dev(dm, cdt), xm)
+        R = torch.empty((N, M), dtype=d.dtype, device="cuda")
+        P.pinv_plan_copy_buffer(plan, P.BUF_R, R)
+        torch.cuda.synchronize()
+    finally:
+        P.pinv_plan_release(plan)
+    e0 = frame_rel(x0.cpu().numpy().astype(np.complex128), o["x"]).max()
+    e2 = frame_rel(x2.cpu().numpy().astype(np.complex128), o["x"]).max()
+    em = frame_rel(xm.cpu().numpy().astype(np.complex128), dm @ o["R"].T).max()
+    print(f"{name} {prec} {cprod}: err0 {e0:.2e} err2 {e2:.2e} mfma-apply {em:.2e}")
+    if prec == "fp64":
+        assert max_rel_entry(R.cpu().numpy(), o["R"]) < 1e-9
+        assert e0 < 1e-9 and e2 < 1e-9 and em < 1e-9
+    else:
+        assert e0 < o["kappa"] * 1e-6 and em < o["kappa"] * 1e-6
+        assert e2 < 1e-5
+
+
+@pytest.mark.parametrize("form", ["psf", "shared", "full"])
+@pytest.mark.parametrize("name", ["ragged_c3", "aligned_c2"])
+def test_gram_forms_match_oracle(P, ctx, name, form):
+    """The Gram through the point-spread function (offset grid times coil
+    cross-products), on MFMA over one coil's samples times the coil
+    cross-products, or over all M rows: FP64 plans, element by element within
+    1e-12 of max|G|, and the same images (1e-9)."""
+    o = oracle_case(name)
+    enc, N = o["w"].enc, o["w"].enc.N
+    g = {"psf": P.GRAM_PSF, "shared": P.GRAM_SHARED, "full": P.GRAM_FULL}[form]
+    plan = build(P, ctx, enc, P.FP64, flags=P.FLAG_UNCACHED, gram=g)
+    try:
+        assert P.pinv_plan_info_get(plan)["gram_form"] == g
+        G = torch.empty((N, N), dtype=torch.complex128, device="cuda")
+        P.pinv_plan_copy_buffer(plan, P.BUF_GRAM, G)
+        d = to_dev(o["d"], np.complex128)
+        x = torch.empty((d.shape[0], N), dtype=d.dtype, device="cuda")
+        P.pinv_apply(ctx, plan, d, x)
+        torch.cuda.synchronize()
+    finally:
+        P.pinv_plan_release(plan)
+    G = G.cpu().numpy()
+    # the kept Gram is full Hermitian: both triangles against the oracle
+    assert np.max(np.abs(G - o["b"].G)) <= 1e-12 * np.max(np.abs(o["b"].G))
+    assert frame_rel(x.cpu().numpy(), o["x"]).max() < 1e-9
+
+
+def test_psf_gram_with_species(P, ctx):
+    """Species without an off-resonance map keep the offset structure (one PSF
+    per species pair): the PSF Gram of a two-species encoding against the
+    oracle, element by element."""
+    w = synth.small_case(seed=151, nx=14, ny=11, C=3, K=640, F=2, species=[0.0, 210.0])
+    enc, N = w.enc, w.enc.N
+    Go = oracle.gram(enc)
+    plan = build(P, ctx, enc, P.FP64, flags=P.FLAG_UNCACHED)
+    try:
+        assert P.pinv_plan_info_get(plan)["gram_form"] == P.GRAM_PSF
+        G = torch.empty((N, N), dtype=torch.complex128, device="cuda")
+        P.pinv_plan_copy_buffer(plan, P.BUF_GRAM, G)
+        torch.cuda.synchronize()
+    finally:
+        P.pinv_plan_release(plan)
+    assert np.max(np.abs(G.cpu().numpy() - Go)) <= 1e-12 * np.max(np.abs(Go))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_r_formed_in_fp64_matches_oracle(P, ctx, name):
+    """FP32 plans with PINV_FLAG_R_FP64: W and R formed in FP64 and R rounded
+    once to complex64.  R within the one rounding (2^-24 of each entry, so
+    2^-23 of max|R| with room for the FP64 products) of the oracle's, element
+    by element; unrefined FP32 applies within 1e-5 of the oracle's images
+    (row-streaming and MFMA paths), where plain FP32 plans need refinement."""
+    o = oracle_case(name)
+    enc, N, M = o["w"].enc, o["w"].enc.N, o["w"].enc.M
+    plan = build(P, ctx, enc, P.FP32, flags=P.FLAG_UNCACHED | P.FLAG_R_FP64)
+    try:
+        info = P.pinv_plan_info_get(plan)
+        assert info["r_fp64"] and info["prec"] == P.FP32
+        R = torch.empty((N, M), dtype=torch.complex64, device="cuda")
+        P.pinv_plan_copy_buffer(plan, P.BUF_R, R)
+        d = to_dev(o["d"], np.complex64)
+        x = torch.empty((d.shape[0], N), dtype=torch.complex64, device="cuda")
+        P.pinv_apply(ctx, plan, d, x)
+        d40 = to_dev(np.tile(o["d"], (8, 1))[:40], np.complex64)
+        x40 = torch.empty((40, N), dtype=torch.complex64, device="cuda")
+        P.pinv_apply(ctx, plan, d40, x40)
+        torch.cuda.synchronize()
+    finally:
+        P.pinv_plan_release(plan)
+    eR = max_rel_entry(R.cpu().numpy().astype(np.complex128), o["R"])
+    e = frame_rel(x.cpu().numpy().astype(np.complex128), o["x"]).max()
+    e40 = frame_rel(x40.cpu().numpy().astype(np.complex128), np.tile(o["x"], (8, 1))[:40]).max()
+    print(f"{name}: R entry err {eR:.2e} image err {e:.2e} / {e40:.2e} (kappa {o['kappa']:.3g})")
+    assert eR <= 2.0 ** -23
+    assert e < 1e-5 and e40 < 1e-5

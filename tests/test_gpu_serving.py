@@ -1,10 +1,14 @@
 """Serving on the GPU through the C-ABI server: every request completes, plans
 are reused by encoding, and each request's image equals what building its
 plan and applying it alone gives (the grouped launches run each item's tiles
-exactly as a single apply does, so equality is bitwise)."""
+exactly as a single apply does, so equality is bitwise).  Every served image
+is also checked against the FP64 oracle's reconstruction of the same data
+(Sec. 4.5, Sec. 5: R reused across requests): within 1e-9 for FP64 plans and
+1e-5 for FP32 plans with one refinement step."""
 import numpy as np
 import pytest
 
+import oracle
 from paper_2410_06129_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -58,6 +62,13 @@ def test_mix_equals_alone(P, prec, refine):
     assert stats["builds"] == len(used)
     assert stats["hits"] == 14 - len(used)
     assert stats["invariant_violations"] == 0 and stats["peak_used"] <= stats["budget"]
+    # against the oracle: each served image is (E^H E + lam I)^-1 E^H d
+    builds = {e: oracle.Build(encs[e], rel=1e-3) for e in used}
+    tol = 1e-5 if prec == "fp32" else 1e-9
+    for e, d, x in reqs:
+        ref = builds[e].reconstruct(d.cpu().numpy().astype(np.complex128))
+        err = oracle.relative_error(x.cpu().numpy().astype(np.complex128), ref).max()
+        assert err < tol, (e, err)
     # alone: a fresh plan per encoding, one apply per request
     plans = {}
     try:

@@ -38,6 +38,10 @@ CASES = {
     "aligned_c2": dict(seed=131, nx=16, ny=12, C=2, K=40, F=3),                       # M 80 < N 192
     "general_c3": dict(seed=132, nx=13, ny=11, C=3, K=29, F=2),                       # M 87 < N 143
     "species_b0": dict(seed=133, nx=12, ny=8, C=2, K=48, F=2, species=[0.0, 150.0], b0=True),
+    # several 64-wide factor blocks (the look-ahead's second part runs) and
+    # several tiles in every grid of the right-pseudoinverse products
+    "multiblock_c3": dict(seed=134, nx=40, ny=36, C=3, K=200, F=2),                   # M 600 < N 1440
+    "multiblock_c2": dict(seed=135, nx=30, ny=26, C=2, K=171, F=2),                   # M 342 < N 780
 }
 
 
@@ -89,7 +93,11 @@ def test_right_pinv_matches_oracle(P, ctx, name, prec):
     tol = 1e-9 if prec == "fp64" else kappa * 1e-6
     g = G.cpu().numpy()
     assert np.max(np.abs(np.tril(g) - np.tril(ob.Gr))) <= 1e-12 * np.max(np.abs(ob.Gr))
-    e_r = rel(R.cpu().numpy().astype(np.complex128), ob.recon_matrix())
+    R_ref = ob.recon_matrix()
+    e_r = rel(R.cpu().numpy().astype(np.complex128), R_ref)
+    if prec == "fp64":   # element by element as well
+        e_entry = np.max(np.abs(R.cpu().numpy() - R_ref)) / np.max(np.abs(R_ref))
+        assert e_entry < 1e-9, e_entry
     e_x = rel(x.cpu().numpy().astype(np.complex128), ob.reconstruct(d))
     print(f"{name} {prec}: kappa={kappa:.3g} R {e_r:.2e} x {e_x:.2e}")
     assert e_r < tol and e_x < tol

@@ -451,3 +451,81 @@ def test_oracle_matches_golden_fixture():
         for got, want in ((G, v["G"]), (b.L, v["L"]), (R, v["R"]), (b.reconstruct(d), v["x"]),
                           (np.diagonal(oracle.srf_matrix(R, E)), v["srf_diag"])):
             assert rel(got, c(want)) < 1e-10, name
+
+
+# --- the error metric: per-frame relative image error (Sec. 3.2 compares images
+#     by normalised squared error; the bar is on the largest frame) ------------
+
+def test_relative_error_hand_computed():
+    x = np.array([[1 + 1j, 2.0, 0.0], [3.0, 4.0, 0.0], [0.0, 0.0, 0.0]])
+    ref = np.array([[1.0, 2.0, 0.0], [0.0, 0.0, 5.0], [1.0, 0.0, 0.0]])
+    # frame 0: |x - ref| = |1j| = 1, |ref| = sqrt(5); frame 1: |(3, 4, -5)| = sqrt(50),
+    # |ref| = 5; frame 2: |(-1, 0, 0)| = 1, |ref| = 1
+    want = np.array([1 / math.sqrt(5), math.sqrt(50) / 5, 1.0])
+    got = oracle.relative_error(x, ref)
+    assert got.shape == (3,)
+    assert np.max(np.abs(got - want)) <= 1e-15
+    assert oracle.relative_error(ref, ref).max() == 0.0
+    # one frame given as a vector
+    assert abs(oracle.relative_error(x[0], ref[0])[0] - 1 / math.sqrt(5)) <= 1e-15
+
+
+# --- voxel masks (Sec. 3.1 and Sec. 4.4: unknowns restricted to a support) ------
+
+def test_mask_selects_columns_of_the_full_encoding():
+    """With a mask the unknowns are the listed voxels: E_mask is the full E
+    with the other columns left out, species block by species block."""
+    base = tiny_enc(seed=11, nx=7, ny=6, C=3, K=60, species=[0.0, 90.0], b0=True)
+    vox = np.array([0, 3, 4, 10, 17, 22, 29, 35, 41], dtype=np.int32)
+    masked = synth.Encoding(base.nx, base.ny, base.k, t=base.t, coil=base.coil, b0_hz=base.b0_hz,
+                            species_hz=base.species_hz, voxels=vox)
+    V = base.nx * base.ny
+    cols = np.concatenate([s * V + vox for s in range(base.S)])
+    E_full = oracle.encoding_matrix(base)
+    E_mask = oracle.encoding_matrix(masked)
+    assert masked.N == 2 * len(vox)
+    assert np.max(np.abs(E_mask - E_full[:, cols])) == 0.0
+    # the column evaluator and the Gram restricted the same way
+    assert np.max(np.abs(oracle.encoding_columns(masked, [1, 12]) - E_full[:, cols[[1, 12]]])) == 0.0
+    G = oracle.gram(masked)
+    assert rel(G, oracle.gram(base)[np.ix_(cols, cols)]) < 1e-14
+
+
+def test_mask_on_cartesian_is_a_restricted_dft():
+    """Fully sampled Cartesian with a circular mask: G = N_grid I on the mask,
+    so R = E_mask^H / (N_grid + lam) (Sec. 4.4 masking; P1)."""
+    n, lam = 8, 2.5
+    vox = synth.circular_mask(n, n)
+    enc = synth.Encoding(n, n, synth.cartesian_full(n, n), voxels=vox)
+    assert 0 < len(vox) < n * n
+    G = oracle.gram(enc)
+    assert np.max(np.abs(G - n * n * np.eye(len(vox)))) <= 1e-12 * n * n
+    R = oracle.Build(enc, lam=lam).recon_matrix()
+    Eh = oracle.encoding_matrix(enc).conj().T
+    assert rel(R, Eh / (n * n + lam)) < 1e-13
+
+
+# --- the Gram's Toeplitz (point-spread) structure: without off-resonance every
+#     Fourier factor depends on two voxels through their offset only (Eq. 2,
+#     Eq. 11) ---------------------------------------------------------------------
+
+def test_gram_is_psf_of_voxel_offsets():
+    """G[a][b] = S[a][b] P(s_a, s_b, ix_b - ix_a, iy_b - iy_a) with S the coil
+    cross-products and P a sum over samples of one exponential per offset,
+    evaluated here straight from its definition (a DFT of the trajectory on the
+    offset grid), not through the oracle's E."""
+    enc = tiny_enc(seed=12, nx=6, ny=5, C=2, K=70, species=[0.0, 130.0])
+    V, S = enc.V, enc.S
+    G = oracle.gram(enc)
+    t = enc.t
+    f = enc.species_hz
+    ix, iy = np.arange(V) % enc.nx, np.arange(V) // enc.nx
+    rng = np.random.default_rng(3)
+    for _ in range(40):
+        a, b = rng.integers(0, S * V, 2)
+        sa, va, sb, vb = a // V, a % V, b // V, b % V
+        dx, dy = ix[vb] - ix[va], iy[vb] - iy[va]
+        P = np.sum(np.exp(-2j * math.pi * (enc.k[:, 0] * dx / enc.nx + enc.k[:, 1] * dy / enc.ny
+                                           + (f[sb] - f[sa]) * t)))
+        Sab = np.sum(enc.coil[:, va].conj() * enc.coil[:, vb])
+        assert abs(G[a, b] - Sab * P) <= 1e-12 * abs(G).max()
