@@ -549,6 +549,12 @@ static bool device_streams(int device, DeviceStreams* out) {
   return true;
 }
 
+// Record a failure's detail for pinv_last_error (library-internal).
+extern "C++" pinv_status pinv_fail(pinv_status s, const std::string& msg) { return fail(s, msg); }
+
+// The device a context runs on (library-internal).
+extern "C++" int pinv_context_device(const pinv_context* c) { return c->device; }
+
 // The serving loop's build and apply streams on `device` (library-internal).
 extern "C++" bool pinv_serving_streams(int device, hipStream_t* build, hipStream_t* apply) {
   DeviceStreams d;
@@ -704,9 +710,12 @@ static pinv_status check_build(const pinv_encoding* e, const pinv_build_opts* o,
   form->gram = gram;
   form->no_r = no_r;
   form->r_fp64 = r_fp64;
+  // AUTO: 3M for the FP32 products; 4M for FP64 products, where 3M saved no
+  // time (W at N = 16384: 6.97 s on 3M against 4.74 s on 4M, the FP64 element
+  // generation and the third LDS plane outweighing the fewer matrix products)
   form->m3 = o->cprod == PINV_CPROD_3M   ? true
              : o->cprod == PINV_CPROD_4M ? false
-                                         : o->prec != PINV_FP64;
+                                         : o->prec != PINV_FP64 && !r_fp64;
   *lam_out = lam;
   const int bits = (form->m3 ? 1 : 0) | (gram << 1) | (r_fp64 ? 16 : 0) | (no_r ? 32 : 0);
   *key_out = plan_key(e, *d, lam, o->prec, bits);
@@ -1153,7 +1162,7 @@ static pinv_status solve_right_item(pinv_plan* p, const void* data, int F, void*
 
 // Scratch bytes one item's apply takes from a fixed region (the stack peak of
 // the steps apply_items runs for it).
-static size_t item_scratch_bytes(const pinv_plan* p, int F, int steps) {
+size_t item_scratch_bytes(const pinv_plan* p, int F, int steps) {
   if (F <= 0) return 0;
   auto al = [](size_t n) { return (n + 255) & ~size_t(255); };
   const size_t N = p->N, M = p->M;
@@ -1161,9 +1170,9 @@ static size_t item_scratch_bytes(const pinv_plan* p, int F, int steps) {
   size_t peak = 0;
   const bool tiles = F > kRowApplyMaxF && !p->no_r && !(p->right && steps > 0);
   if (tiles) {
-    peak = p->prec == PINV_FP64     ? apply_scratch_bytes<double>(F, (int)N, (int)M, p->m3)
+    peak = p->prec == PINV_FP64     ? apply_scratch_bytes<double>(F, (int)N, (int)M, p->m3, false)
            : p->prec == PINV_BF16X3 ? apply_scratch_bytes_b3(F, (int)N, (int)M)
-                                    : apply_scratch_bytes<float>(F, (int)N, (int)M, p->m3);
+                                    : apply_scratch_bytes<float>(F, (int)N, (int)M, p->m3, p->r_fp64);
   }
   if (p->no_r) {
     const size_t adj = p->prec == PINV_FP64
@@ -1193,8 +1202,8 @@ static size_t item_scratch_bytes(const pinv_plan* p, int F, int steps) {
 }  // extern "C++"
 
 // The apply pipeline of pinv_apply_grouped with its scratch from `sc`.
-static pinv_status apply_items(pinv_context* c, int32_t n, const pinv_apply_item* items,
-                               int32_t refine_steps, Scratch& sc, hipStream_t s) {
+extern "C++" pinv_status apply_items(pinv_context* c, int32_t n, const pinv_apply_item* items,
+                                     int32_t refine_steps, Scratch& sc, hipStream_t s) {
   for (int i = 0; i < n; ++i) {
     const pinv_plan* p = (const pinv_plan*)items[i].plan;
     if (!p || p->ctx != c) return fail(PINV_ERR_INVALID, "item " + std::to_string(i) + ": bad plan");
@@ -1210,11 +1219,12 @@ static pinv_status apply_items(pinv_context* c, int32_t n, const pinv_apply_item
   while (i < n) {
     const pinv_plan* p0 = (const pinv_plan*)items[i].plan;
     const int prec = p0->prec;
-    const bool m3 = p0->m3;
+    const bool m3 = p0->m3, seg = p0->r_fp64;
     ApplyBatch b;
     b.n = 0;
     while (i < n && b.n < kMaxGroup && ((const pinv_plan*)items[i].plan)->prec == prec &&
-           ((const pinv_plan*)items[i].plan)->m3 == m3) {
+           ((const pinv_plan*)items[i].plan)->m3 == m3 &&
+           ((const pinv_plan*)items[i].plan)->r_fp64 == seg) {
       const pinv_plan* p = (const pinv_plan*)items[i].plan;
       if (items[i].F > kRowApplyMaxF && !p->no_r && !(p->right && refine_steps > 0)) {
         ApplyItemDev& it = b.it[b.n++];
@@ -1229,11 +1239,11 @@ static pinv_status apply_items(pinv_context* c, int32_t n, const pinv_apply_item
     }
     if (b.n == 0) continue;
     if (prec == PINV_FP64)
-      HIPCHK(launch_apply<double>(b, m3, sc, s));
+      HIPCHK(launch_apply<double>(b, m3, false, sc, s));
     else if (prec == PINV_BF16X3)
       HIPCHK(launch_apply_b3(b, sc, s));
     else
-      HIPCHK(launch_apply<float>(b, m3, sc, s));
+      HIPCHK(launch_apply<float>(b, m3, seg, sc, s));
   }
   // a few frames: stream R row by row (bound by HBM bandwidth, not MFMA)
   for (int j = 0; j < n; ++j) {

@@ -13,7 +13,18 @@ namespace pinv {
 // M (the split depends only on the item's F, N and M, so a result is the same
 // alone and in any group); its splits write partial tiles to item.work and
 // k_apply_reduce adds them in split order.
-template <class Cfg>
+//
+// Tiles run frame-tile fastest, so the F/BM tiles that read one BN-row panel
+// of R are resident together and the panel streams from HBM about once.
+//
+// SEG: the contraction runs in segments of kApplySegRows rows; each segment's
+// accumulators are folded into a second FP32 accumulator set.  A running FP32
+// sum over L terms carries a relative rounding error growing like sqrt(L), so
+// over M = 262144 rows (32768 k-steps) an R exact to its FP32 rounding gave
+// 1.5e-5; segments of 4096 rows keep each running sum 8 times shorter.
+constexpr int kApplySegRows = 4096;
+
+template <class Cfg, bool SEG = false>
 __global__ __launch_bounds__(256) void k_apply(const ApplyBatch batch) {
   typedef typename Cfg::T T;
   // locate the item owning this tile (items carry exclusive tile prefix sums)
@@ -27,8 +38,8 @@ __global__ __launch_bounds__(256) void k_apply(const ApplyBatch batch) {
   const int u0 = t - it.tile0;
   const int split = u0 / it.ntile;
   const int u = u0 - split * it.ntile;
-  const int nbj = (it.N + Cfg::BN - 1) / Cfg::BN;
-  const int bi = u / nbj, bj = u % nbj;
+  const int nbi = (it.F + Cfg::BM - 1) / Cfg::BM;
+  const int bi = u % nbi, bj = u / nbi;
   const int k0 = split * it.kchunk, k1 = min(it.M, k0 + it.kchunk);
   LoadDenseKC<Cfg, Cfg::BM, Cfg::LDA, T, false> la;   // D[f][m]
   la.p = reinterpret_cast<const cx<T>*>(it.D);
@@ -41,12 +52,32 @@ __global__ __launch_bounds__(256) void k_apply(const ApplyBatch batch) {
   lb.o0 = bj * Cfg::BN;
   lb.oend = it.N;
   AccTile<Cfg> acc;
-  acc.zero();
-  mainloop<Cfg>(la, lb, k0, k1, acc, smem_base<Cfg>());
   cx<T>* O = it.splits > 1
                  ? reinterpret_cast<cx<T>*>(it.work) + (size_t)split * it.F * it.N
                  : reinterpret_cast<cx<T>*>(it.X);
   const int r0 = bi * Cfg::BM, c0 = bj * Cfg::BN;
+  if constexpr (SEG) {
+    typename Acc<T>::type ore[Cfg::MB][Cfg::NB], oim[Cfg::MB][Cfg::NB];
+#pragma unroll
+    for (int a = 0; a < Cfg::MB; ++a)
+#pragma unroll
+      for (int b = 0; b < Cfg::NB; ++b) ore[a][b] = oim[a][b] = typename Acc<T>::type{0, 0, 0, 0};
+    int ks = k0;
+    do {
+      const int ke = min(k1, ks + kApplySegRows);
+      acc.zero();
+      mainloop<Cfg>(la, lb, ks, ke, acc, smem_base<Cfg>());
+      acc_fold<Cfg>(acc, ore, oim);
+      ks = ke;
+    } while (ks < k1);
+    acc_foreach_outer<Cfg>(ore, oim, [&](int r, int c, T re, T im) {
+      const int row = r0 + r, col = c0 + c;
+      if (row < it.F && col < it.N) O[(size_t)row * it.N + col] = cx<T>{re, im};
+    });
+    return;
+  }
+  acc.zero();
+  mainloop<Cfg>(la, lb, k0, k1, acc, smem_base<Cfg>());
   acc_foreach<Cfg>(acc, [&](int r, int c, T re, T im) {
     const int row = r0 + r, col = c0 + c;
     if (row < it.F && col < it.N) O[(size_t)row * it.N + col] = cx<T>{re, im};
@@ -64,12 +95,12 @@ __global__ __launch_bounds__(256) void k_apply_reduce(const ApplyBatch batch) {
   cx<T>* X = reinterpret_cast<cx<T>*>(it.X);
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    T zr = W[i].re, zi = W[i].im;
+    double zr = W[i].re, zi = W[i].im;   // partials added in FP64, rounded once
     for (int s = 1; s < it.splits; ++s) {
       zr += W[(int64_t)s * n + i].re;
       zi += W[(int64_t)s * n + i].im;
     }
-    X[i] = cx<T>{zr, zi};
+    X[i] = cx<T>{T(zr), T(zi)};
   }
 }
 
@@ -174,27 +205,27 @@ template <class Cfg> static void plan_item(ApplyItemDev& it, int slots) {
   it.kchunk = cdiv(nchunks, it.splits) * Cfg::BK;
 }
 
-template <class Cfg> static int apply_slots() {
-  static const hipError_t attr = allow_smem(k_apply<Cfg>, smem_bytes<Cfg>());
+template <class Cfg, bool SEG> static int apply_slots() {
+  static const hipError_t attr = allow_smem(k_apply<Cfg, SEG>, smem_bytes<Cfg>());
   (void)attr;
-  return resident_blocks(k_apply<Cfg>, 256, smem_bytes<Cfg>());
+  return resident_blocks(k_apply<Cfg, SEG>, 256, smem_bytes<Cfg>());
 }
 
-template <class Cfg> static size_t item_work_bytes(int F, int N, int M) {
+template <class Cfg, bool SEG> static size_t item_work_bytes(int F, int N, int M) {
   ApplyItemDev it{};
   it.F = F;
   it.N = N;
   it.M = M;
-  plan_item<Cfg>(it, apply_slots<Cfg>());
+  plan_item<Cfg>(it, apply_slots<Cfg, SEG>());
   return it.splits > 1 ? (size_t)it.splits * F * N * 2 * sizeof(typename Cfg::T) : 0;
 }
 
 // Grouped apply with per-item contraction splits: sets each item's split,
 // tile range and partial-sum workspace, runs the tiles, then the reduction.
-template <class Cfg>
+template <class Cfg, bool SEG = false>
 static hipError_t run_apply(ApplyBatch b, Scratch& sc, hipStream_t s) {
   typedef typename Cfg::T T;
-  const int slots = apply_slots<Cfg>();
+  const int slots = apply_slots<Cfg, SEG>();
   int tiles = 0, nsplit = 0;
   size_t work_elems = 0;
   for (int i = 0; i < b.n; ++i) {
@@ -220,7 +251,7 @@ static hipError_t run_apply(ApplyBatch b, Scratch& sc, hipStream_t s) {
         off += (size_t)b.it[i].splits * b.it[i].F * b.it[i].N;
       }
   }
-  hipLaunchKernelGGL(k_apply<Cfg>, dim3(tiles), dim3(256), smem_bytes<Cfg>(), s, b);
+  hipLaunchKernelGGL((k_apply<Cfg, SEG>), dim3(tiles), dim3(256), smem_bytes<Cfg>(), s, b);
   hipError_t err = hipGetLastError();
   if (nsplit) {
     if (err == hipSuccess) {
@@ -233,7 +264,7 @@ static hipError_t run_apply(ApplyBatch b, Scratch& sc, hipStream_t s) {
   return err;
 }
 
-template <typename T, bool M3>
+template <typename T, bool M3, bool SEG>
 static hipError_t apply_form(const ApplyBatch& b, Scratch& sc, hipStream_t s) {
   typedef ApplyCfgOf<T, M3> C;
   if constexpr (std::is_same<T, float>::value) {
@@ -248,29 +279,35 @@ static hipError_t apply_form(const ApplyBatch& b, Scratch& sc, hipStream_t s) {
         many.it[many.n++] = b.it[i];
     }
     if (few.n) {
-      const hipError_t err = run_apply<typename C::few>(few, sc, s);
+      const hipError_t err = run_apply<typename C::few, SEG>(few, sc, s);
       if (err != hipSuccess) return err;
     }
-    return many.n ? run_apply<typename C::many>(many, sc, s) : hipSuccess;
+    return many.n ? run_apply<typename C::many, SEG>(many, sc, s) : hipSuccess;
   } else {
-    return run_apply<typename C::many>(b, sc, s);
+    return run_apply<typename C::many, SEG>(b, sc, s);
   }
 }
 
 template <typename T>
-hipError_t launch_apply(const ApplyBatch& b, bool m3, Scratch& sc, hipStream_t s) {
-  return m3 ? apply_form<T, true>(b, sc, s) : apply_form<T, false>(b, sc, s);
+hipError_t launch_apply(const ApplyBatch& b, bool m3, bool seg, Scratch& sc, hipStream_t s) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (seg) return m3 ? apply_form<T, true, true>(b, sc, s) : apply_form<T, false, true>(b, sc, s);
+  }
+  return m3 ? apply_form<T, true, false>(b, sc, s) : apply_form<T, false, false>(b, sc, s);
 }
 
 template <typename T>
-size_t apply_scratch_bytes(int F, int N, int M, bool m3) {
-  auto go = [&](auto form) -> size_t {
+size_t apply_scratch_bytes(int F, int N, int M, bool m3, bool seg) {
+  auto go = [&](auto form, auto sg) -> size_t {
     typedef ApplyCfgOf<T, decltype(form)::value> C;
+    constexpr bool S = std::is_same<T, float>::value && decltype(sg)::value;
     if (std::is_same<T, float>::value && F <= kFewFramesMaxF)
-      return item_work_bytes<typename C::few>(F, N, M);
-    return item_work_bytes<typename C::many>(F, N, M);
+      return item_work_bytes<typename C::few, S>(F, N, M);
+    return item_work_bytes<typename C::many, S>(F, N, M);
   };
-  return m3 ? go(std::true_type{}) : go(std::false_type{});
+  if (seg)
+    return m3 ? go(std::true_type{}, std::true_type{}) : go(std::false_type{}, std::true_type{});
+  return m3 ? go(std::true_type{}, std::false_type{}) : go(std::false_type{}, std::false_type{});
 }
 
 template <typename T>
@@ -305,13 +342,13 @@ hipError_t launch_apply_b3(const ApplyBatch& b, Scratch& sc, hipStream_t s) {
   return run_apply<B3Cfg>(b, sc, s);
 }
 
-size_t apply_scratch_bytes_b3(int F, int N, int M) { return item_work_bytes<B3Cfg>(F, N, M); }
+size_t apply_scratch_bytes_b3(int F, int N, int M) { return item_work_bytes<B3Cfg, false>(F, N, M); }
 
 // explicit instantiations
-template hipError_t launch_apply<float>(const ApplyBatch&, bool, Scratch&, hipStream_t);
-template hipError_t launch_apply<double>(const ApplyBatch&, bool, Scratch&, hipStream_t);
-template size_t apply_scratch_bytes<float>(int, int, int, bool);
-template size_t apply_scratch_bytes<double>(int, int, int, bool);
+template hipError_t launch_apply<float>(const ApplyBatch&, bool, bool, Scratch&, hipStream_t);
+template hipError_t launch_apply<double>(const ApplyBatch&, bool, bool, Scratch&, hipStream_t);
+template size_t apply_scratch_bytes<float>(int, int, int, bool, bool);
+template size_t apply_scratch_bytes<double>(int, int, int, bool, bool);
 template hipError_t launch_apply_rows<float>(const float*, const float*, float*, int, int, int,
                                              hipStream_t);
 template hipError_t launch_apply_rows<double>(const double*, const double*, double*, int, int, int,

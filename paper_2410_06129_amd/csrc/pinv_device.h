@@ -430,6 +430,43 @@ __device__ __forceinline__ void acc_foreach(const AccTile<Cfg>& acc, F&& f) {
       }
 }
 
+// Fold a tile's accumulators into an outer accumulator pair (re, im), for
+// contractions run in segments.
+template <class Cfg>
+__device__ __forceinline__ void acc_fold(const AccTile<Cfg>& acc,
+                                         typename Acc<typename Cfg::T>::type (&ore)[Cfg::MB][Cfg::NB],
+                                         typename Acc<typename Cfg::T>::type (&oim)[Cfg::MB][Cfg::NB]) {
+#pragma unroll
+  for (int a = 0; a < Cfg::MB; ++a)
+#pragma unroll
+    for (int b = 0; b < Cfg::NB; ++b) {
+      if constexpr (IsM3<Cfg>::value) {
+        ore[a][b] += acc.re[a][b] - acc.t2[a][b];
+        oim[a][b] += acc.im[a][b] - acc.re[a][b] - acc.t2[a][b];
+      } else {
+        ore[a][b] += acc.re[a][b];
+        oim[a][b] += acc.im[a][b];
+      }
+    }
+}
+
+// Visit the elements of an outer accumulator pair: f(row, col, re, im).
+template <class Cfg, class F>
+__device__ __forceinline__ void acc_foreach_outer(
+    const typename Acc<typename Cfg::T>::type (&ore)[Cfg::MB][Cfg::NB],
+    const typename Acc<typename Cfg::T>::type (&oim)[Cfg::MB][Cfg::NB], F&& f) {
+  int row, col;
+#pragma unroll
+  for (int a = 0; a < Cfg::MB; ++a)
+#pragma unroll
+    for (int b = 0; b < Cfg::NB; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        acc_coord<Cfg>(a, b, r, &row, &col);
+        f(row, col, ore[a][b][r], oim[a][b][r]);
+      }
+}
+
 // The same walk with writable accumulator entries (used to start a tile from
 // existing output values).
 template <class Cfg, class F>

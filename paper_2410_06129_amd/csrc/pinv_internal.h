@@ -73,10 +73,12 @@ template <typename T>
 hipError_t launch_trmm_w(const EncDev<T>& e, const T* Li, T* W, bool m3, hipStream_t s);
 template <typename T, typename TO>
 hipError_t launch_trmm_r(const T* Li, const T* W, TO* R, int N, int M, bool m3, hipStream_t s);
+// seg: the FP32 contraction in segments folded into a second accumulator set
+// (plans whose R is formed in FP64).
 template <typename T>
-hipError_t launch_apply(const ApplyBatch& b, bool m3, Scratch& sc, hipStream_t s);
+hipError_t launch_apply(const ApplyBatch& b, bool m3, bool seg, Scratch& sc, hipStream_t s);
 // Scratch bytes launch_apply needs for one item of F frames (split partials).
-template <typename T> size_t apply_scratch_bytes(int F, int N, int M, bool m3);
+template <typename T> size_t apply_scratch_bytes(int F, int N, int M, bool m3, bool seg);
 // Fewer samples than unknowns: the samples' Gram E E^H (FP64, M x M), and
 // R = (L'^-H L'^-1 E)^H from the inverse factor L'^-1 (W, Z: M x N workspaces).
 hipError_t launch_gram_rows(const EncDev<double>& e, double* G, hipStream_t s);

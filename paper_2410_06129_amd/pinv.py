@@ -319,8 +319,9 @@ def pinv_srf(ctx: int, plan: int, out, mode: int = METRIC_DIAG, stream=None) -> 
     full matrix (METRIC_FULL, out [N, N]); complex, in the plan's precision."""
     info = pinv_plan_info_get(plan)
     N = info["N"]
-    shape = (N,) if mode == METRIC_DIAG else (N, N)
-    check_tensor("pinv_srf", "out", out, shape, _complex_dtype(info["prec"]), _ctx_device.get(ctx))
+    if mode in (METRIC_DIAG, METRIC_FULL):   # other modes: the library reports INVALID
+        shape = (N,) if mode == METRIC_DIAG else (N, N)
+        check_tensor("pinv_srf", "out", out, shape, _complex_dtype(info["prec"]), _ctx_device.get(ctx))
     _check(_lib.pinv_srf(ctx, plan, mode, out.data_ptr(), _stream_ptr(stream)), "pinv_srf")
 
 
@@ -333,7 +334,7 @@ def pinv_noise(ctx: int, plan: int, out, coil_cov=None, mode: int = METRIC_DIAG,
     N = info["N"]
     if mode == METRIC_DIAG:
         check_tensor("pinv_noise", "out", out, (N,), _real_dtype(info["prec"]), _ctx_device.get(ctx))
-    else:
+    elif mode == METRIC_FULL:
         check_tensor("pinv_noise", "out", out, (N, N), _complex_dtype(info["prec"]),
                      _ctx_device.get(ctx))
     cov = None

@@ -575,7 +575,7 @@ def test_r_formed_in_fp64_matches_oracle(P, ctx, name):
         d = to_dev(o["d"], np.complex64)
         x = torch.empty((d.shape[0], N), dtype=torch.complex64, device="cuda")
         P.pinv_apply(ctx, plan, d, x)
-        d40 = to_dev(np.tile(o["d"], (8, 1))[:40], np.complex64)
+        d40 = to_dev(np.tile(o["d"], (14, 1))[:40], np.complex64)
         x40 = torch.empty((40, N), dtype=torch.complex64, device="cuda")
         P.pinv_apply(ctx, plan, d40, x40)
         torch.cuda.synchronize()
@@ -583,7 +583,7 @@ def test_r_formed_in_fp64_matches_oracle(P, ctx, name):
         P.pinv_plan_release(plan)
     eR = max_rel_entry(R.cpu().numpy().astype(np.complex128), o["R"])
     e = frame_rel(x.cpu().numpy().astype(np.complex128), o["x"]).max()
-    e40 = frame_rel(x40.cpu().numpy().astype(np.complex128), np.tile(o["x"], (8, 1))[:40]).max()
+    e40 = frame_rel(x40.cpu().numpy().astype(np.complex128), np.tile(o["x"], (14, 1))[:40]).max()
     print(f"{name}: R entry err {eR:.2e} image err {e:.2e} / {e40:.2e} (kappa {o['kappa']:.3g})")
     assert eR <= 2.0 ** -23
     assert e < 1e-5 and e40 < 1e-5
