@@ -249,6 +249,28 @@ pinv_status pinv_apply(pinv_context *ctx, const pinv_plan *p, const void *data, 
 pinv_status pinv_apply_grouped(pinv_context *ctx, int32_t n, const pinv_apply_item *items,
                                int32_t refine_steps, void *hip_stream);
 
+/* ------------------------------------------------------------------------
+ * Apply without allocation.  For callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.
+ * ------------------------------------------------------------------------ */
+#define PINV_NOALLOC_SCRATCH_BYTES (512ull << 20)
+
+/* pinv_apply (same arguments, same results bit for bit) with every scratch
+ * buffer it uses (split-contraction partials, refinement vectors and
+ * residuals, factor-only intermediates) taken from a fixed device region of
+ * PINV_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on
+ * until the process ends; the call makes no hipMalloc, hipFree or other
+ * allocating call.  Every call on a GPU shares that GPU's region, which keeps
+ * the last call's contents (nothing in it needs to start at zero): calls that
+ * overlap on one GPU (on different streams or threads) race, and the caller
+ * must serialise them.  Work enqueued here is not tracked by the plan: it must
+ * have completed before the plan is released.  Errors: as pinv_apply, and
+ * INVALID for an apply that needs more scratch than the region holds (the
+ * message gives the bytes; pinv_apply, or fewer frames per call, serves it). */
+pinv_status pinv_apply_noalloc(pinv_context *ctx, const pinv_plan *p, const void *data, int64_t F,
+                               void *image, int32_t refine_steps, void *hip_stream);
+
 /* Shapes of the image-quality metrics. */
 typedef enum { PINV_METRIC_DIAG = 0, PINV_METRIC_FULL = 1 } pinv_metric_mode;
 

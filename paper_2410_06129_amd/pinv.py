@@ -102,6 +102,7 @@ _sigs = {
     "pinv_plan_wait": [_vp],
     "pinv_apply": [_vp, _vp, _vp, ctypes.c_int64, _vp, ctypes.c_int32, _vp],
     "pinv_apply_grouped": [_vp, ctypes.c_int32, ctypes.POINTER(pinv_apply_item), ctypes.c_int32, _vp],
+    "pinv_apply_noalloc": [_vp, _vp, _vp, ctypes.c_int64, _vp, ctypes.c_int32, _vp],
     "pinv_forward": [_vp, _vp, _vp, ctypes.c_int64, _vp, _vp],
     "pinv_srf": [_vp, _vp, ctypes.c_int32, _vp, _vp],
     "pinv_noise": [_vp, _vp, _vp, ctypes.c_int32, _vp, _vp],
@@ -287,6 +288,15 @@ def pinv_apply(ctx: int, plan: int, data, image, refine_steps: int = 0, stream=N
     F = check_frames("pinv_apply", pinv_plan_info_get(plan), data, image, _ctx_device.get(ctx))
     _check(_lib.pinv_apply(ctx, plan, data.data_ptr(), F, image.data_ptr(), refine_steps,
                            _stream_ptr(stream)), "pinv_apply")
+
+
+def pinv_apply_noalloc(ctx: int, plan: int, data, image, refine_steps: int = 0, stream=None) -> None:
+    """pinv_apply with its scratch from the library's fixed per-GPU region (no
+    device allocation); calls on one GPU must not overlap."""
+    F = check_frames("pinv_apply_noalloc", pinv_plan_info_get(plan), data, image,
+                     _ctx_device.get(ctx))
+    _check(_lib.pinv_apply_noalloc(ctx, plan, data.data_ptr(), F, image.data_ptr(), refine_steps,
+                                   _stream_ptr(stream)), "pinv_apply_noalloc")
 
 
 def pinv_apply_grouped(ctx: int, items: Sequence[tuple], refine_steps: int = 0, stream=None) -> None:
