@@ -156,8 +156,10 @@ def measured_traffic(kernel: str, workload: str):
             "source": "profiles/pmc_traffic.json"}
 
 
-PMC_KERNELS = {"trmm_w": "k_trmm_w<pinv::TileCfg<float", "trmm_r": "k_trmm_r<pinv::TileCfg<float",
-               "apply": "k_apply<pinv::TileCfg<float"}
+# the FP32 plan's kernels (3M, 128x64 tiles), by their template signature
+PMC_KERNELS = {"trmm_w": "k_trmm_w<pinv::TileCfg<float, 128, 64, 8, true>,",
+               "trmm_r": "k_trmm_r<pinv::TileCfg<float, 128, 64, 8, true>, float>",
+               "apply": "k_apply<pinv::TileCfg<float, 128, 64, 8, true>, false>"}
 
 
 def algorithmic_bytes(N: int, M: int, F: int) -> dict:
@@ -621,9 +623,10 @@ def build_only(args) -> dict:
 
 def pmc_run(args) -> None:
     """A short run for counter collection: a plain 2 GiB device copy (the
-    counters' scale), then one FP32 build and one apply of `frames` frames with
-    one refinement step at the default workload (random data: the counters do
-    not depend on values)."""
+    counters' scale), then at the default workload one FP32 build and one
+    apply of `frames` frames with one refinement step, one BF16-split build
+    and apply, and one build and apply of an FP32 plan with R formed in FP64
+    (random data: the counters do not depend on values)."""
     import torch
     from paper_2410_06129_amd import pinv as P
     from paper_2410_06129_amd import synth
@@ -639,12 +642,15 @@ def pmc_run(args) -> None:
     g = torch.Generator(device=dev).manual_seed(5)
     d = torch.randn((args.frames, enc.M), dtype=torch.complex64, device=dev, generator=g)
     x = torch.empty((args.frames, enc.N), dtype=torch.complex64, device=dev)
-    p = P.pinv_build(ctx, enc, w.rel_lambda, P.LAMBDA_REL_MEAN_DIAG, P.FP32, P.FLAG_UNCACHED)
-    P.pinv_apply(ctx, p, d, x, refine_steps=1)
-    torch.cuda.synchronize()
-    P.pinv_plan_wait(p)
-    log(f"pmc run: stage ms {P.pinv_plan_info_get(p)['stage_ms']}")
-    P.pinv_plan_release(p)
+    for name, prec, flags, refine in (("fp32", P.FP32, 0, 1), ("bf16x3", P.BF16X3, 0, 0),
+                                      ("fp32_r_fp64", P.FP32, P.FLAG_R_FP64, 0)):
+        p = P.pinv_build(ctx, enc, w.rel_lambda, P.LAMBDA_REL_MEAN_DIAG, prec, flags | P.FLAG_UNCACHED)
+        P.pinv_apply(ctx, p, d, x, refine_steps=refine)
+        torch.cuda.synchronize()
+        P.pinv_plan_wait(p)
+        log(f"pmc run {name}: stage ms {P.pinv_plan_info_get(p)['stage_ms']}")
+        P.pinv_plan_release(p)
+        P.pinv_context_trim(ctx)
     P.pinv_context_destroy(ctx)
     print(json.dumps({"pmc_run": "done"}), flush=True)
 

@@ -14,8 +14,9 @@ namespace pinv {
 // alone and in any group); its splits write partial tiles to item.work and
 // k_apply_reduce adds them in split order.
 //
-// Tiles run frame-tile fastest, so the F/BM tiles that read one BN-row panel
-// of R are resident together and the panel streams from HBM about once.
+// Tiles run frame-tile fastest and each XCD takes a contiguous range of them,
+// so the F/BM tiles that read one BN-row panel of R are resident together on
+// one XCD and share its L2.
 //
 // SEG: the contraction runs in segments of kApplySegRows rows; each segment's
 // accumulators are folded into a second FP32 accumulator set.  A running FP32
@@ -29,7 +30,7 @@ __global__ __launch_bounds__(256) void k_apply(const ApplyBatch batch) {
   typedef typename Cfg::T T;
   // locate the item owning this tile (items carry exclusive tile prefix sums)
   int lo = 0, hi = batch.n - 1;
-  const int t = blockIdx.x;
+  const int t = xcd_contiguous(blockIdx.x, gridDim.x);
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if (batch.it[mid].tile0 <= t) lo = mid; else hi = mid - 1;

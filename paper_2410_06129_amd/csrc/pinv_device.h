@@ -214,7 +214,10 @@ template <class Cfg, class = void> struct IsB3;
 // -> 16.78 ms, R 16.34 -> 16.06 ms at N = 4096, M = 32768).  The Cholesky's
 // short panel and trailing launches keep the default: raised, they delayed
 // the diagonal-block kernel beside them (7.48 -> 7.84 ms).
-template <class Cfg, bool PRIO = true, class LA, class LB>
+// DOWN: visit the chunks from the top of [kbeg, kend) down (chunk starts
+// kbeg + (nch-1)*BK, ..., kbeg; the loaders still zero-fill k >= kend), so
+// tiles whose ranges share their upper end read the same rows at the same time.
+template <class Cfg, bool PRIO = true, bool DOWN = false, class LA, class LB>
 __device__ __forceinline__ void mainloop(LA& la, LB& lb, int kbeg, int kend, AccTile<Cfg>& acc,
                                          typename Cfg::T* smem) {
   if constexpr (IsB3<Cfg>::value) {
@@ -233,8 +236,9 @@ __device__ __forceinline__ void mainloop(LA& la, LB& lb, int kbeg, int kend, Acc
     if (kend <= kbeg) return;
   }
   const int nch = max(1, (kend - kbeg + Cfg::BK - 1) / Cfg::BK);
-  la.fetch(kbeg, kend);
-  lb.fetch(kbeg, kend);
+  auto chunk = [&](int c) { return DOWN ? kbeg + (nch - 1 - c) * Cfg::BK : kbeg + c * Cfg::BK; };
+  la.fetch(chunk(0), kend);
+  lb.fetch(chunk(0), kend);
 #pragma unroll
   for (int q = 0; q < STEPS; ++q) {
     la.finish(q, STEPS);
@@ -249,8 +253,8 @@ __device__ __forceinline__ void mainloop(LA& la, LB& lb, int kbeg, int kend, Acc
     T* nxt = (c & 1) ? stage0 : stage1;
     const bool more = c + 1 < nch;
     if (more) {
-      la.fetch(kbeg + (c + 1) * Cfg::BK, kend);
-      lb.fetch(kbeg + (c + 1) * Cfg::BK, kend);
+      la.fetch(chunk(c + 1), kend);
+      lb.fetch(chunk(c + 1), kend);
     }
     if constexpr (PRIO) __builtin_amdgcn_s_setprio(1);
     tile_compute<Cfg>(cur, cur + Cfg::PLANES * Cfg::A_PLANE, acc, [&](int kk) {

@@ -134,6 +134,31 @@ __device__ __forceinline__ typename Cfg::T* smem_base() {
   return reinterpret_cast<typename Cfg::T*>(smem_raw);
 }
 
+// Workgroup t of a grid of T runs on XCD t % 8: the dispatcher deals
+// workgroups round-robin over the eight XCDs, each with its own L2.  This
+// renumbering gives every XCD a contiguous range of logical tiles (a
+// bijection of [0, T)), so tiles that are adjacent in logical order, and
+// share operands, run on one XCD and hit one L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_contiguous(int t, int T) {
+  const int x = t % kXcds, l = t / kXcds;
+  const int per = T / kXcds, rem = T % kXcds;
+  return x * per + min(x, rem) + l;
+}
+
+// Logical tile u of an nbi x nbj grid in column groups of GJ: within a group
+// the GJ columns of one row come together, rows in the order `row_of` gives
+// (so a block of resident tiles spans a few rows and GJ columns: each
+// column's operand is shared by the rows, each row's by the columns).
+template <int GJ>
+__device__ __forceinline__ void grouped_tile(int u, int nbi, int nbj, int* r, int* col) {
+  const int g = u / (nbi * GJ);
+  const int gw = min(GJ, nbj - g * GJ);
+  const int local = u - g * nbi * GJ;
+  *r = local / gw;
+  *col = g * GJ + local % gw;
+}
+
 // Lower-triangular tile index -> (bi, bj), bi >= bj.
 __device__ __forceinline__ void tri_index(int t, int* bi, int* bj) {
   int i = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);

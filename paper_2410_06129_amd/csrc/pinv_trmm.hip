@@ -16,8 +16,12 @@ __global__ __launch_bounds__(256) void k_trmm_w(EncDev<typename Cfg::T> e,
   typedef typename Cfg::T T;
   const int N = e.N, M = e.M;
   const int nbi = (N + Cfg::BM - 1) / Cfg::BM, nbj = (M + Cfg::BN - 1) / Cfg::BN;
-  const int t = blockIdx.x;
-  const int bi = nbi - 1 - t / nbj, bj = t % nbj;   // longest K ranges first
+  // each XCD runs column groups of 8 sample blocks over every row block
+  // (longest K ranges first): its resident tiles share the E tables of 8
+  // sample blocks and the L^-1 rows of a few row blocks
+  int r, bj;
+  grouped_tile<8>(xcd_contiguous(blockIdx.x, nbi * nbj), nbi, nbj, &r, &bj);
+  const int bi = nbi - 1 - r;
   LoadDenseKC<Cfg, Cfg::BM, Cfg::LDA, T, false> la;
   la.p = reinterpret_cast<const cx<T>*>(Li);
   la.ld = N;
@@ -97,9 +101,14 @@ __global__ __launch_bounds__(256) void k_trmm_r(const typename Cfg::T* __restric
                                                 const typename Cfg::T* __restrict__ W,
                                                 TO* __restrict__ R, int N, int M) {
   typedef typename Cfg::T T;
-  const int nbj = (M + Cfg::BN - 1) / Cfg::BN;
-  const int t = blockIdx.x;
-  const int bi = t / nbj, bj = t % nbj;               // longest K ranges first
+  const int nbi = (N + Cfg::BM - 1) / Cfg::BM, nbj = (M + Cfg::BN - 1) / Cfg::BN;
+  // each XCD runs column groups of 8 W panels over every row block (longest K
+  // ranges first), and the contraction runs from n = N down: every tile's
+  // range ends at N, so the resident tiles of several row blocks read the
+  // same W rows at the same time, and those of one row block the same L^-1
+  // rows
+  int bi, bj;
+  grouped_tile<8>(xcd_contiguous(blockIdx.x, nbi * nbj), nbi, nbj, &bi, &bj);
   LoadDenseOC<Cfg, Cfg::BM, Cfg::LDA, T, true> la;    // conj(Li[n][i]), i contiguous
   la.p = reinterpret_cast<const cx<T>*>(Li);
   la.ld = N;
@@ -112,7 +121,7 @@ __global__ __launch_bounds__(256) void k_trmm_r(const typename Cfg::T* __restric
   lb.oend = M;
   AccTile<Cfg> acc;
   acc.zero();
-  mainloop<Cfg>(la, lb, bi * Cfg::BM, N, acc, smem_base<Cfg>());
+  mainloop<Cfg, true, true>(la, lb, bi * Cfg::BM, N, acc, smem_base<Cfg>());
   cx<TO>* O = reinterpret_cast<cx<TO>*>(R);
   const int r0 = bi * Cfg::BM, c0 = bj * Cfg::BN;
   acc_foreach<Cfg>(acc, [&](int r, int c, T re, T im) {
