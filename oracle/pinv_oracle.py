@@ -17,6 +17,12 @@ and, for fewer samples than unknowns, the right pseudoinverse (Sec. 2.2)
 
     R   = E^H (E E^H + lam I)^-1     (RightBuild; minimum-norm solution at lam = 0)
 
+and the eigenvalue route with truncation (Eq. 7, Eq. 4)
+
+    E^H E = P Lambda P^H,  R = P_r diag(1/(mu_j + lam)) P_r^H E^H  (EigenBuild)
+
+where P_r holds the eigenvectors of the r eigenvalues a truncation keeps.
+
 The encoding element (paper Eq. 2 and the generalised product form of Sec. 3.3,
 with the sign convention exp(-i 2 pi ...) used throughout this project):
 
@@ -33,7 +39,8 @@ tests/test_oracle_pins.py (Cartesian inverse DFT, DFT special cases for the
 species and off-resonance factors, SVD filter factors, Moore-Penrose
 conditions, conjugate-phase limit, closed-form diagonal, coil-sum identity,
 normal-equation residual, push-through identity, eigen route, SRF identity,
-noise matrix for white and coil-correlated noise).
+noise matrix for white and coil-correlated noise, the truncated eigenvalue
+route against numpy's SVD of E, voxel masks, the Gram's offset structure).
 """
 from __future__ import annotations
 
@@ -327,6 +334,59 @@ class RightBuild:
         """Images x = E^H (E E^H + lam I)^-1 d for frames d [F, M] -> [F, N]."""
         y = solve_normal(self.L, np.atleast_2d(d).T)   # [M, F]
         return adjoint(self.enc, y.T)
+
+
+# ----------------------------------------------------------------------------
+# the eigenvalue route with truncation  (Eq. 7; truncated SVD, Eq. 4)
+# ----------------------------------------------------------------------------
+
+def kept_count(mu: np.ndarray, mode: str, value: float = None) -> int:
+    """How many of the eigenvalues mu of E^H E, sorted descending, a truncation
+    keeps (Sec. 2.1, Sec. 2.2):
+      'none'    all of them;
+      'kappa'   those whose singular value sigma_j = sqrt(mu_j) is within a
+                condition number `value` of the largest: sigma_1 / sigma_j <= value;
+      'energy'  the fewest largest ones whose sum reaches the fraction `value`
+                of the total sum (the energy of E, sum of sigma_j^2)."""
+    mu = np.asarray(mu, dtype=np.float64)
+    if mode == "none":
+        return len(mu)
+    if mode == "kappa":
+        return int(np.sum(mu * value * value >= mu[0]))
+    if mode == "energy":
+        c = np.cumsum(mu)
+        return int(np.searchsorted(c, value * c[-1], side="left") + 1)
+    raise ValueError(mode)
+
+
+class EigenBuild:
+    """Eq. 7: the Gram's eigendecomposition E^H E = P Lambda P^H (library eigh,
+    FP64), then R = P_r diag(f) P_r^H E^H over the r eigenvalues the
+    truncation keeps (largest first), with f_j = 1 / (mu_j + lam): truncation
+    alone (lam = 0) is the truncated SVD of Eq. 4, the shift alone is Tikhonov
+    regularisation, and both can be combined."""
+
+    def __init__(self, enc, lam: float = 0.0, rel: float = None, mode: str = "none",
+                 value: float = None, G: np.ndarray = None):
+        self.enc = enc
+        self.G = gram(enc) if G is None else G
+        self.lam = lambda_abs(self.G, rel) if rel is not None else float(lam)
+        mu, P = np.linalg.eigh(self.G)
+        order = np.argsort(-mu, kind="stable")
+        self.mu = mu[order]
+        self.P = P[:, order]
+        self.rank = kept_count(self.mu, mode, value)
+        self.f = 1.0 / (self.mu[:self.rank] + self.lam)
+
+    def recon_matrix(self) -> np.ndarray:
+        Pr = self.P[:, :self.rank]
+        Eh = encoding_matrix(self.enc).conj().T
+        return (Pr * self.f) @ (Pr.conj().T @ Eh)
+
+    def reconstruct(self, d: np.ndarray) -> np.ndarray:
+        Pr = self.P[:, :self.rank]
+        b = adjoint(self.enc, d)                  # [F, N]
+        return ((b @ Pr.conj()) * self.f) @ Pr.T
 
 
 # ----------------------------------------------------------------------------

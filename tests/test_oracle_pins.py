@@ -529,3 +529,69 @@ def test_gram_is_psf_of_voxel_offsets():
                                            + (f[sb] - f[sa]) * t)))
         Sab = np.sum(enc.coil[:, va].conj() * enc.coil[:, vb])
         assert abs(G[a, b] - Sab * P) <= 1e-12 * abs(G).max()
+
+
+# --- the eigenvalue route with truncation (Eq. 7; truncated SVD, Eq. 4) ---------
+
+def test_kept_count_hand_computed():
+    mu = np.array([16.0, 9.0, 4.0, 1.0, 0.25])          # sigma = 4, 3, 2, 1, 0.5
+    assert oracle.kept_count(mu, "none") == 5
+    # condition number of the kept set: sigma_1 / sigma_j <= kappa
+    assert oracle.kept_count(mu, "kappa", 2.0) == 3       # 4/2 = 2 kept, 4/1 = 4 not
+    assert oracle.kept_count(mu, "kappa", 3.99) == 3
+    assert oracle.kept_count(mu, "kappa", 4.0) == 4
+    assert oracle.kept_count(mu, "kappa", 1.0) == 1
+    # energy: sum mu = 30.25; 16 + 9 = 25 (82.6%), + 4 = 29 (95.9%), + 1 = 30 (99.2%)
+    assert oracle.kept_count(mu, "energy", 0.80) == 2
+    assert oracle.kept_count(mu, "energy", 25.0 / 30.25) == 2
+    assert oracle.kept_count(mu, "energy", 0.95) == 3
+    assert oracle.kept_count(mu, "energy", 0.99) == 4
+    assert oracle.kept_count(mu, "energy", 1.0) == 5
+
+
+@pytest.mark.parametrize("mode,value", [("kappa", 20.0), ("energy", 0.95), ("none", None)])
+def test_eigen_route_truncation_equals_truncated_svd(mode, value):
+    """Eq. 4: truncating the SVD of E keeps the same singular vectors the
+    Gram's eigendecomposition gives (mu = sigma^2), so with lam = 0,
+    P_r diag(1/mu) P_r^H E^H = V_r Sigma_r^-1 U_r^H, computed here from
+    numpy's SVD of the explicit E, a route that never forms E^H E."""
+    enc = tiny_enc(seed=21, nx=6, ny=5, C=3, K=50)
+    E = oracle.encoding_matrix(enc)
+    U, sv, Vh = np.linalg.svd(E, full_matrices=False)
+    if mode == "kappa":
+        r = int(np.sum(sv[0] / sv <= value))
+    elif mode == "energy":
+        c = np.cumsum(sv ** 2)
+        r = int(np.argmax(c >= value * c[-1]) + 1)
+    else:
+        r = len(sv)
+    assert 1 < r <= len(sv)
+    R_svd = (Vh[:r].conj().T / sv[:r]) @ U[:, :r].conj().T
+    b = oracle.EigenBuild(enc, lam=0.0, mode=mode, value=value)
+    assert b.rank == r
+    assert np.allclose(b.mu, sv ** 2, rtol=1e-10, atol=1e-10 * sv[0] ** 2)
+    kappa = sv[0] / sv[r - 1]
+    assert rel(b.recon_matrix(), R_svd) < 1e-12 * kappa ** 2
+    d = synth.unit_complex_noise((2, enc.M), np.random.default_rng(4))
+    assert rel(b.reconstruct(d), d @ R_svd.T) < 1e-12 * kappa ** 2
+
+
+def test_eigen_route_without_truncation_equals_cholesky():
+    """Eq. 7 with only the shift: the same R as the Cholesky route (Eq. 8)."""
+    enc = tiny_enc(seed=22, nx=5, ny=6, C=2, K=60, species=[0.0, 80.0], b0=True)
+    e = oracle.EigenBuild(enc, rel=1e-2)
+    c = oracle.Build(enc, rel=1e-2)
+    assert e.lam == c.lam and e.rank == enc.N
+    assert rel(e.recon_matrix(), c.recon_matrix()) < 1e-11
+
+
+def test_eigen_route_cartesian_closed_form():
+    """Fully sampled Cartesian: every eigenvalue of E^H E is N, so any kappa
+    keeps them all and R = E^H / (N + lam) (P1)."""
+    n, lam = 6, 1.5
+    enc = cartesian_enc(n)
+    b = oracle.EigenBuild(enc, lam=lam, mode="kappa", value=1.0 + 1e-9)
+    assert b.rank == n * n
+    assert np.max(np.abs(b.mu - n * n)) < 1e-12 * n * n
+    Eh = oracle.encoding_matrix(enc).conj().T
+    assert rel(b.recon_matrix(), Eh / (n * n + lam)) < 1e-13
