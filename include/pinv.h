@@ -139,6 +139,30 @@ typedef enum {
                             written): 4 M N^2 flops; the only form for an FP32 Gram */
 } pinv_gram_form;
 
+/* How R is formed from the Gram. */
+typedef enum {
+  PINV_ROUTE_CHOLESKY = 0,  /* G + lambda I = L L^H, R = L^-H L^-1 E^H (Eq. 8) */
+  PINV_ROUTE_EIGEN = 1      /* E^H E = P Lambda P^H (Eq. 7), R = P_r diag(1/(mu_j + lambda))
+                               P_r^H E^H over the eigenvalues mu_j the truncation keeps: with
+                               lambda = 0 the truncated SVD of Eq. 4, with no truncation the
+                               Tikhonov R of the Cholesky route, or both combined (Sec. 2.2).
+                               The FP64 eigendecomposition is a parallel cyclic Jacobi method
+                               on the GPU; pinv_build then blocks until it has converged.
+                               PINV_FP64 and PINV_FP32 plans with M >= N; no refinement, no
+                               PINV_FLAG_NO_R. */
+} pinv_route;
+
+/* Truncation of the eigenvalue route (Sec. 2.1: singular values below a
+ * threshold are dropped; the ratio of the largest to the smallest kept one is
+ * the condition number kappa, and a threshold may instead keep a fraction of
+ * the energy).  mu_j are the eigenvalues of E^H E (sigma_j^2), largest first. */
+typedef enum {
+  PINV_TRUNC_NONE = 0,     /* keep all */
+  PINV_TRUNC_KAPPA = 1,    /* keep sigma_j with sigma_1 / sigma_j <= trunc_value (>= 1) */
+  PINV_TRUNC_ENERGY = 2    /* keep the fewest largest mu_j whose sum reaches trunc_value
+                              (in (0, 1]) of sum mu_j */
+} pinv_trunc;
+
 typedef struct {
   double lambda;              /* >= 0; meaning set by lambda_mode */
   int32_t lambda_mode;        /* pinv_lambda_mode */
@@ -150,6 +174,9 @@ typedef struct {
                                  in registers, one column per lane of a 64-wide wavefront,
                                  and the panel and trailing tiles are 64 x 64 */
   int32_t gram;               /* pinv_gram_form */
+  int32_t route;              /* pinv_route */
+  int32_t trunc;              /* pinv_trunc (PINV_ROUTE_EIGEN only) */
+  double trunc_value;         /* kappa or energy fraction, as pinv_trunc says */
 } pinv_build_opts;
 
 typedef struct {
@@ -170,6 +197,11 @@ typedef struct {
   int64_t nk;                 /* samples per coil */
   int32_t gram_form;          /* the Gram form used (PSF, SHARED or FULL; SHARED for M < N) */
   int32_t r_fp64;             /* 1 if R was formed in FP64 (PINV_FLAG_R_FP64) */
+  int32_t route;              /* pinv_route */
+  int32_t rank;               /* eigenvalues kept by the eigenvalue route (N otherwise; valid
+                                 when ready) */
+  int32_t sweeps;             /* Jacobi sweeps the eigenvalue route took (0 otherwise) */
+  int32_t reserved;           /* 0 */
 } pinv_plan_info;
 
 typedef struct {
@@ -207,6 +239,9 @@ pinv_status pinv_context_destroy(pinv_context *ctx);
  * is not enough, NOMEM.  Errors: INVALID (bad encoding, lambda < 0, flag
  * combinations above), UNSUPPORTED (BF16X3 with M < N), NOMEM, DEVICE.  A
  * non-positive-definite shifted Gram is reported by pinv_plan_wait as NOT_PD. */
+/* With PINV_ROUTE_EIGEN the second stage time is the eigendecomposition, the
+ * truncation and Q^H = diag(1/sqrt(mu_j + lambda)) P_r^H; the third and fourth
+ * are W = Q^H E^H and R = Q W (dense factors, rank rows). */
 pinv_status pinv_build(pinv_context *ctx, const pinv_encoding *e, const pinv_build_opts *o,
                        void *hip_stream, pinv_plan **out);
 
@@ -307,6 +342,12 @@ pinv_status pinv_noise(pinv_context *ctx, const pinv_plan *p, const double *coil
  * on `hip_stream` behind the upload of the plan's tables. */
 pinv_status pinv_forward(pinv_context *ctx, const pinv_plan *p, const void *image, int64_t F,
                          void *data, void *hip_stream);
+
+/* Eigenvalues of E^H E (the squared singular values of E, Sec. 2.1) of a
+ * plan built with PINV_ROUTE_EIGEN, largest first: out is device [N] double,
+ * caller-owned; ordered on hip_stream after the build.  Errors: INVALID (NULL,
+ * a plan of another route). */
+pinv_status pinv_spectrum(pinv_context *ctx, const pinv_plan *p, double *out, void *hip_stream);
 
 /* Plan metadata; stage_ms are filled once the plan is ready. */
 pinv_status pinv_plan_info_get(const pinv_plan *p, pinv_plan_info *out);

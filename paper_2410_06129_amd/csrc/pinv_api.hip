@@ -62,6 +62,10 @@ struct pinv_plan {
   bool m3 = true;            // W, R and apply with three real products per complex product
   int gram_form = PINV_GRAM_SHARED;   // how the Gram was formed
   bool r_fp64 = false;       // FP32 plan whose W and R were formed in FP64
+  int route = PINV_ROUTE_CHOLESKY;
+  int rank = 0;              // eigenvalues kept (eigenvalue route; N otherwise)
+  int sweeps = 0;            // Jacobi sweeps (eigenvalue route)
+  void* spec = nullptr;      // eigenvalues of E^H E, largest first (eigenvalue route)
   int* info = nullptr;
   bool pooled = false;             // device buffers from the context's plan pool
   size_t bytes = 0;
@@ -182,7 +186,8 @@ pinv_status validate(const pinv_encoding* e, Dims* d) {
   return PINV_OK;
 }
 
-uint64_t plan_key(const pinv_encoding* e, const Dims& d, double lam, int prec, int form_bits) {
+uint64_t plan_key(const pinv_encoding* e, const Dims& d, double lam, int prec, int form_bits,
+                  double trunc_value) {
   Fnv f;
   f.add(d.nx);
   f.add(d.ny);
@@ -203,6 +208,7 @@ uint64_t plan_key(const pinv_encoding* e, const Dims& d, double lam, int prec, i
   f.add(lam);
   f.add(prec);
   f.add(form_bits);
+  f.add(trunc_value);
   return f.h;
 }
 
@@ -349,7 +355,7 @@ hipError_t note_use(const pinv_plan* pc, hipStream_t s) {
 // (no plan pool) are freed after the device has finished with them.
 void free_plan_memory(pinv_plan* p) {
   pinv_context* c = p->ctx;
-  void* const bufs[] = {p->tab32, p->tab64, p->R, p->Linv, p->gram, (void*)p->info};
+  void* const bufs[] = {p->tab32, p->tab64, p->R, p->Linv, p->gram, (void*)p->info, p->spec};
   if (p->pooled) {
     pinv_context::PendingFree f;
     for (void* q : bufs)
@@ -404,7 +410,12 @@ struct BuildForm {
   int gram = PINV_GRAM_SHARED;
   bool r_fp64 = false;
   bool no_r = false;
+  int route = PINV_ROUTE_CHOLESKY;
+  int trunc = PINV_TRUNC_NONE;
+  double trunc_value = 0.0;
 };
+
+constexpr int kMaxJacobiSweeps = 40;
 
 // Device bytes a build needs at its peak: plan buffers plus build workspaces.
 size_t plan_footprint(const Dims& d, int prec, const BuildForm& f) {
@@ -423,6 +434,8 @@ size_t plan_footprint(const Dims& d, int prec, const BuildForm& f) {
     b += cs * N * M;            // R
   }
   b += 16 * Gd * Gd;            // the Gram kept
+  if (f.route == PINV_ROUTE_EIGEN)
+    b += 3 * 16 * N * N + eig_work_bytes((int)N) + 8 * N;   // Jacobi copies, eigenvalues
   if (f.gram == PINV_GRAM_PSF) {
     EncDev<double> e{};
     e.nx = d.nx;
@@ -439,7 +452,7 @@ size_t plan_resident(const Dims& d, int prec, bool no_r) {
   const size_t N = d.N, M = d.M;
   const size_t Gd = d.M < d.N ? M : N;
   const size_t cs = prec == PINV_FP64 ? 16 : 8;
-  return (no_r ? 0 : cs * N * M) + cs * Gd * Gd + 16 * Gd * Gd + (16ull << 20);
+  return (no_r ? 0 : cs * N * M) + cs * Gd * Gd + 16 * Gd * Gd + 8 * Gd + (16ull << 20);
 }
 
 // Evict LRU plans held only by the cache until `need` bytes fit.  ctx->mu held.
@@ -682,6 +695,23 @@ static pinv_status check_build(const pinv_encoding* e, const pinv_build_opts* o,
   }
   const bool no_r = (o->flags & PINV_FLAG_NO_R) != 0;
   const bool r_fp64 = (o->flags & PINV_FLAG_R_FP64) != 0;
+  if (o->route != PINV_ROUTE_CHOLESKY && o->route != PINV_ROUTE_EIGEN)
+    return fail(PINV_ERR_INVALID, "unknown route");
+  if (o->trunc < PINV_TRUNC_NONE || o->trunc > PINV_TRUNC_ENERGY)
+    return fail(PINV_ERR_INVALID, "unknown truncation mode");
+  if (o->route == PINV_ROUTE_CHOLESKY && o->trunc != PINV_TRUNC_NONE)
+    return fail(PINV_ERR_INVALID, "truncation needs PINV_ROUTE_EIGEN");
+  if (o->trunc == PINV_TRUNC_KAPPA && !(o->trunc_value >= 1.0 && isfinite(o->trunc_value)))
+    return fail(PINV_ERR_INVALID, "PINV_TRUNC_KAPPA needs trunc_value >= 1");
+  if (o->trunc == PINV_TRUNC_ENERGY && !(o->trunc_value > 0.0 && o->trunc_value <= 1.0))
+    return fail(PINV_ERR_INVALID, "PINV_TRUNC_ENERGY needs trunc_value in (0, 1]");
+  if (o->route == PINV_ROUTE_EIGEN) {
+    if (o->prec == PINV_BF16X3)
+      return fail(PINV_ERR_UNSUPPORTED, "PINV_ROUTE_EIGEN with PINV_BF16X3");
+    if (no_r) return fail(PINV_ERR_INVALID, "PINV_ROUTE_EIGEN forms R; PINV_FLAG_NO_R refused");
+    if (d->M < d->N)
+      return fail(PINV_ERR_UNSUPPORTED, "PINV_ROUTE_EIGEN needs M >= N (the unknowns' Gram)");
+  }
   int gram = o->gram;
   if (o->flags & PINV_FLAG_GRAM_FULL) {
     if (gram != PINV_GRAM_AUTO && gram != PINV_GRAM_FULL)
@@ -710,6 +740,9 @@ static pinv_status check_build(const pinv_encoding* e, const pinv_build_opts* o,
   form->gram = gram;
   form->no_r = no_r;
   form->r_fp64 = r_fp64;
+  form->route = o->route;
+  form->trunc = o->route == PINV_ROUTE_EIGEN ? o->trunc : PINV_TRUNC_NONE;
+  form->trunc_value = form->trunc == PINV_TRUNC_NONE ? 0.0 : o->trunc_value;
   // AUTO: 3M for the FP32 products; 4M for FP64 products, where 3M saved no
   // time (W at N = 16384: 6.97 s on 3M against 4.74 s on 4M, the FP64 element
   // generation and the third LDS plane outweighing the fewer matrix products)
@@ -717,8 +750,9 @@ static pinv_status check_build(const pinv_encoding* e, const pinv_build_opts* o,
              : o->cprod == PINV_CPROD_4M ? false
                                          : o->prec != PINV_FP64 && !r_fp64;
   *lam_out = lam;
-  const int bits = (form->m3 ? 1 : 0) | (gram << 1) | (r_fp64 ? 16 : 0) | (no_r ? 32 : 0);
-  *key_out = plan_key(e, *d, lam, o->prec, bits);
+  const int bits = (form->m3 ? 1 : 0) | (gram << 1) | (r_fp64 ? 16 : 0) | (no_r ? 32 : 0) |
+                   (form->route << 6) | (form->trunc << 7);
+  *key_out = plan_key(e, *d, lam, o->prec, bits, form->trunc_value);
   return PINV_OK;
 }
 
@@ -846,6 +880,8 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
   p->m3 = form.m3;
   p->gram_form = form.gram;
   p->r_fp64 = form.r_fp64;
+  p->route = form.route;
+  p->rank = (int)d.N;
   auto cleanup = [&](pinv_status rs) {
     (void)hipStreamSynchronize(s);
     free_plan_memory(p);
@@ -906,6 +942,7 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
   if (!no_r) BCHK(plan_malloc(&p->R, cs * N * M, c, s));
   BCHK(plan_malloc(&p->Linv, cs * Gd * Gd, c, s));
   BCHK(plan_malloc(&p->gram, 16 * Gd * Gd, c, s));
+  if (form.route == PINV_ROUTE_EIGEN) BCHK(plan_malloc(&p->spec, 8 * Gd, c, s));
   p->gram_exact = !(form.gram == PINV_GRAM_FULL && !f64);
   BCHK(workspace_alloc(&G, 16 * Gd * Gd, c, s));
   if (f64) {
@@ -937,8 +974,60 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
       BCHK(launch_gram<float>(p->e32, (double*)G, 2048, s));
     BCHK(hipMemcpyAsync(p->gram, G, 16 * Gd * Gd, hipMemcpyDeviceToDevice, s));
     BCHK(launch_herm_fill((double*)p->gram, (int)Gd, s));
+    // the eigendecomposition works on the whole Hermitian matrix
+    if (form.route == PINV_ROUTE_EIGEN) BCHK(launch_herm_fill((double*)G, (int)Gd, s));
   }
   BCHK(hipEventRecord(p->ev[1], s));
+  if (form.route == PINV_ROUTE_EIGEN) {
+    // 2. the Gram's eigendecomposition (Jacobi, FP64; synchronous), the
+    // truncation, and Q^H = diag(1/sqrt(mu_j + lam)) P_r^H into L64
+    void *A2 = nullptr, *V = nullptr, *V2 = nullptr, *EW = nullptr;
+    auto eig = [&]() -> hipError_t {
+      hipError_t r = workspace_alloc(&A2, 16 * N * N, c, s);
+      if (r == hipSuccess) r = workspace_alloc(&V, 16 * N * N, c, s);
+      if (r == hipSuccess) r = workspace_alloc(&V2, 16 * N * N, c, s);
+      if (r == hipSuccess) r = workspace_alloc(&EW, eig_work_bytes((int)N), c, s);
+      double *Af = nullptr, *Vf = nullptr;
+      if (r == hipSuccess)
+        r = launch_jacobi_eig((double*)G, (double*)A2, (double*)V, (double*)V2, (int)N, EW,
+                              kMaxJacobiSweeps, s, &p->sweeps, &Af, &Vf);
+      if (r == hipSuccess && p->sweeps > 0)
+        r = launch_eig_select(Af, Vf, (int)N, form.trunc, form.trunc_value, lam, (double*)p->spec,
+                              (double*)L64, p->info, EW, &p->rank, s);
+      for (void* q : {EW, V2, V, A2})
+        if (q) (void)hipFreeAsync(q, s);
+      return r;
+    };
+    BCHK(eig());
+    if (p->sweeps < 0) {
+      fail(PINV_ERR_UNSUPPORTED, "the Jacobi eigendecomposition did not converge in " +
+                                     std::to_string(kMaxJacobiSweeps) + " sweeps");
+      (void)hipFreeAsync(G, s);
+      if (!f64) (void)hipFreeAsync(L64, s);
+      if (W) (void)hipFreeAsync(W, s);
+      return cleanup(PINV_ERR_UNSUPPORTED);
+    }
+    if (!f64) BCHK(launch_to_f32((const double*)L64, (float*)p->Linv, Gd * Gd, s));
+    BCHK(hipEventRecord(p->ev[2], s));
+    // 3. W = Q^H E^H (rank rows), R = Q W
+    const int r = p->rank;
+    if (f64) {
+      BCHK(launch_trmm_w<double>(p->e64, (const double*)p->Linv, (double*)W, form.m3, s, r));
+      BCHK(hipEventRecord(p->ev[3], s));
+      BCHK((launch_trmm_r<double, double>((const double*)p->Linv, (const double*)W, (double*)p->R,
+                                          d.N, d.M, form.m3, s, r)));
+    } else if (form.r_fp64) {
+      BCHK(launch_trmm_w<double>(p->e64, (const double*)L64, (double*)W, form.m3, s, r));
+      BCHK(hipEventRecord(p->ev[3], s));
+      BCHK((launch_trmm_r<double, float>((const double*)L64, (const double*)W, (float*)p->R, d.N,
+                                         d.M, form.m3, s, r)));
+    } else {
+      BCHK(launch_trmm_w<float>(p->e32, (const float*)p->Linv, (float*)W, form.m3, s, r));
+      BCHK(hipEventRecord(p->ev[3], s));
+      BCHK((launch_trmm_r<float, float>((const float*)p->Linv, (const float*)W, (float*)p->R, d.N,
+                                        d.M, form.m3, s, r)));
+    }
+  } else {
   // 2. shift + blocked Cholesky with L^-1 (a4), FP64
   BCHK(launch_cholinv((double*)G, (double*)L64, (int)Gd, lam, p->info, s,
                       s ? p->ctx->aux : p->ctx->aux_nb));
@@ -982,6 +1071,7 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
     BCHK((launch_trmm_r<float, float>((const float*)p->Linv, (const float*)W, (float*)p->R, d.N, d.M,
                                       m3, s)));
   }
+  }   // route
   BCHK(hipEventRecord(p->ev[4], s));
   if (W) BCHK(hipFreeAsync(W, s));
   W = nullptr;
@@ -1207,6 +1297,10 @@ extern "C++" pinv_status apply_items(pinv_context* c, int32_t n, const pinv_appl
   for (int i = 0; i < n; ++i) {
     const pinv_plan* p = (const pinv_plan*)items[i].plan;
     if (!p || p->ctx != c) return fail(PINV_ERR_INVALID, "item " + std::to_string(i) + ": bad plan");
+    if (refine_steps > 0 && p->route == PINV_ROUTE_EIGEN)
+      return fail(PINV_ERR_INVALID, "item " + std::to_string(i) +
+                                        ": eigenvalue-route plans take no refinement (a truncated "
+                                        "R is not the normal equations' solution)");
     if (items[i].F < 0 || items[i].F > (1 << 24))
       return fail(PINV_ERR_INVALID, "item " + std::to_string(i) + ": F out of range");
     if (items[i].F > 0 && (!items[i].data || !items[i].image))
@@ -1474,6 +1568,23 @@ pinv_status pinv_plan_info_get(const pinv_plan* p, pinv_plan_info* out) {
   out->nk = p->K;
   out->gram_form = p->gram_form;
   out->r_fp64 = p->r_fp64 ? 1 : 0;
+  out->route = p->route;
+  out->rank = p->rank;
+  out->sweeps = p->sweeps;
+  out->reserved = 0;
+  return PINV_OK;
+}
+
+pinv_status pinv_spectrum(pinv_context* c, const pinv_plan* p, double* out, void* stream) {
+  if (!c || !p || !out) return fail(PINV_ERR_INVALID, "NULL argument");
+  if (p->ctx != c) return fail(PINV_ERR_INVALID, "plan belongs to another context");
+  if (p->route != PINV_ROUTE_EIGEN || !p->spec)
+    return fail(PINV_ERR_INVALID, "the plan was not built with PINV_ROUTE_EIGEN");
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(hipStreamWaitEvent(s, p->ev[4], 0));
+  HIPCHK(hipMemcpyAsync(out, p->spec, sizeof(double) * (size_t)p->G, hipMemcpyDeviceToDevice, s));
+  HIPCHK(note_use(p, s));
   return PINV_OK;
 }
 

@@ -68,11 +68,16 @@ template <typename T> hipError_t launch_gram_shared(const EncDev<T>& e, double* 
 hipError_t launch_cholinv(double* A, double* Li, int N, double lam, int* info, hipStream_t s,
                           hipStream_t aux);
 // Triangular products forming R; m3 selects three real products per complex
-// product (else four).  R may be stored in a narrower type TO than T.
+// product (else four).  R may be stored in a narrower type TO than T.  With
+// rows / kdim >= 0 the factor is dense instead of lower triangular: W has
+// `rows` rows (W = Q^H E^H, Q^H rows x N) and R sums over kdim rows of W
+// (R = Q W), the eigenvalue route's products.
 template <typename T>
-hipError_t launch_trmm_w(const EncDev<T>& e, const T* Li, T* W, bool m3, hipStream_t s);
+hipError_t launch_trmm_w(const EncDev<T>& e, const T* Li, T* W, bool m3, hipStream_t s,
+                         int rows = -1);
 template <typename T, typename TO>
-hipError_t launch_trmm_r(const T* Li, const T* W, TO* R, int N, int M, bool m3, hipStream_t s);
+hipError_t launch_trmm_r(const T* Li, const T* W, TO* R, int N, int M, bool m3, hipStream_t s,
+                         int kdim = -1);
 // seg: the FP32 contraction in segments folded into a second accumulator set
 // (plans whose R is formed in FP64).
 template <typename T>
@@ -104,6 +109,21 @@ template <typename SX, typename SO>
 hipError_t launch_resid(const double* G, const double* b, const SX* X, int F, int N, double lam,
                         SO* Out, hipStream_t s);
 hipError_t launch_herm_fill(double* G, int N, hipStream_t s);
+// The eigenvalue route: Jacobi eigendecomposition of the FP64 Hermitian N x N
+// matrix A (A2, V, V2: same-size workspaces; the results end in *A_out and
+// *V_out, two of the four), synchronising s once per sweep (*sweeps = -1 when
+// max_sweeps did not converge); then the eigenvalues sorted largest first into
+// spec, the kept count (PINV_TRUNC_* mode and value) into *rank, and
+// Q^H = diag(1/sqrt(mu_j + lam)) P_r^H into Qh (N x N, rows >= rank zero).
+// `work` holds eig_work_bytes(N).
+size_t eig_work_bytes(int N);
+hipError_t launch_jacobi_eig(double* A, double* A2, double* V, double* V2, int N, void* work,
+                             int max_sweeps, hipStream_t s, int* sweeps, double** A_out,
+                             double** V_out);
+hipError_t launch_eig_select(const double* A, const double* V, int N, int mode, double value,
+                             double lam, double* spec, double* Qh, int* info, void* work, int* rank,
+                             hipStream_t s);
+
 // Gram through the point-spread function (no off-resonance map): G and Gk
 // (both full N x N FP64) from the FP64 tables; `work` holds psf_work_bytes.
 size_t psf_work_bytes(const EncDev<double>& e, int* splits);

@@ -9,13 +9,15 @@ namespace pinv {
 // ---------------------------------------------------------------------------
 // W = L^-1 E^H : W[i][m] = sum_{n <= i} Li[i][n] conj(E[m][n])
 // ---------------------------------------------------------------------------
+// `rows` rows of W; Li is lower triangular (tri, rows = N) or dense
+// (rows x N: the eigenvalue route's Q^H).
 template <class Cfg, int FEAT, bool AL>
 __global__ __launch_bounds__(256) void k_trmm_w(EncDev<typename Cfg::T> e,
                                                 const typename Cfg::T* __restrict__ Li,
-                                                typename Cfg::T* __restrict__ W) {
+                                                typename Cfg::T* __restrict__ W, int rows, int tri) {
   typedef typename Cfg::T T;
   const int N = e.N, M = e.M;
-  const int nbi = (N + Cfg::BM - 1) / Cfg::BM, nbj = (M + Cfg::BN - 1) / Cfg::BN;
+  const int nbi = (rows + Cfg::BM - 1) / Cfg::BM, nbj = (M + Cfg::BN - 1) / Cfg::BN;
   // each XCD runs column groups of 8 sample blocks over every row block
   // (longest K ranges first): its resident tiles share the E tables of 8
   // sample blocks and the L^-1 rows of a few row blocks
@@ -26,18 +28,18 @@ __global__ __launch_bounds__(256) void k_trmm_w(EncDev<typename Cfg::T> e,
   la.p = reinterpret_cast<const cx<T>*>(Li);
   la.ld = N;
   la.o0 = bi * Cfg::BM;
-  la.oend = N;
+  la.oend = rows;
   LoadGenRow<Cfg, Cfg::BN, Cfg::LDB, true, FEAT, AL> lb;
   lb.init(e, bj * Cfg::BN);
   AccTile<Cfg> acc;
   acc.zero();
-  const int kend = min(N, (bi + 1) * Cfg::BM);
+  const int kend = tri ? min(N, (bi + 1) * Cfg::BM) : N;
   mainloop<Cfg>(la, lb, 0, kend, acc, smem_base<Cfg>());
   cx<T>* O = reinterpret_cast<cx<T>*>(W);
   const int r0 = bi * Cfg::BM, c0 = bj * Cfg::BN;
   acc_foreach<Cfg>(acc, [&](int r, int c, T re, T im) {
     const int row = r0 + r, col = c0 + c;
-    if (row < N && col < M) O[(size_t)row * M + col] = cx<T>{re, im};
+    if (row < rows && col < M) O[(size_t)row * M + col] = cx<T>{re, im};
   });
 }
 
@@ -96,10 +98,12 @@ __global__ __launch_bounds__(256) void k_conj_transpose(const T* __restrict__ Z,
 // R = L^-H W : R[i][m] = sum_{n >= i} conj(Li[n][i]) W[n][m], stored as TO
 // (an FP64 product rounded once to complex64 for FP32 plans whose R is formed
 // in FP64)
+// Li is lower triangular (tri, kdim = N: the sum runs over n >= i) or dense
+// (kdim x N, the eigenvalue route's Q^H: the sum runs over n < kdim).
 template <class Cfg, typename TO = typename Cfg::T>
 __global__ __launch_bounds__(256) void k_trmm_r(const typename Cfg::T* __restrict__ Li,
                                                 const typename Cfg::T* __restrict__ W,
-                                                TO* __restrict__ R, int N, int M) {
+                                                TO* __restrict__ R, int N, int M, int kdim, int tri) {
   typedef typename Cfg::T T;
   const int nbi = (N + Cfg::BM - 1) / Cfg::BM, nbj = (M + Cfg::BN - 1) / Cfg::BN;
   // each XCD runs column groups of 8 W panels over every row block (longest K
@@ -121,7 +125,7 @@ __global__ __launch_bounds__(256) void k_trmm_r(const typename Cfg::T* __restric
   lb.oend = M;
   AccTile<Cfg> acc;
   acc.zero();
-  mainloop<Cfg, true, true>(la, lb, bi * Cfg::BM, N, acc, smem_base<Cfg>());
+  mainloop<Cfg, true, true>(la, lb, tri ? bi * Cfg::BM : 0, kdim, acc, smem_base<Cfg>());
   cx<TO>* O = reinterpret_cast<cx<TO>*>(R);
   const int r0 = bi * Cfg::BM, c0 = bj * Cfg::BN;
   acc_foreach<Cfg>(acc, [&](int r, int c, T re, T im) {
@@ -155,7 +159,7 @@ hipError_t launch_right_pinv(const EncDev<T>& e, const T* Li, T* W, T* Z, TO* R,
     });
   });
   if (err != hipSuccess) return err;
-  err = launch_trmm_r<T, T>(Li, W, Z, e.M, e.N, m3, s);   // Z = L'^-H W' (M x N)
+  err = launch_trmm_r<T, T>(Li, W, Z, e.M, e.N, m3, s, -1);   // Z = L'^-H W' (M x N)
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL((k_conj_transpose<T, TO>), dim3(cdiv(e.N, 32), cdiv(e.M, 32)), dim3(256), 0, s,
                      Z, R, e.M, e.N);
@@ -163,25 +167,31 @@ hipError_t launch_right_pinv(const EncDev<T>& e, const T* Li, T* W, T* Z, TO* R,
 }
 
 template <typename T>
-hipError_t launch_trmm_w(const EncDev<T>& e, const T* Li, T* W, bool m3, hipStream_t s) {
+hipError_t launch_trmm_w(const EncDev<T>& e, const T* Li, T* W, bool m3, hipStream_t s, int rows) {
+  const int tri = rows < 0;
+  if (tri) rows = e.N;
   return with_form<T>(m3, [&](auto cfg) {
     typedef decltype(cfg) Cfg;
-    const int tiles = cdiv(e.N, Cfg::BM) * cdiv(e.M, Cfg::BN);
+    const int tiles = cdiv(rows, Cfg::BM) * cdiv(e.M, Cfg::BN);
+    if (tiles == 0) return hipSuccess;
     return with_feat_al(enc_features(e), row_aligned(e, Cfg::BK), [&](auto fc, auto al) {
       hipLaunchKernelGGL((k_trmm_w<Cfg, decltype(fc)::value, decltype(al)::value>), dim3(tiles),
-                         dim3(256), smem_bytes<Cfg>(), s, e, Li, W);
+                         dim3(256), smem_bytes<Cfg>(), s, e, Li, W, rows, tri);
       return hipGetLastError();
     });
   });
 }
 
 template <typename T, typename TO>
-hipError_t launch_trmm_r(const T* Li, const T* W, TO* R, int N, int M, bool m3, hipStream_t s) {
+hipError_t launch_trmm_r(const T* Li, const T* W, TO* R, int N, int M, bool m3, hipStream_t s,
+                         int kdim) {
+  const int tri = kdim < 0;
+  if (tri) kdim = N;
   return with_form<T>(m3, [&](auto cfg) {
     typedef decltype(cfg) Cfg;
     const int tiles = cdiv(N, Cfg::BM) * cdiv(M, Cfg::BN);
     hipLaunchKernelGGL((k_trmm_r<Cfg, TO>), dim3(tiles), dim3(256), smem_bytes<Cfg>(), s, Li, W, R,
-                       N, M);
+                       N, M, kdim, tri);
     return hipGetLastError();
   });
 }
@@ -195,7 +205,7 @@ hipError_t launch_trmm_w_b3(const EncDev<float>& e, const float* Li, float* W, h
     // once per kernel (thread-safe static initialisation)
     static const hipError_t attr = allow_smem(kern, smem_bytes<Cfg>());
     if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL(kern, dim3(tiles), dim3(256), smem_bytes<Cfg>(), s, e, Li, W);
+    hipLaunchKernelGGL(kern, dim3(tiles), dim3(256), smem_bytes<Cfg>(), s, e, Li, W, e.N, 1);
     return hipGetLastError();
   });
 }
@@ -205,7 +215,7 @@ hipError_t launch_trmm_r_b3(const float* Li, const float* W, float* R, int N, in
   static const hipError_t attr = allow_smem(k_trmm_r<Cfg>, smem_bytes<Cfg>());
   if (attr != hipSuccess) return attr;
   const int tiles = cdiv(N, Cfg::BM) * cdiv(M, Cfg::BN);
-  hipLaunchKernelGGL(k_trmm_r<Cfg>, dim3(tiles), dim3(256), smem_bytes<Cfg>(), s, Li, W, R, N, M);
+  hipLaunchKernelGGL(k_trmm_r<Cfg>, dim3(tiles), dim3(256), smem_bytes<Cfg>(), s, Li, W, R, N, M, N, 1);
   return hipGetLastError();
 }
 
@@ -217,14 +227,14 @@ template hipError_t launch_right_pinv<double, double>(const EncDev<double>&, con
 template hipError_t launch_right_pinv<double, float>(const EncDev<double>&, const double*, double*,
                                                      double*, float*, bool, hipStream_t);
 template hipError_t launch_trmm_w<float>(const EncDev<float>&, const float*, float*, bool,
-                                         hipStream_t);
+                                         hipStream_t, int);
 template hipError_t launch_trmm_w<double>(const EncDev<double>&, const double*, double*, bool,
-                                          hipStream_t);
+                                          hipStream_t, int);
 template hipError_t launch_trmm_r<float, float>(const float*, const float*, float*, int, int, bool,
-                                                hipStream_t);
+                                                hipStream_t, int);
 template hipError_t launch_trmm_r<double, double>(const double*, const double*, double*, int, int,
-                                                  bool, hipStream_t);
+                                                  bool, hipStream_t, int);
 template hipError_t launch_trmm_r<double, float>(const double*, const double*, float*, int, int,
-                                                 bool, hipStream_t);
+                                                 bool, hipStream_t, int);
 
 }  // namespace pinv

@@ -26,6 +26,8 @@ FLAG_NO_R = 8
 FLAG_R_FP64 = 16
 CPROD_AUTO, CPROD_3M, CPROD_4M = 0, 1, 2
 GRAM_AUTO, GRAM_PSF, GRAM_SHARED, GRAM_FULL = 0, 1, 2, 3
+ROUTE_CHOLESKY, ROUTE_EIGEN = 0, 1
+TRUNC_NONE, TRUNC_KAPPA, TRUNC_ENERGY = 0, 1, 2
 BUF_R, BUF_LINV, BUF_GRAM = 0, 1, 2
 METRIC_DIAG, METRIC_FULL = 0, 1
 
@@ -47,7 +49,8 @@ class pinv_encoding(ctypes.Structure):
 class pinv_build_opts(ctypes.Structure):
     _fields_ = [("lambda_", ctypes.c_double), ("lambda_mode", ctypes.c_int32),
                 ("prec", ctypes.c_int32), ("flags", ctypes.c_int32), ("cprod", ctypes.c_int32),
-                ("nb", ctypes.c_int32), ("gram", ctypes.c_int32)]
+                ("nb", ctypes.c_int32), ("gram", ctypes.c_int32), ("route", ctypes.c_int32),
+                ("trunc", ctypes.c_int32), ("trunc_value", ctypes.c_double)]
 
 
 class pinv_plan_info(ctypes.Structure):
@@ -56,7 +59,9 @@ class pinv_plan_info(ctypes.Structure):
                 ("device_bytes", ctypes.c_size_t), ("stage_ms", ctypes.c_float * 4),
                 ("has_r", ctypes.c_int32), ("gram_order", ctypes.c_int64),
                 ("ncoil", ctypes.c_int32), ("cprod", ctypes.c_int32), ("nk", ctypes.c_int64),
-                ("gram_form", ctypes.c_int32), ("r_fp64", ctypes.c_int32)]
+                ("gram_form", ctypes.c_int32), ("r_fp64", ctypes.c_int32),
+                ("route", ctypes.c_int32), ("rank", ctypes.c_int32), ("sweeps", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class pinv_apply_item(ctypes.Structure):
@@ -107,6 +112,7 @@ _sigs = {
     "pinv_srf": [_vp, _vp, ctypes.c_int32, _vp, _vp],
     "pinv_noise": [_vp, _vp, _vp, ctypes.c_int32, _vp, _vp],
     "pinv_plan_info_get": [_vp, ctypes.POINTER(pinv_plan_info)],
+    "pinv_spectrum": [_vp, _vp, _vp, _vp],
     "pinv_plan_buffers": [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp)],
     "pinv_plan_copy_buffer": [_vp, ctypes.c_int32, _vp, ctypes.c_size_t, _vp],
     "pinv_plan_release": [_vp],
@@ -258,16 +264,19 @@ def _encoding_struct(enc):
     return s, keep
 
 
-def _opts(lam, lambda_mode, prec, flags, cprod, nb, gram):
+def _opts(lam, lambda_mode, prec, flags, cprod, nb, gram, route=ROUTE_CHOLESKY, trunc=TRUNC_NONE,
+          trunc_value=0.0):
     return pinv_build_opts(lambda_=lam, lambda_mode=lambda_mode, prec=prec, flags=flags,
-                           cprod=cprod, nb=nb, gram=gram)
+                           cprod=cprod, nb=nb, gram=gram, route=route, trunc=trunc,
+                           trunc_value=trunc_value)
 
 
 def pinv_build(ctx: int, enc, lam: float, lambda_mode: int = LAMBDA_REL_MEAN_DIAG,
                prec: int = FP32, flags: int = 0, stream=None, cprod: int = CPROD_AUTO, nb: int = 0,
-               gram: int = GRAM_AUTO) -> int:
+               gram: int = GRAM_AUTO, route: int = ROUTE_CHOLESKY, trunc: int = TRUNC_NONE,
+               trunc_value: float = 0.0) -> int:
     s, keep = _encoding_struct(enc)
-    o = _opts(lam, lambda_mode, prec, flags, cprod, nb, gram)
+    o = _opts(lam, lambda_mode, prec, flags, cprod, nb, gram, route, trunc, trunc_value)
     out = _vp()
     st = _lib.pinv_build(ctx, ctypes.byref(s), ctypes.byref(o), _stream_ptr(stream), ctypes.byref(out))
     del keep
@@ -364,7 +373,17 @@ def pinv_plan_info_get(plan: int) -> dict:
     return dict(N=i.N, M=i.M, lambda_abs=i.lambda_abs, prec=i.prec, ready=bool(i.ready),
                 key=i.key, device_bytes=i.device_bytes, stage_ms=list(i.stage_ms),
                 has_r=bool(i.has_r), gram_order=i.gram_order, ncoil=i.ncoil, cprod=i.cprod,
-                nk=i.nk, gram_form=i.gram_form, r_fp64=bool(i.r_fp64))
+                nk=i.nk, gram_form=i.gram_form, r_fp64=bool(i.r_fp64), route=i.route,
+                rank=i.rank, sweeps=i.sweeps)
+
+
+def pinv_spectrum(ctx: int, plan: int, out, stream=None) -> None:
+    """Eigenvalues of E^H E, largest first, of an eigenvalue-route plan: out is
+    a device float64 tensor [N]."""
+    import torch
+    info = pinv_plan_info_get(plan)
+    check_tensor("pinv_spectrum", "out", out, (info["N"],), torch.float64, _ctx_device.get(ctx))
+    _check(_lib.pinv_spectrum(ctx, plan, out.data_ptr(), _stream_ptr(stream)), "pinv_spectrum")
 
 
 def pinv_plan_buffers(plan: int):
@@ -419,9 +438,10 @@ def pinv_context_trim(ctx: int) -> None:
 
 
 def pinv_encoding_key(enc, lam: float, lambda_mode: int = LAMBDA_REL_MEAN_DIAG, prec: int = FP32,
-                      flags: int = 0, cprod: int = CPROD_AUTO, nb: int = 0, gram: int = GRAM_AUTO):
+                      flags: int = 0, cprod: int = CPROD_AUTO, nb: int = 0, gram: int = GRAM_AUTO,
+                      route: int = ROUTE_CHOLESKY, trunc: int = TRUNC_NONE, trunc_value: float = 0.0):
     s, keep = _encoding_struct(enc)
-    o = _opts(lam, lambda_mode, prec, flags, cprod, nb, gram)
+    o = _opts(lam, lambda_mode, prec, flags, cprod, nb, gram, route, trunc, trunc_value)
     k, b = ctypes.c_uint64(), ctypes.c_size_t()
     st = _lib.pinv_encoding_key(ctypes.byref(s), ctypes.byref(o), ctypes.byref(k), ctypes.byref(b))
     del keep

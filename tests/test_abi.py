@@ -181,3 +181,32 @@ def test_binding_checks_tensors_before_the_call():
     with pytest.raises(ValueError) as ei:
         pinv.check_frames("pinv_apply", dict(info, prec=pinv.FP64), d, x)
     assert "complex128" in str(ei.value)
+
+
+def test_eigen_route_options_without_device():
+    """The eigenvalue route (Eq. 7) with truncation (Eq. 4): options validated on
+    the host; the truncation's kind and value are part of the cache key."""
+    ensure_built()
+    from paper_2410_06129_amd import pinv, synth
+    enc = synth.small_case(seed=5, nx=12, ny=10, C=2, K=300, F=1).enc
+    under = synth.small_case(seed=6, nx=16, ny=12, C=2, K=40, F=1).enc   # M < N
+    E = pinv.ROUTE_EIGEN
+    k1 = pinv.pinv_encoding_key(enc, 0.0, pinv.LAMBDA_ABS, route=E, trunc=pinv.TRUNC_KAPPA,
+                                trunc_value=30.0)[0]
+    k2 = pinv.pinv_encoding_key(enc, 0.0, pinv.LAMBDA_ABS, route=E, trunc=pinv.TRUNC_KAPPA,
+                                trunc_value=40.0)[0]
+    k3 = pinv.pinv_encoding_key(enc, 0.0, pinv.LAMBDA_ABS, route=E, trunc=pinv.TRUNC_ENERGY,
+                                trunc_value=0.95)[0]
+    k4 = pinv.pinv_encoding_key(enc, 1e-3, route=E)[0]
+    k5 = pinv.pinv_encoding_key(enc, 1e-3)[0]
+    assert len({k1, k2, k3, k4, k5}) == 5
+    for want, kw, e in ((pinv.ERR_INVALID, dict(trunc=pinv.TRUNC_KAPPA, trunc_value=30.0), enc),
+                        (pinv.ERR_INVALID, dict(route=E, trunc=pinv.TRUNC_KAPPA, trunc_value=0.5), enc),
+                        (pinv.ERR_INVALID, dict(route=E, trunc=pinv.TRUNC_ENERGY, trunc_value=0.0), enc),
+                        (pinv.ERR_INVALID, dict(route=E, trunc=pinv.TRUNC_ENERGY, trunc_value=1.5), enc),
+                        (pinv.ERR_INVALID, dict(route=E, trunc=5), enc),
+                        (pinv.ERR_INVALID, dict(route=2), enc),
+                        (pinv.ERR_UNSUPPORTED, dict(route=E, prec=pinv.BF16X3), enc),
+                        (pinv.ERR_INVALID, dict(route=E, flags=pinv.FLAG_NO_R), enc),
+                        (pinv.ERR_UNSUPPORTED, dict(route=E), under)):
+        _expect(pinv, want, lambda: pinv.pinv_encoding_key(e, 1e-3, **kw))
