@@ -59,7 +59,8 @@ typedef enum {
   PINV_FP64 = 0,    /* everything in FP64 (complex128 data and images) */
   PINV_FP32 = 1,    /* W, R and apply on FP32 MFMA; the Gram (default form) and the
                        factorisation in FP64 */
-  PINV_BF16X3 = 2   /* as FP32 but products as three BF16 MFMAs (hi*hi + hi*lo + lo*hi) */
+  PINV_BF16X3 = 2   /* as FP32 but products as three BF16 MFMAs (hi*hi + hi*lo + lo*hi),
+                       operands split into bf16 hi/lo once, where produced */
 } pinv_precision;
 
 typedef enum {
@@ -353,7 +354,11 @@ pinv_status pinv_spectrum(pinv_context *ctx, const pinv_plan *p, double *out, vo
 pinv_status pinv_plan_info_get(const pinv_plan *p, pinv_plan_info *out);
 
 /* Device pointers held by a ready plan (any may be NULL on output):
- *   R     [N][M] complex, the reconstruction matrix
+ *   R     [N][M] complex, the reconstruction matrix.  A PINV_BF16X3 plan holds
+ *         it split-packed instead: N rows of Mp = 32*ceil(M/32) columns (zero
+ *         past M), each 8 consecutive columns of a row stored as 64 bytes,
+ *         the bf16 planes re_hi[8], re_lo[8], im_hi[8], im_lo[8] (value =
+ *         hi + lo); pinv_plan_copy_buffer returns it as complex64.
  *   Linv  [N][N] complex, L^-1 (lower; FP32 plans hold it as complex64)
  *   gram  [N][N] complex128, E^H E (full Hermitian; used by the refinement residual)
  * The memory stays owned by the plan.  Work the caller enqueues on these

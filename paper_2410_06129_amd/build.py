@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpinv.so")
 SOURCES = ["pinv_gram.hip", "pinv_chol.hip", "pinv_trmm.hip", "pinv_apply.hip", "pinv_solve.hip",
-           "pinv_metrics.hip", "pinv_api.hip", "pinv_serve.hip", "pinv_noalloc.hip", "pinv_eig.hip"]
+           "pinv_metrics.hip", "pinv_api.hip", "pinv_serve.hip", "pinv_noalloc.hip", "pinv_eig.hip",
+           "pinv_split.hip"]
 SIM_LIB = os.path.join(HERE, "libpinv_schedsim.so")
 HEADERS = ["pinv_device.h", "pinv_internal.h"]
 

@@ -428,7 +428,11 @@ size_t plan_footprint(const Dims& d, int prec, const BuildForm& f) {
   b += 16 * Gd * Gd;            // Gram / factor workspace (FP64)
   b += 16 * Gd * Gd;            // L^-1 in FP64 during the factorisation
   b += cs * Gd * Gd;            // L^-1 kept
-  if (!f.no_r) {
+  if (!f.no_r && prec == PINV_BF16X3) {
+    // split-packed L^-1 and L^-H, W^T and R (rows padded to 32 columns)
+    const size_t Np = sp_cols(N), Mp = sp_cols(M);
+    b += 2 * 8 * N * Np + 8 * M * Np + 8 * N * Mp;
+  } else if (!f.no_r) {
     b += ws * N * M;            // W (and Z for the right pseudoinverse)
     if (right) b += ws * N * M;
     b += cs * N * M;            // R
@@ -452,7 +456,8 @@ size_t plan_resident(const Dims& d, int prec, bool no_r) {
   const size_t N = d.N, M = d.M;
   const size_t Gd = d.M < d.N ? M : N;
   const size_t cs = prec == PINV_FP64 ? 16 : 8;
-  return (no_r ? 0 : cs * N * M) + cs * Gd * Gd + 16 * Gd * Gd + 8 * Gd + (16ull << 20);
+  const size_t r = no_r ? 0 : prec == PINV_BF16X3 ? 8 * N * sp_cols(M) : cs * N * M;
+  return r + cs * Gd * Gd + 16 * Gd * Gd + 8 * Gd + (16ull << 20);
 }
 
 // Evict LRU plans held only by the cache until `need` bytes fit.  ctx->mu held.
@@ -896,6 +901,8 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
   const size_t cs = f64 ? 16 : 8;
   const size_t ws = form.r_fp64 ? 16 : cs;   // W and Z element size
   void *G = nullptr, *L64 = nullptr, *W = nullptr, *Z = nullptr, *PW = nullptr;
+  void *LS = nullptr, *LHS = nullptr;   // split-packed L^-1 and L^-H (BF16X3)
+  const bool b3 = o->prec == PINV_BF16X3;
   const size_t Gd = p->G;   // order of the Gram and the factor
   hipError_t he;
 #define BCHK(expr)                                                                    \
@@ -909,6 +916,8 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
       if (W) (void)hipFreeAsync(W, s);                                                \
       if (Z) (void)hipFreeAsync(Z, s);                                                \
       if (PW) (void)hipFreeAsync(PW, s);                                              \
+      if (LS) (void)hipFreeAsync(LS, s);                                              \
+      if (LHS) (void)hipFreeAsync(LHS, s);                                            \
       return cleanup(he == hipErrorOutOfMemory ? PINV_ERR_NOMEM : PINV_ERR_DEVICE);   \
     }                                                                                 \
   } while (0)
@@ -939,7 +948,8 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
   for (auto& ev : p->ev) BCHK(hipEventCreate(&ev));
   BCHK(plan_malloc((void**)&p->info, sizeof(int), c, s));
   BCHK(hipMemsetAsync(p->info, 0, sizeof(int), s));
-  if (!no_r) BCHK(plan_malloc(&p->R, cs * N * M, c, s));
+  // a BF16X3 plan keeps R split-packed (rows n, sp_cols(M) columns)
+  if (!no_r) BCHK(plan_malloc(&p->R, b3 ? 8 * N * sp_cols(M) : cs * N * M, c, s));
   BCHK(plan_malloc(&p->Linv, cs * Gd * Gd, c, s));
   BCHK(plan_malloc(&p->gram, 16 * Gd * Gd, c, s));
   if (form.route == PINV_ROUTE_EIGEN) BCHK(plan_malloc(&p->spec, 8 * Gd, c, s));
@@ -951,7 +961,7 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
     BCHK(workspace_alloc(&L64, 16 * Gd * Gd, c, s));
   }
   BCHK(hipMemsetAsync(L64, 0, 16 * Gd * Gd, s));
-  if (!no_r) BCHK(workspace_alloc(&W, ws * N * M, c, s));
+  if (!no_r) BCHK(workspace_alloc(&W, b3 ? 8 * M * sp_cols(N) : ws * N * M, c, s));
   if (p->right) BCHK(workspace_alloc(&Z, ws * N * M, c, s));
   if (form.gram == PINV_GRAM_PSF) BCHK(workspace_alloc(&PW, psf_work_bytes(p->e64, nullptr), c, s));
 
@@ -1061,10 +1071,21 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
     BCHK(hipEventRecord(p->ev[3], s));
     BCHK((launch_trmm_r<double, float>((const double*)L64, (const double*)W, (float*)p->R, d.N, d.M,
                                        m3, s)));
-  } else if (o->prec == PINV_BF16X3) {
-    BCHK(launch_trmm_w_b3(p->e32, (const float*)p->Linv, (float*)W, s));
+  } else if (b3) {
+    // the factor split once into bf16 hi/lo planes, as rows of L^-1 and of
+    // L^-H; the products write W^T and R split-packed
+    const size_t Np = sp_cols(N);
+    BCHK(workspace_alloc(&LS, 8 * N * Np, c, s));
+    BCHK(workspace_alloc(&LHS, 8 * N * Np, c, s));
+    BCHK(launch_sp_pack<double>((const double*)L64, (int64_t)N, d.N, d.N, false, false, LS, s));
+    BCHK(launch_sp_pack<double>((const double*)L64, (int64_t)N, d.N, d.N, true, true, LHS, s));
+    BCHK(launch_trmm_w_sp(p->e32, LS, W, s));
     BCHK(hipEventRecord(p->ev[3], s));
-    BCHK(launch_trmm_r_b3((const float*)p->Linv, (const float*)W, (float*)p->R, d.N, d.M, s));
+    BCHK(launch_trmm_r_sp(W, LHS, p->R, d.N, d.M, s));
+    BCHK(hipFreeAsync(LHS, s));
+    LHS = nullptr;
+    BCHK(hipFreeAsync(LS, s));
+    LS = nullptr;
   } else {
     BCHK(launch_trmm_w<float>(p->e32, (const float*)p->Linv, (float*)W, m3, s));
     BCHK(hipEventRecord(p->ev[3], s));
@@ -1260,9 +1281,12 @@ size_t item_scratch_bytes(const pinv_plan* p, int F, int steps) {
   size_t peak = 0;
   const bool tiles = F > kRowApplyMaxF && !p->no_r && !(p->right && steps > 0);
   if (tiles) {
-    peak = p->prec == PINV_FP64     ? apply_scratch_bytes<double>(F, (int)N, (int)M, p->m3, false)
-           : p->prec == PINV_BF16X3 ? apply_scratch_bytes_b3(F, (int)N, (int)M)
-                                    : apply_scratch_bytes<float>(F, (int)N, (int)M, p->m3, p->r_fp64);
+    // a BF16X3 item's data is split-packed first (F x sp_cols(M), 8 bytes each)
+    const size_t Mp = sp_cols(M);
+    peak = p->prec == PINV_FP64 ? apply_scratch_bytes<double>(F, (int)N, (int)M, p->m3, false)
+           : p->prec == PINV_BF16X3
+               ? al(8 * F * Mp) + apply_scratch_bytes_b3(F, (int)N, (int)Mp)
+               : apply_scratch_bytes<float>(F, (int)N, (int)M, p->m3, p->r_fp64);
   }
   if (p->no_r) {
     const size_t adj = p->prec == PINV_FP64
@@ -1332,12 +1356,32 @@ extern "C++" pinv_status apply_items(pinv_context* c, int32_t n, const pinv_appl
       ++i;
     }
     if (b.n == 0) continue;
-    if (prec == PINV_FP64)
+    if (prec == PINV_FP64) {
       HIPCHK(launch_apply<double>(b, m3, false, sc, s));
-    else if (prec == PINV_BF16X3)
-      HIPCHK(launch_apply_b3(b, sc, s));
-    else
+    } else if (prec == PINV_BF16X3) {
+      // each item's data split-packed once; the tiles then only move bf16 planes
+      void* packed[kMaxGroup] = {};
+      hipError_t e = hipSuccess;
+      int got = 0;
+      for (; got < b.n && e == hipSuccess; ++got) {
+        ApplyItemDev& it = b.it[got];
+        const int64_t Mp = sp_cols(it.M);
+        e = sc.get(&packed[got], (size_t)8 * it.F * Mp, s);
+        if (e != hipSuccess) break;
+        e = launch_sp_pack<float>((const float*)it.D, it.M, it.F, it.M, false, false, packed[got], s);
+        it.D = packed[got];
+        it.M = (int)Mp;
+      }
+      if (e == hipSuccess) e = launch_apply_b3(b, sc, s);
+      for (int j = got - 1; j >= 0; --j)   // most recent first (the fixed-region scratch is a stack)
+        if (packed[j]) {
+          const hipError_t f = sc.put(packed[j], s);
+          if (e == hipSuccess) e = f;
+        }
+      HIPCHK(e);
+    } else {
       HIPCHK(launch_apply<float>(b, m3, seg, sc, s));
+    }
   }
   // a few frames: stream R row by row (bound by HBM bandwidth, not MFMA)
   for (int j = 0; j < n; ++j) {
@@ -1347,6 +1391,9 @@ extern "C++" pinv_status apply_items(pinv_context* c, int32_t n, const pinv_appl
     if (p->prec == PINV_FP64)
       HIPCHK(launch_apply_rows<double>((const double*)p->R, (const double*)items[j].data,
                                        (double*)items[j].image, p->N, p->M, F, s));
+    else if (p->prec == PINV_BF16X3)
+      HIPCHK(launch_apply_rows_sp(p->R, (const float*)items[j].data, (float*)items[j].image, p->N,
+                                  p->M, F, s));
     else
       HIPCHK(launch_apply_rows<float>((const float*)p->R, (const float*)items[j].data,
                                       (float*)items[j].image, p->N, p->M, F, s));
@@ -1458,6 +1505,19 @@ static bool coil_cholesky(const double* psi, int C, std::vector<double>& L) {
   return true;
 }
 
+// The plan's R as a dense complex matrix of its storage type: p->R itself, or
+// for BF16X3 plans (R kept split-packed) an unpacked complex64 copy in *tmp,
+// which the caller frees stream-ordered.
+static hipError_t dense_r(const pinv_plan* p, hipStream_t s, const void** R, void** tmp) {
+  *tmp = nullptr;
+  *R = p->R;
+  if (p->prec != PINV_BF16X3) return hipSuccess;
+  hipError_t e = hipMallocAsync(tmp, (size_t)8 * p->N * p->M, s);
+  if (e == hipSuccess) e = launch_sp_unpack(p->R, p->N, p->M, (float*)*tmp, s);
+  *R = *tmp;
+  return e;
+}
+
 static pinv_status metric_args(pinv_context* c, const pinv_plan* p, int32_t mode, void* out) {
   if (!c || !p || !out) return fail(PINV_ERR_INVALID, "NULL argument");
   if (p->ctx != c) return fail(PINV_ERR_INVALID, "plan belongs to another context");
@@ -1475,17 +1535,22 @@ pinv_status pinv_srf(pinv_context* c, const pinv_plan* pc, int32_t mode, void* o
   hipStream_t s = (hipStream_t)stream;
   HIPCHK(hipSetDevice(c->device));
   HIPCHK(hipStreamWaitEvent(s, p->ev[4], 0));
-  if (p->prec == PINV_FP64) {
-    if (mode == PINV_METRIC_DIAG)
-      HIPCHK(launch_srf_diag<double>(p->e64, (const double*)p->R, (double*)out, s));
+  const void* R = nullptr;
+  void* tmp = nullptr;
+  hipError_t e = dense_r(p, s, &R, &tmp);
+  if (e == hipSuccess) {
+    if (p->prec == PINV_FP64)
+      e = mode == PINV_METRIC_DIAG ? launch_srf_diag<double>(p->e64, (const double*)R, (double*)out, s)
+                                   : launch_srf_full<double>(p->e64, (const double*)R, (double*)out, s);
     else
-      HIPCHK(launch_srf_full<double>(p->e64, (const double*)p->R, (double*)out, s));
-  } else {
-    if (mode == PINV_METRIC_DIAG)
-      HIPCHK(launch_srf_diag<float>(p->e32, (const float*)p->R, (float*)out, s));
-    else
-      HIPCHK(launch_srf_full<float>(p->e32, (const float*)p->R, (float*)out, s));
+      e = mode == PINV_METRIC_DIAG ? launch_srf_diag<float>(p->e32, (const float*)R, (float*)out, s)
+                                   : launch_srf_full<float>(p->e32, (const float*)R, (float*)out, s);
   }
+  if (tmp) {
+    const hipError_t f = hipFreeAsync(tmp, s);
+    if (e == hipSuccess) e = f;
+  }
+  HIPCHK(e);
   HIPCHK(note_use(p, s));
   return PINV_OK;
 }
@@ -1493,8 +1558,8 @@ pinv_status pinv_srf(pinv_context* c, const pinv_plan* pc, int32_t mode, void* o
 extern "C++" {
 namespace {
 template <typename T>
-pinv_status noise_impl(const pinv_plan* p, const T* Lc, int32_t mode, T* out, hipStream_t s) {
-  const T* R = (const T*)p->R;
+pinv_status noise_impl(const pinv_plan* p, const T* R, const T* Lc, int32_t mode, T* out,
+                       hipStream_t s) {
   if (mode == PINV_METRIC_DIAG) {
     HIPCHK(launch_noise_diag<T>(R, p->N, p->K, p->C, Lc, out, s));
     return PINV_OK;
@@ -1544,9 +1609,16 @@ pinv_status pinv_noise(pinv_context* c, const pinv_plan* pc, const double* coil_
     if (e != hipSuccess && dL) (void)hipFreeAsync(dL, s);
     HIPCHK(e);
   }
-  const pinv_status r = f64 ? noise_impl<double>(p, (const double*)dL, mode, (double*)out, s)
-                            : noise_impl<float>(p, (const float*)dL, mode, (float*)out, s);
+  const void* R = nullptr;
+  void* tmp = nullptr;
+  const hipError_t re = dense_r(p, s, &R, &tmp);
+  pinv_status r = PINV_ERR_DEVICE;
+  if (re == hipSuccess)
+    r = f64 ? noise_impl<double>(p, (const double*)R, (const double*)dL, mode, (double*)out, s)
+            : noise_impl<float>(p, (const float*)R, (const float*)dL, mode, (float*)out, s);
+  if (tmp) (void)hipFreeAsync(tmp, s);
   if (dL) HIPCHK(hipFreeAsync(dL, s));
+  HIPCHK(re);
   if (r == PINV_OK) HIPCHK(note_use(p, s));
   return r;
 }
@@ -1619,7 +1691,10 @@ pinv_status pinv_plan_copy_buffer(const pinv_plan* p, int32_t which, void* dst, 
   hipStream_t s = (hipStream_t)stream;
   HIPCHK(hipSetDevice(p->ctx->device));
   HIPCHK(hipStreamWaitEvent(s, p->ev[4], 0));
-  HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s));
+  if (which == 0 && p->prec == PINV_BF16X3)   // R is kept split-packed
+    HIPCHK(launch_sp_unpack(p->R, p->N, p->M, (float*)dst, s));
+  else
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s));
   HIPCHK(note_use(p, s));
   return PINV_OK;
 }

@@ -42,6 +42,31 @@ __global__ __launch_bounds__(256) void k_apply(const ApplyBatch batch) {
   const int nbi = (it.F + Cfg::BM - 1) / Cfg::BM;
   const int bi = u % nbi, bj = u / nbi;
   const int k0 = split * it.kchunk, k1 = min(it.M, k0 + it.kchunk);
+  const int r0 = bi * Cfg::BM, c0 = bj * Cfg::BN;
+  if constexpr (IsB3<Cfg>::value) {
+    // split-precision items: D and R split-packed, it.M their padded row length
+    cx<T>* O = it.splits > 1
+                   ? reinterpret_cast<cx<T>*>(it.work) + (size_t)split * it.F * it.N
+                   : reinterpret_cast<cx<T>*>(it.X);
+    LoadSP<Cfg, Cfg::BM> la;   // D rows f
+    la.p = reinterpret_cast<const uint4*>(it.D);
+    la.gpr = it.M / 8;
+    la.o0 = r0;
+    la.oend = it.F;
+    LoadSP<Cfg, Cfg::BN> lb;   // R rows n
+    lb.p = reinterpret_cast<const uint4*>(it.R);
+    lb.gpr = it.M / 8;
+    lb.o0 = c0;
+    lb.oend = it.N;
+    AccTile<Cfg> acc;
+    acc.zero();
+    mainloop<Cfg>(la, lb, k0, k1, acc, smem_base<Cfg>());
+    acc_foreach<Cfg>(acc, [&](int r, int c, T re, T im) {
+      const int row = r0 + r, col = c0 + c;
+      if (row < it.F && col < it.N) O[(size_t)row * it.N + col] = cx<T>{re, im};
+    });
+    return;
+  } else {
   LoadDenseKC<Cfg, Cfg::BM, Cfg::LDA, T, false> la;   // D[f][m]
   la.p = reinterpret_cast<const cx<T>*>(it.D);
   la.ld = it.M;
@@ -56,7 +81,6 @@ __global__ __launch_bounds__(256) void k_apply(const ApplyBatch batch) {
   cx<T>* O = it.splits > 1
                  ? reinterpret_cast<cx<T>*>(it.work) + (size_t)split * it.F * it.N
                  : reinterpret_cast<cx<T>*>(it.X);
-  const int r0 = bi * Cfg::BM, c0 = bj * Cfg::BN;
   if constexpr (SEG) {
     typename Acc<T>::type ore[Cfg::MB][Cfg::NB], oim[Cfg::MB][Cfg::NB];
 #pragma unroll
@@ -83,6 +107,7 @@ __global__ __launch_bounds__(256) void k_apply(const ApplyBatch batch) {
     const int row = r0 + r, col = c0 + c;
     if (row < it.F && col < it.N) O[(size_t)row * it.N + col] = cx<T>{re, im};
   });
+  }
 }
 
 // X = sum_s work[s] in split order, for the split items of a grouped apply
@@ -343,7 +368,7 @@ hipError_t launch_apply_b3(const ApplyBatch& b, Scratch& sc, hipStream_t s) {
   return run_apply<B3Cfg>(b, sc, s);
 }
 
-size_t apply_scratch_bytes_b3(int F, int N, int M) { return item_work_bytes<B3Cfg, false>(F, N, M); }
+size_t apply_scratch_bytes_b3(int F, int N, int Mp) { return item_work_bytes<B3Cfg, false>(F, N, Mp); }
 
 // explicit instantiations
 template hipError_t launch_apply<float>(const ApplyBatch&, bool, bool, Scratch&, hipStream_t);

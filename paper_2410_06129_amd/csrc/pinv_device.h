@@ -203,7 +203,7 @@ __device__ __forceinline__ void tile_compute(const typename Cfg::T* __restrict__
 // Loader protocol: fetch(k0, kend) issues the global loads of a chunk,
 // finish<STEP, STEPS>() turns loaded values into operand values (the E
 // element products for generated operands), store(s) writes them to LDS.
-template <class Cfg, class LA, class LB>
+template <class Cfg, bool DOWN, class LA, class LB>
 __device__ __forceinline__ void mainloop_b3(LA& la, LB& lb, int kbeg, int kend, AccTile<Cfg>& acc,
                                             float* smem_f);
 template <class Cfg, class = void> struct IsB3;
@@ -221,7 +221,7 @@ template <class Cfg, bool PRIO = true, bool DOWN = false, class LA, class LB>
 __device__ __forceinline__ void mainloop(LA& la, LB& lb, int kbeg, int kend, AccTile<Cfg>& acc,
                                          typename Cfg::T* smem) {
   if constexpr (IsB3<Cfg>::value) {
-    mainloop_b3<Cfg>(la, lb, kbeg, kend, acc, smem);
+    mainloop_b3<Cfg, DOWN>(la, lb, kbeg, kend, acc, smem);
     return;
   } else {
   typedef typename Cfg::T T;
@@ -275,13 +275,25 @@ __device__ __forceinline__ void mainloop(LA& la, LB& lb, int kbeg, int kend, Acc
 // BF16x3 ("BF16 split") products.  Each FP32 operand value x is split into
 // hi = bf16(x) and lo = bf16(x - hi); a real product is hi*hi + hi*lo + lo*hi
 // on v_mfma_f32_16x16x32_bf16 with FP32 accumulation (relative error ~2^-16
-// per product, the lo*lo term dropped).  LDS holds four bf16 planes per
-// operand (re_hi, re_lo, im_hi, im_lo) laid out [outer][k] so a lane reads its
-// eight consecutive k values with one 16-byte load; one chunk is BK = 32, a
-// single MFMA k-step.  The LDS stage is single-buffered: the next chunk's
-// global loads are in flight while the current chunk's MFMAs run.
+// per product, the lo*lo term dropped).
+//
+// The operands are split once, where they are produced, into "split-packed"
+// (SP) storage: a complex matrix with k contiguous, rows of Kp = 32 *
+// ceil(K / 32) columns (zero beyond K), each group of 8 consecutive k of a row
+// stored as 64 bytes: re_hi[8], re_lo[8], im_hi[8], im_lo[8] (bf16).  That is
+// eight bytes per complex value, as for complex64; a tile moves SP chunks into
+// LDS with 16-byte loads and stores and no arithmetic.
+//
+// LDS holds four bf16 planes per operand (re_hi, re_lo, im_hi, im_lo) laid out
+// [outer][k] with a row stride of LDK = 40 bf16 (80 bytes: the 16-byte reads of
+// 16 consecutive rows fall in distinct banks), so a lane reads its eight
+// consecutive k values with one 16-byte load; one chunk is BK = 32, a single
+// MFMA k-step.  Two LDS stages: the next chunk is written to one while the
+// other's MFMAs run.
 // ---------------------------------------------------------------------------
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2v __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ f32x4 mfma_b16(bf16x8 a, bf16x8 b, f32x4 c) {
@@ -292,10 +304,33 @@ __device__ __forceinline__ bf16x8 neg_b16(bf16x8 v) {
   u ^= 0x80008000u;
   return __builtin_bit_cast(bf16x8, u);
 }
-__device__ __forceinline__ void split_b16(float x, __bf16* hi, __bf16* lo) {
-  const __bf16 h = (__bf16)x;
-  *hi = h;
-  *lo = (__bf16)(x - (float)h);
+// hi and lo parts of x0 and x1, each pair packed in a 32-bit word (x0 in the
+// low half).  x - float(hi) is exact in FP32.
+__device__ __forceinline__ void split2(float x0, float x1, uint32_t& hi, uint32_t& lo) {
+  const uint32_t h = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2v{x0, x1}, bf16x2));
+  const float h0 = __builtin_bit_cast(float, h << 16);
+  const float h1 = __builtin_bit_cast(float, h & 0xffff0000u);
+  hi = h;
+  lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2v{x0 - h0, x1 - h1}, bf16x2));
+}
+// The value a packed hi/lo word pair holds in element e (0 low, 1 high).
+__device__ __forceinline__ float join2(uint32_t hi, uint32_t lo, int e) {
+  const uint32_t sh = e ? 0u : 16u;
+  return __builtin_bit_cast(float, (hi << sh) & 0xffff0000u) +
+         __builtin_bit_cast(float, (lo << sh) & 0xffff0000u);
+}
+// One SP group (64 bytes) from eight complex values.
+__device__ __forceinline__ void sp_group(const float (&re)[8], const float (&im)[8], uint4 (&g)[4]) {
+  uint32_t rh[4], rl[4], ih[4], il[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    split2(re[2 * j], re[2 * j + 1], rh[j], rl[j]);
+    split2(im[2 * j], im[2 * j + 1], ih[j], il[j]);
+  }
+  g[0] = uint4{rh[0], rh[1], rh[2], rh[3]};
+  g[1] = uint4{rl[0], rl[1], rl[2], rl[3]};
+  g[2] = uint4{ih[0], ih[1], ih[2], ih[3]};
+  g[3] = uint4{il[0], il[1], il[2], il[3]};
 }
 
 template <int BM_, int BN_> struct TileCfgB3 {
@@ -308,7 +343,8 @@ template <int BM_, int BN_> struct TileCfgB3 {
   static constexpr int LDK = BK + 8;               // bf16 per LDS row (80 bytes)
   static constexpr int LDA = 0, LDB = 0;            // FP32 layouts unused
   static constexpr int A_PLANE = BM * LDK, B_PLANE = BN * LDK;   // bf16 elements
-  static constexpr int SMEM_BYTES = (4 * A_PLANE + 4 * B_PLANE) * 2;
+  static constexpr int STAGE = 4 * A_PLANE + 4 * B_PLANE;         // bf16 elements
+  static constexpr int SMEM_BYTES = 2 * STAGE * 2;
   static constexpr int SMEM_ELEMS = SMEM_BYTES / 4;
 };
 
@@ -360,35 +396,44 @@ __device__ __forceinline__ void tile_compute_b3(const __bf16* __restrict__ sA,
   }
 }
 
-template <class Cfg, class LA, class LB>
+// Loader protocol as for the FP32 tiles, with store_b3<LDK, PLANE>(s) writing
+// the four bf16 planes.  DOWN as for mainloop.
+template <class Cfg, bool DOWN, class LA, class LB>
 __device__ __forceinline__ void mainloop_b3(LA& la, LB& lb, int kbeg, int kend, AccTile<Cfg>& acc,
                                             float* smem_f) {
   if (kend <= kbeg) return;
-  __bf16* sA = reinterpret_cast<__bf16*>(smem_f);
-  __bf16* sB = sA + 4 * Cfg::A_PLANE;
+  __bf16* const stage0 = reinterpret_cast<__bf16*>(smem_f);
+  __bf16* const stage1 = stage0 + Cfg::STAGE;
   const int nch = (kend - kbeg + Cfg::BK - 1) / Cfg::BK;
-  la.fetch(kbeg, kend);
-  lb.fetch(kbeg, kend);
+  auto chunk = [&](int c) { return DOWN ? kbeg + (nch - 1 - c) * Cfg::BK : kbeg + c * Cfg::BK; };
+  la.fetch(chunk(0), kend);
+  lb.fetch(chunk(0), kend);
 #pragma unroll
   for (int q = 0; q < Cfg::MB; ++q) {
     la.finish(q, Cfg::MB);
     lb.finish(q, Cfg::MB);
   }
+  la.template store_b3<Cfg::LDK, Cfg::A_PLANE>(stage0);
+  lb.template store_b3<Cfg::LDK, Cfg::B_PLANE>(stage0 + 4 * Cfg::A_PLANE);
+  __syncthreads();
   for (int c = 0; c < nch; ++c) {
-    la.template store_b3<Cfg::LDK, Cfg::A_PLANE>(sA);
-    lb.template store_b3<Cfg::LDK, Cfg::B_PLANE>(sB);
-    __syncthreads();
+    __bf16* cur = (c & 1) ? stage1 : stage0;
+    __bf16* nxt = (c & 1) ? stage0 : stage1;
     const bool more = c + 1 < nch;
     if (more) {
-      la.fetch(kbeg + (c + 1) * Cfg::BK, kend);
-      lb.fetch(kbeg + (c + 1) * Cfg::BK, kend);
+      la.fetch(chunk(c + 1), kend);
+      lb.fetch(chunk(c + 1), kend);
     }
-    tile_compute_b3<Cfg>(sA, sB, acc, [&](int i) {
+    tile_compute_b3<Cfg>(cur, cur + 4 * Cfg::A_PLANE, acc, [&](int i) {
       if (more) {
         la.finish(i, Cfg::MB);
         lb.finish(i, Cfg::MB);
       }
     });
+    if (more) {
+      la.template store_b3<Cfg::LDK, Cfg::A_PLANE>(nxt);
+      lb.template store_b3<Cfg::LDK, Cfg::B_PLANE>(nxt + 4 * Cfg::A_PLANE);
+    }
     __syncthreads();
   }
 }
@@ -537,18 +582,6 @@ struct LoadDenseKC {
     }
   }
   __device__ __forceinline__ void finish(int, int) {}
-  template <int LDK, int P>
-  __device__ __forceinline__ void store_b3(__bf16* s) {
-    const int kk = threadIdx.x % TPR;
-#pragma unroll
-    for (int j = 0; j < PASSES; ++j) {
-      const int o = threadIdx.x / TPR + j * RPP;
-      T re, im;
-      dense_value<T, S, CONJ>(v[j], ok[j], re, im);
-      split_b16(re, s + o * LDK + kk, s + P + o * LDK + kk);
-      split_b16(im, s + 2 * P + o * LDK + kk, s + 3 * P + o * LDK + kk);
-    }
-  }
   __device__ __forceinline__ void store(T* s) {
     const int kk = threadIdx.x % TPR;
 #pragma unroll
@@ -587,18 +620,6 @@ struct LoadDenseOC {
     }
   }
   __device__ __forceinline__ void finish(int, int) {}
-  template <int LDK, int P>
-  __device__ __forceinline__ void store_b3(__bf16* s) {
-    const int o = threadIdx.x % OUTER;
-#pragma unroll
-    for (int j = 0; j < PASSES; ++j) {
-      const int kk = threadIdx.x / OUTER + j * KPP;
-      T re, im;
-      dense_value<T, S, CONJ>(v[j], ok[j], re, im);
-      split_b16(re, s + o * LDK + kk, s + P + o * LDK + kk);
-      split_b16(im, s + 2 * P + o * LDK + kk, s + 3 * P + o * LDK + kk);
-    }
-  }
   __device__ __forceinline__ void store(T* s) {
     const int o = threadIdx.x % OUTER;
 #pragma unroll
@@ -724,16 +745,6 @@ struct LoadGenCol {
       im[j] = ok[j] ? (CONJ ? -el.im : el.im) : T(0);
     }
   }
-  template <int LDK, int P>
-  __device__ __forceinline__ void store_b3(__bf16* s) {
-    const int o = threadIdx.x % OUTER;
-#pragma unroll
-    for (int j = 0; j < PASSES; ++j) {
-      const int kk = threadIdx.x / OUTER + j * KPP;
-      split_b16(re[j], s + o * LDK + kk, s + P + o * LDK + kk);
-      split_b16(im[j], s + 2 * P + o * LDK + kk, s + 3 * P + o * LDK + kk);
-    }
-  }
   __device__ __forceinline__ void store(T* s_) {
     const int o = threadIdx.x % OUTER;
 #pragma unroll
@@ -846,16 +857,6 @@ struct LoadGenRow {
       im[j] = ok[j] ? (CONJ ? -el.im : el.im) : T(0);
     }
   }
-  template <int LDK, int P>
-  __device__ __forceinline__ void store_b3(__bf16* s) {
-    const int o = threadIdx.x % OUTER;
-#pragma unroll
-    for (int j = 0; j < PASSES; ++j) {
-      const int kk = threadIdx.x / OUTER + j * KPP;
-      split_b16(re[j], s + o * LDK + kk, s + P + o * LDK + kk);
-      split_b16(im[j], s + 2 * P + o * LDK + kk, s + 3 * P + o * LDK + kk);
-    }
-  }
   __device__ __forceinline__ void store(T* s_) {
     const int o = threadIdx.x % OUTER;
 #pragma unroll
@@ -867,5 +868,197 @@ struct LoadGenRow {
     }
   }
 };
+
+// ---------------------------------------------------------------------------
+// Split-precision loaders and epilogue
+// ---------------------------------------------------------------------------
+
+// An SP matrix operand (rows = outer index, k contiguous): per chunk each row
+// is 256 contiguous bytes (four 8-groups of four planes), moved by 16 threads
+// with one 16-byte load and one 16-byte LDS store each.  Rows at or beyond
+// oend load as zeros; k needs no mask (the storage is zero beyond K and every
+// chunk lies within Kp).
+template <class Cfg, int OUTER> struct LoadSP {
+  static constexpr int PPR = Cfg::BK / 8 * 4;        // 16-byte pieces per row and chunk
+  static constexpr int RPP = Cfg::NT / PPR;          // rows per pass
+  static constexpr int PASSES = OUTER / RPP;
+  static_assert(OUTER % RPP == 0, "loader shape");
+  const uint4* p;   // the SP matrix as 16-byte pieces
+  int64_t gpr;      // 8-groups per row (Kp / 8)
+  int o0, oend;
+  uint4 v[PASSES];
+  bool ok[PASSES];
+  __device__ __forceinline__ void fetch(int k0, int) {
+    const int q = threadIdx.x % PPR;   // piece within the row's chunk, in memory order
+#pragma unroll
+    for (int j = 0; j < PASSES; ++j) {
+      const int o = o0 + (int)(threadIdx.x / PPR) + j * RPP;
+      ok[j] = o < oend;
+      const int oc = min(o, oend - 1);
+      v[j] = p[((int64_t)oc * gpr + (k0 >> 3)) * 4 + q];
+    }
+  }
+  __device__ __forceinline__ void finish(int, int) {}
+  template <int LDK, int P>
+  __device__ __forceinline__ void store_b3(__bf16* s) {
+    const int q = threadIdx.x % PPR, g = q >> 2, pl = q & 3;
+#pragma unroll
+    for (int j = 0; j < PASSES; ++j) {
+      const int o = threadIdx.x / PPR + j * RPP;
+      *reinterpret_cast<uint4*>(s + pl * P + o * LDK + 8 * g) = ok[j] ? v[j] : uint4{0, 0, 0, 0};
+    }
+  }
+};
+
+// Generated operand for split-precision tiles: outer index = row m of E, k =
+// column n of E, element (o, k) = E[o, k] (or its conjugate).  Each thread
+// generates KPT consecutive columns of one row and splits them into packed
+// hi/lo words as it goes (finish), so store_b3 only moves 16-byte pieces.
+// ALIGNED as for LoadGenRow.
+template <class Cfg, int OUTER, bool CONJ, int FEAT, bool ALIGNED = false>
+struct LoadGenRowSP {
+  typedef float T;
+  static constexpr int TPR = Cfg::NT / OUTER;        // threads per row
+  static constexpr int KPT = Cfg::BK / TPR;          // consecutive columns per thread
+  static constexpr int GPT = KPT / 8;                // 8-groups per thread
+  static_assert(Cfg::NT % OUTER == 0 && KPT % 8 == 0, "loader shape");
+  EncDev<T> e;
+  bool valid;
+  int c, i, kk0;
+  T ti;
+  bool ok[KPT];
+  GenRaw<T> raw[KPT];
+  uint32_t pk[GPT][4][4];   // [group][plane][word]
+  __device__ __forceinline__ void init(const EncDev<T>& enc, int o0) {
+    e = enc;
+    const int m = o0 + threadIdx.x % OUTER;
+    valid = m < e.M;
+    const int mm = valid ? m : 0;
+    c = mm / e.K;
+    i = mm - c * e.K;
+    kk0 = (int)(threadIdx.x / OUTER) * KPT;
+    if constexpr (ALIGNED && (FEAT & FEAT_B0) != 0) ti = e.t[i];
+  }
+  __device__ __forceinline__ void fetch(int k0, int kend) {
+    if constexpr (ALIGNED) {
+      // the chunk's columns lie in one image row; the start is clamped to the
+      // last full chunk so every table access stays in bounds (ok[] masks)
+      const int n0 = min(k0, e.N - Cfg::BK) + kk0;
+      const int s = n0 / e.V;
+      const int v0 = n0 - s * e.V;
+      const int iy = v0 / e.nx;
+      const int ix0 = v0 - iy * e.nx;
+      const cx<T> py = reinterpret_cast<const cx<T>*>(e.py)[(size_t)i * e.ny + iy];
+      cx<T> q{T(1), T(0)};
+      if constexpr ((FEAT & FEAT_Q) != 0) q = reinterpret_cast<const cx<T>*>(e.q)[(size_t)i * e.S + s];
+      const cx<T>* px = reinterpret_cast<const cx<T>*>(e.px) + (size_t)i * e.nx + ix0;
+      const cx<T>* coil = reinterpret_cast<const cx<T>*>(e.coil) + (size_t)c * e.V + v0;
+#pragma unroll
+      for (int j = 0; j < KPT; ++j) {
+        ok[j] = valid && k0 + kk0 + j < kend;
+        raw[j].px = px[j];
+        raw[j].py = py;
+        if constexpr ((FEAT & FEAT_Q) != 0) raw[j].q = q;
+        if constexpr ((FEAT & FEAT_B0) != 0) raw[j].b0t = e.b0[v0 + j] * ti;
+        if constexpr ((FEAT & FEAT_COIL) != 0) raw[j].coil = coil[j];
+      }
+      return;
+    }
+    const int n = k0 + kk0;
+    if (e.vxy) {   // voxel mask: each column's grid position from the voxel table
+#pragma unroll
+      for (int j = 0; j < KPT; ++j) {
+        const int nj = n + j;
+        ok[j] = valid && nj < kend;
+        const int nn = nj < e.N ? nj : 0;
+        const int s = nn / e.V;
+        const int v = nn - s * e.V;
+        int ix, iy;
+        voxel_xy(e, v, &ix, &iy);
+        gen_load<FEAT>(e, i, s, v, ix, iy, c, raw[j]);
+      }
+      return;
+    }
+    const int nn = n < e.N ? n : 0;
+    int s = nn / e.V;
+    const int v0 = nn - s * e.V;
+    int iy = v0 / e.nx;
+    int ix = v0 - iy * e.nx;
+#pragma unroll
+    for (int j = 0; j < KPT; ++j) {
+      ok[j] = valid && n + j < kend;
+      const bool in = n + j < e.N;
+      gen_load<FEAT>(e, i, in ? s : 0, in ? iy * e.nx + ix : 0, in ? ix : 0, in ? iy : 0, c, raw[j]);
+      if (++ix == e.nx) {
+        ix = 0;
+        if (++iy == e.ny) {
+          iy = 0;
+          ++s;
+        }
+      }
+    }
+  }
+  // Step `step` of `steps` forms and splits its share of the columns, in pairs.
+  __device__ __forceinline__ void finish(int step, int steps) {
+#pragma unroll
+    for (int j = 0; j < KPT; j += 2) {
+      if ((j * steps) / KPT != step) continue;
+      T re[2], im[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const cx<T> el = gen_product<FEAT>(raw[j + u]);
+        re[u] = ok[j + u] ? el.re : T(0);
+        im[u] = ok[j + u] ? (CONJ ? -el.im : el.im) : T(0);
+      }
+      const int g = j >> 3, w = (j & 7) >> 1;
+      split2(re[0], re[1], pk[g][0][w], pk[g][1][w]);
+      split2(im[0], im[1], pk[g][2][w], pk[g][3][w]);
+    }
+  }
+  template <int LDK, int P>
+  __device__ __forceinline__ void store_b3(__bf16* s) {
+    const int o = threadIdx.x % OUTER;
+#pragma unroll
+    for (int g = 0; g < GPT; ++g)
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl)
+        *reinterpret_cast<uint4*>(s + pl * P + o * LDK + kk0 + 8 * g) =
+            uint4{pk[g][pl][0], pk[g][pl][1], pk[g][pl][2], pk[g][pl][3]};
+  }
+};
+
+// Write a split-precision tile's accumulators to an SP matrix Y whose rows
+// are the tile's columns and whose k index is the tile's row: tile element
+// (row, col) goes to Y row col0 + col, k = row0 + row.  Each lane holds four
+// consecutive tile rows of one column (half of an 8-group) and writes 8 bytes
+// per plane.  Rows at or beyond krows and columns at or beyond cols are not
+// written (krows a multiple of 4).
+template <class Cfg>
+__device__ __forceinline__ void acc_store_sp_t(const AccTile<Cfg>& acc, void* Y, int64_t gpr,
+                                               int row0, int col0, int krows, int cols) {
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  const int wr = wid >> 1, wc = wid & 1;
+  char* y = reinterpret_cast<char*>(Y);
+#pragma unroll
+  for (int a = 0; a < Cfg::MB; ++a)
+#pragma unroll
+    for (int b = 0; b < Cfg::NB; ++b) {
+      const int row = row0 + wr * Cfg::WTM + a * 16 + 4 * (lane >> 4);
+      const int col = col0 + wc * Cfg::WTN + b * 16 + (lane & 15);
+      if (row >= krows || col >= cols) continue;
+      uint32_t rh[2], rl[2], ih[2], il[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        split2(acc.re[a][b][2 * u], acc.re[a][b][2 * u + 1], rh[u], rl[u]);
+        split2(acc.im[a][b][2 * u], acc.im[a][b][2 * u + 1], ih[u], il[u]);
+      }
+      char* g = y + ((int64_t)col * gpr + (row >> 3)) * 64 + ((row & 7) >> 2) * 8;
+      *reinterpret_cast<uint2*>(g) = uint2{rh[0], rh[1]};
+      *reinterpret_cast<uint2*>(g + 16) = uint2{rl[0], rl[1]};
+      *reinterpret_cast<uint2*>(g + 32) = uint2{ih[0], ih[1]};
+      *reinterpret_cast<uint2*>(g + 48) = uint2{il[0], il[1]};
+    }
+}
 
 }  // namespace pinv

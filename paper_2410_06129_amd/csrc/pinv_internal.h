@@ -131,10 +131,29 @@ hipError_t launch_psf_gram(const EncDev<double>& e, void* work, double* G, doubl
                            hipStream_t s);
 template <typename T, int MODE, typename SO>
 hipError_t launch_tri_frames(const T* Li, const T* In, int F, int N, SO* Out, hipStream_t s);
-hipError_t launch_trmm_w_b3(const EncDev<float>& e, const float* Li, float* W, hipStream_t s);
-hipError_t launch_trmm_r_b3(const float* Li, const float* W, float* R, int N, int M, hipStream_t s);
+// Split-precision (BF16x3) plans keep their operands split-packed (SP): a
+// complex matrix with k contiguous, rows of sp_cols(K) columns (zero past K),
+// each 8 consecutive k of a row stored as bf16 planes re_hi, re_lo, im_hi,
+// im_lo (64 bytes).
+inline int64_t sp_cols(int64_t K) { return (K + 31) / 32 * 32; }
+// dst (rows x sp_cols(K), SP) from complex src(r, k) = src[r*ld + k] (or
+// src[k*ld + r] with trans), conjugated with conj.
+template <typename S>
+hipError_t launch_sp_pack(const S* src, int64_t ld, int rows, int K, bool trans, bool conj,
+                          void* dst, hipStream_t s);
+// dst (rows x K complex64) = hi + lo of an SP matrix.
+hipError_t launch_sp_unpack(const void* sp, int rows, int K, float* dst, hipStream_t s);
+// W^T (SP, M rows, k = n) from L^-1 (SP, N rows); R (SP, N rows, k = m) from
+// W^T and L^-H (SP, N rows: conj(Li[n'][n]) at row n, k = n').
+hipError_t launch_trmm_w_sp(const EncDev<float>& e, const void* Li, void* W, hipStream_t s);
+hipError_t launch_trmm_r_sp(const void* W, const void* Lh, void* R, int N, int M, hipStream_t s);
+// Grouped apply on SP operands: items carry D (SP, F rows) and R (SP, N rows)
+// with M = the padded contraction length sp_cols(M).
 hipError_t launch_apply_b3(const ApplyBatch& b, Scratch& sc, hipStream_t s);
-size_t apply_scratch_bytes_b3(int F, int N, int M);
+size_t apply_scratch_bytes_b3(int F, int N, int Mp);
+// At most kRowApplyMaxF frames of complex64 data against an SP R.
+hipError_t launch_apply_rows_sp(const void* R, const float* D, float* X, int N, int M, int F,
+                                hipStream_t s);
 hipError_t launch_to_f32(const double* in, float* out, size_t n_complex, hipStream_t s);
 hipError_t launch_to_f64(const float* in, double* out, size_t n_complex, hipStream_t s);
 template <typename T> hipError_t launch_srf_diag(const EncDev<T>& e, const T* R, T* out, hipStream_t s);

@@ -1,0 +1,293 @@
+// Split-precision (BF16x3) products forming R (Eq. 8) and the few-frame apply
+// (Eq. 3) on split-packed operands: each FP32 value is split into bf16 hi/lo
+// once, where it is produced, and stored "split-packed" (SP: per 8 consecutive
+// k of a row, the re_hi, re_lo, im_hi and im_lo planes, 64 bytes).
+//
+//   L^-1 and L^-H (SP, rows n, k = n')  <- the FP64 factor, split once
+//   W^T[m][n]  = sum_{n' <= n} conj(E[m][n']) Li[n][n']    (SP rows m, k = n)
+//   R[n][m]    = sum_{n' >= n} conj(Li[n'][n]) W[n'][m]    (SP rows n, k = m)
+// The W product's tiles are W tiles (rows n, columns m) and the R product's
+// tiles are R^T tiles (rows m, columns n): the MFMA result layout gives each
+// lane four consecutive tile rows of one column, which is the k direction of
+// the SP matrix each product writes.
+#include "pinv_internal.h"
+
+namespace pinv {
+
+// ---------------------------------------------------------------------------
+// Pack / unpack
+// ---------------------------------------------------------------------------
+// dst row r, 8-group g = split(src(r, 8g .. 8g+7)), zero beyond K, where
+// src(r, k) = src[r*ld + k] or, with TRANS, src[k*ld + r]; conjugated with
+// CONJ.  Non-transposed, consecutive threads take consecutive groups of a row
+// (contiguous reads and writes); transposed, consecutive rows of a group
+// (contiguous reads for each k).
+template <typename S, bool TRANS, bool CONJ>
+__global__ __launch_bounds__(256) void k_sp_pack(const S* __restrict__ src, int64_t ld, int rows,
+                                                 int K, int64_t gpr, uint4* __restrict__ dst) {
+  const cx<S>* z = reinterpret_cast<const cx<S>*>(src);
+  const int64_t total = (int64_t)rows * gpr;
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < total;
+       u += (int64_t)gridDim.x * blockDim.x) {
+    int64_t r, g;
+    if constexpr (TRANS) {
+      g = u / rows;
+      r = u - g * rows;
+    } else {
+      r = u / gpr;
+      g = u - r * gpr;
+    }
+    float re[8], im[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int64_t k = g * 8 + j;
+      re[j] = im[j] = 0.f;
+      if (k < K) {
+        const cx<S> v = TRANS ? z[k * ld + r] : z[r * ld + k];
+        re[j] = float(v.re);
+        im[j] = CONJ ? -float(v.im) : float(v.im);
+      }
+    }
+    uint4 o[4];
+    sp_group(re, im, o);
+#pragma unroll
+    for (int p = 0; p < 4; ++p) dst[(r * gpr + g) * 4 + p] = o[p];
+  }
+}
+
+// dst[r][k] (complex64, row length K) = hi + lo of SP row r.
+__global__ __launch_bounds__(256) void k_sp_unpack(const uint4* __restrict__ sp, int64_t gpr,
+                                                   int rows, int K, float* __restrict__ dst) {
+  cx<float>* d = reinterpret_cast<cx<float>*>(dst);
+  const int64_t total = (int64_t)rows * gpr;
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < total;
+       u += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = u / gpr, g = u - r * gpr;
+    uint4 q[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) q[p] = sp[u * 4 + p];
+    const uint32_t rh[4] = {q[0].x, q[0].y, q[0].z, q[0].w}, rl[4] = {q[1].x, q[1].y, q[1].z, q[1].w};
+    const uint32_t ih[4] = {q[2].x, q[2].y, q[2].z, q[2].w}, il[4] = {q[3].x, q[3].y, q[3].z, q[3].w};
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int64_t k = g * 8 + j;
+      if (k < K) d[r * K + k] = cx<float>{join2(rh[j >> 1], rl[j >> 1], j & 1), join2(ih[j >> 1], il[j >> 1], j & 1)};
+    }
+  }
+}
+
+static int pack_blocks(int64_t total) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 16384));
+}
+
+template <typename S>
+hipError_t launch_sp_pack(const S* src, int64_t ld, int rows, int K, bool trans, bool conj,
+                          void* dst, hipStream_t s) {
+  const int64_t gpr = sp_cols(K) / 8, total = (int64_t)rows * gpr;
+  if (total <= 0) return hipSuccess;
+  uint4* o = reinterpret_cast<uint4*>(dst);
+  const dim3 grid(pack_blocks(total)), block(256);
+  if (trans && conj)
+    hipLaunchKernelGGL((k_sp_pack<S, true, true>), grid, block, 0, s, src, ld, rows, K, gpr, o);
+  else if (trans)
+    hipLaunchKernelGGL((k_sp_pack<S, true, false>), grid, block, 0, s, src, ld, rows, K, gpr, o);
+  else if (conj)
+    hipLaunchKernelGGL((k_sp_pack<S, false, true>), grid, block, 0, s, src, ld, rows, K, gpr, o);
+  else
+    hipLaunchKernelGGL((k_sp_pack<S, false, false>), grid, block, 0, s, src, ld, rows, K, gpr, o);
+  return hipGetLastError();
+}
+
+hipError_t launch_sp_unpack(const void* sp, int rows, int K, float* dst, hipStream_t s) {
+  const int64_t gpr = sp_cols(K) / 8, total = (int64_t)rows * gpr;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sp_unpack, dim3(pack_blocks(total)), dim3(256), 0, s,
+                     reinterpret_cast<const uint4*>(sp), gpr, rows, K, dst);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// W^T = (L^-1 E^H)^T, written SP with rows m and k = n
+// ---------------------------------------------------------------------------
+template <int FEAT, bool AL>
+__global__ __launch_bounds__(256) void k_trmm_w_sp(EncDev<float> e, const uint4* __restrict__ Li,
+                                                   int64_t gn, void* __restrict__ W) {
+  typedef B3Cfg Cfg;
+  const int N = e.N, M = e.M;
+  const int nbi = (N + Cfg::BM - 1) / Cfg::BM, nbj = (M + Cfg::BN - 1) / Cfg::BN;
+  // as the FP32 product: each XCD runs column groups of 8 sample blocks over
+  // every row block, longest K ranges first
+  int r, bj;
+  grouped_tile<8>(xcd_contiguous(blockIdx.x, nbi * nbj), nbi, nbj, &r, &bj);
+  const int bi = nbi - 1 - r;
+  LoadSP<Cfg, Cfg::BM> la;   // L^-1 rows n (zero above the diagonal and past N)
+  la.p = Li;
+  la.gpr = gn;
+  la.o0 = bi * Cfg::BM;
+  la.oend = N;
+  LoadGenRowSP<Cfg, Cfg::BN, true, FEAT, AL> lb;   // conj(E[m][n'])
+  lb.init(e, bj * Cfg::BN);
+  AccTile<Cfg> acc;
+  acc.zero();
+  mainloop<Cfg>(la, lb, 0, min(N, (bi + 1) * Cfg::BM), acc, smem_base<Cfg>());
+  // rows N .. Np of W^T's k range come out zero (their L^-1 rows load as zeros)
+  acc_store_sp_t<Cfg>(acc, W, gn, bi * Cfg::BM, bj * Cfg::BN, (int)(gn * 8), M);
+}
+
+// ---------------------------------------------------------------------------
+// R^T tiles: R^T[m][n] = sum_{n' >= n} W^T[m][n'] conj(Li[n'][n]), written SP
+// as R with rows n and k = m
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_trmm_r_sp(const uint4* __restrict__ W,
+                                                   const uint4* __restrict__ Lh, int64_t gn,
+                                                   void* __restrict__ R, int64_t gm, int N, int M) {
+  typedef B3Cfg Cfg;
+  const int nbm = (M + Cfg::BM - 1) / Cfg::BM, nbn = (N + Cfg::BN - 1) / Cfg::BN;
+  // each XCD runs groups of 8 sample blocks over every unknown block (so the
+  // XCDs' shares of the triangle are equal), the longest K ranges first, and
+  // the contraction runs from n' = N down, so resident tiles read the same
+  // W^T and L^-H chunks at the same time
+  int bn, bm;
+  grouped_tile<8>(xcd_contiguous(blockIdx.x, nbm * nbn), nbn, nbm, &bn, &bm);
+  LoadSP<Cfg, Cfg::BM> la;   // W^T rows m
+  la.p = W;
+  la.gpr = gn;
+  la.o0 = bm * Cfg::BM;
+  la.oend = M;
+  LoadSP<Cfg, Cfg::BN> lb;   // L^-H rows n: conj(Li[n'][n]), zero for n' < n
+  lb.p = Lh;
+  lb.gpr = gn;
+  lb.o0 = bn * Cfg::BN;
+  lb.oend = N;
+  AccTile<Cfg> acc;
+  acc.zero();
+  mainloop<Cfg, true, true>(la, lb, bn * Cfg::BN, N, acc, smem_base<Cfg>());
+  // R's k range M .. Mp comes out zero (W^T rows past M load as zeros)
+  acc_store_sp_t<Cfg>(acc, R, gm, bm * Cfg::BM, bn * Cfg::BN, (int)(gm * 8), N);
+}
+
+hipError_t launch_trmm_w_sp(const EncDev<float>& e, const void* Li, void* W, hipStream_t s) {
+  typedef B3Cfg Cfg;
+  const int tiles = cdiv(e.N, Cfg::BM) * cdiv(e.M, Cfg::BN);
+  if (tiles == 0) return hipSuccess;
+  const int64_t gn = sp_cols(e.N) / 8;
+  return with_feat_al(enc_features(e), row_aligned(e, Cfg::BK), [&](auto fc, auto al) {
+    auto kern = k_trmm_w_sp<decltype(fc)::value, decltype(al)::value>;
+    // once per kernel (thread-safe static initialisation)
+    static const hipError_t attr = allow_smem(kern, smem_bytes<Cfg>());
+    if (attr != hipSuccess) return attr;
+    hipLaunchKernelGGL(kern, dim3(tiles), dim3(256), smem_bytes<Cfg>(), s, e,
+                       reinterpret_cast<const uint4*>(Li), gn, W);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_trmm_r_sp(const void* W, const void* Lh, void* R, int N, int M, hipStream_t s) {
+  typedef B3Cfg Cfg;
+  static const hipError_t attr = allow_smem(k_trmm_r_sp, smem_bytes<Cfg>());
+  if (attr != hipSuccess) return attr;
+  const int tiles = cdiv(N, Cfg::BN) * cdiv(M, Cfg::BM);
+  if (tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_trmm_r_sp, dim3(tiles), dim3(256), smem_bytes<Cfg>(), s,
+                     reinterpret_cast<const uint4*>(W), reinterpret_cast<const uint4*>(Lh),
+                     sp_cols(N) / 8, R, sp_cols(M) / 8, N, M);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// A few frames: stream R's SP rows (HBM-bound), as the FP32 row apply
+// ---------------------------------------------------------------------------
+// Each lane takes whole 8-groups: 64 bytes of R (four 16-byte loads) and the
+// matching eight data values of each frame; R = hi + lo is exact in FP32, so
+// the products and sums are those of the FP32 row apply on that R.
+template <int FM, int RW>
+__global__ __launch_bounds__(256) void k_apply_rows_sp(const uint4* __restrict__ R, int64_t gpr,
+                                                       const float* __restrict__ D,
+                                                       float* __restrict__ X, int N, int M, int F) {
+  const int lane = threadIdx.x & 63;
+  const int n0 = (blockIdx.x * 4 + (int)(threadIdx.x >> 6)) * RW;
+  if (n0 >= N) return;   // the whole wavefront leaves; no barrier follows
+  const uint4* r[RW];
+#pragma unroll
+  for (int j = 0; j < RW; ++j)   // rows past N re-read row N-1 and are not written
+    r[j] = R + (int64_t)min(n0 + j, N - 1) * gpr * 4;
+  const cx<float>* d = reinterpret_cast<const cx<float>*>(D);
+  float ar[RW][FM], ai[RW][FM];
+#pragma unroll
+  for (int j = 0; j < RW; ++j)
+#pragma unroll
+    for (int f = 0; f < FM; ++f) ar[j][f] = ai[j][f] = 0.f;
+  for (int64_t g = lane; g < gpr; g += 64) {
+    float rr[RW][8], ri[RW][8];
+#pragma unroll
+    for (int j = 0; j < RW; ++j) {
+      const uint4 h = r[j][g * 4 + 0], l = r[j][g * 4 + 1], hi = r[j][g * 4 + 2], li = r[j][g * 4 + 3];
+      const uint32_t a[4] = {h.x, h.y, h.z, h.w}, b[4] = {l.x, l.y, l.z, l.w};
+      const uint32_t c[4] = {hi.x, hi.y, hi.z, hi.w}, e[4] = {li.x, li.y, li.z, li.w};
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        rr[j][u] = join2(a[u >> 1], b[u >> 1], u & 1);
+        ri[j][u] = join2(c[u >> 1], e[u >> 1], u & 1);
+      }
+    }
+#pragma unroll
+    for (int f = 0; f < FM; ++f) {
+      if (f >= F) break;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t m = g * 8 + u;
+        if (m >= M) break;   // R is zero there; the data has no such column
+        const cx<float> dv = d[(int64_t)f * M + m];
+#pragma unroll
+        for (int j = 0; j < RW; ++j) {
+          ar[j][f] += dv.re * rr[j][u] - dv.im * ri[j][u];
+          ai[j][f] += dv.re * ri[j][u] + dv.im * rr[j][u];
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < RW; ++j)
+#pragma unroll
+    for (int f = 0; f < FM; ++f) {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        ar[j][f] += __shfl_xor(ar[j][f], off);
+        ai[j][f] += __shfl_xor(ai[j][f], off);
+      }
+    }
+  if (lane == 0) {
+    cx<float>* x = reinterpret_cast<cx<float>*>(X);
+#pragma unroll
+    for (int j = 0; j < RW; ++j)
+#pragma unroll
+      for (int f = 0; f < FM; ++f)
+        if (f < F && n0 + j < N) x[(size_t)f * N + n0 + j] = cx<float>{ar[j][f], ai[j][f]};
+  }
+}
+
+hipError_t launch_apply_rows_sp(const void* R, const float* D, float* X, int N, int M, int F,
+                                hipStream_t s) {
+  if (F <= 0 || N <= 0) return hipSuccess;
+  if (F > kRowApplyMaxF) return hipErrorInvalidValue;
+  const uint4* r = reinterpret_cast<const uint4*>(R);
+  const int64_t gpr = sp_cols(M) / 8;
+  auto go = [&](auto fm, auto rw) {
+    constexpr int FM = decltype(fm)::value, RW = decltype(rw)::value;
+    hipLaunchKernelGGL((k_apply_rows_sp<FM, RW>), dim3(cdiv(N, 4 * RW)), dim3(256), 0, s, r, gpr, D,
+                       X, N, M, F);
+    return hipGetLastError();
+  };
+  using std::integral_constant;
+  if (F <= 1) return go(integral_constant<int, 1>(), integral_constant<int, 1>());
+  if (F <= 2) return go(integral_constant<int, 2>(), integral_constant<int, 4>());
+  if (F <= 4) return go(integral_constant<int, 4>(), integral_constant<int, 4>());
+  return go(integral_constant<int, 8>(), integral_constant<int, 2>());
+}
+
+template hipError_t launch_sp_pack<float>(const float*, int64_t, int, int, bool, bool, void*,
+                                          hipStream_t);
+template hipError_t launch_sp_pack<double>(const double*, int64_t, int, int, bool, bool, void*,
+                                           hipStream_t);
+
+}  // namespace pinv

@@ -196,29 +196,6 @@ hipError_t launch_trmm_r(const T* Li, const T* W, TO* R, int N, int M, bool m3, 
   });
 }
 
-// BF16x3 variants of the FP32-typed products (same kernels, split-precision mainloop)
-hipError_t launch_trmm_w_b3(const EncDev<float>& e, const float* Li, float* W, hipStream_t s) {
-  typedef B3Cfg Cfg;
-  const int tiles = cdiv(e.N, Cfg::BM) * cdiv(e.M, Cfg::BN);
-  return with_feat_al(enc_features(e), row_aligned(e, Cfg::BK), [&](auto fc, auto al) {
-    auto kern = k_trmm_w<Cfg, decltype(fc)::value, decltype(al)::value>;
-    // once per kernel (thread-safe static initialisation)
-    static const hipError_t attr = allow_smem(kern, smem_bytes<Cfg>());
-    if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL(kern, dim3(tiles), dim3(256), smem_bytes<Cfg>(), s, e, Li, W, e.N, 1);
-    return hipGetLastError();
-  });
-}
-
-hipError_t launch_trmm_r_b3(const float* Li, const float* W, float* R, int N, int M, hipStream_t s) {
-  typedef B3Cfg Cfg;
-  static const hipError_t attr = allow_smem(k_trmm_r<Cfg>, smem_bytes<Cfg>());
-  if (attr != hipSuccess) return attr;
-  const int tiles = cdiv(N, Cfg::BM) * cdiv(M, Cfg::BN);
-  hipLaunchKernelGGL(k_trmm_r<Cfg>, dim3(tiles), dim3(256), smem_bytes<Cfg>(), s, Li, W, R, N, M, N, 1);
-  return hipGetLastError();
-}
-
 // explicit instantiations
 template hipError_t launch_right_pinv<float, float>(const EncDev<float>&, const float*, float*,
                                                     float*, float*, bool, hipStream_t);

@@ -69,15 +69,20 @@ def build(P, ctx, w, prec):
 def tol_for(prec, kappa, quadratic=False):
     if prec == "fp64":
         return 1e-9
-    return kappa * (2e-6 if quadratic else 1e-6)
+    # BF16-split products carry ~2^-16 per product against FP32's 2^-24
+    unit = 1e-4 if prec == "bf16x3" else 1e-6
+    return kappa * (2 * unit if quadratic else unit)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+PRECS = {"fp64": "FP64", "fp32": "FP32", "bf16x3": "BF16X3"}
+
+
+@pytest.mark.parametrize("prec", list(PRECS))
 @pytest.mark.parametrize("name", list(CASES))
 def test_srf_matches_oracle(P, ctx, name, prec):
     o = case(name)
     w, N = o["w"], o["w"].enc.N
-    p = build(P, ctx, w, P.FP64 if prec == "fp64" else P.FP32)
+    p = build(P, ctx, w, getattr(P, PRECS[prec]))
     cdt = torch.complex128 if prec == "fp64" else torch.complex64
     try:
         dg = torch.full((N,), float("nan"), dtype=cdt, device="cuda")
@@ -98,13 +103,13 @@ def test_srf_matches_oracle(P, ctx, name, prec):
 
 
 @pytest.mark.parametrize("coils", ["white", "correlated"])
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", list(PRECS))
 @pytest.mark.parametrize("name", list(CASES))
 def test_noise_matches_oracle(P, ctx, name, prec, coils):
     o = case(name)
     w, N, K, C = o["w"], o["w"].enc.N, o["w"].enc.K, o["w"].enc.C
     psi_c = o["psi_c"] if coils == "correlated" else None
-    p = build(P, ctx, w, P.FP64 if prec == "fp64" else P.FP32)
+    p = build(P, ctx, w, getattr(P, PRECS[prec]))
     cdt = torch.complex128 if prec == "fp64" else torch.complex64
     rdt = torch.float64 if prec == "fp64" else torch.float32
     try:

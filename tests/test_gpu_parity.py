@@ -182,20 +182,62 @@ def test_bf16x3_path_matches_oracle(P, ctx, name):
     before refinement within kappa * 1e-4, after two steps within 3e-3 (the BF16-split
     target) -- in practice FP32-level since the correction uses the FP32 factor."""
     o = oracle_case(name)
-    enc, N = o["w"].enc, o["w"].enc.N
+    enc, N, M = o["w"].enc, o["w"].enc.N, o["w"].enc.M
     plan = build(P, ctx, enc, P.BF16X3)
     d = to_dev(o["d"], np.complex64)
     x0 = torch.empty((d.shape[0], N), dtype=torch.complex64, device="cuda")
     P.pinv_apply(ctx, plan, d, x0, refine_steps=0)
     x2 = torch.empty_like(x0)
     P.pinv_apply(ctx, plan, d, x2, refine_steps=2)
+    R = torch.full((N, M), float("nan"), dtype=torch.complex64, device="cuda")
+    P.pinv_plan_copy_buffer(plan, P.BUF_R, R)    # unpacked from the split-packed R
     torch.cuda.synchronize()
     e0 = frame_rel(x0.cpu().numpy().astype(np.complex128), o["x"])
     e2 = frame_rel(x2.cpu().numpy().astype(np.complex128), o["x"])
-    print(f"{name}: bf16x3 err0={e0.max():.2e} err2={e2.max():.2e}")
+    eR = max_rel_entry(R.cpu().numpy().astype(np.complex128), o["R"])
+    print(f"{name}: bf16x3 err0={e0.max():.2e} err2={e2.max():.2e} R {eR:.2e}")
+    assert eR < o["kappa"] * 1e-4
     assert e0.max() < o["kappa"] * 1e-4
     assert e2.max() < 3e-3
     P.pinv_plan_release(plan)
+
+
+@pytest.mark.parametrize("name", ["ragged_c3", "aligned_c2"])
+def test_bf16x3_apply_paths(P, ctx, name):
+    """A BF16X3 plan keeps R split into bf16 hi/lo planes (rows padded to a
+    multiple of 32 columns: M = 2100 leaves a ragged 8-group and padding).
+    Its applies of at most 8 frames stream those rows and multiply by hi + lo
+    in FP32; more frames split the data too and run BF16x3 tiles.  Both
+    against the plan's own R (copied out as complex64, so exact) applied in
+    FP64: rows within 1e-5 (FP32 sums), tiles within 2e-4 (the data's split
+    adds ~2^-16 per product); and against the oracle's R at kappa * 1e-4."""
+    o = oracle_case(name)
+    w, N, M = o["w"], o["w"].enc.N, o["w"].enc.M
+    rng = np.random.default_rng(37)
+    Fmax = 150
+    d = rng.standard_normal((Fmax, M)) + 1j * rng.standard_normal((Fmax, M))
+    d = d.astype(np.complex64).astype(np.complex128)
+    plan = build(P, ctx, w.enc, P.BF16X3, flags=P.FLAG_UNCACHED)
+    try:
+        R = torch.full((N, M), float("nan"), dtype=torch.complex64, device="cuda")
+        P.pinv_plan_copy_buffer(plan, P.BUF_R, R)
+        torch.cuda.synchronize()
+        Rp = R.cpu().numpy().astype(np.complex128)
+        assert np.all(np.isfinite(Rp))
+        x_own, x_or = d @ Rp.T, d @ o["R"].T
+        for F in (1, 3, 8, 9, 40, Fmax):
+            dd = to_dev(d[:F], np.complex64)
+            x = torch.full((F, N), float("nan"), dtype=torch.complex64, device="cuda")
+            torch.cuda.synchronize()
+            P.pinv_apply(ctx, plan, dd, x)
+            torch.cuda.synchronize()
+            xg = x.cpu().numpy().astype(np.complex128)
+            e_own, e_or = frame_rel(xg, x_own[:F]).max(), frame_rel(xg, x_or[:F]).max()
+            print(f"{name} F={F}: vs own R {e_own:.2e}, vs oracle R {e_or:.2e}")
+            assert e_own < (1e-5 if F <= 8 else 2e-4), (F, e_own)
+            assert e_or < o["kappa"] * 1e-4, (F, e_or)
+    finally:
+        P.pinv_plan_release(plan)
 
 
 @pytest.mark.parametrize("name", ["ragged_c3", "aligned_c2"])
