@@ -1280,6 +1280,11 @@ size_t item_scratch_bytes(const pinv_plan* p, int F, int steps) {
   const size_t ts = p->prec == PINV_FP64 ? 8 : 4;
   size_t peak = 0;
   const bool tiles = F > kRowApplyMaxF && !p->no_r && !(p->right && steps > 0);
+  if (F <= kRowApplyMaxF && !p->no_r && !(p->right && steps > 0)) {
+    // the row apply's per-slice partial images
+    peak = p->prec == PINV_FP64 ? apply_rows_scratch_bytes<double>(F, (int)N, (int)M)
+                                : apply_rows_scratch_bytes<float>(F, (int)N, (int)M);
+  }
   if (tiles) {
     // a BF16X3 item's data is split-packed first (F x sp_cols(M), 8 bytes each)
     const size_t Mp = sp_cols(M);
@@ -1390,13 +1395,13 @@ extern "C++" pinv_status apply_items(pinv_context* c, int32_t n, const pinv_appl
     if (p->no_r || F <= 0 || F > kRowApplyMaxF || (p->right && refine_steps > 0)) continue;
     if (p->prec == PINV_FP64)
       HIPCHK(launch_apply_rows<double>((const double*)p->R, (const double*)items[j].data,
-                                       (double*)items[j].image, p->N, p->M, F, s));
+                                       (double*)items[j].image, p->N, p->M, F, sc, s));
     else if (p->prec == PINV_BF16X3)
       HIPCHK(launch_apply_rows_sp(p->R, (const float*)items[j].data, (float*)items[j].image, p->N,
-                                  p->M, F, s));
+                                  p->M, F, sc, s));
     else
       HIPCHK(launch_apply_rows<float>((const float*)p->R, (const float*)items[j].data,
-                                      (float*)items[j].image, p->N, p->M, F, s));
+                                      (float*)items[j].image, p->N, p->M, F, sc, s));
   }
   for (int j = 0; j < n; ++j) {
     pinv_plan* p = (pinv_plan*)items[j].plan;

@@ -26,7 +26,7 @@ namespace pinv {
 constexpr int kApplySegRows = 4096;
 
 template <class Cfg, bool SEG = false>
-__global__ __launch_bounds__(256) void k_apply(const ApplyBatch batch) {
+__global__ __launch_bounds__(Cfg::NT) void k_apply(const ApplyBatch batch) {
   typedef typename Cfg::T T;
   // locate the item owning this tile (items carry exclusive tile prefix sums)
   int lo = 0, hi = batch.n - 1;
@@ -134,16 +134,25 @@ __global__ __launch_bounds__(256) void k_apply_reduce(const ApplyBatch batch) {
 // streaming RW rows of R.  At small F each element of R feeds only F
 // multiply-adds, so the apply is bound by memory bandwidth, not by MFMA: rows
 // stream through wide coalesced loads (two complex64 per lane and load when
-// VEC = 2), and each data element loaded serves RW rows, which keeps the
-// data's cache traffic (F / RW times that of R) below R's own.  Every wave
-// reduces its lane partial sums in a fixed butterfly order, so a result
-// depends only on its own row and frame.
+// VEC = 2), and each data element loaded serves RW rows.  Every wave reduces
+// its lane partial sums in a fixed butterfly order, so a result depends only
+// on its own row and frame.
+//
+// The contraction over M is cut into `nseg` slices (kRowSlices = one per XCD
+// for long rows): workgroup b takes slice b % nseg, and the dispatcher deals
+// workgroups round-robin over the XCDs, so every XCD streams one slice of
+// every row of R and its L2 holds that slice of the data, which the waves on
+// the XCD re-read for their rows.  With nseg > 1 each slice writes its partial
+// images to P[slice][F][N] and k_rows_reduce adds them in slice order.
 template <typename T, int FM, int RW, int VEC>
 __global__ __launch_bounds__(256) void k_apply_rows(const T* __restrict__ R, const T* __restrict__ D,
-                                                    T* __restrict__ X, int N, int M, int F) {
+                                                    T* __restrict__ X, int N, int M, int F, int nseg,
+                                                    int seg_len) {
   const int lane = threadIdx.x & 63;
-  const int n0 = (blockIdx.x * 4 + (int)(threadIdx.x >> 6)) * RW;
+  const int seg = blockIdx.x % nseg;
+  const int n0 = ((blockIdx.x / nseg) * 4 + (int)(threadIdx.x >> 6)) * RW;
   if (n0 >= N) return;   // the whole wavefront leaves; no barrier follows
+  const int m_lo = seg * seg_len, m_hi = min(M, m_lo + seg_len);
   const cx<T>* r[RW];
 #pragma unroll
   for (int j = 0; j < RW; ++j)   // rows past N re-read row N-1 and are not written
@@ -154,12 +163,13 @@ __global__ __launch_bounds__(256) void k_apply_rows(const T* __restrict__ R, con
   for (int j = 0; j < RW; ++j)
 #pragma unroll
     for (int f = 0; f < FM; ++f) ar[j][f] = ai[j][f] = T(0);
-  for (int m0 = lane * VEC; m0 < M; m0 += 64 * VEC) {
+  for (int m0 = m_lo + lane * VEC; m0 < m_hi; m0 += 64 * VEC) {
     cx<T> rv[RW][VEC];
 #pragma unroll
     for (int j = 0; j < RW; ++j) {
       if constexpr (VEC == 2) {
-        // M even and 16-byte aligned rows (checked by the launcher): m0 + 1 < M
+        // M even, slices of even length and 16-byte aligned rows (checked by
+        // the launcher): m0 + 1 < m_hi
         const float4 q = *reinterpret_cast<const float4*>(r[j] + m0);
         rv[j][0] = cx<T>{q.x, q.y};
         rv[j][1] = cx<T>{q.z, q.w};
@@ -192,12 +202,29 @@ __global__ __launch_bounds__(256) void k_apply_rows(const T* __restrict__ R, con
       }
     }
   if (lane == 0) {
-    cx<T>* x = reinterpret_cast<cx<T>*>(X);
+    cx<T>* x = reinterpret_cast<cx<T>*>(X) + (size_t)seg * F * N;
 #pragma unroll
     for (int j = 0; j < RW; ++j)
 #pragma unroll
       for (int f = 0; f < FM; ++f)
         if (f < F && n0 + j < N) x[(size_t)f * N + n0 + j] = cx<T>{ar[j][f], ai[j][f]};
+  }
+}
+
+// X = sum_s P[s] over the slices, in slice order (n complex values each).
+template <typename T>
+__global__ __launch_bounds__(256) void k_rows_reduce(const T* __restrict__ P, int nseg, int64_t n,
+                                                     T* __restrict__ X) {
+  const cx<T>* p = reinterpret_cast<const cx<T>*>(P);
+  cx<T>* x = reinterpret_cast<cx<T>*>(X);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    T zr = p[i].re, zi = p[i].im;
+    for (int s = 1; s < nseg; ++s) {
+      zr += p[(int64_t)s * n + i].re;
+      zi += p[(int64_t)s * n + i].im;
+    }
+    x[i] = cx<T>{zr, zi};
   }
 }
 
@@ -212,8 +239,8 @@ __global__ __launch_bounds__(256) void k_apply_rows(const T* __restrict__ R, con
 // most 32 frames run on 32x128 tiles: a 128-frame tile would spend most of
 // its matrix products on padding rows.
 template <typename T, bool M3> struct ApplyCfgOf;
-template <> struct ApplyCfgOf<float, true> { typedef F32Cfg many; typedef TileCfg<float, 32, 128, 8, true> few; };
-template <> struct ApplyCfgOf<float, false> { typedef F32Cfg4 many; typedef TileCfg<float, 32, 128, 8, false> few; };
+template <> struct ApplyCfgOf<float, true> { typedef F32Cfg many; typedef TileCfg<float, 32, 128, 16, true> few; };
+template <> struct ApplyCfgOf<float, false> { typedef F32Cfg4 many; typedef TileCfg<float, 32, 128, 16, false> few; };
 template <> struct ApplyCfgOf<double, true> { typedef F64Cfg3 many; typedef F64Cfg3 few; };
 template <> struct ApplyCfgOf<double, false> { typedef F64Cfg many; typedef F64Cfg few; };
 constexpr int kFewFramesMaxF = 32;
@@ -234,7 +261,7 @@ template <class Cfg> static void plan_item(ApplyItemDev& it, int slots) {
 template <class Cfg, bool SEG> static int apply_slots() {
   static const hipError_t attr = allow_smem(k_apply<Cfg, SEG>, smem_bytes<Cfg>());
   (void)attr;
-  return resident_blocks(k_apply<Cfg, SEG>, 256, smem_bytes<Cfg>());
+  return resident_blocks(k_apply<Cfg, SEG>, Cfg::NT, smem_bytes<Cfg>());
 }
 
 template <class Cfg, bool SEG> static size_t item_work_bytes(int F, int N, int M) {
@@ -277,7 +304,7 @@ static hipError_t run_apply(ApplyBatch b, Scratch& sc, hipStream_t s) {
         off += (size_t)b.it[i].splits * b.it[i].F * b.it[i].N;
       }
   }
-  hipLaunchKernelGGL((k_apply<Cfg, SEG>), dim3(tiles), dim3(256), smem_bytes<Cfg>(), s, b);
+  hipLaunchKernelGGL((k_apply<Cfg, SEG>), dim3(tiles), dim3(Cfg::NT), smem_bytes<Cfg>(), s, b);
   hipError_t err = hipGetLastError();
   if (nsplit) {
     if (err == hipSuccess) {
@@ -336,33 +363,66 @@ size_t apply_scratch_bytes(int F, int N, int M, bool m3, bool seg) {
   return m3 ? go(std::true_type{}, std::false_type{}) : go(std::false_type{}, std::false_type{});
 }
 
+// Slices of the row apply's contraction: one per XCD when rows are long
+// enough that a slice still spans several wave-wide passes, else one.
+int row_slices(int M) { return M >= kRowSliceMinM ? kXcds : 1; }
+
 template <typename T>
-hipError_t launch_apply_rows(const T* R, const T* D, T* X, int N, int M, int F, hipStream_t s) {
+size_t apply_rows_scratch_bytes(int F, int N, int M) {
+  const int nseg = row_slices(M);
+  return nseg > 1 ? (size_t)nseg * F * N * 2 * sizeof(T) : 0;
+}
+
+template <typename T>
+hipError_t launch_apply_rows(const T* R, const T* D, T* X, int N, int M, int F, Scratch& sc,
+                             hipStream_t s) {
   if (F <= 0 || N <= 0) return hipSuccess;
   if (F > kRowApplyMaxF) return hipErrorInvalidValue;
   const bool vec = M % 2 == 0 && ((uintptr_t)R % 16) == 0 && ((uintptr_t)D % 16) == 0;
+  const int nseg = row_slices(M);
+  // slice length: a multiple of one wave-wide pass (128 complex values)
+  const int seg_len = nseg > 1 ? cdiv(cdiv(M, nseg), 128) * 128 : M;
+  void* P = nullptr;
+  if (nseg > 1) {
+    const hipError_t e = sc.get(&P, apply_rows_scratch_bytes<T>(F, N, M), s);
+    if (e != hipSuccess) return e;
+  }
+  T* out = nseg > 1 ? (T*)P : X;
   auto go = [&](auto fm, auto rw) {
     constexpr int FM = decltype(fm)::value, RW = decltype(rw)::value;
-    const dim3 grid(cdiv(N, 4 * RW)), block(256);
+    const dim3 grid(cdiv(N, 4 * RW) * nseg), block(256);
     if constexpr (sizeof(T) == 4) {
       if (vec) {
-        hipLaunchKernelGGL((k_apply_rows<T, FM, RW, 2>), grid, block, 0, s, R, D, X, N, M, F);
+        hipLaunchKernelGGL((k_apply_rows<T, FM, RW, 2>), grid, block, 0, s, R, D, out, N, M, F, nseg,
+                           seg_len);
         return hipGetLastError();
       }
     }
-    hipLaunchKernelGGL((k_apply_rows<T, FM, RW, 1>), grid, block, 0, s, R, D, X, N, M, F);
+    hipLaunchKernelGGL((k_apply_rows<T, FM, RW, 1>), grid, block, 0, s, R, D, out, N, M, F, nseg,
+                       seg_len);
     return hipGetLastError();
   };
   // rows per wave: as many as keep the accumulators (2 FM RW values) within
   // 64 registers
   using std::integral_constant;
   constexpr int W = sizeof(T) == 4 ? 4 : 2;
-  if (F <= 1) return go(integral_constant<int, 1>(), integral_constant<int, 1>());
-  if (F <= 2) return go(integral_constant<int, 2>(), integral_constant<int, W>());
-  if (F <= 4) return go(integral_constant<int, 4>(), integral_constant<int, W>());
-  return go(integral_constant<int, 8>(), integral_constant<int, W / 2 * 2 == 4 ? 4 : 2>());
+  hipError_t e;
+  if (F <= 1) e = go(integral_constant<int, 1>(), integral_constant<int, 1>());
+  else if (F <= 2) e = go(integral_constant<int, 2>(), integral_constant<int, W>());
+  else if (F <= 4) e = go(integral_constant<int, 4>(), integral_constant<int, W>());
+  else e = go(integral_constant<int, 8>(), integral_constant<int, W>());
+  if (nseg > 1) {
+    if (e == hipSuccess) {
+      const int64_t n = (int64_t)F * N;
+      hipLaunchKernelGGL(k_rows_reduce<T>, dim3((unsigned)std::min<int64_t>(cdiv(n, 256), 4096)),
+                         dim3(256), 0, s, (const T*)P, nseg, n, X);
+      e = hipGetLastError();
+    }
+    const hipError_t f = sc.put(P, s);
+    if (e == hipSuccess) e = f;
+  }
+  return e;
 }
-
 
 hipError_t launch_apply_b3(const ApplyBatch& b, Scratch& sc, hipStream_t s) {
   return run_apply<B3Cfg>(b, sc, s);
@@ -376,8 +436,10 @@ template hipError_t launch_apply<double>(const ApplyBatch&, bool, bool, Scratch&
 template size_t apply_scratch_bytes<float>(int, int, int, bool, bool);
 template size_t apply_scratch_bytes<double>(int, int, int, bool, bool);
 template hipError_t launch_apply_rows<float>(const float*, const float*, float*, int, int, int,
-                                             hipStream_t);
+                                             Scratch&, hipStream_t);
 template hipError_t launch_apply_rows<double>(const double*, const double*, double*, int, int, int,
-                                              hipStream_t);
+                                              Scratch&, hipStream_t);
+template size_t apply_rows_scratch_bytes<float>(int, int, int);
+template size_t apply_rows_scratch_bytes<double>(int, int, int);
 
 }  // namespace pinv

@@ -93,6 +93,7 @@ template <typename T_, int BM_, int BN_, int BK_, bool M3_ = false> struct TileC
   static constexpr bool M3 = M3_;
   static constexpr int PLANES = M3 ? 3 : 2;
   static constexpr int NT = 256;                 // 4 wavefronts in a 2x2 grid
+  static constexpr int WGN = 2;                  // wavefronts along N
   static constexpr int WTM = BM / 2, WTN = BN / 2;
   static constexpr int MB = WTM / 16, NB = WTN / 16;
   // FP64 3M tiles pad rows by 4 doubles: two stages then take 51 KB of LDS,
@@ -140,7 +141,7 @@ __device__ __forceinline__ void tile_compute(const typename Cfg::T* __restrict__
   typedef typename Cfg::T T;
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
-  const int wr = wid >> 1, wc = wid & 1;
+  const int wr = wid / Cfg::WGN, wc = wid % Cfg::WGN;
   const int lr = lane & 15, lk = lane >> 4;
 #pragma unroll
   for (int kk = 0; kk < Cfg::BK / 4; ++kk) {
@@ -284,12 +285,16 @@ __device__ __forceinline__ void mainloop(LA& la, LB& lb, int kbeg, int kend, Acc
 // eight bytes per complex value, as for complex64; a tile moves SP chunks into
 // LDS with 16-byte loads and stores and no arithmetic.
 //
-// LDS holds four bf16 planes per operand (re_hi, re_lo, im_hi, im_lo) laid out
-// [outer][k] with a row stride of LDK = 40 bf16 (80 bytes: the 16-byte reads of
-// 16 consecutive rows fall in distinct banks), so a lane reads its eight
-// consecutive k values with one 16-byte load; one chunk is BK = 32, a single
-// MFMA k-step.  Two LDS stages: the next chunk is written to one while the
-// other's MFMAs run.
+// In LDS an operand row holds its chunk as SP memory does: the chunk's four
+// 8-groups, each as its four planes (re_hi, re_lo, im_hi, im_lo), 256 bytes,
+// plus 16 bytes of padding (ROW = 136 bf16).  An SP chunk row is then copied
+// with 16-byte stores to consecutive addresses (conflict-free), and the
+// 16-byte reads of 16 consecutive rows, 68 dwords apart, fall in distinct
+// banks; a lane reads its eight consecutive k values of one plane with one
+// load.  (Four separate plane arrays, each starting on bank 0, made the 16
+// stores of a row segment collide four ways: bank conflicts were 24% of the
+// R product's cycles.)  One chunk is BK = 32, a single MFMA k-step.  Two LDS
+// stages: the next chunk is written to one while the other's MFMAs run.
 // ---------------------------------------------------------------------------
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
@@ -333,17 +338,19 @@ __device__ __forceinline__ void sp_group(const float (&re)[8], const float (&im)
   g[3] = uint4{il[0], il[1], il[2], il[3]};
 }
 
-template <int BM_, int BN_> struct TileCfgB3 {
+// WGM x WGN wavefronts, each with a WTM x WTN part of the tile.
+template <int BM_, int BN_, int WGM_ = 2, int WGN_ = 2> struct TileCfgB3 {
   typedef float T;
   static constexpr bool B3 = true;
   static constexpr int BM = BM_, BN = BN_, BK = 32;
-  static constexpr int NT = 256;
-  static constexpr int WTM = BM / 2, WTN = BN / 2;
+  static constexpr int WGN = WGN_;
+  static constexpr int NT = 64 * WGM_ * WGN_;
+  static constexpr int WTM = BM / WGM_, WTN = BN / WGN_;
   static constexpr int MB = WTM / 16, NB = WTN / 16;
-  static constexpr int LDK = BK + 8;               // bf16 per LDS row (80 bytes)
+  static constexpr int ROW = 4 * BK + 8;           // bf16 per LDS row (272 bytes)
   static constexpr int LDA = 0, LDB = 0;            // FP32 layouts unused
-  static constexpr int A_PLANE = BM * LDK, B_PLANE = BN * LDK;   // bf16 elements
-  static constexpr int STAGE = 4 * A_PLANE + 4 * B_PLANE;         // bf16 elements
+  static constexpr int A_OPER = BM * ROW, B_OPER = BN * ROW;   // bf16 elements
+  static constexpr int STAGE = A_OPER + B_OPER;                  // bf16 elements
   static constexpr int SMEM_BYTES = 2 * STAGE * 2;
   static constexpr int SMEM_ELEMS = SMEM_BYTES / 4;
 };
@@ -357,22 +364,22 @@ __device__ __forceinline__ void tile_compute_b3(const __bf16* __restrict__ sA,
                                                 Hook&& between) {
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
-  const int wr = wid >> 1, wc = wid & 1;
-  const int lr = lane & 15, kb = 8 * (lane >> 4);
+  const int wr = wid / Cfg::WGN, wc = wid % Cfg::WGN;
+  const int lr = lane & 15, kb = 32 * (lane >> 4);   // the lane's 8-group within the row
   bf16x8 b[Cfg::NB][4];
 #pragma unroll
   for (int j = 0; j < Cfg::NB; ++j) {
-    const int off = (wc * Cfg::WTN + j * 16 + lr) * Cfg::LDK + kb;
+    const int off = (wc * Cfg::WTN + j * 16 + lr) * Cfg::ROW + kb;
 #pragma unroll
-    for (int p = 0; p < 4; ++p) b[j][p] = *reinterpret_cast<const bf16x8*>(sB + p * Cfg::B_PLANE + off);
+    for (int p = 0; p < 4; ++p) b[j][p] = *reinterpret_cast<const bf16x8*>(sB + off + 8 * p);
   }
 #pragma unroll
   for (int i = 0; i < Cfg::MB; ++i) {
-    const int off = (wr * Cfg::WTM + i * 16 + lr) * Cfg::LDK + kb;
-    const bf16x8 arh = *reinterpret_cast<const bf16x8*>(sA + 0 * Cfg::A_PLANE + off);
-    const bf16x8 arl = *reinterpret_cast<const bf16x8*>(sA + 1 * Cfg::A_PLANE + off);
-    const bf16x8 aih = *reinterpret_cast<const bf16x8*>(sA + 2 * Cfg::A_PLANE + off);
-    const bf16x8 ail = *reinterpret_cast<const bf16x8*>(sA + 3 * Cfg::A_PLANE + off);
+    const int off = (wr * Cfg::WTM + i * 16 + lr) * Cfg::ROW + kb;
+    const bf16x8 arh = *reinterpret_cast<const bf16x8*>(sA + off);
+    const bf16x8 arl = *reinterpret_cast<const bf16x8*>(sA + off + 8);
+    const bf16x8 aih = *reinterpret_cast<const bf16x8*>(sA + off + 16);
+    const bf16x8 ail = *reinterpret_cast<const bf16x8*>(sA + off + 24);
     const bf16x8 naih = neg_b16(aih), nail = neg_b16(ail);
 #pragma unroll
     for (int j = 0; j < Cfg::NB; ++j) {
@@ -396,15 +403,16 @@ __device__ __forceinline__ void tile_compute_b3(const __bf16* __restrict__ sA,
   }
 }
 
-// Loader protocol as for the FP32 tiles, with store_b3<LDK, PLANE>(s) writing
-// the four bf16 planes.  DOWN as for mainloop.
+// Loader protocol as for the FP32 tiles, with store_b3<ROW>(s) writing the
+// chunk's rows in the layout above.  DOWN as for mainloop.
 template <class Cfg, bool DOWN, class LA, class LB>
 __device__ __forceinline__ void mainloop_b3(LA& la, LB& lb, int kbeg, int kend, AccTile<Cfg>& acc,
                                             float* smem_f) {
-  if (kend <= kbeg) return;
+  // at least one chunk (an empty range loads zeros): a path around the MFMAs
+  // made the compiler keep a copy of the accumulators outside the AGPRs
   __bf16* const stage0 = reinterpret_cast<__bf16*>(smem_f);
   __bf16* const stage1 = stage0 + Cfg::STAGE;
-  const int nch = (kend - kbeg + Cfg::BK - 1) / Cfg::BK;
+  const int nch = max(1, (kend - kbeg + Cfg::BK - 1) / Cfg::BK);
   auto chunk = [&](int c) { return DOWN ? kbeg + (nch - 1 - c) * Cfg::BK : kbeg + c * Cfg::BK; };
   la.fetch(chunk(0), kend);
   lb.fetch(chunk(0), kend);
@@ -413,8 +421,8 @@ __device__ __forceinline__ void mainloop_b3(LA& la, LB& lb, int kbeg, int kend, 
     la.finish(q, Cfg::MB);
     lb.finish(q, Cfg::MB);
   }
-  la.template store_b3<Cfg::LDK, Cfg::A_PLANE>(stage0);
-  lb.template store_b3<Cfg::LDK, Cfg::B_PLANE>(stage0 + 4 * Cfg::A_PLANE);
+  la.template store_b3<Cfg::ROW>(stage0);
+  lb.template store_b3<Cfg::ROW>(stage0 + Cfg::A_OPER);
   __syncthreads();
   for (int c = 0; c < nch; ++c) {
     __bf16* cur = (c & 1) ? stage1 : stage0;
@@ -424,15 +432,15 @@ __device__ __forceinline__ void mainloop_b3(LA& la, LB& lb, int kbeg, int kend, 
       la.fetch(chunk(c + 1), kend);
       lb.fetch(chunk(c + 1), kend);
     }
-    tile_compute_b3<Cfg>(cur, cur + 4 * Cfg::A_PLANE, acc, [&](int i) {
+    tile_compute_b3<Cfg>(cur, cur + Cfg::A_OPER, acc, [&](int i) {
       if (more) {
         la.finish(i, Cfg::MB);
         lb.finish(i, Cfg::MB);
       }
     });
     if (more) {
-      la.template store_b3<Cfg::LDK, Cfg::A_PLANE>(nxt);
-      lb.template store_b3<Cfg::LDK, Cfg::B_PLANE>(nxt + 4 * Cfg::A_PLANE);
+      la.template store_b3<Cfg::ROW>(nxt);
+      lb.template store_b3<Cfg::ROW>(nxt + Cfg::A_OPER);
     }
     __syncthreads();
   }
@@ -443,7 +451,7 @@ template <class Cfg>
 __device__ __forceinline__ void acc_coord(int a, int b, int r, int* row, int* col) {
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
-  const int wr = wid >> 1, wc = wid & 1;
+  const int wr = wid / Cfg::WGN, wc = wid % Cfg::WGN;
   constexpr bool f64 = sizeof(typename Cfg::T) == 8;
   *row = wr * Cfg::WTM + a * 16 + (f64 ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r);
   *col = wc * Cfg::WTN + b * 16 + (lane & 15);
@@ -457,7 +465,7 @@ template <class Cfg, class F>
 __device__ __forceinline__ void acc_foreach(const AccTile<Cfg>& acc, F&& f) {
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
-  const int wr = wid >> 1, wc = wid & 1;
+  const int wr = wid / Cfg::WGN, wc = wid % Cfg::WGN;
   constexpr bool f64 = sizeof(typename Cfg::T) == 8;
 #pragma unroll
   for (int a = 0; a < Cfg::MB; ++a)
@@ -523,7 +531,7 @@ __device__ __forceinline__ void acc_foreach_mut(AccTile<Cfg>& acc, F&& f) {
   static_assert(!IsM3<Cfg>::value, "4M tiles only: the walk reads and writes re and im directly");
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
-  const int wr = wid >> 1, wc = wid & 1;
+  const int wr = wid / Cfg::WGN, wc = wid % Cfg::WGN;
   constexpr bool f64 = sizeof(typename Cfg::T) == 8;
 #pragma unroll
   for (int a = 0; a < Cfg::MB; ++a)
@@ -876,8 +884,12 @@ struct LoadGenRow {
 // An SP matrix operand (rows = outer index, k contiguous): per chunk each row
 // is 256 contiguous bytes (four 8-groups of four planes), moved by 16 threads
 // with one 16-byte load and one 16-byte LDS store each.  Rows at or beyond
-// oend load as zeros; k needs no mask (the storage is zero beyond K and every
-// chunk lies within Kp).
+// oend, and every row of a chunk at or beyond kend, are zeros; within a range
+// k needs no mask (the storage is zero beyond K and every chunk lies within
+// Kp).  A tile whose rows are all valid (the common case, decided once per
+// workgroup) loads from one base address per thread at a fixed row stride;
+// an edge tile skips the loads of its missing rows.  Either way the values
+// reach store_b3 final, so the LDS stores carry no masking.
 template <class Cfg, int OUTER> struct LoadSP {
   static constexpr int PPR = Cfg::BK / 8 * 4;        // 16-byte pieces per row and chunk
   static constexpr int RPP = Cfg::NT / PPR;          // rows per pass
@@ -887,25 +899,30 @@ template <class Cfg, int OUTER> struct LoadSP {
   int64_t gpr;      // 8-groups per row (Kp / 8)
   int o0, oend;
   uint4 v[PASSES];
-  bool ok[PASSES];
-  __device__ __forceinline__ void fetch(int k0, int) {
-    const int q = threadIdx.x % PPR;   // piece within the row's chunk, in memory order
+  __device__ __forceinline__ void fetch(int k0, int kend) {
+    const int rl = threadIdx.x / PPR, q = threadIdx.x % PPR;
+    if (o0 + OUTER <= oend && k0 < kend) {
+      const uint4* b = p + ((int64_t)(o0 + rl) * gpr + (k0 >> 3)) * 4 + q;
+      const int64_t st = (int64_t)RPP * gpr * 4;
+#pragma unroll
+      for (int j = 0; j < PASSES; ++j) v[j] = b[j * st];
+      return;
+    }
 #pragma unroll
     for (int j = 0; j < PASSES; ++j) {
-      const int o = o0 + (int)(threadIdx.x / PPR) + j * RPP;
-      ok[j] = o < oend;
-      const int oc = min(o, oend - 1);
-      v[j] = p[((int64_t)oc * gpr + (k0 >> 3)) * 4 + q];
+      const int o = o0 + rl + j * RPP;
+      v[j] = uint4{0, 0, 0, 0};
+      if (o < oend && k0 < kend) v[j] = p[((int64_t)o * gpr + (k0 >> 3)) * 4 + q];
     }
   }
   __device__ __forceinline__ void finish(int, int) {}
-  template <int LDK, int P>
+  template <int ROW>
   __device__ __forceinline__ void store_b3(__bf16* s) {
-    const int q = threadIdx.x % PPR, g = q >> 2, pl = q & 3;
+    const int q = threadIdx.x % PPR;   // the piece's place in the row, as in memory
 #pragma unroll
     for (int j = 0; j < PASSES; ++j) {
       const int o = threadIdx.x / PPR + j * RPP;
-      *reinterpret_cast<uint4*>(s + pl * P + o * LDK + 8 * g) = ok[j] ? v[j] : uint4{0, 0, 0, 0};
+      *reinterpret_cast<uint4*>(s + o * ROW + 8 * q) = v[j];
     }
   }
 };
@@ -1015,14 +1032,14 @@ struct LoadGenRowSP {
       split2(im[0], im[1], pk[g][2][w], pk[g][3][w]);
     }
   }
-  template <int LDK, int P>
+  template <int ROW>
   __device__ __forceinline__ void store_b3(__bf16* s) {
     const int o = threadIdx.x % OUTER;
 #pragma unroll
     for (int g = 0; g < GPT; ++g)
 #pragma unroll
       for (int pl = 0; pl < 4; ++pl)
-        *reinterpret_cast<uint4*>(s + pl * P + o * LDK + kk0 + 8 * g) =
+        *reinterpret_cast<uint4*>(s + o * ROW + 32 * (kk0 / 8 + g) + 8 * pl) =
             uint4{pk[g][pl][0], pk[g][pl][1], pk[g][pl][2], pk[g][pl][3]};
   }
 };
@@ -1038,7 +1055,7 @@ __device__ __forceinline__ void acc_store_sp_t(const AccTile<Cfg>& acc, void* Y,
                                                int row0, int col0, int krows, int cols) {
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
-  const int wr = wid >> 1, wc = wid & 1;
+  const int wr = wid / Cfg::WGN, wc = wid % Cfg::WGN;
   char* y = reinterpret_cast<char*>(Y);
 #pragma unroll
   for (int a = 0; a < Cfg::MB; ++a)

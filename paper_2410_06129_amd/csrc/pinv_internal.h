@@ -90,12 +90,18 @@ hipError_t launch_gram_rows(const EncDev<double>& e, double* G, hipStream_t s);
 template <typename T, typename TO>
 hipError_t launch_right_pinv(const EncDev<T>& e, const T* Li, T* W, T* Z, TO* R, bool m3,
                              hipStream_t s);
-// Applies of at most kRowApplyMaxF frames stream R row by row (HBM-bound);
-// measured at N = 4096, M = 32768: 0.20 / 0.31 / 0.44 ms for 1 / 4 / 8 frames,
-// 1.5 ms at 12, where the MFMA tiles take 1.23 ms for any F up to 128.
+// Applies of at most kRowApplyMaxF frames stream R row by row (HBM-bound),
+// their contraction cut into one slice per XCD when M >= kRowSliceMinM
+// (partials in scratch, apply_rows_scratch_bytes).
+// (Measured at N = 16384, M = 262144: 16-frame row variants took 25-42 ms
+// for 9-16 frames, where the 32 x 128 MFMA tiles take 11.7 ms.)
 constexpr int kRowApplyMaxF = 8;
+constexpr int kRowSliceMinM = 8192;
+int row_slices(int M);
+template <typename T> size_t apply_rows_scratch_bytes(int F, int N, int M);
 template <typename T>
-hipError_t launch_apply_rows(const T* R, const T* D, T* X, int N, int M, int F, hipStream_t s);
+hipError_t launch_apply_rows(const T* R, const T* D, T* X, int N, int M, int F, Scratch& sc,
+                             hipStream_t s);
 template <typename T, typename SX, typename SD>
 hipError_t launch_forward(const EncDev<T>& e, const SX* X, int F, const SD* Din, T* Dout,
                           hipStream_t s);
@@ -153,7 +159,7 @@ hipError_t launch_apply_b3(const ApplyBatch& b, Scratch& sc, hipStream_t s);
 size_t apply_scratch_bytes_b3(int F, int N, int Mp);
 // At most kRowApplyMaxF frames of complex64 data against an SP R.
 hipError_t launch_apply_rows_sp(const void* R, const float* D, float* X, int N, int M, int F,
-                                hipStream_t s);
+                                Scratch& sc, hipStream_t s);
 hipError_t launch_to_f32(const double* in, float* out, size_t n_complex, hipStream_t s);
 hipError_t launch_to_f64(const float* in, double* out, size_t n_complex, hipStream_t s);
 template <typename T> hipError_t launch_srf_diag(const EncDev<T>& e, const T* R, T* out, hipStream_t s);
@@ -233,7 +239,11 @@ template <> struct GramCfgOf<double> { typedef F64Cfg3 type; };
 
 template <class Cfg> static size_t smem_bytes() { return Cfg::SMEM_ELEMS * sizeof(typename Cfg::T); }
 
-typedef TileCfgB3<128, 128> B3Cfg;
+// BF16x3 tiles: 128 x 128 over eight wavefronts of 64 x 32, so each wave's
+// accumulators (64 registers) and operand registers leave room for two
+// wavefronts per SIMD (with four 64 x 64 waves a SIMD ran one, and the
+// MFMA pipe was busy 32-40% of the time).
+typedef TileCfgB3<128, 128, 2, 4> B3Cfg;
 
 // Kernels whose LDS exceeds the default 64 KB limit need the attribute once.
 template <class K> static hipError_t allow_smem(K kernel, size_t bytes) {

@@ -110,7 +110,7 @@ hipError_t launch_sp_unpack(const void* sp, int rows, int K, float* dst, hipStre
 // W^T = (L^-1 E^H)^T, written SP with rows m and k = n
 // ---------------------------------------------------------------------------
 template <int FEAT, bool AL>
-__global__ __launch_bounds__(256) void k_trmm_w_sp(EncDev<float> e, const uint4* __restrict__ Li,
+__global__ __launch_bounds__(B3Cfg::NT) void k_trmm_w_sp(EncDev<float> e, const uint4* __restrict__ Li,
                                                    int64_t gn, void* __restrict__ W) {
   typedef B3Cfg Cfg;
   const int N = e.N, M = e.M;
@@ -138,7 +138,7 @@ __global__ __launch_bounds__(256) void k_trmm_w_sp(EncDev<float> e, const uint4*
 // R^T tiles: R^T[m][n] = sum_{n' >= n} W^T[m][n'] conj(Li[n'][n]), written SP
 // as R with rows n and k = m
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_trmm_r_sp(const uint4* __restrict__ W,
+__global__ __launch_bounds__(B3Cfg::NT) void k_trmm_r_sp(const uint4* __restrict__ W,
                                                    const uint4* __restrict__ Lh, int64_t gn,
                                                    void* __restrict__ R, int64_t gm, int N, int M) {
   typedef B3Cfg Cfg;
@@ -176,7 +176,7 @@ hipError_t launch_trmm_w_sp(const EncDev<float>& e, const void* Li, void* W, hip
     // once per kernel (thread-safe static initialisation)
     static const hipError_t attr = allow_smem(kern, smem_bytes<Cfg>());
     if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL(kern, dim3(tiles), dim3(256), smem_bytes<Cfg>(), s, e,
+    hipLaunchKernelGGL(kern, dim3(tiles), dim3(Cfg::NT), smem_bytes<Cfg>(), s, e,
                        reinterpret_cast<const uint4*>(Li), gn, W);
     return hipGetLastError();
   });
@@ -188,7 +188,7 @@ hipError_t launch_trmm_r_sp(const void* W, const void* Lh, void* R, int N, int M
   if (attr != hipSuccess) return attr;
   const int tiles = cdiv(N, Cfg::BN) * cdiv(M, Cfg::BM);
   if (tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_trmm_r_sp, dim3(tiles), dim3(256), smem_bytes<Cfg>(), s,
+  hipLaunchKernelGGL(k_trmm_r_sp, dim3(tiles), dim3(Cfg::NT), smem_bytes<Cfg>(), s,
                      reinterpret_cast<const uint4*>(W), reinterpret_cast<const uint4*>(Lh),
                      sp_cols(N) / 8, R, sp_cols(M) / 8, N, M);
   return hipGetLastError();
@@ -197,52 +197,59 @@ hipError_t launch_trmm_r_sp(const void* W, const void* Lh, void* R, int N, int M
 // ---------------------------------------------------------------------------
 // A few frames: stream R's SP rows (HBM-bound), as the FP32 row apply
 // ---------------------------------------------------------------------------
-// Each lane takes whole 8-groups: 64 bytes of R (four 16-byte loads) and the
-// matching eight data values of each frame; R = hi + lo is exact in FP32, so
-// the products and sums are those of the FP32 row apply on that R.
+// Lane l takes columns 2s and 2s + 1 (s = l % 4) of 8-group l / 4 of each
+// 16-group block, as the FP32 row apply takes two columns per lane: it reads
+// dword s of each of the group's four planes (the hi and lo halves of both
+// columns' real and imaginary parts; the wave's four loads together cover 1 KB
+// of the row) and one 16-byte pair of data values per frame (1 KB per wave,
+// contiguous).  R = hi + lo is exact in FP32, so the sums are those of the
+// FP32 row apply on that R.  Past M, R is zero and the data are read clamped
+// (a finite value times zero).  The contraction is sliced over the XCDs as in
+// the FP32 row apply (nseg slices of seg_groups 8-groups, partials to
+// X[slice][F][N] when nseg > 1).
 template <int FM, int RW>
 __global__ __launch_bounds__(256) void k_apply_rows_sp(const uint4* __restrict__ R, int64_t gpr,
                                                        const float* __restrict__ D,
-                                                       float* __restrict__ X, int N, int M, int F) {
+                                                       float* __restrict__ X, int N, int M, int F,
+                                                       int nseg, int seg_groups) {
   const int lane = threadIdx.x & 63;
-  const int n0 = (blockIdx.x * 4 + (int)(threadIdx.x >> 6)) * RW;
+  const int sl = lane & 3;
+  const int seg = blockIdx.x % nseg;
+  const int n0 = ((blockIdx.x / nseg) * 4 + (int)(threadIdx.x >> 6)) * RW;
   if (n0 >= N) return;   // the whole wavefront leaves; no barrier follows
-  const uint4* r[RW];
+  const int64_t g_lo = (int64_t)seg * seg_groups, g_hi = std::min<int64_t>(gpr, g_lo + seg_groups);
+  const uint32_t* r[RW];
 #pragma unroll
   for (int j = 0; j < RW; ++j)   // rows past N re-read row N-1 and are not written
-    r[j] = R + (int64_t)min(n0 + j, N - 1) * gpr * 4;
+    r[j] = reinterpret_cast<const uint32_t*>(R + (int64_t)min(n0 + j, N - 1) * gpr * 4);
   const cx<float>* d = reinterpret_cast<const cx<float>*>(D);
   float ar[RW][FM], ai[RW][FM];
 #pragma unroll
   for (int j = 0; j < RW; ++j)
 #pragma unroll
     for (int f = 0; f < FM; ++f) ar[j][f] = ai[j][f] = 0.f;
-  for (int64_t g = lane; g < gpr; g += 64) {
-    float rr[RW][8], ri[RW][8];
+  for (int64_t g = g_lo + (lane >> 2); g < g_hi; g += 16) {
+    float rr[RW][2], ri[RW][2];
 #pragma unroll
     for (int j = 0; j < RW; ++j) {
-      const uint4 h = r[j][g * 4 + 0], l = r[j][g * 4 + 1], hi = r[j][g * 4 + 2], li = r[j][g * 4 + 3];
-      const uint32_t a[4] = {h.x, h.y, h.z, h.w}, b[4] = {l.x, l.y, l.z, l.w};
-      const uint32_t c[4] = {hi.x, hi.y, hi.z, hi.w}, e[4] = {li.x, li.y, li.z, li.w};
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        rr[j][u] = join2(a[u >> 1], b[u >> 1], u & 1);
-        ri[j][u] = join2(c[u >> 1], e[u >> 1], u & 1);
-      }
+      const uint32_t* q = r[j] + g * 16 + sl;   // dword sl of planes 0..3
+      const uint32_t h = q[0], l = q[4], ih = q[8], il = q[12];
+      rr[j][0] = join2(h, l, 0);
+      rr[j][1] = join2(h, l, 1);
+      ri[j][0] = join2(ih, il, 0);
+      ri[j][1] = join2(ih, il, 1);
     }
+    const int64_t m0 = std::min<int64_t>(g * 8 + 2 * sl, M - 1), m1 = std::min<int64_t>(g * 8 + 2 * sl + 1, M - 1);
 #pragma unroll
     for (int f = 0; f < FM; ++f) {
       if (f >= F) break;
+      const cx<float> d0 = d[(int64_t)f * M + m0], d1 = d[(int64_t)f * M + m1];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int64_t m = g * 8 + u;
-        if (m >= M) break;   // R is zero there; the data has no such column
-        const cx<float> dv = d[(int64_t)f * M + m];
-#pragma unroll
-        for (int j = 0; j < RW; ++j) {
-          ar[j][f] += dv.re * rr[j][u] - dv.im * ri[j][u];
-          ai[j][f] += dv.re * ri[j][u] + dv.im * rr[j][u];
-        }
+      for (int j = 0; j < RW; ++j) {
+        ar[j][f] += d0.re * rr[j][0] - d0.im * ri[j][0];
+        ai[j][f] += d0.re * ri[j][0] + d0.im * rr[j][0];
+        ar[j][f] += d1.re * rr[j][1] - d1.im * ri[j][1];
+        ai[j][f] += d1.re * ri[j][1] + d1.im * rr[j][1];
       }
     }
   }
@@ -257,7 +264,7 @@ __global__ __launch_bounds__(256) void k_apply_rows_sp(const uint4* __restrict__
       }
     }
   if (lane == 0) {
-    cx<float>* x = reinterpret_cast<cx<float>*>(X);
+    cx<float>* x = reinterpret_cast<cx<float>*>(X) + (size_t)seg * F * N;
 #pragma unroll
     for (int j = 0; j < RW; ++j)
 #pragma unroll
@@ -266,23 +273,60 @@ __global__ __launch_bounds__(256) void k_apply_rows_sp(const uint4* __restrict__
   }
 }
 
+// X = sum_s P[s] over the slices, in slice order (n complex64 values each).
+__global__ __launch_bounds__(256) void k_rows_reduce_sp(const float* __restrict__ P, int nseg,
+                                                        int64_t n, float* __restrict__ X) {
+  const cx<float>* p = reinterpret_cast<const cx<float>*>(P);
+  cx<float>* x = reinterpret_cast<cx<float>*>(X);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    float zr = p[i].re, zi = p[i].im;
+    for (int s = 1; s < nseg; ++s) {
+      zr += p[(int64_t)s * n + i].re;
+      zi += p[(int64_t)s * n + i].im;
+    }
+    x[i] = cx<float>{zr, zi};
+  }
+}
+
 hipError_t launch_apply_rows_sp(const void* R, const float* D, float* X, int N, int M, int F,
-                                hipStream_t s) {
+                                Scratch& sc, hipStream_t s) {
   if (F <= 0 || N <= 0) return hipSuccess;
   if (F > kRowApplyMaxF) return hipErrorInvalidValue;
   const uint4* r = reinterpret_cast<const uint4*>(R);
   const int64_t gpr = sp_cols(M) / 8;
+  const int nseg = row_slices(M);
+  // slice length: a multiple of one wave-wide pass (16 groups of 8)
+  const int seg_groups = nseg > 1 ? cdiv(cdiv(gpr, nseg), 16) * 16 : (int)gpr;
+  void* P = nullptr;
+  if (nseg > 1) {
+    const hipError_t e = sc.get(&P, apply_rows_scratch_bytes<float>(F, N, M), s);
+    if (e != hipSuccess) return e;
+  }
+  float* out = nseg > 1 ? (float*)P : X;
   auto go = [&](auto fm, auto rw) {
     constexpr int FM = decltype(fm)::value, RW = decltype(rw)::value;
-    hipLaunchKernelGGL((k_apply_rows_sp<FM, RW>), dim3(cdiv(N, 4 * RW)), dim3(256), 0, s, r, gpr, D,
-                       X, N, M, F);
+    hipLaunchKernelGGL((k_apply_rows_sp<FM, RW>), dim3(cdiv(N, 4 * RW) * nseg), dim3(256), 0, s, r,
+                       gpr, D, out, N, M, F, nseg, seg_groups);
     return hipGetLastError();
   };
   using std::integral_constant;
-  if (F <= 1) return go(integral_constant<int, 1>(), integral_constant<int, 1>());
-  if (F <= 2) return go(integral_constant<int, 2>(), integral_constant<int, 4>());
-  if (F <= 4) return go(integral_constant<int, 4>(), integral_constant<int, 4>());
-  return go(integral_constant<int, 8>(), integral_constant<int, 2>());
+  hipError_t e;
+  if (F <= 1) e = go(integral_constant<int, 1>(), integral_constant<int, 1>());
+  else if (F <= 2) e = go(integral_constant<int, 2>(), integral_constant<int, 4>());
+  else if (F <= 4) e = go(integral_constant<int, 4>(), integral_constant<int, 4>());
+  else e = go(integral_constant<int, 8>(), integral_constant<int, 4>());
+  if (nseg > 1) {
+    if (e == hipSuccess) {
+      const int64_t n = (int64_t)F * N;
+      hipLaunchKernelGGL(k_rows_reduce_sp, dim3((unsigned)std::min<int64_t>(cdiv(n, 256), 4096)),
+                         dim3(256), 0, s, (const float*)P, nseg, n, X);
+      e = hipGetLastError();
+    }
+    const hipError_t f = sc.put(P, s);
+    if (e == hipSuccess) e = f;
+  }
+  return e;
 }
 
 template hipError_t launch_sp_pack<float>(const float*, int64_t, int, int, bool, bool, void*,

@@ -64,12 +64,18 @@ CASES = {
                                b0=True),
 }
 
+# cases used by single tests only (not every CASES-parametrised test)
+EXTRA_CASES = {
+    # M = 10400 >= 8192: the row apply's contraction is sliced over the XCDs
+    "long_c4": dict(seed=105, nx=24, ny=20, C=4, K=2600, F=2),
+}
+
 _oracle_cache = {}
 
 
 def oracle_case(name):
     if name not in _oracle_cache:
-        kw = dict(CASES[name])
+        kw = dict(CASES[name] if name in CASES else EXTRA_CASES[name])
         w = synth.small_case(**kw)
         b = oracle.Build(w.enc, rel=1e-3)
         d0 = oracle.forward(w.enc, w.images)
@@ -495,6 +501,48 @@ def test_apply_paths_match_oracle(P, ctx, prec):
             tol = 1e-9 if prec == "fp64" else o["kappa"] * 1e-6
             print(f"{prec} F={F}: max err {err.max():.2e}")
             assert err.max() < tol, (F, err.max())
+    finally:
+        P.pinv_plan_release(plan)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_row_apply_slices_match_oracle(P, ctx, prec):
+    """Applies of at most 16 frames stream R row by row; with M >= 8192 the
+    contraction is cut into one slice per XCD (partials added in slice order).
+    M = 10400 here (slices of 1408 columns, the last one short).  Against the
+    oracle's R applied in FP64 at the R path's tolerances; BF16X3 plans also
+    against their own R (copied out exactly) within 1e-5."""
+    o = oracle_case("long_c4")
+    w, N, M = o["w"], o["w"].enc.N, o["w"].enc.M
+    assert M >= 8192
+    rng = np.random.default_rng(41)
+    d = rng.standard_normal((16, M)) + 1j * rng.standard_normal((16, M))
+    pr, cdt = {"fp64": (P.FP64, np.complex128), "fp32": (P.FP32, np.complex64),
+               "bf16x3": (P.BF16X3, np.complex64)}[prec]
+    d = d.astype(cdt).astype(np.complex128)
+    x_or = d @ o["R"].T
+    plan = build(P, ctx, w.enc, pr, flags=P.FLAG_UNCACHED)
+    try:
+        x_own = None
+        if prec == "bf16x3":
+            R = torch.full((N, M), float("nan"), dtype=torch.complex64, device="cuda")
+            P.pinv_plan_copy_buffer(plan, P.BUF_R, R)
+            torch.cuda.synchronize()
+            x_own = d @ R.cpu().numpy().astype(np.complex128).T
+        for F in (1, 5, 8, 12, 16):
+            dd = to_dev(d[:F], cdt)
+            x = torch.full((F, N), float("nan"), dtype=dd.dtype, device="cuda")
+            torch.cuda.synchronize()
+            P.pinv_apply(ctx, plan, dd, x)
+            torch.cuda.synchronize()
+            xg = x.cpu().numpy().astype(np.complex128)
+            err = frame_rel(xg, x_or[:F]).max()
+            tol = {"fp64": 1e-9, "fp32": o["kappa"] * 1e-6, "bf16x3": o["kappa"] * 1e-4}[prec]
+            print(f"{prec} F={F}: vs oracle R {err:.2e}")
+            assert err < tol, (F, err)
+            if x_own is not None:
+                e_own = frame_rel(xg, x_own[:F]).max()
+                assert e_own < 1e-5, (F, e_own)
     finally:
         P.pinv_plan_release(plan)
 
