@@ -142,7 +142,8 @@ def cpu_baseline(enc, rows: int = 4096) -> dict:
 # HBM traffic of the dominant kernels from the counter record
 # ----------------------------------------------------------------------------
 
-DEVICE_SOURCES = ("pinv_device.h", "pinv_internal.h", "pinv_trmm.hip", "pinv_apply.hip")
+DEVICE_SOURCES = ("pinv_device.h", "pinv_internal.h", "pinv_trmm.hip", "pinv_apply.hip",
+                  "pinv_split.hip")
 
 
 def kernel_source_hash() -> str:
@@ -174,19 +175,62 @@ def measured_traffic(kernel: str, workload: str):
             "source": "profiles/pmc_traffic.json"}
 
 
-# the FP32 plan's kernels (3M, 128x64 tiles), by their template signature
+# the FP32 plan's kernels (3M, 128x64 tiles) and the BF16X3 plan's split
+# kernels, by their template signature
 PMC_KERNELS = {"trmm_w": "k_trmm_w<pinv::TileCfg<float, 128, 64, 8, true>,",
                "trmm_r": "k_trmm_r<pinv::TileCfg<float, 128, 64, 8, true>, float>",
-               "apply": "k_apply<pinv::TileCfg<float, 128, 64, 8, true>, false>"}
+               "apply": "k_apply<pinv::TileCfg<float, 128, 64, 8, true>, false>",
+               "trmm_w_bf16x3": "k_trmm_w_sp<4, true>",
+               "trmm_r_bf16x3": "k_trmm_r_sp(",
+               "apply_bf16x3": "k_apply<pinv::TileCfgB3<128, 128, 2, 4>, false>"}
 
 
 def algorithmic_bytes(N: int, M: int, F: int) -> dict:
-    """Compulsory HBM bytes per launch (complex64): L^-1 lower triangle and W
-    written once; L^-1 and W read and R written once; for the apply D, R and X
-    once."""
+    """Compulsory HBM bytes per launch (8 bytes per complex value, complex64 or
+    split-packed): L^-1 lower triangle read and W written once; L^-1 (or L^-H)
+    and W read and R written once; for the apply D, R and X once."""
     tri = 8.0 * N * N / 2
-    return {"trmm_w": tri + 8.0 * N * M, "trmm_r": tri + 16.0 * N * M,
-            "apply": 8.0 * F * M + 8.0 * N * M + 8.0 * F * N}
+    out = {"trmm_w": tri + 8.0 * N * M, "trmm_r": tri + 16.0 * N * M,
+           "apply": 8.0 * F * M + 8.0 * N * M + 8.0 * F * N}
+    for k in ("trmm_w", "trmm_r", "apply"):
+        out[k + "_bf16x3"] = out[k]
+    return out
+
+
+def pmc_mfma_summary(d) -> dict:
+    """Per-kernel MFMA counters of one rocprofv3 --pmc run of `bench.py
+    --pmc-run`: busy = SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / 8 XCDs x
+    1024 SIMDs), executed matrix flops = SQ_INSTS_VALU_MFMA_MOPS_* x 512, LDS
+    bank-conflict cycles per CU over the kernel's cycles."""
+    import sqlite3
+    import glob
+    from collections import defaultdict
+    db = sorted(glob.glob(os.path.join(d, "**", "*results.db"), recursive=True))[0]
+    con = sqlite3.connect(db)
+    rows = con.execute("select kernel_name, counter_name, value, dispatch_id from counters_collection").fetchall()
+    con.close()
+    agg = defaultdict(lambda: defaultdict(float))
+    disp = defaultdict(set)
+    names = dict(PMC_KERNELS, gram_psf="k_psf(", chol_trailing="k_chol_trailing", chol_panel="k_chol_panel",
+                 chol_diag="k_chol_diag", adjoint_fp64="k_adjoint<", resid="k_resid", tri_frames="k_tri_frames",
+                 trmm_w_fp64_formed="k_trmm_w<pinv::TileCfg<double", trmm_r_fp64_formed="k_trmm_r<pinv::TileCfg<double, 64, 64, 8, false>, float>",
+                 apply_seg="k_apply<pinv::TileCfg<float, 128, 64, 8, false>, true>")
+    for k, c, v, did in rows:
+        for key, pat in names.items():
+            if pat in k:
+                agg[key][c] += v
+                disp[key].add(did)
+    out = {"source_hash": kernel_source_hash(), "kernels": {}}
+    for key, a in agg.items():
+        g = a.get("GRBM_GUI_ACTIVE", 0.0) / 8
+        if g <= 0:
+            continue
+        mops = {t: a.get("SQ_INSTS_VALU_MFMA_MOPS_" + t, 0.0) * 512 for t in ("F32", "F64", "BF16")}
+        out["kernels"][key] = {"dispatches": len(disp[key]), "cycles_per_xcd": g,
+                               "mfma_busy": a.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) / (g * 1024),
+                               "lds_bank_conflict_frac": a.get("SQ_LDS_BANK_CONFLICT", 0.0) / 256 / g,
+                               "mfma_flops_executed": {t: v for t, v in mops.items() if v}}
+    return out
 
 
 def pmc_summary(dirs, frames: int) -> dict:
@@ -919,6 +963,8 @@ def main():
                     help="a 2 GiB copy, one FP32 build and one refined apply (counter runs)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/pmc_traffic.json from two rocprofv3 --pmc output folders")
+    ap.add_argument("--pmc-mfma-summary", metavar="DIR",
+                    help="write profiles/pmc_mfma.json from a rocprofv3 --pmc run of the MFMA counters")
     ap.add_argument("--build-only", type=int, nargs=2, metavar=("SIDE", "COILS"),
                     help="build plans for a SIDE^2 image with COILS coils (spiral 2N per coil)")
     ap.add_argument("--precisions", default="fp32,fp64")
@@ -930,6 +976,12 @@ def main():
               "sharding of this path is a design note, not a measured configuration.",
               file=sys.stderr)
         sys.exit(2)
+    if args.pmc_mfma_summary:
+        rec = pmc_mfma_summary(args.pmc_mfma_summary)
+        with open(os.path.join(ROOT, "profiles", "pmc_mfma.json"), "w") as fh:
+            json.dump(rec, fh, indent=1)
+        print(json.dumps(rec), flush=True)
+        return
     if args.pmc_summary:
         rec = pmc_summary(args.pmc_summary, args.frames)
         with open(os.path.join(ROOT, "profiles", "pmc_traffic.json"), "w") as fh:
