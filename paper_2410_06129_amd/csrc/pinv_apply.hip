@@ -25,8 +25,12 @@ namespace pinv {
 // 1.5e-5; segments of 4096 rows keep each running sum 8 times shorter.
 constexpr int kApplySegRows = 4096;
 
+template <class Cfg> struct ApplyMinBlocks { static constexpr int value = 1; };
+template <int BM, int BN, int WGM, int WGN, int ST>
+struct ApplyMinBlocks<TileCfgB3<BM, BN, WGM, WGN, ST>> { static constexpr int value = TileCfgB3<BM, BN, WGM, WGN, ST>::MIN_BLOCKS; };
+
 template <class Cfg, bool SEG = false>
-__global__ __launch_bounds__(Cfg::NT) void k_apply(const ApplyBatch batch) {
+__global__ __launch_bounds__(Cfg::NT, ApplyMinBlocks<Cfg>::value) void k_apply(const ApplyBatch batch) {
   typedef typename Cfg::T T;
   // locate the item owning this tile (items carry exclusive tile prefix sums)
   int lo = 0, hi = batch.n - 1;

@@ -338,11 +338,17 @@ __device__ __forceinline__ void sp_group(const float (&re)[8], const float (&im)
   g[3] = uint4{il[0], il[1], il[2], il[3]};
 }
 
-// WGM x WGN wavefronts, each with a WTM x WTN part of the tile.
-template <int BM_, int BN_, int WGM_ = 2, int WGN_ = 2> struct TileCfgB3 {
+// WGM x WGN wavefronts, each with a WTM x WTN part of the tile; STAGES LDS
+// stages (2: the next chunk is stored while this one computes, one barrier
+// per chunk; 1: store, barrier, compute, barrier, with other workgroups on
+// the CU filling the gaps).
+template <int BM_, int BN_, int WGM_ = 2, int WGN_ = 2, int STAGES_ = 2> struct TileCfgB3 {
   typedef float T;
   static constexpr bool B3 = true;
   static constexpr int BM = BM_, BN = BN_, BK = 32;
+  static constexpr int STAGES = STAGES_;
+  // single-stage tiles are meant to share a CU with another workgroup
+  static constexpr int MIN_BLOCKS = STAGES_ == 1 ? 2 : 1;
   static constexpr int WGN = WGN_;
   static constexpr int NT = 64 * WGM_ * WGN_;
   static constexpr int WTM = BM / WGM_, WTN = BN / WGN_;
@@ -351,7 +357,7 @@ template <int BM_, int BN_, int WGM_ = 2, int WGN_ = 2> struct TileCfgB3 {
   static constexpr int LDA = 0, LDB = 0;            // FP32 layouts unused
   static constexpr int A_OPER = BM * ROW, B_OPER = BN * ROW;   // bf16 elements
   static constexpr int STAGE = A_OPER + B_OPER;                  // bf16 elements
-  static constexpr int SMEM_BYTES = 2 * STAGE * 2;
+  static constexpr int SMEM_BYTES = STAGES * STAGE * 2;
   static constexpr int SMEM_ELEMS = SMEM_BYTES / 4;
 };
 
@@ -420,6 +426,30 @@ __device__ __forceinline__ void mainloop_b3(LA& la, LB& lb, int kbeg, int kend, 
   for (int q = 0; q < Cfg::MB; ++q) {
     la.finish(q, Cfg::MB);
     lb.finish(q, Cfg::MB);
+  }
+  if constexpr (Cfg::STAGES == 1) {
+    for (int c = 0; c < nch; ++c) {
+      const bool more = c + 1 < nch;
+      la.template store_b3<Cfg::ROW>(stage0);
+      lb.template store_b3<Cfg::ROW>(stage0 + Cfg::A_OPER);
+      __syncthreads();
+      if (more) {
+        la.fetch(chunk(c + 1), kend);
+        lb.fetch(chunk(c + 1), kend);
+      }
+      // raised issue priority over the matrix products, as in the FP32 loop:
+      // the other workgroup's stores and address math on the SIMD wait
+      __builtin_amdgcn_s_setprio(1);
+      tile_compute_b3<Cfg>(stage0, stage0 + Cfg::A_OPER, acc, [&](int i) {
+        if (more) {
+          la.finish(i, Cfg::MB);
+          lb.finish(i, Cfg::MB);
+        }
+      });
+      __builtin_amdgcn_s_setprio(0);
+      __syncthreads();
+    }
+    return;
   }
   la.template store_b3<Cfg::ROW>(stage0);
   lb.template store_b3<Cfg::ROW>(stage0 + Cfg::A_OPER);

@@ -239,11 +239,15 @@ template <> struct GramCfgOf<double> { typedef F64Cfg3 type; };
 
 template <class Cfg> static size_t smem_bytes() { return Cfg::SMEM_ELEMS * sizeof(typename Cfg::T); }
 
-// BF16x3 tiles: 128 x 128 over eight wavefronts of 64 x 32, so each wave's
-// accumulators (64 registers) and operand registers leave room for two
-// wavefronts per SIMD (with four 64 x 64 waves a SIMD ran one, and the
-// MFMA pipe was busy 32-40% of the time).
-typedef TileCfgB3<128, 128, 2, 4> B3Cfg;
+// BF16x3 tiles: 128 x 64 over four wavefronts of 64 x 32 with one 52 KB LDS
+// stage, so two workgroups share a CU (two wavefronts per SIMD, at most 256
+// registers each) and one's stores and barriers overlap the other's matrix
+// products.  Measured at N = 16384, M = 262144 (W, R product ms; MFMA busy):
+//   128 x 128, 4 waves of 64 x 64, two stages, one workgroup per CU: 1060, 848
+//   128 x 128, 8 waves of 64 x 32, two stages, one workgroup per CU:  916, 744 (0.38, 0.46)
+//   128 x 64, 4 waves, one stage, two workgroups per CU:              820, 730 (0.44, 0.55)
+//   the same with the issue priority raised over the products:        813, 686 (0.43, 0.56)
+typedef TileCfgB3<128, 64, 2, 2, 1> B3Cfg;
 
 // Kernels whose LDS exceeds the default 64 KB limit need the attribute once.
 template <class K> static hipError_t allow_smem(K kernel, size_t bytes) {

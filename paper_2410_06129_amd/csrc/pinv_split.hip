@@ -110,7 +110,7 @@ hipError_t launch_sp_unpack(const void* sp, int rows, int K, float* dst, hipStre
 // W^T = (L^-1 E^H)^T, written SP with rows m and k = n
 // ---------------------------------------------------------------------------
 template <int FEAT, bool AL>
-__global__ __launch_bounds__(B3Cfg::NT) void k_trmm_w_sp(EncDev<float> e, const uint4* __restrict__ Li,
+__global__ __launch_bounds__(B3Cfg::NT, B3Cfg::MIN_BLOCKS) void k_trmm_w_sp(EncDev<float> e, const uint4* __restrict__ Li,
                                                    int64_t gn, void* __restrict__ W) {
   typedef B3Cfg Cfg;
   const int N = e.N, M = e.M;
@@ -138,7 +138,7 @@ __global__ __launch_bounds__(B3Cfg::NT) void k_trmm_w_sp(EncDev<float> e, const 
 // R^T tiles: R^T[m][n] = sum_{n' >= n} W^T[m][n'] conj(Li[n'][n]), written SP
 // as R with rows n and k = m
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(B3Cfg::NT) void k_trmm_r_sp(const uint4* __restrict__ W,
+__global__ __launch_bounds__(B3Cfg::NT, B3Cfg::MIN_BLOCKS) void k_trmm_r_sp(const uint4* __restrict__ W,
                                                    const uint4* __restrict__ Lh, int64_t gn,
                                                    void* __restrict__ R, int64_t gm, int N, int M) {
   typedef B3Cfg Cfg;
