@@ -240,14 +240,24 @@ __global__ __launch_bounds__(256) void k_rows_reduce(const T* __restrict__ P, in
 // frames, N = 4096, M = 32768; without the priority raise 128x128 had been
 // ahead, 8.1 against 8.3 ms).
 // Tile shapes by element type and complex-product form.  FP32 applies of at
-// most 32 frames run on 32x128 tiles: a 128-frame tile would spend most of
-// its matrix products on padding rows.
+// most 32 frames run on 32x128 tiles and those of at most 16 on 16x128 tiles
+// (four wavefronts side by side): a 128-frame tile would spend most of its
+// matrix products on padding rows.
 template <typename T, bool M3> struct ApplyCfgOf;
-template <> struct ApplyCfgOf<float, true> { typedef F32Cfg many; typedef TileCfg<float, 32, 128, 16, true> few; };
-template <> struct ApplyCfgOf<float, false> { typedef F32Cfg4 many; typedef TileCfg<float, 32, 128, 16, false> few; };
-template <> struct ApplyCfgOf<double, true> { typedef F64Cfg3 many; typedef F64Cfg3 few; };
-template <> struct ApplyCfgOf<double, false> { typedef F64Cfg many; typedef F64Cfg few; };
+template <> struct ApplyCfgOf<float, true> {
+  typedef F32Cfg many;
+  typedef TileCfg<float, 32, 128, 16, true> few;
+  typedef TileCfg<float, 16, 128, 16, true, 1> fewest;
+};
+template <> struct ApplyCfgOf<float, false> {
+  typedef F32Cfg4 many;
+  typedef TileCfg<float, 32, 128, 16, false> few;
+  typedef TileCfg<float, 16, 128, 16, false, 1> fewest;
+};
+template <> struct ApplyCfgOf<double, true> { typedef F64Cfg3 many; typedef F64Cfg3 few; typedef F64Cfg3 fewest; };
+template <> struct ApplyCfgOf<double, false> { typedef F64Cfg many; typedef F64Cfg few; typedef F64Cfg fewest; };
 constexpr int kFewFramesMaxF = 32;
+constexpr int kFewestFramesMaxF = 16;
 // A grouped apply of few frames has few tiles, so its contraction may be split
 // up to 16 ways (the other split launches stop at 4).
 constexpr int kApplyMaxSplit = 16;
@@ -327,13 +337,19 @@ static hipError_t apply_form(const ApplyBatch& b, Scratch& sc, hipStream_t s) {
   if constexpr (std::is_same<T, float>::value) {
     // items go to the tile shape their own frame count selects, so an item's
     // result does not depend on the other items of the group
-    ApplyBatch few, many;
-    few.n = many.n = 0;
+    ApplyBatch fewest, few, many;
+    fewest.n = few.n = many.n = 0;
     for (int i = 0; i < b.n; ++i) {
-      if (b.it[i].F <= kFewFramesMaxF)
+      if (b.it[i].F <= kFewestFramesMaxF)
+        fewest.it[fewest.n++] = b.it[i];
+      else if (b.it[i].F <= kFewFramesMaxF)
         few.it[few.n++] = b.it[i];
       else
         many.it[many.n++] = b.it[i];
+    }
+    if (fewest.n) {
+      const hipError_t err = run_apply<typename C::fewest, SEG>(fewest, sc, s);
+      if (err != hipSuccess) return err;
     }
     if (few.n) {
       const hipError_t err = run_apply<typename C::few, SEG>(few, sc, s);
@@ -358,6 +374,8 @@ size_t apply_scratch_bytes(int F, int N, int M, bool m3, bool seg) {
   auto go = [&](auto form, auto sg) -> size_t {
     typedef ApplyCfgOf<T, decltype(form)::value> C;
     constexpr bool S = std::is_same<T, float>::value && decltype(sg)::value;
+    if (std::is_same<T, float>::value && F <= kFewestFramesMaxF)
+      return item_work_bytes<typename C::fewest, S>(F, N, M);
     if (std::is_same<T, float>::value && F <= kFewFramesMaxF)
       return item_work_bytes<typename C::few, S>(F, N, M);
     return item_work_bytes<typename C::many, S>(F, N, M);

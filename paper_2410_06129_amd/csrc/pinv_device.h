@@ -87,14 +87,16 @@ template <typename T> inline int enc_features(const EncDev<T>& e) {
 //   t1 = ar br, t2 = ai bi, t3 = (ar + ai)(br + bi);  re = t1 - t2, im = t3 - t1 - t2
 // (a third LDS plane holds re + im of each operand value); otherwise four
 // real products (4M).
-template <typename T_, int BM_, int BN_, int BK_, bool M3_ = false> struct TileCfg {
+// Four wavefronts in a WGM_ x (4 / WGM_) grid (2 x 2 by default; 1 x 4 for
+// tiles of only 16 rows).
+template <typename T_, int BM_, int BN_, int BK_, bool M3_ = false, int WGM_ = 2> struct TileCfg {
   typedef T_ T;
   static constexpr int BM = BM_, BN = BN_, BK = BK_;
   static constexpr bool M3 = M3_;
   static constexpr int PLANES = M3 ? 3 : 2;
-  static constexpr int NT = 256;                 // 4 wavefronts in a 2x2 grid
-  static constexpr int WGN = 2;                  // wavefronts along N
-  static constexpr int WTM = BM / 2, WTN = BN / 2;
+  static constexpr int NT = 256;
+  static constexpr int WGN = 4 / WGM_;           // wavefronts along N
+  static constexpr int WTM = BM / WGM_, WTN = BN / WGN;
   static constexpr int MB = WTM / 16, NB = WTN / 16;
   // FP64 3M tiles pad rows by 4 doubles: two stages then take 51 KB of LDS,
   // so three workgroups fit in a CU's 160 KB
@@ -103,7 +105,7 @@ template <typename T_, int BM_, int BN_, int BK_, bool M3_ = false> struct TileC
   static constexpr int A_PLANE = BK * LDA, B_PLANE = BK * LDB;
   static constexpr int STAGE = PLANES * A_PLANE + PLANES * B_PLANE;   // elements of T
   static constexpr int SMEM_ELEMS = 2 * STAGE;
-  static_assert(BM % 32 == 0 && BN % 32 == 0 && BK % 4 == 0, "tile shape");
+  static_assert(WTM % 16 == 0 && WTN % 16 == 0 && BK % 4 == 0, "tile shape");
 };
 
 template <class Cfg, class = void> struct IsM3 { static constexpr bool value = false; };
