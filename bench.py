@@ -45,7 +45,8 @@ PEAK_FP32_MFMA = 157.3   # TFLOP/s, MI355X dense FP32 matrix
 PEAK_FP64_MFMA = 78.6
 PEAK_BF16_MFMA = 2500.0  # TFLOP/s, MI355X dense BF16 matrix (no sparsity)
 PEAK_HBM = 8.0e12        # B/s
-ROW_APPLY_MAX_F = 8      # the library streams R row by row for at most this many frames
+ROW_APPLY_MAX_F = 4      # FP32 plans stream R row by row (VALU) for at most this many frames,
+STREAM_MAX_F = 32        # and into the matrix cores up to this many
 
 
 def log(*a):
@@ -763,14 +764,15 @@ def headline(args) -> dict:
     a0 = apply_ms(P, ctx, p32, d32, x32, stream)
     ar = apply_ms(P, ctx, p32, d32, x32, stream, refine=refine)
     small_f = {}
-    for Fs in (1, 2, 4, 8, 9, 16, 32):
+    for Fs in (1, 2, 4, 5, 8, 9, 16, 24, 32):
         ds = d32[:Fs].contiguous()
         xs = torch.empty((Fs, N), dtype=torch.complex64, device=dev)
         ms = apply_ms(P, ctx, p32, ds, xs, stream, reps=5)
         nbytes = 8.0 * (N * M + Fs * M + Fs * N)
         small_f[str(Fs)] = {"ms": ms, "GB/s": nbytes / (ms * 1e-3) / 1e9,
                             "hbm_frac": nbytes / (ms * 1e-3) / PEAK_HBM,
-                            "path": "rows" if Fs <= ROW_APPLY_MAX_F else "mfma"}
+                            "path": "rows" if Fs <= ROW_APPLY_MAX_F else
+                            "stream" if Fs <= STREAM_MAX_F else "tiles"}
     log(f"small-F applies: {small_f}")
     P.pinv_plan_release(p32)
     P.pinv_context_trim(ctx)

@@ -1279,8 +1279,9 @@ size_t item_scratch_bytes(const pinv_plan* p, int F, int steps) {
   const size_t N = p->N, M = p->M;
   const size_t ts = p->prec == PINV_FP64 ? 8 : 4;
   size_t peak = 0;
-  const bool tiles = F > kRowApplyMaxF && !p->no_r && !(p->right && steps > 0);
-  if (F <= kRowApplyMaxF && !p->no_r && !(p->right && steps > 0)) {
+  const int rows_max = row_apply_max_frames(p->prec == PINV_FP32);
+  const bool tiles = F > rows_max && !p->no_r && !(p->right && steps > 0);
+  if (F <= rows_max && !p->no_r && !(p->right && steps > 0)) {
     // the row apply's per-slice partial images
     peak = p->prec == PINV_FP64 ? apply_rows_scratch_bytes<double>(F, (int)N, (int)M)
                                 : apply_rows_scratch_bytes<float>(F, (int)N, (int)M);
@@ -1349,7 +1350,8 @@ extern "C++" pinv_status apply_items(pinv_context* c, int32_t n, const pinv_appl
            ((const pinv_plan*)items[i].plan)->m3 == m3 &&
            ((const pinv_plan*)items[i].plan)->r_fp64 == seg) {
       const pinv_plan* p = (const pinv_plan*)items[i].plan;
-      if (items[i].F > kRowApplyMaxF && !p->no_r && !(p->right && refine_steps > 0)) {
+      if (items[i].F > row_apply_max_frames(p->prec == PINV_FP32) && !p->no_r &&
+          !(p->right && refine_steps > 0)) {
         ApplyItemDev& it = b.it[b.n++];
         it.D = items[i].data;
         it.R = p->R;
@@ -1392,7 +1394,8 @@ extern "C++" pinv_status apply_items(pinv_context* c, int32_t n, const pinv_appl
   for (int j = 0; j < n; ++j) {
     const pinv_plan* p = (const pinv_plan*)items[j].plan;
     const int F = (int)items[j].F;
-    if (p->no_r || F <= 0 || F > kRowApplyMaxF || (p->right && refine_steps > 0)) continue;
+    if (p->no_r || F <= 0 || F > row_apply_max_frames(p->prec == PINV_FP32) || (p->right && refine_steps > 0))
+      continue;
     if (p->prec == PINV_FP64)
       HIPCHK(launch_apply_rows<double>((const double*)p->R, (const double*)items[j].data,
                                        (double*)items[j].image, p->N, p->M, F, sc, s));

@@ -233,31 +233,240 @@ __global__ __launch_bounds__(256) void k_rows_reduce(const T* __restrict__ P, in
 }
 
 
+// ---------------------------------------------------------------------------
+// 5 to 32 frames: R streamed into the matrix cores through a transposing
+// LDS tile
+// ---------------------------------------------------------------------------
+// Between a few and 32 frames an apply still reads R once (8NM bytes) but
+// does up to 32 complex multiply-adds per element read, more than the VALU
+// row kernel keeps up with.  Each wave takes 16 NB rows of R; on
+// v_mfma_f32_16x16x4f32 an image block is X^T (16 frames x 16 rows of R),
+// A = D (frames x k), B = R^T (k x rows), and lane (j = l % 16, q = l / 16)
+// supplies k-slot q of row (or frame) j.  The operand layout puts 16 rows in
+// every wave-wide access, and loads of that shape (64 bytes from each of 16
+// rows) stream at 0.59 of HBM where loads of four rows x 256 bytes stream at
+// 0.77 (pure reads at N = 16384, M = 262144).  So R is loaded in the second
+// shape, 32 columns (256 bytes) per row and chunk, stored to a wave-private
+// LDS tile (16 NB rows of 256 bytes plus 16 bytes of padding, so the 16 rows
+// a fragment read touches fall in distinct banks) and read back in the
+// operand layout: lane (j, q) reads columns 8q .. 8q + 7 of row j, and MFMA
+// step u pairs slot q with column 8q + u.  The data (at most 32 rows,
+// L2-resident, see below) load straight into that layout.  A wave's LDS
+// operations run in order, so its tile needs no barrier; two chunks of loads
+// are in flight while one computes.  Frames past F and rows past N re-read
+// frame F-1 and row N-1 and are not written; columns past a slice's end
+// count as zero.  VEC: complex values per load (2 when M is even and the
+// rows 16-byte aligned, else 1).  M3 selects the plan's complex-product form.
+//
+// Slices: the contraction is cut into nseg slices of at most
+// kStreamSliceCols columns (nseg a multiple of 8, or 1 for short rows).
+// Workgroup b runs on XCD b % 8 and takes row block (b / 8) % nrb of slice
+// 8 (b / (8 nrb)) + b % 8, so each XCD works through its slices one after
+// another with all row blocks of a slice together, and its L2 holds that
+// slice of the data (at most 32 frames x 4096 columns, 1 MB).  Slice partials
+// go to P[slice][F][N] and k_rows_reduce adds them in slice order; a running
+// FP32 sum so covers at most 4096 columns, as in the segmented tiles.
+constexpr int kStreamSliceCols = 4096;
+
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+
+template <int FB, int NB, int VEC, bool M3>
+__global__ __launch_bounds__(256) void k_apply_stream(const float* __restrict__ R,
+                                                      const float* __restrict__ D,
+                                                      float* __restrict__ X, int N, int M, int F,
+                                                      int nseg, int seg_len, int nrb) {
+  constexpr int L = 32;                 // columns per chunk
+  constexpr int ROWB = 272;             // LDS bytes per row
+  constexpr int RPI = 2 * VEC;          // rows per wave-wide load
+  constexpr int LPR = 32 / VEC;         // lanes per row in a load
+  constexpr int GI = 16 / RPI;          // loads per 16-row block
+  typedef typename std::conditional<VEC == 2, f32x4v, f32x2v>::type VT;
+  __shared__ __attribute__((aligned(16))) char tiles[4][16 * NB * ROWB];
+  const int lane = threadIdx.x & 63, w = (int)(threadIdx.x >> 6);
+  const int j = lane & 15, q = lane >> 4;
+  int seg = 0, rb = blockIdx.x;
+  if (nseg > 1) {
+    const int t = blockIdx.x / kXcds;
+    seg = (t / nrb) * kXcds + (int)(blockIdx.x % kXcds);
+    rb = t % nrb;
+  }
+  const int n0 = (rb * 4 + w) * 16 * NB;
+  if (n0 >= N) return;   // the whole wavefront leaves; no barrier follows
+  const int m_lo = seg * seg_len;
+  const int m_hi = min(M, m_lo + seg_len);
+  char* const tile = tiles[w];
+  // load lanes: row RPI i + l / LPR of each block, chunk columns VEC (l % LPR) ..
+  const int lrow = lane / LPR, lcol = VEC * (lane % LPR);
+  const cx<float>* grow[NB][GI];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int i = 0; i < GI; ++i)
+      grow[b][i] = reinterpret_cast<const cx<float>*>(R) +
+                   (size_t)min(n0 + 16 * b + RPI * i + lrow, N - 1) * M + lcol;
+  const cx<float>* drow[FB];
+#pragma unroll
+  for (int a = 0; a < FB; ++a)
+    drow[a] = reinterpret_cast<const cx<float>*>(D) + (size_t)min(16 * a + j, F - 1) * M + 8 * q;
+
+  struct Raw { VT v[NB][GI]; };        // R as loaded
+  struct Dat { VT v[FB][8 / VEC]; };   // data, operand layout
+  struct Frag { f32x4v v[NB][4]; };    // R, operand layout
+  // TAIL: the slice's last, partial chunk (columns at or past m_hi read
+  // column m_hi - VEC, a whole load, and count as zero)
+  auto gload = [&](Raw& g, int m0, auto tail) __attribute__((always_inline)) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int i = 0; i < GI; ++i) {
+        if constexpr (decltype(tail)::value) {
+          const bool in = m0 + lcol < m_hi;
+          const VT v = *reinterpret_cast<const VT*>(grow[b][i] + (in ? m0 : m_hi - VEC - lcol));
+          g.v[b][i] = in ? v : VT{};
+        } else {
+          g.v[b][i] = *reinterpret_cast<const VT*>(grow[b][i] + m0);
+        }
+      }
+  };
+  auto dload = [&](Dat& d, int m0, auto tail) __attribute__((always_inline)) {
+#pragma unroll
+    for (int a = 0; a < FB; ++a)
+#pragma unroll
+      for (int p = 0; p < 8 / VEC; ++p) {
+        if constexpr (decltype(tail)::value) {
+          const int c = m0 + 8 * q + VEC * p;
+          const bool in = c < m_hi;
+          const VT v = *reinterpret_cast<const VT*>(drow[a] + (in ? m0 + VEC * p : m_hi - VEC - 8 * q));
+          d.v[a][p] = in ? v : VT{};
+        } else {
+          d.v[a][p] = *reinterpret_cast<const VT*>(drow[a] + m0 + VEC * p);
+        }
+      }
+  };
+  auto lwrite = [&](const Raw& g) __attribute__((always_inline)) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int i = 0; i < GI; ++i)
+        *reinterpret_cast<VT*>(tile + (16 * b + RPI * i + lrow) * ROWB + 8 * lcol) = g.v[b][i];
+  };
+  auto lread = [&](Frag& r) __attribute__((always_inline)) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+        r.v[b][p] = *reinterpret_cast<const f32x4v*>(tile + (16 * b + j) * ROWB + 64 * q + 16 * p);
+  };
+  // 4M: re = dr rr - di ri, im = dr ri + di rr.  3M: t1 = dr rr, t2 = di ri,
+  // t3 = (dr + di)(rr + ri); re = t1 - t2, im = t3 - t1 - t2.
+  f32x4 acc[3][FB][NB];
+#pragma unroll
+  for (int t = 0; t < 3; ++t)
+#pragma unroll
+    for (int a = 0; a < FB; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) acc[t][a][b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  auto compute = [&](const Frag& r, const Dat& d) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int a = 0; a < FB; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const float rr = r.v[b][u / 2][2 * (u % 2)], ri = r.v[b][u / 2][2 * (u % 2) + 1];
+          const float dr = d.v[a][u / VEC][2 * (u % VEC)], di = d.v[a][u / VEC][2 * (u % VEC) + 1];
+          if constexpr (M3) {
+            acc[0][a][b] = mfma4(dr, rr, acc[0][a][b]);
+            acc[1][a][b] = mfma4(di, ri, acc[1][a][b]);
+            acc[2][a][b] = mfma4(dr + di, rr + ri, acc[2][a][b]);
+          } else {
+            acc[0][a][b] = mfma4(dr, rr, acc[0][a][b]);
+            acc[0][a][b] = mfma4(-di, ri, acc[0][a][b]);
+            acc[1][a][b] = mfma4(dr, ri, acc[1][a][b]);
+            acc[1][a][b] = mfma4(di, rr, acc[1][a][b]);
+          }
+        }
+  };
+  typedef std::false_type Full;
+  typedef std::true_type Tail;
+  const int nfull = m_hi > m_lo ? (m_hi - m_lo) / L : 0;
+  auto at = [&](int k) { return m_lo + min(k, nfull - 1) * L; };
+  Frag rf;
+  if (nfull > 0) {
+    Raw ga, gb;
+    Dat da, db;
+    gload(ga, at(0), Full());
+    dload(da, at(0), Full());
+    gload(gb, at(1), Full());
+    dload(db, at(1), Full());
+    // two chunks per pass, the loop's only exit at the bottom (an exit between
+    // a load and its use let the compiler sink the load past it); the
+    // scheduling barriers keep each chunk's loads ahead of the previous
+    // chunk's products.  The last passes re-load the final chunk, unused.
+    int k = 0;
+    for (; k + 2 <= nfull; k += 2) {
+      lwrite(ga);
+      lread(rf);
+      gload(ga, at(k + 2), Full());
+      __builtin_amdgcn_sched_barrier(0);
+      compute(rf, da);
+      dload(da, at(k + 2), Full());
+      lwrite(gb);
+      lread(rf);
+      gload(gb, at(k + 3), Full());
+      __builtin_amdgcn_sched_barrier(0);
+      compute(rf, db);
+      dload(db, at(k + 3), Full());
+    }
+    if (k < nfull) {   // odd count: the last chunk is in ga, da
+      lwrite(ga);
+      lread(rf);
+      compute(rf, da);
+    }
+  }
+  const int mt = m_lo + nfull * L;
+  if (mt < m_hi) {
+    Raw g;
+    Dat d;
+    gload(g, mt, Tail());
+    dload(d, mt, Tail());
+    lwrite(g);
+    lread(rf);
+    compute(rf, d);
+  }
+  cx<float>* out = reinterpret_cast<cx<float>*>(X) + (size_t)seg * F * N;
+#pragma unroll
+  for (int a = 0; a < FB; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int f = 16 * a + 4 * q + r, n = n0 + 16 * b + j;
+        float re, im;
+        if constexpr (M3) {
+          re = acc[0][a][b][r] - acc[1][a][b][r];
+          im = acc[2][a][b][r] - acc[0][a][b][r] - acc[1][a][b][r];
+        } else {
+          re = acc[0][a][b][r];
+          im = acc[1][a][b][r];
+        }
+        if (f < F && n < N) out[(size_t)f * N + n] = cx<float>{re, im};
+      }
+}
+
 // host launchers
 // The apply uses the same 128x64 3M tiles as the triangular products: with
 // the raised wave priority over the matrix products, their occupancy of two
 // workgroups per CU beats 128x128 at one (7.76 against 8.04 ms at 1000
 // frames, N = 4096, M = 32768; without the priority raise 128x128 had been
 // ahead, 8.1 against 8.3 ms).
-// Tile shapes by element type and complex-product form.  FP32 applies of at
-// most 32 frames run on 32x128 tiles and those of at most 16 on 16x128 tiles
-// (four wavefronts side by side): a 128-frame tile would spend most of its
-// matrix products on padding rows.
+// Tile shapes by element type and complex-product form (FP32 applies of at
+// most 32 frames stream instead, k_apply_stream).
 template <typename T, bool M3> struct ApplyCfgOf;
-template <> struct ApplyCfgOf<float, true> {
-  typedef F32Cfg many;
-  typedef TileCfg<float, 32, 128, 16, true> few;
-  typedef TileCfg<float, 16, 128, 16, true, 1> fewest;
-};
-template <> struct ApplyCfgOf<float, false> {
-  typedef F32Cfg4 many;
-  typedef TileCfg<float, 32, 128, 16, false> few;
-  typedef TileCfg<float, 16, 128, 16, false, 1> fewest;
-};
-template <> struct ApplyCfgOf<double, true> { typedef F64Cfg3 many; typedef F64Cfg3 few; typedef F64Cfg3 fewest; };
-template <> struct ApplyCfgOf<double, false> { typedef F64Cfg many; typedef F64Cfg few; typedef F64Cfg fewest; };
-constexpr int kFewFramesMaxF = 32;
-constexpr int kFewestFramesMaxF = 16;
+template <> struct ApplyCfgOf<float, true> { typedef F32Cfg many; };
+template <> struct ApplyCfgOf<float, false> { typedef F32Cfg4 many; };
+template <> struct ApplyCfgOf<double, true> { typedef F64Cfg3 many; };
+template <> struct ApplyCfgOf<double, false> { typedef F64Cfg many; };
 // A grouped apply of few frames has few tiles, so its contraction may be split
 // up to 16 ways (the other split launches stop at 4).
 constexpr int kApplyMaxSplit = 16;
@@ -337,23 +546,17 @@ static hipError_t apply_form(const ApplyBatch& b, Scratch& sc, hipStream_t s) {
   if constexpr (std::is_same<T, float>::value) {
     // items go to the tile shape their own frame count selects, so an item's
     // result does not depend on the other items of the group
-    ApplyBatch fewest, few, many;
-    fewest.n = few.n = many.n = 0;
+    ApplyBatch many;
+    many.n = 0;
     for (int i = 0; i < b.n; ++i) {
-      if (b.it[i].F <= kFewestFramesMaxF)
-        fewest.it[fewest.n++] = b.it[i];
-      else if (b.it[i].F <= kFewFramesMaxF)
-        few.it[few.n++] = b.it[i];
-      else
-        many.it[many.n++] = b.it[i];
-    }
-    if (fewest.n) {
-      const hipError_t err = run_apply<typename C::fewest, SEG>(fewest, sc, s);
-      if (err != hipSuccess) return err;
-    }
-    if (few.n) {
-      const hipError_t err = run_apply<typename C::few, SEG>(few, sc, s);
-      if (err != hipSuccess) return err;
+      const ApplyItemDev& it = b.it[i];
+      if (it.F <= kStreamMaxF) {
+        const hipError_t err = launch_apply_stream((const float*)it.R, (const float*)it.D,
+                                                   (float*)it.X, it.N, it.M, it.F, M3, sc, s);
+        if (err != hipSuccess) return err;
+      } else {
+        many.it[many.n++] = it;
+      }
     }
     return many.n ? run_apply<typename C::many, SEG>(many, sc, s) : hipSuccess;
   } else {
@@ -374,10 +577,7 @@ size_t apply_scratch_bytes(int F, int N, int M, bool m3, bool seg) {
   auto go = [&](auto form, auto sg) -> size_t {
     typedef ApplyCfgOf<T, decltype(form)::value> C;
     constexpr bool S = std::is_same<T, float>::value && decltype(sg)::value;
-    if (std::is_same<T, float>::value && F <= kFewestFramesMaxF)
-      return item_work_bytes<typename C::fewest, S>(F, N, M);
-    if (std::is_same<T, float>::value && F <= kFewFramesMaxF)
-      return item_work_bytes<typename C::few, S>(F, N, M);
+    if (std::is_same<T, float>::value && F <= kStreamMaxF) return apply_stream_scratch_bytes(F, N, M);
     return item_work_bytes<typename C::many, S>(F, N, M);
   };
   if (seg)
@@ -438,6 +638,66 @@ hipError_t launch_apply_rows(const T* R, const T* D, T* X, int N, int M, int F, 
       const int64_t n = (int64_t)F * N;
       hipLaunchKernelGGL(k_rows_reduce<T>, dim3((unsigned)std::min<int64_t>(cdiv(n, 256), 4096)),
                          dim3(256), 0, s, (const T*)P, nseg, n, X);
+      e = hipGetLastError();
+    }
+    const hipError_t f = sc.put(P, s);
+    if (e == hipSuccess) e = f;
+  }
+  return e;
+}
+
+// Slices of the streamed apply's contraction (see k_apply_stream).
+static int stream_slices(int M) {
+  if (M < kRowSliceMinM) return 1;
+  return kXcds * cdiv(M, kXcds * kStreamSliceCols);
+}
+
+size_t apply_stream_scratch_bytes(int F, int N, int M) {
+  const int nseg = stream_slices(M);
+  return nseg > 1 ? (size_t)nseg * F * N * 2 * sizeof(float) : 0;
+}
+
+hipError_t launch_apply_stream(const float* R, const float* D, float* X, int N, int M, int F,
+                               bool m3, Scratch& sc, hipStream_t s) {
+  if (F <= 0 || N <= 0) return hipSuccess;
+  if (F < kStreamMinF || F > kStreamMaxF) return hipErrorInvalidValue;
+  const bool vec = M % 2 == 0 && ((uintptr_t)R % 16) == 0 && ((uintptr_t)D % 16) == 0;
+  const int nseg = stream_slices(M);
+  // slice length: whole 32-column chunks, so only the last slice has a
+  // partial chunk
+  const int seg_len = nseg > 1 ? cdiv(cdiv(M, nseg), 32) * 32 : M;
+  void* P = nullptr;
+  if (nseg > 1) {
+    const hipError_t e = sc.get(&P, apply_stream_scratch_bytes(F, N, M), s);
+    if (e != hipSuccess) return e;
+  }
+  float* out = nseg > 1 ? (float*)P : X;
+  auto go = [&](auto fb, auto form) {
+    constexpr int FB = decltype(fb)::value, NB = 2;
+    constexpr bool M3 = decltype(form)::value;
+    const int nrb = cdiv(N, 64 * NB);
+    const dim3 grid((unsigned)(nrb * nseg)), block(256);
+    if (vec)
+      hipLaunchKernelGGL((k_apply_stream<FB, NB, 2, M3>), grid, block, 0, s, R, D, out, N, M, F,
+                         nseg, seg_len, nrb);
+    else
+      hipLaunchKernelGGL((k_apply_stream<FB, NB, 1, M3>), grid, block, 0, s, R, D, out, N, M, F,
+                         nseg, seg_len, nrb);
+    return hipGetLastError();
+  };
+  using std::integral_constant;
+  typedef integral_constant<bool, true> T3;
+  typedef integral_constant<bool, false> T4;
+  hipError_t e;
+  if (F <= 16)
+    e = m3 ? go(integral_constant<int, 1>(), T3()) : go(integral_constant<int, 1>(), T4());
+  else
+    e = m3 ? go(integral_constant<int, 2>(), T3()) : go(integral_constant<int, 2>(), T4());
+  if (nseg > 1) {
+    if (e == hipSuccess) {
+      const int64_t n = (int64_t)F * N;
+      hipLaunchKernelGGL(k_rows_reduce<float>, dim3((unsigned)std::min<int64_t>(cdiv(n, 256), 4096)),
+                         dim3(256), 0, s, (const float*)P, nseg, n, X);
       e = hipGetLastError();
     }
     const hipError_t f = sc.put(P, s);

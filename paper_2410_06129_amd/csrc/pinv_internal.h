@@ -92,16 +92,30 @@ hipError_t launch_right_pinv(const EncDev<T>& e, const T* Li, T* W, T* Z, TO* R,
                              hipStream_t s);
 // Applies of at most kRowApplyMaxF frames stream R row by row (HBM-bound),
 // their contraction cut into one slice per XCD when M >= kRowSliceMinM
-// (partials in scratch, apply_rows_scratch_bytes).
-// (Measured at N = 16384, M = 262144: 16-frame row variants took 25-42 ms
-// for 9-16 frames, where the 32 x 128 MFMA tiles take 11.7 ms.)
+// (partials in scratch, apply_rows_scratch_bytes); FP32 plans do so up to
+// kStreamMinF - 1 frames and stream R into the matrix cores from there
+// (launch_apply_stream).  (Measured at N = 16384, M = 262144: 16-frame row
+// variants took 25-42 ms for 9-16 frames; at 5-8 frames the row kernel takes
+// 6.7-8.0 ms and the streamed one about 5.8 ms.)
 constexpr int kRowApplyMaxF = 8;
+constexpr int kStreamMinF = 5;
+constexpr int kStreamMaxF = 32;
+// The most frames a plan applies with the row kernel (fp32: an FP32 plan,
+// whose R is complex64).
+inline int row_apply_max_frames(bool fp32) { return fp32 ? kStreamMinF - 1 : kRowApplyMaxF; }
 constexpr int kRowSliceMinM = 8192;
 int row_slices(int M);
 template <typename T> size_t apply_rows_scratch_bytes(int F, int N, int M);
 template <typename T>
 hipError_t launch_apply_rows(const T* R, const T* D, T* X, int N, int M, int F, Scratch& sc,
                              hipStream_t s);
+// FP32 applies of kStreamMinF to kStreamMaxF frames stream R through the
+// matrix cores (m3: the plan's complex-product form), their contraction in
+// slices of at most 4096 columns when M >= kRowSliceMinM (partials in
+// scratch, apply_stream_scratch_bytes).
+size_t apply_stream_scratch_bytes(int F, int N, int M);
+hipError_t launch_apply_stream(const float* R, const float* D, float* X, int N, int M, int F,
+                               bool m3, Scratch& sc, hipStream_t s);
 template <typename T, typename SX, typename SD>
 hipError_t launch_forward(const EncDev<T>& e, const SX* X, int F, const SD* Din, T* Dout,
                           hipStream_t s);

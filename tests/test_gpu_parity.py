@@ -68,6 +68,8 @@ CASES = {
 EXTRA_CASES = {
     # M = 10400 >= 8192: the row apply's contraction is sliced over the XCDs
     "long_c4": dict(seed=105, nx=24, ny=20, C=4, K=2600, F=2),
+    # M = 9003, odd: the streamed apply's 8-byte loads, a partial last chunk
+    "long_odd": dict(seed=106, nx=22, ny=19, C=3, K=3001, F=2),
 }
 
 _oracle_cache = {}
@@ -375,11 +377,21 @@ def test_zero_frames_and_grouped_equals_single(P, ctx):
     P.pinv_apply(ctx, p1, e, ex)
     torch.cuda.synchronize()
     assert torch.equal(g1, x1) and torch.equal(g2, x2)
-    # a frame's result does not depend on the other frames in the batch
-    s1 = torch.zeros((1, o1["w"].enc.N), dtype=torch.complex64, device="cuda")
-    P.pinv_apply(ctx, p1, d1[2:3].contiguous(), s1)
-    torch.cuda.synchronize()
-    assert torch.equal(s1[0], x1[2])
+    # a frame's result does not depend on the values of the other frames (the
+    # path follows from F, N and M, so the batch keeps its size; every path
+    # is covered: rows at F = 1, 4, 8, streamed at 5 and 32, tiles at 40)
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    for F in (1, 4, 5, 8, 32, 40):
+        d = torch.randn((F, o1["w"].enc.M), dtype=torch.complex64, device="cuda", generator=gen)
+        d_alt = torch.randn((F, o1["w"].enc.M), dtype=torch.complex64, device="cuda", generator=gen)
+        f = F // 2
+        d_alt[f] = d[f]
+        x, x_alt = (torch.zeros((F, o1["w"].enc.N), dtype=torch.complex64, device="cuda")
+                    for _ in range(2))
+        P.pinv_apply(ctx, p1, d, x)
+        P.pinv_apply(ctx, p1, d_alt, x_alt)
+        torch.cuda.synchronize()
+        assert torch.equal(x[f], x_alt[f]), F
     P.pinv_plan_release(p1)
     P.pinv_plan_release(p2)
 
@@ -505,23 +517,30 @@ def test_apply_paths_match_oracle(P, ctx, prec):
         P.pinv_plan_release(plan)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
-def test_row_apply_slices_match_oracle(P, ctx, prec):
-    """Applies of at most 16 frames stream R row by row; with M >= 8192 the
-    contraction is cut into one slice per XCD (partials added in slice order).
-    M = 10400 here (slices of 1408 columns, the last one short).  Against the
-    oracle's R applied in FP64 at the R path's tolerances; BF16X3 plans also
-    against their own R (copied out exactly) within 1e-5."""
-    o = oracle_case("long_c4")
+@pytest.mark.parametrize("prec,name,cprod", [
+    ("fp64", "long_c4", "3m"), ("fp32", "long_c4", "3m"), ("fp32", "long_c4", "4m"),
+    ("fp32", "long_odd", "3m"), ("fp32", "long_odd", "4m"), ("bf16x3", "long_c4", "auto")])
+def test_few_frame_slices_match_oracle(P, ctx, prec, name, cprod):
+    """Applies of a few frames stream R: at most 8 frames row by row (VALU),
+    9 to 32 frames (FP32 plans) into the matrix cores.  With M >= 8192 the
+    contraction is cut into slices (one per XCD for the row kernel, at most
+    4096 columns for the streamed one), partials added in slice order.
+    long_c4: M = 10400 (N = 480, ragged against the 128-row blocks); long_odd:
+    M = 9003, odd (8-byte loads, a partial last chunk).  Against the oracle's R
+    applied in FP64 at the R path's tolerances; BF16X3 plans also against
+    their own R (copied out exactly) within 1e-5.  Both complex-product forms
+    (the streamed kernel follows the plan's)."""
+    o = oracle_case(name)
     w, N, M = o["w"], o["w"].enc.N, o["w"].enc.M
     assert M >= 8192
     rng = np.random.default_rng(41)
-    d = rng.standard_normal((16, M)) + 1j * rng.standard_normal((16, M))
+    d = rng.standard_normal((32, M)) + 1j * rng.standard_normal((32, M))
     pr, cdt = {"fp64": (P.FP64, np.complex128), "fp32": (P.FP32, np.complex64),
                "bf16x3": (P.BF16X3, np.complex64)}[prec]
     d = d.astype(cdt).astype(np.complex128)
     x_or = d @ o["R"].T
-    plan = build(P, ctx, w.enc, pr, flags=P.FLAG_UNCACHED)
+    form = {"3m": P.CPROD_3M, "4m": P.CPROD_4M, "auto": P.CPROD_AUTO}[cprod]
+    plan = build(P, ctx, w.enc, pr, flags=P.FLAG_UNCACHED, cprod=form)
     try:
         x_own = None
         if prec == "bf16x3":
@@ -529,7 +548,7 @@ def test_row_apply_slices_match_oracle(P, ctx, prec):
             P.pinv_plan_copy_buffer(plan, P.BUF_R, R)
             torch.cuda.synchronize()
             x_own = d @ R.cpu().numpy().astype(np.complex128).T
-        for F in (1, 5, 8, 12, 16):
+        for F in (1, 5, 8, 9, 12, 16, 17, 24, 32):
             dd = to_dev(d[:F], cdt)
             x = torch.full((F, N), float("nan"), dtype=dd.dtype, device="cuda")
             torch.cuda.synchronize()
@@ -538,7 +557,7 @@ def test_row_apply_slices_match_oracle(P, ctx, prec):
             xg = x.cpu().numpy().astype(np.complex128)
             err = frame_rel(xg, x_or[:F]).max()
             tol = {"fp64": 1e-9, "fp32": o["kappa"] * 1e-6, "bf16x3": o["kappa"] * 1e-4}[prec]
-            print(f"{prec} F={F}: vs oracle R {err:.2e}")
+            print(f"{prec} {name} {cprod} F={F}: vs oracle R {err:.2e}")
             assert err < tol, (F, err)
             if x_own is not None:
                 e_own = frame_rel(xg, x_own[:F]).max()
