@@ -45,7 +45,7 @@ PEAK_FP32_MFMA = 157.3   # TFLOP/s, MI355X dense FP32 matrix
 PEAK_FP64_MFMA = 78.6
 PEAK_BF16_MFMA = 2500.0  # TFLOP/s, MI355X dense BF16 matrix (no sparsity)
 PEAK_HBM = 8.0e12        # B/s
-ROW_APPLY_MAX_F = 4      # FP32 plans stream R row by row (VALU) for at most this many frames,
+ROW_APPLY_MAX_F = 2      # FP32 plans stream R row by row (VALU) for at most this many frames,
 STREAM_MAX_F = 32        # and into the matrix cores up to this many
 
 
@@ -764,7 +764,7 @@ def headline(args) -> dict:
     a0 = apply_ms(P, ctx, p32, d32, x32, stream)
     ar = apply_ms(P, ctx, p32, d32, x32, stream, refine=refine)
     small_f = {}
-    for Fs in (1, 2, 4, 5, 8, 9, 16, 24, 32):
+    for Fs in (1, 2, 3, 4, 8, 9, 16, 24, 32):
         ds = d32[:Fs].contiguous()
         xs = torch.empty((Fs, N), dtype=torch.complex64, device=dev)
         ms = apply_ms(P, ctx, p32, ds, xs, stream, reps=5)

@@ -267,9 +267,10 @@ pinv_status pinv_encoding_key(const pinv_encoding *e, const pinv_build_opts *o, 
  * regenerated in FP64, then x += L^-H L^-1 r.  Plans with M < N refine on the
  * sample side instead: y = G'^-1 d with G' = E E^H + lambda I refined against
  * the FP64 G', then x = E^H y with E in FP64.  Applies of a few frames read
- * R once, bound by HBM bandwidth: at most 8 frames (4 for FP32 plans) stream
- * R row by row on the vector units, and 5 to 32 frames of an FP32 plan stream
- * it into the matrix cores; more frames run as MFMA tiles.  The paths round
+ * R once, bound by HBM bandwidth: at most 8 frames of an FP64 plan and 2 of
+ * an FP32 or BF16X3 plan stream R row by row on the vector units, 3 to 32
+ * frames of an FP32 or BF16X3 plan stream it into the matrix cores; more
+ * frames run as MFMA tiles.  The paths round
  * differently.  The path and the split of the sum over M follow from F, N and
  * M alone, and a frame's result does not depend on the values of the other
  * frames.  Errors: INVALID, NOMEM (scratch), DEVICE. */

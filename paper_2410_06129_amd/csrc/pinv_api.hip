@@ -1279,7 +1279,7 @@ size_t item_scratch_bytes(const pinv_plan* p, int F, int steps) {
   const size_t N = p->N, M = p->M;
   const size_t ts = p->prec == PINV_FP64 ? 8 : 4;
   size_t peak = 0;
-  const int rows_max = row_apply_max_frames(p->prec == PINV_FP32);
+  const int rows_max = row_apply_max_frames(p->prec != PINV_FP64);
   const bool tiles = F > rows_max && !p->no_r && !(p->right && steps > 0);
   if (F <= rows_max && !p->no_r && !(p->right && steps > 0)) {
     // the row apply's per-slice partial images
@@ -1291,7 +1291,8 @@ size_t item_scratch_bytes(const pinv_plan* p, int F, int steps) {
     const size_t Mp = sp_cols(M);
     peak = p->prec == PINV_FP64 ? apply_scratch_bytes<double>(F, (int)N, (int)M, p->m3, false)
            : p->prec == PINV_BF16X3
-               ? al(8 * F * Mp) + apply_scratch_bytes_b3(F, (int)N, (int)Mp)
+               ? al(8 * F * Mp) + (F <= kStreamMaxF ? apply_stream_scratch_bytes(F, (int)N, (int)Mp)
+                                                    : apply_scratch_bytes_b3(F, (int)N, (int)Mp))
                : apply_scratch_bytes<float>(F, (int)N, (int)M, p->m3, p->r_fp64);
   }
   if (p->no_r) {
@@ -1350,7 +1351,7 @@ extern "C++" pinv_status apply_items(pinv_context* c, int32_t n, const pinv_appl
            ((const pinv_plan*)items[i].plan)->m3 == m3 &&
            ((const pinv_plan*)items[i].plan)->r_fp64 == seg) {
       const pinv_plan* p = (const pinv_plan*)items[i].plan;
-      if (items[i].F > row_apply_max_frames(p->prec == PINV_FP32) && !p->no_r &&
+      if (items[i].F > row_apply_max_frames(p->prec != PINV_FP64) && !p->no_r &&
           !(p->right && refine_steps > 0)) {
         ApplyItemDev& it = b.it[b.n++];
         it.D = items[i].data;
@@ -1379,7 +1380,17 @@ extern "C++" pinv_status apply_items(pinv_context* c, int32_t n, const pinv_appl
         it.D = packed[got];
         it.M = (int)Mp;
       }
-      if (e == hipSuccess) e = launch_apply_b3(b, sc, s);
+      // up to kStreamMaxF frames stream R; more run as tiles
+      ApplyBatch tiles;
+      tiles.n = 0;
+      for (int t = 0; t < b.n && e == hipSuccess; ++t) {
+        const ApplyItemDev& it = b.it[t];
+        if (it.F <= kStreamMaxF)
+          e = launch_apply_stream_sp(it.R, it.D, (float*)it.X, it.N, it.M, it.F, sc, s);
+        else
+          tiles.it[tiles.n++] = it;
+      }
+      if (e == hipSuccess && tiles.n) e = launch_apply_b3(tiles, sc, s);
       for (int j = got - 1; j >= 0; --j)   // most recent first (the fixed-region scratch is a stack)
         if (packed[j]) {
           const hipError_t f = sc.put(packed[j], s);
@@ -1394,7 +1405,7 @@ extern "C++" pinv_status apply_items(pinv_context* c, int32_t n, const pinv_appl
   for (int j = 0; j < n; ++j) {
     const pinv_plan* p = (const pinv_plan*)items[j].plan;
     const int F = (int)items[j].F;
-    if (p->no_r || F <= 0 || F > row_apply_max_frames(p->prec == PINV_FP32) || (p->right && refine_steps > 0))
+    if (p->no_r || F <= 0 || F > row_apply_max_frames(p->prec != PINV_FP64) || (p->right && refine_steps > 0))
       continue;
     if (p->prec == PINV_FP64)
       HIPCHK(launch_apply_rows<double>((const double*)p->R, (const double*)items[j].data,

@@ -234,8 +234,8 @@ __global__ __launch_bounds__(256) void k_rows_reduce(const T* __restrict__ P, in
 
 
 // ---------------------------------------------------------------------------
-// 5 to 32 frames: R streamed into the matrix cores through a transposing
-// LDS tile
+// 5 to 32 frames: R streamed into the matrix cores through transposing LDS
+// tiles
 // ---------------------------------------------------------------------------
 // Between a few and 32 frames an apply still reads R once (8NM bytes) but
 // does up to 32 complex multiply-adds per element read, more than the VALU
@@ -247,16 +247,25 @@ __global__ __launch_bounds__(256) void k_rows_reduce(const T* __restrict__ P, in
 // rows) stream at 0.59 of HBM where loads of four rows x 256 bytes stream at
 // 0.77 (pure reads at N = 16384, M = 262144).  So R is loaded in the second
 // shape, 32 columns (256 bytes) per row and chunk, stored to a wave-private
-// LDS tile (16 NB rows of 256 bytes plus 16 bytes of padding, so the 16 rows
-// a fragment read touches fall in distinct banks) and read back in the
-// operand layout: lane (j, q) reads columns 8q .. 8q + 7 of row j, and MFMA
-// step u pairs slot q with column 8q + u.  The data (at most 32 rows,
-// L2-resident, see below) load straight into that layout.  A wave's LDS
-// operations run in order, so its tile needs no barrier; two chunks of loads
-// are in flight while one computes.  Frames past F and rows past N re-read
-// frame F-1 and row N-1 and are not written; columns past a slice's end
-// count as zero.  VEC: complex values per load (2 when M is even and the
-// rows 16-byte aligned, else 1).  M3 selects the plan's complex-product form.
+// LDS tile (rows of 256 bytes plus 16 of padding, so the 16 rows a fragment
+// read touches fall in distinct banks) and read back in the operand layout:
+// lane (j, q) reads columns 8q .. 8q + 7 of row j, and MFMA step u pairs
+// slot q with column 8q + u.  A wave's own LDS operations run in order, so
+// its R tile needs no barrier.  The data chunk (16 FB frames x 32 columns) is
+// the same for the workgroup's four waves: each loads a quarter of it into a
+// shared, double-buffered LDS tile, with one barrier per chunk.  Two chunks
+// of R are in flight while one computes.  Frames past F and rows past N
+// re-read frame F-1 and row N-1 and are not written (waves past N still
+// load their share of the data and take the barriers); columns past a
+// slice's end count as zero.  VEC: complex values per load (2 when M is even
+// and the rows 16-byte aligned, else 1).  FORM: the plan's complex-product
+// form on FP32 operands (kForm4M, kForm3M), or kFormB3 for split-packed R and
+// data (BF16X3 plans): there each 64-byte group of a row holds the bf16
+// planes re_hi, re_lo, im_hi, im_lo of 8 columns, so the same 256-byte row
+// pieces and the same fragment reads give a lane the four planes of its
+// 8-group q, one v_mfma_f32_16x16x32_bf16 step per chunk and plane pair
+// (hi*hi + hi*lo + lo*hi per real product).  Split-packed rows are padded to
+// whole chunks (zeros past M), so those slices have no partial chunk.
 //
 // Slices: the contraction is cut into nseg slices of at most
 // kStreamSliceCols columns (nseg a multiple of 8, or 1 for short rows).
@@ -267,10 +276,11 @@ __global__ __launch_bounds__(256) void k_rows_reduce(const T* __restrict__ P, in
 // go to P[slice][F][N] and k_rows_reduce adds them in slice order; a running
 // FP32 sum so covers at most 4096 columns, as in the segmented tiles.
 constexpr int kStreamSliceCols = 4096;
+constexpr int kForm4M = 0, kForm3M = 1, kFormB3 = 2;
 
 typedef float f32x4v __attribute__((ext_vector_type(4)));
 
-template <int FB, int NB, int VEC, bool M3>
+template <int FB, int NB, int VEC, int FORM>
 __global__ __launch_bounds__(256) void k_apply_stream(const float* __restrict__ R,
                                                       const float* __restrict__ D,
                                                       float* __restrict__ X, int N, int M, int F,
@@ -279,9 +289,11 @@ __global__ __launch_bounds__(256) void k_apply_stream(const float* __restrict__ 
   constexpr int ROWB = 272;             // LDS bytes per row
   constexpr int RPI = 2 * VEC;          // rows per wave-wide load
   constexpr int LPR = 32 / VEC;         // lanes per row in a load
-  constexpr int GI = 16 / RPI;          // loads per 16-row block
+  constexpr int GI = 16 / RPI;          // loads per 16-row block of R
+  constexpr int DI = 4 * FB / RPI;      // data loads per wave (its 4 FB frames)
   typedef typename std::conditional<VEC == 2, f32x4v, f32x2v>::type VT;
-  __shared__ __attribute__((aligned(16))) char tiles[4][16 * NB * ROWB];
+  __shared__ __attribute__((aligned(16))) char rtiles[4][16 * NB * ROWB];
+  __shared__ __attribute__((aligned(16))) char dtile[2][16 * FB * ROWB];
   const int lane = threadIdx.x & 63, w = (int)(threadIdx.x >> 6);
   const int j = lane & 15, q = lane >> 4;
   int seg = 0, rb = blockIdx.x;
@@ -291,11 +303,10 @@ __global__ __launch_bounds__(256) void k_apply_stream(const float* __restrict__ 
     rb = t % nrb;
   }
   const int n0 = (rb * 4 + w) * 16 * NB;
-  if (n0 >= N) return;   // the whole wavefront leaves; no barrier follows
   const int m_lo = seg * seg_len;
   const int m_hi = min(M, m_lo + seg_len);
-  char* const tile = tiles[w];
-  // load lanes: row RPI i + l / LPR of each block, chunk columns VEC (l % LPR) ..
+  char* const tile = rtiles[w];
+  // load lanes: row RPI i + l / LPR, chunk columns VEC (l % LPR) ..
   const int lrow = lane / LPR, lcol = VEC * (lane % LPR);
   const cx<float>* grow[NB][GI];
 #pragma unroll
@@ -304,14 +315,16 @@ __global__ __launch_bounds__(256) void k_apply_stream(const float* __restrict__ 
     for (int i = 0; i < GI; ++i)
       grow[b][i] = reinterpret_cast<const cx<float>*>(R) +
                    (size_t)min(n0 + 16 * b + RPI * i + lrow, N - 1) * M + lcol;
-  const cx<float>* drow[FB];
+  const cx<float>* dsrc[DI];
 #pragma unroll
-  for (int a = 0; a < FB; ++a)
-    drow[a] = reinterpret_cast<const cx<float>*>(D) + (size_t)min(16 * a + j, F - 1) * M + 8 * q;
+  for (int i = 0; i < DI; ++i)
+    dsrc[i] = reinterpret_cast<const cx<float>*>(D) +
+              (size_t)min(4 * FB * w + RPI * i + lrow, F - 1) * M + lcol;
 
   struct Raw { VT v[NB][GI]; };        // R as loaded
-  struct Dat { VT v[FB][8 / VEC]; };   // data, operand layout
+  struct DRaw { VT v[DI]; };           // the wave's quarter of the data
   struct Frag { f32x4v v[NB][4]; };    // R, operand layout
+  struct DFrag { f32x4v v[FB][4]; };   // data, operand layout
   // TAIL: the slice's last, partial chunk (columns at or past m_hi read
   // column m_hi - VEC, a whole load, and count as zero)
   auto gload = [&](Raw& g, int m0, auto tail) __attribute__((always_inline)) {
@@ -328,20 +341,17 @@ __global__ __launch_bounds__(256) void k_apply_stream(const float* __restrict__ 
         }
       }
   };
-  auto dload = [&](Dat& d, int m0, auto tail) __attribute__((always_inline)) {
+  auto dload = [&](DRaw& d, int m0, auto tail) __attribute__((always_inline)) {
 #pragma unroll
-    for (int a = 0; a < FB; ++a)
-#pragma unroll
-      for (int p = 0; p < 8 / VEC; ++p) {
-        if constexpr (decltype(tail)::value) {
-          const int c = m0 + 8 * q + VEC * p;
-          const bool in = c < m_hi;
-          const VT v = *reinterpret_cast<const VT*>(drow[a] + (in ? m0 + VEC * p : m_hi - VEC - 8 * q));
-          d.v[a][p] = in ? v : VT{};
-        } else {
-          d.v[a][p] = *reinterpret_cast<const VT*>(drow[a] + m0 + VEC * p);
-        }
+    for (int i = 0; i < DI; ++i) {
+      if constexpr (decltype(tail)::value) {
+        const bool in = m0 + lcol < m_hi;
+        const VT v = *reinterpret_cast<const VT*>(dsrc[i] + (in ? m0 : m_hi - VEC - lcol));
+        d.v[i] = in ? v : VT{};
+      } else {
+        d.v[i] = *reinterpret_cast<const VT*>(dsrc[i] + m0);
       }
+    }
   };
   auto lwrite = [&](const Raw& g) __attribute__((always_inline)) {
 #pragma unroll
@@ -357,16 +367,62 @@ __global__ __launch_bounds__(256) void k_apply_stream(const float* __restrict__ 
       for (int p = 0; p < 4; ++p)
         r.v[b][p] = *reinterpret_cast<const f32x4v*>(tile + (16 * b + j) * ROWB + 64 * q + 16 * p);
   };
-  // 4M: re = dr rr - di ri, im = dr ri + di rr.  3M: t1 = dr rr, t2 = di ri,
-  // t3 = (dr + di)(rr + ri); re = t1 - t2, im = t3 - t1 - t2.
-  f32x4 acc[3][FB][NB];
+  auto dwrite = [&](const DRaw& d, int buf) __attribute__((always_inline)) {
 #pragma unroll
-  for (int t = 0; t < 3; ++t)
+    for (int i = 0; i < DI; ++i)
+      *reinterpret_cast<VT*>(dtile[buf] + (4 * FB * w + RPI * i + lrow) * ROWB + 8 * lcol) = d.v[i];
+  };
+  auto dread = [&](DFrag& df, int buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int a = 0; a < FB; ++a)
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+        df.v[a][p] = *reinterpret_cast<const f32x4v*>(dtile[buf] + (16 * a + j) * ROWB + 64 * q + 16 * p);
+  };
+  // 4M: re = dr rr - di ri, im = dr ri + di rr.  3M: t1 = dr rr, t2 = di ri,
+  // t3 = (dr + di)(rr + ri); re = t1 - t2, im = t3 - t1 - t2.  B3: as 4M,
+  // each real product split.
+  f32x4 acc[FORM == kForm3M ? 3 : 2][FB][NB];
+#pragma unroll
+  for (int t = 0; t < (FORM == kForm3M ? 3 : 2); ++t)
 #pragma unroll
     for (int a = 0; a < FB; ++a)
 #pragma unroll
       for (int b = 0; b < NB; ++b) acc[t][a][b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-  auto compute = [&](const Frag& r, const Dat& d) __attribute__((always_inline)) {
+  auto compute = [&](const Frag& r, const DFrag& d) __attribute__((always_inline)) {
+    if constexpr (FORM == kFormB3) {
+#pragma unroll
+      for (int a = 0; a < FB; ++a) {
+        const bf16x8 arh = __builtin_bit_cast(bf16x8, d.v[a][0]);
+        const bf16x8 arl = __builtin_bit_cast(bf16x8, d.v[a][1]);
+        const bf16x8 aih = __builtin_bit_cast(bf16x8, d.v[a][2]);
+        const bf16x8 ail = __builtin_bit_cast(bf16x8, d.v[a][3]);
+        const bf16x8 naih = neg_b16(aih), nail = neg_b16(ail);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const bf16x8 brh = __builtin_bit_cast(bf16x8, r.v[b][0]);
+          const bf16x8 brl = __builtin_bit_cast(bf16x8, r.v[b][1]);
+          const bf16x8 bih = __builtin_bit_cast(bf16x8, r.v[b][2]);
+          const bf16x8 bil = __builtin_bit_cast(bf16x8, r.v[b][3]);
+          f32x4 cr = acc[0][a][b], ci = acc[1][a][b];
+          cr = mfma_b16(arh, brh, cr);
+          cr = mfma_b16(arh, brl, cr);
+          cr = mfma_b16(arl, brh, cr);
+          cr = mfma_b16(naih, bih, cr);
+          cr = mfma_b16(naih, bil, cr);
+          cr = mfma_b16(nail, bih, cr);
+          ci = mfma_b16(arh, bih, ci);
+          ci = mfma_b16(arh, bil, ci);
+          ci = mfma_b16(arl, bih, ci);
+          ci = mfma_b16(aih, brh, ci);
+          ci = mfma_b16(aih, brl, ci);
+          ci = mfma_b16(ail, brh, ci);
+          acc[0][a][b] = cr;
+          acc[1][a][b] = ci;
+        }
+      }
+      return;
+    }
 #pragma unroll
     for (int u = 0; u < 8; ++u)
 #pragma unroll
@@ -374,8 +430,8 @@ __global__ __launch_bounds__(256) void k_apply_stream(const float* __restrict__ 
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
           const float rr = r.v[b][u / 2][2 * (u % 2)], ri = r.v[b][u / 2][2 * (u % 2) + 1];
-          const float dr = d.v[a][u / VEC][2 * (u % VEC)], di = d.v[a][u / VEC][2 * (u % VEC) + 1];
-          if constexpr (M3) {
+          const float dr = d.v[a][u / 2][2 * (u % 2)], di = d.v[a][u / 2][2 * (u % 2) + 1];
+          if constexpr (FORM == kForm3M) {
             acc[0][a][b] = mfma4(dr, rr, acc[0][a][b]);
             acc[1][a][b] = mfma4(di, ri, acc[1][a][b]);
             acc[2][a][b] = mfma4(dr + di, rr + ri, acc[2][a][b]);
@@ -389,50 +445,69 @@ __global__ __launch_bounds__(256) void k_apply_stream(const float* __restrict__ 
   };
   typedef std::false_type Full;
   typedef std::true_type Tail;
+  // every wave of the workgroup has the same slice, so the same chunk count
+  // and the same barriers
   const int nfull = m_hi > m_lo ? (m_hi - m_lo) / L : 0;
   auto at = [&](int k) { return m_lo + min(k, nfull - 1) * L; };
   Frag rf;
+  DFrag df;
   if (nfull > 0) {
     Raw ga, gb;
-    Dat da, db;
+    DRaw xa, xb;
     gload(ga, at(0), Full());
-    dload(da, at(0), Full());
+    dload(xa, at(0), Full());
     gload(gb, at(1), Full());
-    dload(db, at(1), Full());
-    // two chunks per pass, the loop's only exit at the bottom (an exit between
-    // a load and its use let the compiler sink the load past it); the
-    // scheduling barriers keep each chunk's loads ahead of the previous
-    // chunk's products.  The last passes re-load the final chunk, unused.
+    dload(xb, at(1), Full());
+    dwrite(xa, 0);
+    __syncthreads();
+    dload(xa, at(2), Full());
+    // Two chunks per pass; chunk k computes from R in ga (gb) and data in
+    // buffer k % 2 while chunk k + 1's data goes to the other buffer.  Each
+    // barrier publishes that write and retires every wave's reads of the
+    // buffer the next half overwrites.  The loop's only exit is at the
+    // bottom (an exit between a load and its use let the compiler sink the
+    // load past it); the scheduling barriers keep each chunk's loads ahead
+    // of the previous chunk's products.  The last passes re-load the final
+    // chunk, unused.
     int k = 0;
     for (; k + 2 <= nfull; k += 2) {
       lwrite(ga);
       lread(rf);
+      dread(df, 0);
+      dwrite(xb, 1);
       gload(ga, at(k + 2), Full());
-      __builtin_amdgcn_sched_barrier(0);
-      compute(rf, da);
-      dload(da, at(k + 2), Full());
+      dload(xb, at(k + 3), Full());
+      __syncthreads();
+      compute(rf, df);
       lwrite(gb);
       lread(rf);
+      dread(df, 1);
+      dwrite(xa, 0);
       gload(gb, at(k + 3), Full());
-      __builtin_amdgcn_sched_barrier(0);
-      compute(rf, db);
-      dload(db, at(k + 3), Full());
+      dload(xa, at(k + 4), Full());
+      __syncthreads();
+      compute(rf, df);
     }
-    if (k < nfull) {   // odd count: the last chunk is in ga, da
+    if (k < nfull) {   // odd count: the last chunk's R is in ga, its data in buffer 0
       lwrite(ga);
       lread(rf);
-      compute(rf, da);
+      dread(df, 0);
+      compute(rf, df);
     }
   }
   const int mt = m_lo + nfull * L;
   if (mt < m_hi) {
     Raw g;
-    Dat d;
+    DRaw x;
     gload(g, mt, Tail());
-    dload(d, mt, Tail());
+    dload(x, mt, Tail());
+    __syncthreads();   // every wave's reads of the data buffers are done
+    dwrite(x, 0);
     lwrite(g);
+    __syncthreads();
     lread(rf);
-    compute(rf, d);
+    dread(df, 0);
+    compute(rf, df);
   }
   cx<float>* out = reinterpret_cast<cx<float>*>(X) + (size_t)seg * F * N;
 #pragma unroll
@@ -443,7 +518,7 @@ __global__ __launch_bounds__(256) void k_apply_stream(const float* __restrict__ 
       for (int r = 0; r < 4; ++r) {
         const int f = 16 * a + 4 * q + r, n = n0 + 16 * b + j;
         float re, im;
-        if constexpr (M3) {
+        if constexpr (FORM == kForm3M) {
           re = acc[0][a][b][r] - acc[1][a][b][r];
           im = acc[2][a][b][r] - acc[0][a][b][r] - acc[1][a][b][r];
         } else {
@@ -657,11 +732,15 @@ size_t apply_stream_scratch_bytes(int F, int N, int M) {
   return nseg > 1 ? (size_t)nseg * F * N * 2 * sizeof(float) : 0;
 }
 
-hipError_t launch_apply_stream(const float* R, const float* D, float* X, int N, int M, int F,
-                               bool m3, Scratch& sc, hipStream_t s) {
+// The streamed apply of F frames (form: kForm4M, kForm3M on complex64 R and
+// data; kFormB3 on split-packed R and data, M then their padded row length).
+static hipError_t stream_apply(const void* R, const void* D, float* X, int N, int M, int F, int form,
+                               Scratch& sc, hipStream_t s) {
   if (F <= 0 || N <= 0) return hipSuccess;
   if (F < kStreamMinF || F > kStreamMaxF) return hipErrorInvalidValue;
+  if (form == kFormB3 && M % 32 != 0) return hipErrorInvalidValue;
   const bool vec = M % 2 == 0 && ((uintptr_t)R % 16) == 0 && ((uintptr_t)D % 16) == 0;
+  if (form == kFormB3 && !vec) return hipErrorInvalidValue;
   const int nseg = stream_slices(M);
   // slice length: whole 32-column chunks, so only the last slice has a
   // partial chunk
@@ -672,27 +751,27 @@ hipError_t launch_apply_stream(const float* R, const float* D, float* X, int N, 
     if (e != hipSuccess) return e;
   }
   float* out = nseg > 1 ? (float*)P : X;
-  auto go = [&](auto fb, auto form) {
-    constexpr int FB = decltype(fb)::value, NB = 2;
-    constexpr bool M3 = decltype(form)::value;
+  const float* Rf = (const float*)R;
+  const float* Df = (const float*)D;
+  auto go = [&](auto fb, auto fm) {
+    constexpr int FB = decltype(fb)::value, NB = 2, FORM = decltype(fm)::value;
     const int nrb = cdiv(N, 64 * NB);
     const dim3 grid((unsigned)(nrb * nseg)), block(256);
     if (vec)
-      hipLaunchKernelGGL((k_apply_stream<FB, NB, 2, M3>), grid, block, 0, s, R, D, out, N, M, F,
+      hipLaunchKernelGGL((k_apply_stream<FB, NB, 2, FORM>), grid, block, 0, s, Rf, Df, out, N, M, F,
                          nseg, seg_len, nrb);
-    else
-      hipLaunchKernelGGL((k_apply_stream<FB, NB, 1, M3>), grid, block, 0, s, R, D, out, N, M, F,
+    else if constexpr (FORM != kFormB3)
+      hipLaunchKernelGGL((k_apply_stream<FB, NB, 1, FORM>), grid, block, 0, s, Rf, Df, out, N, M, F,
                          nseg, seg_len, nrb);
     return hipGetLastError();
   };
   using std::integral_constant;
-  typedef integral_constant<bool, true> T3;
-  typedef integral_constant<bool, false> T4;
-  hipError_t e;
-  if (F <= 16)
-    e = m3 ? go(integral_constant<int, 1>(), T3()) : go(integral_constant<int, 1>(), T4());
-  else
-    e = m3 ? go(integral_constant<int, 2>(), T3()) : go(integral_constant<int, 2>(), T4());
+  auto by_form = [&](auto fb) {
+    if (form == kFormB3) return go(fb, integral_constant<int, kFormB3>());
+    if (form == kForm3M) return go(fb, integral_constant<int, kForm3M>());
+    return go(fb, integral_constant<int, kForm4M>());
+  };
+  hipError_t e = F <= 16 ? by_form(integral_constant<int, 1>()) : by_form(integral_constant<int, 2>());
   if (nseg > 1) {
     if (e == hipSuccess) {
       const int64_t n = (int64_t)F * N;
@@ -704,6 +783,16 @@ hipError_t launch_apply_stream(const float* R, const float* D, float* X, int N, 
     if (e == hipSuccess) e = f;
   }
   return e;
+}
+
+hipError_t launch_apply_stream(const float* R, const float* D, float* X, int N, int M, int F,
+                               bool m3, Scratch& sc, hipStream_t s) {
+  return stream_apply(R, D, X, N, M, F, m3 ? kForm3M : kForm4M, sc, s);
+}
+
+hipError_t launch_apply_stream_sp(const void* R, const void* D, float* X, int N, int Mp, int F,
+                                  Scratch& sc, hipStream_t s) {
+  return stream_apply(R, D, X, N, Mp, F, kFormB3, sc, s);
 }
 
 hipError_t launch_apply_b3(const ApplyBatch& b, Scratch& sc, hipStream_t s) {

@@ -92,17 +92,18 @@ hipError_t launch_right_pinv(const EncDev<T>& e, const T* Li, T* W, T* Z, TO* R,
                              hipStream_t s);
 // Applies of at most kRowApplyMaxF frames stream R row by row (HBM-bound),
 // their contraction cut into one slice per XCD when M >= kRowSliceMinM
-// (partials in scratch, apply_rows_scratch_bytes); FP32 plans do so up to
-// kStreamMinF - 1 frames and stream R into the matrix cores from there
-// (launch_apply_stream).  (Measured at N = 16384, M = 262144: 16-frame row
-// variants took 25-42 ms for 9-16 frames; at 5-8 frames the row kernel takes
-// 6.7-8.0 ms and the streamed one about 5.8 ms.)
+// (partials in scratch, apply_rows_scratch_bytes); FP32 and BF16X3 plans do
+// so up to kStreamMinF - 1 frames and stream R into the matrix cores from
+// there (launch_apply_stream, launch_apply_stream_sp).  (Measured at
+// N = 16384, M = 262144: 16-frame row variants took 25-42 ms for 9-16
+// frames; at 4-8 frames the row kernels take 6.2-8.9 ms and the streamed
+// one about 5.8 ms.)
 constexpr int kRowApplyMaxF = 8;
-constexpr int kStreamMinF = 5;
+constexpr int kStreamMinF = 3;
 constexpr int kStreamMaxF = 32;
-// The most frames a plan applies with the row kernel (fp32: an FP32 plan,
-// whose R is complex64).
-inline int row_apply_max_frames(bool fp32) { return fp32 ? kStreamMinF - 1 : kRowApplyMaxF; }
+// The most frames a plan applies with the row kernel (streamed: an FP32 or
+// BF16X3 plan, whose applies of kStreamMinF .. kStreamMaxF frames stream).
+inline int row_apply_max_frames(bool streamed) { return streamed ? kStreamMinF - 1 : kRowApplyMaxF; }
 constexpr int kRowSliceMinM = 8192;
 int row_slices(int M);
 template <typename T> size_t apply_rows_scratch_bytes(int F, int N, int M);
@@ -116,6 +117,10 @@ hipError_t launch_apply_rows(const T* R, const T* D, T* X, int N, int M, int F, 
 size_t apply_stream_scratch_bytes(int F, int N, int M);
 hipError_t launch_apply_stream(const float* R, const float* D, float* X, int N, int M, int F,
                                bool m3, Scratch& sc, hipStream_t s);
+// The same for a BF16X3 plan: split-packed R (N rows of Mp = sp_cols(M)
+// columns) and data (F rows of Mp columns).
+hipError_t launch_apply_stream_sp(const void* R, const void* D, float* X, int N, int Mp, int F,
+                                  Scratch& sc, hipStream_t s);
 template <typename T, typename SX, typename SD>
 hipError_t launch_forward(const EncDev<T>& e, const SX* X, int F, const SD* Din, T* Dout,
                           hipStream_t s);
