@@ -429,9 +429,10 @@ size_t plan_footprint(const Dims& d, int prec, const BuildForm& f) {
   b += 16 * Gd * Gd;            // L^-1 in FP64 during the factorisation
   b += cs * Gd * Gd;            // L^-1 kept
   if (!f.no_r && prec == PINV_BF16X3) {
-    // split-packed L^-1 and L^-H, W^T and R (rows padded to 32 columns)
+    // split-packed L^-1 and L^-H, W^T and R (rows padded to 32 columns), and
+    // a slab of conj(E) during the W product
     const size_t Np = sp_cols(N), Mp = sp_cols(M);
-    b += 2 * 8 * N * Np + 8 * M * Np + 8 * N * Mp;
+    b += 2 * 8 * N * Np + 8 * M * Np + 8 * N * Mp + 8 * Np * (size_t)e_slab_rows(N, M);
   } else if (!f.no_r) {
     b += ws * N * M;            // W (and Z for the right pseudoinverse)
     if (right) b += ws * N * M;
@@ -901,7 +902,7 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
   const size_t cs = f64 ? 16 : 8;
   const size_t ws = form.r_fp64 ? 16 : cs;   // W and Z element size
   void *G = nullptr, *L64 = nullptr, *W = nullptr, *Z = nullptr, *PW = nullptr;
-  void *LS = nullptr, *LHS = nullptr;   // split-packed L^-1 and L^-H (BF16X3)
+  void *LS = nullptr, *LHS = nullptr, *ES = nullptr;   // split-packed L^-1, L^-H, conj(E) slab (BF16X3)
   const bool b3 = o->prec == PINV_BF16X3;
   const size_t Gd = p->G;   // order of the Gram and the factor
   hipError_t he;
@@ -918,6 +919,7 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
       if (PW) (void)hipFreeAsync(PW, s);                                              \
       if (LS) (void)hipFreeAsync(LS, s);                                              \
       if (LHS) (void)hipFreeAsync(LHS, s);                                            \
+      if (ES) (void)hipFreeAsync(ES, s);                                              \
       return cleanup(he == hipErrorOutOfMemory ? PINV_ERR_NOMEM : PINV_ERR_DEVICE);   \
     }                                                                                 \
   } while (0)
@@ -1079,7 +1081,11 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
     BCHK(workspace_alloc(&LHS, 8 * N * Np, c, s));
     BCHK(launch_sp_pack<double>((const double*)L64, (int64_t)N, d.N, d.N, false, false, LS, s));
     BCHK(launch_sp_pack<double>((const double*)L64, (int64_t)N, d.N, d.N, true, true, LHS, s));
-    BCHK(launch_trmm_w_sp(p->e32, LS, W, s));
+    const int64_t slab = e_slab_rows(N, M);
+    BCHK(workspace_alloc(&ES, 8 * slab * Np, c, s));
+    BCHK(launch_trmm_w_sp(p->e32, LS, W, ES, slab, s));
+    BCHK(hipFreeAsync(ES, s));
+    ES = nullptr;
     BCHK(hipEventRecord(p->ev[3], s));
     BCHK(launch_trmm_r_sp(W, LHS, p->R, d.N, d.M, s));
     BCHK(hipFreeAsync(LHS, s));

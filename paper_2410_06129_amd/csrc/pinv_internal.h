@@ -170,7 +170,19 @@ hipError_t launch_sp_pack(const S* src, int64_t ld, int rows, int K, bool trans,
 hipError_t launch_sp_unpack(const void* sp, int rows, int K, float* dst, hipStream_t s);
 // W^T (SP, M rows, k = n) from L^-1 (SP, N rows); R (SP, N rows, k = m) from
 // W^T and L^-H (SP, N rows: conj(Li[n'][n]) at row n, k = n').
-hipError_t launch_trmm_w_sp(const EncDev<float>& e, const void* Li, void* W, hipStream_t s);
+// W^T (SP, rows m, k = n) from L^-1 (SP rows) via conj(E) written to the
+// workspace Es, slab_rows samples at a time (Es: 8 slab_rows sp_cols(N)
+// bytes; slab_rows a multiple of 64, e_slab_rows).
+hipError_t launch_trmm_w_sp(const EncDev<float>& e, const void* Li, void* W, void* Es,
+                            int64_t slab_rows, hipStream_t s);
+// Samples per conj(E) slab of the BF16X3 W product: about 4 GiB, a multiple
+// of 512, at most M rounded up to 64.
+constexpr int64_t kESlabBytes = 4ll << 30;
+inline int64_t e_slab_rows(int64_t N, int64_t M) {
+  const int64_t per = 8 * sp_cols(N);
+  const int64_t s = std::max<int64_t>(512, kESlabBytes / per / 512 * 512);
+  return std::min<int64_t>(s, (M + 63) / 64 * 64);
+}
 hipError_t launch_trmm_r_sp(const void* W, const void* Lh, void* R, int N, int M, hipStream_t s);
 // Grouped apply on SP operands: items carry D (SP, F rows) and R (SP, N rows)
 // with M = the padded contraction length sp_cols(M).

@@ -109,12 +109,51 @@ hipError_t launch_sp_unpack(const void* sp, int rows, int K, float* dst, hipStre
 // ---------------------------------------------------------------------------
 // W^T = (L^-1 E^H)^T, written SP with rows m and k = n
 // ---------------------------------------------------------------------------
+// conj(E) is first written split-packed, a slab of samples at a time (rows m,
+// k = n, zero past N), and the product then loads both operands as the R
+// product does.  Generating E inside the product's loop (two complex
+// multiplies, the split and the table loads per element: 295 vector
+// instructions per chunk against the R product's 132) held the bf16 pipe at
+// 0.43 busy against R's 0.56; the slab costs one write and one read of
+// 8 Np bytes per sample, about 1% of the product.
+//
+// Slab rows r0 .. r0 + 64 of workgroup b, columns (b % nbc) kGenChunks 32 ..
+// for kGenChunks chunks of 32: thread t generates columns 8 (t / 64) .. + 8 of
+// row t % 64 of each chunk, as the generated-row loader does for a tile, and
+// writes the 64-byte group.
+constexpr int kGenChunks = 16;
+
 template <int FEAT, bool AL>
-__global__ __launch_bounds__(B3Cfg::NT, B3Cfg::MIN_BLOCKS) void k_trmm_w_sp(EncDev<float> e, const uint4* __restrict__ Li,
-                                                   int64_t gn, void* __restrict__ W) {
+__global__ __launch_bounds__(256) void k_gen_e_sp(EncDev<float> e, int m0, int rows, int64_t gn,
+                                                  uint4* __restrict__ Es) {
+  typedef B3Cfg Cfg;   // 256 threads, chunks of BK = 32 columns
+  const int64_t kp = gn * 8;
+  const int nbc = (int)((kp + 32 * kGenChunks - 1) / (32 * kGenChunks));
+  const int r0 = (int)(blockIdx.x / nbc) * 64, cb = (int)(blockIdx.x % nbc);
+  LoadGenRowSP<Cfg, 64, true, FEAT, AL> g;   // conj(E[m][n]), zero past M and N
+  g.init(e, m0 + r0);
+  const int o = threadIdx.x % 64, kk0 = (int)(threadIdx.x / 64) * 8;
+  const bool live = r0 + o < rows;
+  for (int c = 0; c < kGenChunks; ++c) {
+    const int k0 = (cb * kGenChunks + c) * 32;
+    if (k0 >= kp) break;   // the same for every thread of the workgroup
+    g.fetch(k0, e.N);
+    g.finish(0, 1);
+    if (live) {
+      uint4* d = Es + ((int64_t)(r0 + o) * gn + (k0 + kk0) / 8) * 4;
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl)
+        d[pl] = uint4{g.pk[0][pl][0], g.pk[0][pl][1], g.pk[0][pl][2], g.pk[0][pl][3]};
+    }
+  }
+}
+
+// W^T tiles for samples m0 .. m0 + rows from the slab Es (its rows 0 ..).
+__global__ __launch_bounds__(B3Cfg::NT, B3Cfg::MIN_BLOCKS) void k_trmm_w_sp(
+    const uint4* __restrict__ Li, const uint4* __restrict__ Es, int64_t gn, int m0, int rows,
+    void* __restrict__ W, int N, int M) {
   typedef B3Cfg Cfg;
-  const int N = e.N, M = e.M;
-  const int nbi = (N + Cfg::BM - 1) / Cfg::BM, nbj = (M + Cfg::BN - 1) / Cfg::BN;
+  const int nbi = (N + Cfg::BM - 1) / Cfg::BM, nbj = (rows + Cfg::BN - 1) / Cfg::BN;
   // as the FP32 product: each XCD runs column groups of 8 sample blocks over
   // every row block, longest K ranges first
   int r, bj;
@@ -125,13 +164,16 @@ __global__ __launch_bounds__(B3Cfg::NT, B3Cfg::MIN_BLOCKS) void k_trmm_w_sp(EncD
   la.gpr = gn;
   la.o0 = bi * Cfg::BM;
   la.oend = N;
-  LoadGenRowSP<Cfg, Cfg::BN, true, FEAT, AL> lb;   // conj(E[m][n'])
-  lb.init(e, bj * Cfg::BN);
+  LoadSP<Cfg, Cfg::BN> lb;   // conj(E) rows m of the slab
+  lb.p = Es;
+  lb.gpr = gn;
+  lb.o0 = bj * Cfg::BN;
+  lb.oend = rows;
   AccTile<Cfg> acc;
   acc.zero();
   mainloop<Cfg>(la, lb, 0, min(N, (bi + 1) * Cfg::BM), acc, smem_base<Cfg>());
   // rows N .. Np of W^T's k range come out zero (their L^-1 rows load as zeros)
-  acc_store_sp_t<Cfg>(acc, W, gn, bi * Cfg::BM, bj * Cfg::BN, (int)(gn * 8), M);
+  acc_store_sp_t<Cfg>(acc, W, gn, bi * Cfg::BM, m0 + bj * Cfg::BN, (int)(gn * 8), M);
 }
 
 // ---------------------------------------------------------------------------
@@ -166,20 +208,33 @@ __global__ __launch_bounds__(B3Cfg::NT, B3Cfg::MIN_BLOCKS) void k_trmm_r_sp(cons
   acc_store_sp_t<Cfg>(acc, R, gm, bm * Cfg::BM, bn * Cfg::BN, (int)(gm * 8), N);
 }
 
-hipError_t launch_trmm_w_sp(const EncDev<float>& e, const void* Li, void* W, hipStream_t s) {
+hipError_t launch_trmm_w_sp(const EncDev<float>& e, const void* Li, void* W, void* Es,
+                            int64_t slab_rows, hipStream_t s) {
   typedef B3Cfg Cfg;
-  const int tiles = cdiv(e.N, Cfg::BM) * cdiv(e.M, Cfg::BN);
-  if (tiles == 0) return hipSuccess;
-  const int64_t gn = sp_cols(e.N) / 8;
-  return with_feat_al(enc_features(e), row_aligned(e, Cfg::BK), [&](auto fc, auto al) {
-    auto kern = k_trmm_w_sp<decltype(fc)::value, decltype(al)::value>;
-    // once per kernel (thread-safe static initialisation)
-    static const hipError_t attr = allow_smem(kern, smem_bytes<Cfg>());
-    if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL(kern, dim3(tiles), dim3(Cfg::NT), smem_bytes<Cfg>(), s, e,
-                       reinterpret_cast<const uint4*>(Li), gn, W);
-    return hipGetLastError();
-  });
+  const int N = e.N, M = e.M;
+  if (N <= 0 || M <= 0) return hipSuccess;
+  if (slab_rows <= 0 || slab_rows % Cfg::BN != 0) return hipErrorInvalidValue;
+  static const hipError_t attr = allow_smem(k_trmm_w_sp, smem_bytes<Cfg>());
+  if (attr != hipSuccess) return attr;
+  const int64_t gn = sp_cols(N) / 8;
+  const int nbc = (int)cdiv(gn * 8, 32 * kGenChunks);
+  for (int64_t m0 = 0; m0 < M; m0 += slab_rows) {
+    const int rows = (int)std::min<int64_t>(slab_rows, M - m0);
+    hipError_t err = with_feat_al(enc_features(e), row_aligned(e, Cfg::BK), [&](auto fc, auto al) {
+      hipLaunchKernelGGL((k_gen_e_sp<decltype(fc)::value, decltype(al)::value>),
+                         dim3((unsigned)(cdiv(rows, 64) * nbc)), dim3(256), 0, s, e, (int)m0, rows, gn,
+                         reinterpret_cast<uint4*>(Es));
+      return hipGetLastError();
+    });
+    if (err != hipSuccess) return err;
+    const int tiles = cdiv(N, Cfg::BM) * cdiv(rows, Cfg::BN);
+    hipLaunchKernelGGL(k_trmm_w_sp, dim3(tiles), dim3(Cfg::NT), smem_bytes<Cfg>(), s,
+                       reinterpret_cast<const uint4*>(Li), reinterpret_cast<const uint4*>(Es), gn,
+                       (int)m0, rows, W, N, M);
+    err = hipGetLastError();
+    if (err != hipSuccess) return err;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_trmm_r_sp(const void* W, const void* Lh, void* R, int N, int M, hipStream_t s) {
