@@ -170,10 +170,14 @@ typedef struct {
   int32_t prec;               /* pinv_precision */
   int32_t flags;              /* PINV_FLAG_* */
   int32_t cprod;              /* pinv_cprod; PINV_BF16X3 plans take only AUTO */
-  int32_t nb;                 /* factorisation block size: 0 (default) or 64.  Fixed at 64:
-                                 the diagonal-block kernel holds one 64 x 64 complex128 block
-                                 in registers, one column per lane of a 64-wide wavefront,
-                                 and the panel and trailing tiles are 64 x 64 */
+  int32_t nb;                 /* factorisation block size (Sec. 2.3): 0 (default, 128), 64 or
+                                 128.  The factorisation steps 64 columns at a time (the
+                                 diagonal-block kernel holds one 64 x 64 complex128 block in
+                                 registers, one column per lane of a wavefront); nb = 64
+                                 updates the whole trailing matrix after every step (rank 64),
+                                 nb = 128 after every second step (rank 128, the first step of
+                                 a pair updating only the next block column).  The
+                                 factorisation's products run 4M whatever cprod says */
   int32_t gram;               /* pinv_gram_form */
   int32_t route;              /* pinv_route */
   int32_t trunc;              /* pinv_trunc (PINV_ROUTE_EIGEN only) */

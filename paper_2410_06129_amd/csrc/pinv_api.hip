@@ -405,8 +405,12 @@ void drain_frees(pinv_context* c, hipStream_t s, bool wait) {
 
 // Build options after defaults: the complex-product form of W, R and the
 // apply, the Gram form, and whether W and R are formed in FP64.
+// Factorisation block size when the options leave it at 0.
+constexpr int kDefaultNb = 128;
+
 struct BuildForm {
   bool m3 = true;
+  int nb = kDefaultNb;
   int gram = PINV_GRAM_SHARED;
   bool r_fp64 = false;
   bool no_r = false;
@@ -675,9 +679,11 @@ static pinv_status check_build(const pinv_encoding* e, const pinv_build_opts* o,
     return fail(PINV_ERR_INVALID, "unknown flag bits");
   if (o->cprod < PINV_CPROD_AUTO || o->cprod > PINV_CPROD_4M)
     return fail(PINV_ERR_INVALID, "unknown cprod");
-  if (o->nb != 0 && o->nb != 64)
-    return fail(PINV_ERR_UNSUPPORTED, "nb must be 0 or 64: the factorisation's diagonal block is "
-                                      "64 x 64, one column per lane of a wavefront");
+  if (o->nb != 0 && o->nb != 64 && o->nb != 128)
+    return fail(PINV_ERR_UNSUPPORTED, "nb must be 0, 64 or 128: the factorisation steps 64 columns "
+                                      "at a time (its diagonal block holds one column per lane of "
+                                      "a wavefront) and updates the trailing matrix every 64 or "
+                                      "128 columns");
   if (o->gram < PINV_GRAM_AUTO || o->gram > PINV_GRAM_FULL)
     return fail(PINV_ERR_INVALID, "unknown gram form");
   if (!(o->lambda >= 0.0) || !isfinite(o->lambda)) return fail(PINV_ERR_INVALID, "lambda must be finite and >= 0");
@@ -755,9 +761,10 @@ static pinv_status check_build(const pinv_encoding* e, const pinv_build_opts* o,
   form->m3 = o->cprod == PINV_CPROD_3M   ? true
              : o->cprod == PINV_CPROD_4M ? false
                                          : o->prec != PINV_FP64 && !r_fp64;
+  form->nb = o->nb == 0 ? kDefaultNb : o->nb;
   *lam_out = lam;
   const int bits = (form->m3 ? 1 : 0) | (gram << 1) | (r_fp64 ? 16 : 0) | (no_r ? 32 : 0) |
-                   (form->route << 6) | (form->trunc << 7);
+                   (form->route << 6) | (form->trunc << 7) | (form->nb == 128 ? 1 << 9 : 0);
   *key_out = plan_key(e, *d, lam, o->prec, bits, form->trunc_value);
   return PINV_OK;
 }
@@ -1042,7 +1049,7 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
   } else {
   // 2. shift + blocked Cholesky with L^-1 (a4), FP64
   BCHK(launch_cholinv((double*)G, (double*)L64, (int)Gd, lam, p->info, s,
-                      s ? p->ctx->aux : p->ctx->aux_nb));
+                      s ? p->ctx->aux : p->ctx->aux_nb, form.nb));
   if (!f64) BCHK(launch_to_f32((const double*)L64, (float*)p->Linv, Gd * Gd, s));
   BCHK(hipEventRecord(p->ev[2], s));
   // 3. W = L^-1 E^H, R = L^-H W (a5); a factor-only plan stops at L^-1.  With

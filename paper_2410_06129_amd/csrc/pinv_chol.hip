@@ -180,9 +180,13 @@ __global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ A, doub
   });
 }
 
-// Step k trailing update: A_ij -= L_ik L_jk^H for k < j <= i ("herk" tiles)
-// and B_ij -= L_ik Y_kj for i > k, j <= k (inverse tiles).  `part` selects
-// the tiles of one launch:
+// Trailing update after steps kb .. k = kb + kn - 1 (kn = 1, or 2 for the
+// two-level factorisation): A_ij -= sum_{l=kb..k} L_il L_jl^H for k < j <= i
+// ("herk" tiles) and B_ij -= sum_{l=kb..k} L_il Y_lj for i > k, j <= k
+// (inverse tiles), one contraction over the kn 64-column panels, which lie
+// side by side in A's columns and in Li's rows (Y_lj for j > l is zero: Li
+// starts zeroed and only its lower blocks are written).  `part` selects the
+// tiles of one launch:
 //   0  all of them;
 //   1  the look-ahead set: block column k+1 of A and block row k+1 of B, all
 //      that step k+1's diagonal block and panel read;
@@ -190,19 +194,20 @@ __global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ A, doub
 //      step k+1's diagonal and panel kernels.
 // The accumulators start from -(old tile), loaded together with the first
 // operand chunk, and the tile is stored negated: no read after the products.
+template <class Cfg>
 __global__ __launch_bounds__(256) void k_chol_trailing(double* __restrict__ A, double* __restrict__ Li,
-                                                       int N, int k, const int* __restrict__ info,
-                                                       int part) {
+                                                       int N, int kb, int kn,
+                                                       const int* __restrict__ info, int part) {
   if (*info) return;
-  typedef CholCfg Cfg;
   const int nb = 64;
+  const int k = kb + kn - 1;
   const int nblk = (N + nb - 1) / nb;
   const int rem = nblk - k - 1;
   const int t = blockIdx.x;
   const cx<double>* Ac = reinterpret_cast<const cx<double>*>(A);
   const cx<double>* Lc = reinterpret_cast<const cx<double>*>(Li);
   double* smem = smem_base<Cfg>();
-  const int kw = min(N, (k + 1) * nb) - k * nb;
+  const int kw = min(N, (k + 1) * nb) - kb * nb;
   bool herk;
   int r0, c0;
   if (part == 1) {
@@ -234,21 +239,21 @@ __global__ __launch_bounds__(256) void k_chol_trailing(double* __restrict__ A, d
     re = -o.re;
     im = -o.im;
   });
-  LoadDenseKC<Cfg, 64, Cfg::LDA, double, false> la;      // L_ik[m][l] at A[(i*nb+m)*N + k*nb + l]
-  la.p = Ac + k * nb;
+  LoadDenseKC<Cfg, 64, Cfg::LDA, double, false> la;      // L_il[m][.] at A[(i*nb+m)*N + kb*nb + .]
+  la.p = Ac + kb * nb;
   la.ld = N;
   la.o0 = r0;
   la.oend = N;
   if (herk) {
-    LoadDenseKC<Cfg, 64, Cfg::LDB, double, true> lb;     // conj(L_jk[n][l])
-    lb.p = Ac + k * nb;
+    LoadDenseKC<Cfg, 64, Cfg::LDB, double, true> lb;     // conj(L_jl[n][.])
+    lb.p = Ac + kb * nb;
     lb.ld = N;
     lb.o0 = c0;
     lb.oend = N;
     mainloop<Cfg, false>(la, lb, 0, kw, acc, smem);
   } else {
-    LoadDenseOC<Cfg, 64, Cfg::LDB, double, false> lb;    // Y_kj[l][n] at Li[(k*nb+l)*N + j*nb + n]
-    lb.p = Lc + (size_t)(k * nb) * N;
+    LoadDenseOC<Cfg, 64, Cfg::LDB, double, false> lb;    // Y_lj[.][n] at Li[(kb*nb+.)*N + j*nb + n]
+    lb.p = Lc + (size_t)(kb * nb) * N;
     lb.ld = N;
     lb.o0 = c0;
     lb.oend = min(N, c0 + nb);
@@ -263,16 +268,44 @@ __global__ __launch_bounds__(256) void k_chol_trailing(double* __restrict__ A, d
 
 // host launcher
 
-// With an auxiliary stream `aux` the factorisation looks ahead one step: on
-// s, step k's look-ahead tiles (part 1) then step k+1's diagonal block and
-// panel; on aux, step k's remaining tiles (part 2) beside them.  Events order
-// part 2 of step k after step k's panel, and step k+1's part 1 after step k's
-// part 2 (which updated the blocks it reads and writes).  Without aux, one
-// launch per step does all trailing tiles on s.
-hipError_t launch_cholinv(double* A, double* Li, int N, double lam, int* info, hipStream_t s,
-                          hipStream_t aux) {
-  const int nb = 64;
-  const int nblk = cdiv(N, nb);
+// One factorisation step's trailing launches of step range kb .. kb + kn - 1
+// over tiles `part`.
+template <class Cfg>
+static void trailing(double* A, double* Li, int N, int kb, int kn, int* info, int part,
+                     hipStream_t st) {
+  const int nblk = cdiv(N, 64);
+  const int k = kb + kn - 1;
+  const int rem = nblk - k - 1;
+  int tiles;
+  if (part == 1) {
+    tiles = rem + (k + 1);
+  } else {
+    const int r = part == 2 ? rem - 1 : rem;
+    tiles = r * (r + 1) / 2 + r * (k + 1);
+  }
+  if (tiles <= 0) return;
+  hipLaunchKernelGGL(k_chol_trailing<Cfg>, dim3(tiles), dim3(256), smem_bytes<Cfg>(), st, A, Li, N,
+                     kb, kn, (const int*)info, part);
+}
+
+// Blocked right-looking factorisation, 64-column steps.  nb = 64: every
+// step updates the whole trailing matrix (rank 64).  nb = 128 (two-level):
+// the first step of each pair updates only the next block column (and block
+// row of the inverse), and after the second step one rank-128 update covers
+// the rest, so the trailing matrix is read and written half as often and
+// each tile runs twice the matrix products per load of its old value (at
+// N = 16384: 238 against 260 ms).
+//
+// With an auxiliary stream `aux` the factorisation looks ahead: the trailing
+// tiles the next step's diagonal block and panel read (part 1) run on s, the
+// rest (part 2) on aux beside the next diagonal and panel kernels.  Events
+// order part 2 after the panel it reads, and every later launch on s that
+// touches its tiles after it.  Without aux everything runs on s in order.
+template <class Cfg>
+static hipError_t cholinv(double* A, double* Li, int N, double lam, int* info, hipStream_t s,
+                          hipStream_t aux, int nb) {
+  const int nblk = cdiv(N, 64);
+  const int kn_max = nb / 64;
   const size_t diag_smem = kDiagSmem;
   const size_t sm = smem_bytes<CholCfg>();
   hipEvent_t ev_panel = nullptr, ev_rest = nullptr;
@@ -286,35 +319,47 @@ hipError_t launch_cholinv(double* A, double* Li, int N, double lam, int* info, h
   }
   hipError_t err = hipSuccess;
   bool rest_pending = false;
-  for (int k = 0; k < nblk && err == hipSuccess; ++k) {
-    hipLaunchKernelGGL(k_chol_diag<kDiagWaves>, dim3(1), dim3(64 * kDiagWaves), diag_smem, s, A, Li,
-                       N, nb, k, lam, info);
-    const int ntiles = nblk - 1;   // (nblk-k-1) panel + k inverse blocks
-    if (ntiles > 0)
-      hipLaunchKernelGGL(k_chol_panel, dim3(ntiles), dim3(256), sm, s, A, Li, N, k, (const int*)info);
-    const int rem = nblk - k - 1;
-    if (rem <= 0) break;
+  auto wait_rest = [&]() {
+    if (rest_pending) {
+      err = hipStreamWaitEvent(s, ev_rest, 0);
+      rest_pending = false;
+    }
+  };
+  for (int kb = 0; kb < nblk && err == hipSuccess; kb += kn_max) {
+    const int kn = std::min(kn_max, nblk - kb);
+    for (int k = kb; k < kb + kn && err == hipSuccess; ++k) {
+      hipLaunchKernelGGL(k_chol_diag<kDiagWaves>, dim3(1), dim3(64 * kDiagWaves), diag_smem, s, A, Li,
+                         N, 64, k, lam, info);
+      if (nblk - 1 > 0)   // (nblk-k-1) panel tiles + k inverse tiles
+        hipLaunchKernelGGL(k_chol_panel, dim3(nblk - 1), dim3(256), sm, s, A, Li, N, k,
+                           (const int*)info);
+      if (k + 1 < kb + kn) {
+        // inside a pair: the next step's block column and row from this step
+        // alone (after the previous pair's part 2, which updated them)
+        wait_rest();
+        if (err != hipSuccess) break;
+        trailing<Cfg>(A, Li, N, k, 1, info, 1, s);
+      }
+    }
+    if (err != hipSuccess) break;
+    const int last = kb + kn - 1;
+    if (nblk - last - 1 <= 0) break;
     if (!aux) {
-      hipLaunchKernelGGL(k_chol_trailing, dim3(rem * (rem + 1) / 2 + rem * (k + 1)), dim3(256), sm, s,
-                         A, Li, N, k, (const int*)info, 0);
+      trailing<Cfg>(A, Li, N, kb, kn, info, 0, s);
       err = hipGetLastError();
       continue;
     }
-    // part 2 of step k (aux) after step k's panel and after part 2 of step k-1
+    // part 2 (aux) after this pair's last panel and after the previous part 2
     if ((err = hipEventRecord(ev_panel, s)) != hipSuccess) break;
     if ((err = hipStreamWaitEvent(aux, ev_panel, 0)) != hipSuccess) break;
-    // part 1 of step k (s) after part 2 of step k-1
-    if (rest_pending && (err = hipStreamWaitEvent(s, ev_rest, 0)) != hipSuccess) break;
-    hipLaunchKernelGGL(k_chol_trailing, dim3(rem + (k + 1)), dim3(256), sm, s, A, Li, N, k,
-                       (const int*)info, 1);
-    const int r2 = rem - 1;
-    if (r2 > 0) {
-      hipLaunchKernelGGL(k_chol_trailing, dim3(r2 * (r2 + 1) / 2 + r2 * (k + 1)), dim3(256), sm, aux,
-                         A, Li, N, k, (const int*)info, 2);
+    // part 1 (s) after the previous part 2
+    wait_rest();
+    if (err != hipSuccess) break;
+    trailing<Cfg>(A, Li, N, kb, kn, info, 1, s);
+    if (nblk - last - 2 > 0) {
+      trailing<Cfg>(A, Li, N, kb, kn, info, 2, aux);
       if ((err = hipEventRecord(ev_rest, aux)) != hipSuccess) break;
       rest_pending = true;
-    } else {
-      rest_pending = false;
     }
     err = hipGetLastError();
   }
@@ -326,6 +371,16 @@ hipError_t launch_cholinv(double* A, double* Li, int N, double lam, int* info, h
   }
   if (err != hipSuccess) return err;
   return hipGetLastError();
+}
+
+// The trailing tiles run four real products per complex product: three (Gauss)
+// took longer at N = 16384 (321 against 260 ms at nb = 64, 277 against 238
+// at nb = 128), the third LDS plane and the extra accumulators (one wavefront
+// per SIMD instead of two) outweighing the fewer matrix products.
+hipError_t launch_cholinv(double* A, double* Li, int N, double lam, int* info, hipStream_t s,
+                          hipStream_t aux, int nb) {
+  if (nb != 64 && nb != 128) return hipErrorInvalidValue;
+  return cholinv<CholCfg>(A, Li, N, lam, info, s, aux, nb);
 }
 
 }  // namespace pinv

@@ -65,8 +65,10 @@ struct Scratch {
 
 template <typename T> hipError_t launch_gram(const EncDev<T>& e, double* G, int flush, hipStream_t s);
 template <typename T> hipError_t launch_gram_shared(const EncDev<T>& e, double* G, hipStream_t s);
+// Cholesky of A + lam I (FP64, in place) with L^-1 formed alongside in Li
+// (zeroed by the caller); nb = 64 or 128 (two-level).
 hipError_t launch_cholinv(double* A, double* Li, int N, double lam, int* info, hipStream_t s,
-                          hipStream_t aux);
+                          hipStream_t aux, int nb);
 // Triangular products forming R; m3 selects three real products per complex
 // product (else four).  R may be stored in a narrower type TO than T.  With
 // rows / kdim >= 0 the factor is dense instead of lower triangular: W has

@@ -122,14 +122,18 @@ def test_product_gram_and_r_forms_without_device():
     _, b32 = pinv.pinv_encoding_key(enc, 1e-3, prec=pinv.FP32)
     k64r, b64r = pinv.pinv_encoding_key(enc, 1e-3, prec=pinv.FP32, flags=pinv.FLAG_R_FP64)
     assert b64r - b32 == 8 * N * M
-    pinv.pinv_encoding_key(enc, 1e-3, nb=64)
+    # nb: 0 resolves to 128 (two-level); 64 is a different factorisation order
+    k0 = pinv.pinv_encoding_key(enc, 1e-3)[0]
+    assert k0 == pinv.pinv_encoding_key(enc, 1e-3, nb=128)[0]
+    assert k0 != pinv.pinv_encoding_key(enc, 1e-3, nb=64)[0]
     pinv.pinv_encoding_key(encb0, 1e-3, gram=pinv.GRAM_SHARED)
     for want, kw, e in ((pinv.ERR_INVALID, dict(gram=pinv.GRAM_PSF), encb0),
                         (pinv.ERR_INVALID, dict(gram=9), enc),
                         (pinv.ERR_INVALID, dict(flags=pinv.FLAG_GRAM_FULL, gram=pinv.GRAM_PSF), enc),
                         (pinv.ERR_INVALID, dict(cprod=3), enc),
                         (pinv.ERR_INVALID, dict(prec=pinv.BF16X3, cprod=pinv.CPROD_3M), enc),
-                        (pinv.ERR_UNSUPPORTED, dict(nb=128), enc),
+                        (pinv.ERR_UNSUPPORTED, dict(nb=96), enc),
+                        (pinv.ERR_UNSUPPORTED, dict(nb=256), enc),
                         (pinv.ERR_INVALID, dict(prec=pinv.FP64, flags=pinv.FLAG_R_FP64), enc),
                         (pinv.ERR_INVALID, dict(flags=pinv.FLAG_R_FP64 | pinv.FLAG_NO_R), enc)):
         _expect(pinv, want, lambda: pinv.pinv_encoding_key(e, 1e-3, **kw))
