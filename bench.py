@@ -178,12 +178,12 @@ def measured_traffic(kernel: str, workload: str):
 
 # the FP32 plan's kernels (3M, 128x64 tiles) and the BF16X3 plan's split
 # kernels, by their template signature
-PMC_KERNELS = {"trmm_w": "k_trmm_w<pinv::TileCfg<float, 128, 64, 8, true>,",
-               "trmm_r": "k_trmm_r<pinv::TileCfg<float, 128, 64, 8, true>, float>",
-               "apply": "k_apply<pinv::TileCfg<float, 128, 64, 8, true>, false>",
-               "trmm_w_bf16x3": "k_trmm_w_sp<4, true>",
+PMC_KERNELS = {"trmm_w": "k_trmm_w<pinv::TileCfg<float, 128, 64, 8, true, 2>,",
+               "trmm_r": "k_trmm_r<pinv::TileCfg<float, 128, 64, 8, true, 2>, float>",
+               "apply": "k_apply<pinv::TileCfg<float, 128, 64, 8, true, 2>, false>",
+               "trmm_w_bf16x3": "k_trmm_w_sp(",
                "trmm_r_bf16x3": "k_trmm_r_sp(",
-               "apply_bf16x3": "k_apply<pinv::TileCfgB3<128, 128, 2, 4>, false>"}
+               "apply_bf16x3": "k_apply<pinv::TileCfgB3<128, 64, 2, 2, 1>, false>"}
 
 
 def algorithmic_bytes(N: int, M: int, F: int) -> dict:
@@ -213,9 +213,11 @@ def pmc_mfma_summary(d) -> dict:
     agg = defaultdict(lambda: defaultdict(float))
     disp = defaultdict(set)
     names = dict(PMC_KERNELS, gram_psf="k_psf(", chol_trailing="k_chol_trailing", chol_panel="k_chol_panel",
+                 gen_e_bf16x3="k_gen_e_sp<",
                  chol_diag="k_chol_diag", adjoint_fp64="k_adjoint<", resid="k_resid", tri_frames="k_tri_frames",
-                 trmm_w_fp64_formed="k_trmm_w<pinv::TileCfg<double", trmm_r_fp64_formed="k_trmm_r<pinv::TileCfg<double, 64, 64, 8, false>, float>",
-                 apply_seg="k_apply<pinv::TileCfg<float, 128, 64, 8, false>, true>")
+                 trmm_w_fp64_formed="k_trmm_w<pinv::TileCfg<double",
+                 trmm_r_fp64_formed="k_trmm_r<pinv::TileCfg<double, 64, 64, 8, false, 2>, float>",
+                 apply_seg="k_apply<pinv::TileCfg<float, 128, 64, 8, false, 2>, true>")
     for k, c, v, did in rows:
         for key, pat in names.items():
             if pat in k:
@@ -235,9 +237,10 @@ def pmc_mfma_summary(d) -> dict:
 
 
 def pmc_summary(dirs, frames: int) -> dict:
-    """Per-launch HBM bytes of the dominant FP32 kernels from two rocprofv3 counter
-    runs of `bench.py --pmc-run` (FETCH_SIZE, WRITE_SIZE; KiB per dispatch),
-    scaled by what the same counters read for the plain 2 GiB copy it runs first."""
+    """HBM bytes per product (build) or apply of the dominant kernels from two
+    rocprofv3 counter runs of `bench.py --pmc-run` (FETCH_SIZE, WRITE_SIZE; KiB
+    per dispatch, summed over a product's launches), scaled by what the same
+    counters read for the plain 2 GiB copy it runs first."""
     import sqlite3
     import glob
 
@@ -259,8 +262,10 @@ def pmc_summary(dirs, frames: int) -> dict:
         copy = max(v for n, v in rows if "copyBuffer" in n or "elementwise_kernel" in n)
         per = {}
         for key, pat in PMC_KERNELS.items():
+            # the run builds and applies each kind once; the BF16X3 W product is
+            # one launch per conj(E) slab, summed to the product's bytes
             xs = [v for n, v in rows if pat in n]
-            per[key] = sum(xs) / len(xs) if xs else None
+            per[key] = sum(xs) if xs else None
         vals[counter] = (copy, per)
     copy_bytes = 2.0 ** 31
     fscale = copy_bytes / (vals["FETCH_SIZE"][0] * 1024.0)

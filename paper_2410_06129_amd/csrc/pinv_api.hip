@@ -84,8 +84,7 @@ struct pinv_plan {
 
 struct pinv_context {
   int device = 0;
-  hipStream_t aux = nullptr;      // look-ahead stream, kept off the last CUs (blocking)
-  hipStream_t aux_nb = nullptr;   // look-ahead stream for builds on the null stream
+  hipStream_t aux_nb = nullptr;   // the factorisation's look-ahead stream (non-blocking)
   // Buffers of released plans whose last uses may still run: freed into the
   // plan pool once all their events have completed (see free_plan_memory).
   struct PendingFree {
@@ -511,17 +510,16 @@ const char* pinv_last_error(void) { return g_last_error.c_str(); }
 // or server landed on different queues each time, and a server whose build
 // and apply streams ended up sharing one queue served half as fast.  Created
 // once, in a fixed order, the mapping stays put.
-//  * aux: the factorisation's look-ahead stream.  It runs the bulk of each
-//    trailing update beside the next diagonal block, panel and look-ahead
-//    tiles, kept off the last 32 CUs so the one-workgroup diagonal kernel and
-//    the short panel launches on the build stream always find free CUs.  A
-//    CU-masked stream is a blocking stream, which the null stream would
-//    serialise against, so builds issued on the null stream use aux_nb.
-//  * aux_nb: unmasked, non-blocking: look-ahead for null-stream builds, the
-//    serving loop's build stream, and frees with no allocating stream.
+//  * aux_nb: non-blocking: the factorisation's look-ahead stream (the bulk of
+//    each trailing update beside the next diagonal block and panel), the
+//    serving loop's build stream, and frees with no allocating stream.  (A
+//    stream kept off the last 32 CUs, leaving them to the one-workgroup
+//    diagonal kernel, gained nothing with rank-128 trailing updates: 262
+//    against 238 ms at N = 16384, where only every second diagonal block runs
+//    beside a trailing update.)
 //  * apply: the serving loop's apply stream.
 struct DeviceStreams {
-  hipStream_t aux = nullptr, aux_nb = nullptr, apply = nullptr;
+  hipStream_t aux_nb = nullptr, apply = nullptr;
 };
 
 static std::mutex g_streams_mu;
@@ -534,7 +532,6 @@ static void destroy_device_streams() {
   if (!g_streams) return;
   for (auto& kv : *g_streams) {
     (void)hipSetDevice(kv.first);
-    if (kv.second.aux != kv.second.aux_nb) (void)hipStreamDestroy(kv.second.aux);
     (void)hipStreamDestroy(kv.second.aux_nb);
     (void)hipStreamDestroy(kv.second.apply);
   }
@@ -556,17 +553,6 @@ static bool device_streams(int device, DeviceStreams* out) {
   DeviceStreams d;
   if (hipStreamCreateWithFlags(&d.aux_nb, hipStreamNonBlocking) != hipSuccess) return false;
   if (hipStreamCreateWithFlags(&d.apply, hipStreamNonBlocking) != hipSuccess) return false;
-  d.aux = d.aux_nb;
-  int cus = 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
-      cus >= 128) {
-    std::vector<uint32_t> mask((cus + 31) / 32, 0u);
-    for (int i = 0; i < cus - 32; ++i) mask[i / 32] |= 1u << (i % 32);
-    if (hipExtStreamCreateWithCUMask(&d.aux, (uint32_t)mask.size(), mask.data()) != hipSuccess) {
-      (void)hipGetLastError();
-      d.aux = d.aux_nb;
-    }
-  }
   streams[device] = d;
   *out = d;
   return true;
@@ -603,7 +589,6 @@ pinv_status pinv_context_create(int device, size_t budget, pinv_context** out) {
     pinv_context_destroy(c);
     return fail(PINV_ERR_DEVICE, "cannot create the library's streams");
   }
-  c->aux = ds.aux;
   c->aux_nb = ds.aux_nb;
   // Keep freed stream-ordered allocations (build workspaces, scratch) mapped
   // across synchronisations: the pool's default release threshold of 0 hands
@@ -971,6 +956,16 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
   }
   BCHK(hipMemsetAsync(L64, 0, 16 * Gd * Gd, s));
   if (!no_r) BCHK(workspace_alloc(&W, b3 ? 8 * M * sp_cols(N) : ws * N * M, c, s));
+  int64_t slab = 0;
+  if (b3 && !no_r && !p->right && form.route == PINV_ROUTE_CHOLESKY) {
+    // split-packed L^-1 and L^-H rows and the conj(E) slab, mapped before the
+    // first stage so no stage's interval includes growing the pool
+    const size_t Np = sp_cols(N);
+    slab = e_slab_rows(N, M);
+    BCHK(workspace_alloc(&LS, 8 * N * Np, c, s));
+    BCHK(workspace_alloc(&LHS, 8 * N * Np, c, s));
+    BCHK(workspace_alloc(&ES, 8 * (size_t)slab * Np, c, s));
+  }
   if (p->right) BCHK(workspace_alloc(&Z, ws * N * M, c, s));
   if (form.gram == PINV_GRAM_PSF) BCHK(workspace_alloc(&PW, psf_work_bytes(p->e64, nullptr), c, s));
 
@@ -1049,7 +1044,7 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
   } else {
   // 2. shift + blocked Cholesky with L^-1 (a4), FP64
   BCHK(launch_cholinv((double*)G, (double*)L64, (int)Gd, lam, p->info, s,
-                      s ? p->ctx->aux : p->ctx->aux_nb, form.nb));
+                      p->ctx->aux_nb, form.nb));
   if (!f64) BCHK(launch_to_f32((const double*)L64, (float*)p->Linv, Gd * Gd, s));
   BCHK(hipEventRecord(p->ev[2], s));
   // 3. W = L^-1 E^H, R = L^-H W (a5); a factor-only plan stops at L^-1.  With
@@ -1083,13 +1078,8 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
   } else if (b3) {
     // the factor split once into bf16 hi/lo planes, as rows of L^-1 and of
     // L^-H; the products write W^T and R split-packed
-    const size_t Np = sp_cols(N);
-    BCHK(workspace_alloc(&LS, 8 * N * Np, c, s));
-    BCHK(workspace_alloc(&LHS, 8 * N * Np, c, s));
     BCHK(launch_sp_pack<double>((const double*)L64, (int64_t)N, d.N, d.N, false, false, LS, s));
     BCHK(launch_sp_pack<double>((const double*)L64, (int64_t)N, d.N, d.N, true, true, LHS, s));
-    const int64_t slab = e_slab_rows(N, M);
-    BCHK(workspace_alloc(&ES, 8 * slab * Np, c, s));
     BCHK(launch_trmm_w_sp(p->e32, LS, W, ES, slab, s));
     BCHK(hipFreeAsync(ES, s));
     ES = nullptr;
