@@ -45,7 +45,7 @@ PEAK_FP32_MFMA = 157.3   # TFLOP/s, MI355X dense FP32 matrix
 PEAK_FP64_MFMA = 78.6
 PEAK_BF16_MFMA = 2500.0  # TFLOP/s, MI355X dense BF16 matrix (no sparsity)
 PEAK_HBM = 8.0e12        # B/s
-ROW_APPLY_MAX_F = 2      # FP32 plans stream R row by row (VALU) for at most this many frames,
+ROW_APPLY_MAX_F = 2      # FP32 and BF16X3 plans stream R row by row (VALU) for at most this many frames,
 STREAM_MAX_F = 32        # and into the matrix cores up to this many
 
 
@@ -768,16 +768,22 @@ def headline(args) -> dict:
     refine = 2 if refine is None else refine
     a0 = apply_ms(P, ctx, p32, d32, x32, stream)
     ar = apply_ms(P, ctx, p32, d32, x32, stream, refine=refine)
-    small_f = {}
-    for Fs in (1, 2, 3, 4, 8, 9, 16, 24, 32):
-        ds = d32[:Fs].contiguous()
-        xs = torch.empty((Fs, N), dtype=torch.complex64, device=dev)
-        ms = apply_ms(P, ctx, p32, ds, xs, stream, reps=5)
-        nbytes = 8.0 * (N * M + Fs * M + Fs * N)
-        small_f[str(Fs)] = {"ms": ms, "GB/s": nbytes / (ms * 1e-3) / 1e9,
+    def few_frames(plan):
+        """Applies of 1-32 frames: one pass over R (8NM bytes, complex64 or
+        split-packed), timed as fractions of the HBM peak."""
+        out = {}
+        for Fs in (1, 2, 3, 4, 8, 9, 16, 24, 32):
+            ds = d32[:Fs].contiguous()
+            xs = torch.empty((Fs, N), dtype=torch.complex64, device=dev)
+            ms = apply_ms(P, ctx, plan, ds, xs, stream, reps=5)
+            nbytes = 8.0 * (N * M + Fs * M + Fs * N)
+            out[str(Fs)] = {"ms": ms, "GB/s": nbytes / (ms * 1e-3) / 1e9,
                             "hbm_frac": nbytes / (ms * 1e-3) / PEAK_HBM,
                             "path": "rows" if Fs <= ROW_APPLY_MAX_F else
                             "stream" if Fs <= STREAM_MAX_F else "tiles"}
+        return out
+
+    small_f = few_frames(p32)
     log(f"small-F applies: {small_f}")
     P.pinv_plan_release(p32)
     P.pinv_context_trim(ctx)
@@ -857,12 +863,14 @@ def headline(args) -> dict:
         b3_err[str(r)] = rel_err(x32, x_ref)[0]
     b3_apply = apply_ms(P, ctx, b3, d32, x32, stream)
     b3_refined = apply_ms(P, ctx, b3, d32, x32, stream, refine=1)
+    b3_small = few_frames(b3)
     P.pinv_plan_release(b3)
     P.pinv_context_trim(ctx)
     exb = build_flops_executed(enc)
     bf16x3 = {"build_ms": float(sum(stb)), "stage_ms": stage_dict(stb),
               "apply_frames_per_s": F / (b3_apply * 1e-3),
               "apply_refined_1_frames_per_s": F / (b3_refined * 1e-3),
+              "apply_small_frames": b3_small,
               "rel_err_by_refine_steps": b3_err,
               "bf16_mfma": bf16x3_mfma(exb, stage_dict(stb), b3_apply, F, enc),
               "speedup_vs_fp32": {"build": build_ms / float(sum(stb)),
