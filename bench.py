@@ -183,7 +183,15 @@ PMC_KERNELS = {"trmm_w": "k_trmm_w<pinv::TileCfg<float, 128, 64, 8, true, 2>,",
                "apply": "k_apply<pinv::TileCfg<float, 128, 64, 8, true, 2>, false>",
                "trmm_w_bf16x3": "k_trmm_w_sp(",
                "trmm_r_bf16x3": "k_trmm_r_sp(",
-               "apply_bf16x3": "k_apply<pinv::TileCfgB3<128, 64, 2, 2, 1>, false>"}
+               "apply_bf16x3": "k_apply<pinv::TileCfgB3<128, 64, 2, 2, 1>, false>",
+               # few-frame applies, one launch each in the counter run (FP32 3M
+               # plan: rows at 1 frame, streamed at 16 and 32; BF16X3: 16)
+               "apply_rows_f1": "k_apply_rows<float, 1, 1, 2>",
+               "apply_stream_f16": "k_apply_stream<1, 2, 2, 1>",
+               "apply_stream_f32": "k_apply_stream<2, 2, 2, 1>",
+               "apply_stream_bf16x3_f16": "k_apply_stream<1, 2, 2, 2>"}
+FEW_FRAMES = {"apply_rows_f1": 1, "apply_stream_f16": 16, "apply_stream_f32": 32,
+              "apply_stream_bf16x3_f16": 16}
 
 
 def algorithmic_bytes(N: int, M: int, F: int) -> dict:
@@ -195,6 +203,8 @@ def algorithmic_bytes(N: int, M: int, F: int) -> dict:
            "apply": 8.0 * F * M + 8.0 * N * M + 8.0 * F * N}
     for k in ("trmm_w", "trmm_r", "apply"):
         out[k + "_bf16x3"] = out[k]
+    for k, f in FEW_FRAMES.items():
+        out[k] = 8.0 * f * M + 8.0 * N * M + 8.0 * f * N
     return out
 
 
@@ -213,7 +223,7 @@ def pmc_mfma_summary(d) -> dict:
     agg = defaultdict(lambda: defaultdict(float))
     disp = defaultdict(set)
     names = dict(PMC_KERNELS, gram_psf="k_psf(", chol_trailing="k_chol_trailing", chol_panel="k_chol_panel",
-                 gen_e_bf16x3="k_gen_e_sp<",
+                 gen_e_bf16x3="k_gen_e_sp<", gram_shared="k_gram_shared<", gram_full="k_gram<",
                  chol_diag="k_chol_diag", adjoint_fp64="k_adjoint<", resid="k_resid", tri_frames="k_tri_frames",
                  trmm_w_fp64_formed="k_trmm_w<pinv::TileCfg<double",
                  trmm_r_fp64_formed="k_trmm_r<pinv::TileCfg<double, 64, 64, 8, false, 2>, float>",
@@ -720,15 +730,28 @@ def pmc_run(args) -> None:
     g = torch.Generator(device=dev).manual_seed(5)
     d = torch.randn((args.frames, enc.M), dtype=torch.complex64, device=dev, generator=g)
     x = torch.empty((args.frames, enc.N), dtype=torch.complex64, device=dev)
+    few = {"fp32": (1, 16, 32), "bf16x3": (16,), "fp32_r_fp64": ()}
     for name, prec, flags, refine in (("fp32", P.FP32, 0, 1), ("bf16x3", P.BF16X3, 0, 0),
                                       ("fp32_r_fp64", P.FP32, P.FLAG_R_FP64, 0)):
         p = P.pinv_build(ctx, enc, w.rel_lambda, P.LAMBDA_REL_MEAN_DIAG, prec, flags | P.FLAG_UNCACHED)
         P.pinv_apply(ctx, p, d, x, refine_steps=refine)
+        for f in few[name]:   # one pass over R each
+            P.pinv_apply(ctx, p, d[:f].contiguous(), x[:f])
         torch.cuda.synchronize()
         P.pinv_plan_wait(p)
         log(f"pmc run {name}: stage ms {P.pinv_plan_info_get(p)['stage_ms']}")
         P.pinv_plan_release(p)
         P.pinv_context_trim(ctx)
+    # the Gram on MFMA: the 5-species, B0 workload (32x32, 8 coils, M = 49152),
+    # whose default Gram is the shared-trajectory product (FP64 3M), and the
+    # all-rows FP32 Gram
+    ws = synth.species5_32x32_c8(F=1)
+    for gram in (P.GRAM_AUTO, P.GRAM_FULL):
+        p = P.pinv_build(ctx, ws.enc, ws.rel_lambda, P.LAMBDA_REL_MEAN_DIAG, P.FP32,
+                         P.FLAG_UNCACHED | P.FLAG_NO_R, gram=gram)
+        P.pinv_plan_wait(p)
+        log(f"pmc run gram {gram}: stage ms {P.pinv_plan_info_get(p)['stage_ms']}")
+        P.pinv_plan_release(p)
     P.pinv_context_destroy(ctx)
     print(json.dumps({"pmc_run": "done"}), flush=True)
 
