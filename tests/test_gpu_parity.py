@@ -567,6 +567,48 @@ def test_few_frame_slices_match_oracle(P, ctx, prec, name, cprod):
         P.pinv_plan_release(plan)
 
 
+@pytest.mark.parametrize("prec,cprod", [("fp64", "auto"), ("fp32", "3m"), ("fp32", "4m"),
+                                        ("bf16x3", "auto")])
+@pytest.mark.parametrize("shape", ["16x18", "15x17"])
+def test_few_frame_tiny_shapes_match_oracle(P, ctx, prec, cprod, shape):
+    """Applies (Eq. 3) at tiny shapes, where the few-frame kernels run one
+    workgroup with waves past N and fewer than 32 columns: N = 16, M = 18 (the
+    streamed kernel's partial chunk alone) and N = 15, M = 17 (odd M: 8-byte
+    loads; split-packed rows padded to 32).  Every path: rows, streamed
+    (16- and 32-frame blocks) and tiles (33 frames).  Against the oracle's R
+    applied in FP64 at the R path's tolerances."""
+    nx, ny, C, K = {"16x18": (4, 4, 2, 9), "15x17": (5, 3, 1, 17)}[shape]
+    w = synth.small_case(seed=107, nx=nx, ny=ny, C=C, K=K, F=1)
+    enc = w.enc
+    N, M = enc.N, enc.M
+    assert M >= N and M < 32
+    ob = oracle.Build(enc, rel=1e-3)
+    R_or = ob.recon_matrix()
+    ev = np.linalg.eigvalsh(ob.G + ob.lam * np.eye(N))
+    kappa = ev[-1] / ev[0]
+    rng = np.random.default_rng(43)
+    d = rng.standard_normal((33, M)) + 1j * rng.standard_normal((33, M))
+    pr, cdt = {"fp64": (P.FP64, np.complex128), "fp32": (P.FP32, np.complex64),
+               "bf16x3": (P.BF16X3, np.complex64)}[prec]
+    d = d.astype(cdt).astype(np.complex128)
+    form = {"3m": P.CPROD_3M, "4m": P.CPROD_4M, "auto": P.CPROD_AUTO}[cprod]
+    plan = build(P, ctx, enc, pr, flags=P.FLAG_UNCACHED, cprod=form)
+    try:
+        for F in (1, 2, 3, 5, 16, 17, 32, 33):
+            dd = to_dev(d[:F], cdt)
+            x = torch.full((F, N), float("nan"), dtype=dd.dtype, device="cuda")
+            torch.cuda.synchronize()
+            P.pinv_apply(ctx, plan, dd, x)
+            torch.cuda.synchronize()
+            xg = x.cpu().numpy().astype(np.complex128)
+            err = frame_rel(xg, d[:F] @ R_or.T).max()
+            tol = {"fp64": 1e-9, "fp32": kappa * 1e-6, "bf16x3": kappa * 1e-4}[prec]
+            print(f"{prec} {cprod} {shape} F={F}: {err:.2e} (kappa {kappa:.2g})")
+            assert err < tol, (F, err)
+    finally:
+        P.pinv_plan_release(plan)
+
+
 def test_cache_hit_and_release(P, ctx):
     o = oracle_case("species_b0")
     a = build(P, ctx, o["w"].enc, P.FP32)
