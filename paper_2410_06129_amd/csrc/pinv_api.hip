@@ -23,9 +23,20 @@ using namespace pinv;
 
 static thread_local std::string g_last_error;
 
+// Records the message and clears the thread's pending HIP error, so that the
+// error of a failed call is not read again by the next call's launch checks.
 static pinv_status fail(pinv_status s, const std::string& msg) {
   g_last_error = msg;
+  (void)hipGetLastError();
   return s;
+}
+
+// Entry of a call that launches work: the device made current, and a HIP
+// error left pending by earlier calls on this thread (the caller's or a
+// failed one's) cleared, so that launch checks report this call's own.
+static hipError_t enter_device(int device) {
+  (void)hipGetLastError();
+  return hipSetDevice(device);
 }
 
 #define HIPCHK(expr)                                                                 \
@@ -578,7 +589,7 @@ pinv_status pinv_context_create(int device, size_t budget, pinv_context** out) {
   int n = 0;
   HIPCHK(hipGetDeviceCount(&n));
   if (device < 0 || device >= n) return fail(PINV_ERR_INVALID, "no such device");
-  HIPCHK(hipSetDevice(device));
+  HIPCHK(enter_device(device));
   size_t fr = 0, tot = 0;
   HIPCHK(hipMemGetInfo(&fr, &tot));
   pinv_context* c = new pinv_context();
@@ -793,6 +804,26 @@ static void trim_pool(pinv_context* c, bool force, bool plans) {
 // serving loop calls this after each batch).
 extern "C++" void pinv_context_trim_scratch(pinv_context* c) { trim_pool(c, false, false); }
 
+// Scratch reclaim for calls that allocate from the default pool: the stream's
+// own frees complete, then every pool of the context hands its unused memory
+// (build workspaces and released plans included) back to the device.
+static void reclaim_pools(void* arg, hipStream_t s) {
+  (void)hipStreamSynchronize(s);
+  trim_pool((pinv_context*)arg, true, true);
+}
+
+// A stream-ordered allocation from the default pool for a call's own
+// temporaries, tried once more after reclaim_pools when memory is short.
+static hipError_t pool_alloc(pinv_context* c, void** ptr, size_t bytes, hipStream_t s) {
+  hipError_t e = hipMallocAsync(ptr, bytes, s);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    reclaim_pools(c, s);
+    e = hipMallocAsync(ptr, bytes, s);
+  }
+  return e;
+}
+
 // A build workspace, stream-ordered on s, from the context's build pool.
 static hipError_t workspace_alloc(void** ptr, size_t bytes, pinv_context* c, hipStream_t s) {
   auto once = [&]() {
@@ -839,7 +870,7 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
   pinv_status st = check_build(e, o, &d, &lam, &key, &form);
   if (st != PINV_OK) return st;
   hipStream_t s = (hipStream_t)stream;
-  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(enter_device(c->device));
 
   const bool uncached = (o->flags & PINV_FLAG_UNCACHED) != 0;
   std::lock_guard<std::mutex> g(c->mu);
@@ -1128,7 +1159,7 @@ pinv_status pinv_build(pinv_context* c, const pinv_encoding* e, const pinv_build
 
 extern "C" pinv_status pinv_context_trim(pinv_context* c) {
   if (!c) return fail(PINV_ERR_INVALID, "context is NULL");
-  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(enter_device(c->device));
   trim_pool(c, true, true);
   return PINV_OK;
 }
@@ -1136,7 +1167,7 @@ extern "C" pinv_status pinv_context_trim(pinv_context* c) {
 pinv_status pinv_plan_wait(pinv_plan* p) {
   if (!p) return fail(PINV_ERR_INVALID, "plan is NULL");
   if (!p->waited) {
-    HIPCHK(hipSetDevice(p->ctx->device));
+    HIPCHK(enter_device(p->ctx->device));
     HIPCHK(hipEventSynchronize(p->ev[4]));
     trim_pool(p->ctx, false, false);
     HIPCHK(hipMemcpy(&p->info_host, p->info, sizeof(int), hipMemcpyDeviceToHost));
@@ -1457,8 +1488,10 @@ pinv_status pinv_apply_grouped(pinv_context* c, int32_t n, const pinv_apply_item
   if (!c || (n > 0 && !items) || n < 0) return fail(PINV_ERR_INVALID, "bad arguments");
   if (refine_steps < 0 || refine_steps > 4) return fail(PINV_ERR_INVALID, "refine_steps in 0..4");
   hipStream_t s = (hipStream_t)stream;
-  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(enter_device(c->device));
   Scratch sc;   // stream-ordered allocations from the default pool
+  sc.reclaim = reclaim_pools;
+  sc.reclaim_arg = c;
   const pinv_status st = apply_items(c, n, items, refine_steps, sc, s);
   if (st != PINV_OK) return st;
   for (int j = 0; j < n; ++j)
@@ -1477,7 +1510,7 @@ pinv_status pinv_forward(pinv_context* c, const pinv_plan* pc, const void* image
   if (!c || !pc || F < 0 || (F > 0 && (!image || !data))) return fail(PINV_ERR_INVALID, "bad arguments");
   pinv_plan* p = (pinv_plan*)pc;
   hipStream_t s = (hipStream_t)stream;
-  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(enter_device(c->device));
   if (F == 0) return PINV_OK;
   HIPCHK(hipStreamWaitEvent(s, p->ev[0], 0));   // the tables are on the device
   if (p->prec == PINV_FP64) {
@@ -1534,7 +1567,7 @@ static hipError_t dense_r(const pinv_plan* p, hipStream_t s, const void** R, voi
   *tmp = nullptr;
   *R = p->R;
   if (p->prec != PINV_BF16X3) return hipSuccess;
-  hipError_t e = hipMallocAsync(tmp, (size_t)8 * p->N * p->M, s);
+  hipError_t e = pool_alloc(p->ctx, tmp, (size_t)8 * p->N * p->M, s);
   if (e == hipSuccess) e = launch_sp_unpack(p->R, p->N, p->M, (float*)*tmp, s);
   *R = *tmp;
   return e;
@@ -1555,7 +1588,7 @@ pinv_status pinv_srf(pinv_context* c, const pinv_plan* pc, int32_t mode, void* o
   if (st != PINV_OK) return st;
   const pinv_plan* p = pc;
   hipStream_t s = (hipStream_t)stream;
-  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(enter_device(c->device));
   HIPCHK(hipStreamWaitEvent(s, p->ev[4], 0));
   const void* R = nullptr;
   void* tmp = nullptr;
@@ -1591,7 +1624,7 @@ pinv_status noise_impl(const pinv_plan* p, const T* R, const T* Lc, int32_t mode
     return PINV_OK;
   }
   void* Rt = nullptr;
-  HIPCHK(hipMallocAsync(&Rt, (size_t)p->N * p->M * 2 * sizeof(T), s));
+  HIPCHK(pool_alloc(p->ctx, &Rt, (size_t)p->N * p->M * 2 * sizeof(T), s));
   hipError_t e = launch_noise_mix<T>(R, p->N, p->K, p->C, Lc, (T*)Rt, s);
   if (e == hipSuccess) e = launch_noise_full<T>((const T*)Rt, p->N, p->M, out, s);
   const hipError_t f = hipFreeAsync(Rt, s);
@@ -1608,7 +1641,7 @@ pinv_status pinv_noise(pinv_context* c, const pinv_plan* pc, const double* coil_
   if (st != PINV_OK) return st;
   const pinv_plan* p = pc;
   hipStream_t s = (hipStream_t)stream;
-  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(enter_device(c->device));
   HIPCHK(hipStreamWaitEvent(s, p->ev[4], 0));
   const bool f64 = p->prec == PINV_FP64;
   const size_t rs = f64 ? 8 : 4;
@@ -1675,7 +1708,7 @@ pinv_status pinv_spectrum(pinv_context* c, const pinv_plan* p, double* out, void
   if (p->route != PINV_ROUTE_EIGEN || !p->spec)
     return fail(PINV_ERR_INVALID, "the plan was not built with PINV_ROUTE_EIGEN");
   hipStream_t s = (hipStream_t)stream;
-  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(enter_device(c->device));
   HIPCHK(hipStreamWaitEvent(s, p->ev[4], 0));
   HIPCHK(hipMemcpyAsync(out, p->spec, sizeof(double) * (size_t)p->G, hipMemcpyDeviceToDevice, s));
   HIPCHK(note_use(p, s));
@@ -1711,7 +1744,7 @@ pinv_status pinv_plan_copy_buffer(const pinv_plan* p, int32_t which, void* dst, 
   if (!src) return fail(PINV_ERR_INVALID, "buffer not held by this plan");
   if (bytes != want) return fail(PINV_ERR_INVALID, "size mismatch: want " + std::to_string(want));
   hipStream_t s = (hipStream_t)stream;
-  HIPCHK(hipSetDevice(p->ctx->device));
+  HIPCHK(enter_device(p->ctx->device));
   HIPCHK(hipStreamWaitEvent(s, p->ev[4], 0));
   if (which == 0 && p->prec == PINV_BF16X3)   // R is kept split-packed
     HIPCHK(launch_sp_unpack(p->R, p->N, p->M, (float*)dst, s));
@@ -1741,7 +1774,7 @@ pinv_status pinv_plan_release(pinv_plan* p) {
 
 pinv_status pinv_cache_trim(pinv_context* c, size_t* freed) {
   if (!c) return fail(PINV_ERR_INVALID, "context is NULL");
-  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(enter_device(c->device));
   std::lock_guard<std::mutex> g(c->mu);
   const size_t before = c->used;
   make_room(c, (size_t)-1 / 2);

@@ -39,15 +39,27 @@ struct ApplyBatch {     // passed by value as a kernel argument
 // 256-aligned block, put() of the most recent block pops it (the stream runs
 // the work in order, so a popped block is free for the next request), and a
 // request beyond the region fails with hipErrorOutOfMemory.  `peak` records
-// the most the stack ever held.
+// the most the stack ever held.  `reclaim`, when set, runs once after a
+// pool allocation fails for lack of memory (it hands memory that other pools
+// hold but do not use back to the device), and the allocation is tried again.
 struct Scratch {
   char* base = nullptr;
   size_t cap = 0, top = 0, peak = 0;
   struct Block { void* p; size_t start; };
   Block stack[16];
   int depth = 0;
+  void (*reclaim)(void* arg, hipStream_t s) = nullptr;
+  void* reclaim_arg = nullptr;
   hipError_t get(void** p, size_t bytes, hipStream_t s) {
-    if (!base) return hipMallocAsync(p, bytes, s);
+    if (!base) {
+      hipError_t e = hipMallocAsync(p, bytes, s);
+      if (e == hipErrorOutOfMemory && reclaim) {
+        (void)hipGetLastError();
+        reclaim(reclaim_arg, s);
+        e = hipMallocAsync(p, bytes, s);
+      }
+      return e;
+    }
     const size_t start = (top + 255) & ~size_t(255);
     if (depth >= 16 || start + bytes > cap) return hipErrorOutOfMemory;
     *p = base + start;

@@ -110,3 +110,48 @@ def test_budget_forces_eviction(P):
     assert len(done) == 6 and all(c["status"] == P.OK for c in done)
     assert st["evictions"] >= 1 and st["peak_used"] <= budget
     assert st["invariant_violations"] == 0
+
+
+def test_pending_hip_error_fails_no_later_call(P):
+    """A failed HIP call whose error is still pending on the calling thread
+    (here an allocation larger than any device) does not fail the next build
+    or apply made on that thread: the serving worker runs builds and applies
+    on one thread, so an apply that ran out of memory must not fail the next
+    build's launch checks.  The results equal those of the same calls made
+    with no error pending, and the build matches the oracle."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so.7")   # the runtime already loaded
+    hip.hipMalloc.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t]
+
+    def leave_error_pending():
+        ptr = ctypes.c_void_p()
+        assert hip.hipMalloc(ctypes.byref(ptr), 1 << 60) != 0
+        assert hip.hipPeekAtLastError() != 0   # the condition under test holds
+
+    enc = encodings()[1]
+    ctx = P.pinv_context_create(0)
+    plans = []
+    try:
+        g = torch.Generator(device="cuda").manual_seed(5)
+        d = torch.randn((6, enc.M), dtype=torch.complex64, device="cuda", generator=g)
+        xs = []
+        for pending in (True, False):
+            if pending:
+                leave_error_pending()
+            plans.append(P.pinv_build(ctx, enc, 1e-3, P.LAMBDA_REL_MEAN_DIAG, P.FP32,
+                                      P.FLAG_UNCACHED))
+            P.pinv_plan_wait(plans[-1])
+            x = torch.zeros((6, enc.N), dtype=torch.complex64, device="cuda")
+            if pending:
+                leave_error_pending()
+            P.pinv_apply(ctx, plans[-1], d, x, refine_steps=1)
+            torch.cuda.synchronize()
+            xs.append(x)
+        assert torch.equal(xs[0], xs[1])
+        ref = oracle.Build(enc, rel=1e-3).reconstruct(d.cpu().numpy().astype(np.complex128))
+        assert oracle.relative_error(xs[0].cpu().numpy().astype(np.complex128), ref).max() < 1e-5
+    finally:
+        hip.hipGetLastError()
+        for q in plans:
+            P.pinv_plan_release(q)
+        P.pinv_context_destroy(ctx)
