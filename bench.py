@@ -474,6 +474,52 @@ def config2_figures(P, ctx, stream, dev, tol) -> dict:
 # other modes
 # ----------------------------------------------------------------------------
 
+class RequestArena:
+    """Request buffers of the serving replay carved first-fit out of one device
+    buffer, so that they never take more than its bytes whatever the mix of
+    sizes (freed buffers in torch's cache would otherwise stay reserved beyond
+    the data cap, beside the plans).  Ranges are 256-byte aligned."""
+
+    def __init__(self, nbytes: int):
+        import torch
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self.free = [(0, nbytes)]   # (offset, size), sorted by offset, disjoint
+
+    @staticmethod
+    def _round(n: int) -> int:
+        return (n + 255) & ~255
+
+    def alloc(self, n: int):
+        n = self._round(n)
+        for i, (o, sz) in enumerate(self.free):
+            if sz >= n:
+                if sz == n:
+                    del self.free[i]
+                else:
+                    self.free[i] = (o + n, sz - n)
+                return o
+        return None
+
+    def release(self, o: int, n: int) -> None:
+        n = self._round(n)
+        i = 0
+        while i < len(self.free) and self.free[i][0] < o:
+            i += 1
+        self.free.insert(i, (o, n))
+        if i + 1 < len(self.free) and o + n == self.free[i + 1][0]:   # merge the next range
+            self.free[i] = (o, n + self.free[i + 1][1])
+            del self.free[i + 1]
+        if i > 0 and self.free[i - 1][0] + self.free[i - 1][1] == o:   # and the previous one
+            self.free[i - 1] = (self.free[i - 1][0], self.free[i - 1][1] + self.free[i][1])
+            del self.free[i]
+
+    def view(self, o: int, shape, dtype):
+        import torch
+        es = torch.empty((), dtype=dtype).element_size()
+        n = es * int(np.prod(shape))
+        return self.buf[o:o + n].view(dtype).view(shape)
+
+
 def serving(args) -> dict:
     """Replay the seeded serving trace (Poisson arrivals; sizes 32^2..128^2 with
     probabilities .4/.3/.2/.1; 1, 8 or 16 coils; spiral of 2N samples per coil;
@@ -482,7 +528,6 @@ def serving(args) -> dict:
     arrival (queueing included).  A request that fails (its plan exceeds the
     budget) counts as never served: p50/p99 are over all requests, failures
     at infinite latency, and over the requests served by every variant."""
-    import threading
     import torch
     from paper_2410_06129_amd import pinv as P
     from paper_2410_06129_amd import synth
@@ -503,15 +548,15 @@ def serving(args) -> dict:
     for label in args.serve_variants.split(","):
         prec, cdt, refine, flags = variants[label]
         ctx = P.pinv_context_create(0)
+        torch.cuda.reset_peak_memory_stats()
         free, total = torch.cuda.mem_get_info()
         srv = P.pinv_server_create(ctx, 0, hbm_budget_bytes=int(free * args.plan_frac),
                                    max_group=16, max_inflight=2, max_builds=1)
         data_cap = int(free * (0.85 - args.plan_frac))
         log(f"[{label}] device free {free / 2**30:.1f} of {total / 2**30:.1f} GiB; plan budget "
             f"{free * args.plan_frac / 2**30:.1f} GiB, data cap {data_cap / 2**30:.1f} GiB")
+        arena = RequestArena(data_cap)
         live = {}
-        lock = threading.Lock()
-        in_bytes = [0]
         sched = {}
         done = []
         t0 = time.perf_counter()
@@ -519,9 +564,8 @@ def serving(args) -> dict:
         def reap():
             for c in P.pinv_server_poll(srv, 1024):
                 done.append((c, time.perf_counter() - t0))
-                with lock:
-                    d = live.pop(c["tag"])
-                    in_bytes[0] -= d[2]
+                off, nb = live.pop(c["tag"])
+                arena.release(off, nb)
 
         flops_offered = 0.0
         for r in trace:
@@ -530,20 +574,23 @@ def serving(args) -> dict:
             while time.perf_counter() - t0 < r.arrival_s:
                 reap()
                 time.sleep(0.001)
-            nbytes = (M + N) * F * (8 if prec != P.FP64 else 16)
+            es = 8 if prec != P.FP64 else 16
+            dbytes = RequestArena._round(M * F * es)
+            nbytes = dbytes + N * F * es
             while True:        # back-pressure on request buffers (counts as queueing)
                 reap()
-                with lock:
-                    if in_bytes[0] + nbytes <= data_cap or not live:
-                        break
+                off = arena.alloc(nbytes)
+                if off is not None:
+                    break
+                if not live:
+                    raise RuntimeError(f"request {r.rid} ({nbytes} B) exceeds the data arena")
                 time.sleep(0.002)
             g = torch.Generator(device="cuda").manual_seed(r.rid)
-            d = torch.randn((F, M), dtype=cdt, device="cuda", generator=g)
-            x = torch.empty((F, N), dtype=cdt, device="cuda")
+            d = arena.view(off, (F, M), cdt)
+            x = arena.view(off + dbytes, (F, N), cdt)
+            torch.randn((F, M), dtype=cdt, device="cuda", generator=g, out=d)
             torch.cuda.current_stream().synchronize()
-            with lock:
-                live[r.rid] = (d, x, nbytes)
-                in_bytes[0] += nbytes
+            live[r.rid] = (off, nbytes)
             sched[r.rid] = r.arrival_s
             P.pinv_server_submit(srv, enc, d, x, 1e-3, P.LAMBDA_REL_MEAN_DIAG, prec, flags=flags,
                                  refine_steps=refine, tag=r.rid)
@@ -555,8 +602,11 @@ def serving(args) -> dict:
             time.sleep(0.002)
         t_end = time.perf_counter() - t0
         st = P.pinv_server_stats_get(srv)
+        torch_peak = torch.cuda.max_memory_reserved()   # request buffers held by torch's cache
         P.pinv_server_destroy(srv)
         live.clear()
+        d = x = None   # the last request's views hold the arena's buffer
+        del arena
         P.pinv_context_destroy(ctx)
         torch.cuda.empty_cache()
         lat = {c["tag"]: (tw - sched[c["tag"]] if c["status"] == P.OK else float("inf"))
@@ -585,6 +635,7 @@ def serving(args) -> dict:
                       "served_tflops_standard": flops_offered / t_end / 1e12,
                       "builds": st["builds"], "hits": st["hits"], "evictions": st["evictions"],
                       "batches": st["batches"], "peak_plan_bytes": st["peak_used"],
+                      "torch_peak_reserved_bytes": torch_peak,
                       "invariant_violations": st["invariant_violations"]}
         log(f"[{label}] {res[label]}")
     common = set.intersection(*[{t for t, v in l.items() if np.isfinite(v)} for l in lat_by.values()])
