@@ -54,6 +54,7 @@ extern "C" pinv_status pinv_apply_noalloc(pinv_context* c, const pinv_plan* p, c
     return pinv_fail(PINV_ERR_INVALID, "refine_steps in 0..4");
   if (F < 0 || F > (1 << 24)) return pinv_fail(PINV_ERR_INVALID, "F out of range");
   const int device = pinv_context_device(c);
+  (void)hipGetLastError();   // an error left pending by earlier calls is not this call's
   const hipError_t de = hipSetDevice(device);
   if (de != hipSuccess) return pinv_fail(PINV_ERR_DEVICE, hipGetErrorString(de));
   const size_t need = item_scratch_bytes(p, (int)F, refine_steps);

@@ -118,7 +118,8 @@ def test_pending_hip_error_fails_no_later_call(P):
     or apply made on that thread: the serving worker runs builds and applies
     on one thread, so an apply that ran out of memory must not fail the next
     build's launch checks.  The results equal those of the same calls made
-    with no error pending, and the build matches the oracle."""
+    with no error pending (the no-allocation apply's included), and the build
+    matches the oracle."""
     import ctypes
     hip = ctypes.CDLL("libamdhip64.so.7")   # the runtime already loaded
     hip.hipMalloc.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t]
@@ -148,6 +149,12 @@ def test_pending_hip_error_fails_no_later_call(P):
             torch.cuda.synchronize()
             xs.append(x)
         assert torch.equal(xs[0], xs[1])
+        # and the no-allocation entry point, which equals pinv_apply bitwise
+        y = torch.zeros_like(xs[0])
+        leave_error_pending()
+        P.pinv_apply_noalloc(ctx, plans[-1], d, y, refine_steps=1)
+        torch.cuda.synchronize()
+        assert torch.equal(y, xs[1])
         ref = oracle.Build(enc, rel=1e-3).reconstruct(d.cpu().numpy().astype(np.complex128))
         assert oracle.relative_error(xs[0].cpu().numpy().astype(np.complex128), ref).max() < 1e-5
     finally:
