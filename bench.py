@@ -524,8 +524,9 @@ def serving(args) -> dict:
     """Replay the seeded serving trace (Poisson arrivals; sizes 32^2..128^2 with
     probabilities .4/.3/.2/.1; 1, 8 or 16 coils; spiral of 2N samples per coil;
     70% of requests reuse an earlier encoding; frames uniform in [50, 2000])
-    through the server, once per variant.  Latency = completion - scheduled
-    arrival (queueing included).  A request that fails (its plan exceeds the
+    through the server, once per variant.  Request buffers (data and image)
+    come first-fit from one device arena of the data cap; a request waits for
+    room.  Latency = completion - scheduled arrival (queueing included).  A request that fails (its plan exceeds the
     budget) counts as never served: p50/p99 are over all requests, failures
     at infinite latency, and over the requests served by every variant."""
     import torch
