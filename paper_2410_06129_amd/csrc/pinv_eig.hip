@@ -24,15 +24,14 @@ __device__ __forceinline__ cx<double> conjc(cx<double> a) { return {a.re, -a.im}
 
 // Layout of the eigensolver's small workspace (bytes from its start).
 struct EigWork {
-  size_t sums, rank, part, partner, us, up, order, total;
+  size_t sums, rank, part, us, up, order, total;
   EigWork(int N) {
     const size_t np = N + (N & 1);
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
     sums = 0;
     rank = 256;
     part = 1024;
-    partner = al(part + 2 * 512 * sizeof(double));
-    us = al(partner + np * sizeof(int));
+    us = al(part + 2 * 512 * sizeof(double));
     up = al(us + np * 2 * sizeof(double));
     order = al(up + np * 2 * sizeof(double));
     total = al(order + (size_t)N * sizeof(int));
@@ -44,11 +43,12 @@ __device__ __forceinline__ int circle_player(int pos, int step, int np) {
   return pos == 0 ? 0 : 1 + (pos - 1 + step) % (np - 1);
 }
 
-// Rotations of one step: for every index i its partner and the entries
-// U[i][i] (us) and U[partner][i] (up) of the step's unitary U.
+// Rotations of one step: for every index i the entries U[i][i] (us) and
+// U[partner][i] (up) of the step's unitary U, the partner being the index
+// paired with i in the step's circle order.
 __global__ __launch_bounds__(256) void k_jac_rot(const double* __restrict__ A, int N, int np,
-                                                 int step, int* __restrict__ partner,
-                                                 double* __restrict__ us, double* __restrict__ up) {
+                                                 int step, double* __restrict__ us,
+                                                 double* __restrict__ up) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= np / 2) return;
   const int p = circle_player(k, step, np), q = circle_player(np - 1 - k, step, np);
@@ -57,7 +57,6 @@ __global__ __launch_bounds__(256) void k_jac_rot(const double* __restrict__ A, i
   if (p >= N || q >= N) {   // paired with the padding index of an odd N
     const int r = p < N ? p : q;
     if (r < N) {
-      partner[r] = r;
       Us[r] = cx<double>{1.0, 0.0};
       Up[r] = cx<double>{0.0, 0.0};
     }
@@ -67,8 +66,6 @@ __global__ __launch_bounds__(256) void k_jac_rot(const double* __restrict__ A, i
   const double app = a[(size_t)p * N + p].re, aqq = a[(size_t)q * N + q].re;
   const cx<double> b = a[(size_t)p * N + q];
   const double ab = hypot(b.re, b.im);
-  partner[p] = q;
-  partner[q] = p;
   if (ab == 0.0) {
     Us[p] = Us[q] = cx<double>{1.0, 0.0};
     Up[p] = Up[q] = cx<double>{0.0, 0.0};
@@ -89,33 +86,66 @@ __global__ __launch_bounds__(256) void k_jac_rot(const double* __restrict__ A, i
 }
 
 // A2 = U^H A U (blockIdx.z = 0) and V2 = V U (blockIdx.z = 1) for the step's
-// block-diagonal U:  with pi = partner(i), u_i = U[i][i], v_i = U[pi][i],
-//   A2[i][j] = conj(u_i) (A[i][j] u_j + A[i][pj] v_j) + conj(v_i) (A[pi][j] u_j + A[pi][pj] v_j)
-//   V2[i][j] = V[i][j] u_j + V[i][pj] v_j
+// block-diagonal U.  A thread takes one pair (p', q') of the step's columns
+// and, for A, one pair (p, q) of its rows: it reads the four entries
+// A[p|q][p'|q'] once and writes their rotated values; for V it takes one row
+// and the column pair.  With u_x = U[x][x] and v_x = U[partner x][x]:
+//   (A U)[i][p'] = A[i][p'] u_p' + A[i][q'] v_p',  (A U)[i][q'] = A[i][q'] u_q' + A[i][p'] v_q'
+//   A2[p][j] = conj(u_p) (A U)[p][j] + conj(v_p) (A U)[q][j]   (and p, q swapped)
+// An index paired with the padding of an odd N keeps u = 1, v = 0 and its
+// partner's entries count as zero.  Consecutive threads take consecutive
+// column pairs, whose p' run up and q' run down the row: both coalesce.
+// (Forming the rotations here instead of in k_jac_rot, each thread from the
+// pair entries it needs, was slower: 10.5 against 6.1 s of Jacobi at
+// N = 2304, the FP64 divides and square roots and the scattered diagonal
+// reads outweighing the saved launch.)
 __global__ __launch_bounds__(256) void k_jac_apply(const double* __restrict__ A, double* __restrict__ A2,
                                                    const double* __restrict__ V, double* __restrict__ V2,
-                                                   int N, const int* __restrict__ partner,
+                                                   int N, int np, int step,
                                                    const double* __restrict__ us,
                                                    const double* __restrict__ up) {
-  const int j = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
-  if (i >= N || j >= N) return;
+  const int l = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int r = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (l >= np / 2) return;
   const cx<double>* Us = reinterpret_cast<const cx<double>*>(us);
   const cx<double>* Up = reinterpret_cast<const cx<double>*>(up);
-  const int pj = partner[j];
-  const cx<double> uj = Us[j], vj = Up[j];
+  const cx<double> zero{0.0, 0.0};
+  const int jp = circle_player(l, step, np), jq = circle_player(np - 1 - l, step, np);
+  const bool hjp = jp < N, hjq = jq < N;
+  const cx<double> ujp = hjp ? Us[jp] : cx<double>{1.0, 0.0}, vjp = hjp ? Up[jp] : zero;
+  const cx<double> ujq = hjq ? Us[jq] : cx<double>{1.0, 0.0}, vjq = hjq ? Up[jq] : zero;
+  // a row's two entries of the column pair, times U
+  auto cols = [&](const cx<double>* row, cx<double>& yp, cx<double>& yq) {
+    const cx<double> xp = hjp ? row[jp] : zero, xq = hjq ? row[jq] : zero;
+    yp = cadd(cmul(xp, ujp), cmul(xq, vjp));
+    yq = cadd(cmul(xq, ujq), cmul(xp, vjq));
+  };
   if (blockIdx.z == 0) {
+    if (r >= np / 2) return;
+    const int ip = circle_player(r, step, np), iq = circle_player(np - 1 - r, step, np);
+    const bool hip_ = ip < N, hiq = iq < N;
     const cx<double>* a = reinterpret_cast<const cx<double>*>(A);
-    const int pi = partner[i];
-    const cx<double> ui = Us[i], vi = Up[i];
-    const cx<double> x1 = cadd(cmul(a[(size_t)i * N + j], uj), cmul(a[(size_t)i * N + pj], vj));
-    const cx<double> x2 = cadd(cmul(a[(size_t)pi * N + j], uj), cmul(a[(size_t)pi * N + pj], vj));
-    const cx<double> r = cadd(cmul(conjc(ui), x1), cmul(conjc(vi), x2));
-    reinterpret_cast<cx<double>*>(A2)[(size_t)i * N + j] = r;
+    cx<double> pp = zero, pq = zero, qp = zero, qq = zero;
+    if (hip_) cols(a + (size_t)ip * N, pp, pq);
+    if (hiq) cols(a + (size_t)iq * N, qp, qq);
+    cx<double>* o = reinterpret_cast<cx<double>*>(A2);
+    if (hip_) {
+      const cx<double> u = conjc(Us[ip]), v = conjc(Up[ip]);
+      if (hjp) o[(size_t)ip * N + jp] = cadd(cmul(u, pp), cmul(v, qp));
+      if (hjq) o[(size_t)ip * N + jq] = cadd(cmul(u, pq), cmul(v, qq));
+    }
+    if (hiq) {
+      const cx<double> u = conjc(Us[iq]), v = conjc(Up[iq]);
+      if (hjp) o[(size_t)iq * N + jp] = cadd(cmul(u, qp), cmul(v, pp));
+      if (hjq) o[(size_t)iq * N + jq] = cadd(cmul(u, qq), cmul(v, pq));
+    }
   } else {
-    const cx<double>* v = reinterpret_cast<const cx<double>*>(V);
-    const cx<double> r = cadd(cmul(v[(size_t)i * N + j], uj), cmul(v[(size_t)i * N + pj], vj));
-    reinterpret_cast<cx<double>*>(V2)[(size_t)i * N + j] = r;
+    if (r >= N) return;
+    cx<double> yp, yq;
+    cols(reinterpret_cast<const cx<double>*>(V) + (size_t)r * N, yp, yq);
+    cx<double>* o = reinterpret_cast<cx<double>*>(V2) + (size_t)r * N;
+    if (hjp) o[jp] = yp;
+    if (hjq) o[jq] = yq;
   }
 }
 
@@ -290,21 +320,21 @@ hipError_t launch_jacobi_eig(double* A, double* A2, double* V, double* V2, int N
   char* w = (char*)work;
   double* sums = (double*)(w + L.sums);
   double* part = (double*)(w + L.part);
-  int* partner = (int*)(w + L.partner);
   double* us = (double*)(w + L.us);
   double* up = (double*)(w + L.up);
   hipLaunchKernelGGL(k_eye, dim3(1024), dim3(256), 0, s, V, N);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  const dim3 agrid(cdiv(N, 64), cdiv(N, 4), 2);
+  // column pairs across, row pairs (A) or rows (V) down
+  const dim3 agrid(cdiv(np / 2, 64), cdiv(N, 4), 2);
   double prev = -1.0;
   *sweeps = -1;
   for (int sw = 0; sw < max_sweeps; ++sw) {
     for (int st = 0; st < np - 1; ++st) {
       hipLaunchKernelGGL(k_jac_rot, dim3(cdiv(np / 2, 256)), dim3(256), 0, s, (const double*)A, N, np, st,
-                         partner, us, up);
+                         us, up);
       hipLaunchKernelGGL(k_jac_apply, agrid, dim3(256), 0, s, (const double*)A, A2, (const double*)V, V2,
-                         N, (const int*)partner, (const double*)us, (const double*)up);
+                         N, np, st, (const double*)us, (const double*)up);
       std::swap(A, A2);
       std::swap(V, V2);
     }
