@@ -649,6 +649,63 @@ def serving(args) -> dict:
     return res
 
 
+def eigen_study(args) -> dict:
+    """The eigenvalue route (Eq. 7; truncation, Eq. 4) at moderate N: FP64 plans
+    of SIDE^2 images with 8 coils and a spiral of 2N samples per coil, built
+    once uncached.  Per build: Jacobi sweeps, kept rank, stage times (Gram,
+    eigendecomposition + truncation + Q^H, W, R).  The Jacobi stage's rate
+    counts the rotation passes' compulsory bytes, 64 N^2 per step (A and V
+    read and their rotated copies written, complex128) over np - 1 steps a
+    sweep, against 8 TB/s; the stage time also holds the per-sweep norms and
+    host check, the ranking and Q^H.  The spectrum is checked against
+    numpy.linalg.eigvalsh of the plan's own FP64 Gram, and the plain
+    Cholesky FP64 build of the same encoding is timed beside it."""
+    import torch
+    from paper_2410_06129_amd import pinv as P
+    from paper_2410_06129_amd import synth
+
+    ctx = P.pinv_context_create(0)
+    out = {"coils": 8, "builds": []}
+    for side in [int(x) for x in args.eigen_sides.split(",")]:
+        enc = synth.serving_encoding(side, 8, 0)
+        N, M = enc.N, enc.M
+        rec = {"side": side, "N": N, "M": M}
+        for label, kw in (("eigen_kappa100", dict(route=P.ROUTE_EIGEN, trunc=P.TRUNC_KAPPA,
+                                                  trunc_value=100.0)),
+                          ("cholesky", {})):
+            t0 = time.perf_counter()
+            p = P.pinv_build(ctx, enc, 1e-3, P.LAMBDA_REL_MEAN_DIAG, P.FP64, P.FLAG_UNCACHED, **kw)
+            P.pinv_plan_wait(p)
+            wall = (time.perf_counter() - t0) * 1e3
+            info = P.pinv_plan_info_get(p)
+            r = {"wall_ms": wall, "stage_ms": dict(zip(("gram", "factor", "trmm_w", "trmm_r"),
+                                                       info["stage_ms"]))}
+            if label.startswith("eigen"):
+                sweeps = info["sweeps"]
+                steps = sweeps * (N + N % 2 - 1)
+                nbytes = 64.0 * N * N * steps
+                ms = info["stage_ms"][1]
+                spec = torch.empty((N,), dtype=torch.float64, device="cuda")
+                P.pinv_spectrum(ctx, p, spec)
+                G = torch.empty((N, N), dtype=torch.complex128, device="cuda")
+                P.pinv_plan_copy_buffer(p, P.BUF_GRAM, G)
+                torch.cuda.synchronize()
+                ref = np.linalg.eigvalsh(G.cpu().numpy())
+                got = np.sort(spec.cpu().numpy())
+                del G
+                r.update(sweeps=sweeps, rank=info["rank"], rotation_steps=steps,
+                         jacobi_bytes=nbytes, jacobi_GBps=nbytes / (ms * 1e-3) / 1e9,
+                         jacobi_hbm_frac=nbytes / (ms * 1e-3) / PEAK_HBM,
+                         spectrum_max_abs_err_rel=float(np.abs(got - ref).max() / np.abs(ref).max()))
+            rec[label] = r
+            P.pinv_plan_release(p)
+            P.pinv_context_trim(ctx)
+            log(f"eigen study {side}^2 {label}: {r}")
+        out["builds"].append(rec)
+    P.pinv_context_destroy(ctx)
+    return out
+
+
 def precision_study(args) -> dict:
     """96x96, 16 coils, 8192-sample spiral per coil (M=131072), 500 frames:
     relative image error of FP32 plans (FP64 PSF Gram, and an FP32 Gram over
@@ -1059,6 +1116,9 @@ def main():
                     help="build plans for a SIDE^2 image with COILS coils (spiral 2N per coil)")
     ap.add_argument("--precisions", default="fp32,fp64")
     ap.add_argument("--precision-study", action="store_true")
+    ap.add_argument("--eigen-study", action="store_true",
+                    help="time the eigenvalue route (Jacobi) at moderate N beside the Cholesky route")
+    ap.add_argument("--eigen-sides", default="32,48,64")
     ap.add_argument("--frames-study", type=int, default=500)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -1095,6 +1155,13 @@ def main():
         return
     if args.build_only:
         print(json.dumps(build_only(args)), flush=True)
+        return
+    if args.eigen_study:
+        res = eigen_study(args)
+        print(json.dumps({"metric": "eigenvalue-route build stages (ms) and Jacobi HBM rate",
+                          "unit": "ms", "higher_is_better": False, "data": "synthetic",
+                          "config": {"workload": "spiral 2N per coil, 8 coils, sides "
+                                                 + args.eigen_sides}, "study": res}), flush=True)
         return
     if args.serving:
         res = serving(args)
