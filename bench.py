@@ -68,6 +68,11 @@ def gram_flops_executed(enc, form: str) -> float:
 
 def build_flops_executed(enc, form: str = "psf") -> dict:
     N, M = enc.N, enc.M
+    if M < N:
+        # right pseudoinverse: the M x M Gram E E^H over the N unknowns (lower
+        # triangle), its factor and inverse, Z = L'^-1 E and R^H = L'^-H Z
+        return {"gram": 4.0 * N * M * M, "chol_inv": 8.0 * M ** 3 / 3.0,
+                "trmm_w": 4.0 * N * M * M, "trmm_r": 4.0 * N * M * M}
     return {"gram": gram_flops_executed(enc, form), "chol_inv": 8.0 * N ** 3 / 3.0,
             "trmm_w": 4.0 * M * N * N, "trmm_r": 4.0 * M * N * N}
 
@@ -775,12 +780,20 @@ def build_only(args) -> dict:
     import torch  # noqa: F401
     from paper_2410_06129_amd import pinv as P
     from paper_2410_06129_amd import synth
+    import dataclasses
     side, coils = args.build_only
     enc = synth.serving_encoding(side, coils, 0)
+    K = args.samples_per_coil or enc.K
+    if args.samples_per_coil:
+        enc = dataclasses.replace(enc, k=synth.vd_spiral(side, K))
+    if args.mask == "disc":   # unknowns: the voxels inside the inscribed circle
+        enc = dataclasses.replace(enc, voxels=synth.circular_mask(side, side).astype(np.int32))
     N, M = enc.N, enc.M
     ctx = P.pinv_context_create(0)
+    route = "right pseudoinverse" if M < N else "left pseudoinverse"
     out = {"metric": "R-build executed TFLOP/s", "unit": "TFLOP/s",
-           "config": {"workload": f"{side}x{side} image, {coils} coils, spiral {2 * N} per coil",
+           "config": {"workload": f"{side}x{side} image, {coils} coils, spiral {K} per coil"
+                                  + (", disc mask" if args.mask == "disc" else "") + f", {route}",
                       "N": N, "M": M}, "builds": {}}
     for name in args.precisions.split(","):
         prec, flags, kw = {"fp32": (P.FP32, 0, {}), "fp64": (P.FP64, 0, {}),
@@ -812,6 +825,12 @@ def build_only(args) -> dict:
             "tflops_standard_count_effective": build_flops_standard(enc) / (total * 1e-3) / 1e12,
             "stage_tflops_executed": {k: ex[k] / (st[i] * 1e-3) / 1e12 if st[i] > 0 else None
                                       for i, k in enumerate(("gram", "chol_inv", "trmm_w", "trmm_r"))}}
+        if M < N:
+            # the right route runs both products (and R = Z^H) inside the last
+            # stage interval: one rate for the two
+            sx = out["builds"][name]["stage_tflops_executed"]
+            del sx["trmm_w"], sx["trmm_r"]
+            sx["products"] = (ex["trmm_w"] + ex["trmm_r"]) / ((st[2] + st[3]) * 1e-3) / 1e12
         log(json.dumps(out["builds"][name]))
     out["value"] = out["builds"][next(iter(out["builds"]))]["tflops_executed"]
     P.pinv_context_destroy(ctx)
@@ -1115,6 +1134,11 @@ def main():
     ap.add_argument("--build-only", type=int, nargs=2, metavar=("SIDE", "COILS"),
                     help="build plans for a SIDE^2 image with COILS coils (spiral 2N per coil)")
     ap.add_argument("--precisions", default="fp32,fp64")
+    ap.add_argument("--samples-per-coil", type=int, default=0,
+                    help="--build-only: spiral samples per coil (default 2N; fewer than N/C "
+                         "gives the right pseudoinverse)")
+    ap.add_argument("--mask", choices=("none", "disc"), default="none",
+                    help="--build-only: restrict the unknowns to the inscribed disc")
     ap.add_argument("--precision-study", action="store_true")
     ap.add_argument("--eigen-study", action="store_true",
                     help="time the eigenvalue route (Jacobi) at moderate N beside the Cholesky route")

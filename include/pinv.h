@@ -193,7 +193,10 @@ typedef struct {
   size_t device_bytes;        /* device memory the plan holds */
   float stage_ms[4];          /* Gram, Cholesky+inverse, W = L^-1 E^H, R = L^-H W
                                  (HIP event times on the build stream; valid when ready;
-                                 the last two are 0 for factor-only plans) */
+                                 the last two are 0 for factor-only plans; with M < N the
+                                 last holds both products of the right pseudoinverse and
+                                 the third is 0; on the eigenvalue route the second is the
+                                 eigendecomposition, truncation and Q^H) */
   int32_t has_r;              /* 0 for plans built with PINV_FLAG_NO_R */
   int64_t gram_order;         /* N, or M when M < N (the samples' Gram E E^H, right
                                  pseudoinverse R = E^H (E E^H + lambda I)^-1, Sec. 2.2) */
