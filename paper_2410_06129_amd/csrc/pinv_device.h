@@ -857,8 +857,11 @@ struct LoadGenRow {
         const int nj = n + j * KPP;
         ok[j] = valid && nj < kend;
         const int nn = nj < e.N ? nj : 0;
-        const int s = nn / e.V;
-        const int v = nn - s * e.V;
+        int s = 0, v = nn;   // without a species table there is one species
+        if constexpr ((FEAT & FEAT_Q) != 0) {
+          s = nn / e.V;
+          v = nn - s * e.V;
+        }
         int ix, iy;
         voxel_xy(e, v, &ix, &iy);
         gen_load<FEAT>(e, i, s, v, ix, iy, c, raw[j]);
@@ -1020,8 +1023,11 @@ struct LoadGenRowSP {
         const int nj = n + j;
         ok[j] = valid && nj < kend;
         const int nn = nj < e.N ? nj : 0;
-        const int s = nn / e.V;
-        const int v = nn - s * e.V;
+        int s = 0, v = nn;   // without a species table there is one species
+        if constexpr ((FEAT & FEAT_Q) != 0) {
+          s = nn / e.V;
+          v = nn - s * e.V;
+        }
         int ix, iy;
         voxel_xy(e, v, &ix, &iy);
         gen_load<FEAT>(e, i, s, v, ix, iy, c, raw[j]);
