@@ -4,7 +4,8 @@ FP64 oracle restricted to the same voxels.
 
 The masked encodings are ragged against every tile (N = S * nvox is no multiple
 of 64) and their voxel lists break the image-row alignment the row-generated
-loaders otherwise use.  Bars as for the unmasked parity tests: FP64 plans 1e-9
+loaders otherwise use (the wide case at 64 x 48, 2395 unknowns, spans many
+tiles).  Bars as for the unmasked parity tests: FP64 plans 1e-9
 relative (R and L^-1 element by element, the Gram within 1e-12 of max|G|),
 FP32 plans 1e-5 after two refinement steps.
 """
@@ -53,6 +54,10 @@ def case(name):
     if name == "threshold_c2":    # voxels above 30% of the phantom's peak (PSF Gram)
         w = synth.small_case(seed=202, nx=24, ny=24, C=2, K=1100, F=3)
         return w, masked(w, synth.threshold_mask(w.images[0], 0.3))
+    if name == "wide_disc_c2":    # rows up to 64 voxels wide, wider than a 32-column
+        # chunk: several tiles in each dimension and chunks within and across rows
+        w = synth.small_case(seed=204, nx=64, ny=48, C=2, K=2600, F=3)
+        return w, masked(w, synth.circular_mask(64, 48))
     if name == "circle_species_b0":   # two species and off-resonance (MFMA Gram)
         w = synth.small_case(seed=203, nx=16, ny=16, C=2, K=700, F=3, species=[0.0, 150.0], b0=True)
         return w, masked(w, synth.circular_mask(16, 16, 0.9))
@@ -73,7 +78,7 @@ def oracle_case(name):
     return _cache[name]
 
 
-NAMES = ["circle_c3", "threshold_c2", "circle_species_b0"]
+NAMES = ["circle_c3", "threshold_c2", "wide_disc_c2", "circle_species_b0"]
 
 
 @pytest.mark.parametrize("name", NAMES)
