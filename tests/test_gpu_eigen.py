@@ -12,7 +12,8 @@ with Q = P_r diag(1/sqrt(mu_j + lam))), against the oracle's EigenBuild
   eigenvectors' error, u ||G|| / gap, amplified by the kept condition number
   mu_1 / mu_r, which the choice of cut keeps within 1e4); images within 1e-8.
 * FP32 plans: images within (mu_1 + lam) / (mu_r + lam) * 1e-6.
-* Odd N (the Jacobi ordering pads one index) and a voxel mask are covered.
+* Odd N (the Jacobi ordering pads one index), a voxel mask and N = 1024 (about
+  30 sweeps) are covered.
 """
 import numpy as np
 import pytest
@@ -46,6 +47,8 @@ def encoding(name):
                                 b0=True).enc
     if name == "odd_c2":        # N = 13 * 11 = 143, odd
         return synth.small_case(seed=503, nx=13, ny=11, C=2, K=400, F=1).enc
+    if name == "n1024":         # 32 x 32, 8 coils, spiral of 2N per coil (M = 16384)
+        return synth.serving_encoding(32, 8, 0)
     if name == "masked":        # circular mask, N odd or even as it falls
         w = synth.small_case(seed=504, nx=22, ny=22, C=2, K=900, F=1)
         e = w.enc
@@ -128,6 +131,24 @@ def test_eigen_route_fp64_matches_oracle(P, ctx, name, how):
     print(f"{name} {how}: rank {info['rank']} / {enc.N} (oracle {ob.rank}), {info['sweeps']} sweeps")
     assert info["route"] == P.ROUTE_EIGEN and info["sweeps"] > 0
     assert info["rank"] == ob.rank
+    assert np.max(np.abs(spec - ob.mu)) <= 1e-12 * ob.mu[0]
+    R_ref = ob.recon_matrix()
+    assert np.max(np.abs(R - R_ref)) <= 1e-8 * np.max(np.abs(R_ref))
+    xr = ob.reconstruct(d)
+    assert np.max(np.linalg.norm(x - xr, axis=1) / np.linalg.norm(xr, axis=1)) < 1e-8
+
+
+def test_eigen_route_at_n1024_matches_oracle(P, ctx):
+    """N = 1024, where the Jacobi solver needs about 30 sweeps (ill-conditioned
+    Gram, clustered small eigenvalues): spectrum, kept rank, R and images of a
+    kappa-truncated FP64 plan against the oracle, at the bars above."""
+    enc, G, mu = oracle_spectrum("n1024")
+    value, r = gap_kappa(mu)
+    ob = oracle.EigenBuild(enc, lam=0.0, mode="kappa", value=value, G=G)
+    assert ob.rank == r
+    info, spec, R, d, x = run(P, ctx, enc, P.FP64, 0.0, P.LAMBDA_ABS, P.TRUNC_KAPPA, value)
+    print(f"n1024: rank {info['rank']} / {enc.N}, {info['sweeps']} sweeps")
+    assert info["sweeps"] > 0 and info["rank"] == ob.rank
     assert np.max(np.abs(spec - ob.mu)) <= 1e-12 * ob.mu[0]
     R_ref = ob.recon_matrix()
     assert np.max(np.abs(R - R_ref)) <= 1e-8 * np.max(np.abs(R_ref))
